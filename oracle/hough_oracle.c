@@ -1,0 +1,441 @@
+/*
+ * hough_oracle.c -- plain, slow CPU oracle of the fixed-point Hough transform.
+ *
+ * TEST INFRASTRUCTURE, NOT PRODUCT CODE.  Only the test-suite, the smoke check
+ * and the benchmark's CPU-baseline leg load this library.  It shares no code,
+ * header, table or constant generator with the GPU library: every constant is
+ * derived here from its definition, every value is recomputed per sample.
+ *
+ * What it computes (Halyo et al., "GPU Enhancement of the Trigger to Extend
+ * Physics Reach at the LHC", Sec. "Proposed Fast Tracking Algorithm" and its
+ * Fig. "hough" caption; Sec. "Preliminary Results", the curved-track and
+ * displaced-track paragraph):
+ *   - every hit is mapped to the set of helix parameters it is compatible
+ *     with; votes of all hits are summed in a binned parameter space;
+ *   - local maxima of that space are the track candidates;
+ *   - the hits that voted for a candidate are the input of the track fit
+ *     (Sec. "Preliminary Results", fitting paragraph).
+ * The paper gives no parameterisation, grid, binning or tie rule.  The
+ * discretisation used here is the "fixed-point transform" written out step by
+ * step below (one reading of the silent points; the same reading is stated in
+ * the design notes of the repository).
+ *
+ * Parameters: phi0 (azimuth of the track direction at the point of closest
+ * approach, PCA), q/pT (GeV^-1) and d0 (signed transverse impact parameter,
+ * cm; PCA = d0 * (-sin phi0, cos phi0)).  Signed curvature c = -kappa * q/pT
+ * with kappa = 0.299792458e-2 * B (B in tesla, lengths in cm): positive charges
+ * bend clockwise for B along +z.  A point at radius r on the circle, on the
+ * branch leaving the PCA, has azimuth phi with
+ *     sin(phi - phi0) = A(r, c, d0) = (c (r^2 + d0^2) + 2 d0) / (2 r (1 + c d0)),
+ * so phi0 = phi - asin(A).  For d0 = 0 this is phi0 = phi - asin(c r / 2).
+ *
+ * Parity status of each function: see the pins in tests/test_oracle_pins.py.
+ * All functions here are pinned; none is "parity unpinned".
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#ifndef M_PI
+#define M_PI 3.14159265358979323846
+#endif
+
+/* Configuration as plain numbers (the oracle's own struct). */
+typedef struct {
+    int32_t n_layers;
+    const double* r_cm;        /* nominal layer radii */
+    const double* halflen_cm;  /* may be NULL; not used by the transform */
+    double B_tesla;
+    int32_t n_phi, n_qpt, n_d0;
+    int32_t frac_bits;         /* F: angle bits below one phi0 bin */
+    double qpt_min, qpt_max, d0_min, d0_max;
+    int32_t n_cot, n_z0;
+    double cot_min, cot_max, z0_min, z0_max;
+} or_cfg_t;
+
+/* ------------------------------------------------------------------------ */
+/* Step 1 of the transform: Q16.16 fixed point of a float coordinate.        */
+/* The float is scaled by 2^16 (exact) and rounded to nearest, ties to even. */
+/* ------------------------------------------------------------------------ */
+int32_t or_q16(float v)
+{
+    double s = (double)v * 65536.0;
+    return (int32_t)llrint(s);
+}
+
+/* A coordinate is usable when it is finite and strictly inside +-32768 cm. */
+static int or_coord_ok(float v)
+{
+    return isfinite(v) && fabsf(v) < 32768.0f;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Step 2: azimuth of (X, Y) in 32-bit binary angle measure (2^32 == 2 pi),  */
+/* by integer CORDIC in vectoring mode (Volder, 1959).                       */
+/*   - turn the vector by -90 degrees until it lies in [0, 90) degrees,      */
+/*     counting the quarter turns q;                                         */
+/*   - 16 guard bits; 30 micro-rotations by atan(2^-i), each pushing y       */
+/*     towards zero, accumulating the signed angle constants                 */
+/*     T_i = round(atan(2^-i) * 2^31 / pi);                                  */
+/*   - result = q * 2^30 + accumulated angle, modulo 2^32.                   */
+/* ------------------------------------------------------------------------ */
+static int64_t or_cordic_const(int i)
+{
+    return llrint(atan(ldexp(1.0, -i)) * (2147483648.0 / M_PI));
+}
+
+uint32_t or_azimuth(int32_t X, int32_t Y)
+{
+    int64_t x = X, y = Y, tmp, dx, dy, theta = 0;
+    uint32_t quarter = 0;
+    int i;
+    while (!(x > 0 && y >= 0)) { /* rotate by -90 degrees */
+        tmp = x;
+        x = y;
+        y = -tmp;
+        quarter++;
+    }
+    x *= 65536;
+    y *= 65536;
+    for (i = 0; i < 30; i++) {
+        dx = x >> i; /* arithmetic shifts (floor) */
+        dy = y >> i;
+        if (y >= 0) {
+            x = x + dy;
+            y = y - dx;
+            theta += or_cordic_const(i);
+        } else {
+            x = x - dy;
+            y = y + dx;
+            theta -= or_cordic_const(i);
+        }
+    }
+    return (uint32_t)((uint64_t)quarter * 1073741824ull + (uint64_t)theta);
+}
+
+/* Validity of one hit and its fixed-point coordinates. */
+int or_hit(float x, float y, uint8_t layer, int32_t n_layers, int32_t* X, int32_t* Y)
+{
+    if ((int32_t)layer >= n_layers) return 0;
+    if (!or_coord_ok(x) || !or_coord_ok(y)) return 0;
+    *X = or_q16(x);
+    *Y = or_q16(y);
+    if (*X == 0 && *Y == 0) return 0;
+    return 1;
+}
+
+/* Per-hit preparation for a batch: azimuth (32-bit BAM) and validity. */
+void or_prep(int32_t n, const float* x, const float* y, const uint8_t* layer, int32_t n_layers,
+             uint32_t* phi_out, uint8_t* valid_out)
+{
+    int32_t h, X, Y;
+    for (h = 0; h < n; h++) {
+        valid_out[h] = (uint8_t)or_hit(x[h], y[h], layer[h], n_layers, &X, &Y);
+        phi_out[h] = valid_out[h] ? or_azimuth(X, Y) : 0u;
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Step 3: grid.  Bin centres of q/pT and d0; phi0 bins are the top          */
+/* log2(n_phi) bits of an M-bit angle, M = log2(n_phi) + F.                  */
+/* ------------------------------------------------------------------------ */
+static int or_log2(int32_t v)
+{
+    int s = 0;
+    while ((1 << s) < v) s++;
+    return s;
+}
+
+int32_t or_angle_bits(const or_cfg_t* g)
+{
+    return or_log2(g->n_phi) + g->frac_bits;
+}
+
+double or_qpt_centre(const or_cfg_t* g, int32_t k)
+{
+    return g->qpt_min + ((double)k + 0.5) * ((g->qpt_max - g->qpt_min) / (double)g->n_qpt);
+}
+
+double or_d0_centre(const or_cfg_t* g, int32_t l)
+{
+    return g->d0_min + ((double)l + 0.5) * ((g->d0_max - g->d0_min) / (double)g->n_d0);
+}
+
+double or_curvature(const or_cfg_t* g, int32_t k)
+{
+    double kappa = 0.299792458e-2 * g->B_tesla;
+    return -kappa * or_qpt_centre(g, k);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Step 4: one sample.  For a hit on a layer of radius r and the parameter   */
+/* cell (c, d), the phi0 offset asin(A) in M-bit BAM, or "invalid" when the  */
+/* circle does not reach radius r (|A| > 1) or the denominator is not        */
+/* positive.  Evaluated per call, in IEEE double, in this operation order.   */
+/* ------------------------------------------------------------------------ */
+int or_sample(double r, double c, double d, int32_t M, int32_t* E)
+{
+    double num = c * (r * r + d * d) + 2.0 * d;
+    double den = 2.0 * r * (1.0 + c * d);
+    double A, K;
+    if (!(den > 0.0)) return 0;
+    A = num / den;
+    if (!(fabs(A) <= 1.0)) return 0;
+    K = ldexp(1.0, M - 1) / M_PI;
+    *E = (int32_t)llrint(asin(A) * K);
+    return 1;
+}
+
+/* phi0 bin of a hit with M-bit azimuth phiM for sample value E. */
+static int32_t or_bin(uint32_t phiM, int32_t E, int32_t M, int32_t F)
+{
+    uint32_t mask = (M >= 32) ? 0xffffffffu : ((1u << M) - 1u);
+    return (int32_t)(((phiM - (uint32_t)E) & mask) >> F);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Step 5: vote.  acc[l][k][b] (b fastest), int32, fully overwritten.        */
+/* For every valid hit, every d0 bin l and every q/pT bin k whose sample is  */
+/* valid: one vote into the phi0 bin of phi - asin(A).                       */
+/* Returns the number of votes cast.                                         */
+/* ------------------------------------------------------------------------ */
+int64_t or_vote(const or_cfg_t* g, int32_t n, const float* x, const float* y, const uint8_t* layer,
+                int32_t* acc)
+{
+    int32_t M = or_angle_bits(g), F = g->frac_bits;
+    int64_t total = 0, nbins = (int64_t)g->n_d0 * g->n_qpt * g->n_phi;
+    uint32_t* phiM = (uint32_t*)malloc(sizeof(uint32_t) * (size_t)(n > 0 ? n : 1));
+    uint8_t* ok = (uint8_t*)malloc((size_t)(n > 0 ? n : 1));
+    int32_t h, l;
+    or_prep(n, x, y, layer, g->n_layers, phiM, ok);
+    for (h = 0; h < n; h++) phiM[h] >>= (32 - M);
+    memset(acc, 0, sizeof(int32_t) * (size_t)nbins);
+#pragma omp parallel for schedule(dynamic, 1) reduction(+ : total)
+    for (l = 0; l < g->n_d0; l++) {
+        double d = or_d0_centre(g, l);
+        int32_t hh, k, E;
+        for (hh = 0; hh < n; hh++) {
+            if (!ok[hh]) continue;
+            for (k = 0; k < g->n_qpt; k++) {
+                double c = or_curvature(g, k);
+                if (!or_sample(g->r_cm[layer[hh]], c, d, M, &E)) continue;
+                acc[((int64_t)l * g->n_qpt + k) * g->n_phi + or_bin(phiM[hh], E, M, F)] += 1;
+                total += 1;
+            }
+        }
+    }
+    free(phiM);
+    free(ok);
+    return total;
+}
+
+/* The same votes restricted to a list of (l, k) columns: out[i][b] for the  */
+/* column (cols[2i], cols[2i+1]).  Used to check large accumulators by       */
+/* sampling columns.                                                          */
+void or_vote_columns(const or_cfg_t* g, int32_t n, const float* x, const float* y,
+                     const uint8_t* layer, int32_t n_cols, const int32_t* cols, int32_t* out)
+{
+    int32_t M = or_angle_bits(g), F = g->frac_bits;
+    uint32_t* phiM = (uint32_t*)malloc(sizeof(uint32_t) * (size_t)(n > 0 ? n : 1));
+    uint8_t* ok = (uint8_t*)malloc((size_t)(n > 0 ? n : 1));
+    int32_t h, i;
+    or_prep(n, x, y, layer, g->n_layers, phiM, ok);
+    for (h = 0; h < n; h++) phiM[h] >>= (32 - M);
+    memset(out, 0, sizeof(int32_t) * (size_t)n_cols * g->n_phi);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (i = 0; i < n_cols; i++) {
+        int32_t l = cols[2 * i], k = cols[2 * i + 1], hh, E;
+        double d = or_d0_centre(g, l), c = or_curvature(g, k);
+        for (hh = 0; hh < n; hh++) {
+            if (!ok[hh]) continue;
+            if (!or_sample(g->r_cm[layer[hh]], c, d, M, &E)) continue;
+            out[(int64_t)i * g->n_phi + or_bin(phiM[hh], E, M, F)] += 1;
+        }
+    }
+    free(phiM);
+    free(ok);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Step 6: peaks.  Bin i = (l, k, b) is a candidate iff acc[i] >= thr and,   */
+/* for every neighbour j in the 3x3x3 block around it (phi0 cyclic, q/pT and */
+/* d0 clipped at the grid edge), acc[i] > acc[j] when j precedes i and       */
+/* acc[i] >= acc[j] otherwise.  j precedes i when (l_j, k_j) < (l_i, k_i)    */
+/* lexicographically, or when j is the previous phi0 bin (b - 1 mod n_phi)   */
+/* of the same (l, k) column.  Output in increasing linear index            */
+/* (l * n_qpt + k) * n_phi + b as {l, k, b, votes}; only the first `cap` are */
+/* written; the return value is the total count.                             */
+/* ------------------------------------------------------------------------ */
+static int or_is_peak(const or_cfg_t* g, const int32_t* acc, int32_t l, int32_t k, int32_t b, int32_t thr)
+{
+    int32_t Nd = g->n_d0, Nk = g->n_qpt, Np = g->n_phi, dl, dk, db;
+    int32_t v = acc[((int64_t)l * Nk + k) * Np + b];
+    if (v < thr) return 0;
+    for (dl = -1; dl <= 1; dl++) {
+        int32_t l2 = l + dl;
+        if (l2 < 0 || l2 >= Nd) continue;
+        for (dk = -1; dk <= 1; dk++) {
+            int32_t k2 = k + dk;
+            if (k2 < 0 || k2 >= Nk) continue;
+            for (db = -1; db <= 1; db++) {
+                int32_t b2, u, precedes;
+                if (dl == 0 && dk == 0 && db == 0) continue;
+                b2 = (b + db + Np) % Np;
+                u = acc[((int64_t)l2 * Nk + k2) * Np + b2];
+                precedes = (l2 < l) || (l2 == l && k2 < k) || (l2 == l && k2 == k && db == -1);
+                if (precedes ? !(v > u) : !(v >= u)) return 0;
+            }
+        }
+    }
+    return 1;
+}
+
+int64_t or_peaks(const or_cfg_t* g, const int32_t* acc, int32_t thr, int64_t cap, int32_t* out)
+{
+    int64_t count = 0;
+    int32_t l, k, b;
+    for (l = 0; l < g->n_d0; l++)
+        for (k = 0; k < g->n_qpt; k++)
+            for (b = 0; b < g->n_phi; b++) {
+                if (!or_is_peak(g, acc, l, k, b, thr)) continue;
+                if (count < cap) {
+                    out[4 * count + 0] = l;
+                    out[4 * count + 1] = k;
+                    out[4 * count + 2] = b;
+                    out[4 * count + 3] = acc[((int64_t)l * g->n_qpt + k) * g->n_phi + b];
+                }
+                count++;
+            }
+    return count;
+}
+
+/* Peak test of a single bin (for sampled checks of large accumulators). */
+int or_peak_at(const or_cfg_t* g, const int32_t* acc, int32_t l, int32_t k, int32_t b, int32_t thr)
+{
+    return or_is_peak(g, acc, l, k, b, thr);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Step 7: assignment.  For each candidate p = (l_p, k_p, b_p), the valid    */
+/* hits whose sample at (l_p, k_p) is valid and falls in phi0 bin b_p, in    */
+/* increasing hit index (so the list length equals acc at the candidate).    */
+/* CSR output: offsets[0..n_peaks], hit_idx[offsets[p] .. offsets[p+1]),    */
+/* entries at positions >= cap_pairs are not written.  Returns the total.    */
+/* The sample values of the candidate's cell are evaluated once per layer    */
+/* for each candidate (they depend only on the layer, l_p and k_p).          */
+/* ------------------------------------------------------------------------ */
+int64_t or_assign(const or_cfg_t* g, int32_t n, const float* x, const float* y, const uint8_t* layer,
+                  int32_t n_peaks, const int32_t* peaks, int64_t* offsets, int32_t* hit_idx,
+                  int64_t cap_pairs)
+{
+    int32_t M = or_angle_bits(g), F = g->frac_bits, p, h, L;
+    uint32_t* phiM = (uint32_t*)malloc(sizeof(uint32_t) * (size_t)(n > 0 ? n : 1));
+    uint8_t* ok = (uint8_t*)malloc((size_t)(n > 0 ? n : 1));
+    int32_t* E = (int32_t*)malloc(sizeof(int32_t) * (size_t)g->n_layers);
+    uint8_t* Ev = (uint8_t*)malloc((size_t)g->n_layers);
+    int64_t pos = 0;
+    or_prep(n, x, y, layer, g->n_layers, phiM, ok);
+    for (h = 0; h < n; h++) phiM[h] >>= (32 - M);
+    for (p = 0; p < n_peaks; p++) {
+        int32_t lp = peaks[4 * p], kp = peaks[4 * p + 1], bp = peaks[4 * p + 2];
+        double d = or_d0_centre(g, lp), c = or_curvature(g, kp);
+        offsets[p] = pos;
+        for (L = 0; L < g->n_layers; L++) Ev[L] = (uint8_t)or_sample(g->r_cm[L], c, d, M, &E[L]);
+        for (h = 0; h < n; h++) {
+            if (!ok[h] || !Ev[layer[h]]) continue;
+            if (or_bin(phiM[h], E[layer[h]], M, F) != bp) continue;
+            if (pos < cap_pairs) hit_idx[pos] = h;
+            pos++;
+        }
+    }
+    offsets[n_peaks] = pos;
+    free(phiM);
+    free(ok);
+    free(E);
+    free(Ev);
+    return pos;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Step 8 (second stage, r-z): for one candidate (l, k), vote its hits into  */
+/* a cot(theta) x z0 grid with the helix model z = z0 + s cot(theta), where  */
+/* s is the transverse arc length from the PCA to the hit:                    */
+/*   chord  Lc = sqrt(r^2 + d^2 - 2 d r A),                                   */
+/*   arc    s  = Lc                    if c == 0,                             */
+/*             = (2/|c|) asin(|c| Lc/2) otherwise;                            */
+/* S = round(s * 2^16) (Q16.16), C_m = round(cot_m * 2^16) at the bin centre, */
+/* z0 = Z * 2^16 - S * C_m exactly in Q32.32; bin j = floor((z0 - z0min)/W)  */
+/* with z0min = round(z0_min * 2^32) and W = round(bin width * 2^32).        */
+/* Output per candidate: the bin with most votes (lowest m * n_z0 + j among  */
+/* ties) and its count, or (-1, -1, 0) when nothing voted.                    */
+/* ------------------------------------------------------------------------ */
+int or_arclen(double r, double c, double d, int64_t* S)
+{
+    double num = c * (r * r + d * d) + 2.0 * d;
+    double den = 2.0 * r * (1.0 + c * d);
+    double A, Lc2, Lc, s, u;
+    if (!(den > 0.0)) return 0;
+    A = num / den;
+    if (!(fabs(A) <= 1.0)) return 0;
+    Lc2 = r * r + d * d - 2.0 * d * r * A;
+    Lc = sqrt(Lc2 > 0.0 ? Lc2 : 0.0);
+    if (c == 0.0) {
+        s = Lc;
+    } else {
+        u = fabs(c) * Lc / 2.0;
+        if (u > 1.0) u = 1.0;
+        s = (2.0 / fabs(c)) * asin(u);
+    }
+    *S = llrint(s * 65536.0);
+    return 1;
+}
+
+int64_t or_cot_centre_q16(const or_cfg_t* g, int32_t m)
+{
+    double v = g->cot_min + ((double)m + 0.5) * ((g->cot_max - g->cot_min) / (double)g->n_cot);
+    return llrint(v * 65536.0);
+}
+
+void or_zvote(const or_cfg_t* g, int32_t n, const float* z, const uint8_t* layer, int32_t n_peaks,
+              const int32_t* peaks, const int64_t* offsets, const int32_t* hit_idx, int32_t* out)
+{
+    int64_t z0min = llrint(g->z0_min * 4294967296.0);
+    int64_t W = llrint(((g->z0_max - g->z0_min) / (double)g->n_z0) * 4294967296.0);
+    int32_t* zacc = (int32_t*)malloc(sizeof(int32_t) * (size_t)g->n_cot * g->n_z0);
+    int64_t* C = (int64_t*)malloc(sizeof(int64_t) * (size_t)g->n_cot);
+    int32_t p, m;
+    (void)n;
+    for (m = 0; m < g->n_cot; m++) C[m] = or_cot_centre_q16(g, m);
+    for (p = 0; p < n_peaks; p++) {
+        int32_t lp = peaks[4 * p], kp = peaks[4 * p + 1], best = -1, bestv = 0, i;
+        double d = or_d0_centre(g, lp), c = or_curvature(g, kp);
+        int64_t q;
+        memset(zacc, 0, sizeof(int32_t) * (size_t)g->n_cot * g->n_z0);
+        for (q = offsets[p]; q < offsets[p + 1]; q++) {
+            int32_t h = hit_idx[q], Z;
+            int64_t S;
+            if (!or_coord_ok(z[h])) continue;
+            Z = or_q16(z[h]);
+            if (!or_arclen(g->r_cm[layer[h]], c, d, &S)) continue;
+            for (m = 0; m < g->n_cot; m++) {
+                int64_t z0 = (int64_t)Z * 65536 - S * C[m] - z0min;
+                int64_t j;
+                if (z0 < 0) continue;
+                j = z0 / W;
+                if (j >= g->n_z0) continue;
+                zacc[(int64_t)m * g->n_z0 + j] += 1;
+            }
+        }
+        for (i = 0; i < g->n_cot * g->n_z0; i++)
+            if (zacc[i] > bestv) {
+                bestv = zacc[i];
+                best = i;
+            }
+        out[3 * p + 0] = best < 0 ? -1 : best / g->n_z0;
+        out[3 * p + 1] = best < 0 ? -1 : best % g->n_z0;
+        out[3 * p + 2] = bestv;
+    }
+    free(zacc);
+    free(C);
+}

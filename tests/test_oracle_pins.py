@@ -1,0 +1,636 @@
+"""Pins of the CPU oracle against what the mathematics fixes.
+
+None of these re-types the oracle's formulas: each pin is a closed form, an
+exact high-precision evaluation (mpmath), a textbook special case (straight
+line Hough, conformal mapping), a conservation law, a symmetry, or brute force
+on tiny inputs written in a different formulation (interval membership
+instead of shifts).  A dropped term, a sign error, a transposed index or a
+wrong rounding in the oracle fails at least one of them.
+"""
+import math
+from fractions import Fraction
+
+import mpmath as mp
+import numpy as np
+import pytest
+
+from paper_1305_4855_amd import configs, synth
+
+TWO32 = 1 << 32
+
+
+def circ_diff(a, b, mod=TWO32):
+    d = (int(a) - int(b)) % mod
+    return min(d, mod - d)
+
+
+# ----------------------------------------------------------------- Q16.16 --
+def test_q16_exact_values(oracle_mod):
+    O = oracle_mod
+    assert O.q16(1.0) == 65536
+    assert O.q16(-2.5) == -163840
+    assert O.q16(0.0) == 0
+    u = 1.0 / 65536.0
+    # round half to even on the Q16.16 grid
+    assert O.q16(0.5 * u) == 0
+    assert O.q16(1.5 * u) == 2
+    assert O.q16(2.5 * u) == 2
+    assert O.q16(-1.5 * u) == -2
+    assert O.q16(0.75 * u) == 1
+    assert O.q16(0.25 * u) == 0
+
+
+def test_q16_roundtrip_error(oracle_mod):
+    rng = np.random.default_rng(1)
+    v = rng.uniform(-200.0, 200.0, size=2000).astype(np.float32)
+    for x in v:
+        assert abs(oracle_mod.q16(float(x)) / 65536.0 - float(x)) <= 2.0 ** -17
+
+
+# ----------------------------------------------------------------- CORDIC --
+def _mp_bam(X, Y):
+    mp.mp.dps = 40
+    a = mp.atan2(mp.mpf(int(Y)), mp.mpf(int(X)))
+    return int(mp.nint(a * mp.mpf(2) ** 31 / mp.pi)) % TWO32
+
+
+def test_azimuth_accuracy_vs_mpmath(oracle_mod):
+    rng = np.random.default_rng(2)
+    worst = 0
+    for _ in range(1500):
+        r = 10.0 ** rng.uniform(0.0, math.log10(30000.0))  # 1 cm .. 300 m
+        phi = rng.uniform(0, 2 * math.pi)
+        X, Y = int(round(r * math.cos(phi) * 65536)), int(round(r * math.sin(phi) * 65536))
+        worst = max(worst, circ_diff(oracle_mod.azimuth(X, Y), _mp_bam(X, Y)))
+    assert worst <= 16, worst
+
+
+def test_azimuth_axes_and_quadrants(oracle_mod):
+    O = oracle_mod
+    for X, Y, want in [(65536, 0, 0), (0, 65536, 1 << 30), (-65536, 0, 1 << 31), (0, -65536, 3 << 30),
+                       (65536, 65536, 1 << 29), (-3 * 65536, 3 * 65536, 3 << 29)]:
+        assert circ_diff(O.azimuth(X, Y), want) <= 16
+
+
+def test_azimuth_quarter_turn_covariance(oracle_mod):
+    rng = np.random.default_rng(3)
+    O = oracle_mod
+    for _ in range(3000):
+        X, Y = (int(v) for v in rng.integers(-(1 << 30), 1 << 30, size=2))
+        if X == 0 and Y == 0:
+            continue
+        p = O.azimuth(X, Y)
+        assert O.azimuth(-Y, X) == (p + (1 << 30)) % TWO32
+        assert O.azimuth(-X, -Y) == (p + (1 << 31)) % TWO32
+        assert O.azimuth(Y, -X) == (p + (3 << 30)) % TWO32
+
+
+def test_hit_validity(oracle_mod):
+    O = oracle_mod
+    assert O.hit(10.0, 5.0, 3, 10)[0]
+    assert not O.hit(float("nan"), 5.0, 3, 10)[0]
+    assert not O.hit(float("inf"), 5.0, 3, 10)[0]
+    assert not O.hit(5.0, -float("inf"), 3, 10)[0]
+    assert not O.hit(32768.0, 1.0, 3, 10)[0]
+    assert O.hit(32767.0, 1.0, 3, 10)[0]
+    assert not O.hit(1.0, 1.0, 10, 10)[0]
+    assert not O.hit(1.0, 1.0, 255, 10)[0]
+    assert not O.hit(0.0, 0.0, 0, 10)[0]
+    assert not O.hit(2.0 ** -18, -(2.0 ** -18), 0, 10)[0]  # rounds to the origin
+    ok, X, Y = O.hit(-3.25, 7.5, 0, 10)
+    assert ok and X == -3.25 * 65536 and Y == 7.5 * 65536
+
+
+# ------------------------------------------------------------------ grid ---
+def test_grid_centres_exact(oracle_mod):
+    O = oracle_mod
+    for base in (configs.C1, configs.C2, configs.C4):
+        g = O.Cfg(base)
+        dq = Fraction(base.qpt_max) - Fraction(base.qpt_min)
+        for k in range(base.n_qpt):
+            want = Fraction(base.qpt_min) + (Fraction(2 * k + 1, 2)) * dq / base.n_qpt
+            assert Fraction(O.qpt_centre(g, k)) == want
+            # the grids are symmetric: centre k and n-1-k are exact negatives
+            assert O.qpt_centre(g, base.n_qpt - 1 - k) == -O.qpt_centre(g, k)
+        dd = Fraction(base.d0_max) - Fraction(base.d0_min)
+        for l in range(base.n_d0):
+            want = Fraction(base.d0_min) + Fraction(2 * l + 1, 2) * dd / base.n_d0
+            assert abs(Fraction(O.d0_centre(g, l)) - want) <= Fraction(1, 1 << 48)
+        # curvature: positive charges bend clockwise (negative signed curvature)
+        kappa = 0.299792458e-2 * base.B_tesla
+        k_pos = base.n_qpt - 1
+        assert O.curvature(g, k_pos) < 0 < O.curvature(g, 0)
+        assert abs(O.curvature(g, k_pos) + kappa * O.qpt_centre(g, k_pos)) < 1e-15
+
+
+# ------------------------------------------------------- sample vs mpmath --
+def _mp_E(r, c, d, M):
+    mp.mp.dps = 40
+    r, c, d = mp.mpf(r), mp.mpf(c), mp.mpf(d)
+    num = c * (r * r + d * d) + 2 * d
+    den = 2 * r * (1 + c * d)
+    if den <= 0:
+        return None, None
+    A = num / den
+    if abs(A) > 1:
+        return None, A
+    return mp.asin(A) * mp.mpf(2) ** (M - 1) / mp.pi, A
+
+
+def _check_table(O, base, stride=1):
+    g = O.Cfg(base)
+    M = O.angle_bits(g)
+    min_tie = 1.0
+    n_valid = 0
+    for L, r in enumerate(base.radii_cm):
+        for l in range(0, base.n_d0, stride):
+            d = O.d0_centre(g, l)
+            for k in range(0, base.n_qpt, stride):
+                c = O.curvature(g, k)
+                ok, E = O.sample(r, c, d, M)
+                v, A = _mp_E(r, c, d, M)
+                if v is None:
+                    assert not ok, (L, l, k)
+                    if A is not None:
+                        assert abs(A) - 1 > 1e-12  # far from the validity edge
+                    continue
+                assert ok, (L, l, k)
+                n_valid += 1
+                assert E == int(mp.nint(v)), (L, l, k, E, v)
+                frac = float(v - mp.floor(v))
+                min_tie = min(min_tie, abs(frac - 0.5))
+    return n_valid, min_tie
+
+
+def test_sample_table_vs_mpmath_c1(oracle_mod):
+    n_valid, min_tie = _check_table(oracle_mod, configs.C1)
+    assert n_valid == 10 * 256  # every (layer, q/pT) of the 2-D grid reaches every layer
+    assert min_tie > 1e-6
+
+
+@pytest.mark.slow
+def test_sample_table_vs_mpmath_c2(oracle_mod):
+    n_valid, min_tie = _check_table(oracle_mod, configs.C2)
+    assert n_valid > 0.9 * 10 * 64 * 256
+    assert min_tie > 1e-6
+
+
+def test_sample_table_vs_mpmath_c4_sampled(oracle_mod):
+    n_valid, min_tie = _check_table(oracle_mod, configs.C4, stride=13)
+    assert n_valid > 0
+    assert min_tie > 1e-6
+
+
+def test_sample_closed_forms(oracle_mod):
+    O = oracle_mod
+    M = 17
+    K = 2.0 ** (M - 1) / math.pi
+    # d0 = 0 (prompt): phi - phi0 = asin(c r / 2)
+    for r, c in [(4.4, 0.0113), (78.0, -0.0113), (33.9, 0.004)]:
+        ok, E = O.sample(r, c, 0.0, M)
+        assert ok and abs(E - math.asin(c * r / 2) * K) <= 0.5 + 1e-9
+    # straight line (c = 0): sin(phi - phi0) = d0 / r
+    ok, E = O.sample(10.0, 0.0, 5.0, M)
+    assert ok and E == round(math.pi / 6 * K)
+    ok, E = O.sample(10.0, 0.0, -10.0, M)
+    assert ok and E == -(1 << (M - 2))
+    # a circle that never reaches the layer
+    assert O.sample(78.0, 0.0114, 0.0, M)[0]      # 2R = 175.6 cm > 78 cm: reaches
+    assert not O.sample(4.4, 0.0, 6.0, M)[0]       # line further than the layer
+    assert not O.sample(200.0, 0.0114, 0.0, M)[0]  # beyond the diameter of the helix
+
+
+def test_sample_antisymmetry(oracle_mod):
+    O = oracle_mod
+    for base in (configs.C2, configs.C4):
+        g = O.Cfg(base)
+        M = O.angle_bits(g)
+        rng = np.random.default_rng(4)
+        for _ in range(3000):
+            L = int(rng.integers(0, 10)); l = int(rng.integers(0, base.n_d0)); k = int(rng.integers(0, base.n_qpt))
+            a = O.sample(base.radii_cm[L], O.curvature(g, k), O.d0_centre(g, l), M)
+            b = O.sample(base.radii_cm[L], O.curvature(g, base.n_qpt - 1 - k),
+                         O.d0_centre(g, base.n_d0 - 1 - l), M)
+            assert a[0] == b[0]
+            if a[0]:
+                assert a[1] == -b[1]
+
+
+# ------------------------------------------------------------------- vote --
+def _tiny_cfg(**kw):
+    base = configs.C2.with_(name="tiny", n_phi=16, n_qpt=8, n_d0=4, frac_bits=8)
+    return base.with_(**kw)
+
+
+def _tiny_event(rng, n, n_layers=10, bad=True):
+    r = np.asarray(configs.RADII_CM)
+    lay = rng.integers(0, n_layers, size=n).astype(np.uint8)
+    phi = rng.uniform(0, 2 * np.pi, size=n)
+    x = (r[np.minimum(lay, 9)] * np.cos(phi)).astype(np.float32)
+    y = (r[np.minimum(lay, 9)] * np.sin(phi)).astype(np.float32)
+    if bad and n >= 3:
+        x[0] = np.nan
+        lay[1] = 12
+        x[2] = 0.0; y[2] = 0.0
+    return synth.Event(x=x, y=y, z=None, layer=lay, track_id=np.full(n, -1, np.int32), truth={})
+
+
+def test_vote_bruteforce_bin_centric(oracle_mod):
+    """For every bin, count the hits whose phi0 interval contains it (interval
+    membership, not a shift), and compare with the oracle's scatter."""
+    O = oracle_mod
+    rng = np.random.default_rng(5)
+    for trial in range(6):
+        base = _tiny_cfg(frac_bits=int(rng.integers(3, 9)))
+        g = O.Cfg(base)
+        M = O.angle_bits(g)
+        F = base.frac_bits
+        ev = _tiny_event(rng, 8)
+        acc, nv = O.vote(g, ev)
+        phi, ok = O.prep(ev, 10)
+        want = np.zeros_like(acc)
+        for l in range(base.n_d0):
+            for k in range(base.n_qpt):
+                for b in range(base.n_phi):
+                    lo, hi = b << F, (b + 1) << F
+                    for h in range(ev.n):
+                        if not ok[h]:
+                            continue
+                        okE, E = O.sample(base.radii_cm[ev.layer[h]], O.curvature(g, k), O.d0_centre(g, l), M)
+                        if not okE:
+                            continue
+                        rel = ((int(phi[h]) >> (32 - M)) - E) % (1 << M)
+                        if lo <= rel < hi:
+                            want[l, k, b] += 1
+        np.testing.assert_array_equal(acc, want)
+        assert nv == int(want.sum())
+
+
+def test_vote_conservation(oracle_mod):
+    O = oracle_mod
+    base = configs.small_variant(configs.C2, n_tracks=30, n_phi=128, n_qpt=32, n_d0=16)
+    g = O.Cfg(base)
+    M = O.angle_bits(g)
+    ev = synth.make_event(base, 0)
+    acc, nv = O.vote(g, ev)
+    _, ok = O.prep(ev, base.n_layers)
+    valid = np.zeros((base.n_layers, base.n_d0, base.n_qpt), dtype=bool)
+    for L in range(base.n_layers):
+        for l in range(base.n_d0):
+            for k in range(base.n_qpt):
+                valid[L, l, k] = O.sample(base.radii_cm[L], O.curvature(g, k), O.d0_centre(g, l), M)[0]
+    per_layer = np.bincount(ev.layer[ok], minlength=base.n_layers)
+    col_want = np.einsum("L,Llk->lk", per_layer, valid.astype(np.int64))
+    np.testing.assert_array_equal(acc.sum(axis=2), col_want)
+    assert nv == acc.sum() == col_want.sum()
+
+
+def _centred_track_event(base, g, O, rng, n_tracks, displaced=True, smear=0.0):
+    """Noise-free tracks whose (q/pT, d0, phi0) sit at bin centres."""
+    cells = []
+    tracks = []
+    for _ in range(n_tracks):
+        k = int(rng.integers(0, base.n_qpt))
+        qpt = O.qpt_centre(g, k)
+        if abs(qpt) < 0.01:
+            continue
+        l = int(rng.integers(0, base.n_d0)) if displaced else (base.n_d0 - 1) // 2
+        d0 = O.d0_centre(g, l) if displaced else 0.0
+        b = int(rng.integers(0, base.n_phi))
+        phi0 = (b + 0.5) * 2 * np.pi / base.n_phi
+        cells.append((l, k, b))
+        tracks.append((np.sign(qpt), abs(qpt), phi0, d0))
+    q, ipt, p0, d0 = (np.array(v) for v in zip(*tracks))
+    cfg = base.with_(smear_rphi_cm=smear)
+    x, y, z, lay, tid = synth._helix_hits(rng, cfg, q, ipt, p0, d0, np.zeros(len(q)), np.zeros(len(q)))
+    ev = synth.Event(x=x.astype(np.float32), y=y.astype(np.float32), z=None, layer=lay.astype(np.uint8),
+                     track_id=tid.astype(np.int32), truth={})
+    return ev, cells
+
+
+def test_vote_bin_centred_tracks_land_in_their_bin(oracle_mod):
+    """A noise-free helix with parameters at bin centres puts exactly one vote
+    per crossed layer into its generating bin (hits from independent
+    circle-circle geometry)."""
+    O = oracle_mod
+    rng = np.random.default_rng(6)
+    for base in (configs.C1, configs.small_variant(configs.C2, n_phi=512, n_qpt=64, n_d0=16)):
+        g = O.Cfg(base)
+        for _ in range(12):
+            ev, cells = _centred_track_event(base, g, O, rng, 1, displaced=base.n_d0 > 1)
+            if not cells or ev.n == 0:
+                continue
+            acc, _ = O.vote(g, ev)
+            l, k, b = cells[0]
+            assert acc[l, k, b] == ev.n, (base.name, cells, ev.n, acc[l, k].max())
+
+
+def test_vote_rotation_covariance(oracle_mod):
+    O = oracle_mod
+    base = configs.small_variant(configs.C2, n_tracks=25, n_phi=256, n_qpt=32, n_d0=8)
+    g = O.Cfg(base)
+    ev = synth.make_event(base, 3)
+    rot = synth.Event(x=-ev.y, y=ev.x.copy(), z=None, layer=ev.layer, track_id=ev.track_id, truth={})
+    a, _ = O.vote(g, ev)
+    b, _ = O.vote(g, rot)
+    np.testing.assert_array_equal(np.roll(a, base.n_phi // 4, axis=2), b)
+
+
+def _textbook_line_hough(x, y, n_theta, rho_min, rho_max, n_rho):
+    """Duda-Hart normal-form Hough: rho = x cos(theta) + y sin(theta)."""
+    acc = np.zeros((n_theta, n_rho), dtype=np.int64)
+    th = (np.arange(n_theta) + 0.5) * 2 * np.pi / n_theta
+    for xi, yi in zip(x, y):
+        rho = xi * np.cos(th) + yi * np.sin(th)
+        j = np.floor((rho - rho_min) / (rho_max - rho_min) * n_rho).astype(int)
+        m = (j >= 0) & (j < n_rho)
+        np.add.at(acc, (np.nonzero(m)[0], j[m]), 1)
+    return acc
+
+
+def test_vote_B0_is_textbook_line_hough(oracle_mod):
+    """With no field every track is a straight line and the transform is the
+    Duda-Hart normal-form line Hough with theta = phi0 + pi/2 and rho = d0.
+    Straight tracks (paper-style, one hit per layer) with (phi0, d0) at bin
+    centres put all their hits into one cell of both accumulators."""
+    O = oracle_mod
+    base = configs.C2.with_(name="lines", B_tesla=0.0, n_phi=256, n_qpt=1, n_d0=64)
+    g = O.Cfg(base)
+    rng = np.random.default_rng(7)
+    radii = np.asarray(base.radii_cm)
+    fine = 16  # textbook theta bins per phi0 bin
+    for _ in range(6):
+        b = int(rng.integers(0, 256)); l = int(rng.integers(8, 56))
+        phi0 = (b + 0.5) * 2 * np.pi / 256
+        d0 = -10.0 + (l + 0.5) * 20.0 / 64
+        t = np.array([np.cos(phi0), np.sin(phi0)])
+        n = np.array([-np.sin(phi0), np.cos(phi0)])
+        pts = [(d0 * n + np.sqrt(r * r - d0 * d0) * t, L) for L, r in enumerate(radii) if r > abs(d0)]
+        ev = synth.Event(x=np.array([p[0][0] for p in pts], np.float32),
+                         y=np.array([p[0][1] for p in pts], np.float32), z=None,
+                         layer=np.array([p[1] for p in pts], np.uint8),
+                         track_id=np.zeros(len(pts), np.int32), truth={})
+        acc, _ = O.vote(g, ev)
+        assert acc[l, 0, b] == ev.n
+        text = _textbook_line_hough(ev.x.astype(np.float64), ev.y.astype(np.float64), 256 * fine,
+                                    -10.0, 10.0, 64)
+        jt = ((b + 64) % 256) * fine  # theta = phi0 + pi/2
+        assert text[jt:jt + fine, l].max() == ev.n
+        # and nowhere else does the textbook transform collect all the hits,
+        # except at its own mirror image (theta + pi, -rho) of the same line
+        for j, m in np.argwhere(text == ev.n):
+            same = circ_diff(j // fine, (b + 64) % 256, 256) <= 1 and abs(m - l) <= 1
+            mirror = circ_diff(j // fine, (b + 192) % 256, 256) <= 1 and abs(m - (63 - l)) <= 1
+            assert same or mirror, (j, m)
+
+
+def test_vote_prompt_is_conformal_line_hough(oracle_mod):
+    """d0 = 0: the conformal map (u, v) = (x, y)/r^2 sends circles through the
+    origin to lines -u sin(phi0) + v cos(phi0) = c/2, so a textbook line Hough
+    in (u, v) finds (phi0, c) of each prompt track where the oracle does."""
+    O = oracle_mod
+    base = configs.C1
+    g = O.Cfg(base)
+    rng = np.random.default_rng(8)
+    ev, cells = _centred_track_event(base, g, O, rng, 8, displaced=False)
+    acc, _ = O.vote(g, ev)
+    x = ev.x.astype(np.float64); y = ev.y.astype(np.float64)
+    r2 = x * x + y * y
+    u, v = x / r2, y / r2
+    kappa = 0.299792458e-2 * base.B_tesla
+    cmax = kappa * 1.0
+    text = _textbook_line_hough(u, v, 256, -cmax / 2, cmax / 2, 256)  # rho = c/2, c in [-kappa, kappa]
+    for (l, k, b) in cells:
+        c = O.curvature(g, k)
+        assert acc[l, k, b] >= 9
+        j = int(((b + 0.5) / 256 * 2 * np.pi + np.pi / 2) % (2 * np.pi) / (2 * np.pi) * 256)
+        rb = int((c / 2 + cmax / 2) / cmax * 256)
+        win = [(m % 256, q) for m in range(j - 1, j + 2) for q in range(rb - 1, rb + 2) if 0 <= q < 256]
+        assert max(text[w] for w in win) >= 9
+
+
+# ------------------------------------------------------------------ peaks --
+def test_peaks_plateaus_and_ties(oracle_mod):
+    O = oracle_mod
+    base = _tiny_cfg(n_phi=8, n_qpt=4, n_d0=3)
+    g = O.Cfg(base)
+    acc = np.zeros((3, 4, 8), dtype=np.int32)
+    acc[1, 1, 2] = 5; acc[1, 1, 3] = 5              # run along phi0: first one wins
+    acc[0, 3, 7] = 9; acc[0, 3, 0] = 9              # run across the phi0 wrap: b = 7 precedes b = 0
+    acc[2, 2, 5] = 7; acc[2, 3, 5] = 7              # equal in neighbouring q/pT columns: lower k wins
+    acc[0, 0, 4] = 6; acc[1, 0, 4] = 6              # equal in neighbouring d0 planes: lower l wins
+    acc[2, 0, :] = 3                                 # a full ring of equal values: no peak
+    n, pk = O.peaks(g, acc, 2)
+    got = [tuple(p) for p in pk]
+    assert got == [(0, 0, 4, 6), (0, 3, 7, 9), (1, 1, 2, 5), (2, 2, 5, 7)], got
+    # threshold is inclusive
+    n, pk = O.peaks(g, acc, 9)
+    assert [tuple(p) for p in pk] == [(0, 3, 7, 9)]
+    n, pk = O.peaks(g, acc, 10)
+    assert n == 0
+
+
+def test_peaks_equal_maximum_filter_on_unique_values(oracle_mod):
+    """Without ties the rule is 'strict local maximum over the 26-neighbourhood'
+    (phi0 cyclic, edges clipped): scipy's maximum filter gives the same set."""
+    from scipy import ndimage
+    O = oracle_mod
+    rng = np.random.default_rng(9)
+    for shape in [(5, 6, 16), (1, 9, 32), (4, 1, 8)]:
+        base = _tiny_cfg(n_d0=shape[0], n_qpt=shape[1], n_phi=shape[2])
+        g = O.Cfg(base)
+        acc = rng.permutation(np.prod(shape)).reshape(shape).astype(np.int32)
+        thr = int(np.prod(shape) // 3)
+        mf = ndimage.maximum_filter(acc, size=3, mode=["constant", "constant", "wrap"], cval=-1)
+        want = np.argwhere((acc == mf) & (acc >= thr))
+        n, pk = O.peaks(g, acc, thr)
+        np.testing.assert_array_equal(pk[:, :3], want)
+        np.testing.assert_array_equal(pk[:, 3], acc[tuple(want.T)])
+
+
+def test_peaks_no_adjacent_equal_pairs_and_cap(oracle_mod):
+    O = oracle_mod
+    rng = np.random.default_rng(10)
+    base = _tiny_cfg(n_d0=6, n_qpt=10, n_phi=32)
+    g = O.Cfg(base)
+    acc = rng.integers(0, 4, size=(6, 10, 32)).astype(np.int32)
+    n, pk = O.peaks(g, acc, 1)
+    s = set(map(tuple, pk[:, :3]))
+    for l, k, b in s:
+        for dl in (-1, 0, 1):
+            for dk in (-1, 0, 1):
+                for db in (-1, 0, 1):
+                    if (dl, dk, db) != (0, 0, 0):
+                        assert (l + dl, k + dk, (b + db) % 32) not in s or \
+                            acc[l, k, b] != acc[l + dl, k + dk, (b + db) % 32]
+    lin = (pk[:, 0] * 10 + pk[:, 1]) * 32 + pk[:, 2]
+    assert np.all(np.diff(lin) > 0)
+    n2, pk2 = O.peaks(g, acc, 1, cap=5)
+    assert n2 == n and pk2.shape[0] == 5
+    np.testing.assert_array_equal(pk2, pk[:5])
+
+
+def test_peaks_rotation_covariance(oracle_mod):
+    O = oracle_mod
+    base = configs.small_variant(configs.C2, n_tracks=25, n_phi=128, n_qpt=32, n_d0=8)
+    g = O.Cfg(base)
+    ev = synth.make_event(base, 4)
+    rot = synth.Event(x=-ev.y, y=ev.x.copy(), z=None, layer=ev.layer, track_id=ev.track_id, truth={})
+    a, _ = O.vote(g, ev)
+    b, _ = O.vote(g, rot)
+    na, pa = O.peaks(g, a, 4)
+    nb, pb = O.peaks(g, b, 4)
+    assert na == nb > 0
+    pa = pa.copy()
+    pa[:, 2] = (pa[:, 2] + 32) % 128
+    key = lambda p: ((p[:, 0] * 32 + p[:, 1]) * 128 + p[:, 2])
+    np.testing.assert_array_equal(pa[np.argsort(key(pa))], pb)
+
+
+# ----------------------------------------------------------------- assign --
+def test_assign_bruteforce_and_counts(oracle_mod):
+    O = oracle_mod
+    rng = np.random.default_rng(11)
+    base = _tiny_cfg(n_phi=32, n_qpt=8, n_d0=4)
+    g = O.Cfg(base)
+    M = O.angle_bits(g)
+    ev = _tiny_event(rng, 40)
+    acc, _ = O.vote(g, ev)
+    n, pk = O.peaks(g, acc, 1)
+    offs, hit_idx, tot = O.assign(g, ev, pk)
+    assert tot == pk[:, 3].sum() == offs[-1]
+    np.testing.assert_array_equal(np.diff(offs), pk[:, 3])
+    phi, ok = O.prep(ev, 10)
+    for p, (l, k, b, v) in enumerate(pk):
+        lst = hit_idx[offs[p]:offs[p + 1]]
+        assert np.all(np.diff(lst) > 0)
+        want = []
+        for h in range(ev.n):
+            if not ok[h]:
+                continue
+            okE, E = O.sample(base.radii_cm[ev.layer[h]], O.curvature(g, l * 0 + k), O.d0_centre(g, l), M)
+            if okE and ((int(phi[h]) >> (32 - M)) - E) % (1 << M) // (1 << base.frac_bits) == b:
+                want.append(h)
+        assert list(lst) == want
+    # capacity: truncated list, true total
+    offs2, hit2, tot2 = O.assign(g, ev, pk, cap_pairs=7)
+    assert tot2 == tot and len(hit2) == 7
+    np.testing.assert_array_equal(hit2, hit_idx[:7])
+
+
+# ------------------------------------------------------------------ zvote --
+def test_arclen_closed_forms(oracle_mod):
+    O = oracle_mod
+    # straight line from the origin: s = r
+    ok, S = O.arclen(50.0, 0.0, 0.0)
+    assert ok and S == 50 * 65536
+    # straight displaced line: s = sqrt(r^2 - d^2)
+    ok, S = O.arclen(10.0, 0.0, 6.0)
+    assert ok and S == 8 * 65536
+    # prompt circle: chord r, arc (2/|c|) asin(|c| r / 2)
+    c, r = 0.01, 60.0
+    ok, S = O.arclen(r, c, 0.0)
+    assert ok and abs(S / 65536 - 2 / c * math.asin(c * r / 2)) < 2e-5
+
+
+def test_arclen_matches_generator_geometry(oracle_mod):
+    O = oracle_mod
+    rng = np.random.default_rng(12)
+    base = configs.C4
+    g = O.Cfg(base)
+    for _ in range(20):
+        k = int(rng.integers(0, base.n_qpt)); l = int(rng.integers(0, base.n_d0))
+        qpt, d0 = O.qpt_centre(g, k), O.d0_centre(g, l)
+        if abs(qpt) < 0.01:
+            continue
+        phi0 = rng.uniform(0, 2 * np.pi)
+        R = synth._radius_cm(np.array([abs(qpt)]), base.B_tesla)
+        q = np.sign(qpt)
+        nx, ny = -np.sin(phi0), np.cos(phi0)
+        px, py = d0 * nx, d0 * ny
+        cx, cy = px - q * R * nx, py - q * R * ny
+        X, Y, arc, okm = synth._first_crossings(cx, cy, R, np.array([-q]), np.array([px]), np.array([py]),
+                                                base.radii_cm)
+        for L in range(10):
+            if not okm[0, L]:
+                continue
+            ok, S = O.arclen(base.radii_cm[L], O.curvature(g, k), d0)
+            assert ok
+            assert abs(S / 65536 - arc[0, L]) < 1e-3
+
+
+def test_zvote_bin_centred_track(oracle_mod):
+    O = oracle_mod
+    base = configs.C4
+    g = O.Cfg(base)
+    rng = np.random.default_rng(13)
+    for _ in range(5):
+        k = int(rng.integers(0, base.n_qpt))
+        qpt = O.qpt_centre(g, k)
+        if abs(qpt) < 0.05:
+            continue
+        l = int(rng.integers(base.n_d0 // 4, 3 * base.n_d0 // 4))
+        d0 = O.d0_centre(g, l)
+        m = int(rng.integers(32, 96)); j = int(rng.integers(16, 112))
+        cot = O.cot_centre_q16(g, m) / 65536.0
+        z0 = base.z0_min + (j + 0.5) * (base.z0_max - base.z0_min) / base.n_z0
+        b = int(rng.integers(0, base.n_phi))
+        phi0 = (b + 0.5) * 2 * np.pi / base.n_phi
+        cfg = base.with_(smear_rphi_cm=0.0, smear_z_cm=0.0, halflen_cm=(1e4,) * 10)
+        x, y, z, lay, tid = synth._helix_hits(rng, cfg, np.array([np.sign(qpt)]), np.array([abs(qpt)]),
+                                              np.array([phi0]), np.array([d0]), np.array([z0]), np.array([cot]))
+        ev = synth.Event(x=x.astype(np.float32), y=y.astype(np.float32), z=z.astype(np.float32),
+                         layer=lay.astype(np.uint8), track_id=tid.astype(np.int32), truth={})
+        if ev.n < 3:
+            continue
+        pk = np.array([[l, k, b, ev.n]], dtype=np.int32)
+        offs, hit_idx, tot = O.assign(g, ev, pk)
+        assert tot == ev.n  # every hit sits in the generating bin
+        out = O.zvote(g, ev, pk, offs, hit_idx)
+        assert tuple(out[0]) == (m, j, ev.n)
+
+
+def test_zvote_empty_candidate(oracle_mod):
+    O = oracle_mod
+    g = O.Cfg(configs.C4)
+    ev = synth.Event(x=np.array([10.0], np.float32), y=np.array([0.0], np.float32),
+                     z=np.array([0.0], np.float32), layer=np.array([2], np.uint8),
+                     track_id=np.zeros(1, np.int32), truth={})
+    pk = np.array([[0, 0, 0, 0]], np.int32)
+    out = O.zvote(g, ev, pk, np.array([0, 0], np.int64), np.zeros(0, np.int32))
+    assert tuple(out[0]) == (-1, -1, 0)
+
+
+# -------------------------------------------------------------- generator --
+def test_generator_hits_on_layers_and_reproducible():
+    ev = synth.make_event(configs.C2, 0)
+    ev2 = synth.make_event(configs.C2, 0)
+    np.testing.assert_array_equal(ev.x, ev2.x)
+    r = np.hypot(ev.x.astype(np.float64), ev.y.astype(np.float64))
+    R = np.asarray(configs.RADII_CM)[ev.layer]
+    assert np.max(np.abs(r - R)) < 1e-4
+    n_track_hits = int((ev.track_id >= 0).sum())
+    assert int((ev.track_id < 0).sum()) == round(0.2 * n_track_hits)
+    assert 10000 < ev.n < 13000
+    ev3 = synth.make_event(configs.C2, 1)
+    assert ev3.n != ev.n or not np.array_equal(ev3.x, ev.x)
+
+
+def test_zvote_single_hit_tie_rule(oracle_mod):
+    """One hit votes once in every cot(theta) row: all maxima tie at 1 and the
+    lowest linear index (first cot row) must be reported."""
+    O = oracle_mod
+    base = configs.C4
+    g = O.Cfg(base)
+    l, k = base.n_d0 // 2 + 3, base.n_qpt // 2 + 40
+    ev = synth.Event(x=np.array([4.4], np.float32), y=np.array([0.0], np.float32),
+                     z=np.array([1.25], np.float32), layer=np.array([0], np.uint8),
+                     track_id=np.zeros(1, np.int32), truth={})
+    ok, S = O.arclen(4.4, O.curvature(g, k), O.d0_centre(g, l))
+    assert ok
+    cot0 = Fraction(base.cot_min) + Fraction(1, 2) * (Fraction(base.cot_max) - Fraction(base.cot_min)) / base.n_cot
+    z0 = Fraction(5, 4) - Fraction(S, 65536) * cot0
+    j = math.floor((z0 - base.z0_min) / (Fraction(base.z0_max - base.z0_min) / base.n_z0))
+    out = O.zvote(g, ev, np.array([[l, k, 0, 1]], np.int32), np.array([0, 1], np.int64),
+                  np.array([0], np.int32))
+    assert tuple(out[0]) == (0, j, 1)
