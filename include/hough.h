@@ -1,0 +1,171 @@
+/*
+ * hough.h -- C ABI of the MI355X (gfx950) Hough-transform track finder.
+ *
+ * The method (Halyo et al., "GPU Enhancement of the Trigger to Extend Physics
+ * Reach at the LHC"):
+ *   Sec. "Proposed Fast Tracking Algorithm", Fig. "hough" caption: every hit
+ *     votes for all track parameters it is compatible with; peaks of the
+ *     accumulated parameter space are the track candidates (local maxima);
+ *   Sec. "Preliminary Results", curved-track paragraph: curved tracks from
+ *     the interaction point use a two-parameter space; displaced curved
+ *     tracks need a third parameter (here: the transverse impact parameter
+ *     d0, so the space is phi0 x q/pT x d0);
+ *   Sec. "Preliminary Results", fitting paragraph: the hits of each
+ *     candidate are handed to a track fit (here: hough_assign lists them);
+ *   Sec. "Preliminary Results", data paragraph: hits, parameter space and
+ *     peak detection stay resident in GPU memory for the whole event.
+ *
+ * Discretisation ("fixed-point transform"; the paper is silent on it):
+ *   X, Y = round-half-even(x * 2^16), (y * 2^16) as int32 (Q16.16 cm);
+ *   Phi  = azimuth of (X, Y) in 32-bit binary angle measure (2^32 = 2 pi) by
+ *          30-step integer CORDIC (Volder 1959) with 16 guard bits;
+ *   M    = log2(n_phi) + frac_bits;  PhiM = Phi >> (32 - M);
+ *   per (layer L, d0 bin l, q/pT bin k), in IEEE double:
+ *          q_k = qpt_min + (k + 0.5) * ((qpt_max - qpt_min) / n_qpt)
+ *          d_l = d0_min  + (l + 0.5) * ((d0_max  - d0_min)  / n_d0)
+ *          c   = -(0.299792458e-2 * B) * q_k,   r = nominal radius of L
+ *          A   = (c * (r*r + d*d) + 2.0*d) / (2.0 * r * (1.0 + c*d))
+ *          valid iff the denominator > 0 and |A| <= 1
+ *          E   = llrint(asin(A) * 2^(M-1) / pi)
+ *   vote:  b = ((PhiM - E) mod 2^M) >> frac_bits;  acc[l][k][b] += 1.
+ *
+ * Conventions
+ *   - Every pointer marked (dev) is device memory owned by the caller; the
+ *     library never allocates or frees it.  A plan owns only its own
+ *     immutable device tables.
+ *   - All compute calls are asynchronous on the given stream (NULL = the
+ *     default stream), do not synchronise the host, and pass counts between
+ *     calls through device memory, so a vote -> peaks -> assign chain can be
+ *     captured in a hipGraph.
+ *   - Synchronous return codes report argument errors (HOUGH_E_*); data
+ *     errors are reported asynchronously in hough_status_t: bad hits are
+ *     skipped and counted; an output that exceeds its capacity is truncated
+ *     deterministically, its true size is stored and a flag is set.
+ *   - A plan may be used concurrently on several streams as long as the
+ *     output and workspace buffers of the calls are distinct.
+ *   - Results are bit-identical across runs, launch shapes and streams.
+ */
+#ifndef HOUGH_H
+#define HOUGH_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* return codes */
+#define HOUGH_OK 0
+#define HOUGH_E_INVAL (-1)       /* null pointer, negative size, size beyond a limit  */
+#define HOUGH_E_UNSUPPORTED (-2) /* grid or geometry outside what the kernels support */
+#define HOUGH_E_HIP (-3)         /* a HIP runtime call failed (launch, copy, ...)     */
+#define HOUGH_E_NOMEM (-4)       /* plan tables could not be allocated                */
+#define HOUGH_E_SMALL_WS (-5)    /* workspace smaller than the size query returned    */
+
+/* status flags */
+#define HOUGH_F_PEAK_OVERFLOW 1  /* more peaks than cap: first cap written             */
+#define HOUGH_F_PAIR_OVERFLOW 2  /* more hit-candidate pairs than cap: first cap written */
+#define HOUGH_F_TOO_MANY_HITS 4  /* n > max_hits_per_event of the plan: nothing voted  */
+
+typedef struct {
+    int32_t n_layers;          /* 1..32 */
+    const double* r_cm;        /* [n_layers] nominal layer radii (host memory, copied) */
+    const double* halflen_cm;  /* [n_layers] or NULL (informational)                   */
+    double B_tesla;            /* solenoid field along +z                              */
+} hough_geometry_t;
+
+typedef struct {
+    int32_t n_phi;             /* phi0 bins, power of two, 16..4096                    */
+    int32_t n_qpt;             /* q/pT bins (multiple of 64)                           */
+    int32_t n_d0;              /* d0 bins (1 = prompt 2-D search)                      */
+    int32_t frac_bits;         /* angle bits below one phi0 bin: 8 (int32), 7 (int16)  */
+    double qpt_min, qpt_max;   /* GeV^-1                                               */
+    double d0_min, d0_max;     /* cm                                                   */
+    int32_t acc_bits;          /* 32 or 16 (int16 requires max_hits_per_event < 32768) */
+    int32_t n_cot, n_z0;       /* second-stage r-z grid (0 = none)                     */
+    double cot_min, cot_max;   /* cot(theta) range                                     */
+    double z0_min, z0_max;     /* cm                                                   */
+    int32_t max_hits_per_event;
+} hough_grid_t;
+
+/* Structure-of-arrays hits of one event, device memory. */
+typedef struct {
+    const float* x;            /* (dev) [n] cm */
+    const float* y;            /* (dev) [n] cm */
+    const float* z;            /* (dev) [n] cm, may be NULL unless hough_zvote is used */
+    const uint8_t* layer;      /* (dev) [n] layer id                                   */
+    int32_t n;
+} hough_hits_t;
+
+typedef struct {
+    int32_t l, k, b, votes;    /* d0 bin, q/pT bin, phi0 bin, accumulator value        */
+} hough_peak_t;
+
+/* Written by the kernels (device memory, 32 bytes). */
+typedef struct {
+    int32_t n_hits;            /* hits given to the vote                               */
+    int32_t n_bad_hits;        /* skipped: non-finite, |coord| >= 32768 cm, layer out of
+                                  range, or at the origin                              */
+    int64_t n_votes;           /* hit-votes cast = sum of the accumulator              */
+    int32_t n_peaks;           /* true number of candidates (may exceed the capacity)  */
+    int32_t flags;             /* HOUGH_F_*                                            */
+    int64_t n_pairs;           /* true number of hit-candidate pairs                   */
+} hough_status_t;
+
+typedef struct hough_plan hough_plan_t;
+
+/* Create a plan on the current HIP device: validates geometry and grid and
+ * builds the per-(layer, d0, q/pT) sample table E (and, with a zvote grid,
+ * the arc-length table) in device memory.  Synchronous. */
+int hough_plan_create(const hough_geometry_t* geom, const hough_grid_t* grid, hough_plan_t** out);
+void hough_plan_destroy(hough_plan_t* plan);
+
+/* Sizes in bytes. */
+size_t hough_acc_bytes(const hough_plan_t* plan);             /* n_d0*n_qpt*n_phi*acc_bits/8 */
+size_t hough_event_ws_bytes(const hough_plan_t* plan, int32_t max_peaks);
+int32_t hough_angle_bits(const hough_plan_t* plan);           /* M */
+
+/* Copy the sample table E[L][l][k] (int32, INT32_MIN = invalid) to host memory
+ * `out` of n_layers*n_d0*n_qpt entries.  Synchronous; for tests. */
+int hough_plan_table(const hough_plan_t* plan, int32_t* out);
+
+/* a1 -- per-hit preparation: Q16.16 conversion, CORDIC azimuth, validity and
+ * bucketing of valid hits by (layer, azimuth cell) into the workspace.
+ * phi_out (dev, may be NULL): [n] 32-bit azimuth of each hit (0 when invalid).
+ * ws (dev): at least hough_event_ws_bytes bytes; st (dev): status, reset here. */
+int hough_prep(const hough_plan_t* plan, const hough_hits_t* hits, uint32_t* phi_out, void* ws,
+               size_t ws_bytes, hough_status_t* st, hipStream_t stream);
+
+/* a1 + a2 -- vote: prep, then acc[l][k][b] (dev, fully overwritten; int32 or
+ * int16 per acc_bits, b fastest).  The prepared hits stay in ws for
+ * hough_assign.  If n > max_hits_per_event the call returns HOUGH_E_INVAL. */
+int hough_vote(const hough_plan_t* plan, const hough_hits_t* hits, void* acc, void* ws, size_t ws_bytes,
+               hough_status_t* st, hipStream_t stream);
+
+/* a3 -- peaks: bin (l,k,b) is a candidate iff acc >= threshold and, against
+ * each of its 3x3x3 neighbours j (phi0 cyclic, q/pT and d0 clipped),
+ * acc > acc[j] when j precedes it and acc >= acc[j] otherwise; j precedes
+ * when (l_j, k_j) < (l, k) lexicographically or j is bin b-1 (mod n_phi) of
+ * the same column.  peaks (dev) [cap] in increasing linear index
+ * (l*n_qpt + k)*n_phi + b; st->n_peaks = true count. */
+int hough_peaks(const hough_plan_t* plan, const void* acc, int32_t threshold, hough_peak_t* peaks,
+                int32_t cap, void* ws, size_t ws_bytes, hough_status_t* st, hipStream_t stream);
+
+/* a4 -- assign: for each of the min(st->n_peaks, cap_peaks) candidates, the
+ * valid hits whose sample at (l, k) falls in bin b, in increasing hit index
+ * (so each list has `votes` entries).  CSR: offsets (dev) [cap_peaks+1]
+ * (int32), hit_idx (dev) [cap_pairs]; entries beyond cap_pairs are not
+ * written.  Uses the prepared hits left in ws by hough_vote of the same
+ * event. */
+int hough_assign(const hough_plan_t* plan, const hough_peak_t* peaks, int32_t cap_peaks, int32_t* offsets,
+                 int32_t* hit_idx, int32_t cap_pairs, void* ws, size_t ws_bytes, hough_status_t* st,
+                 hipStream_t stream);
+
+const char* hough_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HOUGH_H */

@@ -1,0 +1,230 @@
+"""Thin ctypes binding of libhough.so (include/hough.h).
+
+Argument marshalling only: every step of the path runs in the library's HIP
+kernels.  Tensors are used for device memory and streams; the library is
+loaded from this package directory and a missing library raises at import
+(there is no CPU fallback).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libhough.so")
+
+HOUGH_F_PEAK_OVERFLOW = 1
+HOUGH_F_PAIR_OVERFLOW = 2
+
+
+class HoughError(RuntimeError):
+    pass
+
+
+class Geometry(C.Structure):
+    _fields_ = [("n_layers", C.c_int32), ("r_cm", C.POINTER(C.c_double)),
+                ("halflen_cm", C.POINTER(C.c_double)), ("B_tesla", C.c_double)]
+
+
+class Grid(C.Structure):
+    _fields_ = [("n_phi", C.c_int32), ("n_qpt", C.c_int32), ("n_d0", C.c_int32), ("frac_bits", C.c_int32),
+                ("qpt_min", C.c_double), ("qpt_max", C.c_double), ("d0_min", C.c_double), ("d0_max", C.c_double),
+                ("acc_bits", C.c_int32), ("n_cot", C.c_int32), ("n_z0", C.c_int32),
+                ("cot_min", C.c_double), ("cot_max", C.c_double), ("z0_min", C.c_double), ("z0_max", C.c_double),
+                ("max_hits_per_event", C.c_int32)]
+
+
+class Hits(C.Structure):
+    _fields_ = [("x", C.c_void_p), ("y", C.c_void_p), ("z", C.c_void_p), ("layer", C.c_void_p), ("n", C.c_int32)]
+
+
+STATUS_BYTES = 32
+PEAK_INTS = 4
+
+
+def _load() -> C.CDLL:
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built: run `python -c 'import __graft_entry__ as g; g.build()'`")
+    L = C.CDLL(LIB_PATH)
+    P, S = C.c_void_p, C.c_size_t
+    L.hough_plan_create.restype = C.c_int
+    L.hough_plan_create.argtypes = [C.POINTER(Geometry), C.POINTER(Grid), C.POINTER(C.c_void_p)]
+    L.hough_plan_destroy.restype = None; L.hough_plan_destroy.argtypes = [P]
+    L.hough_acc_bytes.restype = S; L.hough_acc_bytes.argtypes = [P]
+    L.hough_event_ws_bytes.restype = S; L.hough_event_ws_bytes.argtypes = [P, C.c_int32]
+    L.hough_angle_bits.restype = C.c_int32; L.hough_angle_bits.argtypes = [P]
+    L.hough_plan_table.restype = C.c_int; L.hough_plan_table.argtypes = [P, P]
+    L.hough_prep.restype = C.c_int; L.hough_prep.argtypes = [P, C.POINTER(Hits), P, P, S, P, P]
+    L.hough_vote.restype = C.c_int; L.hough_vote.argtypes = [P, C.POINTER(Hits), P, P, S, P, P]
+    L.hough_peaks.restype = C.c_int
+    L.hough_peaks.argtypes = [P, P, C.c_int32, P, C.c_int32, P, S, P, P]
+    L.hough_assign.restype = C.c_int
+    L.hough_assign.argtypes = [P, P, C.c_int32, P, P, C.c_int32, P, S, P, P]
+    L.hough_strerror.restype = C.c_char_p; L.hough_strerror.argtypes = [C.c_int]
+    return L
+
+
+lib = _load()
+
+EXPORTED = ["hough_plan_create", "hough_plan_destroy", "hough_acc_bytes", "hough_event_ws_bytes",
+            "hough_angle_bits", "hough_plan_table", "hough_prep", "hough_vote", "hough_peaks",
+            "hough_assign", "hough_strerror"]
+
+
+def _check(rc: int, what: str) -> None:
+    if rc != 0:
+        raise HoughError(f"{what}: {lib.hough_strerror(rc).decode()} ({rc})")
+
+
+def _ptr(t: Optional[torch.Tensor]) -> Optional[int]:
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise HoughError("device tensor expected")
+    return t.data_ptr()
+
+
+def _stream(stream) -> Optional[int]:
+    if stream is None:
+        return torch.cuda.current_stream().cuda_stream
+    return stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+
+
+class Plan:
+    """A plan for one detector geometry and parameter grid (owns the sample table)."""
+
+    def __init__(self, cfg, max_hits: Optional[int] = None):
+        self.cfg = cfg
+        self._r = np.ascontiguousarray(cfg.radii_cm, dtype=np.float64)
+        self._hl = np.ascontiguousarray(cfg.halflen_cm, dtype=np.float64)
+        geo = Geometry(len(self._r), self._r.ctypes.data_as(C.POINTER(C.c_double)),
+                       self._hl.ctypes.data_as(C.POINTER(C.c_double)), cfg.B_tesla)
+        self.max_hits = int(max_hits if max_hits is not None else cfg.max_hits_per_event)
+        grid = Grid(cfg.n_phi, cfg.n_qpt, cfg.n_d0, cfg.frac_bits, cfg.qpt_min, cfg.qpt_max, cfg.d0_min,
+                    cfg.d0_max, cfg.acc_bits, cfg.n_cot, cfg.n_z0, cfg.cot_min, cfg.cot_max, cfg.z0_min,
+                    cfg.z0_max, self.max_hits)
+        h = C.c_void_p()
+        _check(lib.hough_plan_create(C.byref(geo), C.byref(grid), C.byref(h)), "hough_plan_create")
+        self.handle = h.value
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib.hough_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def acc_bytes(self) -> int:
+        return int(lib.hough_acc_bytes(self.handle))
+
+    @property
+    def acc_dtype(self):
+        return torch.int32 if self.cfg.acc_bits == 32 else torch.int16
+
+    @property
+    def angle_bits(self) -> int:
+        return int(lib.hough_angle_bits(self.handle))
+
+    def ws_bytes(self, max_peaks: int = 0) -> int:
+        return int(lib.hough_event_ws_bytes(self.handle, int(max_peaks)))
+
+    def table(self) -> np.ndarray:
+        c = self.cfg
+        out = np.zeros((c.n_layers, c.n_d0, c.n_qpt), dtype=np.int32)
+        _check(lib.hough_plan_table(self.handle, out.ctypes.data), "hough_plan_table")
+        return out
+
+
+def make_hits(x: torch.Tensor, y: torch.Tensor, layer: torch.Tensor, z: Optional[torch.Tensor] = None) -> Hits:
+    n = int(x.shape[0])
+    for t, dt in ((x, torch.float32), (y, torch.float32), (layer, torch.uint8)):
+        if t.dtype != dt or not t.is_contiguous() or int(t.shape[0]) != n:
+            raise HoughError("hits must be contiguous float32 x, y and uint8 layer of equal length")
+    return Hits(_ptr(x), _ptr(y), _ptr(z), _ptr(layer), n)
+
+
+def prep(plan: Plan, hits: Hits, phi_out: Optional[torch.Tensor], ws: torch.Tensor, status: torch.Tensor,
+         stream=None) -> None:
+    _check(lib.hough_prep(plan.handle, C.byref(hits), _ptr(phi_out), _ptr(ws), ws.numel(), _ptr(status),
+                          _stream(stream)), "hough_prep")
+
+
+def vote(plan: Plan, hits: Hits, acc: torch.Tensor, ws: torch.Tensor, status: torch.Tensor, stream=None) -> None:
+    if acc.numel() * acc.element_size() < plan.acc_bytes:
+        raise HoughError("accumulator too small")
+    _check(lib.hough_vote(plan.handle, C.byref(hits), _ptr(acc), _ptr(ws), ws.numel(), _ptr(status),
+                          _stream(stream)), "hough_vote")
+
+
+def peaks(plan: Plan, acc: torch.Tensor, threshold: int, out: torch.Tensor, ws: torch.Tensor,
+          status: torch.Tensor, stream=None) -> None:
+    cap = out.shape[0]
+    _check(lib.hough_peaks(plan.handle, _ptr(acc), int(threshold), _ptr(out), int(cap), _ptr(ws), ws.numel(),
+                           _ptr(status), _stream(stream)), "hough_peaks")
+
+
+def assign(plan: Plan, pk: torch.Tensor, offsets: torch.Tensor, hit_idx: torch.Tensor, ws: torch.Tensor,
+           status: torch.Tensor, stream=None) -> None:
+    cap_peaks = pk.shape[0]
+    if offsets.numel() < cap_peaks + 1:
+        raise HoughError("offsets needs cap_peaks + 1 entries")
+    _check(lib.hough_assign(plan.handle, _ptr(pk), int(cap_peaks), _ptr(offsets), _ptr(hit_idx),
+                            int(hit_idx.numel()), _ptr(ws), ws.numel(), _ptr(status), _stream(stream)),
+           "hough_assign")
+
+
+def status_dict(status: torch.Tensor) -> dict:
+    b = status.detach().to("cpu").numpy().view(np.uint8)[:STATUS_BYTES].tobytes()
+    n_hits, n_bad = np.frombuffer(b[0:8], dtype=np.int32)
+    (n_votes,) = np.frombuffer(b[8:16], dtype=np.int64)
+    n_peaks, flags = np.frombuffer(b[16:24], dtype=np.int32)
+    (n_pairs,) = np.frombuffer(b[24:32], dtype=np.int64)
+    return dict(n_hits=int(n_hits), n_bad_hits=int(n_bad), n_votes=int(n_votes), n_peaks=int(n_peaks),
+                flags=int(flags), n_pairs=int(n_pairs))
+
+
+class EventBuffers:
+    """Device buffers for one event of a plan: accumulator, workspace, status,
+    candidate list and CSR hit lists (caller-owned memory, reused per event)."""
+
+    def __init__(self, plan: Plan, cap_peaks: int, cap_pairs: int, device="cuda"):
+        self.plan = plan
+        c = plan.cfg
+        self.acc = torch.empty((c.n_d0, c.n_qpt, c.n_phi), dtype=plan.acc_dtype, device=device)
+        self.ws = torch.empty(plan.ws_bytes(cap_peaks), dtype=torch.uint8, device=device)
+        self.status = torch.zeros(STATUS_BYTES // 4, dtype=torch.int32, device=device)
+        self.peaks = torch.empty((cap_peaks, PEAK_INTS), dtype=torch.int32, device=device)
+        self.offsets = torch.empty(cap_peaks + 1, dtype=torch.int32, device=device)
+        self.hit_idx = torch.empty(cap_pairs, dtype=torch.int32, device=device)
+
+    def run(self, hits: Hits, threshold: int, stream=None, do_assign: bool = True) -> None:
+        vote(self.plan, hits, self.acc, self.ws, self.status, stream)
+        peaks(self.plan, self.acc, threshold, self.peaks, self.ws, self.status, stream)
+        if do_assign:
+            assign(self.plan, self.peaks, self.offsets, self.hit_idx, self.ws, self.status, stream)
+
+    def results(self) -> dict:
+        st = status_dict(self.status)
+        n = min(st["n_peaks"], self.peaks.shape[0])
+        pk = self.peaks[:n].cpu().numpy()
+        offs = self.offsets[: n + 1].cpu().numpy().astype(np.int64)
+        npairs = min(st["n_pairs"], self.hit_idx.numel())
+        hit_idx = self.hit_idx[:npairs].cpu().numpy()
+        return dict(status=st, peaks=pk, offsets=offs, hit_idx=hit_idx)
+
+
+def hits_to_device(ev, device="cuda"):
+    x = torch.from_numpy(np.ascontiguousarray(ev.x)).to(device)
+    y = torch.from_numpy(np.ascontiguousarray(ev.y)).to(device)
+    lay = torch.from_numpy(np.ascontiguousarray(ev.layer)).to(device)
+    z = torch.from_numpy(np.ascontiguousarray(ev.z)).to(device) if getattr(ev, "z", None) is not None else None
+    return x, y, lay, z
