@@ -318,22 +318,38 @@ int or_peak_at(const or_cfg_t* g, const int32_t* acc, int32_t l, int32_t k, int3
 
 /* ------------------------------------------------------------------------ */
 /* Step 7: assignment.  For each candidate p = (l_p, k_p, b_p), the valid    */
-/* hits whose sample at (l_p, k_p) is valid and falls in phi0 bin b_p, in    */
-/* increasing hit index (so the list length equals acc at the candidate).    */
+/* hits whose sample at (l_p, k_p) is valid and falls in phi0 bin b_p (so    */
+/* the list length equals acc at the candidate).  Order: layer by layer from */
+/* the innermost layer outwards, within a layer by the hit's angle inside    */
+/* the bin, rel = ((PhiM - E) mod 2^M) - b_p * 2^F, ties by hit index -- the */
+/* order in which a track fit meets the hits along the track.               */
 /* CSR output: offsets[0..n_peaks], hit_idx[offsets[p] .. offsets[p+1]),    */
 /* entries at positions >= cap_pairs are not written.  Returns the total.    */
 /* The sample values of the candidate's cell are evaluated once per layer    */
 /* for each candidate (they depend only on the layer, l_p and k_p).          */
 /* ------------------------------------------------------------------------ */
+typedef struct {
+    uint32_t rel;
+    int32_t h;
+} or_member_t;
+
+static int or_member_cmp(const void* a, const void* b)
+{
+    const or_member_t* x = (const or_member_t*)a;
+    const or_member_t* y = (const or_member_t*)b;
+    if (x->rel != y->rel) return x->rel < y->rel ? -1 : 1;
+    return (x->h > y->h) - (x->h < y->h);
+}
+
 int64_t or_assign(const or_cfg_t* g, int32_t n, const float* x, const float* y, const uint8_t* layer,
                   int32_t n_peaks, const int32_t* peaks, int64_t* offsets, int32_t* hit_idx,
                   int64_t cap_pairs)
 {
-    int32_t M = or_angle_bits(g), F = g->frac_bits, p, h, L;
+    int32_t M = or_angle_bits(g), F = g->frac_bits, p, h, L, i, m;
+    uint32_t mask = (M >= 32) ? 0xffffffffu : ((1u << M) - 1u);
     uint32_t* phiM = (uint32_t*)malloc(sizeof(uint32_t) * (size_t)(n > 0 ? n : 1));
     uint8_t* ok = (uint8_t*)malloc((size_t)(n > 0 ? n : 1));
-    int32_t* E = (int32_t*)malloc(sizeof(int32_t) * (size_t)g->n_layers);
-    uint8_t* Ev = (uint8_t*)malloc((size_t)g->n_layers);
+    or_member_t* mem = (or_member_t*)malloc(sizeof(or_member_t) * (size_t)(n > 0 ? n : 1));
     int64_t pos = 0;
     or_prep(n, x, y, layer, g->n_layers, phiM, ok);
     for (h = 0; h < n; h++) phiM[h] >>= (32 - M);
@@ -341,19 +357,28 @@ int64_t or_assign(const or_cfg_t* g, int32_t n, const float* x, const float* y, 
         int32_t lp = peaks[4 * p], kp = peaks[4 * p + 1], bp = peaks[4 * p + 2];
         double d = or_d0_centre(g, lp), c = or_curvature(g, kp);
         offsets[p] = pos;
-        for (L = 0; L < g->n_layers; L++) Ev[L] = (uint8_t)or_sample(g->r_cm[L], c, d, M, &E[L]);
-        for (h = 0; h < n; h++) {
-            if (!ok[h] || !Ev[layer[h]]) continue;
-            if (or_bin(phiM[h], E[layer[h]], M, F) != bp) continue;
-            if (pos < cap_pairs) hit_idx[pos] = h;
-            pos++;
+        for (L = 0; L < g->n_layers; L++) {
+            int32_t E;
+            if (!or_sample(g->r_cm[L], c, d, M, &E)) continue;
+            m = 0;
+            for (h = 0; h < n; h++) {
+                if (!ok[h] || layer[h] != L) continue;
+                if (or_bin(phiM[h], E, M, F) != bp) continue;
+                mem[m].rel = ((phiM[h] - (uint32_t)E) & mask) - ((uint32_t)bp << F);
+                mem[m].h = h;
+                m++;
+            }
+            qsort(mem, (size_t)m, sizeof(or_member_t), or_member_cmp);
+            for (i = 0; i < m; i++) {
+                if (pos < cap_pairs) hit_idx[pos] = mem[i].h;
+                pos++;
+            }
         }
     }
     offsets[n_peaks] = pos;
     free(phiM);
     free(ok);
-    free(E);
-    free(Ev);
+    free(mem);
     return pos;
 }
 

@@ -36,8 +36,11 @@ MUTATIONS = {
     "peaks_non_strict": ("if (precedes ? !(v > u) : !(v >= u)) return 0;", "if (!(v >= u)) return 0;"),
     "peaks_no_wrap": ("b2 = (b + db + Np) % Np;", "b2 = b + db; if (b2 < 0 || b2 >= Np) continue;"),
     "peaks_threshold_strict": ("if (v < thr) return 0;", "if (v <= thr) return 0;"),
-    "assign_wrong_bin": ("if (or_bin(phiM[h], E[layer[h]], M, F) != bp) continue;",
-                         "if (or_bin(phiM[h], E[layer[h]], M, F) != (bp + 1) % g->n_phi) continue;"),
+    "assign_wrong_bin": ("if (or_bin(phiM[h], E, M, F) != bp) continue;",
+                         "if (or_bin(phiM[h], E, M, F) != (bp + 1) % g->n_phi) continue;"),
+    "assign_order_by_hit_only": ("if (x->rel != y->rel) return x->rel < y->rel ? -1 : 1;", ""),
+    "assign_layer_descending": ("for (L = 0; L < g->n_layers; L++) {\n            int32_t E;",
+                                "for (L = g->n_layers - 1; L >= 0; L--) {\n            int32_t E;"),
     "zvote_sign": ("int64_t z0 = (int64_t)Z * 65536 - S * C[m] - z0min;", "int64_t z0 = (int64_t)Z * 65536 + S * C[m] - z0min;"),
     "arclen_half": ("s = (2.0 / fabs(c)) * asin(u);", "s = (1.0 / fabs(c)) * asin(u);"),
     "arclen_chord_sign": ("Lc2 = r * r + d * d - 2.0 * d * r * A;", "Lc2 = r * r + d * d + 2.0 * d * r * A;"),

@@ -503,15 +503,19 @@ def test_assign_bruteforce_and_counts(oracle_mod):
     phi, ok = O.prep(ev, 10)
     for p, (l, k, b, v) in enumerate(pk):
         lst = hit_idx[offs[p]:offs[p + 1]]
-        assert np.all(np.diff(lst) > 0)
+        # brute force by interval membership; order: layer, angle inside the bin, hit index
         want = []
         for h in range(ev.n):
             if not ok[h]:
                 continue
-            okE, E = O.sample(base.radii_cm[ev.layer[h]], O.curvature(g, l * 0 + k), O.d0_centre(g, l), M)
-            if okE and ((int(phi[h]) >> (32 - M)) - E) % (1 << M) // (1 << base.frac_bits) == b:
-                want.append(h)
-        assert list(lst) == want
+            okE, E = O.sample(base.radii_cm[ev.layer[h]], O.curvature(g, k), O.d0_centre(g, l), M)
+            if not okE:
+                continue
+            lo = (E + (int(b) << base.frac_bits)) % (1 << M)
+            rel = ((int(phi[h]) >> (32 - M)) - lo) % (1 << M)
+            if rel < (1 << base.frac_bits):
+                want.append((int(ev.layer[h]), rel, h))
+        assert list(lst) == [h for _, _, h in sorted(want)]
     # capacity: truncated list, true total
     offs2, hit2, tot2 = O.assign(g, ev, pk, cap_pairs=7)
     assert tot2 == tot and len(hit2) == 7
