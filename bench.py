@@ -1,0 +1,174 @@
+#!/usr/bin/env python3
+"""Throughput of the Hough-transform hot path on one MI355X.
+
+One step = one event through the whole path (prep -> vote -> peaks -> assign)
+on the dense single-event workload: 1000 helical tracks (10 % displaced) plus
+20 % noise hits, about 12k hits, voted into a 512 x 256 x 64 int32
+phi0 x q/pT x d0 accumulator (32 MiB), candidates at >= 7 votes that are local
+maxima of their 3x3x3 neighbourhood, and their CSR hit lists.  Inputs are
+resident in HBM before the timed region; every step recomputes everything.
+
+Prints one JSON line (see the keys below).  The `roofline` object is for the
+dominant kernel (the vote), timed with HIP events on the stream it runs on;
+`cpu_baseline` times the CPU oracle on the same event.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "events/s and hit-votes/s at 1 MI355X (batched vs plain), p99 event latency"
+# MI355X: 256 CUs at 2.4 GHz; an LDS atomic of a 64-wide wave (ds_add_u32) issues once per 4 clocks per CU
+# (16 lanes/clk/CU), so 256 * 2.4e9 * 16 = 9.83e12 atomic adds/s; one hit-vote is one LDS atomic.
+CUS, CLOCK_HZ, LDS_ATOMIC_LANES_PER_CLK = 256, 2.4e9, 16
+LDS_ATOMIC_PEAK_GVOTES = CUS * CLOCK_HZ * LDS_ATOMIC_LANES_PER_CLK / 1e9
+HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "vote_c2_traffic.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_1305_4855_amd", "csrc", "hough.hip")
+
+
+def src_hash() -> str:
+    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+
+
+def cpu_baseline(cfg, ev):
+    from oracle import oracle as O
+    O.build()
+    g = O.Cfg(cfg)
+    t0 = time.perf_counter()
+    acc, nv = O.vote(g, ev)
+    n, pk = O.peaks(g, acc, cfg.threshold)
+    O.assign(g, ev, pk)
+    dt = time.perf_counter() - t0
+    cores = int(os.environ.get("OMP_NUM_THREADS") or os.cpu_count() or 1)
+    return {"value": round(1.0 / dt, 4), "unit": "events/s", "cores": cores, "kind": "oracle",
+            "sample": (f"1 full event of the same workload ({ev.n} hits, {nv} hit-votes, {n} candidates): "
+                       f"vote on {cores} OpenMP threads, peaks and assign single-threaded; {dt:.1f} s"),
+            "hit_votes_per_s": round(nv / dt, 1)}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--pmc-calibration", action="store_true",
+                    help="also run a plain 256 MiB device copy (for scaling HBM counters)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for --gpus {args.gpus})",
+              file=sys.stderr)
+        return 2
+
+    import torch
+
+    from paper_1305_4855_amd import configs, synth
+    from paper_1305_4855_amd import hough as H
+
+    torch.cuda.set_device(0)
+    cfg = configs.C2
+    ev = synth.make_event(cfg, 0)
+    plan = H.Plan(cfg, max_hits=16384)
+    bufs = H.EventBuffers(plan, cap_peaks=1 << 19, cap_pairs=1 << 24)
+    x, y, lay, _ = H.hits_to_device(ev)
+    hits = H.make_hits(x, y, lay)
+    stream = torch.cuda.current_stream()
+
+    if args.pmc_calibration:
+        a = torch.empty(64 << 20, dtype=torch.int32, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+
+    def step(ev_pair=None):
+        H.prep(plan, hits, None, bufs.ws, bufs.status, stream)
+        if ev_pair is not None:
+            ev_pair[0].record(stream)
+        H.vote_prepared(plan, bufs.acc, bufs.ws, bufs.status, stream)
+        if ev_pair is not None:
+            ev_pair[1].record(stream)
+        H.peaks(plan, bufs.acc, cfg.threshold, bufs.peaks, bufs.ws, bufs.status, stream)
+        H.assign(plan, bufs.peaks, bufs.offsets, bufs.hit_idx, bufs.ws, bufs.status, stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    pairs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+             for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step(pairs[i])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    vote_ms = sum(a.elapsed_time(b) for a, b in pairs) / args.steps
+
+    # per-stage breakdown (separate, untimed for the headline number)
+    stage_ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
+    reps = 20
+    stage_ms = [0.0] * 4
+    for _ in range(reps):
+        stage_ev[0].record(stream)
+        H.prep(plan, hits, None, bufs.ws, bufs.status, stream)
+        stage_ev[1].record(stream)
+        H.vote_prepared(plan, bufs.acc, bufs.ws, bufs.status, stream)
+        stage_ev[2].record(stream)
+        H.peaks(plan, bufs.acc, cfg.threshold, bufs.peaks, bufs.ws, bufs.status, stream)
+        stage_ev[3].record(stream)
+        H.assign(plan, bufs.peaks, bufs.offsets, bufs.hit_idx, bufs.ws, bufs.status, stream)
+        stage_ev[4].record(stream)
+        torch.cuda.synchronize()
+        for j in range(4):
+            stage_ms[j] += stage_ev[j].elapsed_time(stage_ev[j + 1]) / reps
+    st = H.status_dict(bufs.status)
+
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    events_per_s = 1e3 / ms_per_step
+    achieved = st["n_votes"] / (vote_ms * 1e-3) / 1e9
+    traffic = None
+    if os.path.exists(TRAFFIC_FILE):
+        tr = json.load(open(TRAFFIC_FILE))
+        if tr.get("kernel_src_sha256_16") == src_hash():
+            traffic = tr.get("hbm_bytes_per_launch")
+    out = {
+        "metric": METRIC,
+        "value": round(events_per_s, 2),
+        "unit": "events/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": "dense single event, 3-D displaced search (c2)", "mode": "plain",
+                   "tracks": 1000, "noise_frac": 0.2, "displaced_frac": 0.1, "hits": ev.n,
+                   "grid": [cfg.n_phi, cfg.n_qpt, cfg.n_d0], "acc": "int32", "threshold": cfg.threshold},
+        "hit_votes_per_s": round(st["n_votes"] * events_per_s, 1),
+        "per_event": {"hit_votes": st["n_votes"], "candidates": st["n_peaks"], "pairs": st["n_pairs"],
+                      "bad_hits": st["n_bad_hits"]},
+        "stages_ms": {k: round(v, 5) for k, v in zip(("prep", "vote", "peaks", "assign"), stage_ms)},
+        "roofline": {"kernel": "k_vote", "bound": "alu", "achieved": round(achieved, 1),
+                     "peak": LDS_ATOMIC_PEAK_GVOTES, "unit": "Gvote/s (LDS atomic adds)",
+                     "frac": round(achieved / LDS_ATOMIC_PEAK_GVOTES, 4), "traffic": traffic,
+                     "avg_launch_ms": round(vote_ms, 5), "votes_per_launch": st["n_votes"]},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(cfg, ev)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -67,7 +67,6 @@ extern "C" {
 /* status flags */
 #define HOUGH_F_PEAK_OVERFLOW 1  /* more peaks than cap: first cap written             */
 #define HOUGH_F_PAIR_OVERFLOW 2  /* more hit-candidate pairs than cap: first cap written */
-#define HOUGH_F_TOO_MANY_HITS 4  /* n > max_hits_per_event of the plan: nothing voted  */
 
 typedef struct {
     int32_t n_layers;          /* 1..32 */
@@ -131,8 +130,8 @@ int32_t hough_angle_bits(const hough_plan_t* plan);           /* M */
  * `out` of n_layers*n_d0*n_qpt entries.  Synchronous; for tests. */
 int hough_plan_table(const hough_plan_t* plan, int32_t* out);
 
-/* a1 -- per-hit preparation: Q16.16 conversion, CORDIC azimuth, validity and
- * bucketing of valid hits by (layer, azimuth cell) into the workspace.
+/* a1 -- per-hit preparation: Q16.16 conversion, CORDIC azimuth, validity, and
+ * the valid hits sorted by (layer, M-bit angle, hit index) into the workspace.
  * phi_out (dev, may be NULL): [n] 32-bit azimuth of each hit (0 when invalid).
  * ws (dev): at least hough_event_ws_bytes bytes; st (dev): status, reset here. */
 int hough_prep(const hough_plan_t* plan, const hough_hits_t* hits, uint32_t* phi_out, void* ws,
@@ -144,21 +143,31 @@ int hough_prep(const hough_plan_t* plan, const hough_hits_t* hits, uint32_t* phi
 int hough_vote(const hough_plan_t* plan, const hough_hits_t* hits, void* acc, void* ws, size_t ws_bytes,
                hough_status_t* st, hipStream_t stream);
 
-/* a3 -- peaks: bin (l,k,b) is a candidate iff acc >= threshold and, against
- * each of its 3x3x3 neighbours j (phi0 cyclic, q/pT and d0 clipped),
+/* a2 alone -- the vote from hits already prepared in ws by hough_prep (or a
+ * previous hough_vote) of the same event; acc as for hough_vote. */
+int hough_vote_prepared(const hough_plan_t* plan, void* acc, void* ws, size_t ws_bytes, hough_status_t* st,
+                        hipStream_t stream);
+
+/* a3 -- peaks: bin (l,k,b) is a candidate iff acc >= threshold (>= 1) and,
+ * against each of its 3x3x3 neighbours j (phi0 cyclic, q/pT and d0 clipped),
  * acc > acc[j] when j precedes it and acc >= acc[j] otherwise; j precedes
  * when (l_j, k_j) < (l, k) lexicographically or j is bin b-1 (mod n_phi) of
  * the same column.  peaks (dev) [cap] in increasing linear index
- * (l*n_qpt + k)*n_phi + b; st->n_peaks = true count. */
+ * (l*n_qpt + k)*n_phi + b; st->n_peaks = true count.  Also leaves in ws the
+ * number of listed candidates and their CSR offsets for hough_assign
+ * (ws of at least hough_event_ws_bytes(plan, cap) bytes). */
 int hough_peaks(const hough_plan_t* plan, const void* acc, int32_t threshold, hough_peak_t* peaks,
                 int32_t cap, void* ws, size_t ws_bytes, hough_status_t* st, hipStream_t stream);
 
-/* a4 -- assign: for each of the min(st->n_peaks, cap_peaks) candidates, the
- * valid hits whose sample at (l, k) falls in bin b, in increasing hit index
- * (so each list has `votes` entries).  CSR: offsets (dev) [cap_peaks+1]
- * (int32), hit_idx (dev) [cap_pairs]; entries beyond cap_pairs are not
- * written.  Uses the prepared hits left in ws by hough_vote of the same
- * event. */
+/* a4 -- assign: for each of the first min(listed, cap_peaks) candidates of the
+ * preceding hough_peaks call on this ws, the valid hits whose sample at (l, k)
+ * falls in bin b (so each list has `votes` entries), ordered layer by layer
+ * from the innermost layer, within a layer by the angle inside the bin
+ * ((PhiM - E) mod 2^M - b * 2^frac_bits), ties by hit index.
+ * CSR: offsets (dev) [cap_peaks+1] (int32; offsets[i] is the prefix sum of the
+ * vote counts), hit_idx (dev) [cap_pairs]; entries beyond cap_pairs are not
+ * written; st->n_pairs = true total.  Uses the sorted hits left in ws by
+ * hough_vote (or hough_prep) of the same event. */
 int hough_assign(const hough_plan_t* plan, const hough_peak_t* peaks, int32_t cap_peaks, int32_t* offsets,
                  int32_t* hit_idx, int32_t cap_pairs, void* ws, size_t ws_bytes, hough_status_t* st,
                  hipStream_t stream);

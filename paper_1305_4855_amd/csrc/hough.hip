@@ -3,10 +3,11 @@
 // The operations (prep, vote, peaks, assign) and their exact integer
 // definitions are documented in include/hough.h.  This file is the MI355X
 // implementation:
-//   prep    per-hit Q16.16 + integer CORDIC azimuth, then a counting sort of
-//           the valid hits by (layer, azimuth cell) so that the vote reads
-//           each layer's hits as one contiguous run and the assignment can
-//           answer "which hits of layer L lie in this phi0 window" by cells;
+//   prep    per-hit Q16.16 + integer CORDIC azimuth (one thread per hit), then
+//           one workgroup sorts the valid hits by (layer, angle, hit index):
+//           LDS histogram over (layer, azimuth cell), scan, scatter, and a
+//           rank sort inside each cell; the vote reads each layer's hits as
+//           one contiguous run, the assignment finds a bin's hits as one run;
 //   vote    one workgroup per slab of 64 (l, k) columns holds the whole phi0
 //           range of its columns in LDS as [bin][column] (one 256-byte row per
 //           bin), loops over all hits of the event layer by layer and adds
@@ -16,11 +17,12 @@
 //           disjoint, integer sums are order independent);
 //   peaks   one thread per 8-bin strip of a column walks an l range keeping
 //           a 3-plane window in registers (separable 3-wide maxima), writes
-//           one flag byte per strip and per-group counts; a scan and a write
-//           pass compact the candidates in increasing linear index;
-//   assign  the CSR offsets are the prefix sums of the candidates' vote
-//           counts; each candidate gathers its hits from the cells its phi0
-//           window covers, layer by layer, and sorts them by hit index.
+//           one flag byte per strip and per-group candidate and vote counts;
+//           one tiled scan and a write pass compact the candidates in
+//           increasing linear index together with their CSR offsets (the
+//           prefix sums of their vote counts);
+//   assign  each candidate copies, layer by layer, the run of sorted hits
+//           whose angle falls into its phi0 window.
 #include <hip/hip_runtime.h>
 
 #include <climits>
@@ -42,6 +44,7 @@ constexpr int kStrip = 8;           // phi0 bins per peak-finder thread
 constexpr int kPeakPlanes = 8;      // d0 planes per peak-finder thread
 constexpr int kScanThreads = 1024;
 constexpr int kAssignBlock = 256;
+constexpr int kMaxCells = 32768;    // LDS histogram of the prep sort (128 KiB)
 
 struct CordicTable {
     int32_t t[kCordicSteps];
@@ -76,8 +79,8 @@ namespace {
 
 // ------------------------------------------------------------------ layout
 struct WsLayout {
-    size_t phi32, lay, cell_count, cell_start, cell_cursor, sorted_phi, sorted_h;
-    size_t flags, grp_count, grp_off, blk_sum, blk_off, misc, total;
+    size_t phi32, lay, cell_start, tmp_phi, tmp_h, sorted_phi, sorted_h;
+    size_t flags, grp_count, grp_votes, grp_off, grp_voff, peak_voff, misc, total;
 };
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
@@ -91,25 +94,26 @@ int64_t peak_groups(const hough_plan* p) {
     return p->n_bins / ((int64_t)kStrip * peak_group_lanes(p));
 }
 
+// Workspace of one event.  `misc` holds the number of candidates listed by the peaks pass (int32).
 WsLayout ws_layout(const hough_plan* p, int32_t max_peaks) {
     WsLayout L{};
     size_t o = 0;
     const size_t maxh = (size_t)p->g.max_hits_per_event;
     auto take = [&](size_t bytes) { size_t at = o; o = align_up(o + bytes, 256); return at; };
+    L.misc = take(256);  // first: its offset must not depend on max_peaks
     L.phi32 = take(4 * maxh);
     L.lay = take(maxh);
-    L.cell_count = take(4 * ((size_t)p->n_cells + 1));
     L.cell_start = take(4 * ((size_t)p->n_cells + 1));
-    L.cell_cursor = take(4 * ((size_t)p->n_cells + 1));
+    L.tmp_phi = take(4 * maxh);
+    L.tmp_h = take(4 * maxh);
     L.sorted_phi = take(4 * maxh);
     L.sorted_h = take(4 * maxh);
     L.flags = take((size_t)(p->n_bins / kStrip));
     L.grp_count = take(4 * (size_t)(peak_groups(p) + 1));
+    L.grp_votes = take(4 * (size_t)(peak_groups(p) + 1));
     L.grp_off = take(4 * (size_t)(peak_groups(p) + 1));
-    size_t nblk = (size_t)(max_peaks > 0 ? max_peaks : 1) / kAssignBlock + 2;
-    L.blk_sum = take(8 * nblk);
-    L.blk_off = take(8 * nblk);
-    L.misc = take(256);
+    L.grp_voff = take(8 * (size_t)(peak_groups(p) + 1));
+    L.peak_voff = take(8 * (size_t)(max_peaks > 0 ? max_peaks : 1));  // last: sized by max_peaks
     L.total = o;
     return L;
 }
@@ -152,110 +156,144 @@ __device__ __forceinline__ int32_t wave_sum(int32_t v) {
     return v;
 }
 
-// exclusive scan of n int32 counts by one workgroup of kScanThreads threads
-__device__ int64_t block_exclusive_scan(const int32_t* in, int32_t* out, int64_t n, int64_t* sums) {
-    __shared__ int64_t part[kScanThreads];
-    const int tid = threadIdx.x;
-    const int64_t per = (n + kScanThreads - 1) / kScanThreads;
-    const int64_t lo = per * tid, hi = lo + per < n ? lo + per : n;
-    int64_t s = 0;
-    for (int64_t i = lo; i < hi; ++i) s += in[i];
-    part[tid] = s;
-    __syncthreads();
-    for (int d = 1; d < kScanThreads; d <<= 1) {
-        int64_t v = tid >= d ? part[tid - d] : 0;
-        __syncthreads();
-        part[tid] += v;
-        __syncthreads();
+// Inclusive scan of one int64 value per thread over a workgroup of kScanThreads threads.
+// `wsum` is LDS scratch of kScanThreads / 64 entries.  Returns the inclusive prefix; *total = sum.
+__device__ __forceinline__ int64_t block_inclusive_scan(int64_t v, int64_t* wsum, int64_t* total) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int64_t u = __shfl_up(v, o, 64);
+        if (lane >= o) v += u;
     }
-    int64_t run = part[tid] - s;
-    for (int64_t i = lo; i < hi; ++i) {
-        int32_t c = in[i];
-        if (out) out[i] = (int32_t)run;
-        if (sums) sums[i] = run;
-        run += c;
-    }
-    int64_t total = part[kScanThreads - 1];
+    if (lane == 63) wsum[w] = v;
     __syncthreads();
-    return total;
+    if (w == 0) {
+        int64_t t = lane < kScanThreads / 64 ? wsum[lane] : 0;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int64_t u = __shfl_up(t, o, 64);
+            if (lane >= o) t += u;
+        }
+        if (lane < kScanThreads / 64) wsum[lane] = t;
+    }
+    __syncthreads();
+    const int64_t r = v + (w > 0 ? wsum[w - 1] : 0);
+    *total = wsum[kScanThreads / 64 - 1];
+    __syncthreads();
+    return r;
 }
 
 // ------------------------------------------------------------------ prep kernels
-__global__ void k_prep_init(int32_t* cell_count, int n_cells, hough_status_t* st, int32_t n_hits) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    for (; i <= n_cells; i += gridDim.x * blockDim.x) cell_count[i] = 0;
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        st->n_hits = n_hits;
-        st->n_bad_hits = 0;
-        st->n_votes = 0;
+// One thread per hit: validity, Q16.16, CORDIC azimuth.  No atomics.
+__global__ __launch_bounds__(256) void k_prep_hits(const float* __restrict__ hx, const float* __restrict__ hy,
+                                                   const uint8_t* __restrict__ hl, int32_t n, int n_layers,
+                                                   CordicTable T, uint32_t* __restrict__ phi32,
+                                                   uint8_t* __restrict__ lay, uint32_t* __restrict__ phi_out) {
+    const int h = blockIdx.x * blockDim.x + threadIdx.x;
+    if (h >= n) return;
+    const float x = hx[h], y = hy[h];
+    const uint8_t L = hl[h];
+    bool ok = (int)L < n_layers && isfinite(x) && isfinite(y) && fabsf(x) < 32768.0f && fabsf(y) < 32768.0f;
+    uint32_t phi = 0;
+    if (ok) {
+        // x * 2^16 is exact in float; round half to even
+        const int32_t X = __float2int_rn(x * 65536.0f);
+        const int32_t Y = __float2int_rn(y * 65536.0f);
+        ok = !(X == 0 && Y == 0);
+        if (ok) phi = cordic_azimuth(X, Y, T);
+    }
+    phi32[h] = phi;
+    lay[h] = ok ? L : (uint8_t)0xFF;
+    if (phi_out) phi_out[h] = phi;
+}
+
+// One workgroup: sort the valid hits by (layer, M-bit angle, hit index) and reset the status.
+//   1. LDS histogram over cells (layer, top `cell_bits` bits of the angle), counting bad hits;
+//   2. exclusive scan -> cell_start (global), hit-vote total from the per-layer counts;
+//   3. scatter into cell order (LDS cursors; arbitrary order inside a cell) -> tmp;
+//   4. rank inside the cell by (angle, hit index) -> sorted.
+__global__ __launch_bounds__(kScanThreads) void k_prep_sort(
+    const uint32_t* __restrict__ phi32, const uint8_t* __restrict__ lay, int32_t n, int n_layers, int cell_bits,
+    int M, LayerTable LT, int32_t* __restrict__ cell_start, uint32_t* __restrict__ tmp_phi,
+    int32_t* __restrict__ tmp_h, uint32_t* __restrict__ sorted_phi, int32_t* __restrict__ sorted_h,
+    hough_status_t* st) {
+    __shared__ int32_t cur[kMaxCells];
+    __shared__ int64_t wsum[kScanThreads / 64];
+    __shared__ int32_t layer_n[kMaxLayers];
+    const int tid = threadIdx.x;
+    const int n_cells = n_layers << cell_bits;
+    const int cshift = 32 - cell_bits;
+    for (int i = tid; i < n_cells; i += kScanThreads) cur[i] = 0;
+    __syncthreads();
+    int32_t bad = 0;
+    for (int h = tid; h < n; h += kScanThreads) {
+        const uint8_t L = lay[h];
+        if (L == 0xFF) {
+            ++bad;
+            continue;
+        }
+        atomicAdd(&cur[((int)L << cell_bits) | (int)(phi32[h] >> cshift)], 1);
+    }
+    __syncthreads();
+    // exclusive scan of the histogram: each thread owns a contiguous chunk
+    const int per = (n_cells + kScanThreads - 1) / kScanThreads;
+    const int lo = min(n_cells, tid * per), hi = min(n_cells, lo + per);
+    int64_t s = 0;
+    for (int i = lo; i < hi; ++i) s += cur[i];
+    int64_t tot;
+    int64_t run = block_inclusive_scan(s, wsum, &tot) - s;
+    int64_t bad_tot;
+    block_inclusive_scan(bad, wsum, &bad_tot);
+    for (int i = lo; i < hi; ++i) {
+        const int32_t c = cur[i];
+        cur[i] = (int32_t)run;
+        cell_start[i] = (int32_t)run;
+        run += c;
+    }
+    if (tid == 0) cell_start[n_cells] = (int32_t)tot;
+    __syncthreads();
+    if (tid < n_layers) {
+        const int a = cur[tid << cell_bits];
+        const int z = tid + 1 < n_layers ? cur[(tid + 1) << cell_bits] : (int32_t)tot;
+        layer_n[tid] = z - a;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        int64_t votes = 0;
+        for (int L = 0; L < n_layers; ++L) votes += (int64_t)layer_n[L] * LT.valid_cols[L];
+        st->n_hits = n;
+        st->n_bad_hits = (int32_t)bad_tot;
+        st->n_votes = votes;
         st->n_peaks = 0;
         st->flags = 0;
         st->n_pairs = 0;
     }
-}
-
-__global__ __launch_bounds__(256) void k_prep_hits(const float* __restrict__ hx, const float* __restrict__ hy,
-                                                   const uint8_t* __restrict__ hl, int32_t n, int n_layers,
-                                                   int cell_bits, CordicTable T, uint32_t* __restrict__ phi32,
-                                                   uint8_t* __restrict__ lay, uint32_t* __restrict__ phi_out,
-                                                   int32_t* __restrict__ cell_count, hough_status_t* st) {
-    const int h = blockIdx.x * blockDim.x + threadIdx.x;
-    bool ok = false;
-    uint32_t phi = 0;
-    uint8_t L = 0xFF;
-    if (h < n) {
-        const float x = hx[h], y = hy[h];
-        L = hl[h];
-        ok = (int)L < n_layers && isfinite(x) && isfinite(y) && fabsf(x) < 32768.0f && fabsf(y) < 32768.0f;
-        if (ok) {
-            // x * 2^16 is exact in float; round half to even
-            const int32_t X = __float2int_rn(x * 65536.0f);
-            const int32_t Y = __float2int_rn(y * 65536.0f);
-            ok = !(X == 0 && Y == 0);
-            if (ok) phi = cordic_azimuth(X, Y, T);
-        }
-        phi32[h] = phi;
-        lay[h] = ok ? L : (uint8_t)0xFF;
-        if (phi_out) phi_out[h] = phi;
-        if (ok) atomicAdd(&cell_count[((int)L << cell_bits) | (int)(phi >> (32 - cell_bits))], 1);
+    // scatter (cur[c] walks from the start of cell c to its end = the start of cell c + 1)
+    for (int h = tid; h < n; h += kScanThreads) {
+        const uint8_t L = lay[h];
+        if (L == 0xFF) continue;
+        const uint32_t phi = phi32[h];
+        const int pos = atomicAdd(&cur[((int)L << cell_bits) | (int)(phi >> cshift)], 1);
+        tmp_phi[pos] = phi >> (32 - M);
+        tmp_h[pos] = h;
     }
-    const uint64_t bad = __ballot(h < n && !ok);
-    if ((threadIdx.x & 63) == 0 && bad) atomicAdd(&st->n_bad_hits, (int32_t)__popcll(bad));
-}
-
-__global__ __launch_bounds__(kScanThreads) void k_prep_scan(const int32_t* __restrict__ cell_count,
-                                                            int32_t* __restrict__ cell_start,
-                                                            int32_t* __restrict__ cell_cursor, int n_cells,
-                                                            int n_layers, int cell_bits, LayerTable LT,
-                                                            hough_status_t* st) {
-    int64_t total = block_exclusive_scan(cell_count, cell_start, n_cells, nullptr);
-    for (int i = threadIdx.x; i < n_cells; i += blockDim.x) cell_cursor[i] = cell_start[i];
-    if (threadIdx.x == 0) cell_start[n_cells] = (int32_t)total;
+    __threadfence_block();
     __syncthreads();
-    if (threadIdx.x == 0) {
-        int64_t votes = 0;
-        for (int L = 0; L < n_layers; ++L) {
-            const int lo = cell_start[L << cell_bits];
-            const int hi = (L + 1 == n_layers) ? (int32_t)total : cell_start[(L + 1) << cell_bits];
-            votes += (int64_t)(hi - lo) * LT.valid_cols[L];
+    // rank inside the cell: final position = cell start + #{members with smaller (angle, hit)}
+    const int mshift = M - cell_bits;
+    for (int q = tid; q < (int)tot; q += kScanThreads) {
+        const uint32_t a = tmp_phi[q];
+        const int32_t h = tmp_h[q];
+        const int c = ((int)lay[h] << cell_bits) | (int)(a >> mshift);
+        const int c0 = c > 0 ? cur[c - 1] : 0, c1 = cur[c];
+        int rank = 0;
+        for (int j = c0; j < c1; ++j) {
+            const uint32_t b = tmp_phi[j];
+            rank += (b < a || (b == a && tmp_h[j] < h)) ? 1 : 0;
         }
-        st->n_votes = votes;
+        sorted_phi[c0 + rank] = a;
+        sorted_h[c0 + rank] = h;
     }
-}
-
-__global__ __launch_bounds__(256) void k_prep_scatter(const uint32_t* __restrict__ phi32,
-                                                      const uint8_t* __restrict__ lay, int32_t n, int cell_bits,
-                                                      int M, int32_t* __restrict__ cell_cursor,
-                                                      uint32_t* __restrict__ sorted_phi,
-                                                      int32_t* __restrict__ sorted_h) {
-    const int h = blockIdx.x * blockDim.x + threadIdx.x;
-    if (h >= n) return;
-    const uint8_t L = lay[h];
-    if (L == 0xFF) return;
-    const uint32_t phi = phi32[h];
-    const int pos = atomicAdd(&cell_cursor[((int)L << cell_bits) | (int)(phi >> (32 - cell_bits))], 1);
-    sorted_phi[pos] = phi >> (32 - M);
-    sorted_h[pos] = h;
 }
 
 // ------------------------------------------------------------------ vote
@@ -429,14 +467,15 @@ __device__ __forceinline__ void load_plane(const T* __restrict__ acc, int l, int
 template <typename T>
 __global__ __launch_bounds__(256) void k_peaks_mark(const T* __restrict__ acc, int32_t thr, int n_d0, int n_qpt,
                                                     int n_phi, int group_lanes, uint8_t* __restrict__ flags,
-                                                    int32_t* __restrict__ grp_count) {
+                                                    int32_t* __restrict__ grp_count,
+                                                    int32_t* __restrict__ grp_votes) {
     const int strips = n_phi / kStrip;
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int s = (int)(t % strips);
     const int k = (int)((t / strips) % n_qpt);
     const int lr = (int)(t / ((int64_t)strips * n_qpt));
     const int l0 = lr * kPeakPlanes;
-    if (l0 >= n_d0) return;  // whole groups exit together (groups never straddle planes)
+    if (l0 >= n_d0) return;  // whole waves exit together (strips * n_qpt is a multiple of 64)
     const int l1 = min(n_d0, l0 + kPeakPlanes);
     PlaneWin prev, cur, next;
     load_plane(acc, l0 - 1, k, s, n_d0, n_qpt, n_phi, prev);
@@ -444,6 +483,7 @@ __global__ __launch_bounds__(256) void k_peaks_mark(const T* __restrict__ acc, i
     for (int l = l0; l < l1; ++l) {
         load_plane(acc, l + 1, k, s, n_d0, n_qpt, n_phi, next);
         uint32_t bits = 0;
+        int32_t vsum = 0;
 #pragma unroll
         for (int i = 0; i < kStrip; ++i) {
             const int32_t v = cur.mid[i + 1];
@@ -451,184 +491,186 @@ __global__ __launch_bounds__(256) void k_peaks_mark(const T* __restrict__ acc, i
             // neighbours that follow must be <= v
             const int32_t P = max(max(prev.all[i], cur.lo[i]), cur.mid[i]);
             const int32_t Q = max(max(next.all[i], cur.hi[i]), cur.mid[i + 2]);
-            if (v >= thr && v > P && v >= Q) bits |= 1u << i;
+            if (v >= thr && v > P && v >= Q) {
+                bits |= 1u << i;
+                vsum += v;
+            }
         }
         const int64_t strip_id = ((int64_t)l * n_qpt + k) * strips + s;
         flags[strip_id] = (uint8_t)bits;
-        // per-group counts: a group is `group_lanes` consecutive strips of one column
+        // per-group sums: a group is `group_lanes` consecutive strips of one column
         int32_t cnt = __popc(bits);
-        for (int o = group_lanes >> 1; o >= 1; o >>= 1) cnt += __shfl_xor(cnt, o, 64);
-        if ((threadIdx.x & (group_lanes - 1)) == 0) grp_count[strip_id / group_lanes] = cnt;
+        for (int o = group_lanes >> 1; o >= 1; o >>= 1) {
+            cnt += __shfl_xor(cnt, o, 64);
+            vsum += __shfl_xor(vsum, o, 64);
+        }
+        if ((threadIdx.x & (group_lanes - 1)) == 0) {
+            grp_count[strip_id / group_lanes] = cnt;
+            grp_votes[strip_id / group_lanes] = vsum;
+        }
         prev = cur;
         cur = next;
     }
 }
 
+// One workgroup, tiles of kScanThreads * 16 groups: exclusive prefix sums of the per-group
+// candidate counts (grp_off, int32) and vote counts (grp_voff, int64).
+constexpr int kScanPer = 8;
 __global__ __launch_bounds__(kScanThreads) void k_peaks_scan(const int32_t* __restrict__ grp_count,
-                                                             int32_t* __restrict__ grp_off, int64_t n_groups,
-                                                             int32_t cap, hough_status_t* st) {
-    int64_t total = block_exclusive_scan(grp_count, grp_off, n_groups, nullptr);
-    if (threadIdx.x == 0) {
-        grp_off[n_groups] = (int32_t)min(total, (int64_t)INT32_MAX);
-        st->n_peaks = (int32_t)min(total, (int64_t)INT32_MAX);
-        if (total > cap) atomicOr(&st->flags, HOUGH_F_PEAK_OVERFLOW);
+                                                             const int32_t* __restrict__ grp_votes,
+                                                             int32_t* __restrict__ grp_off,
+                                                             int64_t* __restrict__ grp_voff, int64_t n_groups,
+                                                             int32_t cap, int32_t* __restrict__ listed,
+                                                             hough_status_t* st) {
+    __shared__ int32_t tc[kScanThreads * kScanPer];
+    __shared__ int32_t tv[kScanThreads * kScanPer];
+    __shared__ int64_t wsum[kScanThreads / 64];
+    const int tid = threadIdx.x;
+    int64_t carry_c = 0, carry_v = 0;
+    for (int64_t base = 0; base < n_groups; base += kScanThreads * kScanPer) {
+        const int m = (int)min((int64_t)kScanThreads * kScanPer, n_groups - base);
+        for (int i = tid; i < kScanThreads * kScanPer; i += kScanThreads) {
+            tc[i] = i < m ? grp_count[base + i] : 0;
+            tv[i] = i < m ? grp_votes[base + i] : 0;
+        }
+        __syncthreads();
+        int64_t sc = 0, sv = 0;
+        for (int j = 0; j < kScanPer; ++j) {
+            sc += tc[tid * kScanPer + j];
+            sv += tv[tid * kScanPer + j];
+        }
+        int64_t totc, totv;
+        int64_t rc = block_inclusive_scan(sc, wsum, &totc) - sc + carry_c;
+        int64_t rv = block_inclusive_scan(sv, wsum, &totv) - sv + carry_v;
+        for (int j = 0; j < kScanPer; ++j) {
+            const int i = tid * kScanPer + j;
+            if (i < m) {
+                grp_off[base + i] = (int32_t)min(rc, (int64_t)INT32_MAX);
+                grp_voff[base + i] = rv;
+            }
+            rc += tc[i];
+            rv += tv[i];
+        }
+        carry_c += totc;
+        carry_v += totv;
+        __syncthreads();
+    }
+    if (tid == 0) {
+        grp_off[n_groups] = (int32_t)min(carry_c, (int64_t)INT32_MAX);
+        grp_voff[n_groups] = carry_v;
+        st->n_peaks = (int32_t)min(carry_c, (int64_t)INT32_MAX);
+        *listed = (int32_t)min(carry_c, (int64_t)cap);
+        if (carry_c > cap) atomicOr(&st->flags, HOUGH_F_PEAK_OVERFLOW);
     }
 }
 
+// One thread per strip: writes its candidates and their vote-prefix (CSR offset) in linear order.
 template <typename T>
 __global__ __launch_bounds__(256) void k_peaks_write(const T* __restrict__ acc, const uint8_t* __restrict__ flags,
-                                                     const int32_t* __restrict__ grp_off, int n_qpt, int n_phi,
-                                                     int group_lanes, int64_t n_strips, hough_peak_t* peaks,
-                                                     int32_t cap) {
+                                                     const int32_t* __restrict__ grp_off,
+                                                     const int64_t* __restrict__ grp_voff, int64_t n_groups,
+                                                     int n_qpt, int n_phi, int group_lanes, int64_t n_strips,
+                                                     hough_peak_t* __restrict__ peaks,
+                                                     int64_t* __restrict__ peak_voff, int32_t cap) {
     const int strips = n_phi / kStrip;
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const uint32_t bits = t < n_strips ? flags[t] : 0u;
-    // exclusive prefix of the popcounts within the group
-    const int gl = threadIdx.x & (group_lanes - 1);
-    int32_t inc = __popc(bits);
-    for (int o = 1; o < group_lanes; o <<= 1) {
-        const int32_t v = __shfl_up(inc, o, group_lanes);
-        if (gl >= o) inc += v;
-    }
-    if (t >= n_strips || bits == 0) return;
-    int32_t pos = grp_off[t / group_lanes] + inc - __popc(bits);
     const int s = (int)(t % strips);
     const int64_t row = t / strips;
+    int32_t vs[kStrip];
+    int32_t vsum = 0;
+#pragma unroll
+    for (int i = 0; i < kStrip; ++i) vs[i] = 0;
+    if (bits) {  // only strips inside the accumulator have flags
+        const T* r = acc + row * n_phi;
+#pragma unroll
+        for (int i = 0; i < kStrip; ++i)
+            if (bits & (1u << i)) vs[i] = (int32_t)r[s * kStrip + i];
+    }
+#pragma unroll
+    for (int i = 0; i < kStrip; ++i) vsum += vs[i];
+    // inclusive prefix of candidate and vote counts within the group
+    const int gl = threadIdx.x & (group_lanes - 1);
+    int32_t inc = __popc(bits);
+    int32_t vinc = vsum;
+    for (int o = 1; o < group_lanes; o <<= 1) {
+        const int32_t a = __shfl_up(inc, o, group_lanes);
+        const int32_t b = __shfl_up(vinc, o, group_lanes);
+        if (gl >= o) {
+            inc += a;
+            vinc += b;
+        }
+    }
+    if (t >= n_strips || bits == 0) return;
+    const int64_t g = t / group_lanes;
+    int32_t pos = grp_off[g] + inc - __popc(bits);
+    int64_t voff = grp_voff[g] + vinc - vsum;
     const int k = (int)(row % n_qpt);
     const int l = (int)(row / n_qpt);
-    const T* r = acc + row * n_phi;
     for (int i = 0; i < kStrip; ++i) {
         if (!(bits & (1u << i))) continue;
         if (pos < cap) {
-            const int b = s * kStrip + i;
             hough_peak_t pk;
             pk.l = l;
             pk.k = k;
-            pk.b = b;
-            pk.votes = (int32_t)r[b];
+            pk.b = s * kStrip + i;
+            pk.votes = vs[i];
             peaks[pos] = pk;
+            peak_voff[pos] = voff;
         }
         ++pos;
+        voff += vs[i];
     }
 }
 
 // ------------------------------------------------------------------ assign
-__global__ __launch_bounds__(kAssignBlock) void k_assign_blocksum(const hough_peak_t* __restrict__ peaks,
-                                                                  int32_t cap_peaks, const hough_status_t* st,
-                                                                  int64_t* __restrict__ blk_sum) {
-    const int n = min(st->n_peaks, cap_peaks);
-    const int i = blockIdx.x * kAssignBlock + threadIdx.x;
-    if ((int)blockIdx.x * kAssignBlock >= n) return;
-    int32_t v = i < n ? peaks[i].votes : 0;
-    __shared__ int32_t red[kAssignBlock / 64];
-    v = wave_sum(v);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int64_t s = 0;
-        for (int w = 0; w < kAssignBlock / 64; ++w) s += red[w];
-        blk_sum[blockIdx.x] = s;
-    }
-}
-
-__global__ __launch_bounds__(kScanThreads) void k_assign_topscan(const int64_t* __restrict__ blk_sum,
-                                                                 int64_t* __restrict__ blk_off, int32_t cap_peaks,
-                                                                 int32_t* offsets, int32_t cap_pairs,
-                                                                 hough_status_t* st) {
-    const int n = min(st->n_peaks, cap_peaks);
-    const int nblk = (n + kAssignBlock - 1) / kAssignBlock;
-    __shared__ int64_t part[kScanThreads];
-    const int tid = threadIdx.x;
-    const int per = (nblk + kScanThreads - 1) / kScanThreads;
-    const int lo = per * tid, hi = min(nblk, lo + per);
-    int64_t s = 0;
-    for (int i = lo; i < hi; ++i) s += blk_sum[i];
-    part[tid] = s;
-    __syncthreads();
-    for (int d = 1; d < kScanThreads; d <<= 1) {
-        int64_t v = tid >= d ? part[tid - d] : 0;
-        __syncthreads();
-        part[tid] += v;
-        __syncthreads();
-    }
-    int64_t run = part[tid] - s;
-    for (int i = lo; i < hi; ++i) {
-        blk_off[i] = run;
-        run += blk_sum[i];
-    }
-    if (tid == 0) {
-        const int64_t total = part[kScanThreads - 1];
-        st->n_pairs = total;
-        offsets[n] = (int32_t)min(total, (int64_t)INT32_MAX);
-        if (total > cap_pairs) atomicOr(&st->flags, HOUGH_F_PAIR_OVERFLOW);
-    }
-}
-
+// One thread per listed candidate (the first min(listed, cap_peaks) written by the peaks pass):
+// CSR offset from the peaks pass, then for each layer the run(s)
+// of sorted hits with angle in [lo, lo + 2^F) (mod 2^M), lo = E + b * 2^F, copied in order.
 __global__ __launch_bounds__(kAssignBlock) void k_assign_fill(
-    const hough_peak_t* __restrict__ peaks, int32_t cap_peaks, const hough_status_t* st,
-    const int64_t* __restrict__ blk_off, const int32_t* __restrict__ E, const int32_t* __restrict__ cell_start,
-    const uint32_t* __restrict__ sorted_phi, const int32_t* __restrict__ sorted_h, int n_layers, int cell_bits,
-    int n_cols, int n_qpt, int M, int F, int32_t* __restrict__ offsets, int32_t* __restrict__ hit_idx,
-    int32_t cap_pairs) {
-    const int n = min(st->n_peaks, cap_peaks);
-    if ((int)blockIdx.x * kAssignBlock >= n) return;
+    const hough_peak_t* __restrict__ peaks, int32_t cap_peaks, hough_status_t* st,
+    const int64_t* __restrict__ peak_voff, const int32_t* __restrict__ listed,
+    const int32_t* __restrict__ E, const int32_t* __restrict__ cell_start, const uint32_t* __restrict__ sorted_phi,
+    const int32_t* __restrict__ sorted_h, int n_layers, int cell_bits, int n_cols, int n_qpt, int M, int F,
+    int32_t* __restrict__ offsets, int32_t* __restrict__ hit_idx, int32_t cap_pairs) {
+    const int n = min(*listed, cap_peaks);
     const int i = blockIdx.x * kAssignBlock + threadIdx.x;
-    const int32_t votes = i < n ? peaks[i].votes : 0;
-    // block-local exclusive scan of the vote counts
-    __shared__ int32_t sc[kAssignBlock];
-    sc[threadIdx.x] = votes;
-    __syncthreads();
-    for (int d = 1; d < kAssignBlock; d <<= 1) {
-        int32_t v = threadIdx.x >= d ? sc[threadIdx.x - d] : 0;
-        __syncthreads();
-        sc[threadIdx.x] += v;
-        __syncthreads();
+    if (i == 0) {
+        const int64_t tot = n > 0 ? peak_voff[n - 1] + peaks[n - 1].votes : 0;
+        offsets[n] = (int32_t)min(tot, (int64_t)INT32_MAX);
+        st->n_pairs = tot;
+        if (tot > cap_pairs) atomicOr(&st->flags, HOUGH_F_PAIR_OVERFLOW);
     }
     if (i >= n) return;
-    const int64_t off = blk_off[blockIdx.x] + sc[threadIdx.x] - votes;
+    const int64_t off = peak_voff[i];
     offsets[i] = (int32_t)min(off, (int64_t)INT32_MAX);
-    if (off >= cap_pairs || votes == 0) return;
-    const int64_t room = (int64_t)cap_pairs - off;
-    const int limit = (int)min((int64_t)votes, room);
-    int32_t* out = hit_idx + off;
-
+    if (off >= cap_pairs) return;
     const hough_peak_t pk = peaks[i];
-    const uint32_t maskM = (M >= 32) ? 0xFFFFFFFFu : ((1u << M) - 1u);
+    const uint32_t span = 1u << M;
     const uint32_t W = 1u << F;
     const int cshift = M - cell_bits;
-    const uint32_t n_cell = 1u << cell_bits;
-    int found = 0;
-    for (int L = 0; L < n_layers; ++L) {
+    int64_t w = off;
+    for (int L = 0; L < n_layers && w < cap_pairs; ++L) {
         const int32_t e = E[(size_t)L * n_cols + (size_t)pk.l * n_qpt + pk.k];
         if (e == INT32_MIN) continue;
-        // hits of layer L with PhiM in [lo, lo + W) (mod 2^M) fall into bin b
-        const uint32_t lo = ((uint32_t)e + ((uint32_t)pk.b << F)) & maskM;
-        const uint32_t c0 = lo >> cshift;
-        const uint32_t c1 = ((lo + W - 1) & maskM) >> cshift;
-        const uint32_t ncells = ((c1 - c0) & (n_cell - 1)) + 1;
-        for (uint32_t j = 0; j < ncells; ++j) {
-            const int cell = (L << cell_bits) | (int)((c0 + j) & (n_cell - 1));
-            const int a = cell_start[cell], z = cell_start[cell + 1];
-            for (int q = a; q < z; ++q) {
-                if (((sorted_phi[q] - lo) & maskM) >= W) continue;
-                const int32_t h = sorted_h[q];
-                // keep the `limit` smallest hit indices, ascending (insertion)
-                if (found < limit) {
-                    int p = found++;
-                    while (p > 0 && out[p - 1] > h) {
-                        out[p] = out[p - 1];
-                        --p;
-                    }
-                    out[p] = h;
-                } else if (out[limit - 1] > h) {
-                    int p = limit - 1;
-                    while (p > 0 && out[p - 1] > h) {
-                        out[p] = out[p - 1];
-                        --p;
-                    }
-                    out[p] = h;
-                }
-            }
+        const uint32_t lo = ((uint32_t)e + ((uint32_t)pk.b << F)) & (span - 1u);
+        const uint32_t hi = lo + W;  // may exceed 2^M: the window wraps
+        const int cb = L << cell_bits;
+        const int lay_end = cell_start[cb + (1 << cell_bits)];
+        // first hit with angle >= lo
+        int q = cell_start[cb + (int)(lo >> cshift)];
+        while (q < lay_end && sorted_phi[q] < lo) ++q;
+        if (hi <= span) {
+            int z = hi < span ? cell_start[cb + (int)(hi >> cshift)] : lay_end;
+            while (z < lay_end && sorted_phi[z] < hi) ++z;
+            for (; q < z && w < cap_pairs; ++q) hit_idx[w++] = sorted_h[q];
+        } else {
+            for (; q < lay_end && w < cap_pairs; ++q) hit_idx[w++] = sorted_h[q];
+            const uint32_t hw = hi - span;
+            int r = cell_start[cb];
+            int z = cell_start[cb + (int)(hw >> cshift)];
+            while (z < lay_end && sorted_phi[z] < hw) ++z;
+            for (; r < z && w < cap_pairs; ++r) hit_idx[w++] = sorted_h[r];
         }
     }
 }
@@ -684,6 +726,7 @@ int hough_plan_create(const hough_geometry_t* geom, const hough_grid_t* grid, ho
     if ((size_t)g.n_phi * 128 > 160 * 1024 && g.acc_bits == 16) return HOUGH_E_UNSUPPORTED;
     if (!(g.qpt_max >= g.qpt_min) || !(g.d0_max >= g.d0_min)) return HOUGH_E_INVAL;
     if ((int64_t)g.n_d0 * g.n_qpt * g.n_phi > ((int64_t)1 << 31)) return HOUGH_E_UNSUPPORTED;
+    if ((geom->n_layers << (lp < 10 ? lp : 10)) > kMaxCells) return HOUGH_E_UNSUPPORTED;
 
     hough_plan* p = new (std::nothrow) hough_plan();
     if (!p) return HOUGH_E_NOMEM;
@@ -701,7 +744,8 @@ int hough_plan_create(const hough_geometry_t* geom, const hough_grid_t* grid, ho
     p->log2_phi = lp;
     p->F = g.frac_bits;
     p->M = lp + g.frac_bits;
-    p->cell_bits = p->M < 12 ? p->M : 12;
+    // one azimuth cell per phi0 bin (at most 2^10 cells per layer): a bin's window spans <= 2 cells
+    p->cell_bits = lp < 10 ? lp : 10;
     p->n_cols = g.n_d0 * g.n_qpt;
     p->n_cells = p->n_layers << p->cell_bits;
     p->n_bins = (int64_t)p->n_cols * g.n_phi;
@@ -801,28 +845,21 @@ int hough_prep(const hough_plan_t* p, const hough_hits_t* hits, uint32_t* phi_ou
     const WsLayout L = ws_layout(p, 0);
     if (ws_bytes < L.total) return HOUGH_E_SMALL_WS;
     const int n = hits->n;
-    hipLaunchKernelGGL(k_prep_init, dim3(((p->n_cells + 1) + 1023) / 1024), dim3(1024), 0, stream,
-                       at<int32_t>(ws, L.cell_count), p->n_cells, st, n);
     if (n > 0)
-        hipLaunchKernelGGL(k_prep_hits, dim3((n + 255) / 256), dim3(256), 0, stream, hits->x, hits->y,
-                           hits->layer, n, p->n_layers, p->cell_bits, p->cordic, at<uint32_t>(ws, L.phi32),
-                           at<uint8_t>(ws, L.lay), phi_out, at<int32_t>(ws, L.cell_count), st);
-    hipLaunchKernelGGL(k_prep_scan, dim3(1), dim3(kScanThreads), 0, stream, at<int32_t>(ws, L.cell_count),
-                       at<int32_t>(ws, L.cell_start), at<int32_t>(ws, L.cell_cursor), p->n_cells, p->n_layers,
-                       p->cell_bits, p->layers, st);
-    if (n > 0)
-        hipLaunchKernelGGL(k_prep_scatter, dim3((n + 255) / 256), dim3(256), 0, stream, at<uint32_t>(ws, L.phi32),
-                           at<uint8_t>(ws, L.lay), n, p->cell_bits, p->M, at<int32_t>(ws, L.cell_cursor),
-                           at<uint32_t>(ws, L.sorted_phi), at<int32_t>(ws, L.sorted_h));
+        hipLaunchKernelGGL(k_prep_hits, dim3((n + 255) / 256), dim3(256), 0, stream, hits->x, hits->y, hits->layer,
+                           n, p->n_layers, p->cordic, at<uint32_t>(ws, L.phi32), at<uint8_t>(ws, L.lay), phi_out);
+    hipLaunchKernelGGL(k_prep_sort, dim3(1), dim3(kScanThreads), 0, stream, at<uint32_t>(ws, L.phi32),
+                       at<uint8_t>(ws, L.lay), n, p->n_layers, p->cell_bits, p->M, p->layers,
+                       at<int32_t>(ws, L.cell_start), at<uint32_t>(ws, L.tmp_phi), at<int32_t>(ws, L.tmp_h),
+                       at<uint32_t>(ws, L.sorted_phi), at<int32_t>(ws, L.sorted_h), st);
     return launch_status();
 }
 
-int hough_vote(const hough_plan_t* p, const hough_hits_t* hits, void* acc, void* ws, size_t ws_bytes,
-               hough_status_t* st, hipStream_t stream) {
-    if (!acc) return HOUGH_E_INVAL;
-    int rc = hough_prep(p, hits, nullptr, ws, ws_bytes, st, stream);
-    if (rc) return rc;
+int hough_vote_prepared(const hough_plan_t* p, void* acc, void* ws, size_t ws_bytes, hough_status_t* st,
+                        hipStream_t stream) {
+    if (!p || !acc || !ws || !st) return HOUGH_E_INVAL;
     const WsLayout L = ws_layout(p, 0);
+    if (ws_bytes < L.total) return HOUGH_E_SMALL_WS;
     const int n_slabs = p->n_cols / kVoteCols;
     if (p->g.acc_bits == 32)
         hipLaunchKernelGGL(k_vote<false>, dim3(n_slabs), dim3(kVoteThreads), p->g.n_phi * 256, stream, p->d_E,
@@ -835,10 +872,18 @@ int hough_vote(const hough_plan_t* p, const hough_hits_t* hits, void* acc, void*
     return launch_status();
 }
 
+int hough_vote(const hough_plan_t* p, const hough_hits_t* hits, void* acc, void* ws, size_t ws_bytes,
+               hough_status_t* st, hipStream_t stream) {
+    if (!acc) return HOUGH_E_INVAL;
+    int rc = hough_prep(p, hits, nullptr, ws, ws_bytes, st, stream);
+    if (rc) return rc;
+    return hough_vote_prepared(p, acc, ws, ws_bytes, st, stream);
+}
+
 int hough_peaks(const hough_plan_t* p, const void* acc, int32_t threshold, hough_peak_t* peaks, int32_t cap,
                 void* ws, size_t ws_bytes, hough_status_t* st, hipStream_t stream) {
     if (!p || !acc || !peaks || !ws || !st || cap < 1 || threshold < 1) return HOUGH_E_INVAL;
-    const WsLayout L = ws_layout(p, 0);
+    const WsLayout L = ws_layout(p, cap);
     if (ws_bytes < L.total) return HOUGH_E_SMALL_WS;
     const int strips = p->g.n_phi / kStrip;
     const int gl = peak_group_lanes(p);
@@ -846,24 +891,26 @@ int hough_peaks(const hough_plan_t* p, const void* acc, int32_t threshold, hough
     const int64_t mark_threads = (int64_t)strips * p->g.n_qpt * lranges;
     const int64_t n_strips = p->n_bins / kStrip;
     const int64_t groups = peak_groups(p);
+    const dim3 gm((unsigned)((mark_threads + 255) / 256)), gw((unsigned)((n_strips + 255) / 256));
     if (p->g.acc_bits == 32)
-        hipLaunchKernelGGL(k_peaks_mark<int32_t>, dim3((unsigned)((mark_threads + 255) / 256)), dim3(256), 0,
-                           stream, static_cast<const int32_t*>(acc), threshold, p->g.n_d0, p->g.n_qpt,
-                           p->g.n_phi, gl, at<uint8_t>(ws, L.flags), at<int32_t>(ws, L.grp_count));
+        hipLaunchKernelGGL(k_peaks_mark<int32_t>, gm, dim3(256), 0, stream, static_cast<const int32_t*>(acc),
+                           threshold, p->g.n_d0, p->g.n_qpt, p->g.n_phi, gl, at<uint8_t>(ws, L.flags),
+                           at<int32_t>(ws, L.grp_count), at<int32_t>(ws, L.grp_votes));
     else
-        hipLaunchKernelGGL(k_peaks_mark<int16_t>, dim3((unsigned)((mark_threads + 255) / 256)), dim3(256), 0,
-                           stream, static_cast<const int16_t*>(acc), threshold, p->g.n_d0, p->g.n_qpt,
-                           p->g.n_phi, gl, at<uint8_t>(ws, L.flags), at<int32_t>(ws, L.grp_count));
+        hipLaunchKernelGGL(k_peaks_mark<int16_t>, gm, dim3(256), 0, stream, static_cast<const int16_t*>(acc),
+                           threshold, p->g.n_d0, p->g.n_qpt, p->g.n_phi, gl, at<uint8_t>(ws, L.flags),
+                           at<int32_t>(ws, L.grp_count), at<int32_t>(ws, L.grp_votes));
     hipLaunchKernelGGL(k_peaks_scan, dim3(1), dim3(kScanThreads), 0, stream, at<int32_t>(ws, L.grp_count),
-                       at<int32_t>(ws, L.grp_off), groups, cap, st);
+                       at<int32_t>(ws, L.grp_votes), at<int32_t>(ws, L.grp_off), at<int64_t>(ws, L.grp_voff), groups,
+                       cap, at<int32_t>(ws, L.misc), st);
     if (p->g.acc_bits == 32)
-        hipLaunchKernelGGL(k_peaks_write<int32_t>, dim3((unsigned)((n_strips + 255) / 256)), dim3(256), 0, stream,
-                           static_cast<const int32_t*>(acc), at<uint8_t>(ws, L.flags), at<int32_t>(ws, L.grp_off),
-                           p->g.n_qpt, p->g.n_phi, gl, n_strips, peaks, cap);
+        hipLaunchKernelGGL(k_peaks_write<int32_t>, gw, dim3(256), 0, stream, static_cast<const int32_t*>(acc),
+                           at<uint8_t>(ws, L.flags), at<int32_t>(ws, L.grp_off), at<int64_t>(ws, L.grp_voff), groups,
+                           p->g.n_qpt, p->g.n_phi, gl, n_strips, peaks, at<int64_t>(ws, L.peak_voff), cap);
     else
-        hipLaunchKernelGGL(k_peaks_write<int16_t>, dim3((unsigned)((n_strips + 255) / 256)), dim3(256), 0, stream,
-                           static_cast<const int16_t*>(acc), at<uint8_t>(ws, L.flags), at<int32_t>(ws, L.grp_off),
-                           p->g.n_qpt, p->g.n_phi, gl, n_strips, peaks, cap);
+        hipLaunchKernelGGL(k_peaks_write<int16_t>, gw, dim3(256), 0, stream, static_cast<const int16_t*>(acc),
+                           at<uint8_t>(ws, L.flags), at<int32_t>(ws, L.grp_off), at<int64_t>(ws, L.grp_voff), groups,
+                           p->g.n_qpt, p->g.n_phi, gl, n_strips, peaks, at<int64_t>(ws, L.peak_voff), cap);
     return launch_status();
 }
 
@@ -874,12 +921,8 @@ int hough_assign(const hough_plan_t* p, const hough_peak_t* peaks, int32_t cap_p
     const WsLayout L = ws_layout(p, cap_peaks);
     if (ws_bytes < L.total) return HOUGH_E_SMALL_WS;
     const unsigned nblk = (unsigned)((cap_peaks + kAssignBlock - 1) / kAssignBlock);
-    hipLaunchKernelGGL(k_assign_blocksum, dim3(nblk), dim3(kAssignBlock), 0, stream, peaks, cap_peaks, st,
-                       at<int64_t>(ws, L.blk_sum));
-    hipLaunchKernelGGL(k_assign_topscan, dim3(1), dim3(kScanThreads), 0, stream, at<int64_t>(ws, L.blk_sum),
-                       at<int64_t>(ws, L.blk_off), cap_peaks, offsets, cap_pairs, st);
     hipLaunchKernelGGL(k_assign_fill, dim3(nblk), dim3(kAssignBlock), 0, stream, peaks, cap_peaks, st,
-                       at<int64_t>(ws, L.blk_off), p->d_E, at<int32_t>(ws, L.cell_start),
+                       at<int64_t>(ws, L.peak_voff), at<int32_t>(ws, L.misc), p->d_E, at<int32_t>(ws, L.cell_start),
                        at<uint32_t>(ws, L.sorted_phi), at<int32_t>(ws, L.sorted_h), p->n_layers, p->cell_bits,
                        p->n_cols, p->g.n_qpt, p->M, p->F, offsets, hit_idx, cap_pairs);
     return launch_status();

@@ -60,6 +60,7 @@ def _load() -> C.CDLL:
     L.hough_plan_table.restype = C.c_int; L.hough_plan_table.argtypes = [P, P]
     L.hough_prep.restype = C.c_int; L.hough_prep.argtypes = [P, C.POINTER(Hits), P, P, S, P, P]
     L.hough_vote.restype = C.c_int; L.hough_vote.argtypes = [P, C.POINTER(Hits), P, P, S, P, P]
+    L.hough_vote_prepared.restype = C.c_int; L.hough_vote_prepared.argtypes = [P, P, P, S, P, P]
     L.hough_peaks.restype = C.c_int
     L.hough_peaks.argtypes = [P, P, C.c_int32, P, C.c_int32, P, S, P, P]
     L.hough_assign.restype = C.c_int
@@ -71,7 +72,7 @@ def _load() -> C.CDLL:
 lib = _load()
 
 EXPORTED = ["hough_plan_create", "hough_plan_destroy", "hough_acc_bytes", "hough_event_ws_bytes",
-            "hough_angle_bits", "hough_plan_table", "hough_prep", "hough_vote", "hough_peaks",
+            "hough_angle_bits", "hough_plan_table", "hough_prep", "hough_vote", "hough_vote_prepared", "hough_peaks",
             "hough_assign", "hough_strerror"]
 
 
@@ -163,6 +164,13 @@ def vote(plan: Plan, hits: Hits, acc: torch.Tensor, ws: torch.Tensor, status: to
         raise HoughError("accumulator too small")
     _check(lib.hough_vote(plan.handle, C.byref(hits), _ptr(acc), _ptr(ws), ws.numel(), _ptr(status),
                           _stream(stream)), "hough_vote")
+
+
+def vote_prepared(plan: Plan, acc: torch.Tensor, ws: torch.Tensor, status: torch.Tensor, stream=None) -> None:
+    if acc.numel() * acc.element_size() < plan.acc_bytes:
+        raise HoughError("accumulator too small")
+    _check(lib.hough_vote_prepared(plan.handle, _ptr(acc), _ptr(ws), ws.numel(), _ptr(status), _stream(stream)),
+           "hough_vote_prepared")
 
 
 def peaks(plan: Plan, acc: torch.Tensor, threshold: int, out: torch.Tensor, ws: torch.Tensor,
