@@ -79,7 +79,7 @@ namespace {
 
 // ------------------------------------------------------------------ layout
 struct WsLayout {
-    size_t phi32, lay, cell_start, tmp_phi, tmp_h, sorted_phi, sorted_h;
+    size_t phi32, lay, cell_start, tmp_phi, tmp_key, sorted_phi, sorted_h;
     size_t flags, grp_count, grp_votes, grp_off, grp_voff, peak_voff, misc, total;
 };
 
@@ -105,7 +105,7 @@ WsLayout ws_layout(const hough_plan* p, int32_t max_peaks) {
     L.lay = take(maxh);
     L.cell_start = take(4 * ((size_t)p->n_cells + 1));
     L.tmp_phi = take(4 * maxh);
-    L.tmp_h = take(4 * maxh);
+    L.tmp_key = take(4 * maxh);
     L.sorted_phi = take(4 * maxh);
     L.sorted_h = take(4 * maxh);
     L.flags = take((size_t)(p->n_bins / kStrip));
@@ -207,16 +207,17 @@ __global__ __launch_bounds__(256) void k_prep_hits(const float* __restrict__ hx,
     if (phi_out) phi_out[h] = phi;
 }
 
-// One workgroup: sort the valid hits by (layer, M-bit angle, hit index) and reset the status.
-//   1. LDS histogram over cells (layer, top `cell_bits` bits of the angle), counting bad hits;
+// One workgroup: bucket the valid hits by cell (layer, top `cell_bits` bits of the angle) and reset
+// the status.
+//   1. LDS histogram over cells, counting bad hits;
 //   2. exclusive scan -> cell_start (global), hit-vote total from the per-layer counts;
-//   3. scatter into cell order (LDS cursors; arbitrary order inside a cell) -> tmp;
-//   4. rank inside the cell by (angle, hit index) -> sorted.
-__global__ __launch_bounds__(kScanThreads) void k_prep_sort(
+//   3. scatter into cell order (LDS cursors; arbitrary order inside a cell) -> tmp_phi, tmp_key.
+// tmp_key = (layer << 24) | hit index.
+constexpr int kBucketUnroll = 8;
+__global__ __launch_bounds__(kScanThreads) void k_prep_bucket(
     const uint32_t* __restrict__ phi32, const uint8_t* __restrict__ lay, int32_t n, int n_layers, int cell_bits,
     int M, LayerTable LT, int32_t* __restrict__ cell_start, uint32_t* __restrict__ tmp_phi,
-    int32_t* __restrict__ tmp_h, uint32_t* __restrict__ sorted_phi, int32_t* __restrict__ sorted_h,
-    hough_status_t* st) {
+    int32_t* __restrict__ tmp_key, hough_status_t* st) {
     __shared__ int32_t cur[kMaxCells];
     __shared__ int64_t wsum[kScanThreads / 64];
     __shared__ int32_t layer_n[kMaxLayers];
@@ -226,13 +227,20 @@ __global__ __launch_bounds__(kScanThreads) void k_prep_sort(
     for (int i = tid; i < n_cells; i += kScanThreads) cur[i] = 0;
     __syncthreads();
     int32_t bad = 0;
-    for (int h = tid; h < n; h += kScanThreads) {
-        const uint8_t L = lay[h];
-        if (L == 0xFF) {
-            ++bad;
-            continue;
+    for (int base = 0; base < n; base += kScanThreads * kBucketUnroll) {
+        uint8_t L[kBucketUnroll];
+        uint32_t ph[kBucketUnroll];
+#pragma unroll
+        for (int j = 0; j < kBucketUnroll; ++j) {
+            const int h = base + j * kScanThreads + tid;
+            L[j] = h < n ? lay[h] : (uint8_t)0xFE;
+            ph[j] = h < n ? phi32[h] : 0u;
         }
-        atomicAdd(&cur[((int)L << cell_bits) | (int)(phi32[h] >> cshift)], 1);
+#pragma unroll
+        for (int j = 0; j < kBucketUnroll; ++j) {
+            if (L[j] == 0xFF) ++bad;
+            else if (L[j] != 0xFE) atomicAdd(&cur[((int)L[j] << cell_bits) | (int)(ph[j] >> cshift)], 1);
+        }
     }
     __syncthreads();
     // exclusive scan of the histogram: each thread owns a contiguous chunk
@@ -268,32 +276,46 @@ __global__ __launch_bounds__(kScanThreads) void k_prep_sort(
         st->flags = 0;
         st->n_pairs = 0;
     }
-    // scatter (cur[c] walks from the start of cell c to its end = the start of cell c + 1)
-    for (int h = tid; h < n; h += kScanThreads) {
-        const uint8_t L = lay[h];
-        if (L == 0xFF) continue;
-        const uint32_t phi = phi32[h];
-        const int pos = atomicAdd(&cur[((int)L << cell_bits) | (int)(phi >> cshift)], 1);
-        tmp_phi[pos] = phi >> (32 - M);
-        tmp_h[pos] = h;
-    }
-    __threadfence_block();
-    __syncthreads();
-    // rank inside the cell: final position = cell start + #{members with smaller (angle, hit)}
-    const int mshift = M - cell_bits;
-    for (int q = tid; q < (int)tot; q += kScanThreads) {
-        const uint32_t a = tmp_phi[q];
-        const int32_t h = tmp_h[q];
-        const int c = ((int)lay[h] << cell_bits) | (int)(a >> mshift);
-        const int c0 = c > 0 ? cur[c - 1] : 0, c1 = cur[c];
-        int rank = 0;
-        for (int j = c0; j < c1; ++j) {
-            const uint32_t b = tmp_phi[j];
-            rank += (b < a || (b == a && tmp_h[j] < h)) ? 1 : 0;
+    for (int base = 0; base < n; base += kScanThreads * kBucketUnroll) {
+        uint8_t L[kBucketUnroll];
+        uint32_t ph[kBucketUnroll];
+#pragma unroll
+        for (int j = 0; j < kBucketUnroll; ++j) {
+            const int h = base + j * kScanThreads + tid;
+            L[j] = h < n ? lay[h] : (uint8_t)0xFF;
+            ph[j] = h < n ? phi32[h] : 0u;
         }
-        sorted_phi[c0 + rank] = a;
-        sorted_h[c0 + rank] = h;
+#pragma unroll
+        for (int j = 0; j < kBucketUnroll; ++j) {
+            if (L[j] == 0xFF) continue;
+            const int h = base + j * kScanThreads + tid;
+            const int pos = atomicAdd(&cur[((int)L[j] << cell_bits) | (int)(ph[j] >> cshift)], 1);
+            tmp_phi[pos] = ph[j] >> (32 - M);
+            tmp_key[pos] = ((int32_t)L[j] << 24) | h;
+        }
     }
+}
+
+// One thread per bucketed hit: rank inside its cell by (angle, hit index) -> sorted position.
+__global__ __launch_bounds__(256) void k_prep_rank(const uint32_t* __restrict__ tmp_phi,
+                                                   const int32_t* __restrict__ tmp_key,
+                                                   const int32_t* __restrict__ cell_start, int n_cells,
+                                                   int cell_bits, int M, uint32_t* __restrict__ sorted_phi,
+                                                   int32_t* __restrict__ sorted_h) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= cell_start[n_cells]) return;
+    const uint32_t a = tmp_phi[q];
+    const int32_t key = tmp_key[q];
+    const int32_t h = key & 0xFFFFFF;
+    const int c = ((key >> 24) << cell_bits) | (int)(a >> (M - cell_bits));
+    const int c0 = cell_start[c], c1 = cell_start[c + 1];
+    int rank = 0;
+    for (int j = c0; j < c1; ++j) {
+        const uint32_t b = tmp_phi[j];
+        rank += (b < a || (b == a && (tmp_key[j] & 0xFFFFFF) < h)) ? 1 : 0;
+    }
+    sorted_phi[c0 + rank] = a;
+    sorted_h[c0 + rank] = h;
 }
 
 // ------------------------------------------------------------------ vote
@@ -523,13 +545,15 @@ __global__ __launch_bounds__(kScanThreads) void k_peaks_scan(const int32_t* __re
                                                              int32_t cap, int32_t* __restrict__ listed,
                                                              hough_status_t* st) {
     __shared__ int32_t tc[kScanThreads * kScanPer];
-    __shared__ int32_t tv[kScanThreads * kScanPer];
+    __shared__ int64_t tv[kScanThreads * kScanPer];
     __shared__ int64_t wsum[kScanThreads / 64];
     const int tid = threadIdx.x;
     int64_t carry_c = 0, carry_v = 0;
     for (int64_t base = 0; base < n_groups; base += kScanThreads * kScanPer) {
         const int m = (int)min((int64_t)kScanThreads * kScanPer, n_groups - base);
-        for (int i = tid; i < kScanThreads * kScanPer; i += kScanThreads) {
+#pragma unroll
+        for (int j = 0; j < kScanPer; ++j) {
+            const int i = j * kScanThreads + tid;
             tc[i] = i < m ? grp_count[base + i] : 0;
             tv[i] = i < m ? grp_votes[base + i] : 0;
         }
@@ -542,14 +566,24 @@ __global__ __launch_bounds__(kScanThreads) void k_peaks_scan(const int32_t* __re
         int64_t totc, totv;
         int64_t rc = block_inclusive_scan(sc, wsum, &totc) - sc + carry_c;
         int64_t rv = block_inclusive_scan(sv, wsum, &totv) - sv + carry_v;
+        // exclusive prefixes back into the tiles, then coalesced stores
         for (int j = 0; j < kScanPer; ++j) {
             const int i = tid * kScanPer + j;
+            const int32_t c = tc[i];
+            const int64_t v = tv[i];
+            tc[i] = (int32_t)min(rc, (int64_t)INT32_MAX);
+            tv[i] = rv;
+            rc += c;
+            rv += v;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < kScanPer; ++j) {
+            const int i = j * kScanThreads + tid;
             if (i < m) {
-                grp_off[base + i] = (int32_t)min(rc, (int64_t)INT32_MAX);
-                grp_voff[base + i] = rv;
+                grp_off[base + i] = tc[i];
+                grp_voff[base + i] = tv[i];
             }
-            rc += tc[i];
-            rv += tv[i];
         }
         carry_c += totc;
         carry_v += totv;
@@ -625,53 +659,97 @@ __global__ __launch_bounds__(256) void k_peaks_write(const T* __restrict__ acc, 
 
 // ------------------------------------------------------------------ assign
 // One thread per listed candidate (the first min(listed, cap_peaks) written by the peaks pass):
-// CSR offset from the peaks pass, then for each layer the run(s)
-// of sorted hits with angle in [lo, lo + 2^F) (mod 2^M), lo = E + b * 2^F, copied in order.
-__global__ __launch_bounds__(kAssignBlock) void k_assign_fill(
+// CSR offset from the peaks pass, then for each layer the run(s) of sorted hits with angle in
+// [lo, lo + 2^F) (mod 2^M), lo = E + b * 2^F, copied in order.  The 64 candidates of a wave own one
+// contiguous stretch of the CSR list: it is assembled in an LDS buffer of the wave and then written
+// with coalesced stores (positions beyond the buffer go straight to memory).  The cell table is
+// staged in LDS; the per-layer sample values of a candidate are loaded together.
+constexpr int kAssignThreads = 1024;
+constexpr int kAssignBufMax = 2048;  // words of CSR list buffered per wave (less if the cell table is large)
+
+__global__ __launch_bounds__(kAssignThreads) void k_assign_fill(
     const hough_peak_t* __restrict__ peaks, int32_t cap_peaks, hough_status_t* st,
     const int64_t* __restrict__ peak_voff, const int32_t* __restrict__ listed,
-    const int32_t* __restrict__ E, const int32_t* __restrict__ cell_start, const uint32_t* __restrict__ sorted_phi,
-    const int32_t* __restrict__ sorted_h, int n_layers, int cell_bits, int n_cols, int n_qpt, int M, int F,
-    int32_t* __restrict__ offsets, int32_t* __restrict__ hit_idx, int32_t cap_pairs) {
+    const int32_t* __restrict__ E, const int32_t* __restrict__ g_cell_start,
+    const uint32_t* __restrict__ sorted_phi, const int32_t* __restrict__ sorted_h, int n_layers, int cell_bits,
+    int n_cols, int n_qpt, int M, int F, int32_t* __restrict__ offsets, int32_t* __restrict__ hit_idx,
+    int32_t cap_pairs, int buf_words) {
+    extern __shared__ int32_t sm_i32[];  // [waves][buf_words] buffers, then the cell table
     const int n = min(*listed, cap_peaks);
-    const int i = blockIdx.x * kAssignBlock + threadIdx.x;
-    if (i == 0) {
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    if (blockIdx.x == 0 && tid == 0) {
         const int64_t tot = n > 0 ? peak_voff[n - 1] + peaks[n - 1].votes : 0;
         offsets[n] = (int32_t)min(tot, (int64_t)INT32_MAX);
         st->n_pairs = tot;
         if (tot > cap_pairs) atomicOr(&st->flags, HOUGH_F_PAIR_OVERFLOW);
     }
-    if (i >= n) return;
-    const int64_t off = peak_voff[i];
-    offsets[i] = (int32_t)min(off, (int64_t)INT32_MAX);
-    if (off >= cap_pairs) return;
-    const hough_peak_t pk = peaks[i];
+    if ((int)blockIdx.x * kAssignThreads >= n) return;  // uniform per block
+    const int n_cells = n_layers << cell_bits;
+    int32_t* buf = sm_i32 + wave * buf_words;
+    int32_t* cell_start = sm_i32 + (kAssignThreads / 64) * buf_words;
+    for (int i = tid; i <= n_cells; i += kAssignThreads) cell_start[i] = g_cell_start[i];
+    __syncthreads();
     const uint32_t span = 1u << M;
     const uint32_t W = 1u << F;
     const int cshift = M - cell_bits;
-    int64_t w = off;
-    for (int L = 0; L < n_layers && w < cap_pairs; ++L) {
-        const int32_t e = E[(size_t)L * n_cols + (size_t)pk.l * n_qpt + pk.k];
-        if (e == INT32_MIN) continue;
-        const uint32_t lo = ((uint32_t)e + ((uint32_t)pk.b << F)) & (span - 1u);
-        const uint32_t hi = lo + W;  // may exceed 2^M: the window wraps
-        const int cb = L << cell_bits;
-        const int lay_end = cell_start[cb + (1 << cell_bits)];
-        // first hit with angle >= lo
-        int q = cell_start[cb + (int)(lo >> cshift)];
-        while (q < lay_end && sorted_phi[q] < lo) ++q;
-        if (hi <= span) {
-            int z = hi < span ? cell_start[cb + (int)(hi >> cshift)] : lay_end;
-            while (z < lay_end && sorted_phi[z] < hi) ++z;
-            for (; q < z && w < cap_pairs; ++q) hit_idx[w++] = sorted_h[q];
-        } else {
-            for (; q < lay_end && w < cap_pairs; ++q) hit_idx[w++] = sorted_h[q];
-            const uint32_t hw = hi - span;
-            int r = cell_start[cb];
-            int z = cell_start[cb + (int)(hw >> cshift)];
-            while (z < lay_end && sorted_phi[z] < hw) ++z;
-            for (; r < z && w < cap_pairs; ++r) hit_idx[w++] = sorted_h[r];
+    for (int base = blockIdx.x * kAssignThreads + wave * 64; base < n; base += gridDim.x * kAssignThreads) {
+        const int i = base + lane;
+        // the wave's stretch of the list: [o0, o1)
+        const int last = min(n, base + 64) - 1;
+        const int64_t o0 = peak_voff[base];
+        const int64_t o1 = peak_voff[last] + peaks[last].votes;
+        if (i < n) {
+            const int64_t off = peak_voff[i];
+            offsets[i] = (int32_t)min(off, (int64_t)INT32_MAX);
+            const hough_peak_t pk = peaks[i];
+            const int32_t* Ec = E + (size_t)pk.l * n_qpt + pk.k;
+            int32_t e[kMaxLayers];
+#pragma unroll
+            for (int L = 0; L < kMaxLayers; ++L) e[L] = L < n_layers ? Ec[(size_t)L * n_cols] : INT32_MIN;
+            int64_t w = off;
+#pragma unroll
+            for (int L = 0; L < kMaxLayers; ++L) {
+                if (L >= n_layers || w >= cap_pairs) break;
+                if (e[L] == INT32_MIN) continue;
+                const uint32_t lo = ((uint32_t)e[L] + ((uint32_t)pk.b << F)) & (span - 1u);
+                const uint32_t hi = lo + W;  // may exceed 2^M: the window wraps
+                const int cb = L << cell_bits;
+                const int lay_end = cell_start[cb + (1 << cell_bits)];
+                int q = cell_start[cb + (int)(lo >> cshift)];
+                const uint32_t he = hi <= span ? hi : span;
+                int z = he < span ? cell_start[cb + (int)(he >> cshift)] : lay_end;
+                while (q < lay_end && sorted_phi[q] < lo) ++q;
+                while (z < lay_end && sorted_phi[z] < he) ++z;
+                int r = -1, z2 = -1;
+                if (hi > span) {
+                    const uint32_t hw = hi - span;
+                    r = cell_start[cb];
+                    z2 = cell_start[cb + (int)(hw >> cshift)];
+                    while (z2 < lay_end && sorted_phi[z2] < hw) ++z2;
+                }
+                for (int seg = 0; seg < 2; ++seg) {
+                    const int a0 = seg == 0 ? q : r;
+                    const int a1 = seg == 0 ? z : z2;
+                    for (int j = a0; j < a1 && w < cap_pairs; ++j, ++w) {
+                        const int32_t h = sorted_h[j];
+                        const int64_t rel = w - o0;
+                        if (rel < buf_words) buf[rel] = h;
+                        else hit_idx[w] = h;
+                    }
+                }
+            }
         }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        // coalesced flush of the buffered part of the stretch
+        const int64_t fe = min(min(o1, o0 + buf_words), (int64_t)cap_pairs);
+        for (int64_t w = o0 + lane; w < fe; w += 64) hit_idx[w] = buf[w - o0];
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
 }
 
@@ -713,6 +791,7 @@ int hough_plan_create(const hough_geometry_t* geom, const hough_grid_t* grid, ho
     const int lp = ilog2_exact(g.n_phi);
     if (lp < 4 || lp > 12) return HOUGH_E_UNSUPPORTED;
     if (g.n_qpt < 1 || g.n_d0 < 1 || g.max_hits_per_event < 1) return HOUGH_E_INVAL;
+    if (g.max_hits_per_event > (1 << 24) - 1) return HOUGH_E_UNSUPPORTED;
     if (g.n_qpt % kVoteCols) return HOUGH_E_UNSUPPORTED;
     if (g.acc_bits == 32) {
         if (g.frac_bits != 8) return HOUGH_E_UNSUPPORTED;
@@ -796,10 +875,13 @@ int hough_plan_create(const hough_geometry_t* geom, const hough_grid_t* grid, ho
         delete p;
         return HOUGH_E_HIP;
     }
-    const int vote_lds = g.acc_bits == 32 ? g.n_phi * 256 : g.n_phi * 128;
-    hipError_t ae = g.acc_bits == 32
-                        ? hipFuncSetAttribute((const void*)k_vote<false>, hipFuncAttributeMaxDynamicSharedMemorySize, vote_lds)
-                        : hipFuncSetAttribute((const void*)k_vote<true>, hipFuncAttributeMaxDynamicSharedMemorySize, vote_lds);
+    // dynamic LDS limits set to the whole 160 KiB once (a lower per-plan value would break other plans)
+    const int lds_max = 160 * 1024;
+    hipError_t ae = hipFuncSetAttribute((const void*)k_vote<false>, hipFuncAttributeMaxDynamicSharedMemorySize, lds_max);
+    if (ae == hipSuccess)
+        ae = hipFuncSetAttribute((const void*)k_vote<true>, hipFuncAttributeMaxDynamicSharedMemorySize, lds_max);
+    if (ae == hipSuccess)
+        ae = hipFuncSetAttribute((const void*)k_assign_fill, hipFuncAttributeMaxDynamicSharedMemorySize, lds_max);
     if (ae != hipSuccess) {
         (void)hipFree(p->d_E);
         delete p;
@@ -848,10 +930,13 @@ int hough_prep(const hough_plan_t* p, const hough_hits_t* hits, uint32_t* phi_ou
     if (n > 0)
         hipLaunchKernelGGL(k_prep_hits, dim3((n + 255) / 256), dim3(256), 0, stream, hits->x, hits->y, hits->layer,
                            n, p->n_layers, p->cordic, at<uint32_t>(ws, L.phi32), at<uint8_t>(ws, L.lay), phi_out);
-    hipLaunchKernelGGL(k_prep_sort, dim3(1), dim3(kScanThreads), 0, stream, at<uint32_t>(ws, L.phi32),
+    hipLaunchKernelGGL(k_prep_bucket, dim3(1), dim3(kScanThreads), 0, stream, at<uint32_t>(ws, L.phi32),
                        at<uint8_t>(ws, L.lay), n, p->n_layers, p->cell_bits, p->M, p->layers,
-                       at<int32_t>(ws, L.cell_start), at<uint32_t>(ws, L.tmp_phi), at<int32_t>(ws, L.tmp_h),
-                       at<uint32_t>(ws, L.sorted_phi), at<int32_t>(ws, L.sorted_h), st);
+                       at<int32_t>(ws, L.cell_start), at<uint32_t>(ws, L.tmp_phi), at<int32_t>(ws, L.tmp_key), st);
+    if (n > 0)
+        hipLaunchKernelGGL(k_prep_rank, dim3((n + 255) / 256), dim3(256), 0, stream, at<uint32_t>(ws, L.tmp_phi),
+                           at<int32_t>(ws, L.tmp_key), at<int32_t>(ws, L.cell_start), p->n_cells, p->cell_bits, p->M,
+                           at<uint32_t>(ws, L.sorted_phi), at<int32_t>(ws, L.sorted_h));
     return launch_status();
 }
 
@@ -920,11 +1005,16 @@ int hough_assign(const hough_plan_t* p, const hough_peak_t* peaks, int32_t cap_p
     if (!p || !peaks || !offsets || !hit_idx || !ws || !st || cap_peaks < 1 || cap_pairs < 1) return HOUGH_E_INVAL;
     const WsLayout L = ws_layout(p, cap_peaks);
     if (ws_bytes < L.total) return HOUGH_E_SMALL_WS;
-    const unsigned nblk = (unsigned)((cap_peaks + kAssignBlock - 1) / kAssignBlock);
-    hipLaunchKernelGGL(k_assign_fill, dim3(nblk), dim3(kAssignBlock), 0, stream, peaks, cap_peaks, st,
+    const int64_t want = ((int64_t)cap_peaks + kAssignThreads - 1) / kAssignThreads;
+    const unsigned nblk = (unsigned)(want < 2 * 256 ? want : 2 * 256);
+    const size_t cells_bytes = 4 * ((size_t)p->n_cells + 1);
+    int buf_words = (int)((160 * 1024 - cells_bytes) / 4 / (kAssignThreads / 64)) & ~63;
+    buf_words = buf_words > kAssignBufMax ? kAssignBufMax : buf_words;
+    const size_t lds = 4 * (size_t)(kAssignThreads / 64) * buf_words + cells_bytes;
+    hipLaunchKernelGGL(k_assign_fill, dim3(nblk), dim3(kAssignThreads), lds, stream, peaks, cap_peaks, st,
                        at<int64_t>(ws, L.peak_voff), at<int32_t>(ws, L.misc), p->d_E, at<int32_t>(ws, L.cell_start),
                        at<uint32_t>(ws, L.sorted_phi), at<int32_t>(ws, L.sorted_h), p->n_layers, p->cell_bits,
-                       p->n_cols, p->g.n_qpt, p->M, p->F, offsets, hit_idx, cap_pairs);
+                       p->n_cols, p->g.n_qpt, p->M, p->F, offsets, hit_idx, cap_pairs, buf_words);
     return launch_status();
 }
 
