@@ -67,6 +67,8 @@ extern "C" {
 /* status flags */
 #define HOUGH_F_PEAK_OVERFLOW 1  /* more peaks than cap: first cap written             */
 #define HOUGH_F_PAIR_OVERFLOW 2  /* more hit-candidate pairs than cap: first cap written */
+#define HOUGH_F_EVENT_TOO_LARGE 4 /* batch event with more hits than max_hits_per_event:
+                                     treated as empty (zero accumulator, no candidates) */
 
 typedef struct {
     int32_t n_layers;          /* 1..32 */
@@ -115,11 +117,21 @@ typedef struct {
 
 typedef struct hough_plan hough_plan_t;
 
+/* Launch shapes (results are identical for every valid choice). */
+typedef struct {
+    int32_t vote_threads;      /* threads per vote workgroup: 256, 512 or 1024            */
+    int32_t vote_grid;         /* persistent vote workgroups of a batch (0 = 256)          */
+    int32_t peak_planes;       /* d0 planes walked by one peak-finder thread (1..64)       */
+} hough_tuning_t;
+
 /* Create a plan on the current HIP device: validates geometry and grid and
  * builds the per-(layer, d0, q/pT) sample table E (and, with a zvote grid,
  * the arc-length table) in device memory.  Synchronous. */
 int hough_plan_create(const hough_geometry_t* geom, const hough_grid_t* grid, hough_plan_t** out);
 void hough_plan_destroy(hough_plan_t* plan);
+
+int hough_plan_set_tuning(hough_plan_t* plan, const hough_tuning_t* t);
+int hough_plan_get_tuning(const hough_plan_t* plan, hough_tuning_t* t);
 
 /* Sizes in bytes. */
 size_t hough_acc_bytes(const hough_plan_t* plan);             /* n_d0*n_qpt*n_phi*acc_bits/8 */
@@ -171,6 +183,45 @@ int hough_peaks(const hough_plan_t* plan, const void* acc, int32_t threshold, ho
 int hough_assign(const hough_plan_t* plan, const hough_peak_t* peaks, int32_t cap_peaks, int32_t* offsets,
                  int32_t* hit_idx, int32_t cap_pairs, void* ws, size_t ws_bytes, hough_status_t* st,
                  hipStream_t stream);
+
+/* a7 -- batched form: many events of uneven size in one launch chain.  The
+ * hits of all events are packed (CSR: event e owns hits [hit_offsets[e],
+ * hit_offsets[e+1])); every per-event output is strided by its capacity.
+ * The vote is one persistent kernel that pulls (event, slab of 64 columns)
+ * items from a device work queue, largest events first (Sec. "Preliminary
+ * Results", data paragraph: each GPU processes one event after another; here
+ * the events of a batch share the GPU).  Results of each event are identical
+ * to the single-event calls.  Stream-ordered; capturable in a hipGraph. */
+typedef struct {
+    const float* x;            /* (dev) packed hits of all events                        */
+    const float* y;
+    const float* z;            /* may be NULL                                            */
+    const uint8_t* layer;
+    const int32_t* hit_offsets;/* (dev) [n_events + 1]                                   */
+    int32_t n_events;
+    int32_t threshold;         /* peak threshold (>= 1)                                  */
+    int32_t cap_peaks;         /* per event                                              */
+    int32_t cap_pairs;         /* per event                                              */
+    void* acc;                 /* (dev) n_events x hough_acc_bytes                       */
+    hough_peak_t* peaks;       /* (dev) n_events x cap_peaks                             */
+    int32_t* offsets;          /* (dev) n_events x (cap_peaks + 1)                       */
+    int32_t* hit_idx;          /* (dev) n_events x cap_pairs                             */
+    void* ws;                  /* (dev) hough_batch_ws_bytes(plan, n_events, cap_peaks)  */
+    size_t ws_bytes;
+    hough_status_t* status;    /* (dev) n_events                                         */
+} hough_batch_t;
+
+size_t hough_batch_ws_bytes(const hough_plan_t* plan, int32_t n_events, int32_t cap_peaks);
+int hough_run_batch(const hough_plan_t* plan, const hough_batch_t* batch, hipStream_t stream);
+
+/* The batched chain captured once into a hipGraph and replayed: buffers are
+ * bound at capture time (refill the same buffers with new events between
+ * launches).  `stream` must not be the NULL stream. */
+typedef struct hough_graph hough_graph_t;
+int hough_batch_graph_create(const hough_plan_t* plan, const hough_batch_t* batch, hipStream_t stream,
+                             hough_graph_t** out);
+int hough_graph_launch(hough_graph_t* graph, hipStream_t stream);
+void hough_graph_destroy(hough_graph_t* graph);
 
 const char* hough_strerror(int code);
 

@@ -2,27 +2,33 @@
 //
 // The operations (prep, vote, peaks, assign) and their exact integer
 // definitions are documented in include/hough.h.  This file is the MI355X
-// implementation:
+// implementation.  Every kernel handles a batch of events (blockIdx.y or a
+// work queue selects the event); a single-event call is the batch of one.
 //   prep    per-hit Q16.16 + integer CORDIC azimuth (one thread per hit), then
-//           one workgroup sorts the valid hits by (layer, angle, hit index):
-//           LDS histogram over (layer, azimuth cell), scan, scatter, and a
-//           rank sort inside each cell; the vote reads each layer's hits as
+//           one workgroup per event buckets the valid hits by (layer, azimuth
+//           cell) in LDS (histogram, scan, scatter) and one thread per hit
+//           ranks it inside its cell by (angle, hit index): the hits end up
+//           sorted by (layer, angle, hit); the vote reads each layer's hits as
 //           one contiguous run, the assignment finds a bin's hits as one run;
-//   vote    one workgroup per slab of 64 (l, k) columns holds the whole phi0
-//           range of its columns in LDS as [bin][column] (one 256-byte row per
-//           bin), loops over all hits of the event layer by layer and adds
-//           each vote with a conflict-free ds_add_u32: one lane per column,
-//           one hit per instruction, 2 VALU ops + 1 LDS atomic per vote; the
-//           slab is then written once to HBM (no global atomics, slabs are
-//           disjoint, integer sums are order independent);
-//   peaks   one thread per 8-bin strip of a column walks an l range keeping
-//           a 3-plane window in registers (separable 3-wide maxima), writes
-//           one flag byte per strip and per-group candidate and vote counts;
-//           one tiled scan and a write pass compact the candidates in
-//           increasing linear index together with their CSR offsets (the
-//           prefix sums of their vote counts);
+//   vote    one workgroup per (event, slab of 64 (l, k) columns) holds the
+//           whole phi0 range of its columns in LDS as [bin][column] (one
+//           256-byte row per bin), loops over all hits of the event layer by
+//           layer and adds each vote with a conflict-free ds_add_u32: one lane
+//           per column, one hit per instruction, 2 VALU ops + 1 LDS atomic per
+//           vote; the slab is then written once to HBM (no global atomics,
+//           slabs are disjoint, integer sums are order independent).  Batches
+//           run it as a persistent kernel pulling (event, slab) items from a
+//           device work queue, largest events first;
+//   peaks   one thread per 8-bin strip of a column walks a range of d0 planes
+//           keeping a 3-plane window in registers (separable 3-wide maxima),
+//           writes one flag byte per strip and per-group candidate and vote
+//           counts; one tiled scan per event and a write pass compact the
+//           candidates in increasing linear index together with their CSR
+//           offsets (the prefix sums of their vote counts);
 //   assign  each candidate copies, layer by layer, the run of sorted hits
-//           whose angle falls into its phi0 window.
+//           whose angle falls into its phi0 window; the candidates of a wave
+//           assemble their stretch of the CSR list in LDS and store it
+//           coalesced.
 #include <hip/hip_runtime.h>
 
 #include <climits>
@@ -38,13 +44,14 @@ namespace {
 
 constexpr int kMaxLayers = 32;
 constexpr int kCordicSteps = 30;
-constexpr int kVoteThreads = 1024;
+constexpr int kVoteMaxThreads = 1024;
 constexpr int kVoteCols = 64;       // columns per vote slab (one per lane)
 constexpr int kStrip = 8;           // phi0 bins per peak-finder thread
-constexpr int kPeakPlanes = 8;      // d0 planes per peak-finder thread
 constexpr int kScanThreads = 1024;
-constexpr int kAssignBlock = 256;
-constexpr int kMaxCells = 32768;    // LDS histogram of the prep sort (128 KiB)
+constexpr int kMaxCells = 32768;    // LDS histogram of the prep bucketing (128 KiB)
+constexpr int kAssignThreads = 1024;
+constexpr int kAssignBufMax = 2048; // words of CSR list buffered per wave (less if the cell table is large)
+constexpr int kLdsBytes = 160 * 1024;
 
 struct CordicTable {
     int32_t t[kCordicSteps];
@@ -52,6 +59,14 @@ struct CordicTable {
 
 struct LayerTable {
     int32_t valid_cols[kMaxLayers];  // number of (l, k) columns whose sample is valid, per layer
+};
+
+// Where the events of a call live.  One event: hit_off == nullptr and n_single hits.
+struct Events {
+    const int32_t* hit_off;  // (dev) [n_events + 1] start of each event in the packed hit arrays
+    int32_t n_single;
+    int32_t max_hits;        // events with more hits are not processed (flagged)
+    size_t ws_stride;        // bytes between the workspaces of consecutive events
 };
 
 }  // namespace
@@ -72,6 +87,7 @@ struct hough_plan {
     int64_t n_bins;
     CordicTable cordic;
     LayerTable layers;
+    hough_tuning_t tuning;
     int32_t* d_E;    // [n_layers][n_d0][n_qpt], INT32_MIN = invalid
 };
 
@@ -79,8 +95,8 @@ namespace {
 
 // ------------------------------------------------------------------ layout
 struct WsLayout {
-    size_t phi32, lay, cell_start, tmp_phi, tmp_key, sorted_phi, sorted_h;
-    size_t flags, grp_count, grp_votes, grp_off, grp_voff, peak_voff, misc, total;
+    size_t misc, phi32, lay, cell_start, tmp_phi, tmp_key, sorted_phi, sorted_h;
+    size_t flags, grp_count, grp_votes, grp_off, grp_voff, peak_voff, total;
 };
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
@@ -118,8 +134,25 @@ WsLayout ws_layout(const hough_plan* p, int32_t max_peaks) {
     return L;
 }
 
+// Batch header in front of the per-event workspaces: work-queue counter and event order.
+size_t batch_header_bytes(int32_t n_events) { return align_up(256 + 4 * (size_t)n_events, 256); }
+
 template <typename T>
-T* at(void* base, size_t off) { return reinterpret_cast<T*>(static_cast<char*>(base) + off); }
+__device__ __host__ __forceinline__ T* at(void* base, size_t off) {
+    return reinterpret_cast<T*>(static_cast<char*>(base) + off);
+}
+
+__device__ __forceinline__ void event_hits(const Events& ev, int e, int& h0, int& n) {
+    if (ev.hit_off) {
+        h0 = ev.hit_off[e];
+        n = ev.hit_off[e + 1] - h0;
+    } else {
+        h0 = 0;
+        n = ev.n_single;
+    }
+}
+
+__device__ __forceinline__ char* event_ws(char* ws, const Events& ev, int e) { return ws + (size_t)e * ev.ws_stride; }
 
 // ------------------------------------------------------------------ device helpers
 __device__ __forceinline__ uint32_t cordic_azimuth(int32_t X, int32_t Y, const CordicTable& T) {
@@ -150,12 +183,6 @@ __device__ __forceinline__ uint32_t cordic_azimuth(int32_t X, int32_t Y, const C
     return quarter * 1073741824u + (uint32_t)theta;
 }
 
-__device__ __forceinline__ int32_t wave_sum(int32_t v) {
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
-
 // Inclusive scan of one int64 value per thread over a workgroup of kScanThreads threads.
 // `wsum` is LDS scratch of kScanThreads / 64 entries.  Returns the inclusive prefix; *total = sum.
 __device__ __forceinline__ int64_t block_inclusive_scan(int64_t v, int64_t* wsum, int64_t* total) {
@@ -183,16 +210,48 @@ __device__ __forceinline__ int64_t block_inclusive_scan(int64_t v, int64_t* wsum
     return r;
 }
 
+struct WsOff {
+    size_t misc, phi32, lay, cell_start, tmp_phi, tmp_key, sorted_phi, sorted_h;
+    size_t flags, grp_count, grp_votes, grp_off, grp_voff, peak_voff;
+};
+
+WsOff ws_off(const WsLayout& L) {
+    return WsOff{L.misc,  L.phi32,     L.lay,       L.cell_start, L.tmp_phi, L.tmp_key, L.sorted_phi,
+                 L.sorted_h, L.flags, L.grp_count, L.grp_votes, L.grp_off,  L.grp_voff, L.peak_voff};
+}
+
+// ------------------------------------------------------------------ batch set-up
+// One workgroup: order the events by decreasing hit count (ties by index) for the vote's work
+// queue, and reset the queue counter.
+__global__ __launch_bounds__(1024) void k_batch_init(const int32_t* __restrict__ hit_off, int32_t n_events,
+                                                    int32_t* __restrict__ queue, int32_t* __restrict__ order) {
+    for (int e = threadIdx.x; e < n_events; e += blockDim.x) {
+        const int ne = hit_off[e + 1] - hit_off[e];
+        int rank = 0;
+        for (int j = 0; j < n_events; ++j) {
+            const int nj = hit_off[j + 1] - hit_off[j];
+            rank += (nj > ne || (nj == ne && j < e)) ? 1 : 0;
+        }
+        order[rank] = e;
+    }
+    if (threadIdx.x == 0) *queue = 0;
+}
+
 // ------------------------------------------------------------------ prep kernels
-// One thread per hit: validity, Q16.16, CORDIC azimuth.  No atomics.
-__global__ __launch_bounds__(256) void k_prep_hits(const float* __restrict__ hx, const float* __restrict__ hy,
-                                                   const uint8_t* __restrict__ hl, int32_t n, int n_layers,
-                                                   CordicTable T, uint32_t* __restrict__ phi32,
-                                                   uint8_t* __restrict__ lay, uint32_t* __restrict__ phi_out) {
+// One thread per hit (grid.y = event): validity, Q16.16, CORDIC azimuth.  No atomics.
+__global__ __launch_bounds__(256) void k_prep_hits(Events ev, const float* __restrict__ hx,
+                                                   const float* __restrict__ hy, const uint8_t* __restrict__ hl,
+                                                   int n_layers, CordicTable T, char* __restrict__ ws, WsOff O,
+                                                   uint32_t* __restrict__ phi_out) {
+    const int e = blockIdx.y;
+    int h0, n;
+    event_hits(ev, e, h0, n);
+    if (n > ev.max_hits) return;
     const int h = blockIdx.x * blockDim.x + threadIdx.x;
     if (h >= n) return;
-    const float x = hx[h], y = hy[h];
-    const uint8_t L = hl[h];
+    char* w = event_ws(ws, ev, e);
+    const float x = hx[h0 + h], y = hy[h0 + h];
+    const uint8_t L = hl[h0 + h];
     bool ok = (int)L < n_layers && isfinite(x) && isfinite(y) && fabsf(x) < 32768.0f && fabsf(y) < 32768.0f;
     uint32_t phi = 0;
     if (ok) {
@@ -202,25 +261,37 @@ __global__ __launch_bounds__(256) void k_prep_hits(const float* __restrict__ hx,
         ok = !(X == 0 && Y == 0);
         if (ok) phi = cordic_azimuth(X, Y, T);
     }
-    phi32[h] = phi;
-    lay[h] = ok ? L : (uint8_t)0xFF;
-    if (phi_out) phi_out[h] = phi;
+    at<uint32_t>(w, O.phi32)[h] = phi;
+    at<uint8_t>(w, O.lay)[h] = ok ? L : (uint8_t)0xFF;
+    if (phi_out) phi_out[h0 + h] = phi;
 }
 
-// One workgroup: bucket the valid hits by cell (layer, top `cell_bits` bits of the angle) and reset
-// the status.
+// One workgroup per event: bucket the valid hits by cell (layer, top `cell_bits` bits of the angle)
+// and reset the event's status.
 //   1. LDS histogram over cells, counting bad hits;
-//   2. exclusive scan -> cell_start (global), hit-vote total from the per-layer counts;
-//   3. scatter into cell order (LDS cursors; arbitrary order inside a cell) -> tmp_phi, tmp_key.
-// tmp_key = (layer << 24) | hit index.
+//   2. exclusive scan -> cell_start, hit-vote total from the per-layer counts;
+//   3. scatter into cell order (LDS cursors; arbitrary order inside a cell) -> tmp_phi, tmp_key,
+//      tmp_key = (layer << 24) | hit index.
+// An event with more than max_hits hits is treated as empty and flagged.
 constexpr int kBucketUnroll = 8;
-__global__ __launch_bounds__(kScanThreads) void k_prep_bucket(
-    const uint32_t* __restrict__ phi32, const uint8_t* __restrict__ lay, int32_t n, int n_layers, int cell_bits,
-    int M, LayerTable LT, int32_t* __restrict__ cell_start, uint32_t* __restrict__ tmp_phi,
-    int32_t* __restrict__ tmp_key, hough_status_t* st) {
+__global__ __launch_bounds__(kScanThreads) void k_prep_bucket(Events ev, int n_layers, int cell_bits, int M,
+                                                              LayerTable LT, char* __restrict__ ws, WsOff O,
+                                                              hough_status_t* __restrict__ st_base) {
     __shared__ int32_t cur[kMaxCells];
     __shared__ int64_t wsum[kScanThreads / 64];
     __shared__ int32_t layer_n[kMaxLayers];
+    const int e = blockIdx.y;
+    int h0, n;
+    event_hits(ev, e, h0, n);
+    const int n_given = n;
+    if (n > ev.max_hits) n = 0;
+    char* w = event_ws(ws, ev, e);
+    const uint32_t* phi32 = at<uint32_t>(w, O.phi32);
+    const uint8_t* lay = at<uint8_t>(w, O.lay);
+    int32_t* cell_start = at<int32_t>(w, O.cell_start);
+    uint32_t* tmp_phi = at<uint32_t>(w, O.tmp_phi);
+    int32_t* tmp_key = at<int32_t>(w, O.tmp_key);
+    hough_status_t* st = st_base + e;
     const int tid = threadIdx.x;
     const int n_cells = n_layers << cell_bits;
     const int cshift = 32 - cell_bits;
@@ -269,11 +340,11 @@ __global__ __launch_bounds__(kScanThreads) void k_prep_bucket(
     if (tid == 0) {
         int64_t votes = 0;
         for (int L = 0; L < n_layers; ++L) votes += (int64_t)layer_n[L] * LT.valid_cols[L];
-        st->n_hits = n;
+        st->n_hits = n_given;
         st->n_bad_hits = (int32_t)bad_tot;
         st->n_votes = votes;
         st->n_peaks = 0;
-        st->flags = 0;
+        st->flags = n_given > ev.max_hits ? HOUGH_F_EVENT_TOO_LARGE : 0;
         st->n_pairs = 0;
     }
     for (int base = 0; base < n; base += kScanThreads * kBucketUnroll) {
@@ -296,14 +367,15 @@ __global__ __launch_bounds__(kScanThreads) void k_prep_bucket(
     }
 }
 
-// One thread per bucketed hit: rank inside its cell by (angle, hit index) -> sorted position.
-__global__ __launch_bounds__(256) void k_prep_rank(const uint32_t* __restrict__ tmp_phi,
-                                                   const int32_t* __restrict__ tmp_key,
-                                                   const int32_t* __restrict__ cell_start, int n_cells,
-                                                   int cell_bits, int M, uint32_t* __restrict__ sorted_phi,
-                                                   int32_t* __restrict__ sorted_h) {
+// One thread per bucketed hit (grid.y = event): rank inside its cell by (angle, hit index).
+__global__ __launch_bounds__(256) void k_prep_rank(Events ev, int n_cells, int cell_bits, int M,
+                                                   char* __restrict__ ws, WsOff O) {
+    char* w = event_ws(ws, ev, blockIdx.y);
+    const int32_t* cell_start = at<int32_t>(w, O.cell_start);
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= cell_start[n_cells]) return;
+    const uint32_t* tmp_phi = at<uint32_t>(w, O.tmp_phi);
+    const int32_t* tmp_key = at<int32_t>(w, O.tmp_key);
     const uint32_t a = tmp_phi[q];
     const int32_t key = tmp_key[q];
     const int32_t h = key & 0xFFFFFF;
@@ -314,8 +386,8 @@ __global__ __launch_bounds__(256) void k_prep_rank(const uint32_t* __restrict__ 
         const uint32_t b = tmp_phi[j];
         rank += (b < a || (b == a && (tmp_key[j] & 0xFFFFFF) < h)) ? 1 : 0;
     }
-    sorted_phi[c0 + rank] = a;
-    sorted_h[c0 + rank] = h;
+    at<uint32_t>(w, O.sorted_phi)[c0 + rank] = a;
+    at<int32_t>(w, O.sorted_h)[c0 + rank] = h;
 }
 
 // ------------------------------------------------------------------ vote
@@ -331,103 +403,129 @@ typedef __attribute__((address_space(3))) uint32_t lds_u32;
 
 // ACC16 = false: slab dword (b * 64 + c), one int32 counter per (bin, column), F = 8.
 // ACC16 = true : slab dword (b * 32 + c % 32), 16-bit halves for columns c and c + 32, F = 7.
+// Work items are (event, slab) pairs, item = rank * n_slabs + slab where rank orders the events
+// (order == nullptr: identity).  Items 0 .. gridDim.x-1 are taken by block index; with a queue the
+// next items come from an atomic counter (which must start at 0), otherwise by a stride of gridDim.x.
 template <bool ACC16>
-__global__ __launch_bounds__(kVoteThreads) void k_vote(const int32_t* __restrict__ E,
-                                                       const int32_t* __restrict__ cell_start,
-                                                       const uint32_t* __restrict__ sorted_phi, int n_layers,
-                                                       int cell_bits, int n_cols, int n_phi, int F,
-                                                       void* __restrict__ acc_out, hough_status_t* st) {
-    extern __shared__ uint32_t slab[];
+__global__ __launch_bounds__(kVoteMaxThreads) void k_vote(Events ev, const int32_t* __restrict__ E, int n_layers,
+                                                          int cell_bits, int n_cols, int n_phi, int F,
+                                                          char* __restrict__ ws, WsOff O,
+                                                          char* __restrict__ acc_base, size_t acc_stride,
+                                                          int n_events, const int32_t* __restrict__ order,
+                                                          int32_t* __restrict__ queue, hough_status_t* st_base) {
+    extern __shared__ uint32_t slab[];  // [slab_dwords] counters, then one word for the queue broadcast
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int n_waves = kVoteThreads / 64;
-    const int col = blockIdx.x * kVoteCols + lane;
+    const int n_waves = blockDim.x >> 6;
+    const int n_slabs = n_cols / kVoteCols;
+    const int total = n_events * n_slabs;
     const int slab_dwords = ACC16 ? n_phi * 32 : n_phi * 64;
 
-    // The vote addresses LDS by byte offset from 0: the slab must be the only LDS allocation.
+    // The vote addresses LDS by byte offset from 0: the slab must be the kernel's only LDS object
+    // (no static __shared__ variables in this kernel).
     const uint32_t lds_base = (uint32_t)(uintptr_t)(lds_u32*)slab;
     if (lds_base != 0) {
-        if (tid == 0 && blockIdx.x == 0) atomicOr(&st->flags, 0x40000000);
+        if (tid == 0 && blockIdx.x == 0) atomicOr(&st_base->flags, 0x40000000);
         return;
     }
-
-    uint4* s4 = reinterpret_cast<uint4*>(slab);
-    for (int i = tid; i < slab_dwords / 4; i += kVoteThreads) s4[i] = make_uint4(0, 0, 0, 0);
-    __syncthreads();
-
     const uint32_t mask = (uint32_t)(n_phi - 1) << F;
     const uint32_t lanebits = ACC16 ? (uint32_t)(lane & 31) << 2 : (uint32_t)lane << 2;
     const uint32_t data = ACC16 ? (lane >= 32 ? 0x10000u : 1u) : 1u;
+    uint4* s4 = reinterpret_cast<uint4*>(slab);
 
-    // The hits of each layer are cut into chunks of 64; chunk g (counted over all layers) goes to
-    // wave g % n_waves.  A wave loads a chunk with one coalesced load (one hit per lane) and then
-    // broadcasts hit j with v_readlane: the hit values travel in VGPRs, so waiting for them never
-    // waits for the LDS atomics (scalar loads would share the LDS wait counter).
-    int chunk_base = 0;
-    for (int L = 0; L < n_layers; ++L) {
-        const int lo = cell_start[L << cell_bits];
-        const int hi = cell_start[(L + 1) << cell_bits];
-        const int n_chunks = (hi - lo + 63) >> 6;
-        const int first = (wave - chunk_base % n_waves + n_waves) % n_waves;
-        chunk_base += n_chunks;
-        if (first >= n_chunks) continue;
-        const int32_t e = E[(size_t)L * n_cols + col];
-        const bool valid = e != INT32_MIN;
-        const uint32_t ue = (uint32_t)e;
-        int c = first;
-        int h = lo + (c << 6);
-        uint32_t cur = h + lane < hi ? sorted_phi[h + lane] : 0u;
-        for (; c < n_chunks; c += n_waves) {
-            h = lo + (c << 6);
-            const int hn = h + (n_waves << 6);
-            const uint32_t nxt = hn + lane < hi ? sorted_phi[hn + lane] : 0u;  // prefetch the next chunk
-            const int cnt = min(64, hi - h);
-            if (valid) {
-                if (cnt == 64) {
+    int item = blockIdx.x;
+    while (item < total) {
+        const int rank = item / n_slabs;
+        const int e = order ? order[rank] : rank;
+        const int slab_id = item - rank * n_slabs;
+        const int col = slab_id * kVoteCols + lane;
+        char* w = event_ws(ws, ev, e);
+        const int32_t* cell_start = at<int32_t>(w, O.cell_start);
+        const uint32_t* sorted_phi = at<uint32_t>(w, O.sorted_phi);
+
+        for (int i = tid; i < slab_dwords / 4; i += blockDim.x) s4[i] = make_uint4(0, 0, 0, 0);
+        __syncthreads();
+        // The hits of each layer are cut into chunks of 64; chunk g (counted over all layers) goes
+        // to wave g % n_waves.  A wave loads a chunk with one coalesced load (one hit per lane) and
+        // then broadcasts hit j with v_readlane: the hit values travel in VGPRs, so waiting for
+        // them never waits for the LDS atomics (scalar loads would share the LDS wait counter).
+        int chunk_base = 0;
+        for (int L = 0; L < n_layers; ++L) {
+            const int lo = cell_start[L << cell_bits];
+            const int hi = cell_start[(L + 1) << cell_bits];
+            const int n_chunks = (hi - lo + 63) >> 6;
+            const int first = (wave - chunk_base % n_waves + n_waves) % n_waves;
+            chunk_base += n_chunks;
+            if (first >= n_chunks) continue;
+            const int32_t e_l = E[(size_t)L * n_cols + col];
+            const bool valid = e_l != INT32_MIN;
+            const uint32_t ue = (uint32_t)e_l;
+            int c = first;
+            int h = lo + (c << 6);
+            uint32_t cur = h + lane < hi ? sorted_phi[h + lane] : 0u;
+            for (; c < n_chunks; c += n_waves) {
+                h = lo + (c << 6);
+                const int hn = h + (n_waves << 6);
+                const uint32_t nxt = hn + lane < hi ? sorted_phi[hn + lane] : 0u;  // prefetch next chunk
+                const int cnt = min(64, hi - h);
+                if (valid) {
+                    if (cnt == 64) {
 #pragma unroll
-                    for (int j = 0; j < 64; ++j)
-                        lds_vote((uint32_t)__builtin_amdgcn_readlane((int)cur, j), ue, mask, lanebits, data);
-                } else {
-                    for (int j = 0; j < cnt; ++j)
-                        lds_vote((uint32_t)__builtin_amdgcn_readlane((int)cur, j), ue, mask, lanebits, data);
+                        for (int j = 0; j < 64; ++j)
+                            lds_vote((uint32_t)__builtin_amdgcn_readlane((int)cur, j), ue, mask, lanebits, data);
+                    } else {
+                        for (int j = 0; j < cnt; ++j)
+                            lds_vote((uint32_t)__builtin_amdgcn_readlane((int)cur, j), ue, mask, lanebits, data);
+                    }
                 }
+                cur = nxt;
             }
-            cur = nxt;
         }
-    }
-    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
-    __syncthreads();
+        asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+        __syncthreads();
 
-    // store the slab: acc[col][b], b fastest
-    const int col0 = blockIdx.x * kVoteCols;
-    if (!ACC16) {
-        int32_t* acc = static_cast<int32_t*>(acc_out);
-        const int quads = n_phi / 4;
-        for (int i = tid; i < quads * kVoteCols; i += kVoteThreads) {
-            const int c = i & 63, q = i >> 6;
-            uint4 v;
-            v.x = slab[(4 * q + 0) * 64 + c];
-            v.y = slab[(4 * q + 1) * 64 + c];
-            v.z = slab[(4 * q + 2) * 64 + c];
-            v.w = slab[(4 * q + 3) * 64 + c];
-            *reinterpret_cast<uint4*>(acc + (size_t)(col0 + c) * n_phi + 4 * q) = v;
-        }
-    } else {
-        int16_t* acc = static_cast<int16_t*>(acc_out);
-        const int octs = n_phi / 8;
-        for (int i = tid; i < octs * kVoteCols; i += kVoteThreads) {
-            const int c = i & 63, q = i >> 6;
-            const int sh = c >= 32 ? 16 : 0;
-            uint32_t w[8];
+        // store the slab: acc[col][b], b fastest
+        const int col0 = slab_id * kVoteCols;
+        char* acc_e = acc_base + (size_t)e * acc_stride;
+        if (!ACC16) {
+            int32_t* acc = reinterpret_cast<int32_t*>(acc_e);
+            const int quads = n_phi / 4;
+            for (int i = tid; i < quads * kVoteCols; i += blockDim.x) {
+                const int c = i & 63, q = i >> 6;
+                uint4 v;
+                v.x = slab[(4 * q + 0) * 64 + c];
+                v.y = slab[(4 * q + 1) * 64 + c];
+                v.z = slab[(4 * q + 2) * 64 + c];
+                v.w = slab[(4 * q + 3) * 64 + c];
+                *reinterpret_cast<uint4*>(acc + (size_t)(col0 + c) * n_phi + 4 * q) = v;
+            }
+        } else {
+            int16_t* acc = reinterpret_cast<int16_t*>(acc_e);
+            const int octs = n_phi / 8;
+            for (int i = tid; i < octs * kVoteCols; i += blockDim.x) {
+                const int c = i & 63, q = i >> 6;
+                const int sh = c >= 32 ? 16 : 0;
+                uint32_t wv[8];
 #pragma unroll
-            for (int j = 0; j < 8; ++j) w[j] = (slab[(8 * q + j) * 32 + (c & 31)] >> sh) & 0xFFFFu;
-            uint4 v;
-            v.x = w[0] | (w[1] << 16);
-            v.y = w[2] | (w[3] << 16);
-            v.z = w[4] | (w[5] << 16);
-            v.w = w[6] | (w[7] << 16);
-            *reinterpret_cast<uint4*>(acc + (size_t)(col0 + c) * n_phi + 8 * q) = v;
+                for (int j = 0; j < 8; ++j) wv[j] = (slab[(8 * q + j) * 32 + (c & 31)] >> sh) & 0xFFFFu;
+                uint4 v;
+                v.x = wv[0] | (wv[1] << 16);
+                v.y = wv[2] | (wv[3] << 16);
+                v.z = wv[4] | (wv[5] << 16);
+                v.w = wv[6] | (wv[7] << 16);
+                *reinterpret_cast<uint4*>(acc + (size_t)(col0 + c) * n_phi + 8 * q) = v;
+            }
+        }
+        if (queue) {
+            int* next_item = reinterpret_cast<int*>(slab + slab_dwords);
+            if (tid == 0) *next_item = (int)gridDim.x + atomicAdd(queue, 1);
+            __syncthreads();  // also: the slab reads above are done before the next zeroing
+            item = *next_item;
+            __syncthreads();
+        } else {
+            __syncthreads();
+            item += gridDim.x;
         }
     }
 }
@@ -486,19 +584,25 @@ __device__ __forceinline__ void load_plane(const T* __restrict__ acc, int l, int
     for (int i = 0; i < kStrip; ++i) w.all[i] = max(max(w.lo[i], m0[i]), w.hi[i]);
 }
 
+// grid.y = event.  Each thread walks `planes` d0 planes of one strip.
 template <typename T>
-__global__ __launch_bounds__(256) void k_peaks_mark(const T* __restrict__ acc, int32_t thr, int n_d0, int n_qpt,
-                                                    int n_phi, int group_lanes, uint8_t* __restrict__ flags,
-                                                    int32_t* __restrict__ grp_count,
-                                                    int32_t* __restrict__ grp_votes) {
+__global__ __launch_bounds__(256) void k_peaks_mark(Events ev, const char* __restrict__ acc_base, size_t acc_stride,
+                                                    int32_t thr, int n_d0, int n_qpt, int n_phi, int group_lanes,
+                                                    int planes, char* __restrict__ ws, WsOff O) {
+    const int e = blockIdx.y;
+    const T* acc = reinterpret_cast<const T*>(acc_base + (size_t)e * acc_stride);
+    char* w = event_ws(ws, ev, e);
+    uint8_t* flags = at<uint8_t>(w, O.flags);
+    int32_t* grp_count = at<int32_t>(w, O.grp_count);
+    int32_t* grp_votes = at<int32_t>(w, O.grp_votes);
     const int strips = n_phi / kStrip;
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int s = (int)(t % strips);
     const int k = (int)((t / strips) % n_qpt);
     const int lr = (int)(t / ((int64_t)strips * n_qpt));
-    const int l0 = lr * kPeakPlanes;
+    const int l0 = lr * planes;
     if (l0 >= n_d0) return;  // whole waves exit together (strips * n_qpt is a multiple of 64)
-    const int l1 = min(n_d0, l0 + kPeakPlanes);
+    const int l1 = min(n_d0, l0 + planes);
     PlaneWin prev, cur, next;
     load_plane(acc, l0 - 1, k, s, n_d0, n_qpt, n_phi, prev);
     load_plane(acc, l0, k, s, n_d0, n_qpt, n_phi, cur);
@@ -535,18 +639,22 @@ __global__ __launch_bounds__(256) void k_peaks_mark(const T* __restrict__ acc, i
     }
 }
 
-// One workgroup, tiles of kScanThreads * 16 groups: exclusive prefix sums of the per-group
-// candidate counts (grp_off, int32) and vote counts (grp_voff, int64).
+// One workgroup per event, tiles of kScanThreads * kScanPer groups: exclusive prefix sums of the
+// per-group candidate counts (grp_off, int32) and vote counts (grp_voff, int64).
 constexpr int kScanPer = 8;
-__global__ __launch_bounds__(kScanThreads) void k_peaks_scan(const int32_t* __restrict__ grp_count,
-                                                             const int32_t* __restrict__ grp_votes,
-                                                             int32_t* __restrict__ grp_off,
-                                                             int64_t* __restrict__ grp_voff, int64_t n_groups,
-                                                             int32_t cap, int32_t* __restrict__ listed,
-                                                             hough_status_t* st) {
+__global__ __launch_bounds__(kScanThreads) void k_peaks_scan(Events ev, int64_t n_groups, int32_t cap,
+                                                             char* __restrict__ ws, WsOff O,
+                                                             hough_status_t* __restrict__ st_base) {
     __shared__ int32_t tc[kScanThreads * kScanPer];
     __shared__ int64_t tv[kScanThreads * kScanPer];
     __shared__ int64_t wsum[kScanThreads / 64];
+    const int e = blockIdx.y;
+    char* w = event_ws(ws, ev, e);
+    const int32_t* grp_count = at<int32_t>(w, O.grp_count);
+    const int32_t* grp_votes = at<int32_t>(w, O.grp_votes);
+    int32_t* grp_off = at<int32_t>(w, O.grp_off);
+    int64_t* grp_voff = at<int64_t>(w, O.grp_voff);
+    hough_status_t* st = st_base + e;
     const int tid = threadIdx.x;
     int64_t carry_c = 0, carry_v = 0;
     for (int64_t base = 0; base < n_groups; base += kScanThreads * kScanPer) {
@@ -593,19 +701,26 @@ __global__ __launch_bounds__(kScanThreads) void k_peaks_scan(const int32_t* __re
         grp_off[n_groups] = (int32_t)min(carry_c, (int64_t)INT32_MAX);
         grp_voff[n_groups] = carry_v;
         st->n_peaks = (int32_t)min(carry_c, (int64_t)INT32_MAX);
-        *listed = (int32_t)min(carry_c, (int64_t)cap);
+        *at<int32_t>(w, O.misc) = (int32_t)min(carry_c, (int64_t)cap);
         if (carry_c > cap) atomicOr(&st->flags, HOUGH_F_PEAK_OVERFLOW);
     }
 }
 
-// One thread per strip: writes its candidates and their vote-prefix (CSR offset) in linear order.
+// One thread per strip (grid.y = event): writes its candidates and their vote-prefix (CSR offset)
+// in linear order.
 template <typename T>
-__global__ __launch_bounds__(256) void k_peaks_write(const T* __restrict__ acc, const uint8_t* __restrict__ flags,
-                                                     const int32_t* __restrict__ grp_off,
-                                                     const int64_t* __restrict__ grp_voff, int64_t n_groups,
-                                                     int n_qpt, int n_phi, int group_lanes, int64_t n_strips,
-                                                     hough_peak_t* __restrict__ peaks,
-                                                     int64_t* __restrict__ peak_voff, int32_t cap) {
+__global__ __launch_bounds__(256) void k_peaks_write(Events ev, const char* __restrict__ acc_base,
+                                                     size_t acc_stride, int64_t n_groups, int n_qpt, int n_phi,
+                                                     int group_lanes, int64_t n_strips, char* __restrict__ ws,
+                                                     WsOff O, hough_peak_t* __restrict__ peaks_base, int32_t cap) {
+    const int e = blockIdx.y;
+    const T* acc = reinterpret_cast<const T*>(acc_base + (size_t)e * acc_stride);
+    char* w = event_ws(ws, ev, e);
+    const uint8_t* flags = at<uint8_t>(w, O.flags);
+    const int32_t* grp_off = at<int32_t>(w, O.grp_off);
+    const int64_t* grp_voff = at<int64_t>(w, O.grp_voff);
+    int64_t* peak_voff = at<int64_t>(w, O.peak_voff);
+    hough_peak_t* peaks = peaks_base + (size_t)e * cap;
     const int strips = n_phi / kStrip;
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const uint32_t bits = t < n_strips ? flags[t] : 0u;
@@ -658,24 +773,29 @@ __global__ __launch_bounds__(256) void k_peaks_write(const T* __restrict__ acc, 
 }
 
 // ------------------------------------------------------------------ assign
-// One thread per listed candidate (the first min(listed, cap_peaks) written by the peaks pass):
-// CSR offset from the peaks pass, then for each layer the run(s) of sorted hits with angle in
-// [lo, lo + 2^F) (mod 2^M), lo = E + b * 2^F, copied in order.  The 64 candidates of a wave own one
-// contiguous stretch of the CSR list: it is assembled in an LDS buffer of the wave and then written
-// with coalesced stores (positions beyond the buffer go straight to memory).  The cell table is
-// staged in LDS; the per-layer sample values of a candidate are loaded together.
-constexpr int kAssignThreads = 1024;
-constexpr int kAssignBufMax = 2048;  // words of CSR list buffered per wave (less if the cell table is large)
-
+// One thread per listed candidate (the first min(listed, cap_peaks) written by the peaks pass;
+// grid.y = event): CSR offset from the peaks pass, then for each layer the run(s) of sorted hits
+// with angle in [lo, lo + 2^F) (mod 2^M), lo = E + b * 2^F, copied in order.  The 64 candidates of
+// a wave own one contiguous stretch of the CSR list: it is assembled in an LDS buffer of the wave
+// and then written with coalesced stores (positions beyond the buffer go straight to memory).  The
+// cell table is staged in LDS; the per-layer sample values of a candidate are loaded together.
 __global__ __launch_bounds__(kAssignThreads) void k_assign_fill(
-    const hough_peak_t* __restrict__ peaks, int32_t cap_peaks, hough_status_t* st,
-    const int64_t* __restrict__ peak_voff, const int32_t* __restrict__ listed,
-    const int32_t* __restrict__ E, const int32_t* __restrict__ g_cell_start,
-    const uint32_t* __restrict__ sorted_phi, const int32_t* __restrict__ sorted_h, int n_layers, int cell_bits,
-    int n_cols, int n_qpt, int M, int F, int32_t* __restrict__ offsets, int32_t* __restrict__ hit_idx,
-    int32_t cap_pairs, int buf_words) {
+    Events ev, const hough_peak_t* __restrict__ peaks_base, int32_t peak_stride, int32_t cap_peaks,
+    hough_status_t* __restrict__ st_base, const int32_t* __restrict__ E, int n_layers, int cell_bits, int n_cols,
+    int n_qpt, int M, int F, char* __restrict__ ws, WsOff O, int32_t* __restrict__ offsets_base,
+    int32_t* __restrict__ hit_idx_base, int32_t cap_pairs, int buf_words) {
     extern __shared__ int32_t sm_i32[];  // [waves][buf_words] buffers, then the cell table
-    const int n = min(*listed, cap_peaks);
+    const int e = blockIdx.y;
+    char* w = event_ws(ws, ev, e);
+    const hough_peak_t* peaks = peaks_base + (size_t)e * peak_stride;
+    const int64_t* peak_voff = at<int64_t>(w, O.peak_voff);
+    const int32_t* g_cell_start = at<int32_t>(w, O.cell_start);
+    const uint32_t* sorted_phi = at<uint32_t>(w, O.sorted_phi);
+    const int32_t* sorted_h = at<int32_t>(w, O.sorted_h);
+    int32_t* offsets = offsets_base + (size_t)e * (cap_peaks + 1);
+    int32_t* hit_idx = hit_idx_base + (size_t)e * cap_pairs;
+    hough_status_t* st = st_base + e;
+    const int n = min(*at<int32_t>(w, O.misc), cap_peaks);
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
@@ -705,15 +825,15 @@ __global__ __launch_bounds__(kAssignThreads) void k_assign_fill(
             offsets[i] = (int32_t)min(off, (int64_t)INT32_MAX);
             const hough_peak_t pk = peaks[i];
             const int32_t* Ec = E + (size_t)pk.l * n_qpt + pk.k;
-            int32_t e[kMaxLayers];
+            int32_t ev_l[kMaxLayers];
 #pragma unroll
-            for (int L = 0; L < kMaxLayers; ++L) e[L] = L < n_layers ? Ec[(size_t)L * n_cols] : INT32_MIN;
-            int64_t w = off;
+            for (int L = 0; L < kMaxLayers; ++L) ev_l[L] = L < n_layers ? Ec[(size_t)L * n_cols] : INT32_MIN;
+            int64_t wpos = off;
 #pragma unroll
             for (int L = 0; L < kMaxLayers; ++L) {
-                if (L >= n_layers || w >= cap_pairs) break;
-                if (e[L] == INT32_MIN) continue;
-                const uint32_t lo = ((uint32_t)e[L] + ((uint32_t)pk.b << F)) & (span - 1u);
+                if (L >= n_layers || wpos >= cap_pairs) break;
+                if (ev_l[L] == INT32_MIN) continue;
+                const uint32_t lo = ((uint32_t)ev_l[L] + ((uint32_t)pk.b << F)) & (span - 1u);
                 const uint32_t hi = lo + W;  // may exceed 2^M: the window wraps
                 const int cb = L << cell_bits;
                 const int lay_end = cell_start[cb + (1 << cell_bits)];
@@ -732,11 +852,11 @@ __global__ __launch_bounds__(kAssignThreads) void k_assign_fill(
                 for (int seg = 0; seg < 2; ++seg) {
                     const int a0 = seg == 0 ? q : r;
                     const int a1 = seg == 0 ? z : z2;
-                    for (int j = a0; j < a1 && w < cap_pairs; ++j, ++w) {
+                    for (int j = a0; j < a1 && wpos < cap_pairs; ++j, ++wpos) {
                         const int32_t h = sorted_h[j];
-                        const int64_t rel = w - o0;
+                        const int64_t rel = wpos - o0;
                         if (rel < buf_words) buf[rel] = h;
-                        else hit_idx[w] = h;
+                        else hit_idx[wpos] = h;
                     }
                 }
             }
@@ -746,7 +866,7 @@ __global__ __launch_bounds__(kAssignThreads) void k_assign_fill(
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         // coalesced flush of the buffered part of the stretch
         const int64_t fe = min(min(o1, o0 + buf_words), (int64_t)cap_pairs);
-        for (int64_t w = o0 + lane; w < fe; w += 64) hit_idx[w] = buf[w - o0];
+        for (int64_t wq = o0 + lane; wq < fe; wq += 64) hit_idx[wq] = buf[wq - o0];
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -762,6 +882,86 @@ int ilog2_exact(int v) {
 }
 
 int launch_status() { return hipGetLastError() == hipSuccess ? HOUGH_OK : HOUGH_E_HIP; }
+
+// Launchers shared by the single-event and batched entry points.
+void launch_prep(const hough_plan* p, const Events& ev, int n_events, int max_n, const float* x, const float* y,
+                 const uint8_t* layer, uint32_t* phi_out, char* ws, const WsOff& O, hough_status_t* st,
+                 hipStream_t stream) {
+    if (max_n > 0)
+        hipLaunchKernelGGL(k_prep_hits, dim3((max_n + 255) / 256, n_events), dim3(256), 0, stream, ev, x, y, layer,
+                           p->n_layers, p->cordic, ws, O, phi_out);
+    hipLaunchKernelGGL(k_prep_bucket, dim3(1, n_events), dim3(kScanThreads), 0, stream, ev, p->n_layers,
+                       p->cell_bits, p->M, p->layers, ws, O, st);
+    if (max_n > 0)
+        hipLaunchKernelGGL(k_prep_rank, dim3((max_n + 255) / 256, n_events), dim3(256), 0, stream, ev, p->n_cells,
+                           p->cell_bits, p->M, ws, O);
+}
+
+void launch_vote(const hough_plan* p, const Events& ev, int n_events, char* ws, const WsOff& O, void* acc,
+                 size_t acc_stride, const int32_t* order, int32_t* queue, int grid, hough_status_t* st,
+                 hipStream_t stream) {
+    const int threads = p->tuning.vote_threads;
+    if (p->g.acc_bits == 32)
+        hipLaunchKernelGGL(k_vote<false>, dim3(grid), dim3(threads), p->g.n_phi * 256 + 16, stream, ev, p->d_E,
+                           p->n_layers, p->cell_bits, p->n_cols, p->g.n_phi, p->F, ws, O, static_cast<char*>(acc),
+                           acc_stride, n_events, order, queue, st);
+    else
+        hipLaunchKernelGGL(k_vote<true>, dim3(grid), dim3(threads), p->g.n_phi * 128 + 16, stream, ev, p->d_E,
+                           p->n_layers, p->cell_bits, p->n_cols, p->g.n_phi, p->F, ws, O, static_cast<char*>(acc),
+                           acc_stride, n_events, order, queue, st);
+}
+
+void launch_peaks(const hough_plan* p, const Events& ev, int n_events, const void* acc, size_t acc_stride,
+                  int32_t threshold, hough_peak_t* peaks, int32_t cap, char* ws, const WsOff& O,
+                  hough_status_t* st, hipStream_t stream) {
+    const int strips = p->g.n_phi / kStrip;
+    const int gl = peak_group_lanes(p);
+    const int planes = p->tuning.peak_planes;
+    const int lranges = (p->g.n_d0 + planes - 1) / planes;
+    const int64_t mark_threads = (int64_t)strips * p->g.n_qpt * lranges;
+    const int64_t n_strips = p->n_bins / kStrip;
+    const int64_t groups = peak_groups(p);
+    const dim3 gm((unsigned)((mark_threads + 255) / 256), n_events);
+    const dim3 gw((unsigned)((n_strips + 255) / 256), n_events);
+    const char* a = static_cast<const char*>(acc);
+    if (p->g.acc_bits == 32)
+        hipLaunchKernelGGL(k_peaks_mark<int32_t>, gm, dim3(256), 0, stream, ev, a, acc_stride, threshold, p->g.n_d0,
+                           p->g.n_qpt, p->g.n_phi, gl, planes, ws, O);
+    else
+        hipLaunchKernelGGL(k_peaks_mark<int16_t>, gm, dim3(256), 0, stream, ev, a, acc_stride, threshold, p->g.n_d0,
+                           p->g.n_qpt, p->g.n_phi, gl, planes, ws, O);
+    hipLaunchKernelGGL(k_peaks_scan, dim3(1, n_events), dim3(kScanThreads), 0, stream, ev, groups, cap, ws, O, st);
+    if (p->g.acc_bits == 32)
+        hipLaunchKernelGGL(k_peaks_write<int32_t>, gw, dim3(256), 0, stream, ev, a, acc_stride, groups, p->g.n_qpt,
+                           p->g.n_phi, gl, n_strips, ws, O, peaks, cap);
+    else
+        hipLaunchKernelGGL(k_peaks_write<int16_t>, gw, dim3(256), 0, stream, ev, a, acc_stride, groups, p->g.n_qpt,
+                           p->g.n_phi, gl, n_strips, ws, O, peaks, cap);
+}
+
+void launch_assign(const hough_plan* p, const Events& ev, int n_events, const hough_peak_t* peaks,
+                   int32_t peak_stride, int32_t cap_peaks, int32_t* offsets, int32_t* hit_idx, int32_t cap_pairs,
+                   char* ws, const WsOff& O, hough_status_t* st, hipStream_t stream) {
+    const int64_t want = ((int64_t)cap_peaks + kAssignThreads - 1) / kAssignThreads;
+    const int per_event_cap = n_events > 1 ? 64 : 2 * 256;
+    const unsigned nblk = (unsigned)(want < per_event_cap ? want : per_event_cap);
+    const size_t cells_bytes = 4 * ((size_t)p->n_cells + 1);
+    int buf_words = (int)((kLdsBytes - cells_bytes) / 4 / (kAssignThreads / 64)) & ~63;
+    buf_words = buf_words > kAssignBufMax ? kAssignBufMax : buf_words;
+    const size_t lds = 4 * (size_t)(kAssignThreads / 64) * buf_words + cells_bytes;
+    hipLaunchKernelGGL(k_assign_fill, dim3(nblk, n_events), dim3(kAssignThreads), lds, stream, ev, peaks, peak_stride,
+                       cap_peaks, st, p->d_E, p->n_layers, p->cell_bits, p->n_cols, p->g.n_qpt, p->M, p->F, ws, O,
+                       offsets, hit_idx, cap_pairs, buf_words);
+}
+
+int check_hits(const hough_plan* p, const hough_hits_t* hits) {
+    if (!p || !hits) return HOUGH_E_INVAL;
+    if (hits->n < 0 || hits->n > p->g.max_hits_per_event) return HOUGH_E_INVAL;
+    if (hits->n > 0 && (!hits->x || !hits->y || !hits->layer)) return HOUGH_E_INVAL;
+    return HOUGH_OK;
+}
+
+Events single_event(const hough_plan* p, int n) { return Events{nullptr, n, p->g.max_hits_per_event, 0}; }
 
 }  // namespace
 
@@ -801,8 +1001,8 @@ int hough_plan_create(const hough_geometry_t* geom, const hough_grid_t* grid, ho
         return HOUGH_E_UNSUPPORTED;
     }
     // the slab of one vote workgroup must fit the 160 KiB of LDS
-    if ((size_t)g.n_phi * 256 > 160 * 1024 && g.acc_bits == 32) return HOUGH_E_UNSUPPORTED;
-    if ((size_t)g.n_phi * 128 > 160 * 1024 && g.acc_bits == 16) return HOUGH_E_UNSUPPORTED;
+    if ((size_t)g.n_phi * 256 + 16 > (size_t)kLdsBytes && g.acc_bits == 32) return HOUGH_E_UNSUPPORTED;
+    if ((size_t)g.n_phi * 128 + 16 > (size_t)kLdsBytes && g.acc_bits == 16) return HOUGH_E_UNSUPPORTED;
     if (!(g.qpt_max >= g.qpt_min) || !(g.d0_max >= g.d0_min)) return HOUGH_E_INVAL;
     if ((int64_t)g.n_d0 * g.n_qpt * g.n_phi > ((int64_t)1 << 31)) return HOUGH_E_UNSUPPORTED;
     if ((geom->n_layers << (lp < 10 ? lp : 10)) > kMaxCells) return HOUGH_E_UNSUPPORTED;
@@ -828,6 +1028,9 @@ int hough_plan_create(const hough_geometry_t* geom, const hough_grid_t* grid, ho
     p->n_cols = g.n_d0 * g.n_qpt;
     p->n_cells = p->n_layers << p->cell_bits;
     p->n_bins = (int64_t)p->n_cols * g.n_phi;
+    p->tuning.vote_threads = 1024;
+    p->tuning.vote_grid = 0;
+    p->tuning.peak_planes = 8;
     for (int i = 0; i < kCordicSteps; ++i)
         p->cordic.t[i] = (int32_t)llrint(atan(ldexp(1.0, -i)) * (2147483648.0 / M_PI));
 
@@ -876,12 +1079,11 @@ int hough_plan_create(const hough_geometry_t* geom, const hough_grid_t* grid, ho
         return HOUGH_E_HIP;
     }
     // dynamic LDS limits set to the whole 160 KiB once (a lower per-plan value would break other plans)
-    const int lds_max = 160 * 1024;
-    hipError_t ae = hipFuncSetAttribute((const void*)k_vote<false>, hipFuncAttributeMaxDynamicSharedMemorySize, lds_max);
+    hipError_t ae = hipFuncSetAttribute((const void*)k_vote<false>, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
     if (ae == hipSuccess)
-        ae = hipFuncSetAttribute((const void*)k_vote<true>, hipFuncAttributeMaxDynamicSharedMemorySize, lds_max);
+        ae = hipFuncSetAttribute((const void*)k_vote<true>, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
     if (ae == hipSuccess)
-        ae = hipFuncSetAttribute((const void*)k_assign_fill, hipFuncAttributeMaxDynamicSharedMemorySize, lds_max);
+        ae = hipFuncSetAttribute((const void*)k_assign_fill, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
     if (ae != hipSuccess) {
         (void)hipFree(p->d_E);
         delete p;
@@ -895,6 +1097,20 @@ void hough_plan_destroy(hough_plan_t* plan) {
     if (!plan) return;
     if (plan->d_E) (void)hipFree(plan->d_E);
     delete plan;
+}
+
+int hough_plan_set_tuning(hough_plan_t* p, const hough_tuning_t* t) {
+    if (!p || !t) return HOUGH_E_INVAL;
+    if (t->vote_threads != 256 && t->vote_threads != 512 && t->vote_threads != 1024) return HOUGH_E_INVAL;
+    if (t->vote_grid < 0 || t->peak_planes < 1 || t->peak_planes > 64) return HOUGH_E_INVAL;
+    p->tuning = *t;
+    return HOUGH_OK;
+}
+
+int hough_plan_get_tuning(const hough_plan_t* p, hough_tuning_t* t) {
+    if (!p || !t) return HOUGH_E_INVAL;
+    *t = p->tuning;
+    return HOUGH_OK;
 }
 
 size_t hough_acc_bytes(const hough_plan_t* p) { return p ? (size_t)p->n_bins * (p->g.acc_bits / 8) : 0; }
@@ -912,13 +1128,6 @@ int hough_plan_table(const hough_plan_t* p, int32_t* out) {
                                                                                              : HOUGH_E_HIP;
 }
 
-static int check_hits(const hough_plan_t* p, const hough_hits_t* hits) {
-    if (!p || !hits) return HOUGH_E_INVAL;
-    if (hits->n < 0 || hits->n > p->g.max_hits_per_event) return HOUGH_E_INVAL;
-    if (hits->n > 0 && (!hits->x || !hits->y || !hits->layer)) return HOUGH_E_INVAL;
-    return HOUGH_OK;
-}
-
 int hough_prep(const hough_plan_t* p, const hough_hits_t* hits, uint32_t* phi_out, void* ws, size_t ws_bytes,
                hough_status_t* st, hipStream_t stream) {
     int rc = check_hits(p, hits);
@@ -926,17 +1135,8 @@ int hough_prep(const hough_plan_t* p, const hough_hits_t* hits, uint32_t* phi_ou
     if (!ws || !st) return HOUGH_E_INVAL;
     const WsLayout L = ws_layout(p, 0);
     if (ws_bytes < L.total) return HOUGH_E_SMALL_WS;
-    const int n = hits->n;
-    if (n > 0)
-        hipLaunchKernelGGL(k_prep_hits, dim3((n + 255) / 256), dim3(256), 0, stream, hits->x, hits->y, hits->layer,
-                           n, p->n_layers, p->cordic, at<uint32_t>(ws, L.phi32), at<uint8_t>(ws, L.lay), phi_out);
-    hipLaunchKernelGGL(k_prep_bucket, dim3(1), dim3(kScanThreads), 0, stream, at<uint32_t>(ws, L.phi32),
-                       at<uint8_t>(ws, L.lay), n, p->n_layers, p->cell_bits, p->M, p->layers,
-                       at<int32_t>(ws, L.cell_start), at<uint32_t>(ws, L.tmp_phi), at<int32_t>(ws, L.tmp_key), st);
-    if (n > 0)
-        hipLaunchKernelGGL(k_prep_rank, dim3((n + 255) / 256), dim3(256), 0, stream, at<uint32_t>(ws, L.tmp_phi),
-                           at<int32_t>(ws, L.tmp_key), at<int32_t>(ws, L.cell_start), p->n_cells, p->cell_bits, p->M,
-                           at<uint32_t>(ws, L.sorted_phi), at<int32_t>(ws, L.sorted_h));
+    launch_prep(p, single_event(p, hits->n), 1, hits->n, hits->x, hits->y, hits->layer, phi_out,
+                static_cast<char*>(ws), ws_off(L), st, stream);
     return launch_status();
 }
 
@@ -945,15 +1145,8 @@ int hough_vote_prepared(const hough_plan_t* p, void* acc, void* ws, size_t ws_by
     if (!p || !acc || !ws || !st) return HOUGH_E_INVAL;
     const WsLayout L = ws_layout(p, 0);
     if (ws_bytes < L.total) return HOUGH_E_SMALL_WS;
-    const int n_slabs = p->n_cols / kVoteCols;
-    if (p->g.acc_bits == 32)
-        hipLaunchKernelGGL(k_vote<false>, dim3(n_slabs), dim3(kVoteThreads), p->g.n_phi * 256, stream, p->d_E,
-                           at<int32_t>(ws, L.cell_start), at<uint32_t>(ws, L.sorted_phi), p->n_layers,
-                           p->cell_bits, p->n_cols, p->g.n_phi, p->F, acc, st);
-    else
-        hipLaunchKernelGGL(k_vote<true>, dim3(n_slabs), dim3(kVoteThreads), p->g.n_phi * 128, stream, p->d_E,
-                           at<int32_t>(ws, L.cell_start), at<uint32_t>(ws, L.sorted_phi), p->n_layers,
-                           p->cell_bits, p->n_cols, p->g.n_phi, p->F, acc, st);
+    launch_vote(p, single_event(p, 0), 1, static_cast<char*>(ws), ws_off(L), acc, 0, nullptr, nullptr,
+                p->n_cols / kVoteCols, st, stream);
     return launch_status();
 }
 
@@ -970,32 +1163,8 @@ int hough_peaks(const hough_plan_t* p, const void* acc, int32_t threshold, hough
     if (!p || !acc || !peaks || !ws || !st || cap < 1 || threshold < 1) return HOUGH_E_INVAL;
     const WsLayout L = ws_layout(p, cap);
     if (ws_bytes < L.total) return HOUGH_E_SMALL_WS;
-    const int strips = p->g.n_phi / kStrip;
-    const int gl = peak_group_lanes(p);
-    const int lranges = (p->g.n_d0 + kPeakPlanes - 1) / kPeakPlanes;
-    const int64_t mark_threads = (int64_t)strips * p->g.n_qpt * lranges;
-    const int64_t n_strips = p->n_bins / kStrip;
-    const int64_t groups = peak_groups(p);
-    const dim3 gm((unsigned)((mark_threads + 255) / 256)), gw((unsigned)((n_strips + 255) / 256));
-    if (p->g.acc_bits == 32)
-        hipLaunchKernelGGL(k_peaks_mark<int32_t>, gm, dim3(256), 0, stream, static_cast<const int32_t*>(acc),
-                           threshold, p->g.n_d0, p->g.n_qpt, p->g.n_phi, gl, at<uint8_t>(ws, L.flags),
-                           at<int32_t>(ws, L.grp_count), at<int32_t>(ws, L.grp_votes));
-    else
-        hipLaunchKernelGGL(k_peaks_mark<int16_t>, gm, dim3(256), 0, stream, static_cast<const int16_t*>(acc),
-                           threshold, p->g.n_d0, p->g.n_qpt, p->g.n_phi, gl, at<uint8_t>(ws, L.flags),
-                           at<int32_t>(ws, L.grp_count), at<int32_t>(ws, L.grp_votes));
-    hipLaunchKernelGGL(k_peaks_scan, dim3(1), dim3(kScanThreads), 0, stream, at<int32_t>(ws, L.grp_count),
-                       at<int32_t>(ws, L.grp_votes), at<int32_t>(ws, L.grp_off), at<int64_t>(ws, L.grp_voff), groups,
-                       cap, at<int32_t>(ws, L.misc), st);
-    if (p->g.acc_bits == 32)
-        hipLaunchKernelGGL(k_peaks_write<int32_t>, gw, dim3(256), 0, stream, static_cast<const int32_t*>(acc),
-                           at<uint8_t>(ws, L.flags), at<int32_t>(ws, L.grp_off), at<int64_t>(ws, L.grp_voff), groups,
-                           p->g.n_qpt, p->g.n_phi, gl, n_strips, peaks, at<int64_t>(ws, L.peak_voff), cap);
-    else
-        hipLaunchKernelGGL(k_peaks_write<int16_t>, gw, dim3(256), 0, stream, static_cast<const int16_t*>(acc),
-                           at<uint8_t>(ws, L.flags), at<int32_t>(ws, L.grp_off), at<int64_t>(ws, L.grp_voff), groups,
-                           p->g.n_qpt, p->g.n_phi, gl, n_strips, peaks, at<int64_t>(ws, L.peak_voff), cap);
+    launch_peaks(p, single_event(p, 0), 1, acc, 0, threshold, peaks, cap, static_cast<char*>(ws), ws_off(L), st,
+                 stream);
     return launch_status();
 }
 
@@ -1005,17 +1174,90 @@ int hough_assign(const hough_plan_t* p, const hough_peak_t* peaks, int32_t cap_p
     if (!p || !peaks || !offsets || !hit_idx || !ws || !st || cap_peaks < 1 || cap_pairs < 1) return HOUGH_E_INVAL;
     const WsLayout L = ws_layout(p, cap_peaks);
     if (ws_bytes < L.total) return HOUGH_E_SMALL_WS;
-    const int64_t want = ((int64_t)cap_peaks + kAssignThreads - 1) / kAssignThreads;
-    const unsigned nblk = (unsigned)(want < 2 * 256 ? want : 2 * 256);
-    const size_t cells_bytes = 4 * ((size_t)p->n_cells + 1);
-    int buf_words = (int)((160 * 1024 - cells_bytes) / 4 / (kAssignThreads / 64)) & ~63;
-    buf_words = buf_words > kAssignBufMax ? kAssignBufMax : buf_words;
-    const size_t lds = 4 * (size_t)(kAssignThreads / 64) * buf_words + cells_bytes;
-    hipLaunchKernelGGL(k_assign_fill, dim3(nblk), dim3(kAssignThreads), lds, stream, peaks, cap_peaks, st,
-                       at<int64_t>(ws, L.peak_voff), at<int32_t>(ws, L.misc), p->d_E, at<int32_t>(ws, L.cell_start),
-                       at<uint32_t>(ws, L.sorted_phi), at<int32_t>(ws, L.sorted_h), p->n_layers, p->cell_bits,
-                       p->n_cols, p->g.n_qpt, p->M, p->F, offsets, hit_idx, cap_pairs, buf_words);
+    launch_assign(p, single_event(p, 0), 1, peaks, cap_peaks, cap_peaks, offsets, hit_idx, cap_pairs,
+                  static_cast<char*>(ws), ws_off(L), st, stream);
     return launch_status();
+}
+
+// ---------------------------------------------------------------------- batches
+size_t hough_batch_ws_bytes(const hough_plan_t* p, int32_t n_events, int32_t cap_peaks) {
+    if (!p || n_events < 1) return 0;
+    return batch_header_bytes(n_events) + (size_t)n_events * ws_layout(p, cap_peaks).total;
+}
+
+int hough_run_batch(const hough_plan_t* p, const hough_batch_t* b, hipStream_t stream) {
+    if (!p || !b) return HOUGH_E_INVAL;
+    if (b->n_events < 1 || b->cap_peaks < 1 || b->cap_pairs < 1 || b->threshold < 1) return HOUGH_E_INVAL;
+    if (!b->hit_offsets || !b->x || !b->y || !b->layer || !b->acc || !b->peaks || !b->offsets || !b->hit_idx ||
+        !b->ws || !b->status)
+        return HOUGH_E_INVAL;
+    const WsLayout L = ws_layout(p, b->cap_peaks);
+    const size_t hdr = batch_header_bytes(b->n_events);
+    if (b->ws_bytes < hdr + (size_t)b->n_events * L.total) return HOUGH_E_SMALL_WS;
+    char* ws = static_cast<char*>(b->ws);
+    int32_t* queue = reinterpret_cast<int32_t*>(ws);
+    int32_t* order = reinterpret_cast<int32_t*>(ws + 256);
+    char* ev_ws = ws + hdr;
+    const Events ev{b->hit_offsets, 0, p->g.max_hits_per_event, L.total};
+    const WsOff O = ws_off(L);
+    const int max_n = p->g.max_hits_per_event;  // per-event grids cover the plan's limit; extra blocks exit
+    hipLaunchKernelGGL(k_batch_init, dim3(1), dim3(1024), 0, stream, b->hit_offsets, b->n_events, queue, order);
+    launch_prep(p, ev, b->n_events, max_n, b->x, b->y, b->layer, nullptr, ev_ws, O, b->status, stream);
+    int grid = p->tuning.vote_grid;
+    if (grid <= 0) grid = 256;
+    const int items = b->n_events * (p->n_cols / kVoteCols);
+    if (grid > items) grid = items;
+    launch_vote(p, ev, b->n_events, ev_ws, O, b->acc, hough_acc_bytes(p), order, queue, grid, b->status, stream);
+    launch_peaks(p, ev, b->n_events, b->acc, hough_acc_bytes(p), b->threshold, b->peaks, b->cap_peaks, ev_ws, O,
+                 b->status, stream);
+    launch_assign(p, ev, b->n_events, b->peaks, b->cap_peaks, b->cap_peaks, b->offsets, b->hit_idx, b->cap_pairs,
+                  ev_ws, O, b->status, stream);
+    return launch_status();
+}
+
+struct hough_graph {
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+};
+
+int hough_batch_graph_create(const hough_plan_t* p, const hough_batch_t* b, hipStream_t stream,
+                             hough_graph_t** out) {
+    if (!p || !b || !out || !stream) return HOUGH_E_INVAL;
+    *out = nullptr;
+    hough_graph* g = new (std::nothrow) hough_graph();
+    if (!g) return HOUGH_E_NOMEM;
+    if (hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        delete g;
+        return HOUGH_E_HIP;
+    }
+    const int rc = hough_run_batch(p, b, stream);
+    hipGraph_t graph = nullptr;
+    const hipError_t ee = hipStreamEndCapture(stream, &graph);
+    if (rc != HOUGH_OK || ee != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        delete g;
+        return rc != HOUGH_OK ? rc : HOUGH_E_HIP;
+    }
+    if (hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+        (void)hipGraphDestroy(graph);
+        delete g;
+        return HOUGH_E_HIP;
+    }
+    g->graph = graph;
+    *out = g;
+    return HOUGH_OK;
+}
+
+int hough_graph_launch(hough_graph_t* g, hipStream_t stream) {
+    if (!g) return HOUGH_E_INVAL;
+    return hipGraphLaunch(g->exec, stream) == hipSuccess ? HOUGH_OK : HOUGH_E_HIP;
+}
+
+void hough_graph_destroy(hough_graph_t* g) {
+    if (!g) return;
+    (void)hipGraphExecDestroy(g->exec);
+    (void)hipGraphDestroy(g->graph);
+    delete g;
 }
 
 }  // extern "C"

@@ -42,8 +42,21 @@ class Hits(C.Structure):
     _fields_ = [("x", C.c_void_p), ("y", C.c_void_p), ("z", C.c_void_p), ("layer", C.c_void_p), ("n", C.c_int32)]
 
 
+class Tuning(C.Structure):
+    _fields_ = [("vote_threads", C.c_int32), ("vote_grid", C.c_int32), ("peak_planes", C.c_int32)]
+
+
+class Batch(C.Structure):
+    _fields_ = [("x", C.c_void_p), ("y", C.c_void_p), ("z", C.c_void_p), ("layer", C.c_void_p),
+                ("hit_offsets", C.c_void_p), ("n_events", C.c_int32), ("threshold", C.c_int32),
+                ("cap_peaks", C.c_int32), ("cap_pairs", C.c_int32), ("acc", C.c_void_p), ("peaks", C.c_void_p),
+                ("offsets", C.c_void_p), ("hit_idx", C.c_void_p), ("ws", C.c_void_p), ("ws_bytes", C.c_size_t),
+                ("status", C.c_void_p)]
+
+
 STATUS_BYTES = 32
 PEAK_INTS = 4
+HOUGH_F_EVENT_TOO_LARGE = 4
 
 
 def _load() -> C.CDLL:
@@ -66,6 +79,14 @@ def _load() -> C.CDLL:
     L.hough_assign.restype = C.c_int
     L.hough_assign.argtypes = [P, P, C.c_int32, P, P, C.c_int32, P, S, P, P]
     L.hough_strerror.restype = C.c_char_p; L.hough_strerror.argtypes = [C.c_int]
+    L.hough_plan_set_tuning.restype = C.c_int; L.hough_plan_set_tuning.argtypes = [P, C.POINTER(Tuning)]
+    L.hough_plan_get_tuning.restype = C.c_int; L.hough_plan_get_tuning.argtypes = [P, C.POINTER(Tuning)]
+    L.hough_batch_ws_bytes.restype = S; L.hough_batch_ws_bytes.argtypes = [P, C.c_int32, C.c_int32]
+    L.hough_run_batch.restype = C.c_int; L.hough_run_batch.argtypes = [P, C.POINTER(Batch), P]
+    L.hough_batch_graph_create.restype = C.c_int
+    L.hough_batch_graph_create.argtypes = [P, C.POINTER(Batch), P, C.POINTER(C.c_void_p)]
+    L.hough_graph_launch.restype = C.c_int; L.hough_graph_launch.argtypes = [P, P]
+    L.hough_graph_destroy.restype = None; L.hough_graph_destroy.argtypes = [P]
     return L
 
 
@@ -73,7 +94,9 @@ lib = _load()
 
 EXPORTED = ["hough_plan_create", "hough_plan_destroy", "hough_acc_bytes", "hough_event_ws_bytes",
             "hough_angle_bits", "hough_plan_table", "hough_prep", "hough_vote", "hough_vote_prepared", "hough_peaks",
-            "hough_assign", "hough_strerror"]
+            "hough_assign", "hough_strerror", "hough_plan_set_tuning", "hough_plan_get_tuning",
+            "hough_batch_ws_bytes", "hough_run_batch", "hough_batch_graph_create", "hough_graph_launch",
+            "hough_graph_destroy"]
 
 
 def _check(rc: int, what: str) -> None:
@@ -137,6 +160,19 @@ class Plan:
 
     def ws_bytes(self, max_peaks: int = 0) -> int:
         return int(lib.hough_event_ws_bytes(self.handle, int(max_peaks)))
+
+    def batch_ws_bytes(self, n_events: int, cap_peaks: int) -> int:
+        return int(lib.hough_batch_ws_bytes(self.handle, int(n_events), int(cap_peaks)))
+
+    @property
+    def tuning(self) -> dict:
+        t = Tuning()
+        _check(lib.hough_plan_get_tuning(self.handle, C.byref(t)), "hough_plan_get_tuning")
+        return dict(vote_threads=t.vote_threads, vote_grid=t.vote_grid, peak_planes=t.peak_planes)
+
+    def set_tuning(self, vote_threads: int = 1024, vote_grid: int = 0, peak_planes: int = 8) -> None:
+        t = Tuning(int(vote_threads), int(vote_grid), int(peak_planes))
+        _check(lib.hough_plan_set_tuning(self.handle, C.byref(t)), "hough_plan_set_tuning")
 
     def table(self) -> np.ndarray:
         c = self.cfg
@@ -236,3 +272,80 @@ def hits_to_device(ev, device="cuda"):
     lay = torch.from_numpy(np.ascontiguousarray(ev.layer)).to(device)
     z = torch.from_numpy(np.ascontiguousarray(ev.z)).to(device) if getattr(ev, "z", None) is not None else None
     return x, y, lay, z
+
+
+class BatchBuffers:
+    """Device buffers of a batch of up to `n_events` events (packed hits and strided outputs)."""
+
+    def __init__(self, plan: Plan, n_events: int, max_total_hits: int, cap_peaks: int, cap_pairs: int,
+                 device="cuda"):
+        self.plan = plan
+        c = plan.cfg
+        self.n_events = int(n_events)
+        self.cap_peaks, self.cap_pairs = int(cap_peaks), int(cap_pairs)
+        self.x = torch.zeros(max(max_total_hits, 1), dtype=torch.float32, device=device)
+        self.y = torch.zeros_like(self.x)
+        self.layer = torch.zeros(max(max_total_hits, 1), dtype=torch.uint8, device=device)
+        self.hit_offsets = torch.zeros(self.n_events + 1, dtype=torch.int32, device=device)
+        self.acc = torch.empty((self.n_events, c.n_d0, c.n_qpt, c.n_phi), dtype=plan.acc_dtype, device=device)
+        self.peaks = torch.empty((self.n_events, cap_peaks, PEAK_INTS), dtype=torch.int32, device=device)
+        self.offsets = torch.empty((self.n_events, cap_peaks + 1), dtype=torch.int32, device=device)
+        self.hit_idx = torch.empty((self.n_events, cap_pairs), dtype=torch.int32, device=device)
+        self.ws = torch.empty(plan.batch_ws_bytes(self.n_events, cap_peaks), dtype=torch.uint8, device=device)
+        self.status = torch.zeros((self.n_events, STATUS_BYTES // 4), dtype=torch.int32, device=device)
+
+    def load(self, events, stream=None) -> None:
+        """Copy the packed hits of `events` (at most n_events) into the device buffers."""
+        assert len(events) == self.n_events
+        offs = np.zeros(len(events) + 1, dtype=np.int32)
+        offs[1:] = np.cumsum([e.n for e in events])
+        n = int(offs[-1])
+        assert n <= self.x.numel()
+        if n:
+            self.x[:n].copy_(torch.from_numpy(np.concatenate([e.x for e in events])), non_blocking=False)
+            self.y[:n].copy_(torch.from_numpy(np.concatenate([e.y for e in events])), non_blocking=False)
+            self.layer[:n].copy_(torch.from_numpy(np.concatenate([e.layer for e in events])), non_blocking=False)
+        self.hit_offsets.copy_(torch.from_numpy(offs))
+
+    def struct(self, threshold: int) -> Batch:
+        return Batch(_ptr(self.x), _ptr(self.y), None, _ptr(self.layer), _ptr(self.hit_offsets), self.n_events,
+                     int(threshold), self.cap_peaks, self.cap_pairs, _ptr(self.acc), _ptr(self.peaks),
+                     _ptr(self.offsets), _ptr(self.hit_idx), _ptr(self.ws), self.ws.numel(), _ptr(self.status))
+
+    def run(self, threshold: int, stream=None) -> None:
+        b = self.struct(threshold)
+        _check(lib.hough_run_batch(self.plan.handle, C.byref(b), _stream(stream)), "hough_run_batch")
+
+    def results(self, e: int) -> dict:
+        st = status_dict(self.status[e])
+        n = min(st["n_peaks"], self.cap_peaks)
+        pk = self.peaks[e, :n].cpu().numpy()
+        offs = self.offsets[e, : n + 1].cpu().numpy().astype(np.int64)
+        npairs = min(st["n_pairs"], self.cap_pairs)
+        return dict(status=st, peaks=pk, offsets=offs, hit_idx=self.hit_idx[e, :npairs].cpu().numpy())
+
+
+class Graph:
+    """The batched chain of a BatchBuffers captured into a hipGraph (buffers bound at capture)."""
+
+    def __init__(self, bufs: BatchBuffers, threshold: int, stream):
+        self.bufs = bufs
+        self._b = bufs.struct(threshold)
+        h = C.c_void_p()
+        _check(lib.hough_batch_graph_create(bufs.plan.handle, C.byref(self._b), _stream(stream), C.byref(h)),
+               "hough_batch_graph_create")
+        self.handle = h.value
+
+    def launch(self, stream=None) -> None:
+        _check(lib.hough_graph_launch(self.handle, _stream(stream)), "hough_graph_launch")
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib.hough_graph_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
