@@ -21,6 +21,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -123,6 +125,79 @@ def bench_batched(H, torch, n_events: int, reps: int):
     }
 
 
+def bench_large_grid(H, torch, reps: int):
+    """The large-grid workload: 64 events of 600 prompt tracks plus two displaced vertices, 20 %
+    noise, with z, on a 1024x512x128 int16 grid, batched, followed by the second-stage
+    cot(theta) x z0 (128 x 128) vote of every candidate.  The r-z stage's share is the
+    difference between the chain with and without it."""
+    from paper_1305_4855_amd import configs, synth
+
+    cfg = configs.C4
+    events = [synth.make_event(cfg, i) for i in range(cfg.n_events)]
+    plan = H.Plan(cfg, max_hits=cfg.max_hits_per_event)
+    total = sum(e.n for e in events)
+    bufs = H.BatchBuffers(plan, len(events), total, cap_peaks=1 << 21, cap_pairs=1 << 25)
+    bufs.load(events)
+    stream = torch.cuda.current_stream()
+    bufs.run(cfg.threshold, stream)
+    torch.cuda.synchronize()
+    times = {}
+    for with_z in (False, True):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(reps):
+            bufs.run(cfg.threshold, stream, zvote=with_z)
+        b.record(stream)
+        torch.cuda.synchronize()
+        times[with_z] = a.elapsed_time(b) / reps
+    st = bufs.status.cpu().numpy()
+    votes = int(st.view("int64")[:, 1].sum())
+    cands = int(st[:, 4].sum())
+    pairs = int(st.view("int64")[:, 3].sum())
+    flags = int(np.bitwise_or.reduce(st[:, 5]))
+    del bufs
+    zv_ms = times[True] - times[False]
+    return {
+        "workload": f"batch of {len(events)} events (c4): 600 prompt tracks + 2 displaced vertices, 20% noise, "
+                    f"1024x512x128 int16, then 128x128 cot(theta) x z0 vote per candidate",
+        "hits": total, "hit_votes": votes, "candidates": cands, "pairs": pairs, "status_flags_or": flags,
+        "ms_per_batch": round(times[True], 3), "ms_per_batch_without_zvote": round(times[False], 3),
+        "events_per_s": round(len(events) / times[True] * 1e3, 2),
+        "events_per_s_without_zvote": round(len(events) / times[False] * 1e3, 2),
+        "zvote_ms_per_event": round(zv_ms / len(events), 4),
+    }
+
+
+def bench_serving(H, torch, duration_s: float, rate_hz: float, pool_size: int = 256):
+    """Streaming trigger serving: Poisson arrivals at rate_hz for duration_s, event sizes as in the
+    batched workload, admitted into device-resident slots within a 64 GiB accumulator budget, continuous
+    batching over concurrent lanes (see paper_1305_4855_amd/serve.py)."""
+    from paper_1305_4855_amd import configs, serve, synth, tune
+
+    cfg = configs.C5
+    pool = [synth.make_event(cfg, i) for i in range(pool_size)]
+    plan = H.Plan(cfg, max_hits=cfg.max_hits_per_event)
+    tune.apply(plan)
+    srv = serve.Server(plan, cfg.threshold, acc_budget_bytes=cfg.hbm_budget_bytes, max_lanes=4,
+                       max_lane_events=512, cap_peaks=1 << 19, cap_pairs=1 << 23, hits_per_slot=8192, topk=64)
+    # warm up every lane once
+    warm = np.linspace(0.0, 0.01, srv.slots)
+    srv.serve(pool, warm, np.arange(len(warm)) % pool_size)
+    arrivals = serve.poisson_arrivals(rate_hz, duration_s)
+    rng = np.random.default_rng([13054855, 5, 1])
+    pool_idx = rng.integers(0, pool_size, size=len(arrivals))
+    print(f"[bench] serving {len(arrivals)} arrivals over {duration_s:.0f} s in {srv.slots} slots", file=sys.stderr,
+          flush=True)
+    stats = srv.serve(pool, arrivals, pool_idx, progress=lambda t, n, q: print(
+        f"[bench] serving t={t:.0f}s served={n} queued={q}", file=sys.stderr, flush=True))
+    stats.update(workload=f"Poisson arrivals at {rate_hz:.0f} Hz for {duration_s:.0f} s, sizes as the batched "
+                          f"workload (pool of {pool_size} distinct events), 64 GiB accumulator budget "
+                          f"({srv.slots} slots in {srv.n_lanes} lanes), 512x256x64 int32",
+                 latency_definition="arrival -> candidate list complete on the device, status and first 64 "
+                                    "candidates on the host")
+    return stats
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -131,6 +206,10 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batch-events", type=int, default=256)
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-large-grid", action="store_true")
+    ap.add_argument("--serve-seconds", type=float, default=60.0)
+    ap.add_argument("--serve-rate", type=float, default=20000.0)
     ap.add_argument("--pmc-calibration", action="store_true",
                     help="also run a plain 256 MiB device copy (for scaling HBM counters)")
     args = ap.parse_args()
@@ -238,9 +317,15 @@ def main() -> int:
     }
     if not args.no_batched:
         out["batched"] = bench_batched(H, torch, args.batch_events, reps=10)
+    if not args.no_large_grid:
+        out["large_grid"] = bench_large_grid(H, torch, reps=3)
+    if not args.no_serving:
+        del bufs
+        torch.cuda.empty_cache()
+        out["serving"] = bench_serving(H, torch, args.serve_seconds, args.serve_rate)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, ev)
-    print(json.dumps(out), flush=True)
+    print(json.dumps(out, default=lambda o: o.item() if isinstance(o, np.generic) else str(o)), flush=True)
     return 0
 
 

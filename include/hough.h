@@ -184,14 +184,44 @@ int hough_assign(const hough_plan_t* plan, const hough_peak_t* peaks, int32_t ca
                  int32_t* hit_idx, int32_t cap_pairs, void* ws, size_t ws_bytes, hough_status_t* st,
                  hipStream_t stream);
 
+/* a5 -- second-stage r-z vote of every candidate (an extension: the paper's
+ * detector model is transverse only, Sec. "Preliminary Results"; this is the
+ * straight-line Hough of Sec. "Proposed Fast Tracking Algorithm" applied to
+ * the (s, z) plane of each candidate, z = z0 + s cot(theta)).
+ * Needs a plan with n_cot, n_z0 > 0.  For candidate p with d0 centre d and
+ * curvature c of its (l, k), each hit h of its CSR list with a usable z
+ * (finite, |z| < 32768 cm) has Z = rne(z * 2^16) and the arc length to its
+ * layer S = llrint(s * 2^16), s = (2/|c|) asin(|c| Lc / 2) (Lc when c = 0),
+ * Lc = sqrt(r^2 + d^2 - 2 d r A) the chord from the origin, A as in the
+ * sample.  For each cot(theta) row m (Q16.16 centre C_m = llrint(centre *
+ * 2^16)) the hit votes into z0 bin j = floor((Z * 2^16 - S * C_m - Z0) / W)
+ * when 0 <= j < n_z0, with Z0 = llrint(z0_min * 2^32) and W =
+ * llrint(z0 bin width * 2^32) (Q32.32 cm).  out (dev) [cap_peaks][3] gets
+ * (m, j, votes) of the fullest bin, lowest m * n_z0 + j on ties;
+ * (-1, -1, 0) when no hit votes; (-1, -1, -1) when the candidate's list was
+ * cut by cap_pairs.  Candidates: the first min(st->n_peaks, cap_peaks)
+ * (st read on the device).  Supported grids: n_z0 <= 512, n_cot * n_z0 <=
+ * 65536, W a power of two, the C_m an exact arithmetic progression,
+ * |cot| <= 1024, |z0| <= 32768 cm, max_hits_per_event <= 65535 (otherwise
+ * hough_plan_create returns HOUGH_E_UNSUPPORTED).  hits->x, y are not read. */
+int hough_zvote(const hough_plan_t* plan, const hough_hits_t* hits, const hough_peak_t* peaks, int32_t cap_peaks,
+                const int32_t* offsets, const int32_t* hit_idx, int32_t cap_pairs, const hough_status_t* st,
+                int32_t* out, hipStream_t stream);
+
+/* Copy the arc-length table S[L][l][k] (int32 Q16.16, -1 = invalid) of a
+ * plan with an r-z grid to host memory `out` (n_layers*n_d0*n_qpt entries).
+ * Synchronous; for tests. */
+int hough_plan_arclen_table(const hough_plan_t* plan, int32_t* out);
+
 /* a7 -- batched form: many events of uneven size in one launch chain.  The
  * hits of all events are packed (CSR: event e owns hits [hit_offsets[e],
  * hit_offsets[e+1])); every per-event output is strided by its capacity.
  * The vote is one persistent kernel that pulls (event, slab of 64 columns)
  * items from a device work queue, largest events first (Sec. "Preliminary
  * Results", data paragraph: each GPU processes one event after another; here
- * the events of a batch share the GPU).  Results of each event are identical
- * to the single-event calls.  Stream-ordered; capturable in a hipGraph. */
+ * the events of a batch share the GPU).  With `zvote` set (plan with an r-z
+ * grid, z given) the chain ends with hough_zvote of every event.  Results of
+ * each event are identical to the single-event calls.  Stream-ordered; capturable in a hipGraph. */
 typedef struct {
     const float* x;            /* (dev) packed hits of all events                        */
     const float* y;
@@ -209,6 +239,7 @@ typedef struct {
     void* ws;                  /* (dev) hough_batch_ws_bytes(plan, n_events, cap_peaks)  */
     size_t ws_bytes;
     hough_status_t* status;    /* (dev) n_events                                         */
+    int32_t* zvote;            /* (dev) n_events x cap_peaks x 3, or NULL: no r-z stage  */
 } hough_batch_t;
 
 size_t hough_batch_ws_bytes(const hough_plan_t* plan, int32_t n_events, int32_t cap_peaks);

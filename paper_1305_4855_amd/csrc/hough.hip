@@ -28,7 +28,13 @@
 //   assign  each candidate copies, layer by layer, the run of sorted hits
 //           whose angle falls into its phi0 window; the candidates of a wave
 //           assemble their stretch of the CSR list in LDS and store it
-//           coalesced.
+//           coalesced;
+//   zvote   (second stage in r-z) one wave per candidate: with H <= 64 hits,
+//           min(16, 64 / H) rows of the cot(theta) x z0 grid are voted at once,
+//           one lane per (row, hit), into per-row LDS histograms whose words
+//           carry their own tie-break key, so the argmax is tracked from the
+//           atomic's return value and each touched word is restored right
+//           after the vote (no clearing pass, no scan of the grid).
 #include <hip/hip_runtime.h>
 
 #include <climits>
@@ -52,6 +58,9 @@ constexpr int kMaxCells = 32768;    // LDS histogram of the prep bucketing (128 
 constexpr int kAssignThreads = 1024;
 constexpr int kAssignBufMax = 2048; // words of CSR list buffered per wave (less if the cell table is large)
 constexpr int kLdsBytes = 160 * 1024;
+constexpr int kZvoteThreads = 256;
+constexpr int kZvoteSlots = 16;     // rows of the r-z grid one wave votes at once
+constexpr int kZvoteMaxZ0 = 512;    // z0 bins (LDS: 4 waves x 16 rows x 4 bytes per bin)
 
 struct CordicTable {
     int32_t t[kCordicSteps];
@@ -67,6 +76,16 @@ struct Events {
     int32_t n_single;
     int32_t max_hits;        // events with more hits are not processed (flagged)
     size_t ws_stride;        // bytes between the workspaces of consecutive events
+};
+
+// Second-stage r-z grid in the kernels' integer units.  Row m has the Q16.16 cot(theta) centre
+// c0 + m * dc (the plan checks that the centres form this exact progression); z0 bins have the
+// width 2^shift in Q32.32 cm starting at z0min, so a z0 value v (Q32.32) falls into bin
+// (v - z0min) >> shift when 0 <= v - z0min < lim = n_z0 << shift.
+struct ZGrid {
+    int32_t n_cot, n_z0, shift;
+    int64_t z0min, c0, dc;
+    uint64_t lim;
 };
 
 }  // namespace
@@ -89,6 +108,9 @@ struct hough_plan {
     LayerTable layers;
     hough_tuning_t tuning;
     int32_t* d_E;    // [n_layers][n_d0][n_qpt], INT32_MIN = invalid
+    bool zvote;      // second-stage grid present
+    ZGrid zg;
+    int32_t* d_S;    // [n_layers][n_d0][n_qpt] Q16.16 arc length to the layer, -1 = invalid (zvote only)
 };
 
 namespace {
@@ -873,6 +895,136 @@ __global__ __launch_bounds__(kAssignThreads) void k_assign_fill(
     }
 }
 
+// ------------------------------------------------------------------ zvote
+// Per candidate p (one wave; grid.y = event): every hit h of its list with a usable z votes, for
+// each cot(theta) row m, into z0 bin j(m) = (Z_h * 2^16 - S_h * C_m - z0min) >> shift, where S_h is
+// the arc length from the origin to the hit's layer for the candidate's (d0, q/pT) centre; the
+// output is the (m, j) with the most votes, lowest m * n_z0 + j on ties.
+//
+// Each LDS word of a row histogram holds (count << 16) | (0xFFFF - j).  Adding 1 << 16 returns the
+// old word, so old + 2^16 - m * n_z0 = (count << 16) | (0xFFFF - (m * n_z0 + j)) is a key whose
+// maximum over all votes is the argmax with the lowest linear index (a bin's last vote returns its
+// final count; counts < 2^16 and n_cot * n_z0 <= 2^16 are plan limits).  The voter then writes
+// the word back to (0xFFFF - j): the atomics of one instruction complete before the next LDS
+// instruction of the wave, so the row is clean for the next row voted in that slot.  Candidates
+// with more than 64 hits vote one row at a time in chunks of 64 hits and restore the row after
+// its last chunk.
+__device__ __forceinline__ void zvote_hit(int32_t h, const float* __restrict__ hz, const uint8_t* __restrict__ hl,
+                                          int h0, const int32_t* __restrict__ Sc, int n_layers, size_t s_layer,
+                                          const ZGrid& zg, bool& ok, int64_t& A, int64_t& B) {
+    const float zf = hz[h0 + h];
+    const int L = hl[h0 + h];
+    ok = isfinite(zf) && fabsf(zf) < 32768.0f && L < n_layers;
+    int32_t S = ok ? Sc[(size_t)L * s_layer] : -1;
+    ok = ok && S >= 0;
+    const int32_t Z = ok ? __float2int_rn(zf * 65536.0f) : 0;
+    S = ok ? S : 0;
+    A = (int64_t)Z * 65536 - zg.z0min - (int64_t)S * zg.c0;
+    B = (int64_t)S * zg.dc;
+}
+
+__global__ __launch_bounds__(kZvoteThreads) void k_zvote(
+    Events ev, const float* __restrict__ hz, const uint8_t* __restrict__ hl, int n_layers,
+    const hough_peak_t* __restrict__ peaks_base, int32_t cap_peaks, const int32_t* __restrict__ offsets_base,
+    const int32_t* __restrict__ hit_idx_base, int32_t cap_pairs, const hough_status_t* __restrict__ st_base,
+    const int32_t* __restrict__ S, int n_d0, int n_qpt, ZGrid zg, int32_t* __restrict__ out_base) {
+    extern __shared__ uint32_t zs_u32[];
+    const int e = blockIdx.y;
+    int h0, nh;
+    event_hits(ev, e, h0, nh);
+    const hough_peak_t* peaks = peaks_base + (size_t)e * cap_peaks;
+    const int32_t* offsets = offsets_base + (size_t)e * ((size_t)cap_peaks + 1);
+    const int32_t* hit_idx = hit_idx_base + (size_t)e * cap_pairs;
+    int32_t* out = out_base + (size_t)e * 3 * cap_peaks;
+    const int n = min(st_base[e].n_peaks, cap_peaks);
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int nz = zg.n_z0;
+    const size_t s_layer = (size_t)n_d0 * n_qpt;
+    uint32_t* region = zs_u32 + (size_t)wave * kZvoteSlots * nz;
+    for (int i = lane; i < kZvoteSlots * nz; i += 64) region[i] = 0xFFFFu - (uint32_t)(i % nz);
+    const int waves = kZvoteThreads / 64;
+    for (int p = blockIdx.x * waves + wave; p < n; p += gridDim.x * waves) {
+        // wave-uniform candidate data
+        const int32_t pl = __builtin_amdgcn_readfirstlane(peaks[p].l);
+        const int32_t pkk = __builtin_amdgcn_readfirstlane(peaks[p].k);
+        const int32_t o0 = __builtin_amdgcn_readfirstlane(offsets[p]);
+        const int32_t o1 = __builtin_amdgcn_readfirstlane(offsets[p + 1]);
+        int32_t* o = out + 3 * (size_t)p;
+        if (o1 > cap_pairs) {  // hit list cut by the pair capacity: no result
+            if (lane == 0) {
+                o[0] = -1;
+                o[1] = -1;
+                o[2] = -1;
+            }
+            continue;
+        }
+        const int H = o1 - o0;
+        const int32_t* Sc = S + (size_t)pl * n_qpt + pkk;
+        uint32_t best = 0;
+        if (H >= 1 && H <= 64) {
+            const int R = min(kZvoteSlots, 64 / H);
+            const int slot = lane / H;
+            bool ok = false;
+            int64_t A = 0, B = 0;
+            if (slot < R) zvote_hit(hit_idx[o0 + lane - slot * H], hz, hl, h0, Sc, n_layers, s_layer, zg, ok, A, B);
+            uint32_t* row = region + slot * nz;
+            int64_t z0 = A - (int64_t)slot * B;
+            const int64_t step = (int64_t)R * B;
+            uint32_t kc = 0x10000u - (uint32_t)(slot * nz);
+            const uint32_t kstep = (uint32_t)(R * nz);
+            const int iters = (zg.n_cot + R - 1) / R;
+            int m = slot;
+            for (int it = 0; it < iters; ++it) {
+                if (ok && m < zg.n_cot && (uint64_t)z0 < zg.lim) {
+                    const uint32_t j = (uint32_t)((uint64_t)z0 >> zg.shift);
+                    const uint32_t old =
+                        __hip_atomic_fetch_add(row + j, 0x10000u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                    best = max(best, old + kc);
+                    row[j] = 0xFFFFu - j;
+                }
+                asm volatile("" ::: "memory");
+                z0 -= step;
+                m += R;
+                kc -= kstep;
+            }
+        } else if (H > 64) {
+            for (int m = 0; m < zg.n_cot; ++m) {
+                const uint32_t kc = 0x10000u - (uint32_t)(m * nz);
+                for (int c = 0; c < H; c += 64) {
+                    bool ok = false;
+                    int64_t A = 0, B = 0;
+                    if (c + lane < H) zvote_hit(hit_idx[o0 + c + lane], hz, hl, h0, Sc, n_layers, s_layer, zg, ok, A, B);
+                    const int64_t z0 = A - (int64_t)m * B;
+                    if (ok && (uint64_t)z0 < zg.lim) {
+                        const uint32_t j = (uint32_t)((uint64_t)z0 >> zg.shift);
+                        const uint32_t old =
+                            __hip_atomic_fetch_add(region + j, 0x10000u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                        best = max(best, old + kc);
+                    }
+                    asm volatile("" ::: "memory");
+                }
+                for (int j = lane; j < nz; j += 64) region[j] = 0xFFFFu - (uint32_t)j;
+                asm volatile("" ::: "memory");
+            }
+        }
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1) best = max(best, (uint32_t)__shfl_xor((int)best, d, 64));
+        if (lane == 0) {
+            if (best == 0) {
+                o[0] = -1;
+                o[1] = -1;
+                o[2] = 0;
+            } else {
+                const uint32_t lin = 0xFFFFu - (best & 0xFFFFu);
+                o[0] = (int32_t)(lin / (uint32_t)nz);
+                o[1] = (int32_t)(lin % (uint32_t)nz);
+                o[2] = (int32_t)(best >> 16);
+            }
+        }
+    }
+}
+
 // ------------------------------------------------------------------ host helpers
 int ilog2_exact(int v) {
     if (v <= 0 || (v & (v - 1))) return -1;
@@ -954,6 +1106,19 @@ void launch_assign(const hough_plan* p, const Events& ev, int n_events, const ho
                        offsets, hit_idx, cap_pairs, buf_words);
 }
 
+void launch_zvote(const hough_plan* p, const Events& ev, int n_events, const float* z, const uint8_t* layer,
+                  const hough_peak_t* peaks, int32_t cap_peaks, const int32_t* offsets, const int32_t* hit_idx,
+                  int32_t cap_pairs, const hough_status_t* st, int32_t* out, hipStream_t stream) {
+    // enough waves to fill the chip (5 workgroups of 4 waves per CU at 128 z0 bins), split over the events
+    const int64_t want = ((int64_t)cap_peaks + 3) / 4;
+    int64_t per_event = (2560 + n_events - 1) / n_events;
+    per_event = per_event < want ? per_event : want;
+    const unsigned nblk = (unsigned)(per_event > 0 ? per_event : 1);
+    const size_t lds = (size_t)(kZvoteThreads / 64) * kZvoteSlots * p->zg.n_z0 * 4;
+    hipLaunchKernelGGL(k_zvote, dim3(nblk, n_events), dim3(kZvoteThreads), lds, stream, ev, z, layer, p->n_layers,
+                       peaks, cap_peaks, offsets, hit_idx, cap_pairs, st, p->d_S, p->g.n_d0, p->g.n_qpt, p->zg, out);
+}
+
 int check_hits(const hough_plan* p, const hough_hits_t* hits) {
     if (!p || !hits) return HOUGH_E_INVAL;
     if (hits->n < 0 || hits->n > p->g.max_hits_per_event) return HOUGH_E_INVAL;
@@ -1006,6 +1171,37 @@ int hough_plan_create(const hough_geometry_t* geom, const hough_grid_t* grid, ho
     if (!(g.qpt_max >= g.qpt_min) || !(g.d0_max >= g.d0_min)) return HOUGH_E_INVAL;
     if ((int64_t)g.n_d0 * g.n_qpt * g.n_phi > ((int64_t)1 << 31)) return HOUGH_E_UNSUPPORTED;
     if ((geom->n_layers << (lp < 10 ? lp : 10)) > kMaxCells) return HOUGH_E_UNSUPPORTED;
+    // second-stage r-z grid: cot(theta) centres on an exact Q16.16 progression, z0 bins of a
+    // power-of-two width in Q32.32 (the integer forms the zvote kernel steps through)
+    const bool zvote = g.n_cot != 0 || g.n_z0 != 0;
+    ZGrid zg{};
+    if (zvote) {
+        if (g.n_cot < 1 || g.n_z0 < 1) return HOUGH_E_INVAL;
+        if (g.n_z0 > kZvoteMaxZ0 || (int64_t)g.n_cot * g.n_z0 > 65536) return HOUGH_E_UNSUPPORTED;
+        if (g.max_hits_per_event > 65535) return HOUGH_E_UNSUPPORTED;
+        if (!std::isfinite(g.cot_min) || !std::isfinite(g.cot_max) || !(g.cot_max > g.cot_min) ||
+            !std::isfinite(g.z0_min) || !std::isfinite(g.z0_max) || !(g.z0_max > g.z0_min))
+            return HOUGH_E_INVAL;
+        if (fabs(g.cot_min) > 1024.0 || fabs(g.cot_max) > 1024.0 || fabs(g.z0_min) > 32768.0 ||
+            fabs(g.z0_max) > 32768.0)
+            return HOUGH_E_UNSUPPORTED;
+        const int64_t W = llrint(((g.z0_max - g.z0_min) / (double)g.n_z0) * 4294967296.0);
+        if (W < 1 || (W & (W - 1))) return HOUGH_E_UNSUPPORTED;
+        int shift = 0;
+        while (((int64_t)1 << shift) < W) ++shift;
+        zg.n_cot = g.n_cot;
+        zg.n_z0 = g.n_z0;
+        zg.shift = shift;
+        zg.z0min = llrint(g.z0_min * 4294967296.0);
+        zg.lim = (uint64_t)g.n_z0 << shift;
+        const double cstep = (g.cot_max - g.cot_min) / (double)g.n_cot;
+        for (int m = 0; m < g.n_cot; ++m) {
+            const int64_t C = llrint((g.cot_min + ((double)m + 0.5) * cstep) * 65536.0);
+            if (m == 0) zg.c0 = C;
+            if (m == 1) zg.dc = C - zg.c0;
+            if (C != zg.c0 + (int64_t)m * zg.dc) return HOUGH_E_UNSUPPORTED;
+        }
+    }
 
     hough_plan* p = new (std::nothrow) hough_plan();
     if (!p) return HOUGH_E_NOMEM;
@@ -1020,6 +1216,8 @@ int hough_plan_create(const hough_geometry_t* geom, const hough_grid_t* grid, ho
     }
     p->B = geom->B_tesla;
     p->g = g;
+    p->zvote = zvote;
+    p->zg = zg;
     p->log2_phi = lp;
     p->F = g.frac_bits;
     p->M = lp + g.frac_bits;
@@ -1041,6 +1239,16 @@ int hough_plan_create(const hough_geometry_t* geom, const hough_grid_t* grid, ho
         delete p;
         return HOUGH_E_NOMEM;
     }
+    int32_t* Stab = nullptr;
+    if (zvote) {
+        Stab = (int32_t*)malloc(ntab * sizeof(int32_t));
+        if (!Stab) {
+            free(E);
+            delete p;
+            return HOUGH_E_NOMEM;
+        }
+    }
+    bool s_range_ok = true;
     const double kappa = 0.299792458e-2 * p->B;
     const double K = ldexp(1.0, p->M - 1) / M_PI;
     for (int L = 0; L < p->n_layers; ++L) {
@@ -1053,28 +1261,63 @@ int hough_plan_create(const hough_geometry_t* geom, const hough_grid_t* grid, ho
                 const double c = -kappa * q;
                 const double num = c * (r * r + d * d) + 2.0 * d;
                 const double den = 2.0 * r * (1.0 + c * d);
-                int32_t v = INT32_MIN;
+                int32_t v = INT32_MIN, sv = -1;
                 if (den > 0.0) {
                     const double A = num / den;
                     if (fabs(A) <= 1.0) {
                         v = (int32_t)llrint(asin(A) * K);
                         ++nvalid;
+                        if (Stab) {
+                            // arc length in the transverse plane from the origin to the layer crossing:
+                            // chord length, then the arc of curvature c over it
+                            const double Lc2 = r * r + d * d - 2.0 * d * r * A;
+                            const double Lc = sqrt(Lc2 > 0.0 ? Lc2 : 0.0);
+                            double sl;
+                            if (c == 0.0) {
+                                sl = Lc;
+                            } else {
+                                double u = fabs(c) * Lc / 2.0;
+                                if (u > 1.0) u = 1.0;
+                                sl = (2.0 / fabs(c)) * asin(u);
+                            }
+                            const long long S = llrint(sl * 65536.0);
+                            if (S > INT32_MAX) s_range_ok = false;
+                            sv = (int32_t)(S > INT32_MAX ? INT32_MAX : S);
+                        }
                     }
                 }
                 E[((size_t)L * g.n_d0 + l) * g.n_qpt + k] = v;
+                if (Stab) Stab[((size_t)L * g.n_d0 + l) * g.n_qpt + k] = sv;
             }
         }
         p->layers.valid_cols[L] = nvalid;
     }
+    if (!s_range_ok) {
+        free(E);
+        free(Stab);
+        delete p;
+        return HOUGH_E_UNSUPPORTED;
+    }
     if (hipMalloc(&p->d_E, ntab * sizeof(int32_t)) != hipSuccess) {
         free(E);
+        free(Stab);
         delete p;
         return HOUGH_E_NOMEM;
     }
-    const hipError_t ce = hipMemcpy(p->d_E, E, ntab * sizeof(int32_t), hipMemcpyHostToDevice);
+    if (Stab && hipMalloc(&p->d_S, ntab * sizeof(int32_t)) != hipSuccess) {
+        (void)hipFree(p->d_E);
+        free(E);
+        free(Stab);
+        delete p;
+        return HOUGH_E_NOMEM;
+    }
+    hipError_t ce = hipMemcpy(p->d_E, E, ntab * sizeof(int32_t), hipMemcpyHostToDevice);
+    if (ce == hipSuccess && Stab) ce = hipMemcpy(p->d_S, Stab, ntab * sizeof(int32_t), hipMemcpyHostToDevice);
     free(E);
+    free(Stab);
     if (ce != hipSuccess) {
         (void)hipFree(p->d_E);
+        if (p->d_S) (void)hipFree(p->d_S);
         delete p;
         return HOUGH_E_HIP;
     }
@@ -1084,8 +1327,11 @@ int hough_plan_create(const hough_geometry_t* geom, const hough_grid_t* grid, ho
         ae = hipFuncSetAttribute((const void*)k_vote<true>, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
     if (ae == hipSuccess)
         ae = hipFuncSetAttribute((const void*)k_assign_fill, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
+    if (ae == hipSuccess)
+        ae = hipFuncSetAttribute((const void*)k_zvote, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
     if (ae != hipSuccess) {
         (void)hipFree(p->d_E);
+        if (p->d_S) (void)hipFree(p->d_S);
         delete p;
         return HOUGH_E_HIP;
     }
@@ -1096,6 +1342,7 @@ int hough_plan_create(const hough_geometry_t* geom, const hough_grid_t* grid, ho
 void hough_plan_destroy(hough_plan_t* plan) {
     if (!plan) return;
     if (plan->d_E) (void)hipFree(plan->d_E);
+    if (plan->d_S) (void)hipFree(plan->d_S);
     delete plan;
 }
 
@@ -1125,6 +1372,14 @@ int hough_plan_table(const hough_plan_t* p, int32_t* out) {
     if (!p || !out) return HOUGH_E_INVAL;
     const size_t n = (size_t)p->n_layers * p->n_cols;
     return hipMemcpy(out, p->d_E, n * sizeof(int32_t), hipMemcpyDeviceToHost) == hipSuccess ? HOUGH_OK
+                                                                                             : HOUGH_E_HIP;
+}
+
+int hough_plan_arclen_table(const hough_plan_t* p, int32_t* out) {
+    if (!p || !out) return HOUGH_E_INVAL;
+    if (!p->zvote) return HOUGH_E_UNSUPPORTED;
+    const size_t n = (size_t)p->n_layers * p->n_cols;
+    return hipMemcpy(out, p->d_S, n * sizeof(int32_t), hipMemcpyDeviceToHost) == hipSuccess ? HOUGH_OK
                                                                                              : HOUGH_E_HIP;
 }
 
@@ -1179,6 +1434,19 @@ int hough_assign(const hough_plan_t* p, const hough_peak_t* peaks, int32_t cap_p
     return launch_status();
 }
 
+int hough_zvote(const hough_plan_t* p, const hough_hits_t* hits, const hough_peak_t* peaks, int32_t cap_peaks,
+                const int32_t* offsets, const int32_t* hit_idx, int32_t cap_pairs, const hough_status_t* st,
+                int32_t* out, hipStream_t stream) {
+    if (!p || !hits || !peaks || !offsets || !hit_idx || !st || !out || cap_peaks < 1 || cap_pairs < 1)
+        return HOUGH_E_INVAL;
+    if (!p->zvote) return HOUGH_E_UNSUPPORTED;
+    if (hits->n < 0 || hits->n > p->g.max_hits_per_event) return HOUGH_E_INVAL;
+    if (hits->n > 0 && (!hits->z || !hits->layer)) return HOUGH_E_INVAL;
+    launch_zvote(p, single_event(p, hits->n), 1, hits->z, hits->layer, peaks, cap_peaks, offsets, hit_idx, cap_pairs,
+                 st, out, stream);
+    return launch_status();
+}
+
 // ---------------------------------------------------------------------- batches
 size_t hough_batch_ws_bytes(const hough_plan_t* p, int32_t n_events, int32_t cap_peaks) {
     if (!p || n_events < 1) return 0;
@@ -1191,6 +1459,7 @@ int hough_run_batch(const hough_plan_t* p, const hough_batch_t* b, hipStream_t s
     if (!b->hit_offsets || !b->x || !b->y || !b->layer || !b->acc || !b->peaks || !b->offsets || !b->hit_idx ||
         !b->ws || !b->status)
         return HOUGH_E_INVAL;
+    if (b->zvote && (!p->zvote || !b->z)) return p->zvote ? HOUGH_E_INVAL : HOUGH_E_UNSUPPORTED;
     const WsLayout L = ws_layout(p, b->cap_peaks);
     const size_t hdr = batch_header_bytes(b->n_events);
     if (b->ws_bytes < hdr + (size_t)b->n_events * L.total) return HOUGH_E_SMALL_WS;
@@ -1212,6 +1481,9 @@ int hough_run_batch(const hough_plan_t* p, const hough_batch_t* b, hipStream_t s
                  b->status, stream);
     launch_assign(p, ev, b->n_events, b->peaks, b->cap_peaks, b->cap_peaks, b->offsets, b->hit_idx, b->cap_pairs,
                   ev_ws, O, b->status, stream);
+    if (b->zvote)
+        launch_zvote(p, ev, b->n_events, b->z, b->layer, b->peaks, b->cap_peaks, b->offsets, b->hit_idx,
+                     b->cap_pairs, b->status, b->zvote, stream);
     return launch_status();
 }
 

@@ -51,7 +51,7 @@ class Batch(C.Structure):
                 ("hit_offsets", C.c_void_p), ("n_events", C.c_int32), ("threshold", C.c_int32),
                 ("cap_peaks", C.c_int32), ("cap_pairs", C.c_int32), ("acc", C.c_void_p), ("peaks", C.c_void_p),
                 ("offsets", C.c_void_p), ("hit_idx", C.c_void_p), ("ws", C.c_void_p), ("ws_bytes", C.c_size_t),
-                ("status", C.c_void_p)]
+                ("status", C.c_void_p), ("zvote", C.c_void_p)]
 
 
 STATUS_BYTES = 32
@@ -78,6 +78,9 @@ def _load() -> C.CDLL:
     L.hough_peaks.argtypes = [P, P, C.c_int32, P, C.c_int32, P, S, P, P]
     L.hough_assign.restype = C.c_int
     L.hough_assign.argtypes = [P, P, C.c_int32, P, P, C.c_int32, P, S, P, P]
+    L.hough_zvote.restype = C.c_int
+    L.hough_zvote.argtypes = [P, C.POINTER(Hits), P, C.c_int32, P, P, C.c_int32, P, P, P]
+    L.hough_plan_arclen_table.restype = C.c_int; L.hough_plan_arclen_table.argtypes = [P, P]
     L.hough_strerror.restype = C.c_char_p; L.hough_strerror.argtypes = [C.c_int]
     L.hough_plan_set_tuning.restype = C.c_int; L.hough_plan_set_tuning.argtypes = [P, C.POINTER(Tuning)]
     L.hough_plan_get_tuning.restype = C.c_int; L.hough_plan_get_tuning.argtypes = [P, C.POINTER(Tuning)]
@@ -94,7 +97,7 @@ lib = _load()
 
 EXPORTED = ["hough_plan_create", "hough_plan_destroy", "hough_acc_bytes", "hough_event_ws_bytes",
             "hough_angle_bits", "hough_plan_table", "hough_prep", "hough_vote", "hough_vote_prepared", "hough_peaks",
-            "hough_assign", "hough_strerror", "hough_plan_set_tuning", "hough_plan_get_tuning",
+            "hough_assign", "hough_zvote", "hough_plan_arclen_table", "hough_strerror", "hough_plan_set_tuning", "hough_plan_get_tuning",
             "hough_batch_ws_bytes", "hough_run_batch", "hough_batch_graph_create", "hough_graph_launch",
             "hough_graph_destroy"]
 
@@ -180,6 +183,16 @@ class Plan:
         _check(lib.hough_plan_table(self.handle, out.ctypes.data), "hough_plan_table")
         return out
 
+    @property
+    def has_zvote(self) -> bool:
+        return self.cfg.n_cot > 0
+
+    def arclen_table(self) -> np.ndarray:
+        c = self.cfg
+        out = np.zeros((c.n_layers, c.n_d0, c.n_qpt), dtype=np.int32)
+        _check(lib.hough_plan_arclen_table(self.handle, out.ctypes.data), "hough_plan_arclen_table")
+        return out
+
 
 def make_hits(x: torch.Tensor, y: torch.Tensor, layer: torch.Tensor, z: Optional[torch.Tensor] = None) -> Hits:
     n = int(x.shape[0])
@@ -226,6 +239,15 @@ def assign(plan: Plan, pk: torch.Tensor, offsets: torch.Tensor, hit_idx: torch.T
            "hough_assign")
 
 
+def zvote(plan: Plan, hits: Hits, pk: torch.Tensor, offsets: torch.Tensor, hit_idx: torch.Tensor,
+          status: torch.Tensor, out: torch.Tensor, stream=None) -> None:
+    cap_peaks = pk.shape[0]
+    if offsets.numel() < cap_peaks + 1 or out.numel() < 3 * cap_peaks:
+        raise HoughError("offsets needs cap_peaks + 1 entries and out 3 * cap_peaks")
+    _check(lib.hough_zvote(plan.handle, C.byref(hits), _ptr(pk), int(cap_peaks), _ptr(offsets), _ptr(hit_idx),
+                           int(hit_idx.numel()), _ptr(status), _ptr(out), _stream(stream)), "hough_zvote")
+
+
 def status_dict(status: torch.Tensor) -> dict:
     b = status.detach().to("cpu").numpy().view(np.uint8)[:STATUS_BYTES].tobytes()
     n_hits, n_bad = np.frombuffer(b[0:8], dtype=np.int32)
@@ -249,12 +271,15 @@ class EventBuffers:
         self.peaks = torch.empty((cap_peaks, PEAK_INTS), dtype=torch.int32, device=device)
         self.offsets = torch.empty(cap_peaks + 1, dtype=torch.int32, device=device)
         self.hit_idx = torch.empty(cap_pairs, dtype=torch.int32, device=device)
+        self.zv = torch.empty((cap_peaks, 3), dtype=torch.int32, device=device) if plan.has_zvote else None
 
     def run(self, hits: Hits, threshold: int, stream=None, do_assign: bool = True) -> None:
         vote(self.plan, hits, self.acc, self.ws, self.status, stream)
         peaks(self.plan, self.acc, threshold, self.peaks, self.ws, self.status, stream)
         if do_assign:
             assign(self.plan, self.peaks, self.offsets, self.hit_idx, self.ws, self.status, stream)
+            if self.zv is not None and hits.z:
+                zvote(self.plan, hits, self.peaks, self.offsets, self.hit_idx, self.status, self.zv, stream)
 
     def results(self) -> dict:
         st = status_dict(self.status)
@@ -263,7 +288,10 @@ class EventBuffers:
         offs = self.offsets[: n + 1].cpu().numpy().astype(np.int64)
         npairs = min(st["n_pairs"], self.hit_idx.numel())
         hit_idx = self.hit_idx[:npairs].cpu().numpy()
-        return dict(status=st, peaks=pk, offsets=offs, hit_idx=hit_idx)
+        out = dict(status=st, peaks=pk, offsets=offs, hit_idx=hit_idx)
+        if self.zv is not None:
+            out["zvote"] = self.zv[:n].cpu().numpy()
+        return out
 
 
 def hits_to_device(ev, device="cuda"):
@@ -285,6 +313,7 @@ class BatchBuffers:
         self.cap_peaks, self.cap_pairs = int(cap_peaks), int(cap_pairs)
         self.x = torch.zeros(max(max_total_hits, 1), dtype=torch.float32, device=device)
         self.y = torch.zeros_like(self.x)
+        self.z = torch.zeros_like(self.x) if plan.has_zvote else None
         self.layer = torch.zeros(max(max_total_hits, 1), dtype=torch.uint8, device=device)
         self.hit_offsets = torch.zeros(self.n_events + 1, dtype=torch.int32, device=device)
         self.acc = torch.empty((self.n_events, c.n_d0, c.n_qpt, c.n_phi), dtype=plan.acc_dtype, device=device)
@@ -293,6 +322,8 @@ class BatchBuffers:
         self.hit_idx = torch.empty((self.n_events, cap_pairs), dtype=torch.int32, device=device)
         self.ws = torch.empty(plan.batch_ws_bytes(self.n_events, cap_peaks), dtype=torch.uint8, device=device)
         self.status = torch.zeros((self.n_events, STATUS_BYTES // 4), dtype=torch.int32, device=device)
+        self.zv = (torch.empty((self.n_events, cap_peaks, 3), dtype=torch.int32, device=device)
+                   if plan.has_zvote else None)
 
     def load(self, events, stream=None) -> None:
         """Copy the packed hits of `events` (at most n_events) into the device buffers."""
@@ -305,15 +336,21 @@ class BatchBuffers:
             self.x[:n].copy_(torch.from_numpy(np.concatenate([e.x for e in events])), non_blocking=False)
             self.y[:n].copy_(torch.from_numpy(np.concatenate([e.y for e in events])), non_blocking=False)
             self.layer[:n].copy_(torch.from_numpy(np.concatenate([e.layer for e in events])), non_blocking=False)
+            if self.z is not None:
+                self.z[:n].copy_(torch.from_numpy(np.concatenate([e.z for e in events]).astype(np.float32)))
         self.hit_offsets.copy_(torch.from_numpy(offs))
 
-    def struct(self, threshold: int) -> Batch:
-        return Batch(_ptr(self.x), _ptr(self.y), None, _ptr(self.layer), _ptr(self.hit_offsets), self.n_events,
+    def struct(self, threshold: int, n_events: Optional[int] = None, zvote: bool = True) -> Batch:
+        n_events = self.n_events if n_events is None else int(n_events)
+        if not 1 <= n_events <= self.n_events:
+            raise HoughError("n_events out of range")
+        return Batch(_ptr(self.x), _ptr(self.y), _ptr(self.z), _ptr(self.layer), _ptr(self.hit_offsets), n_events,
                      int(threshold), self.cap_peaks, self.cap_pairs, _ptr(self.acc), _ptr(self.peaks),
-                     _ptr(self.offsets), _ptr(self.hit_idx), _ptr(self.ws), self.ws.numel(), _ptr(self.status))
+                     _ptr(self.offsets), _ptr(self.hit_idx), _ptr(self.ws), self.ws.numel(), _ptr(self.status),
+                     _ptr(self.zv) if zvote else None)
 
-    def run(self, threshold: int, stream=None) -> None:
-        b = self.struct(threshold)
+    def run(self, threshold: int, stream=None, n_events: Optional[int] = None, zvote: bool = True) -> None:
+        b = self.struct(threshold, n_events, zvote)
         _check(lib.hough_run_batch(self.plan.handle, C.byref(b), _stream(stream)), "hough_run_batch")
 
     def results(self, e: int) -> dict:
@@ -322,7 +359,10 @@ class BatchBuffers:
         pk = self.peaks[e, :n].cpu().numpy()
         offs = self.offsets[e, : n + 1].cpu().numpy().astype(np.int64)
         npairs = min(st["n_pairs"], self.cap_pairs)
-        return dict(status=st, peaks=pk, offsets=offs, hit_idx=self.hit_idx[e, :npairs].cpu().numpy())
+        out = dict(status=st, peaks=pk, offsets=offs, hit_idx=self.hit_idx[e, :npairs].cpu().numpy())
+        if self.zv is not None:
+            out["zvote"] = self.zv[e, :n].cpu().numpy()
+        return out
 
 
 class Graph:
