@@ -121,7 +121,7 @@ typedef struct hough_plan hough_plan_t;
 typedef struct {
     int32_t vote_threads;      /* threads per vote workgroup: 256, 512 or 1024            */
     int32_t vote_grid;         /* persistent vote workgroups of a batch (0 = 256)          */
-    int32_t peak_planes;       /* d0 planes walked by one peak-finder thread (1..64)       */
+    int32_t peak_planes;       /* d0 planes walked by one peak-finder thread (1..16)       */
 } hough_tuning_t;
 
 /* Create a plan on the current HIP device: validates geometry and grid and
@@ -132,6 +132,13 @@ void hough_plan_destroy(hough_plan_t* plan);
 
 int hough_plan_set_tuning(hough_plan_t* plan, const hough_tuning_t* t);
 int hough_plan_get_tuning(const hough_plan_t* plan, hough_tuning_t* t);
+
+/* Kernel timing: while set, every vote kernel launched with this plan (single
+ * event or batch) records `start` and `stop` (events created by the caller,
+ * timing enabled, may be NULL) with the kernel's own start and end, so their
+ * elapsed time is the kernel's duration without launch gaps.  Not for plans
+ * used by several threads at once.  NULL, NULL switches it off (default). */
+int hough_plan_set_vote_events(hough_plan_t* plan, hipEvent_t start, hipEvent_t stop);
 
 /* Sizes in bytes. */
 size_t hough_acc_bytes(const hough_plan_t* plan);             /* n_d0*n_qpt*n_phi*acc_bits/8 */

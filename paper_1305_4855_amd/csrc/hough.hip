@@ -35,6 +35,7 @@
 //           carry their own tie-break key, so the argmax is tracked from the
 //           atomic's return value and each touched word is restored right
 //           after the vote (no clearing pass, no scan of the grid).
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <climits>
@@ -56,11 +57,11 @@ constexpr int kStrip = 8;           // phi0 bins per peak-finder thread
 constexpr int kScanThreads = 1024;
 constexpr int kMaxCells = 32768;    // LDS histogram of the prep bucketing (128 KiB)
 constexpr int kAssignThreads = 1024;
-constexpr int kAssignBufMax = 2048; // words of CSR list buffered per wave (less if the cell table is large)
+constexpr int kAssignBufMax = 512;  // words of CSR list buffered per wave (less if the cell table is large)
 constexpr int kLdsBytes = 160 * 1024;
 constexpr int kZvoteThreads = 256;
-constexpr int kZvoteSlots = 16;     // rows of the r-z grid one wave votes at once
-constexpr int kZvoteMaxZ0 = 512;    // z0 bins (LDS: 4 waves x 16 rows x 4 bytes per bin)
+constexpr int kZvoteSlots = 8;      // rows of the r-z grid one wave votes at once
+constexpr int kZvoteMaxZ0 = 512;    // z0 bins (LDS: 4 waves x 8 rows x 4 bytes per bin + staging)
 
 struct CordicTable {
     int32_t t[kCordicSteps];
@@ -111,6 +112,7 @@ struct hough_plan {
     bool zvote;      // second-stage grid present
     ZGrid zg;
     int32_t* d_S;    // [n_layers][n_d0][n_qpt] Q16.16 arc length to the layer, -1 = invalid (zvote only)
+    hipEvent_t vote_start, vote_stop;  // recorded by every vote launch when set (kernel timing)
 };
 
 namespace {
@@ -295,7 +297,7 @@ __global__ __launch_bounds__(256) void k_prep_hits(Events ev, const float* __res
 //   3. scatter into cell order (LDS cursors; arbitrary order inside a cell) -> tmp_phi, tmp_key,
 //      tmp_key = (layer << 24) | hit index.
 // An event with more than max_hits hits is treated as empty and flagged.
-constexpr int kBucketUnroll = 8;
+constexpr int kBucketUnroll = 16;  // hits per thread and pass: events up to 16384 hits stay in registers
 __global__ __launch_bounds__(kScanThreads) void k_prep_bucket(Events ev, int n_layers, int cell_bits, int M,
                                                               LayerTable LT, char* __restrict__ ws, WsOff O,
                                                               hough_status_t* __restrict__ st_base) {
@@ -317,18 +319,23 @@ __global__ __launch_bounds__(kScanThreads) void k_prep_bucket(Events ev, int n_l
     const int tid = threadIdx.x;
     const int n_cells = n_layers << cell_bits;
     const int cshift = 32 - cell_bits;
+    const bool resident = n <= kScanThreads * kBucketUnroll;  // one pass holds every hit
     for (int i = tid; i < n_cells; i += kScanThreads) cur[i] = 0;
-    __syncthreads();
-    int32_t bad = 0;
-    for (int base = 0; base < n; base += kScanThreads * kBucketUnroll) {
-        uint8_t L[kBucketUnroll];
-        uint32_t ph[kBucketUnroll];
+    uint8_t L[kBucketUnroll];
+    uint32_t ph[kBucketUnroll];
+    auto load = [&](int base) {
 #pragma unroll
         for (int j = 0; j < kBucketUnroll; ++j) {
             const int h = base + j * kScanThreads + tid;
-            L[j] = h < n ? lay[h] : (uint8_t)0xFE;
+            L[j] = h < n ? lay[h] : (uint8_t)0xFE;  // 0xFE: no hit, 0xFF: bad hit
             ph[j] = h < n ? phi32[h] : 0u;
         }
+    };
+    if (resident) load(0);
+    __syncthreads();
+    int32_t bad = 0;
+    for (int base = 0; base < n; base += kScanThreads * kBucketUnroll) {
+        if (!resident) load(base);
 #pragma unroll
         for (int j = 0; j < kBucketUnroll; ++j) {
             if (L[j] == 0xFF) ++bad;
@@ -361,7 +368,7 @@ __global__ __launch_bounds__(kScanThreads) void k_prep_bucket(Events ev, int n_l
     __syncthreads();
     if (tid == 0) {
         int64_t votes = 0;
-        for (int L = 0; L < n_layers; ++L) votes += (int64_t)layer_n[L] * LT.valid_cols[L];
+        for (int Ly = 0; Ly < n_layers; ++Ly) votes += (int64_t)layer_n[Ly] * LT.valid_cols[Ly];
         st->n_hits = n_given;
         st->n_bad_hits = (int32_t)bad_tot;
         st->n_votes = votes;
@@ -369,18 +376,12 @@ __global__ __launch_bounds__(kScanThreads) void k_prep_bucket(Events ev, int n_l
         st->flags = n_given > ev.max_hits ? HOUGH_F_EVENT_TOO_LARGE : 0;
         st->n_pairs = 0;
     }
+    // scatter into cell order
     for (int base = 0; base < n; base += kScanThreads * kBucketUnroll) {
-        uint8_t L[kBucketUnroll];
-        uint32_t ph[kBucketUnroll];
+        if (!resident) load(base);
 #pragma unroll
         for (int j = 0; j < kBucketUnroll; ++j) {
-            const int h = base + j * kScanThreads + tid;
-            L[j] = h < n ? lay[h] : (uint8_t)0xFF;
-            ph[j] = h < n ? phi32[h] : 0u;
-        }
-#pragma unroll
-        for (int j = 0; j < kBucketUnroll; ++j) {
-            if (L[j] == 0xFF) continue;
+            if (L[j] >= 0xFE) continue;
             const int h = base + j * kScanThreads + tid;
             const int pos = atomicAdd(&cur[((int)L[j] << cell_bits) | (int)(ph[j] >> cshift)], 1);
             tmp_phi[pos] = ph[j] >> (32 - M);
@@ -468,41 +469,67 @@ __global__ __launch_bounds__(kVoteMaxThreads) void k_vote(Events ev, const int32
 
         for (int i = tid; i < slab_dwords / 4; i += blockDim.x) s4[i] = make_uint4(0, 0, 0, 0);
         __syncthreads();
-        // The hits of each layer are cut into chunks of 64; chunk g (counted over all layers) goes
-        // to wave g % n_waves.  A wave loads a chunk with one coalesced load (one hit per lane) and
-        // then broadcasts hit j with v_readlane: the hit values travel in VGPRs, so waiting for
-        // them never waits for the LDS atomics (scalar loads would share the LDS wait counter).
-        int chunk_base = 0;
-        for (int L = 0; L < n_layers; ++L) {
-            const int lo = cell_start[L << cell_bits];
-            const int hi = cell_start[(L + 1) << cell_bits];
-            const int n_chunks = (hi - lo + 63) >> 6;
-            const int first = (wave - chunk_base % n_waves + n_waves) % n_waves;
-            chunk_base += n_chunks;
-            if (first >= n_chunks) continue;
-            const int32_t e_l = E[(size_t)L * n_cols + col];
-            const bool valid = e_l != INT32_MIN;
-            const uint32_t ue = (uint32_t)e_l;
-            int c = first;
-            int h = lo + (c << 6);
-            uint32_t cur = h + lane < hi ? sorted_phi[h + lane] : 0u;
-            for (; c < n_chunks; c += n_waves) {
-                h = lo + (c << 6);
-                const int hn = h + (n_waves << 6);
-                const uint32_t nxt = hn + lane < hi ? sorted_phi[hn + lane] : 0u;  // prefetch next chunk
-                const int cnt = min(64, hi - h);
-                if (valid) {
-                    if (cnt == 64) {
+        // The hits of each layer are cut into chunks of 64; chunk g (counted over all layers, layer
+        // by layer) goes to wave g % n_waves.  Lane L holds layer L's hit range and the index of its
+        // first chunk, so the layer of a chunk is one ballot away.  A wave loads a chunk with one
+        // coalesced load (one hit per lane) together with its lane's sample value for that layer,
+        // keeps four chunks in flight across layer boundaries, and broadcasts hit j with
+        // v_readlane: the hit values travel in VGPRs, so waiting for them never waits for the LDS
+        // atomics (scalar loads would share the LDS wait counter).
+        int lo_L = 0, hi_L = 0;
+        if (lane < n_layers) {
+            lo_L = cell_start[lane << cell_bits];
+            hi_L = cell_start[(lane + 1) << cell_bits];
+        }
+        const int nch_L = (hi_L - lo_L + 63) >> 6;
+        int end_L = nch_L;  // inclusive prefix over the layers
 #pragma unroll
-                        for (int j = 0; j < 64; ++j)
-                            lds_vote((uint32_t)__builtin_amdgcn_readlane((int)cur, j), ue, mask, lanebits, data);
-                    } else {
-                        for (int j = 0; j < cnt; ++j)
-                            lds_vote((uint32_t)__builtin_amdgcn_readlane((int)cur, j), ue, mask, lanebits, data);
-                    }
+        for (int o = 1; o < 64; o <<= 1) {
+            const int u = __shfl_up(end_L, o, 64);
+            if (lane >= o) end_L += u;
+        }
+        const int cs_L = end_L - nch_L;
+        const int total_chunks = __builtin_amdgcn_readlane(end_L, 63);
+        // Branch-free: every fetch issues its two loads (clamped in bounds), so the wait before a
+        // chunk's votes covers that chunk only; a chunk past the end has cnt = 0 and votes nothing.
+        auto fetch = [&](int g, uint32_t& phi, int32_t& ev, int& cnt) {
+            const int L = min((int)__popcll(__ballot(end_L <= g)), n_layers - 1);
+            const int lo = __builtin_amdgcn_readlane(lo_L, L);
+            const int hi = __builtin_amdgcn_readlane(hi_L, L);
+            const int h = lo + ((g - __builtin_amdgcn_readlane(cs_L, L)) << 6);
+            cnt = g < total_chunks ? min(64, hi - h) : 0;
+            phi = sorted_phi[min(h + lane, max(hi - 1, 0))];
+            ev = E[(size_t)L * n_cols + col];
+        };
+        auto vote_chunk = [&](uint32_t phi, int32_t ev, int cnt) {
+            if (ev != INT32_MIN) {
+                const uint32_t ue = (uint32_t)ev;
+                if (cnt == 64) {
+#pragma unroll
+                    for (int j = 0; j < 64; ++j)
+                        lds_vote((uint32_t)__builtin_amdgcn_readlane((int)phi, j), ue, mask, lanebits, data);
+                } else {
+                    for (int j = 0; j < cnt; ++j)
+                        lds_vote((uint32_t)__builtin_amdgcn_readlane((int)phi, j), ue, mask, lanebits, data);
                 }
-                cur = nxt;
             }
+        };
+        uint32_t p0, p1, p2, p3;
+        int32_t e0, e1, e2, e3;
+        int n0, n1, n2, n3;
+        fetch(wave, p0, e0, n0);
+        fetch(wave + n_waves, p1, e1, n1);
+        fetch(wave + 2 * n_waves, p2, e2, n2);
+        fetch(wave + 3 * n_waves, p3, e3, n3);
+        for (int g = wave; g < total_chunks; g += 4 * n_waves) {
+            vote_chunk(p0, e0, n0);
+            fetch(g + 4 * n_waves, p0, e0, n0);
+            vote_chunk(p1, e1, n1);
+            fetch(g + 5 * n_waves, p1, e1, n1);
+            vote_chunk(p2, e2, n2);
+            fetch(g + 6 * n_waves, p2, e2, n2);
+            vote_chunk(p3, e3, n3);
+            fetch(g + 7 * n_waves, p3, e3, n3);
         }
         asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
         __syncthreads();
@@ -553,14 +580,11 @@ __global__ __launch_bounds__(kVoteMaxThreads) void k_vote(Events ev, const int32
 }
 
 // ------------------------------------------------------------------ peaks
+// One strip of kStrip bins of column (l, k) with its two cyclic edge bins.  (l, k) must be in range:
+// callers clamp and mask afterwards, so that every load is issued unconditionally.
 template <typename T>
-__device__ __forceinline__ void load_strip(const T* __restrict__ acc, int l, int k, int s, int n_d0, int n_qpt,
-                                           int n_phi, int32_t v[kStrip + 2]) {
-    if (l < 0 || l >= n_d0 || k < 0 || k >= n_qpt) {
-#pragma unroll
-        for (int i = 0; i < kStrip + 2; ++i) v[i] = INT32_MIN;
-        return;
-    }
+__device__ __forceinline__ void load_strip(const T* __restrict__ acc, int l, int k, int s, int n_qpt, int n_phi,
+                                           int32_t v[kStrip + 2]) {
     const T* row = acc + ((size_t)l * n_qpt + k) * n_phi;
     const int b0 = s * kStrip;
     if (sizeof(T) == 4) {
@@ -570,13 +594,51 @@ __device__ __forceinline__ void load_strip(const T* __restrict__ acc, int l, int
         v[5] = (int32_t)c.x; v[6] = (int32_t)c.y; v[7] = (int32_t)c.z; v[8] = (int32_t)c.w;
     } else {
         const uint4 a = *reinterpret_cast<const uint4*>(row + b0);
-        v[1] = (int16_t)(a.x & 0xFFFF); v[2] = (int16_t)(a.x >> 16);
-        v[3] = (int16_t)(a.y & 0xFFFF); v[4] = (int16_t)(a.y >> 16);
-        v[5] = (int16_t)(a.z & 0xFFFF); v[6] = (int16_t)(a.z >> 16);
-        v[7] = (int16_t)(a.w & 0xFFFF); v[8] = (int16_t)(a.w >> 16);
+        v[1] = (int32_t)a.x; v[2] = (int32_t)a.y; v[3] = (int32_t)a.z; v[4] = (int32_t)a.w;  // unpacked later
     }
     v[0] = (int32_t)row[(b0 - 1) & (n_phi - 1)];
     v[kStrip + 1] = (int32_t)row[(b0 + kStrip) & (n_phi - 1)];
+}
+
+// Raw loads of one d0 plane (columns k-1, k, k+1) in flight, with the masks to apply once they land.
+struct PlaneRaw {
+    int32_t a[kStrip + 2], m[kStrip + 2], c[kStrip + 2];
+    bool ok_plane, ok_lo, ok_hi;
+};
+
+template <typename T>
+__device__ __forceinline__ void load_plane_raw(const T* __restrict__ acc, int l, int k, int s, int n_d0, int n_qpt,
+                                               int n_phi, PlaneRaw& r) {
+    r.ok_plane = l >= 0 && l < n_d0;
+    r.ok_lo = k > 0;
+    r.ok_hi = k + 1 < n_qpt;
+    const int lc = min(max(l, 0), n_d0 - 1);
+    load_strip(acc, lc, max(k - 1, 0), s, n_qpt, n_phi, r.a);
+    load_strip(acc, lc, k, s, n_qpt, n_phi, r.m);
+    load_strip(acc, lc, min(k + 1, n_qpt - 1), s, n_qpt, n_phi, r.c);
+}
+
+template <typename T>
+__device__ __forceinline__ void unpack_strip(int32_t v[kStrip + 2], bool ok, bool uniform) {
+    if (sizeof(T) == 2) {
+        const uint32_t w0 = (uint32_t)v[1], w1 = (uint32_t)v[2], w2 = (uint32_t)v[3], w3 = (uint32_t)v[4];
+        v[1] = (int16_t)(w0 & 0xFFFF); v[2] = (int16_t)(w0 >> 16);
+        v[3] = (int16_t)(w1 & 0xFFFF); v[4] = (int16_t)(w1 >> 16);
+        v[5] = (int16_t)(w2 & 0xFFFF); v[6] = (int16_t)(w2 >> 16);
+        v[7] = (int16_t)(w3 & 0xFFFF); v[8] = (int16_t)(w3 >> 16);
+        v[0] = (int16_t)v[0];
+        v[kStrip + 1] = (int16_t)v[kStrip + 1];
+    }
+    if (uniform) {
+        // `ok` is the same for the whole wave (a wave covers one column of one plane): a branch
+        if (!__builtin_amdgcn_readfirstlane((int)ok)) {
+#pragma unroll
+            for (int i = 0; i < kStrip + 2; ++i) v[i] = INT32_MIN;
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < kStrip + 2; ++i) v[i] = ok ? v[i] : INT32_MIN;
+    }
 }
 
 // 3-wide maxima along phi0 of a strip with its two edge bins: m[i] = max(v[i], v[i+1], v[i+2])
@@ -593,24 +655,35 @@ struct PlaneWin {
 };
 
 template <typename T>
-__device__ __forceinline__ void load_plane(const T* __restrict__ acc, int l, int k, int s, int n_d0, int n_qpt,
-                                           int n_phi, PlaneWin& w) {
-    int32_t a[kStrip + 2], c[kStrip + 2], m0[kStrip];
-    load_strip(acc, l, k - 1, s, n_d0, n_qpt, n_phi, a);
-    load_strip(acc, l, k, s, n_d0, n_qpt, n_phi, w.mid);
-    load_strip(acc, l, k + 1, s, n_d0, n_qpt, n_phi, c);
-    max3(a, w.lo);
-    max3(w.mid, m0);
-    max3(c, w.hi);
+__device__ __forceinline__ void finish_plane(PlaneRaw& r, PlaneWin& w, bool uniform) {
+    unpack_strip<T>(r.a, r.ok_plane && r.ok_lo, uniform);
+    unpack_strip<T>(r.m, r.ok_plane, uniform);
+    unpack_strip<T>(r.c, r.ok_plane && r.ok_hi, uniform);
+    int32_t m0[kStrip];
+#pragma unroll
+    for (int i = 0; i < kStrip + 2; ++i) w.mid[i] = r.m[i];
+    max3(r.a, w.lo);
+    max3(r.m, m0);
+    max3(r.c, w.hi);
 #pragma unroll
     for (int i = 0; i < kStrip; ++i) w.all[i] = max(max(w.lo[i], m0[i]), w.hi[i]);
 }
 
-// grid.y = event.  Each thread walks `planes` d0 planes of one strip.
+// grid.y = event.  Each thread walks `planes` (<= kMaxPeakPlanes) d0 planes of one strip, keeping
+// the planes l-1, l, l+1 reduced in registers and the loads of plane l+2 in flight.  Its outputs
+// (flag bytes, group sums) are kept in LDS and stored after the walk: a global store inside the
+// walk would make every wait for the next plane's loads also wait for that store.
+constexpr int kMaxPeakPlanes = 16;
+constexpr int kMarkThreads = 256;
+
 template <typename T>
-__global__ __launch_bounds__(256) void k_peaks_mark(Events ev, const char* __restrict__ acc_base, size_t acc_stride,
-                                                    int32_t thr, int n_d0, int n_qpt, int n_phi, int group_lanes,
-                                                    int planes, char* __restrict__ ws, WsOff O) {
+__global__ __launch_bounds__(kMarkThreads) void k_peaks_mark(Events ev, const char* __restrict__ acc_base,
+                                                             size_t acc_stride, int32_t thr, int n_d0, int n_qpt,
+                                                             int n_phi, int group_lanes, int planes,
+                                                             char* __restrict__ ws, WsOff O) {
+    __shared__ uint8_t s_flags[kMaxPeakPlanes][kMarkThreads];
+    __shared__ int32_t s_cnt[kMaxPeakPlanes][kMarkThreads / 2];
+    __shared__ int32_t s_vs[kMaxPeakPlanes][kMarkThreads / 2];
     const int e = blockIdx.y;
     const T* acc = reinterpret_cast<const T*>(acc_base + (size_t)e * acc_stride);
     char* w = event_ws(ws, ev, e);
@@ -618,18 +691,28 @@ __global__ __launch_bounds__(256) void k_peaks_mark(Events ev, const char* __res
     int32_t* grp_count = at<int32_t>(w, O.grp_count);
     int32_t* grp_votes = at<int32_t>(w, O.grp_votes);
     const int strips = n_phi / kStrip;
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    // Workgroups go to the 8 XCDs round-robin and each XCD has its own L2: block b works on tile
+    // (b % 8) * (gridDim.x / 8) + b / 8 (gridDim.x is a multiple of 8), so the neighbouring q/pT
+    // columns one tile re-reads are mostly loaded by tiles on the same XCD.
+    const unsigned tile = (blockIdx.x % 8u) * (gridDim.x / 8u) + blockIdx.x / 8u;
+    const int64_t t = (int64_t)tile * blockDim.x + threadIdx.x;
     const int s = (int)(t % strips);
     const int k = (int)((t / strips) % n_qpt);
     const int lr = (int)(t / ((int64_t)strips * n_qpt));
     const int l0 = lr * planes;
     if (l0 >= n_d0) return;  // whole waves exit together (strips * n_qpt is a multiple of 64)
     const int l1 = min(n_d0, l0 + planes);
+    PlaneRaw raw;
     PlaneWin prev, cur, next;
-    load_plane(acc, l0 - 1, k, s, n_d0, n_qpt, n_phi, prev);
-    load_plane(acc, l0, k, s, n_d0, n_qpt, n_phi, cur);
+    load_plane_raw(acc, l0 - 1, k, s, n_d0, n_qpt, n_phi, raw);
+    const bool uniform = strips >= 64;  // then a wave holds one column of one plane
+    finish_plane<T>(raw, prev, uniform);
+    load_plane_raw(acc, l0, k, s, n_d0, n_qpt, n_phi, raw);
+    finish_plane<T>(raw, cur, uniform);
+    load_plane_raw(acc, l0 + 1, k, s, n_d0, n_qpt, n_phi, raw);
     for (int l = l0; l < l1; ++l) {
-        load_plane(acc, l + 1, k, s, n_d0, n_qpt, n_phi, next);
+        finish_plane<T>(raw, next, uniform);
+        load_plane_raw(acc, l + 2, k, s, n_d0, n_qpt, n_phi, raw);
         uint32_t bits = 0;
         int32_t vsum = 0;
 #pragma unroll
@@ -644,8 +727,7 @@ __global__ __launch_bounds__(256) void k_peaks_mark(Events ev, const char* __res
                 vsum += v;
             }
         }
-        const int64_t strip_id = ((int64_t)l * n_qpt + k) * strips + s;
-        flags[strip_id] = (uint8_t)bits;
+        s_flags[l - l0][threadIdx.x] = (uint8_t)bits;
         // per-group sums: a group is `group_lanes` consecutive strips of one column
         int32_t cnt = __popc(bits);
         for (int o = group_lanes >> 1; o >= 1; o >>= 1) {
@@ -653,23 +735,51 @@ __global__ __launch_bounds__(256) void k_peaks_mark(Events ev, const char* __res
             vsum += __shfl_xor(vsum, o, 64);
         }
         if ((threadIdx.x & (group_lanes - 1)) == 0) {
-            grp_count[strip_id / group_lanes] = cnt;
-            grp_votes[strip_id / group_lanes] = vsum;
+            s_cnt[l - l0][threadIdx.x / group_lanes] = cnt;
+            s_vs[l - l0][threadIdx.x / group_lanes] = vsum;
         }
         prev = cur;
         cur = next;
     }
+    for (int l = l0; l < l1; ++l) {
+        const int64_t strip_id = ((int64_t)l * n_qpt + k) * strips + s;
+        flags[strip_id] = s_flags[l - l0][threadIdx.x];
+        if ((threadIdx.x & (group_lanes - 1)) == 0) {
+            grp_count[strip_id / group_lanes] = s_cnt[l - l0][threadIdx.x / group_lanes];
+            grp_votes[strip_id / group_lanes] = s_vs[l - l0][threadIdx.x / group_lanes];
+        }
+    }
 }
 
-// One workgroup per event, tiles of kScanThreads * kScanPer groups: exclusive prefix sums of the
-// per-group candidate counts (grp_off, int32) and vote counts (grp_voff, int64).
-constexpr int kScanPer = 8;
+// One workgroup per event: exclusive scans of the per-group candidate counts and vote sums into
+// grp_off / grp_voff (the CSR base of each group), the candidate total into the status and the
+// number of listed candidates into `misc`.  Each thread owns kPScanPer consecutive groups (vector
+// loads and stores); the next tile's loads are issued before the current tile is scanned.
+constexpr int kPScanPer = 8;
+
+__device__ __forceinline__ void load_groups(const int32_t* __restrict__ src, int64_t i0, int64_t n,
+                                            int32_t (&v)[kPScanPer]) {
+    if (i0 + kPScanPer <= n) {
+        const int4* p = reinterpret_cast<const int4*>(src + i0);
+#pragma unroll
+        for (int q = 0; q < kPScanPer / 4; ++q) {
+            const int4 t = p[q];
+            v[4 * q] = t.x;
+            v[4 * q + 1] = t.y;
+            v[4 * q + 2] = t.z;
+            v[4 * q + 3] = t.w;
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < kPScanPer; ++j) v[j] = i0 + j < n ? src[i0 + j] : 0;
+    }
+}
+
 __global__ __launch_bounds__(kScanThreads) void k_peaks_scan(Events ev, int64_t n_groups, int32_t cap,
                                                              char* __restrict__ ws, WsOff O,
                                                              hough_status_t* __restrict__ st_base) {
-    __shared__ int32_t tc[kScanThreads * kScanPer];
-    __shared__ int64_t tv[kScanThreads * kScanPer];
-    __shared__ int64_t wsum[kScanThreads / 64];
+    __shared__ int64_t wsum_c[kScanThreads / 64];
+    __shared__ int64_t wsum_v[kScanThreads / 64];
     const int e = blockIdx.y;
     char* w = event_ws(ws, ev, e);
     const int32_t* grp_count = at<int32_t>(w, O.grp_count);
@@ -678,46 +788,80 @@ __global__ __launch_bounds__(kScanThreads) void k_peaks_scan(Events ev, int64_t 
     int64_t* grp_voff = at<int64_t>(w, O.grp_voff);
     hough_status_t* st = st_base + e;
     const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wv = tid >> 6;
+    constexpr int64_t tile = (int64_t)kScanThreads * kPScanPer;
     int64_t carry_c = 0, carry_v = 0;
-    for (int64_t base = 0; base < n_groups; base += kScanThreads * kScanPer) {
-        const int m = (int)min((int64_t)kScanThreads * kScanPer, n_groups - base);
+    int32_t c[kPScanPer], v[kPScanPer];
+    load_groups(grp_count, (int64_t)tid * kPScanPer, n_groups, c);
+    load_groups(grp_votes, (int64_t)tid * kPScanPer, n_groups, v);
+    for (int64_t base = 0; base < n_groups; base += tile) {
+        const int64_t i0 = base + (int64_t)tid * kPScanPer;
+        int32_t sc = 0, sv = 0;  // a thread's groups hold < 2^31 candidates and votes
 #pragma unroll
-        for (int j = 0; j < kScanPer; ++j) {
-            const int i = j * kScanThreads + tid;
-            tc[i] = i < m ? grp_count[base + i] : 0;
-            tv[i] = i < m ? grp_votes[base + i] : 0;
+        for (int j = 0; j < kPScanPer; ++j) {
+            sc += c[j];
+            sv += v[j];
         }
-        __syncthreads();
-        int64_t sc = 0, sv = 0;
-        for (int j = 0; j < kScanPer; ++j) {
-            sc += tc[tid * kScanPer + j];
-            sv += tv[tid * kScanPer + j];
-        }
-        int64_t totc, totv;
-        int64_t rc = block_inclusive_scan(sc, wsum, &totc) - sc + carry_c;
-        int64_t rv = block_inclusive_scan(sv, wsum, &totv) - sv + carry_v;
-        // exclusive prefixes back into the tiles, then coalesced stores
-        for (int j = 0; j < kScanPer; ++j) {
-            const int i = tid * kScanPer + j;
-            const int32_t c = tc[i];
-            const int64_t v = tv[i];
-            tc[i] = (int32_t)min(rc, (int64_t)INT32_MAX);
-            tv[i] = rv;
-            rc += c;
-            rv += v;
-        }
-        __syncthreads();
+        // inclusive scans of (sc, sv) over the workgroup
+        int32_t ic = sc;
+        int64_t iv = sv;
 #pragma unroll
-        for (int j = 0; j < kScanPer; ++j) {
-            const int i = j * kScanThreads + tid;
-            if (i < m) {
-                grp_off[base + i] = tc[i];
-                grp_voff[base + i] = tv[i];
+        for (int o = 1; o < 64; o <<= 1) {
+            const int32_t uc = __shfl_up(ic, o, 64);
+            const int64_t uv = __shfl_up(iv, o, 64);
+            if (lane >= o) {
+                ic += uc;
+                iv += uv;
             }
         }
-        carry_c += totc;
-        carry_v += totv;
+        if (lane == 63) {
+            wsum_c[wv] = ic;
+            wsum_v[wv] = iv;
+        }
         __syncthreads();
+        int64_t pc = 0, pv = 0, tc = 0, tv = 0;
+#pragma unroll
+        for (int k = 0; k < kScanThreads / 64; ++k) {
+            const int64_t a = wsum_c[k], b = wsum_v[k];
+            pc += k < wv ? a : 0;
+            pv += k < wv ? b : 0;
+            tc += a;
+            tv += b;
+        }
+        __syncthreads();  // wsum is rewritten by the next tile
+        int64_t rc = carry_c + pc + ic - sc;
+        int64_t rv = carry_v + pv + iv - sv;
+        if (i0 + kPScanPer <= n_groups) {
+#pragma unroll
+            for (int q = 0; q < kPScanPer / 4; ++q) {
+                int4 o4;
+                longlong2 va, vb;
+                o4.x = (int32_t)min(rc, (int64_t)INT32_MAX); va.x = rv; rc += c[4 * q]; rv += v[4 * q];
+                o4.y = (int32_t)min(rc, (int64_t)INT32_MAX); va.y = rv; rc += c[4 * q + 1]; rv += v[4 * q + 1];
+                o4.z = (int32_t)min(rc, (int64_t)INT32_MAX); vb.x = rv; rc += c[4 * q + 2]; rv += v[4 * q + 2];
+                o4.w = (int32_t)min(rc, (int64_t)INT32_MAX); vb.y = rv; rc += c[4 * q + 3]; rv += v[4 * q + 3];
+                reinterpret_cast<int4*>(grp_off + i0)[q] = o4;
+                reinterpret_cast<longlong2*>(grp_voff + i0)[2 * q] = va;
+                reinterpret_cast<longlong2*>(grp_voff + i0)[2 * q + 1] = vb;
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < kPScanPer; ++j) {
+                if (i0 + j < n_groups) {
+                    grp_off[i0 + j] = (int32_t)min(rc, (int64_t)INT32_MAX);
+                    grp_voff[i0 + j] = rv;
+                }
+                rc += c[j];
+                rv += v[j];
+            }
+        }
+        carry_c += tc;
+        carry_v += tv;
+        if (base + tile < n_groups) {  // the next tile
+            load_groups(grp_count, i0 + tile, n_groups, c);
+            load_groups(grp_votes, i0 + tile, n_groups, v);
+        }
     }
     if (tid == 0) {
         grp_off[n_groups] = (int32_t)min(carry_c, (int64_t)INT32_MAX);
@@ -728,8 +872,12 @@ __global__ __launch_bounds__(kScanThreads) void k_peaks_scan(Events ev, int64_t 
     }
 }
 
-// One thread per strip (grid.y = event): writes its candidates and their vote-prefix (CSR offset)
-// in linear order.
+// grid.y = event.  One thread per kWriteStrips consecutive strips (64 bins) of one group (fewer
+// when a group is smaller): it loads their flag bytes and the values of the flagged bins, takes
+// its candidates' position and vote prefix from the group's CSR bases plus an in-group scan over
+// the group's threads, and writes its candidates and their CSR offsets in linear order.
+constexpr int kWriteStrips = 8;
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_peaks_write(Events ev, const char* __restrict__ acc_base,
                                                      size_t acc_stride, int64_t n_groups, int n_qpt, int n_phi,
@@ -744,69 +892,128 @@ __global__ __launch_bounds__(256) void k_peaks_write(Events ev, const char* __re
     int64_t* peak_voff = at<int64_t>(w, O.peak_voff);
     hough_peak_t* peaks = peaks_base + (size_t)e * cap;
     const int strips = n_phi / kStrip;
+    const int sp = min(kWriteStrips, group_lanes);  // strips per thread (both powers of two)
+    const int tpg = group_lanes / sp;              // threads per group (1..8)
+    const int64_t n_thr = n_strips / sp;
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const uint32_t bits = t < n_strips ? flags[t] : 0u;
-    const int s = (int)(t % strips);
-    const int64_t row = t / strips;
-    int32_t vs[kStrip];
-    int32_t vsum = 0;
-#pragma unroll
-    for (int i = 0; i < kStrip; ++i) vs[i] = 0;
-    if (bits) {  // only strips inside the accumulator have flags
-        const T* r = acc + row * n_phi;
-#pragma unroll
-        for (int i = 0; i < kStrip; ++i)
-            if (bits & (1u << i)) vs[i] = (int32_t)r[s * kStrip + i];
-    }
-#pragma unroll
-    for (int i = 0; i < kStrip; ++i) vsum += vs[i];
-    // inclusive prefix of candidate and vote counts within the group
-    const int gl = threadIdx.x & (group_lanes - 1);
-    int32_t inc = __popc(bits);
-    int32_t vinc = vsum;
-    for (int o = 1; o < group_lanes; o <<= 1) {
-        const int32_t a = __shfl_up(inc, o, group_lanes);
-        const int32_t b = __shfl_up(vinc, o, group_lanes);
-        if (gl >= o) {
-            inc += a;
-            vinc += b;
+    const bool live = t < n_thr;
+    const int64_t strip0 = (live ? t : n_thr - 1) * sp;
+    // the group's CSR bases do not depend on the flags: load them together
+    const int64_t g = strip0 / group_lanes;
+    const int32_t g_off = grp_off[g];
+    const int64_t g_voff = grp_voff[g];
+    uint64_t bits = 0;
+    if (live) {
+        if (sp == kWriteStrips) {
+            bits = *reinterpret_cast<const uint64_t*>(flags + strip0);
+        } else {
+            for (int i = 0; i < sp; ++i) bits |= (uint64_t)flags[strip0 + i] << (8 * i);
         }
     }
-    if (t >= n_strips || bits == 0) return;
-    const int64_t g = t / group_lanes;
-    int32_t pos = grp_off[g] + inc - __popc(bits);
-    int64_t voff = grp_voff[g] + vinc - vsum;
+    const int64_t row = strip0 / strips;
+    const int s0 = (int)(strip0 - row * strips);
+    const T* r = acc + row * n_phi + s0 * kStrip;
+    const int32_t cnt = __popcll(bits);
+    int32_t vsum = 0;
+    for (uint64_t b = bits; b; b &= b - 1) vsum += (int32_t)r[__ffsll((long long)b) - 1];
+    // inclusive prefix of candidate and vote counts over the group's threads
+    const int gl = threadIdx.x & (tpg - 1);
+    int32_t inc = cnt, vinc = vsum;
+    for (int o = 1; o < tpg; o <<= 1) {
+        const int32_t a = __shfl_up(inc, o, tpg);
+        const int32_t c = __shfl_up(vinc, o, tpg);
+        if (gl >= o) {
+            inc += a;
+            vinc += c;
+        }
+    }
+    if (!live || bits == 0) return;
+    int32_t pos = g_off + inc - cnt;
+    int64_t voff = g_voff + vinc - vsum;
     const int k = (int)(row % n_qpt);
     const int l = (int)(row / n_qpt);
-    for (int i = 0; i < kStrip; ++i) {
-        if (!(bits & (1u << i))) continue;
+    for (uint64_t b = bits; b; b &= b - 1) {
+        const int i = __ffsll((long long)b) - 1;
+        const int32_t v = (int32_t)r[i];
         if (pos < cap) {
             hough_peak_t pk;
             pk.l = l;
             pk.k = k;
-            pk.b = s * kStrip + i;
-            pk.votes = vs[i];
+            pk.b = s0 * kStrip + i;
+            pk.votes = v;
             peaks[pos] = pk;
             peak_voff[pos] = voff;
         }
         ++pos;
-        voff += vs[i];
+        voff += v;
     }
 }
 
 // ------------------------------------------------------------------ assign
+typedef __attribute__((address_space(3))) const uint32_t lds_cu32;
+typedef __attribute__((address_space(3))) const int32_t lds_ci32;
+
+// The list of one candidate, layer by layer: the run(s) of sorted hits with angle in
+// [lo, lo + 2^F) (mod 2^M), lo = E + b * 2^F, found from the cell table and a short scan, copied in
+// order to the wave's LDS buffer (or straight to memory beyond it).  PhiT/HT: global or LDS arrays.
+template <typename PhiT, typename HT>
+__device__ __forceinline__ void assign_candidate(const hough_peak_t& pk, int64_t off, int64_t o0, const int32_t* Ec,
+                                                 int n_layers, int cell_bits, int n_cols, int M, int F,
+                                                 const int32_t* cell_start, PhiT sorted_phi, HT sorted_h,
+                                                 int32_t* buf, int buf_words, int32_t* hit_idx, int32_t cap_pairs) {
+    const uint32_t span = 1u << M;
+    const uint32_t W = 1u << F;
+    const int cshift = M - cell_bits;
+    int32_t ev_l[kMaxLayers];
+#pragma unroll
+    for (int L = 0; L < kMaxLayers; ++L) ev_l[L] = L < n_layers ? Ec[(size_t)L * n_cols] : INT32_MIN;
+    int64_t wpos = off;
+#pragma unroll
+    for (int L = 0; L < kMaxLayers; ++L) {
+        if (L >= n_layers || wpos >= cap_pairs) break;
+        if (ev_l[L] == INT32_MIN) continue;
+        const uint32_t lo = ((uint32_t)ev_l[L] + ((uint32_t)pk.b << F)) & (span - 1u);
+        const uint32_t hi = lo + W;  // may exceed 2^M: the window wraps
+        const int cb = L << cell_bits;
+        const int lay_end = cell_start[cb + (1 << cell_bits)];
+        int q = cell_start[cb + (int)(lo >> cshift)];
+        const uint32_t he = hi <= span ? hi : span;
+        int z = he < span ? cell_start[cb + (int)(he >> cshift)] : lay_end;
+        while (q < lay_end && sorted_phi[q] < lo) ++q;
+        while (z < lay_end && sorted_phi[z] < he) ++z;
+        int r = -1, z2 = -1;
+        if (hi > span) {
+            const uint32_t hw = hi - span;
+            r = cell_start[cb];
+            z2 = cell_start[cb + (int)(hw >> cshift)];
+            while (z2 < lay_end && sorted_phi[z2] < hw) ++z2;
+        }
+        for (int seg = 0; seg < 2; ++seg) {
+            const int a0 = seg == 0 ? q : r;
+            const int a1 = seg == 0 ? z : z2;
+            for (int j = a0; j < a1 && wpos < cap_pairs; ++j, ++wpos) {
+                const int32_t h = sorted_h[j];
+                const int64_t rel = wpos - o0;
+                if (rel < buf_words) buf[rel] = h;
+                else hit_idx[wpos] = h;
+            }
+        }
+    }
+}
+
 // One thread per listed candidate (the first min(listed, cap_peaks) written by the peaks pass;
-// grid.y = event): CSR offset from the peaks pass, then for each layer the run(s) of sorted hits
-// with angle in [lo, lo + 2^F) (mod 2^M), lo = E + b * 2^F, copied in order.  The 64 candidates of
-// a wave own one contiguous stretch of the CSR list: it is assembled in an LDS buffer of the wave
-// and then written with coalesced stores (positions beyond the buffer go straight to memory).  The
-// cell table is staged in LDS; the per-layer sample values of a candidate are loaded together.
+// grid.y = event): CSR offset from the peaks pass, then its list (assign_candidate).  The 64
+// candidates of a wave own one contiguous stretch of the CSR list: it is assembled in an LDS
+// buffer of the wave and then written with coalesced stores.  The cell table and, when they fit
+// (stage_hits), the event's sorted angles and hit indices are staged in LDS, so the scans and
+// copies do not wait on memory; the per-layer sample values of a candidate are loaded together.
 __global__ __launch_bounds__(kAssignThreads) void k_assign_fill(
     Events ev, const hough_peak_t* __restrict__ peaks_base, int32_t peak_stride, int32_t cap_peaks,
     hough_status_t* __restrict__ st_base, const int32_t* __restrict__ E, int n_layers, int cell_bits, int n_cols,
     int n_qpt, int M, int F, char* __restrict__ ws, WsOff O, int32_t* __restrict__ offsets_base,
-    int32_t* __restrict__ hit_idx_base, int32_t cap_pairs, int buf_words) {
-    extern __shared__ int32_t sm_i32[];  // [waves][buf_words] buffers, then the cell table
+    int32_t* __restrict__ hit_idx_base, int32_t cap_pairs, int buf_words, int stage_hits) {
+    // LDS: [waves][buf_words] buffers, the cell table, then [stage_hits] angles and hit indices
+    extern __shared__ int32_t sm_i32[];
     const int e = blockIdx.y;
     char* w = event_ws(ws, ev, e);
     const hough_peak_t* peaks = peaks_base + (size_t)e * peak_stride;
@@ -831,11 +1038,18 @@ __global__ __launch_bounds__(kAssignThreads) void k_assign_fill(
     const int n_cells = n_layers << cell_bits;
     int32_t* buf = sm_i32 + wave * buf_words;
     int32_t* cell_start = sm_i32 + (kAssignThreads / 64) * buf_words;
+    uint32_t* s_phi = reinterpret_cast<uint32_t*>(cell_start + n_cells + 1);
+    int32_t* s_h = cell_start + n_cells + 1 + stage_hits;
     for (int i = tid; i <= n_cells; i += kAssignThreads) cell_start[i] = g_cell_start[i];
+    const int n_valid = g_cell_start[n_cells];
+    const bool staged = n_valid <= stage_hits;
+    if (staged) {
+        for (int i = tid; i < n_valid; i += kAssignThreads) {
+            s_phi[i] = sorted_phi[i];
+            s_h[i] = sorted_h[i];
+        }
+    }
     __syncthreads();
-    const uint32_t span = 1u << M;
-    const uint32_t W = 1u << F;
-    const int cshift = M - cell_bits;
     for (int base = blockIdx.x * kAssignThreads + wave * 64; base < n; base += gridDim.x * kAssignThreads) {
         const int i = base + lane;
         // the wave's stretch of the list: [o0, o1)
@@ -847,41 +1061,12 @@ __global__ __launch_bounds__(kAssignThreads) void k_assign_fill(
             offsets[i] = (int32_t)min(off, (int64_t)INT32_MAX);
             const hough_peak_t pk = peaks[i];
             const int32_t* Ec = E + (size_t)pk.l * n_qpt + pk.k;
-            int32_t ev_l[kMaxLayers];
-#pragma unroll
-            for (int L = 0; L < kMaxLayers; ++L) ev_l[L] = L < n_layers ? Ec[(size_t)L * n_cols] : INT32_MIN;
-            int64_t wpos = off;
-#pragma unroll
-            for (int L = 0; L < kMaxLayers; ++L) {
-                if (L >= n_layers || wpos >= cap_pairs) break;
-                if (ev_l[L] == INT32_MIN) continue;
-                const uint32_t lo = ((uint32_t)ev_l[L] + ((uint32_t)pk.b << F)) & (span - 1u);
-                const uint32_t hi = lo + W;  // may exceed 2^M: the window wraps
-                const int cb = L << cell_bits;
-                const int lay_end = cell_start[cb + (1 << cell_bits)];
-                int q = cell_start[cb + (int)(lo >> cshift)];
-                const uint32_t he = hi <= span ? hi : span;
-                int z = he < span ? cell_start[cb + (int)(he >> cshift)] : lay_end;
-                while (q < lay_end && sorted_phi[q] < lo) ++q;
-                while (z < lay_end && sorted_phi[z] < he) ++z;
-                int r = -1, z2 = -1;
-                if (hi > span) {
-                    const uint32_t hw = hi - span;
-                    r = cell_start[cb];
-                    z2 = cell_start[cb + (int)(hw >> cshift)];
-                    while (z2 < lay_end && sorted_phi[z2] < hw) ++z2;
-                }
-                for (int seg = 0; seg < 2; ++seg) {
-                    const int a0 = seg == 0 ? q : r;
-                    const int a1 = seg == 0 ? z : z2;
-                    for (int j = a0; j < a1 && wpos < cap_pairs; ++j, ++wpos) {
-                        const int32_t h = sorted_h[j];
-                        const int64_t rel = wpos - o0;
-                        if (rel < buf_words) buf[rel] = h;
-                        else hit_idx[wpos] = h;
-                    }
-                }
-            }
+            if (staged)
+                assign_candidate(pk, off, o0, Ec, n_layers, cell_bits, n_cols, M, F, cell_start, (lds_cu32*)s_phi,
+                                 (lds_ci32*)s_h, buf, buf_words, hit_idx, cap_pairs);
+            else
+                assign_candidate(pk, off, o0, Ec, n_layers, cell_bits, n_cols, M, F, cell_start, sorted_phi,
+                                 sorted_h, buf, buf_words, hit_idx, cap_pairs);
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
@@ -896,31 +1081,137 @@ __global__ __launch_bounds__(kAssignThreads) void k_assign_fill(
 }
 
 // ------------------------------------------------------------------ zvote
-// Per candidate p (one wave; grid.y = event): every hit h of its list with a usable z votes, for
-// each cot(theta) row m, into z0 bin j(m) = (Z_h * 2^16 - S_h * C_m - z0min) >> shift, where S_h is
-// the arc length from the origin to the hit's layer for the candidate's (d0, q/pT) centre; the
-// output is the (m, j) with the most votes, lowest m * n_z0 + j on ties.
+// Per candidate p (grid.y = event): every hit h of its list with a usable z votes, for each
+// cot(theta) row m, into z0 bin j(m) = (Z_h * 2^16 - S_h * C_m - z0min) >> shift, where S_h is the
+// arc length from the origin to the hit's layer for the candidate's (d0, q/pT) centre; the output
+// is the (m, j) with the most votes, lowest m * n_z0 + j on ties.  With A_h = Z_h * 2^16 - z0min -
+// S_h * C_0 and B_h = S_h * dC, the value for row m is A_h - m * B_h (exact int64).
+//
+// A wave takes groups of kZvoteGroup consecutive candidates.  It first stages (A_h, B_h) of all
+// hits of the group in its LDS (one pass of independent loads for the whole group: hit index,
+// then z and layer, then the arc length), then votes the candidates one by one: with H <= 64
+// hits, R = min(kZvoteSlots, 64 / H) rows at once, one lane per (row slot, hit).
 //
 // Each LDS word of a row histogram holds (count << 16) | (0xFFFF - j).  Adding 1 << 16 returns the
 // old word, so old + 2^16 - m * n_z0 = (count << 16) | (0xFFFF - (m * n_z0 + j)) is a key whose
 // maximum over all votes is the argmax with the lowest linear index (a bin's last vote returns its
 // final count; counts < 2^16 and n_cot * n_z0 <= 2^16 are plan limits).  The voter then writes
 // the word back to (0xFFFF - j): the atomics of one instruction complete before the next LDS
-// instruction of the wave, so the row is clean for the next row voted in that slot.  Candidates
-// with more than 64 hits vote one row at a time in chunks of 64 hits and restore the row after
-// its last chunk.
+// instruction of the wave, so the row is clean for the next row voted in that slot.  A group
+// holding a candidate of more than 64 hits is voted from memory instead, one row at a time in
+// chunks of 64 hits, restoring the row after its last chunk.
+constexpr int kZvoteGroup = 2;                    // candidates staged together by a wave
+constexpr int kZvoteStage = kZvoteGroup * 64;     // staged hits per wave (A, B: 16 bytes each)
+
 __device__ __forceinline__ void zvote_hit(int32_t h, const float* __restrict__ hz, const uint8_t* __restrict__ hl,
                                           int h0, const int32_t* __restrict__ Sc, int n_layers, size_t s_layer,
-                                          const ZGrid& zg, bool& ok, int64_t& A, int64_t& B) {
+                                          const ZGrid& zg, int64_t& A, int64_t& B) {
     const float zf = hz[h0 + h];
     const int L = hl[h0 + h];
-    ok = isfinite(zf) && fabsf(zf) < 32768.0f && L < n_layers;
+    bool ok = isfinite(zf) && fabsf(zf) < 32768.0f && L < n_layers;
     int32_t S = ok ? Sc[(size_t)L * s_layer] : -1;
     ok = ok && S >= 0;
     const int32_t Z = ok ? __float2int_rn(zf * 65536.0f) : 0;
     S = ok ? S : 0;
-    A = (int64_t)Z * 65536 - zg.z0min - (int64_t)S * zg.c0;
+    // an unusable hit gets A = -1, B = 0: its value is negative on every row and never votes
+    A = ok ? (int64_t)Z * 65536 - zg.z0min - (int64_t)S * zg.c0 : -1;
     B = (int64_t)S * zg.dc;
+}
+
+// floor(65536 / H) + 1 for H = 1..64: slot = (lane * kInvH[H]) >> 16 equals lane / H for lane < 64.
+struct InvTable {
+    uint32_t v[65];
+};
+constexpr InvTable make_inv_table() {
+    InvTable t{};
+    for (int h = 1; h <= 64; ++h) t.v[h] = 65536u / (uint32_t)h + 1u;
+    return t;
+}
+__constant__ InvTable kInvH = make_inv_table();
+
+// Votes of one candidate of H (1..64) hits whose (A, B) the lane fetches with get(i), i < H.
+// Lane = (row slot, hit); rows m = slot, slot + R, ...  For a z0 bin width 2^s with 28 <= s <= 32
+// (FAST) the bin index j and the remainder below it (left-aligned in 32 bits) step by constant
+// amounts from row to row: j - bH - borrow, an exact 64-bit subtraction done in two 32-bit halves.
+// Otherwise the 64-bit value is stepped and shifted.  The vote's word is restored with an atomic
+// subtract of the same amount (the adds of one instruction all precede it).
+template <bool FAST, typename Get>
+__device__ __forceinline__ uint32_t zvote_small(int H, int lane, uint32_t* region, const ZGrid& zg, Get get) {
+    const int nz = zg.n_z0;
+    const int R = min(kZvoteSlots, 64 / H);
+    const int slot = (int)(((uint32_t)lane * kInvH.v[H]) >> 16);
+    int64_t A = -1, B = 0;
+    if (slot < R) get(lane - slot * H, A, B);
+    uint32_t* row = region + slot * nz;
+    const int64_t z0 = A - (int64_t)slot * B;
+    const int64_t step = (int64_t)R * B;
+    uint32_t kc = 0x10000u - (uint32_t)(slot * nz);
+    const uint32_t kstep = (uint32_t)(R * nz);
+    const int iters = (zg.n_cot + R - 1) / R;
+    const uint32_t unit = 0x10000u;
+    uint32_t best = 0;
+    if (FAST) {
+        const int sh = zg.shift;
+        const uint64_t lowmask = (sh == 64) ? ~0ull : ((1ull << sh) - 1);
+        int32_t j = (int32_t)(z0 >> sh);
+        uint32_t low = (uint32_t)(((uint64_t)z0 & lowmask) << (32 - sh));
+        const int32_t bH = (int32_t)(step >> sh);
+        const uint32_t bL = (uint32_t)(((uint64_t)step & lowmask) << (32 - sh));
+        // every row of all but the last iteration exists (m < n_cot); the last one is checked
+        for (int it = 0; it + 1 < iters; ++it) {
+            if ((uint32_t)j < (uint32_t)nz) {
+                const uint32_t old = __hip_atomic_fetch_add(row + j, unit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                best = max(best, old + kc);
+                __hip_atomic_fetch_sub(row + j, unit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            }
+            asm volatile("" ::: "memory");
+            const uint32_t nl = low - bL;
+            j = j - bH - (nl > low ? 1 : 0);
+            low = nl;
+            kc -= kstep;
+        }
+        if (slot + (iters - 1) * R < zg.n_cot && (uint32_t)j < (uint32_t)nz) {
+            const uint32_t old = __hip_atomic_fetch_add(row + j, unit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            best = max(best, old + kc);
+            __hip_atomic_fetch_sub(row + j, unit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        }
+        asm volatile("" ::: "memory");
+    } else {
+        int64_t z = z0;
+        int m = slot;
+        for (int it = 0; it < iters; ++it) {
+            if (m < zg.n_cot && (uint64_t)z < zg.lim) {
+                const uint32_t j = (uint32_t)((uint64_t)z >> zg.shift);
+                const uint32_t old = __hip_atomic_fetch_add(row + j, unit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                best = max(best, old + kc);
+                __hip_atomic_fetch_sub(row + j, unit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            }
+            asm volatile("" ::: "memory");
+            z -= step;
+            m += R;
+            kc -= kstep;
+        }
+    }
+    return best;
+}
+
+__device__ __forceinline__ void zvote_write(int32_t* o, uint32_t best, int nz) {
+    if (best == 0) {
+        o[0] = -1;
+        o[1] = -1;
+        o[2] = 0;
+    } else {
+        const uint32_t lin = 0xFFFFu - (best & 0xFFFFu);
+        o[0] = (int32_t)(lin / (uint32_t)nz);
+        o[1] = (int32_t)(lin % (uint32_t)nz);
+        o[2] = (int32_t)(best >> 16);
+    }
+}
+
+__device__ __forceinline__ uint32_t wave_max(uint32_t v) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v = max(v, (uint32_t)__shfl_xor((int)v, d, 64));
+    return v;
 }
 
 __global__ __launch_bounds__(kZvoteThreads) void k_zvote(
@@ -928,6 +1219,7 @@ __global__ __launch_bounds__(kZvoteThreads) void k_zvote(
     const hough_peak_t* __restrict__ peaks_base, int32_t cap_peaks, const int32_t* __restrict__ offsets_base,
     const int32_t* __restrict__ hit_idx_base, int32_t cap_pairs, const hough_status_t* __restrict__ st_base,
     const int32_t* __restrict__ S, int n_d0, int n_qpt, ZGrid zg, int32_t* __restrict__ out_base) {
+    // LDS per wave: kZvoteSlots row histograms of n_z0 words, then kZvoteStage staged (A, B)
     extern __shared__ uint32_t zs_u32[];
     const int e = blockIdx.y;
     int h0, nh;
@@ -941,85 +1233,115 @@ __global__ __launch_bounds__(kZvoteThreads) void k_zvote(
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int nz = zg.n_z0;
     const size_t s_layer = (size_t)n_d0 * n_qpt;
-    uint32_t* region = zs_u32 + (size_t)wave * kZvoteSlots * nz;
+    const size_t wave_words = (size_t)kZvoteSlots * nz + 4 * kZvoteStage;
+    uint32_t* region = zs_u32 + (size_t)wave * wave_words;
+    int64_t* stage = reinterpret_cast<int64_t*>(region + (size_t)kZvoteSlots * nz);  // [kZvoteStage][2]
     for (int i = lane; i < kZvoteSlots * nz; i += 64) region[i] = 0xFFFFu - (uint32_t)(i % nz);
     const int waves = kZvoteThreads / 64;
-    for (int p = blockIdx.x * waves + wave; p < n; p += gridDim.x * waves) {
-        // wave-uniform candidate data
-        const int32_t pl = __builtin_amdgcn_readfirstlane(peaks[p].l);
-        const int32_t pkk = __builtin_amdgcn_readfirstlane(peaks[p].k);
-        const int32_t o0 = __builtin_amdgcn_readfirstlane(offsets[p]);
-        const int32_t o1 = __builtin_amdgcn_readfirstlane(offsets[p + 1]);
-        int32_t* o = out + 3 * (size_t)p;
-        if (o1 > cap_pairs) {  // hit list cut by the pair capacity: no result
-            if (lane == 0) {
-                o[0] = -1;
-                o[1] = -1;
-                o[2] = -1;
-            }
-            continue;
+    const int n_groups = (n + kZvoteGroup - 1) / kZvoteGroup;
+    const bool fast = zg.shift >= 28 && zg.shift <= 32;
+    for (int grp = blockIdx.x * waves + wave; grp < n_groups; grp += gridDim.x * waves) {
+        const int p0 = grp * kZvoteGroup;
+        const int cnt = min(kZvoteGroup, n - p0);
+        // lane c < cnt: candidate p0 + c (its list start, (l, k)); lane cnt: the end of the last list
+        const int32_t my_off = lane <= cnt ? offsets[p0 + lane] : 0;
+        const int32_t my_l = lane < cnt ? peaks[p0 + lane].l : 0;
+        const int32_t my_k = lane < cnt ? peaks[p0 + lane].k : 0;
+        const int32_t q0 = __builtin_amdgcn_readlane(my_off, 0);
+        int32_t qe = __builtin_amdgcn_readlane(my_off, cnt);
+        bool small = true;
+        for (int c = 0; c < cnt; ++c) {
+            const int32_t a = __builtin_amdgcn_readlane(my_off, c), b = __builtin_amdgcn_readlane(my_off, c + 1);
+            small = small && b - a <= 64;
         }
-        const int H = o1 - o0;
-        const int32_t* Sc = S + (size_t)pl * n_qpt + pkk;
-        uint32_t best = 0;
-        if (H >= 1 && H <= 64) {
-            const int R = min(kZvoteSlots, 64 / H);
-            const int slot = lane / H;
-            bool ok = false;
-            int64_t A = 0, B = 0;
-            if (slot < R) zvote_hit(hit_idx[o0 + lane - slot * H], hz, hl, h0, Sc, n_layers, s_layer, zg, ok, A, B);
-            uint32_t* row = region + slot * nz;
-            int64_t z0 = A - (int64_t)slot * B;
-            const int64_t step = (int64_t)R * B;
-            uint32_t kc = 0x10000u - (uint32_t)(slot * nz);
-            const uint32_t kstep = (uint32_t)(R * nz);
-            const int iters = (zg.n_cot + R - 1) / R;
-            int m = slot;
-            for (int it = 0; it < iters; ++it) {
-                if (ok && m < zg.n_cot && (uint64_t)z0 < zg.lim) {
-                    const uint32_t j = (uint32_t)((uint64_t)z0 >> zg.shift);
-                    const uint32_t old =
-                        __hip_atomic_fetch_add(row + j, 0x10000u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                    best = max(best, old + kc);
-                    row[j] = 0xFFFFu - j;
-                }
-                asm volatile("" ::: "memory");
-                z0 -= step;
-                m += R;
-                kc -= kstep;
-            }
-        } else if (H > 64) {
-            for (int m = 0; m < zg.n_cot; ++m) {
-                const uint32_t kc = 0x10000u - (uint32_t)(m * nz);
-                for (int c = 0; c < H; c += 64) {
-                    bool ok = false;
-                    int64_t A = 0, B = 0;
-                    if (c + lane < H) zvote_hit(hit_idx[o0 + c + lane], hz, hl, h0, Sc, n_layers, s_layer, zg, ok, A, B);
-                    const int64_t z0 = A - (int64_t)m * B;
-                    if (ok && (uint64_t)z0 < zg.lim) {
-                        const uint32_t j = (uint32_t)((uint64_t)z0 >> zg.shift);
-                        const uint32_t old =
-                            __hip_atomic_fetch_add(region + j, 0x10000u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                        best = max(best, old + kc);
-                    }
-                    asm volatile("" ::: "memory");
-                }
-                for (int j = lane; j < nz; j += 64) region[j] = 0xFFFFu - (uint32_t)j;
-                asm volatile("" ::: "memory");
-            }
-        }
+        qe = min(qe, cap_pairs);
+        if (small) {
+            // stage (A, B) of every listed hit of the group: pair q -> candidate = number of list
+            // starts <= q, minus one
 #pragma unroll
-        for (int d = 32; d >= 1; d >>= 1) best = max(best, (uint32_t)__shfl_xor((int)best, d, 64));
-        if (lane == 0) {
-            if (best == 0) {
-                o[0] = -1;
-                o[1] = -1;
-                o[2] = 0;
-            } else {
-                const uint32_t lin = 0xFFFFu - (best & 0xFFFFu);
-                o[0] = (int32_t)(lin / (uint32_t)nz);
-                o[1] = (int32_t)(lin % (uint32_t)nz);
-                o[2] = (int32_t)(best >> 16);
+            for (int i = 0; i < kZvoteStage / 64; ++i) {
+                const int32_t q = q0 + i * 64 + lane;
+                int c = 0;
+                for (int j = 1; j < cnt; ++j) c += q >= __builtin_amdgcn_readlane(my_off, j) ? 1 : 0;
+                // with every lane active: a lane shuffle reads nothing from inactive lanes
+                const int32_t l = __shfl(my_l, c, 64), k = __shfl(my_k, c, 64);
+                if (q < qe) {
+                    int64_t A, B;
+                    zvote_hit(hit_idx[q], hz, hl, h0, S + (size_t)l * n_qpt + k, n_layers, s_layer, zg, A, B);
+                    stage[2 * (q - q0)] = A;
+                    stage[2 * (q - q0) + 1] = B;
+                }
+            }
+            asm volatile("" ::: "memory");
+            for (int c = 0; c < cnt; ++c) {
+                const int32_t o0 = __builtin_amdgcn_readlane(my_off, c);
+                const int32_t o1 = __builtin_amdgcn_readlane(my_off, c + 1);
+                int32_t* o = out + 3 * (size_t)(p0 + c);
+                if (o1 > cap_pairs) {  // hit list cut by the pair capacity: no result
+                    if (lane == 0) {
+                        o[0] = -1;
+                        o[1] = -1;
+                        o[2] = -1;
+                    }
+                    continue;
+                }
+                const int H = o1 - o0;
+                uint32_t best = 0;
+                if (H >= 1) {
+                    const int64_t* st_c = stage + 2 * (o0 - q0);
+                    auto get = [&](int i, int64_t& A, int64_t& B) {
+                        A = st_c[2 * i];
+                        B = st_c[2 * i + 1];
+                    };
+                    best = fast ? zvote_small<true>(H, lane, region, zg, get) : zvote_small<false>(H, lane, region, zg, get);
+                }
+                best = wave_max(best);
+                if (lane == 0) zvote_write(o, best, nz);
+            }
+            asm volatile("" ::: "memory");
+        } else {
+            for (int c = 0; c < cnt; ++c) {
+                const int32_t o0 = __builtin_amdgcn_readlane(my_off, c);
+                const int32_t o1 = __builtin_amdgcn_readlane(my_off, c + 1);
+                const int32_t pl = __builtin_amdgcn_readlane(my_l, c), pk = __builtin_amdgcn_readlane(my_k, c);
+                int32_t* o = out + 3 * (size_t)(p0 + c);
+                if (o1 > cap_pairs) {
+                    if (lane == 0) {
+                        o[0] = -1;
+                        o[1] = -1;
+                        o[2] = -1;
+                    }
+                    continue;
+                }
+                const int H = o1 - o0;
+                const int32_t* Sc = S + (size_t)pl * n_qpt + pk;
+                uint32_t best = 0;
+                if (H >= 1 && H <= 64) {
+                    auto get = [&](int i, int64_t& A, int64_t& B) {
+                        zvote_hit(hit_idx[o0 + i], hz, hl, h0, Sc, n_layers, s_layer, zg, A, B);
+                    };
+                    best = fast ? zvote_small<true>(H, lane, region, zg, get) : zvote_small<false>(H, lane, region, zg, get);
+                } else if (H > 64) {
+                    for (int m = 0; m < zg.n_cot; ++m) {
+                        const uint32_t kc = 0x10000u - (uint32_t)(m * nz);
+                        for (int c0 = 0; c0 < H; c0 += 64) {
+                            int64_t A = -1, B = 0;
+                            if (c0 + lane < H) zvote_hit(hit_idx[o0 + c0 + lane], hz, hl, h0, Sc, n_layers, s_layer, zg, A, B);
+                            const int64_t z0 = A - (int64_t)m * B;
+                            if ((uint64_t)z0 < zg.lim) {
+                                const uint32_t j = (uint32_t)((uint64_t)z0 >> zg.shift);
+                                const uint32_t old = __hip_atomic_fetch_add(region + j, 0x10000u, __ATOMIC_RELAXED,
+                                                                            __HIP_MEMORY_SCOPE_WORKGROUP);
+                                best = max(best, old + kc);
+                            }
+                            asm volatile("" ::: "memory");
+                        }
+                        for (int j = lane; j < nz; j += 64) region[j] = 0xFFFFu - (uint32_t)j;
+                        asm volatile("" ::: "memory");
+                    }
+                }
+                best = wave_max(best);
+                if (lane == 0) zvote_write(o, best, nz);
             }
         }
     }
@@ -1053,14 +1375,16 @@ void launch_vote(const hough_plan* p, const Events& ev, int n_events, char* ws, 
                  size_t acc_stride, const int32_t* order, int32_t* queue, int grid, hough_status_t* st,
                  hipStream_t stream) {
     const int threads = p->tuning.vote_threads;
+    char* a = static_cast<char*>(acc);
+    // with timing events set, the launch itself records them at the kernel's start and end
     if (p->g.acc_bits == 32)
-        hipLaunchKernelGGL(k_vote<false>, dim3(grid), dim3(threads), p->g.n_phi * 256 + 16, stream, ev, p->d_E,
-                           p->n_layers, p->cell_bits, p->n_cols, p->g.n_phi, p->F, ws, O, static_cast<char*>(acc),
-                           acc_stride, n_events, order, queue, st);
+        hipExtLaunchKernelGGL(k_vote<false>, dim3(grid), dim3(threads), p->g.n_phi * 256 + 16, stream, p->vote_start,
+                              p->vote_stop, 0, ev, (const int32_t*)p->d_E, p->n_layers, p->cell_bits, p->n_cols,
+                              p->g.n_phi, p->F, ws, O, a, acc_stride, n_events, order, queue, st);
     else
-        hipLaunchKernelGGL(k_vote<true>, dim3(grid), dim3(threads), p->g.n_phi * 128 + 16, stream, ev, p->d_E,
-                           p->n_layers, p->cell_bits, p->n_cols, p->g.n_phi, p->F, ws, O, static_cast<char*>(acc),
-                           acc_stride, n_events, order, queue, st);
+        hipExtLaunchKernelGGL(k_vote<true>, dim3(grid), dim3(threads), p->g.n_phi * 128 + 16, stream, p->vote_start,
+                              p->vote_stop, 0, ev, (const int32_t*)p->d_E, p->n_layers, p->cell_bits, p->n_cols,
+                              p->g.n_phi, p->F, ws, O, a, acc_stride, n_events, order, queue, st);
 }
 
 void launch_peaks(const hough_plan* p, const Events& ev, int n_events, const void* acc, size_t acc_stride,
@@ -1073,14 +1397,15 @@ void launch_peaks(const hough_plan* p, const Events& ev, int n_events, const voi
     const int64_t mark_threads = (int64_t)strips * p->g.n_qpt * lranges;
     const int64_t n_strips = p->n_bins / kStrip;
     const int64_t groups = peak_groups(p);
-    const dim3 gm((unsigned)((mark_threads + 255) / 256), n_events);
-    const dim3 gw((unsigned)((n_strips + 255) / 256), n_events);
+    const dim3 gm((unsigned)(((mark_threads + 255) / 256 + 7) / 8 * 8), n_events);  // multiple of 8: see k_peaks_mark
+    const int wsp = gl < kWriteStrips ? gl : kWriteStrips;
+    const dim3 gw((unsigned)((n_strips / wsp + 255) / 256), n_events);
     const char* a = static_cast<const char*>(acc);
     if (p->g.acc_bits == 32)
-        hipLaunchKernelGGL(k_peaks_mark<int32_t>, gm, dim3(256), 0, stream, ev, a, acc_stride, threshold, p->g.n_d0,
+        hipLaunchKernelGGL(k_peaks_mark<int32_t>, gm, dim3(kMarkThreads), 0, stream, ev, a, acc_stride, threshold, p->g.n_d0,
                            p->g.n_qpt, p->g.n_phi, gl, planes, ws, O);
     else
-        hipLaunchKernelGGL(k_peaks_mark<int16_t>, gm, dim3(256), 0, stream, ev, a, acc_stride, threshold, p->g.n_d0,
+        hipLaunchKernelGGL(k_peaks_mark<int16_t>, gm, dim3(kMarkThreads), 0, stream, ev, a, acc_stride, threshold, p->g.n_d0,
                            p->g.n_qpt, p->g.n_phi, gl, planes, ws, O);
     hipLaunchKernelGGL(k_peaks_scan, dim3(1, n_events), dim3(kScanThreads), 0, stream, ev, groups, cap, ws, O, st);
     if (p->g.acc_bits == 32)
@@ -1100,21 +1425,25 @@ void launch_assign(const hough_plan* p, const Events& ev, int n_events, const ho
     const size_t cells_bytes = 4 * ((size_t)p->n_cells + 1);
     int buf_words = (int)((kLdsBytes - cells_bytes) / 4 / (kAssignThreads / 64)) & ~63;
     buf_words = buf_words > kAssignBufMax ? kAssignBufMax : buf_words;
-    const size_t lds = 4 * (size_t)(kAssignThreads / 64) * buf_words + cells_bytes;
+    // the rest of the LDS stages the event's sorted hits (8 bytes each) when they fit
+    const size_t used = 4 * (size_t)(kAssignThreads / 64) * buf_words + cells_bytes;
+    const int stage_hits = used < (size_t)kLdsBytes ? (int)(((size_t)kLdsBytes - used) / 8) : 0;
+    const size_t lds = used + 8 * (size_t)stage_hits;
     hipLaunchKernelGGL(k_assign_fill, dim3(nblk, n_events), dim3(kAssignThreads), lds, stream, ev, peaks, peak_stride,
                        cap_peaks, st, p->d_E, p->n_layers, p->cell_bits, p->n_cols, p->g.n_qpt, p->M, p->F, ws, O,
-                       offsets, hit_idx, cap_pairs, buf_words);
+                       offsets, hit_idx, cap_pairs, buf_words, stage_hits);
 }
 
 void launch_zvote(const hough_plan* p, const Events& ev, int n_events, const float* z, const uint8_t* layer,
                   const hough_peak_t* peaks, int32_t cap_peaks, const int32_t* offsets, const int32_t* hit_idx,
                   int32_t cap_pairs, const hough_status_t* st, int32_t* out, hipStream_t stream) {
-    // enough waves to fill the chip (5 workgroups of 4 waves per CU at 128 z0 bins), split over the events
-    const int64_t want = ((int64_t)cap_peaks + 3) / 4;
+    // enough waves to fill the chip several times over, split over the events; a wave takes groups
+    // of kZvoteGroup candidates
+    const int64_t want = ((int64_t)cap_peaks + 4 * kZvoteGroup - 1) / (4 * kZvoteGroup);
     int64_t per_event = (2560 + n_events - 1) / n_events;
     per_event = per_event < want ? per_event : want;
     const unsigned nblk = (unsigned)(per_event > 0 ? per_event : 1);
-    const size_t lds = (size_t)(kZvoteThreads / 64) * kZvoteSlots * p->zg.n_z0 * 4;
+    const size_t lds = (size_t)(kZvoteThreads / 64) * ((size_t)kZvoteSlots * p->zg.n_z0 * 4 + 16 * kZvoteStage);
     hipLaunchKernelGGL(k_zvote, dim3(nblk, n_events), dim3(kZvoteThreads), lds, stream, ev, z, layer, p->n_layers,
                        peaks, cap_peaks, offsets, hit_idx, cap_pairs, st, p->d_S, p->g.n_d0, p->g.n_qpt, p->zg, out);
 }
@@ -1349,8 +1678,15 @@ void hough_plan_destroy(hough_plan_t* plan) {
 int hough_plan_set_tuning(hough_plan_t* p, const hough_tuning_t* t) {
     if (!p || !t) return HOUGH_E_INVAL;
     if (t->vote_threads != 256 && t->vote_threads != 512 && t->vote_threads != 1024) return HOUGH_E_INVAL;
-    if (t->vote_grid < 0 || t->peak_planes < 1 || t->peak_planes > 64) return HOUGH_E_INVAL;
+    if (t->vote_grid < 0 || t->peak_planes < 1 || t->peak_planes > kMaxPeakPlanes) return HOUGH_E_INVAL;
     p->tuning = *t;
+    return HOUGH_OK;
+}
+
+int hough_plan_set_vote_events(hough_plan_t* p, hipEvent_t start, hipEvent_t stop) {
+    if (!p) return HOUGH_E_INVAL;
+    p->vote_start = start;
+    p->vote_stop = stop;
     return HOUGH_OK;
 }
 

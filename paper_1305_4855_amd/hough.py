@@ -84,6 +84,7 @@ def _load() -> C.CDLL:
     L.hough_strerror.restype = C.c_char_p; L.hough_strerror.argtypes = [C.c_int]
     L.hough_plan_set_tuning.restype = C.c_int; L.hough_plan_set_tuning.argtypes = [P, C.POINTER(Tuning)]
     L.hough_plan_get_tuning.restype = C.c_int; L.hough_plan_get_tuning.argtypes = [P, C.POINTER(Tuning)]
+    L.hough_plan_set_vote_events.restype = C.c_int; L.hough_plan_set_vote_events.argtypes = [P, P, P]
     L.hough_batch_ws_bytes.restype = S; L.hough_batch_ws_bytes.argtypes = [P, C.c_int32, C.c_int32]
     L.hough_run_batch.restype = C.c_int; L.hough_run_batch.argtypes = [P, C.POINTER(Batch), P]
     L.hough_batch_graph_create.restype = C.c_int
@@ -97,7 +98,7 @@ lib = _load()
 
 EXPORTED = ["hough_plan_create", "hough_plan_destroy", "hough_acc_bytes", "hough_event_ws_bytes",
             "hough_angle_bits", "hough_plan_table", "hough_prep", "hough_vote", "hough_vote_prepared", "hough_peaks",
-            "hough_assign", "hough_zvote", "hough_plan_arclen_table", "hough_strerror", "hough_plan_set_tuning", "hough_plan_get_tuning",
+            "hough_assign", "hough_zvote", "hough_plan_arclen_table", "hough_strerror", "hough_plan_set_tuning", "hough_plan_get_tuning", "hough_plan_set_vote_events",
             "hough_batch_ws_bytes", "hough_run_batch", "hough_batch_graph_create", "hough_graph_launch",
             "hough_graph_destroy"]
 
@@ -176,6 +177,17 @@ class Plan:
     def set_tuning(self, vote_threads: int = 1024, vote_grid: int = 0, peak_planes: int = 8) -> None:
         t = Tuning(int(vote_threads), int(vote_grid), int(peak_planes))
         _check(lib.hough_plan_set_tuning(self.handle, C.byref(t)), "hough_plan_set_tuning")
+
+    def set_vote_events(self, start=None, stop=None) -> None:
+        """Have the vote kernel record these torch.cuda.Events (timing enabled) at its own start and
+        end; None, None switches it off."""
+        def raw(ev):
+            if ev is None:
+                return None
+            if not ev.cuda_event:  # torch creates the HIP event at its first record
+                ev.record()
+            return ev.cuda_event
+        _check(lib.hough_plan_set_vote_events(self.handle, raw(start), raw(stop)), "hough_plan_set_vote_events")
 
     def table(self) -> np.ndarray:
         c = self.cfg
