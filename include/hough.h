@@ -81,7 +81,9 @@ typedef struct {
     int32_t n_phi;             /* phi0 bins, power of two, 16..4096                    */
     int32_t n_qpt;             /* q/pT bins (multiple of 64)                           */
     int32_t n_d0;              /* d0 bins (1 = prompt 2-D search)                      */
-    int32_t frac_bits;         /* angle bits below one phi0 bin: 8 (int32), 7 (int16)  */
+    int32_t frac_bits;         /* angle bits below one phi0 bin: 7 (16-bit vote counters
+                                  in LDS; int32 or int16 accumulator, max_hits_per_event
+                                  <= 65535, resp. 32767) or 8 (32-bit counters, int32) */
     double qpt_min, qpt_max;   /* GeV^-1                                               */
     double d0_min, d0_max;     /* cm                                                   */
     int32_t acc_bits;          /* 32 or 16 (int16 requires max_hits_per_event < 32768) */

@@ -30,7 +30,7 @@ class HoughConfig:
     n_phi: int = 512
     n_qpt: int = 256
     n_d0: int = 64
-    frac_bits: int = 8          # angle bits below one phi0 bin
+    frac_bits: int = 7          # angle bits below one phi0 bin
     qpt_min: float = -1.0
     qpt_max: float = 1.0
     d0_min: float = -10.0

@@ -113,6 +113,7 @@ struct hough_plan {
     ZGrid zg;
     int32_t* d_S;    // [n_layers][n_d0][n_qpt] Q16.16 arc length to the layer, -1 = invalid (zvote only)
     hipEvent_t vote_start, vote_stop;  // recorded by every vote launch when set (kernel timing)
+    int n_cu;        // compute units of the plan's device
 };
 
 namespace {
@@ -422,14 +423,33 @@ __device__ __forceinline__ void lds_vote(uint32_t phi, uint32_t e, uint32_t mask
     asm volatile("ds_add_u32 %0, %1" ::"v"(a), "v"(data) : "memory");
 }
 
+// Four votes at once: the four addresses live in four registers, so no atomic waits for the one
+// before it to have read its address register before the next address can be formed.
+__device__ __forceinline__ void lds_vote4(uint32_t p0, uint32_t p1, uint32_t p2, uint32_t p3, uint32_t e,
+                                          uint32_t mask, uint32_t lanebits, uint32_t data) {
+    uint32_t a0, a1, a2, a3;
+    asm("v_and_or_b32 %0, %1, %2, %3" : "=v"(a0) : "v"(p0 - e), "s"(mask), "v"(lanebits));
+    asm("v_and_or_b32 %0, %1, %2, %3" : "=v"(a1) : "v"(p1 - e), "s"(mask), "v"(lanebits));
+    asm("v_and_or_b32 %0, %1, %2, %3" : "=v"(a2) : "v"(p2 - e), "s"(mask), "v"(lanebits));
+    asm("v_and_or_b32 %0, %1, %2, %3" : "=v"(a3) : "v"(p3 - e), "s"(mask), "v"(lanebits));
+    asm volatile(
+        "ds_add_u32 %0, %4\n\t"
+        "ds_add_u32 %1, %4\n\t"
+        "ds_add_u32 %2, %4\n\t"
+        "ds_add_u32 %3, %4" ::"v"(a0), "v"(a1), "v"(a2), "v"(a3), "v"(data) : "memory");
+}
+
 typedef __attribute__((address_space(3))) uint32_t lds_u32;
 
-// ACC16 = false: slab dword (b * 64 + c), one int32 counter per (bin, column), F = 8.
-// ACC16 = true : slab dword (b * 32 + c % 32), 16-bit halves for columns c and c + 32, F = 7.
+// SLAB16 = false: slab dword (b * 64 + c), one 32-bit counter per (bin, column), F = 8.
+// SLAB16 = true : slab dword (b * 32 + c % 32), 16-bit halves for columns c and c + 32, F = 7
+//                 (half the LDS, so two workgroups share a CU and one's store overlaps the
+//                 other's votes; a half never carries: a column counts at most max_hits <= 65535).
+// OUT16: the accumulator in HBM is int16 (else int32).
 // Work items are (event, slab) pairs, item = rank * n_slabs + slab where rank orders the events
 // (order == nullptr: identity).  Items 0 .. gridDim.x-1 are taken by block index; with a queue the
 // next items come from an atomic counter (which must start at 0), otherwise by a stride of gridDim.x.
-template <bool ACC16>
+template <bool SLAB16, bool OUT16>
 __global__ __launch_bounds__(kVoteMaxThreads) void k_vote(Events ev, const int32_t* __restrict__ E, int n_layers,
                                                           int cell_bits, int n_cols, int n_phi, int F,
                                                           char* __restrict__ ws, WsOff O,
@@ -443,7 +463,7 @@ __global__ __launch_bounds__(kVoteMaxThreads) void k_vote(Events ev, const int32
     const int n_waves = blockDim.x >> 6;
     const int n_slabs = n_cols / kVoteCols;
     const int total = n_events * n_slabs;
-    const int slab_dwords = ACC16 ? n_phi * 32 : n_phi * 64;
+    const int slab_dwords = SLAB16 ? n_phi * 32 : n_phi * 64;
 
     // The vote addresses LDS by byte offset from 0: the slab must be the kernel's only LDS object
     // (no static __shared__ variables in this kernel).
@@ -453,8 +473,8 @@ __global__ __launch_bounds__(kVoteMaxThreads) void k_vote(Events ev, const int32
         return;
     }
     const uint32_t mask = (uint32_t)(n_phi - 1) << F;
-    const uint32_t lanebits = ACC16 ? (uint32_t)(lane & 31) << 2 : (uint32_t)lane << 2;
-    const uint32_t data = ACC16 ? (lane >= 32 ? 0x10000u : 1u) : 1u;
+    const uint32_t lanebits = SLAB16 ? (uint32_t)(lane & 31) << 2 : (uint32_t)lane << 2;
+    const uint32_t data = SLAB16 ? (lane >= 32 ? 0x10000u : 1u) : 1u;
     uint4* s4 = reinterpret_cast<uint4*>(slab);
 
     int item = blockIdx.x;
@@ -506,8 +526,11 @@ __global__ __launch_bounds__(kVoteMaxThreads) void k_vote(Events ev, const int32
                 const uint32_t ue = (uint32_t)ev;
                 if (cnt == 64) {
 #pragma unroll
-                    for (int j = 0; j < 64; ++j)
-                        lds_vote((uint32_t)__builtin_amdgcn_readlane((int)phi, j), ue, mask, lanebits, data);
+                    for (int j = 0; j < 64; j += 4)
+                        lds_vote4((uint32_t)__builtin_amdgcn_readlane((int)phi, j),
+                                  (uint32_t)__builtin_amdgcn_readlane((int)phi, j + 1),
+                                  (uint32_t)__builtin_amdgcn_readlane((int)phi, j + 2),
+                                  (uint32_t)__builtin_amdgcn_readlane((int)phi, j + 3), ue, mask, lanebits, data);
                 } else {
                     for (int j = 0; j < cnt; ++j)
                         lds_vote((uint32_t)__builtin_amdgcn_readlane((int)phi, j), ue, mask, lanebits, data);
@@ -537,7 +560,7 @@ __global__ __launch_bounds__(kVoteMaxThreads) void k_vote(Events ev, const int32
         // store the slab: acc[col][b], b fastest
         const int col0 = slab_id * kVoteCols;
         char* acc_e = acc_base + (size_t)e * acc_stride;
-        if (!ACC16) {
+        if (!SLAB16) {
             int32_t* acc = reinterpret_cast<int32_t*>(acc_e);
             const int quads = n_phi / 4;
             for (int i = tid; i < quads * kVoteCols; i += blockDim.x) {
@@ -550,7 +573,6 @@ __global__ __launch_bounds__(kVoteMaxThreads) void k_vote(Events ev, const int32
                 *reinterpret_cast<uint4*>(acc + (size_t)(col0 + c) * n_phi + 4 * q) = v;
             }
         } else {
-            int16_t* acc = reinterpret_cast<int16_t*>(acc_e);
             const int octs = n_phi / 8;
             for (int i = tid; i < octs * kVoteCols; i += blockDim.x) {
                 const int c = i & 63, q = i >> 6;
@@ -558,12 +580,20 @@ __global__ __launch_bounds__(kVoteMaxThreads) void k_vote(Events ev, const int32
                 uint32_t wv[8];
 #pragma unroll
                 for (int j = 0; j < 8; ++j) wv[j] = (slab[(8 * q + j) * 32 + (c & 31)] >> sh) & 0xFFFFu;
-                uint4 v;
-                v.x = wv[0] | (wv[1] << 16);
-                v.y = wv[2] | (wv[3] << 16);
-                v.z = wv[4] | (wv[5] << 16);
-                v.w = wv[6] | (wv[7] << 16);
-                *reinterpret_cast<uint4*>(acc + (size_t)(col0 + c) * n_phi + 8 * q) = v;
+                if (OUT16) {
+                    int16_t* acc = reinterpret_cast<int16_t*>(acc_e);
+                    uint4 v;
+                    v.x = wv[0] | (wv[1] << 16);
+                    v.y = wv[2] | (wv[3] << 16);
+                    v.z = wv[4] | (wv[5] << 16);
+                    v.w = wv[6] | (wv[7] << 16);
+                    *reinterpret_cast<uint4*>(acc + (size_t)(col0 + c) * n_phi + 8 * q) = v;
+                } else {
+                    int32_t* acc = reinterpret_cast<int32_t*>(acc_e);
+                    uint4* dst = reinterpret_cast<uint4*>(acc + (size_t)(col0 + c) * n_phi + 8 * q);
+                    dst[0] = make_uint4(wv[0], wv[1], wv[2], wv[3]);
+                    dst[1] = make_uint4(wv[4], wv[5], wv[6], wv[7]);
+                }
             }
         }
         if (queue) {
@@ -956,7 +986,27 @@ typedef __attribute__((address_space(3))) const int32_t lds_ci32;
 // The list of one candidate, layer by layer: the run(s) of sorted hits with angle in
 // [lo, lo + 2^F) (mod 2^M), lo = E + b * 2^F, found from the cell table and a short scan, copied in
 // order to the wave's LDS buffer (or straight to memory beyond it).  PhiT/HT: global or LDS arrays.
-template <typename PhiT, typename HT>
+// First index of cell c (hits [cs[c], cs[c+1]) sorted by angle) whose angle is >= x.  SCAN8: the
+// first 8 entries of the cell are compared at once (independent loads, no divergent loop; the
+// cells hold about two hits on average), a longer cell continues one by one.
+template <bool SCAN8, typename PhiT>
+__device__ __forceinline__ int cell_lower_bound(const int32_t* cs, int c, PhiT phi, uint32_t x) {
+    const int a = cs[c];
+    const int n_in = cs[c + 1] - a;
+    if (!SCAN8) {
+        int q = a;
+        while (q < a + n_in && phi[q] < x) ++q;
+        return q;
+    }
+    int cnt = 0;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) cnt += (i < n_in && phi[a + i] < x) ? 1 : 0;
+    if (n_in > 8 && cnt == 8)
+        while (cnt < n_in && phi[a + cnt] < x) ++cnt;
+    return a + cnt;
+}
+
+template <bool SCAN8, typename PhiT, typename HT>
 __device__ __forceinline__ void assign_candidate(const hough_peak_t& pk, int64_t off, int64_t o0, const int32_t* Ec,
                                                  int n_layers, int cell_bits, int n_cols, int M, int F,
                                                  const int32_t* cell_start, PhiT sorted_phi, HT sorted_h,
@@ -974,19 +1024,18 @@ __device__ __forceinline__ void assign_candidate(const hough_peak_t& pk, int64_t
         if (ev_l[L] == INT32_MIN) continue;
         const uint32_t lo = ((uint32_t)ev_l[L] + ((uint32_t)pk.b << F)) & (span - 1u);
         const uint32_t hi = lo + W;  // may exceed 2^M: the window wraps
-        const int cb = L << cell_bits;
-        const int lay_end = cell_start[cb + (1 << cell_bits)];
-        int q = cell_start[cb + (int)(lo >> cshift)];
+        // the window's first and last hits lie in the cells of its two ends: every hit of a later
+        // cell has a larger angle than the window's start, every hit of an earlier cell a smaller one
+        const int32_t* cs = cell_start + (L << cell_bits);
+        const int lay_end = cs[1 << cell_bits];
+        const int q = cell_lower_bound<SCAN8>(cs, (int)(lo >> cshift), sorted_phi, lo);
         const uint32_t he = hi <= span ? hi : span;
-        int z = he < span ? cell_start[cb + (int)(he >> cshift)] : lay_end;
-        while (q < lay_end && sorted_phi[q] < lo) ++q;
-        while (z < lay_end && sorted_phi[z] < he) ++z;
+        const int z = he < span ? cell_lower_bound<SCAN8>(cs, (int)(he >> cshift), sorted_phi, he) : lay_end;
         int r = -1, z2 = -1;
         if (hi > span) {
             const uint32_t hw = hi - span;
-            r = cell_start[cb];
-            z2 = cell_start[cb + (int)(hw >> cshift)];
-            while (z2 < lay_end && sorted_phi[z2] < hw) ++z2;
+            r = cs[0];
+            z2 = cell_lower_bound<SCAN8>(cs, (int)(hw >> cshift), sorted_phi, hw);
         }
         for (int seg = 0; seg < 2; ++seg) {
             const int a0 = seg == 0 ? q : r;
@@ -1062,11 +1111,11 @@ __global__ __launch_bounds__(kAssignThreads) void k_assign_fill(
             const hough_peak_t pk = peaks[i];
             const int32_t* Ec = E + (size_t)pk.l * n_qpt + pk.k;
             if (staged)
-                assign_candidate(pk, off, o0, Ec, n_layers, cell_bits, n_cols, M, F, cell_start, (lds_cu32*)s_phi,
-                                 (lds_ci32*)s_h, buf, buf_words, hit_idx, cap_pairs);
+                assign_candidate<true>(pk, off, o0, Ec, n_layers, cell_bits, n_cols, M, F, cell_start,
+                                       (lds_cu32*)s_phi, (lds_ci32*)s_h, buf, buf_words, hit_idx, cap_pairs);
             else
-                assign_candidate(pk, off, o0, Ec, n_layers, cell_bits, n_cols, M, F, cell_start, sorted_phi,
-                                 sorted_h, buf, buf_words, hit_idx, cap_pairs);
+                assign_candidate<false>(pk, off, o0, Ec, n_layers, cell_bits, n_cols, M, F, cell_start, sorted_phi,
+                                        sorted_h, buf, buf_words, hit_idx, cap_pairs);
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
@@ -1374,16 +1423,28 @@ void launch_prep(const hough_plan* p, const Events& ev, int n_events, int max_n,
 void launch_vote(const hough_plan* p, const Events& ev, int n_events, char* ws, const WsOff& O, void* acc,
                  size_t acc_stride, const int32_t* order, int32_t* queue, int grid, hough_status_t* st,
                  hipStream_t stream) {
-    const int threads = p->tuning.vote_threads;
+    int threads = p->tuning.vote_threads;
     char* a = static_cast<char*>(acc);
+    const int32_t* E = p->d_E;
+    size_t lds = (size_t)p->g.n_phi * ((size_t)1 << p->F) + 16;
+    if (grid <= p->n_cu) {
+        // At most one workgroup per CU: the most waves per workgroup, and more than half the LDS
+        // so that no CU gets two slabs while another idles (the dispatcher packs what fits).
+        threads = kVoteMaxThreads;
+        if (lds <= (size_t)kLdsBytes / 2) lds = (size_t)kLdsBytes / 2 + 256;
+    }
     // with timing events set, the launch itself records them at the kernel's start and end
-    if (p->g.acc_bits == 32)
-        hipExtLaunchKernelGGL(k_vote<false>, dim3(grid), dim3(threads), p->g.n_phi * 256 + 16, stream, p->vote_start,
-                              p->vote_stop, 0, ev, (const int32_t*)p->d_E, p->n_layers, p->cell_bits, p->n_cols,
+    if (p->F == 8)
+        hipExtLaunchKernelGGL(k_vote<false, false>, dim3(grid), dim3(threads), lds, stream,
+                              p->vote_start, p->vote_stop, 0, ev, E, p->n_layers, p->cell_bits, p->n_cols,
+                              p->g.n_phi, p->F, ws, O, a, acc_stride, n_events, order, queue, st);
+    else if (p->g.acc_bits == 32)
+        hipExtLaunchKernelGGL(k_vote<true, false>, dim3(grid), dim3(threads), lds, stream,
+                              p->vote_start, p->vote_stop, 0, ev, E, p->n_layers, p->cell_bits, p->n_cols,
                               p->g.n_phi, p->F, ws, O, a, acc_stride, n_events, order, queue, st);
     else
-        hipExtLaunchKernelGGL(k_vote<true>, dim3(grid), dim3(threads), p->g.n_phi * 128 + 16, stream, p->vote_start,
-                              p->vote_stop, 0, ev, (const int32_t*)p->d_E, p->n_layers, p->cell_bits, p->n_cols,
+        hipExtLaunchKernelGGL(k_vote<true, true>, dim3(grid), dim3(threads), lds, stream,
+                              p->vote_start, p->vote_stop, 0, ev, E, p->n_layers, p->cell_bits, p->n_cols,
                               p->g.n_phi, p->F, ws, O, a, acc_stride, n_events, order, queue, st);
 }
 
@@ -1487,16 +1548,17 @@ int hough_plan_create(const hough_geometry_t* geom, const hough_grid_t* grid, ho
     if (g.n_qpt < 1 || g.n_d0 < 1 || g.max_hits_per_event < 1) return HOUGH_E_INVAL;
     if (g.max_hits_per_event > (1 << 24) - 1) return HOUGH_E_UNSUPPORTED;
     if (g.n_qpt % kVoteCols) return HOUGH_E_UNSUPPORTED;
-    if (g.acc_bits == 32) {
-        if (g.frac_bits != 8) return HOUGH_E_UNSUPPORTED;
-    } else if (g.acc_bits == 16) {
-        if (g.frac_bits != 7 || g.max_hits_per_event > 32767) return HOUGH_E_UNSUPPORTED;
+    // vote slab rows are 2^F bytes: F = 8 -> 32-bit counters, F = 7 -> 16-bit counters
+    if (g.acc_bits != 32 && g.acc_bits != 16) return HOUGH_E_UNSUPPORTED;
+    if (g.frac_bits == 8) {
+        if (g.acc_bits != 32) return HOUGH_E_UNSUPPORTED;
+    } else if (g.frac_bits == 7) {
+        if (g.max_hits_per_event > (g.acc_bits == 16 ? 32767 : 65535)) return HOUGH_E_UNSUPPORTED;
     } else {
         return HOUGH_E_UNSUPPORTED;
     }
     // the slab of one vote workgroup must fit the 160 KiB of LDS
-    if ((size_t)g.n_phi * 256 + 16 > (size_t)kLdsBytes && g.acc_bits == 32) return HOUGH_E_UNSUPPORTED;
-    if ((size_t)g.n_phi * 128 + 16 > (size_t)kLdsBytes && g.acc_bits == 16) return HOUGH_E_UNSUPPORTED;
+    if ((size_t)g.n_phi * ((size_t)1 << g.frac_bits) + 16 > (size_t)kLdsBytes) return HOUGH_E_UNSUPPORTED;
     if (!(g.qpt_max >= g.qpt_min) || !(g.d0_max >= g.d0_min)) return HOUGH_E_INVAL;
     if ((int64_t)g.n_d0 * g.n_qpt * g.n_phi > ((int64_t)1 << 31)) return HOUGH_E_UNSUPPORTED;
     if ((geom->n_layers << (lp < 10 ? lp : 10)) > kMaxCells) return HOUGH_E_UNSUPPORTED;
@@ -1534,7 +1596,8 @@ int hough_plan_create(const hough_geometry_t* geom, const hough_grid_t* grid, ho
 
     hough_plan* p = new (std::nothrow) hough_plan();
     if (!p) return HOUGH_E_NOMEM;
-    if (hipGetDevice(&p->device) != hipSuccess) {
+    if (hipGetDevice(&p->device) != hipSuccess ||
+        hipDeviceGetAttribute(&p->n_cu, hipDeviceAttributeMultiprocessorCount, p->device) != hipSuccess) {
         delete p;
         return HOUGH_E_HIP;
     }
@@ -1651,9 +1714,14 @@ int hough_plan_create(const hough_geometry_t* geom, const hough_grid_t* grid, ho
         return HOUGH_E_HIP;
     }
     // dynamic LDS limits set to the whole 160 KiB once (a lower per-plan value would break other plans)
-    hipError_t ae = hipFuncSetAttribute((const void*)k_vote<false>, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
+    hipError_t ae = hipFuncSetAttribute((const void*)k_vote<false, false>,
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
     if (ae == hipSuccess)
-        ae = hipFuncSetAttribute((const void*)k_vote<true>, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
+        ae = hipFuncSetAttribute((const void*)k_vote<true, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 kLdsBytes);
+    if (ae == hipSuccess)
+        ae = hipFuncSetAttribute((const void*)k_vote<true, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 kLdsBytes);
     if (ae == hipSuccess)
         ae = hipFuncSetAttribute((const void*)k_assign_fill, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
     if (ae == hipSuccess)

@@ -110,12 +110,14 @@ def test_c1_full_parity(H, oracle_mod, event_id):
     check_full(H, oracle_mod, configs.C1, synth.make_event(configs.C1, event_id))
 
 
-@pytest.mark.parametrize("shape,tracks,eid", [
-    ((512, 64, 8), 30, 0), ((512, 128, 16), 57, 1), ((256, 64, 3), 11, 2), ((512, 64, 5), 45, 3),
-    ((128, 192, 7), 23, 4), ((16, 64, 2), 5, 5)])
-def test_c2_family_small_full_parity(H, oracle_mod, shape, tracks, eid):
+@pytest.mark.parametrize("shape,tracks,eid,frac", [
+    ((512, 64, 8), 30, 0, 7), ((512, 128, 16), 57, 1, 7), ((256, 64, 3), 11, 2, 7), ((512, 64, 5), 45, 3, 7),
+    ((128, 192, 7), 23, 4, 7), ((16, 64, 2), 5, 5, 7), ((1024, 64, 4), 40, 6, 7),
+    ((512, 64, 8), 30, 0, 8), ((256, 128, 5), 33, 7, 8), ((16, 64, 3), 6, 8, 8)])
+def test_c2_family_small_full_parity(H, oracle_mod, shape, tracks, eid, frac):
+    """frac_bits 7: 16-bit vote counters in LDS, int32 accumulator; 8: 32-bit counters."""
     nphi, nqpt, nd0 = shape
-    cfg = configs.small_variant(configs.C2, n_tracks=tracks, n_phi=nphi, n_qpt=nqpt, n_d0=nd0)
+    cfg = configs.small_variant(configs.C2, n_tracks=tracks, n_phi=nphi, n_qpt=nqpt, n_d0=nd0).with_(frac_bits=frac)
     check_full(H, oracle_mod, cfg, synth.make_event(cfg, eid))
 
 
@@ -222,9 +224,17 @@ def test_capacity_overflow(H, oracle_mod):
 
 
 def test_unsupported_grids_rejected(H):
-    # an int32 slab of 1024 phi0 bins x 64 columns needs 256 KiB of LDS (160 KiB on gfx950)
+    # a vote slab of 64 columns x 1024 phi0 bins of 32-bit counters (frac_bits 8), or of 2048
+    # bins of 16-bit counters (frac_bits 7), needs 256 KiB of LDS (160 KiB on gfx950)
     with pytest.raises(H.HoughError, match="unsupported"):
-        H.Plan(configs.C2.with_(n_phi=1024), max_hits=10)
+        H.Plan(configs.C2.with_(n_phi=1024, frac_bits=8), max_hits=10)
+    with pytest.raises(H.HoughError, match="unsupported"):
+        H.Plan(configs.C2.with_(n_phi=2048), max_hits=10)
+    # 16-bit counters: at most 65535 hits per event (32767 for an int16 accumulator)
+    with pytest.raises(H.HoughError, match="unsupported"):
+        H.Plan(configs.C2, max_hits=65536)
+    with pytest.raises(H.HoughError, match="unsupported"):
+        H.Plan(configs.C2.with_(frac_bits=6), max_hits=10)
     with pytest.raises(H.HoughError, match="unsupported"):
         H.Plan(configs.C2.with_(n_qpt=100), max_hits=10)
     with pytest.raises(H.HoughError, match="unsupported"):

@@ -525,14 +525,16 @@ def test_assign_bruteforce_and_counts(oracle_mod):
 # ------------------------------------------------------------------ zvote --
 def test_angle_bits_reading(oracle_mod):
     """M = log2(n_phi) + frac_bits angle bits (the fixed-point reading of the
-    phi0 binning): 8 bits below a bin on the int32 grids, 7 on the int16 grid.
-    Runs first (alphabetically) so that a wrong M is reported before any vote
-    writes with it."""
+    phi0 binning): 7 bits below a bin on every workload grid.  Runs first
+    (alphabetically) so that a wrong M is reported before any vote writes
+    with it."""
     O = oracle_mod
-    for cfg in (configs.C1, configs.C2, configs.C3, configs.C4):
+    for cfg in (configs.C1, configs.C2, configs.C3, configs.C4, configs.C5):
         g = O.Cfg(cfg)
-        assert O.angle_bits(g) == int(np.log2(cfg.n_phi)) + cfg.frac_bits
-        assert cfg.frac_bits == (8 if cfg.acc_bits == 32 else 7)
+        assert cfg.frac_bits == 7
+        assert O.angle_bits(g) == int(np.log2(cfg.n_phi)) + 7
+    g = O.Cfg(configs.C2.with_(frac_bits=8))
+    assert O.angle_bits(g) == 9 + 8
 
 
 def test_arclen_closed_forms(oracle_mod):
