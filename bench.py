@@ -185,10 +185,11 @@ def bench_large_grid(H, torch, reps: int):
     }
 
 
-def bench_serving(H, torch, duration_s: float, rate_hz: float, pool_size: int = 256):
-    """Streaming trigger serving: Poisson arrivals at rate_hz for duration_s, event sizes as in the
-    batched workload, admitted into device-resident slots within a 64 GiB accumulator budget, continuous
-    batching over concurrent lanes (see paper_1305_4855_amd/serve.py)."""
+def bench_serving(H, torch, runs, pool_size: int = 256):
+    """Streaming trigger serving: for each (rate_hz, duration_s) of `runs`, Poisson arrivals at that
+    rate, event sizes as in the batched workload, admitted into device-resident slots within a
+    64 GiB accumulator budget, continuous batching over concurrent lanes (see
+    paper_1305_4855_amd/serve.py).  One server (slots allocated once) serves every run."""
     from paper_1305_4855_amd import configs, serve, synth, tune
 
     cfg = configs.C5
@@ -200,47 +201,28 @@ def bench_serving(H, torch, duration_s: float, rate_hz: float, pool_size: int = 
     # warm up every lane once
     warm = np.linspace(0.0, 0.01, srv.slots)
     srv.serve(pool, warm, np.arange(len(warm)) % pool_size)
-    arrivals = serve.poisson_arrivals(rate_hz, duration_s)
-    rng = np.random.default_rng([13054855, 5, 1])
-    pool_idx = rng.integers(0, pool_size, size=len(arrivals))
-    print(f"[bench] serving {len(arrivals)} arrivals over {duration_s:.0f} s in {srv.slots} slots", file=sys.stderr,
-          flush=True)
-    stats = srv.serve(pool, arrivals, pool_idx, progress=lambda t, n, q: print(
-        f"[bench] serving t={t:.0f}s served={n} queued={q}", file=sys.stderr, flush=True))
-    stats.update(workload=f"Poisson arrivals at {rate_hz:.0f} Hz for {duration_s:.0f} s, sizes as the batched "
-                          f"workload (pool of {pool_size} distinct events), 64 GiB accumulator budget "
-                          f"({srv.slots} slots in {srv.n_lanes} lanes), 512x256x64 int32",
-                 latency_definition="arrival -> candidate list complete on the device, status and first 64 "
-                                    "candidates on the host")
-    return stats
+    results = []
+    for i, (rate_hz, duration_s) in enumerate(runs):
+        arrivals = serve.poisson_arrivals(rate_hz, duration_s, seed=13054855 + i)
+        rng = np.random.default_rng([13054855, 5, 1 + i])
+        pool_idx = rng.integers(0, pool_size, size=len(arrivals))
+        print(f"[bench] serving {len(arrivals)} arrivals at {rate_hz:.0f} Hz over {duration_s:.0f} s in "
+              f"{srv.slots} slots", file=sys.stderr, flush=True)
+        stats = srv.serve(pool, arrivals, pool_idx, progress=lambda t, n, q: print(
+            f"[bench] serving t={t:.0f}s served={n} queued={q}", file=sys.stderr, flush=True))
+        stats.update(workload=f"Poisson arrivals at {rate_hz:.0f} Hz for {duration_s:.0f} s, sizes as the batched "
+                              f"workload (pool of {pool_size} distinct events), 64 GiB accumulator budget "
+                              f"({srv.slots} slots in {srv.n_lanes} lanes), 512x256x64 int32",
+                     latency_definition="arrival -> candidate list complete on the device, status and first 64 "
+                                        "candidates on the host")
+        results.append(stats)
+    return results
 
 
-def main() -> int:
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=500)
-    ap.add_argument("--warmup", type=int, default=50)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-batched", action="store_true")
-    ap.add_argument("--batch-events", type=int, default=256)
-    ap.add_argument("--no-serving", action="store_true")
-    ap.add_argument("--no-large-grid", action="store_true")
-    ap.add_argument("--serve-seconds", type=float, default=60.0)
-    ap.add_argument("--serve-rate", type=float, default=20000.0)
-    ap.add_argument("--pmc-calibration", action="store_true",
-                    help="also run a plain 256 MiB device copy (for scaling HBM counters)")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for --gpus {args.gpus})",
-              file=sys.stderr)
-        return 2
-
-    import torch
-
+def bench_plain(H, torch, args):
+    """The dense single event (c2), one event per launch chain: prep -> vote -> peaks -> assign."""
     from paper_1305_4855_amd import configs, synth, tune
-    from paper_1305_4855_amd import hough as H
 
-    torch.cuda.set_device(0)
     cfg = configs.C2
     ev = synth.make_event(cfg, 0)
     plan = H.Plan(cfg, max_hits=16384)
@@ -337,16 +319,59 @@ def main() -> int:
                      "frac": round(achieved / LDS_ATOMIC_PEAK_GVOTES, 4), "traffic": traffic,
                      "avg_launch_ms": round(vote_ms, 5), "votes_per_launch": st["n_votes"]},
     }
+    return out
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--batch-events", type=int, default=256)
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-plain", action="store_true", help="skip the single-event section (profiling runs)")
+    ap.add_argument("--no-large-grid", action="store_true")
+    ap.add_argument("--serve-seconds", type=float, default=60.0)
+    ap.add_argument("--serve-rate", type=float, default=20000.0)
+    ap.add_argument("--serve-rate-low", type=float, default=14000.0,
+                    help="a second, short serving run at this rate (0: none)")
+    ap.add_argument("--pmc-calibration", action="store_true",
+                    help="also run a plain 256 MiB device copy (for scaling HBM counters)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for --gpus {args.gpus})",
+              file=sys.stderr)
+        return 2
+
+    import torch
+
+    from paper_1305_4855_amd import hough as H
+
+    torch.cuda.set_device(0)
+    from paper_1305_4855_amd import configs, synth
+    out = {"metric": METRIC, "value": None, "unit": "events/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "int32", "data": "synthetic"}
+    if not args.no_plain:
+        out = bench_plain(H, torch, args)
+        torch.cuda.empty_cache()
     if not args.no_batched:
         out["batched"] = bench_batched(H, torch, args.batch_events, reps=10)
     if not args.no_large_grid:
         out["large_grid"] = bench_large_grid(H, torch, reps=3)
     if not args.no_serving:
-        del bufs
         torch.cuda.empty_cache()
-        out["serving"] = bench_serving(H, torch, args.serve_seconds, args.serve_rate)
+        runs = [(args.serve_rate, args.serve_seconds)]
+        if args.serve_rate_low > 0:
+            runs.append((args.serve_rate_low, min(args.serve_seconds, 10.0)))
+        res = bench_serving(H, torch, runs)
+        out["serving"] = res[0]
+        if len(res) > 1:
+            out["serving_below_capacity"] = res[1]
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(cfg, ev)
+        out["cpu_baseline"] = cpu_baseline(configs.C2, synth.make_event(configs.C2, 0))
     print(json.dumps(out, default=lambda o: o.item() if isinstance(o, np.generic) else str(o)), flush=True)
     return 0
 
