@@ -114,6 +114,7 @@ struct hough_plan {
     int32_t* d_S;    // [n_layers][n_d0][n_qpt] Q16.16 arc length to the layer, -1 = invalid (zvote only)
     hipEvent_t vote_start, vote_stop;  // recorded by every vote launch when set (kernel timing)
     int n_cu;        // compute units of the plan's device
+    void* d_zero;    // one accumulator row of zeros (n_phi x 4 bytes): out-of-grid neighbours
 };
 
 namespace {
@@ -610,12 +611,10 @@ __global__ __launch_bounds__(kVoteMaxThreads) void k_vote(Events ev, const int32
 }
 
 // ------------------------------------------------------------------ peaks
-// One strip of kStrip bins of column (l, k) with its two cyclic edge bins.  (l, k) must be in range:
-// callers clamp and mask afterwards, so that every load is issued unconditionally.
+// One strip of kStrip bins of a column row with its two cyclic edge bins (int16 rows: the 8 bins
+// arrive packed in v[1..4] and are unpacked by finish_plane).
 template <typename T>
-__device__ __forceinline__ void load_strip(const T* __restrict__ acc, int l, int k, int s, int n_qpt, int n_phi,
-                                           int32_t v[kStrip + 2]) {
-    const T* row = acc + ((size_t)l * n_qpt + k) * n_phi;
+__device__ __forceinline__ void load_strip(const T* __restrict__ row, int s, int n_phi, int32_t v[kStrip + 2]) {
     const int b0 = s * kStrip;
     if (sizeof(T) == 4) {
         const uint4 a = *reinterpret_cast<const uint4*>(row + b0);
@@ -624,50 +623,38 @@ __device__ __forceinline__ void load_strip(const T* __restrict__ acc, int l, int
         v[5] = (int32_t)c.x; v[6] = (int32_t)c.y; v[7] = (int32_t)c.z; v[8] = (int32_t)c.w;
     } else {
         const uint4 a = *reinterpret_cast<const uint4*>(row + b0);
-        v[1] = (int32_t)a.x; v[2] = (int32_t)a.y; v[3] = (int32_t)a.z; v[4] = (int32_t)a.w;  // unpacked later
+        v[1] = (int32_t)a.x; v[2] = (int32_t)a.y; v[3] = (int32_t)a.z; v[4] = (int32_t)a.w;
     }
     v[0] = (int32_t)row[(b0 - 1) & (n_phi - 1)];
     v[kStrip + 1] = (int32_t)row[(b0 + kStrip) & (n_phi - 1)];
 }
 
-// Raw loads of one d0 plane (columns k-1, k, k+1) in flight, with the masks to apply once they land.
+// Raw loads of one d0 plane (columns k-1, k, k+1) in flight.  A neighbour outside the grid (d0 plane
+// or q/pT column) is read from a row of zeros: accumulator values are >= 0 and candidates need
+// >= threshold >= 1 votes, so a zero neighbour never decides a comparison, and every load is
+// issued without a branch.
 struct PlaneRaw {
     int32_t a[kStrip + 2], m[kStrip + 2], c[kStrip + 2];
-    bool ok_plane, ok_lo, ok_hi;
 };
 
 template <typename T>
-__device__ __forceinline__ void load_plane_raw(const T* __restrict__ acc, int l, int k, int s, int n_d0, int n_qpt,
-                                               int n_phi, PlaneRaw& r) {
-    r.ok_plane = l >= 0 && l < n_d0;
-    r.ok_lo = k > 0;
-    r.ok_hi = k + 1 < n_qpt;
-    const int lc = min(max(l, 0), n_d0 - 1);
-    load_strip(acc, lc, max(k - 1, 0), s, n_qpt, n_phi, r.a);
-    load_strip(acc, lc, k, s, n_qpt, n_phi, r.m);
-    load_strip(acc, lc, min(k + 1, n_qpt - 1), s, n_qpt, n_phi, r.c);
+__device__ __forceinline__ void load_plane_raw(const T* __restrict__ acc, const T* __restrict__ zero_row, int l,
+                                               int k, int s, int n_d0, int n_qpt, int n_phi, PlaneRaw& r) {
+    const bool ok_plane = l >= 0 && l < n_d0;
+    const T* base = acc + ((size_t)(ok_plane ? l : 0) * n_qpt + k) * n_phi;
+    load_strip(ok_plane && k > 0 ? base - n_phi : zero_row, s, n_phi, r.a);
+    load_strip(ok_plane ? base : zero_row, s, n_phi, r.m);
+    load_strip(ok_plane && k + 1 < n_qpt ? base + n_phi : zero_row, s, n_phi, r.c);
 }
 
 template <typename T>
-__device__ __forceinline__ void unpack_strip(int32_t v[kStrip + 2], bool ok, bool uniform) {
+__device__ __forceinline__ void unpack_strip(int32_t v[kStrip + 2]) {
     if (sizeof(T) == 2) {
         const uint32_t w0 = (uint32_t)v[1], w1 = (uint32_t)v[2], w2 = (uint32_t)v[3], w3 = (uint32_t)v[4];
         v[1] = (int16_t)(w0 & 0xFFFF); v[2] = (int16_t)(w0 >> 16);
         v[3] = (int16_t)(w1 & 0xFFFF); v[4] = (int16_t)(w1 >> 16);
         v[5] = (int16_t)(w2 & 0xFFFF); v[6] = (int16_t)(w2 >> 16);
         v[7] = (int16_t)(w3 & 0xFFFF); v[8] = (int16_t)(w3 >> 16);
-        v[0] = (int16_t)v[0];
-        v[kStrip + 1] = (int16_t)v[kStrip + 1];
-    }
-    if (uniform) {
-        // `ok` is the same for the whole wave (a wave covers one column of one plane): a branch
-        if (!__builtin_amdgcn_readfirstlane((int)ok)) {
-#pragma unroll
-            for (int i = 0; i < kStrip + 2; ++i) v[i] = INT32_MIN;
-        }
-    } else {
-#pragma unroll
-        for (int i = 0; i < kStrip + 2; ++i) v[i] = ok ? v[i] : INT32_MIN;
     }
 }
 
@@ -685,10 +672,10 @@ struct PlaneWin {
 };
 
 template <typename T>
-__device__ __forceinline__ void finish_plane(PlaneRaw& r, PlaneWin& w, bool uniform) {
-    unpack_strip<T>(r.a, r.ok_plane && r.ok_lo, uniform);
-    unpack_strip<T>(r.m, r.ok_plane, uniform);
-    unpack_strip<T>(r.c, r.ok_plane && r.ok_hi, uniform);
+__device__ __forceinline__ void finish_plane(PlaneRaw& r, PlaneWin& w) {
+    unpack_strip<T>(r.a);
+    unpack_strip<T>(r.m);
+    unpack_strip<T>(r.c);
     int32_t m0[kStrip];
 #pragma unroll
     for (int i = 0; i < kStrip + 2; ++i) w.mid[i] = r.m[i];
@@ -708,9 +695,10 @@ constexpr int kMarkThreads = 256;
 
 template <typename T>
 __global__ __launch_bounds__(kMarkThreads) void k_peaks_mark(Events ev, const char* __restrict__ acc_base,
-                                                             size_t acc_stride, int32_t thr, int n_d0, int n_qpt,
-                                                             int n_phi, int group_lanes, int planes,
-                                                             char* __restrict__ ws, WsOff O) {
+                                                             size_t acc_stride, const T* __restrict__ zero_row,
+                                                             int32_t thr, int n_d0, int n_qpt, int n_phi,
+                                                             int group_lanes, int planes, char* __restrict__ ws,
+                                                             WsOff O) {
     __shared__ uint8_t s_flags[kMaxPeakPlanes][kMarkThreads];
     __shared__ int32_t s_cnt[kMaxPeakPlanes][kMarkThreads / 2];
     __shared__ int32_t s_vs[kMaxPeakPlanes][kMarkThreads / 2];
@@ -733,16 +721,16 @@ __global__ __launch_bounds__(kMarkThreads) void k_peaks_mark(Events ev, const ch
     if (l0 >= n_d0) return;  // whole waves exit together (strips * n_qpt is a multiple of 64)
     const int l1 = min(n_d0, l0 + planes);
     PlaneRaw raw;
-    PlaneWin prev, cur, next;
-    load_plane_raw(acc, l0 - 1, k, s, n_d0, n_qpt, n_phi, raw);
-    const bool uniform = strips >= 64;  // then a wave holds one column of one plane
-    finish_plane<T>(raw, prev, uniform);
-    load_plane_raw(acc, l0, k, s, n_d0, n_qpt, n_phi, raw);
-    finish_plane<T>(raw, cur, uniform);
-    load_plane_raw(acc, l0 + 1, k, s, n_d0, n_qpt, n_phi, raw);
-    for (int l = l0; l < l1; ++l) {
-        finish_plane<T>(raw, next, uniform);
-        load_plane_raw(acc, l + 2, k, s, n_d0, n_qpt, n_phi, raw);
+    PlaneWin wa, wb, wc;  // planes l-1, l, l+1 rotate through these (no copies between planes)
+    load_plane_raw(acc, zero_row, l0 - 1, k, s, n_d0, n_qpt, n_phi, raw);
+    finish_plane<T>(raw, wa);
+    load_plane_raw(acc, zero_row, l0, k, s, n_d0, n_qpt, n_phi, raw);
+    finish_plane<T>(raw, wb);
+    load_plane_raw(acc, zero_row, l0 + 1, k, s, n_d0, n_qpt, n_phi, raw);
+    // test plane l (cur) against prev and next, with the loads of plane l + 2 in flight
+    auto test_plane = [&](int l, const PlaneWin& prev, const PlaneWin& cur, PlaneWin& next) {
+        finish_plane<T>(raw, next);
+        load_plane_raw(acc, zero_row, l + 2, k, s, n_d0, n_qpt, n_phi, raw);
         uint32_t bits = 0;
         int32_t vsum = 0;
 #pragma unroll
@@ -768,8 +756,13 @@ __global__ __launch_bounds__(kMarkThreads) void k_peaks_mark(Events ev, const ch
             s_cnt[l - l0][threadIdx.x / group_lanes] = cnt;
             s_vs[l - l0][threadIdx.x / group_lanes] = vsum;
         }
-        prev = cur;
-        cur = next;
+    };
+    for (int l = l0; l < l1; l += 3) {
+        test_plane(l, wa, wb, wc);
+        if (l + 1 >= l1) break;
+        test_plane(l + 1, wb, wc, wa);
+        if (l + 2 >= l1) break;
+        test_plane(l + 2, wc, wa, wb);
     }
     for (int l = l0; l < l1; ++l) {
         const int64_t strip_id = ((int64_t)l * n_qpt + k) * strips + s;
@@ -1463,10 +1456,12 @@ void launch_peaks(const hough_plan* p, const Events& ev, int n_events, const voi
     const dim3 gw((unsigned)((n_strips / wsp + 255) / 256), n_events);
     const char* a = static_cast<const char*>(acc);
     if (p->g.acc_bits == 32)
-        hipLaunchKernelGGL(k_peaks_mark<int32_t>, gm, dim3(kMarkThreads), 0, stream, ev, a, acc_stride, threshold, p->g.n_d0,
+        hipLaunchKernelGGL(k_peaks_mark<int32_t>, gm, dim3(kMarkThreads), 0, stream, ev, a, acc_stride,
+                           static_cast<const int32_t*>(p->d_zero), threshold, p->g.n_d0,
                            p->g.n_qpt, p->g.n_phi, gl, planes, ws, O);
     else
-        hipLaunchKernelGGL(k_peaks_mark<int16_t>, gm, dim3(kMarkThreads), 0, stream, ev, a, acc_stride, threshold, p->g.n_d0,
+        hipLaunchKernelGGL(k_peaks_mark<int16_t>, gm, dim3(kMarkThreads), 0, stream, ev, a, acc_stride,
+                           static_cast<const int16_t*>(p->d_zero), threshold, p->g.n_d0,
                            p->g.n_qpt, p->g.n_phi, gl, planes, ws, O);
     hipLaunchKernelGGL(k_peaks_scan, dim3(1, n_events), dim3(kScanThreads), 0, stream, ev, groups, cap, ws, O, st);
     if (p->g.acc_bits == 32)
@@ -1696,7 +1691,17 @@ int hough_plan_create(const hough_geometry_t* geom, const hough_grid_t* grid, ho
         delete p;
         return HOUGH_E_NOMEM;
     }
+    if (hipMalloc(&p->d_zero, (size_t)g.n_phi * 4) != hipSuccess ||
+        hipMemset(p->d_zero, 0, (size_t)g.n_phi * 4) != hipSuccess) {
+        if (p->d_zero) (void)hipFree(p->d_zero);
+        (void)hipFree(p->d_E);
+        free(E);
+        free(Stab);
+        delete p;
+        return HOUGH_E_NOMEM;
+    }
     if (Stab && hipMalloc(&p->d_S, ntab * sizeof(int32_t)) != hipSuccess) {
+        (void)hipFree(p->d_zero);
         (void)hipFree(p->d_E);
         free(E);
         free(Stab);
@@ -1709,6 +1714,7 @@ int hough_plan_create(const hough_geometry_t* geom, const hough_grid_t* grid, ho
     free(Stab);
     if (ce != hipSuccess) {
         (void)hipFree(p->d_E);
+        (void)hipFree(p->d_zero);
         if (p->d_S) (void)hipFree(p->d_S);
         delete p;
         return HOUGH_E_HIP;
@@ -1728,6 +1734,7 @@ int hough_plan_create(const hough_geometry_t* geom, const hough_grid_t* grid, ho
         ae = hipFuncSetAttribute((const void*)k_zvote, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
     if (ae != hipSuccess) {
         (void)hipFree(p->d_E);
+        (void)hipFree(p->d_zero);
         if (p->d_S) (void)hipFree(p->d_S);
         delete p;
         return HOUGH_E_HIP;
@@ -1740,6 +1747,7 @@ void hough_plan_destroy(hough_plan_t* plan) {
     if (!plan) return;
     if (plan->d_E) (void)hipFree(plan->d_E);
     if (plan->d_S) (void)hipFree(plan->d_S);
+    if (plan->d_zero) (void)hipFree(plan->d_zero);
     delete plan;
 }
 
