@@ -457,7 +457,8 @@ __global__ __launch_bounds__(kVoteMaxThreads) void k_vote(Events ev, const int32
                                                           char* __restrict__ acc_base, size_t acc_stride,
                                                           int n_events, const int32_t* __restrict__ order,
                                                           int32_t* __restrict__ queue, hough_status_t* st_base) {
-    extern __shared__ uint32_t slab[];  // [slab_dwords] counters, then one word for the queue broadcast
+    // LDS: [slab_dwords] counters, the queue broadcast word, then (16-bit slabs) the store tile
+    extern __shared__ uint32_t slab[];
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -574,27 +575,41 @@ __global__ __launch_bounds__(kVoteMaxThreads) void k_vote(Events ev, const int32
                 *reinterpret_cast<uint4*>(acc + (size_t)(col0 + c) * n_phi + 4 * q) = v;
             }
         } else {
-            const int octs = n_phi / 8;
-            for (int i = tid; i < octs * kVoteCols; i += blockDim.x) {
-                const int c = i & 63, q = i >> 6;
-                const int sh = c >= 32 ? 16 : 0;
-                uint32_t wv[8];
-#pragma unroll
-                for (int j = 0; j < 8; ++j) wv[j] = (slab[(8 * q + j) * 32 + (c & 31)] >> sh) & 0xFFFFu;
-                if (OUT16) {
-                    int16_t* acc = reinterpret_cast<int16_t*>(acc_e);
-                    uint4 v;
-                    v.x = wv[0] | (wv[1] << 16);
-                    v.y = wv[2] | (wv[3] << 16);
-                    v.z = wv[4] | (wv[5] << 16);
-                    v.w = wv[6] | (wv[7] << 16);
-                    *reinterpret_cast<uint4*>(acc + (size_t)(col0 + c) * n_phi + 8 * q) = v;
-                } else {
-                    int32_t* acc = reinterpret_cast<int32_t*>(acc_e);
-                    uint4* dst = reinterpret_cast<uint4*>(acc + (size_t)(col0 + c) * n_phi + 8 * q);
-                    dst[0] = make_uint4(wv[0], wv[1], wv[2], wv[3]);
-                    dst[1] = make_uint4(wv[4], wv[5], wv[6], wv[7]);
+            // Tiles of TB bins (a column's share of a tile is one 128-byte line of the accumulator)
+            // go through a padded LDS tile T[64][TB + 1] of 32-bit words: read row by row from the
+            // slab (conflict-free), written back column by column, so that eight lanes store one
+            // column's line and a wave stores eight whole lines per instruction.
+            const int TB = min(OUT16 ? 64 : 32, n_phi);  // n_phi >= 16 is a power of two
+            const int TP = TB + 1;
+            constexpr int CH = OUT16 ? 8 : 4;  // bins per 16-byte store
+            const int NCH = TB / CH;           // stores per column and tile
+            uint32_t* T = slab + slab_dwords + 64;
+            for (int b0 = 0; b0 < n_phi; b0 += TB) {
+                for (int i = tid; i < TB * 32; i += blockDim.x) {
+                    const int r = i >> 5, d = i & 31;
+                    const uint32_t w = slab[(b0 + r) * 32 + d];
+                    T[d * TP + r] = w & 0xFFFFu;
+                    T[(d + 32) * TP + r] = w >> 16;
                 }
+                __syncthreads();
+                for (int i = tid; i < kVoteCols * NCH; i += blockDim.x) {
+                    const int c = i / NCH, p = i % NCH;
+                    const uint32_t* t = T + c * TP + p * CH;
+                    uint4 v;
+                    if (OUT16) {
+                        v.x = t[0] | (t[1] << 16);
+                        v.y = t[2] | (t[3] << 16);
+                        v.z = t[4] | (t[5] << 16);
+                        v.w = t[6] | (t[7] << 16);
+                        int16_t* acc = reinterpret_cast<int16_t*>(acc_e);
+                        *reinterpret_cast<uint4*>(acc + (size_t)(col0 + c) * n_phi + b0 + p * CH) = v;
+                    } else {
+                        v = make_uint4(t[0], t[1], t[2], t[3]);
+                        int32_t* acc = reinterpret_cast<int32_t*>(acc_e);
+                        *reinterpret_cast<uint4*>(acc + (size_t)(col0 + c) * n_phi + b0 + p * CH) = v;
+                    }
+                }
+                __syncthreads();
             }
         }
         if (queue) {
@@ -1413,13 +1428,22 @@ void launch_prep(const hough_plan* p, const Events& ev, int n_events, int max_n,
                            p->cell_bits, p->M, ws, O);
 }
 
+// LDS of one vote workgroup: the slab, the queue word (padded to 256 bytes) and, for 16-bit slabs,
+// the store tile of 64 columns x (TB + 1) words (TB = 64 bins for int16 outputs, 32 for int32).
+size_t vote_lds_bytes(const hough_plan* p) {
+    const size_t slab = (size_t)p->g.n_phi * ((size_t)1 << p->F);
+    if (p->F == 8) return slab + 16;
+    const size_t tb = p->g.acc_bits == 16 ? 64 : 32;
+    return slab + 256 + 64 * (tb + 1) * 4;
+}
+
 void launch_vote(const hough_plan* p, const Events& ev, int n_events, char* ws, const WsOff& O, void* acc,
                  size_t acc_stride, const int32_t* order, int32_t* queue, int grid, hough_status_t* st,
                  hipStream_t stream) {
     int threads = p->tuning.vote_threads;
     char* a = static_cast<char*>(acc);
     const int32_t* E = p->d_E;
-    size_t lds = (size_t)p->g.n_phi * ((size_t)1 << p->F) + 16;
+    size_t lds = vote_lds_bytes(p);
     if (grid <= p->n_cu) {
         // At most one workgroup per CU: the most waves per workgroup, and more than half the LDS
         // so that no CU gets two slabs while another idles (the dispatcher packs what fits).
@@ -1552,8 +1576,12 @@ int hough_plan_create(const hough_geometry_t* geom, const hough_grid_t* grid, ho
     } else {
         return HOUGH_E_UNSUPPORTED;
     }
-    // the slab of one vote workgroup must fit the 160 KiB of LDS
-    if ((size_t)g.n_phi * ((size_t)1 << g.frac_bits) + 16 > (size_t)kLdsBytes) return HOUGH_E_UNSUPPORTED;
+    // the slab of one vote workgroup (and its store tile) must fit the 160 KiB of LDS
+    {
+        const size_t slab = (size_t)g.n_phi * ((size_t)1 << g.frac_bits);
+        const size_t tile = g.frac_bits == 8 ? 0 : 256 + 64 * (size_t)((g.acc_bits == 16 ? 64 : 32) + 1) * 4;
+        if (slab + 16 + tile > (size_t)kLdsBytes) return HOUGH_E_UNSUPPORTED;
+    }
     if (!(g.qpt_max >= g.qpt_min) || !(g.d0_max >= g.d0_min)) return HOUGH_E_INVAL;
     if ((int64_t)g.n_d0 * g.n_qpt * g.n_phi > ((int64_t)1 << 31)) return HOUGH_E_UNSUPPORTED;
     if ((geom->n_layers << (lp < 10 ? lp : 10)) > kMaxCells) return HOUGH_E_UNSUPPORTED;

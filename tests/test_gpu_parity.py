@@ -205,6 +205,37 @@ def test_ragged_hit_counts(H, oracle_mod):
         check_full(H, oracle_mod, cfg, ev, max_hits=n)
 
 
+def test_large_events_take_the_long_paths(H, oracle_mod):
+    """Events beyond what the fast paths hold: more hits than the bucketing keeps in registers
+    (16384), more valid hits than the assignment stages in LDS, more than 65535 hits with 32-bit
+    vote counters (frac_bits 8), and a batch mixing such an event with small ones."""
+    cfg = configs.small_variant(configs.C2, n_phi=256, n_qpt=64, n_d0=2).with_(threshold=30)
+    rng = np.random.default_rng(25)
+    r = np.asarray(configs.RADII_CM)
+    for n, frac in ((30000, 7), (65535, 7), (70000, 8)):
+        lay = rng.integers(0, 10, n).astype(np.uint8)
+        phi = rng.uniform(0, 2 * np.pi, n)
+        ev = _event(r[lay] * np.cos(phi), r[lay] * np.sin(phi), lay)
+        check_full(H, oracle_mod, cfg.with_(frac_bits=frac), ev, max_hits=n, cap_peaks=1 << 16, cap_pairs=1 << 23)
+    n = 30000
+    lay = rng.integers(0, 10, n).astype(np.uint8)
+    phi = rng.uniform(0, 2 * np.pi, n)
+    big = _event(r[lay] * np.cos(phi), r[lay] * np.sin(phi), lay)
+    small = [synth.make_event(cfg.with_(n_tracks=t, track_dist="fixed"), 40 + i) for i, t in enumerate([3, 50])]
+    events = [small[0], big, small[1]]
+    plan = H.Plan(cfg, max_hits=n)
+    bufs = H.BatchBuffers(plan, 3, sum(e.n for e in events), 1 << 16, 1 << 23)
+    bufs.load(events)
+    bufs.run(cfg.threshold)
+    torch.cuda.synchronize()
+    for e, ev in enumerate(events):
+        single = run_gpu(H, cfg, ev, cap_peaks=1 << 16, cap_pairs=1 << 23, plan=plan)
+        got = bufs.results(e)
+        np.testing.assert_array_equal(got["peaks"], single["peaks"])
+        np.testing.assert_array_equal(got["hit_idx"], single["hit_idx"])
+        np.testing.assert_array_equal(bufs.acc[e].cpu().numpy(), single["acc"])
+
+
 def test_capacity_overflow(H, oracle_mod):
     O = oracle_mod
     cfg = configs.small_variant(configs.C2, n_tracks=40, n_phi=256, n_qpt=64, n_d0=8)

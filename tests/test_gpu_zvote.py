@@ -172,3 +172,38 @@ def test_zvote_needs_small_events(H):
     cfg = dataclasses.replace(_small_cfg(), acc_bits=32, frac_bits=8)
     with pytest.raises(H.HoughError, match="unsupported"):
         H.Plan(cfg, max_hits=70000)
+
+
+def test_zvote_in_captured_graph(H):
+    """The batched chain with the r-z stage, captured once in a hipGraph and replayed with eager
+    work and reloads in between, equals the eager chain every time."""
+    cfg = _small_cfg()
+    sets = [[synth.make_event(cfg.with_(n_tracks=nt, track_dist="fixed"), 60 + 10 * r + i)
+             for i, nt in enumerate([25, 4, 70])] for r in range(2)]
+    plan = H.Plan(cfg, max_hits=4096)
+    cap_peaks, cap_pairs = 1 << 15, 1 << 19
+    n_max = max(sum(e.n for e in evs) for evs in sets)
+    bufs = H.BatchBuffers(plan, 3, n_max, cap_peaks, cap_pairs)
+    refs = []
+    for evs in sets:
+        bufs.load(evs)
+        bufs.run(cfg.threshold)
+        torch.cuda.synchronize()
+        refs.append([bufs.results(e) for e in range(3)])
+    stream = torch.cuda.Stream()
+    graph = H.Graph(bufs, cfg.threshold, stream)
+    for rep in range(4):
+        junk = torch.randn(1 << 18, device="cuda").sum()
+        torch.cuda.synchronize()
+        bufs.load(sets[rep % 2])
+        bufs.zv.fill_(-9)
+        bufs.status.fill_(-7)
+        torch.cuda.synchronize()
+        graph.launch(stream)
+        stream.synchronize()
+        for e in range(3):
+            got, ref = bufs.results(e), refs[rep % 2][e]
+            np.testing.assert_array_equal(got["peaks"], ref["peaks"])
+            np.testing.assert_array_equal(got["zvote"], ref["zvote"])
+        del junk
+    graph.close()
