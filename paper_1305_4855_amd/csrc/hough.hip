@@ -626,51 +626,85 @@ __global__ __launch_bounds__(kVoteMaxThreads) void k_vote(Events ev, const int32
 }
 
 // ------------------------------------------------------------------ peaks
-// One strip of kStrip bins of a column row with its two cyclic edge bins (int16 rows: the 8 bins
-// arrive packed in v[1..4] and are unpacked by finish_plane).
+// The cyclic phi0 neighbours of a strip (its edge bins) are the last bin of the strip before and
+// the first bin of the strip after.  Consecutive lanes hold consecutive strips of a row, so the
+// edge bins come from neighbouring lanes (ds_bpermute) instead of two narrow loads per row; only
+// when a row is wider than a wave (more than 64 strips) do its first and last lanes load the
+// bin beyond the wave from memory.
+struct EdgeLanes {
+    int left4, right4;  // byte addresses (lane * 4) of the lanes holding strips s-1 and s+1
+    bool mem_l, mem_r;  // this lane loads its left / right edge bin from memory
+};
+
+__device__ __forceinline__ EdgeLanes edge_lanes(int strips) {
+    const int lane = threadIdx.x & 63;
+    const int g = strips < 64 ? strips : 64;  // strips of one row inside a wave (powers of two)
+    const int row0 = lane & ~(g - 1);
+    EdgeLanes e;
+    e.left4 = (row0 | ((lane - 1) & (g - 1))) * 4;
+    e.right4 = (row0 | ((lane + 1) & (g - 1))) * 4;
+    e.mem_l = strips > 64 && lane == 0;
+    e.mem_r = strips > 64 && lane == 63;
+    return e;
+}
+
+// One strip of kStrip bins of a column row as 32-bit words (int16 rows: two bins per word); with
+// rows wider than a wave (WIDE), the first and last lanes also load their outer edge bin.
 template <typename T>
-__device__ __forceinline__ void load_strip(const T* __restrict__ row, int s, int n_phi, int32_t v[kStrip + 2]) {
+struct PlaneRaw {
+    static constexpr int kW = sizeof(T) == 4 ? kStrip : kStrip / 2;
+    uint32_t a[kW], m[kW], c[kW];  // columns k-1, k, k+1
+    int32_t ea[2], em[2], ec[2];   // edge bins from memory (WIDE only)
+};
+
+template <typename T, bool WIDE>
+__device__ __forceinline__ void load_strip(const T* __restrict__ row, int s, int n_phi, const EdgeLanes& el,
+                                           uint32_t (&w)[PlaneRaw<T>::kW], int32_t (&e)[2]) {
     const int b0 = s * kStrip;
+    const uint4 x = *reinterpret_cast<const uint4*>(row + b0);
+    w[0] = x.x; w[1] = x.y; w[2] = x.z; w[3] = x.w;
     if (sizeof(T) == 4) {
-        const uint4 a = *reinterpret_cast<const uint4*>(row + b0);
-        const uint4 c = *reinterpret_cast<const uint4*>(row + b0 + 4);
-        v[1] = (int32_t)a.x; v[2] = (int32_t)a.y; v[3] = (int32_t)a.z; v[4] = (int32_t)a.w;
-        v[5] = (int32_t)c.x; v[6] = (int32_t)c.y; v[7] = (int32_t)c.z; v[8] = (int32_t)c.w;
-    } else {
-        const uint4 a = *reinterpret_cast<const uint4*>(row + b0);
-        v[1] = (int32_t)a.x; v[2] = (int32_t)a.y; v[3] = (int32_t)a.z; v[4] = (int32_t)a.w;
+        const uint4 y = *reinterpret_cast<const uint4*>(row + b0 + 4);
+        w[4 % PlaneRaw<T>::kW] = y.x; w[5 % PlaneRaw<T>::kW] = y.y;
+        w[6 % PlaneRaw<T>::kW] = y.z; w[7 % PlaneRaw<T>::kW] = y.w;
     }
-    v[0] = (int32_t)row[(b0 - 1) & (n_phi - 1)];
-    v[kStrip + 1] = (int32_t)row[(b0 + kStrip) & (n_phi - 1)];
+    if (WIDE) {
+        e[0] = 0;
+        e[1] = 0;
+        if (el.mem_l) e[0] = (int32_t)row[(b0 - 1) & (n_phi - 1)];
+        if (el.mem_r) e[1] = (int32_t)row[(b0 + kStrip) & (n_phi - 1)];
+    }
+}
+
+// The strip's bins v[1..8] and its edge bins v[0], v[9] (from the neighbouring lanes; every lane
+// of the wave is active).
+template <typename T, bool WIDE>
+__device__ __forceinline__ void row_values(const uint32_t (&w)[PlaneRaw<T>::kW], const int32_t (&e)[2],
+                                           const EdgeLanes& el, int32_t v[kStrip + 2]) {
+#pragma unroll
+    for (int i = 0; i < kStrip; ++i) {
+        if (sizeof(T) == 4) v[i + 1] = (int32_t)w[i % PlaneRaw<T>::kW];
+        else v[i + 1] = (int32_t)(int16_t)(w[(i >> 1) % PlaneRaw<T>::kW] >> (16 * (i & 1)));
+    }
+    const int l = __builtin_amdgcn_ds_bpermute(el.left4, v[kStrip]);
+    const int r = __builtin_amdgcn_ds_bpermute(el.right4, v[1]);
+    v[0] = WIDE && el.mem_l ? e[0] : l;
+    v[kStrip + 1] = WIDE && el.mem_r ? e[1] : r;
 }
 
 // Raw loads of one d0 plane (columns k-1, k, k+1) in flight.  A neighbour outside the grid (d0 plane
 // or q/pT column) is read from a row of zeros: accumulator values are >= 0 and candidates need
 // >= threshold >= 1 votes, so a zero neighbour never decides a comparison, and every load is
 // issued without a branch.
-struct PlaneRaw {
-    int32_t a[kStrip + 2], m[kStrip + 2], c[kStrip + 2];
-};
-
-template <typename T>
+template <typename T, bool WIDE>
 __device__ __forceinline__ void load_plane_raw(const T* __restrict__ acc, const T* __restrict__ zero_row, int l,
-                                               int k, int s, int n_d0, int n_qpt, int n_phi, PlaneRaw& r) {
+                                               int k, int s, int n_d0, int n_qpt, int n_phi, const EdgeLanes& el,
+                                               PlaneRaw<T>& r) {
     const bool ok_plane = l >= 0 && l < n_d0;
     const T* base = acc + ((size_t)(ok_plane ? l : 0) * n_qpt + k) * n_phi;
-    load_strip(ok_plane && k > 0 ? base - n_phi : zero_row, s, n_phi, r.a);
-    load_strip(ok_plane ? base : zero_row, s, n_phi, r.m);
-    load_strip(ok_plane && k + 1 < n_qpt ? base + n_phi : zero_row, s, n_phi, r.c);
-}
-
-template <typename T>
-__device__ __forceinline__ void unpack_strip(int32_t v[kStrip + 2]) {
-    if (sizeof(T) == 2) {
-        const uint32_t w0 = (uint32_t)v[1], w1 = (uint32_t)v[2], w2 = (uint32_t)v[3], w3 = (uint32_t)v[4];
-        v[1] = (int16_t)(w0 & 0xFFFF); v[2] = (int16_t)(w0 >> 16);
-        v[3] = (int16_t)(w1 & 0xFFFF); v[4] = (int16_t)(w1 >> 16);
-        v[5] = (int16_t)(w2 & 0xFFFF); v[6] = (int16_t)(w2 >> 16);
-        v[7] = (int16_t)(w3 & 0xFFFF); v[8] = (int16_t)(w3 >> 16);
-    }
+    load_strip<T, WIDE>(ok_plane && k > 0 ? base - n_phi : zero_row, s, n_phi, el, r.a, r.ea);
+    load_strip<T, WIDE>(ok_plane ? base : zero_row, s, n_phi, el, r.m, r.em);
+    load_strip<T, WIDE>(ok_plane && k + 1 < n_qpt ? base + n_phi : zero_row, s, n_phi, el, r.c, r.ec);
 }
 
 // 3-wide maxima along phi0 of a strip with its two edge bins: m[i] = max(v[i], v[i+1], v[i+2])
@@ -686,17 +720,15 @@ struct PlaneWin {
     int32_t all[kStrip];      // 3x3 max over columns k-1..k+1
 };
 
-template <typename T>
-__device__ __forceinline__ void finish_plane(PlaneRaw& r, PlaneWin& w) {
-    unpack_strip<T>(r.a);
-    unpack_strip<T>(r.m);
-    unpack_strip<T>(r.c);
-    int32_t m0[kStrip];
-#pragma unroll
-    for (int i = 0; i < kStrip + 2; ++i) w.mid[i] = r.m[i];
-    max3(r.a, w.lo);
-    max3(r.m, m0);
-    max3(r.c, w.hi);
+template <typename T, bool WIDE>
+__device__ __forceinline__ void finish_plane(const PlaneRaw<T>& r, const EdgeLanes& el, PlaneWin& w) {
+    int32_t v[kStrip + 2], m0[kStrip];
+    row_values<T, WIDE>(r.a, r.ea, el, v);
+    max3(v, w.lo);
+    row_values<T, WIDE>(r.c, r.ec, el, v);
+    max3(v, w.hi);
+    row_values<T, WIDE>(r.m, r.em, el, w.mid);
+    max3(w.mid, m0);
 #pragma unroll
     for (int i = 0; i < kStrip; ++i) w.all[i] = max(max(w.lo[i], m0[i]), w.hi[i]);
 }
@@ -705,10 +737,10 @@ __device__ __forceinline__ void finish_plane(PlaneRaw& r, PlaneWin& w) {
 // the planes l-1, l, l+1 reduced in registers and the loads of plane l+2 in flight.  Its outputs
 // (flag bytes, group sums) are kept in LDS and stored after the walk: a global store inside the
 // walk would make every wait for the next plane's loads also wait for that store.
-constexpr int kMaxPeakPlanes = 16;
+constexpr int kMaxPeakPlanes = 32;
 constexpr int kMarkThreads = 256;
 
-template <typename T>
+template <typename T, bool WIDE>
 __global__ __launch_bounds__(kMarkThreads) void k_peaks_mark(Events ev, const char* __restrict__ acc_base,
                                                              size_t acc_stride, const T* __restrict__ zero_row,
                                                              int32_t thr, int n_d0, int n_qpt, int n_phi,
@@ -735,17 +767,18 @@ __global__ __launch_bounds__(kMarkThreads) void k_peaks_mark(Events ev, const ch
     const int l0 = lr * planes;
     if (l0 >= n_d0) return;  // whole waves exit together (strips * n_qpt is a multiple of 64)
     const int l1 = min(n_d0, l0 + planes);
-    PlaneRaw raw;
+    PlaneRaw<T> raw;
     PlaneWin wa, wb, wc;  // planes l-1, l, l+1 rotate through these (no copies between planes)
-    load_plane_raw(acc, zero_row, l0 - 1, k, s, n_d0, n_qpt, n_phi, raw);
-    finish_plane<T>(raw, wa);
-    load_plane_raw(acc, zero_row, l0, k, s, n_d0, n_qpt, n_phi, raw);
-    finish_plane<T>(raw, wb);
-    load_plane_raw(acc, zero_row, l0 + 1, k, s, n_d0, n_qpt, n_phi, raw);
+    const EdgeLanes el = edge_lanes(strips);
+    load_plane_raw<T, WIDE>(acc, zero_row, l0 - 1, k, s, n_d0, n_qpt, n_phi, el, raw);
+    finish_plane<T, WIDE>(raw, el, wa);
+    load_plane_raw<T, WIDE>(acc, zero_row, l0, k, s, n_d0, n_qpt, n_phi, el, raw);
+    finish_plane<T, WIDE>(raw, el, wb);
+    load_plane_raw<T, WIDE>(acc, zero_row, l0 + 1, k, s, n_d0, n_qpt, n_phi, el, raw);
     // test plane l (cur) against prev and next, with the loads of plane l + 2 in flight
     auto test_plane = [&](int l, const PlaneWin& prev, const PlaneWin& cur, PlaneWin& next) {
-        finish_plane<T>(raw, next);
-        load_plane_raw(acc, zero_row, l + 2, k, s, n_d0, n_qpt, n_phi, raw);
+        finish_plane<T, WIDE>(raw, el, next);
+        load_plane_raw<T, WIDE>(acc, zero_row, l + 2, k, s, n_d0, n_qpt, n_phi, el, raw);
         uint32_t bits = 0;
         int32_t vsum = 0;
 #pragma unroll
@@ -794,6 +827,7 @@ __global__ __launch_bounds__(kMarkThreads) void k_peaks_mark(Events ev, const ch
 // number of listed candidates into `misc`.  Each thread owns kPScanPer consecutive groups (vector
 // loads and stores); the next tile's loads are issued before the current tile is scanned.
 constexpr int kPScanPer = 8;
+constexpr int kPScanThreads = 512;  // (1024 would cap the registers at 128 and spill)
 
 __device__ __forceinline__ void load_groups(const int32_t* __restrict__ src, int64_t i0, int64_t n,
                                             int32_t (&v)[kPScanPer]) {
@@ -813,11 +847,11 @@ __device__ __forceinline__ void load_groups(const int32_t* __restrict__ src, int
     }
 }
 
-__global__ __launch_bounds__(kScanThreads) void k_peaks_scan(Events ev, int64_t n_groups, int32_t cap,
+__global__ __launch_bounds__(kPScanThreads) void k_peaks_scan(Events ev, int64_t n_groups, int32_t cap,
                                                              char* __restrict__ ws, WsOff O,
                                                              hough_status_t* __restrict__ st_base) {
-    __shared__ int64_t wsum_c[kScanThreads / 64];
-    __shared__ int64_t wsum_v[kScanThreads / 64];
+    __shared__ int64_t wsum_c[kPScanThreads / 64];
+    __shared__ int64_t wsum_v[kPScanThreads / 64];
     const int e = blockIdx.y;
     char* w = event_ws(ws, ev, e);
     const int32_t* grp_count = at<int32_t>(w, O.grp_count);
@@ -828,7 +862,7 @@ __global__ __launch_bounds__(kScanThreads) void k_peaks_scan(Events ev, int64_t 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wv = tid >> 6;
-    constexpr int64_t tile = (int64_t)kScanThreads * kPScanPer;
+    constexpr int64_t tile = (int64_t)kPScanThreads * kPScanPer;
     int64_t carry_c = 0, carry_v = 0;
     int32_t c[kPScanPer], v[kPScanPer];
     load_groups(grp_count, (int64_t)tid * kPScanPer, n_groups, c);
@@ -860,7 +894,7 @@ __global__ __launch_bounds__(kScanThreads) void k_peaks_scan(Events ev, int64_t 
         __syncthreads();
         int64_t pc = 0, pv = 0, tc = 0, tv = 0;
 #pragma unroll
-        for (int k = 0; k < kScanThreads / 64; ++k) {
+        for (int k = 0; k < kPScanThreads / 64; ++k) {
             const int64_t a = wsum_c[k], b = wsum_v[k];
             pc += k < wv ? a : 0;
             pv += k < wv ? b : 0;
@@ -1026,9 +1060,7 @@ __device__ __forceinline__ void assign_candidate(const hough_peak_t& pk, int64_t
 #pragma unroll
     for (int L = 0; L < kMaxLayers; ++L) ev_l[L] = L < n_layers ? Ec[(size_t)L * n_cols] : INT32_MIN;
     int64_t wpos = off;
-#pragma unroll
-    for (int L = 0; L < kMaxLayers; ++L) {
-        if (L >= n_layers || wpos >= cap_pairs) break;
+    for (int L = 0; L < n_layers && wpos < cap_pairs; ++L) {
         if (ev_l[L] == INT32_MIN) continue;
         const uint32_t lo = ((uint32_t)ev_l[L] + ((uint32_t)pk.b << F)) & (span - 1u);
         const uint32_t hi = lo + W;  // may exceed 2^M: the window wraps
@@ -1039,20 +1071,66 @@ __device__ __forceinline__ void assign_candidate(const hough_peak_t& pk, int64_t
         const int q = cell_lower_bound<SCAN8>(cs, (int)(lo >> cshift), sorted_phi, lo);
         const uint32_t he = hi <= span ? hi : span;
         const int z = he < span ? cell_lower_bound<SCAN8>(cs, (int)(he >> cshift), sorted_phi, he) : lay_end;
-        int r = -1, z2 = -1;
+        int r = 0, z2 = 0;
         if (hi > span) {
             const uint32_t hw = hi - span;
             r = cs[0];
             z2 = cell_lower_bound<SCAN8>(cs, (int)(hw >> cshift), sorted_phi, hw);
         }
+        // copy the run(s) four entries at a time: the four loads go out before the four stores
         for (int seg = 0; seg < 2; ++seg) {
             const int a0 = seg == 0 ? q : r;
             const int a1 = seg == 0 ? z : z2;
-            for (int j = a0; j < a1 && wpos < cap_pairs; ++j, ++wpos) {
-                const int32_t h = sorted_h[j];
-                const int64_t rel = wpos - o0;
-                if (rel < buf_words) buf[rel] = h;
-                else hit_idx[wpos] = h;
+            for (int j = a0; j < a1; j += 4) {
+                int32_t h[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) h[u] = sorted_h[min(j + u, a1 - 1)];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int64_t wp = wpos + (j - a0) + u;
+                    if (j + u < a1 && wp < cap_pairs) {
+                        const int64_t rel = wp - o0;
+                        if (rel < buf_words) buf[rel] = h[u];
+                        else hit_idx[wp] = h[u];
+                    }
+                }
+            }
+            wpos += a1 > a0 ? a1 - a0 : 0;
+        }
+    }
+}
+
+// Copies the cell table (nc words) and, when staged, the event's sorted angles and hit indices
+// (nh words each) from global memory to LDS, 16 bytes per load, with all of a thread's loads of a
+// round issued before its first store (a load-then-store loop would wait on memory once per
+// element).  Sources and destinations are 16-byte aligned; a source is read up to the next
+// multiple of four words (inside its 256-byte padded workspace array).
+constexpr int kStageUnroll = 8;  // 16-byte loads per thread and round: 128 KiB per round at 1024 threads
+
+__device__ __forceinline__ void assign_stage(int32_t* d_cells, const int32_t* __restrict__ g_cells, int nc,
+                                             uint32_t* d_phi, const uint32_t* __restrict__ g_phi,
+                                             int32_t* d_h, const int32_t* __restrict__ g_h, int nh, int tid) {
+    const int c4 = (nc + 3) >> 2;
+    const int h4 = (nh + 3) >> 2;
+    const int total = c4 + 2 * h4;
+    for (int r0 = tid; r0 < total; r0 += kStageUnroll * kAssignThreads) {
+        uint4 v[kStageUnroll];
+#pragma unroll
+        for (int u = 0; u < kStageUnroll; ++u) {
+            const int c = min(r0 + u * kAssignThreads, total - 1);
+            const uint4* src = c < c4 ? reinterpret_cast<const uint4*>(g_cells) + c
+                             : c < c4 + h4 ? reinterpret_cast<const uint4*>(g_phi) + (c - c4)
+                                           : reinterpret_cast<const uint4*>(g_h) + (c - c4 - h4);
+            v[u] = *src;
+        }
+#pragma unroll
+        for (int u = 0; u < kStageUnroll; ++u) {
+            const int c = r0 + u * kAssignThreads;
+            if (c < total) {
+                uint4* dst = c < c4 ? reinterpret_cast<uint4*>(d_cells) + c
+                           : c < c4 + h4 ? reinterpret_cast<uint4*>(d_phi) + (c - c4)
+                                         : reinterpret_cast<uint4*>(d_h) + (c - c4 - h4);
+                *dst = v[u];
             }
         }
     }
@@ -1063,13 +1141,15 @@ __device__ __forceinline__ void assign_candidate(const hough_peak_t& pk, int64_t
 // candidates of a wave own one contiguous stretch of the CSR list: it is assembled in an LDS
 // buffer of the wave and then written with coalesced stores.  The cell table and, when they fit
 // (stage_hits), the event's sorted angles and hit indices are staged in LDS, so the scans and
-// copies do not wait on memory; the per-layer sample values of a candidate are loaded together.
+// copies do not wait on memory; the per-layer sample values of a candidate are loaded together,
+// and a wave's next 64 candidates are loaded while it works on the current ones.
 __global__ __launch_bounds__(kAssignThreads) void k_assign_fill(
     Events ev, const hough_peak_t* __restrict__ peaks_base, int32_t peak_stride, int32_t cap_peaks,
     hough_status_t* __restrict__ st_base, const int32_t* __restrict__ E, int n_layers, int cell_bits, int n_cols,
     int n_qpt, int M, int F, char* __restrict__ ws, WsOff O, int32_t* __restrict__ offsets_base,
-    int32_t* __restrict__ hit_idx_base, int32_t cap_pairs, int buf_words, int stage_hits) {
-    // LDS: [waves][buf_words] buffers, the cell table, then [stage_hits] angles and hit indices
+    int32_t* __restrict__ hit_idx_base, int32_t cap_pairs, int buf_words, int cells_words, int stage_hits) {
+    // LDS: [waves][buf_words] buffers, the cell table (cells_words), then [stage_hits] angles and
+    // [stage_hits] hit indices; every part starts on a 16-byte boundary
     extern __shared__ int32_t sm_i32[];
     const int e = blockIdx.y;
     char* w = event_ws(ws, ev, e);
@@ -1095,35 +1175,44 @@ __global__ __launch_bounds__(kAssignThreads) void k_assign_fill(
     const int n_cells = n_layers << cell_bits;
     int32_t* buf = sm_i32 + wave * buf_words;
     int32_t* cell_start = sm_i32 + (kAssignThreads / 64) * buf_words;
-    uint32_t* s_phi = reinterpret_cast<uint32_t*>(cell_start + n_cells + 1);
-    int32_t* s_h = cell_start + n_cells + 1 + stage_hits;
-    for (int i = tid; i <= n_cells; i += kAssignThreads) cell_start[i] = g_cell_start[i];
+    uint32_t* s_phi = reinterpret_cast<uint32_t*>(cell_start + cells_words);
+    int32_t* s_h = cell_start + cells_words + stage_hits;
     const int n_valid = g_cell_start[n_cells];
     const bool staged = n_valid <= stage_hits;
-    if (staged) {
-        for (int i = tid; i < n_valid; i += kAssignThreads) {
-            s_phi[i] = sorted_phi[i];
-            s_h[i] = sorted_h[i];
-        }
+    const int stride = gridDim.x * kAssignThreads;
+    int base = blockIdx.x * kAssignThreads + wave * 64;
+    // the wave's first candidates: their loads overlap the staging
+    hough_peak_t pk{};
+    int64_t off = 0;
+    if (base < n) {
+        const int i = min(base + lane, n - 1);
+        pk = peaks[i];
+        off = peak_voff[i];
     }
+    assign_stage(cell_start, g_cell_start, n_cells + 1, s_phi, sorted_phi, s_h, sorted_h, staged ? n_valid : 0, tid);
     __syncthreads();
-    for (int base = blockIdx.x * kAssignThreads + wave * 64; base < n; base += gridDim.x * kAssignThreads) {
+    for (; base < n; base += stride) {
         const int i = base + lane;
-        // the wave's stretch of the list: [o0, o1)
         const int last = min(n, base + 64) - 1;
-        const int64_t o0 = peak_voff[base];
-        const int64_t o1 = peak_voff[last] + peaks[last].votes;
+        // the wave's stretch of the list, [o0, o1): from the first and last lanes' candidates
+        const int64_t o0 = __shfl(off, 0, 64);
+        const int64_t o1 = __shfl(off, last - base, 64) + __shfl(pk.votes, last - base, 64);
+        const hough_peak_t cur = pk;
+        const int64_t cur_off = off;
+        if (base + stride < n) {  // the wave's next candidates (wave-uniform)
+            const int i2 = min(base + stride + lane, n - 1);
+            pk = peaks[i2];
+            off = peak_voff[i2];
+        }
         if (i < n) {
-            const int64_t off = peak_voff[i];
-            offsets[i] = (int32_t)min(off, (int64_t)INT32_MAX);
-            const hough_peak_t pk = peaks[i];
-            const int32_t* Ec = E + (size_t)pk.l * n_qpt + pk.k;
+            offsets[i] = (int32_t)min(cur_off, (int64_t)INT32_MAX);
+            const int32_t* Ec = E + (size_t)cur.l * n_qpt + cur.k;
             if (staged)
-                assign_candidate<true>(pk, off, o0, Ec, n_layers, cell_bits, n_cols, M, F, cell_start,
+                assign_candidate<true>(cur, cur_off, o0, Ec, n_layers, cell_bits, n_cols, M, F, cell_start,
                                        (lds_cu32*)s_phi, (lds_ci32*)s_h, buf, buf_words, hit_idx, cap_pairs);
             else
-                assign_candidate<false>(pk, off, o0, Ec, n_layers, cell_bits, n_cols, M, F, cell_start, sorted_phi,
-                                        sorted_h, buf, buf_words, hit_idx, cap_pairs);
+                assign_candidate<false>(cur, cur_off, o0, Ec, n_layers, cell_bits, n_cols, M, F, cell_start,
+                                        sorted_phi, sorted_h, buf, buf_words, hit_idx, cap_pairs);
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
@@ -1470,24 +1559,37 @@ void launch_peaks(const hough_plan* p, const Events& ev, int n_events, const voi
                   hough_status_t* st, hipStream_t stream) {
     const int strips = p->g.n_phi / kStrip;
     const int gl = peak_group_lanes(p);
-    const int planes = p->tuning.peak_planes;
+    // fewer planes per thread when the launch would leave CUs without a workgroup (a small batch)
+    int planes = p->tuning.peak_planes;
+    auto mark_blocks = [&](int pl) {
+        return ((int64_t)strips * p->g.n_qpt * ((p->g.n_d0 + pl - 1) / pl) + kMarkThreads - 1) / kMarkThreads;
+    };
+    while (planes > 1 && mark_blocks(planes) * n_events < p->n_cu) planes = (planes + 1) / 2;
     const int lranges = (p->g.n_d0 + planes - 1) / planes;
     const int64_t mark_threads = (int64_t)strips * p->g.n_qpt * lranges;
     const int64_t n_strips = p->n_bins / kStrip;
     const int64_t groups = peak_groups(p);
-    const dim3 gm((unsigned)(((mark_threads + 255) / 256 + 7) / 8 * 8), n_events);  // multiple of 8: see k_peaks_mark
+    const dim3 gm((unsigned)(((mark_threads + kMarkThreads - 1) / kMarkThreads + 7) / 8 * 8), n_events);  // multiple of 8: see k_peaks_mark
     const int wsp = gl < kWriteStrips ? gl : kWriteStrips;
     const dim3 gw((unsigned)((n_strips / wsp + 255) / 256), n_events);
     const char* a = static_cast<const char*>(acc);
-    if (p->g.acc_bits == 32)
-        hipLaunchKernelGGL(k_peaks_mark<int32_t>, gm, dim3(kMarkThreads), 0, stream, ev, a, acc_stride,
-                           static_cast<const int32_t*>(p->d_zero), threshold, p->g.n_d0,
-                           p->g.n_qpt, p->g.n_phi, gl, planes, ws, O);
+    const int16_t* z16 = static_cast<const int16_t*>(p->d_zero);
+    const int32_t* z32 = static_cast<const int32_t*>(p->d_zero);
+    const int nd = p->g.n_d0, nq = p->g.n_qpt, nph = p->g.n_phi;
+    const dim3 mb(kMarkThreads);
+    if (p->g.acc_bits == 32 && strips > 64)
+        hipLaunchKernelGGL((k_peaks_mark<int32_t, true>), gm, mb, 0, stream, ev, a, acc_stride, z32, threshold, nd,
+                           nq, nph, gl, planes, ws, O);
+    else if (p->g.acc_bits == 32)
+        hipLaunchKernelGGL((k_peaks_mark<int32_t, false>), gm, mb, 0, stream, ev, a, acc_stride, z32, threshold, nd,
+                           nq, nph, gl, planes, ws, O);
+    else if (strips > 64)
+        hipLaunchKernelGGL((k_peaks_mark<int16_t, true>), gm, mb, 0, stream, ev, a, acc_stride, z16, threshold, nd,
+                           nq, nph, gl, planes, ws, O);
     else
-        hipLaunchKernelGGL(k_peaks_mark<int16_t>, gm, dim3(kMarkThreads), 0, stream, ev, a, acc_stride,
-                           static_cast<const int16_t*>(p->d_zero), threshold, p->g.n_d0,
-                           p->g.n_qpt, p->g.n_phi, gl, planes, ws, O);
-    hipLaunchKernelGGL(k_peaks_scan, dim3(1, n_events), dim3(kScanThreads), 0, stream, ev, groups, cap, ws, O, st);
+        hipLaunchKernelGGL((k_peaks_mark<int16_t, false>), gm, mb, 0, stream, ev, a, acc_stride, z16, threshold, nd,
+                           nq, nph, gl, planes, ws, O);
+    hipLaunchKernelGGL(k_peaks_scan, dim3(1, n_events), dim3(kPScanThreads), 0, stream, ev, groups, cap, ws, O, st);
     if (p->g.acc_bits == 32)
         hipLaunchKernelGGL(k_peaks_write<int32_t>, gw, dim3(256), 0, stream, ev, a, acc_stride, groups, p->g.n_qpt,
                            p->g.n_phi, gl, n_strips, ws, O, peaks, cap);
@@ -1502,16 +1604,18 @@ void launch_assign(const hough_plan* p, const Events& ev, int n_events, const ho
     const int64_t want = ((int64_t)cap_peaks + kAssignThreads - 1) / kAssignThreads;
     const int per_event_cap = n_events > 1 ? 64 : 2 * 256;
     const unsigned nblk = (unsigned)(want < per_event_cap ? want : per_event_cap);
-    const size_t cells_bytes = 4 * ((size_t)p->n_cells + 1);
+    // LDS: per-wave list buffers, the cell table, then the staged sorted hits (8 bytes each) in
+    // what is left; every part a multiple of 16 bytes
+    const int cells_words = (p->n_cells + 1 + 3) & ~3;
+    const size_t cells_bytes = 4 * (size_t)cells_words;
     int buf_words = (int)((kLdsBytes - cells_bytes) / 4 / (kAssignThreads / 64)) & ~63;
     buf_words = buf_words > kAssignBufMax ? kAssignBufMax : buf_words;
-    // the rest of the LDS stages the event's sorted hits (8 bytes each) when they fit
     const size_t used = 4 * (size_t)(kAssignThreads / 64) * buf_words + cells_bytes;
-    const int stage_hits = used < (size_t)kLdsBytes ? (int)(((size_t)kLdsBytes - used) / 8) : 0;
+    const int stage_hits = used < (size_t)kLdsBytes ? (int)(((size_t)kLdsBytes - used) / 8) & ~3 : 0;
     const size_t lds = used + 8 * (size_t)stage_hits;
     hipLaunchKernelGGL(k_assign_fill, dim3(nblk, n_events), dim3(kAssignThreads), lds, stream, ev, peaks, peak_stride,
                        cap_peaks, st, p->d_E, p->n_layers, p->cell_bits, p->n_cols, p->g.n_qpt, p->M, p->F, ws, O,
-                       offsets, hit_idx, cap_pairs, buf_words, stage_hits);
+                       offsets, hit_idx, cap_pairs, buf_words, cells_words, stage_hits);
 }
 
 void launch_zvote(const hough_plan* p, const Events& ev, int n_events, const float* z, const uint8_t* layer,

@@ -19,7 +19,7 @@ import time
 HERE = os.path.dirname(os.path.abspath(__file__))
 CACHE = os.path.join(HERE, "tuning_cache.json")
 
-CANDIDATES = dict(vote_threads=(512, 1024), vote_grid=(256, 512, 1024), peak_planes=(4, 8, 16))
+CANDIDATES = dict(vote_threads=(512, 1024), vote_grid=(256, 512, 1024), peak_planes=(8, 16, 32))
 
 
 def cache_key(cfg, arch: str) -> str:

@@ -92,7 +92,7 @@ def test_batch_event_too_large_is_flagged(H):
 
 
 def test_batch_full_grid_uneven_events(H, oracle_mod):
-    """Sixteen events of the batched workload (Gamma-Poisson track counts, full
+    """Sixteen events of the batched workload in the tuned launch shape (Gamma-Poisson track counts, full
     512x256x64 grid): accumulators, candidates and CSR offsets of every event
     equal the oracle; hit lists equal the single-event path (itself checked
     against the oracle) and the oracle on sampled candidates."""
@@ -100,10 +100,12 @@ def test_batch_full_grid_uneven_events(H, oracle_mod):
     cfg = configs.C3
     events = [synth.make_event(cfg, i) for i in range(16)]
     plan = H.Plan(cfg, max_hits=32767)
+    from paper_1305_4855_amd import tune
+    shape = tune.apply(plan)  # the benchmark's launch shape
     cap_peaks, cap_pairs = 1 << 19, 1 << 23
     bufs = H.BatchBuffers(plan, len(events), sum(e.n for e in events), cap_peaks, cap_pairs)
     bufs.load(events)
-    print(f"[batch] c3 x16: {[e.n for e in events]} hits", flush=True)
+    print(f"[batch] c3 x16 {shape}: {[e.n for e in events]} hits", flush=True)
     bufs.run(cfg.threshold)
     torch.cuda.synchronize()
     g = O.Cfg(cfg)
@@ -173,6 +175,7 @@ def test_graph_replays_match_eager(H):
 
 @pytest.mark.parametrize("tune", [dict(vote_threads=512, vote_grid=64, peak_planes=4),
                                   dict(vote_threads=256, vote_grid=7, peak_planes=16),
+                                  dict(vote_threads=512, vote_grid=512, peak_planes=32),
                                   dict(vote_threads=1024, vote_grid=0, peak_planes=3)])
 def test_results_identical_across_launch_shapes(H, tune):
     cfg, events = _small_batch_events()

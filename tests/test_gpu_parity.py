@@ -128,15 +128,18 @@ def test_c4_family_int16_small_full_parity(H, oracle_mod):
 
 
 def test_c2_full_size_parity(H, oracle_mod):
-    """The full dense event (about 12k hits, 512x256x64 bins): accumulator and
-    candidate list compared in full, hit lists on sampled candidates plus the
-    first and last ones, CSR offsets in full."""
+    """The full dense event (about 12k hits, 512x256x64 bins) in the tuned launch
+    shape: accumulator and candidate list compared in full, hit lists on sampled
+    candidates plus the first and last ones, CSR offsets in full."""
     O = oracle_mod
     cfg = configs.C2
     ev = synth.make_event(cfg, 0)
     print(f"[parity] c2 full n_hits={ev.n}", flush=True)
     g = O.Cfg(cfg)
-    res = run_gpu(H, cfg, ev, cap_peaks=1 << 19, cap_pairs=1 << 24, max_hits=16384)
+    from paper_1305_4855_amd import tune
+    plan = H.Plan(cfg, max_hits=16384)
+    print(f"[parity] c2 full launch shape {tune.apply(plan)}", flush=True)  # the benchmark's shape
+    res = run_gpu(H, cfg, ev, cap_peaks=1 << 19, cap_pairs=1 << 24, plan=plan)
     acc_ref, nv = O.vote(g, ev)
     assert int(np.count_nonzero(res["acc"] != acc_ref)) == 0
     assert res["status"]["n_votes"] == nv
