@@ -949,6 +949,7 @@ __global__ __launch_bounds__(kPScanThreads) void k_peaks_scan(Events ev, int64_t
 // its candidates' position and vote prefix from the group's CSR bases plus an in-group scan over
 // the group's threads, and writes its candidates and their CSR offsets in linear order.
 constexpr int kWriteStrips = 8;
+constexpr int kWriteFirst = 4;  // candidates per thread whose values are loaded together
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_peaks_write(Events ev, const char* __restrict__ acc_base,
@@ -986,8 +987,22 @@ __global__ __launch_bounds__(256) void k_peaks_write(Events ev, const char* __re
     const int s0 = (int)(strip0 - row * strips);
     const T* r = acc + row * n_phi + s0 * kStrip;
     const int32_t cnt = __popcll(bits);
+    // the first kWriteFirst candidates' bins and values: their loads go out together (a bin with
+    // no candidate loads bin 0 of the thread's range and is not used)
+    int idx[kWriteFirst];
+    int32_t val[kWriteFirst];
+    uint64_t rest = bits;
+#pragma unroll
+    for (int j = 0; j < kWriteFirst; ++j) {
+        idx[j] = rest ? __ffsll((long long)rest) - 1 : 0;
+        rest &= rest - 1;
+    }
+#pragma unroll
+    for (int j = 0; j < kWriteFirst; ++j) val[j] = (int32_t)r[idx[j]];
     int32_t vsum = 0;
-    for (uint64_t b = bits; b; b &= b - 1) vsum += (int32_t)r[__ffsll((long long)b) - 1];
+#pragma unroll
+    for (int j = 0; j < kWriteFirst; ++j) vsum += j < cnt ? val[j] : 0;
+    for (uint64_t b = rest; b; b &= b - 1) vsum += (int32_t)r[__ffsll((long long)b) - 1];
     // inclusive prefix of candidate and vote counts over the group's threads
     const int gl = threadIdx.x & (tpg - 1);
     int32_t inc = cnt, vinc = vsum;
@@ -1004,9 +1019,7 @@ __global__ __launch_bounds__(256) void k_peaks_write(Events ev, const char* __re
     int64_t voff = g_voff + vinc - vsum;
     const int k = (int)(row % n_qpt);
     const int l = (int)(row / n_qpt);
-    for (uint64_t b = bits; b; b &= b - 1) {
-        const int i = __ffsll((long long)b) - 1;
-        const int32_t v = (int32_t)r[i];
+    auto emit = [&](int i, int32_t v) {
         if (pos < cap) {
             hough_peak_t pk;
             pk.l = l;
@@ -1018,6 +1031,13 @@ __global__ __launch_bounds__(256) void k_peaks_write(Events ev, const char* __re
         }
         ++pos;
         voff += v;
+    };
+#pragma unroll
+    for (int j = 0; j < kWriteFirst; ++j)
+        if (j < cnt) emit(idx[j], val[j]);
+    for (uint64_t b = rest; b; b &= b - 1) {
+        const int i = __ffsll((long long)b) - 1;
+        emit(i, (int32_t)r[i]);
     }
 }
 
