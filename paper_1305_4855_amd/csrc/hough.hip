@@ -1048,9 +1048,9 @@ typedef __attribute__((address_space(3))) const int32_t lds_ci32;
 // The list of one candidate, layer by layer: the run(s) of sorted hits with angle in
 // [lo, lo + 2^F) (mod 2^M), lo = E + b * 2^F, found from the cell table and a short scan, copied in
 // order to the wave's LDS buffer (or straight to memory beyond it).  PhiT/HT: global or LDS arrays.
-// First index of cell c (hits [cs[c], cs[c+1]) sorted by angle) whose angle is >= x.  SCAN8: the
-// first 8 entries of the cell are compared at once (independent loads, no divergent loop; the
-// cells hold about two hits on average), a longer cell continues one by one.
+// First index of cell c (hits [cs[c], cs[c+1]) sorted by angle) whose angle is >= x.  SCAN8 (LDS
+// arrays only): the first 8 entries of the cell are compared at once (independent loads, no
+// divergent loop; the cells hold about two hits on average), a longer cell continues one by one.
 template <bool SCAN8, typename PhiT>
 __device__ __forceinline__ int cell_lower_bound(const int32_t* cs, int c, PhiT phi, uint32_t x) {
     const int a = cs[c];
@@ -1060,9 +1060,14 @@ __device__ __forceinline__ int cell_lower_bound(const int32_t* cs, int c, PhiT p
         while (q < a + n_in && phi[q] < x) ++q;
         return q;
     }
+    // all eight loads are issued before any compare (a load under `i < n_in` would wait on its
+    // own); the staged arrays leave room for reads up to 8 entries past the last hit
+    uint32_t v[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) v[i] = phi[a + i];
     int cnt = 0;
 #pragma unroll
-    for (int i = 0; i < 8; ++i) cnt += (i < n_in && phi[a + i] < x) ? 1 : 0;
+    for (int i = 0; i < 8; ++i) cnt += (int)((i < n_in) & (v[i] < x));
     if (n_in > 8 && cnt == 8)
         while (cnt < n_in && phi[a + cnt] < x) ++cnt;
     return a + cnt;
@@ -1631,7 +1636,10 @@ void launch_assign(const hough_plan* p, const Events& ev, int n_events, const ho
     int buf_words = (int)((kLdsBytes - cells_bytes) / 4 / (kAssignThreads / 64)) & ~63;
     buf_words = buf_words > kAssignBufMax ? kAssignBufMax : buf_words;
     const size_t used = 4 * (size_t)(kAssignThreads / 64) * buf_words + cells_bytes;
-    const int stage_hits = used < (size_t)kLdsBytes ? (int)(((size_t)kLdsBytes - used) / 8) & ~3 : 0;
+    // (the 8-entry window scan reads up to 7 entries past the last staged angle, into the hit
+    // indices that follow: at least 16 of them)
+    int stage_hits = used < (size_t)kLdsBytes ? (int)(((size_t)kLdsBytes - used) / 8) & ~3 : 0;
+    if (stage_hits < 16) stage_hits = 0;
     const size_t lds = used + 8 * (size_t)stage_hits;
     hipLaunchKernelGGL(k_assign_fill, dim3(nblk, n_events), dim3(kAssignThreads), lds, stream, ev, peaks, peak_stride,
                        cap_peaks, st, p->d_E, p->n_layers, p->cell_bits, p->n_cols, p->g.n_qpt, p->M, p->F, ws, O,
