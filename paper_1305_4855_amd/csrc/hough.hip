@@ -296,14 +296,21 @@ __global__ __launch_bounds__(256) void k_prep_hits(Events ev, const float* __res
 // and reset the event's status.
 //   1. LDS histogram over cells, counting bad hits;
 //   2. exclusive scan -> cell_start, hit-vote total from the per-layer counts;
-//   3. scatter into cell order (LDS cursors; arbitrary order inside a cell) -> tmp_phi, tmp_key,
-//      tmp_key = (layer << 24) | hit index.
+//   3. scatter into cell order (LDS cursors; arbitrary order inside a cell) of (angle, key),
+//      key = (layer << 24) | hit index: for an event of at most cap_h hits into LDS, where each
+//      hit is then ranked inside its cell by (angle, hit index) and written to sorted_phi /
+//      sorted_h (the event is then flagged sorted in misc word 1; a scatter of single words to
+//      random global addresses from one workgroup is slow); a larger event goes to tmp_phi /
+//      tmp_key for k_prep_rank.
 // An event with more than max_hits hits is treated as empty and flagged.
 constexpr int kBucketUnroll = 16;  // hits per thread and pass: events up to 16384 hits stay in registers
+constexpr int kRankBatch = 4;      // hits a thread ranks inside their cells at once
 __global__ __launch_bounds__(kScanThreads) void k_prep_bucket(Events ev, int n_layers, int cell_bits, int M,
                                                               LayerTable LT, char* __restrict__ ws, WsOff O,
-                                                              hough_status_t* __restrict__ st_base) {
-    __shared__ int32_t cur[kMaxCells];
+                                                              hough_status_t* __restrict__ st_base, int cells_pad,
+                                                              int cap_h) {
+    // LDS: cursors [cells_pad], then (cap_h > 0) angles [cap_h + 8] and keys [cap_h + 8]
+    extern __shared__ int32_t cur[];
     __shared__ int64_t wsum[kScanThreads / 64];
     __shared__ int32_t layer_n[kMaxLayers];
     const int e = blockIdx.y;
@@ -378,6 +385,74 @@ __global__ __launch_bounds__(kScanThreads) void k_prep_bucket(Events ev, int n_l
         st->flags = n_given > ev.max_hits ? HOUGH_F_EVENT_TOO_LARGE : 0;
         st->n_pairs = 0;
     }
+    int32_t* sorted_flag = at<int32_t>(w, O.misc) + 1;
+    if (resident && n <= cap_h) {
+        // scatter into LDS, rank inside the cell, write the sorted arrays (nearly in order)
+        uint32_t* s_phi = reinterpret_cast<uint32_t*>(cur + cells_pad);
+        int32_t* s_key = cur + cells_pad + cap_h + 8;
+#pragma unroll
+        for (int j = 0; j < kBucketUnroll; ++j) {
+            if (L[j] >= 0xFE) continue;
+            const int h = j * kScanThreads + tid;
+            const int pos = atomicAdd(&cur[((int)L[j] << cell_bits) | (int)(ph[j] >> cshift)], 1);
+            s_phi[pos] = ph[j] >> (32 - M);
+            s_key[pos] = ((int32_t)L[j] << 24) | h;
+        }
+        __syncthreads();
+        // every cursor now holds the end of its cell, i.e. the start of the next one.  Rank
+        // kRankBatch hits of a thread at a time, with the first 8 entries of each of their cells
+        // loaded together (the arrays keep 8 entries of slack); a longer cell continues one by one.
+        uint32_t* sorted_phi = at<uint32_t>(w, O.sorted_phi);
+        int32_t* sorted_h = at<int32_t>(w, O.sorted_h);
+        const int nt = (int)tot;
+        for (int q0 = tid; q0 < nt; q0 += kRankBatch * kScanThreads) {
+            uint32_t a[kRankBatch];
+            int32_t hh[kRankBatch], c0[kRankBatch], n_in[kRankBatch], rank[kRankBatch];
+#pragma unroll
+            for (int u = 0; u < kRankBatch; ++u) {
+                const int q = min(q0 + u * kScanThreads, nt - 1);
+                a[u] = s_phi[q];
+                const int32_t key = s_key[q];
+                hh[u] = key & 0xFFFFFF;
+                c0[u] = ((key >> 24) << cell_bits) | (int)(a[u] >> (M - cell_bits));  // the cell, for now
+            }
+#pragma unroll
+            for (int u = 0; u < kRankBatch; ++u) {
+                const int c = c0[u];
+                c0[u] = c > 0 ? cur[c - 1] : 0;
+                n_in[u] = cur[c] - c0[u];
+            }
+#pragma unroll
+            for (int u = 0; u < kRankBatch; ++u) {
+                uint32_t b[8];
+                int32_t k2[8];
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    b[i] = s_phi[c0[u] + i];
+                    k2[i] = s_key[c0[u] + i];
+                }
+                int r = 0;
+#pragma unroll
+                for (int i = 0; i < 8; ++i)
+                    r += (int)((i < n_in[u]) & ((b[i] < a[u]) | ((b[i] == a[u]) & ((k2[i] & 0xFFFFFF) < hh[u]))));
+                rank[u] = r;
+            }
+#pragma unroll
+            for (int u = 0; u < kRankBatch; ++u) {
+                for (int j = 8; j < n_in[u]; ++j) {
+                    const uint32_t b = s_phi[c0[u] + j];
+                    rank[u] += (b < a[u] || (b == a[u] && (s_key[c0[u] + j] & 0xFFFFFF) < hh[u])) ? 1 : 0;
+                }
+                if (q0 + u * kScanThreads < nt) {
+                    sorted_phi[c0[u] + rank[u]] = a[u];
+                    sorted_h[c0[u] + rank[u]] = hh[u];
+                }
+            }
+        }
+        if (tid == 0) *sorted_flag = 1;
+        return;
+    }
+    if (tid == 0) *sorted_flag = 0;
     // scatter into cell order
     for (int base = 0; base < n; base += kScanThreads * kBucketUnroll) {
         if (!resident) load(base);
@@ -396,6 +471,7 @@ __global__ __launch_bounds__(kScanThreads) void k_prep_bucket(Events ev, int n_l
 __global__ __launch_bounds__(256) void k_prep_rank(Events ev, int n_cells, int cell_bits, int M,
                                                    char* __restrict__ ws, WsOff O) {
     char* w = event_ws(ws, ev, blockIdx.y);
+    if (at<int32_t>(w, O.misc)[1]) return;  // sorted by the bucketing pass
     const int32_t* cell_start = at<int32_t>(w, O.cell_start);
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= cell_start[n_cells]) return;
@@ -1528,6 +1604,16 @@ int ilog2_exact(int v) {
 
 int launch_status() { return hipGetLastError() == hipSuccess ? HOUGH_OK : HOUGH_E_HIP; }
 
+// Largest event (hits) the bucketing workgroup sorts in LDS: resident in one pass and with its
+// angles and keys beside the cell cursors in the LDS (0: none).
+int bucket_cap_hits(const hough_plan* p) {
+    const int cells_pad = (p->n_cells + 3) & ~3;
+    const long room = ((long)kLdsBytes - 4L * cells_pad - 1024) / 8 - 8;  // static LDS aside, 8 entries of slack
+    long cap = room < (long)kScanThreads * kBucketUnroll ? room : (long)kScanThreads * kBucketUnroll;
+    cap = cap < p->g.max_hits_per_event ? cap : p->g.max_hits_per_event;
+    return cap >= 64 ? (int)cap : 0;
+}
+
 // Launchers shared by the single-event and batched entry points.
 void launch_prep(const hough_plan* p, const Events& ev, int n_events, int max_n, const float* x, const float* y,
                  const uint8_t* layer, uint32_t* phi_out, char* ws, const WsOff& O, hough_status_t* st,
@@ -1535,9 +1621,14 @@ void launch_prep(const hough_plan* p, const Events& ev, int n_events, int max_n,
     if (max_n > 0)
         hipLaunchKernelGGL(k_prep_hits, dim3((max_n + 255) / 256, n_events), dim3(256), 0, stream, ev, x, y, layer,
                            p->n_layers, p->cordic, ws, O, phi_out);
-    hipLaunchKernelGGL(k_prep_bucket, dim3(1, n_events), dim3(kScanThreads), 0, stream, ev, p->n_layers,
-                       p->cell_bits, p->M, p->layers, ws, O, st);
-    if (max_n > 0)
+    // events of at most cap_h hits are sorted inside the bucketing workgroup (LDS); the rank pass
+    // runs only if a larger event is possible
+    const int cells_pad = (p->n_cells + 3) & ~3;
+    const int cap_h = bucket_cap_hits(p);
+    const size_t lds = 4 * (size_t)cells_pad + (cap_h > 0 ? 8 * ((size_t)cap_h + 8) : 0);
+    hipLaunchKernelGGL(k_prep_bucket, dim3(1, n_events), dim3(kScanThreads), lds, stream, ev, p->n_layers,
+                       p->cell_bits, p->M, p->layers, ws, O, st, cells_pad, cap_h);
+    if (max_n > cap_h)
         hipLaunchKernelGGL(k_prep_rank, dim3((max_n + 255) / 256, n_events), dim3(256), 0, stream, ev, p->n_cells,
                            p->cell_bits, p->M, ws, O);
 }
@@ -1890,6 +1981,9 @@ int hough_plan_create(const hough_geometry_t* geom, const hough_grid_t* grid, ho
                                  kLdsBytes);
     if (ae == hipSuccess)
         ae = hipFuncSetAttribute((const void*)k_assign_fill, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
+    if (ae == hipSuccess)
+        ae = hipFuncSetAttribute((const void*)k_prep_bucket, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 kLdsBytes - 1024);
     if (ae == hipSuccess)
         ae = hipFuncSetAttribute((const void*)k_zvote, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
     if (ae != hipSuccess) {
