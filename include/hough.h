@@ -124,7 +124,8 @@ typedef struct {
     int32_t vote_threads;      /* threads per vote workgroup: 256, 512 or 1024            */
     int32_t vote_grid;         /* persistent vote workgroups of a batch (0 = 256)          */
     int32_t peak_planes;       /* d0 planes walked by one peak-finder thread (1..32);
-                                  halved while a launch would leave compute units idle */
+                                  halved while a launch would give a compute unit
+                                  fewer than two workgroups                         */
 } hough_tuning_t;
 
 /* Create a plan on the current HIP device: validates geometry and grid and

@@ -1348,6 +1348,7 @@ __global__ __launch_bounds__(kAssignThreads) void k_assign_fill(
 // holding a candidate of more than 64 hits is voted from memory instead, one row at a time in
 // chunks of 64 hits, restoring the row after its last chunk.
 constexpr int kZvoteGroup = 2;                    // candidates staged together by a wave
+constexpr int kZvoteUnroll = 4;                   // rows voted before their returned words are used
 constexpr int kZvoteStage = kZvoteGroup * 64;     // staged hits per wave (A, B: 16 bytes each)
 
 __device__ __forceinline__ void zvote_hit(int32_t h, const float* __restrict__ hz, const uint8_t* __restrict__ hl,
@@ -1404,8 +1405,33 @@ __device__ __forceinline__ uint32_t zvote_small(int H, int lane, uint32_t* regio
         uint32_t low = (uint32_t)(((uint64_t)z0 & lowmask) << (32 - sh));
         const int32_t bH = (int32_t)(step >> sh);
         const uint32_t bL = (uint32_t)(((uint64_t)step & lowmask) << (32 - sh));
-        // every row of all but the last iteration exists (m < n_cot); the last one is checked
-        for (int it = 0; it + 1 < iters; ++it) {
+        // every row of all but the last iteration exists (m < n_cot); the last one is checked.
+        // kZvoteUnroll rows are voted before their returned words are used: the add and restore
+        // of one row precede those of the next in the wave's LDS order, so nothing waits per row.
+        int it = 0;
+        for (; it + kZvoteUnroll < iters; it += kZvoteUnroll) {
+            uint32_t got[kZvoteUnroll];
+            bool ok[kZvoteUnroll];
+            uint32_t kcs[kZvoteUnroll];
+#pragma unroll
+            for (int u = 0; u < kZvoteUnroll; ++u) {
+                ok[u] = (uint32_t)j < (uint32_t)nz;
+                kcs[u] = kc;
+                got[u] = 0;
+                if (ok[u]) {
+                    got[u] = __hip_atomic_fetch_add(row + j, unit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                    __hip_atomic_fetch_sub(row + j, unit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                }
+                asm volatile("" ::: "memory");
+                const uint32_t nl = low - bL;
+                j = j - bH - (nl > low ? 1 : 0);
+                low = nl;
+                kc -= kstep;
+            }
+#pragma unroll
+            for (int u = 0; u < kZvoteUnroll; ++u) best = max(best, ok[u] ? got[u] + kcs[u] : 0u);
+        }
+        for (; it + 1 < iters; ++it) {
             if ((uint32_t)j < (uint32_t)nz) {
                 const uint32_t old = __hip_atomic_fetch_add(row + j, unit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
                 best = max(best, old + kc);
@@ -1675,12 +1701,13 @@ void launch_peaks(const hough_plan* p, const Events& ev, int n_events, const voi
                   hough_status_t* st, hipStream_t stream) {
     const int strips = p->g.n_phi / kStrip;
     const int gl = peak_group_lanes(p);
-    // fewer planes per thread when the launch would leave CUs without a workgroup (a small batch)
+    // fewer planes per thread while the launch would give a CU fewer than two workgroups (a single
+    // event or a small batch: one 4-wave workgroup per CU leaves the loads too few waves to hide in)
     int planes = p->tuning.peak_planes;
     auto mark_blocks = [&](int pl) {
         return ((int64_t)strips * p->g.n_qpt * ((p->g.n_d0 + pl - 1) / pl) + kMarkThreads - 1) / kMarkThreads;
     };
-    while (planes > 1 && mark_blocks(planes) * n_events < p->n_cu) planes = (planes + 1) / 2;
+    while (planes > 1 && mark_blocks(planes) * n_events < 2 * (int64_t)p->n_cu) planes = (planes + 1) / 2;
     const int lranges = (p->g.n_d0 + planes - 1) / planes;
     const int64_t mark_threads = (int64_t)strips * p->g.n_qpt * lranges;
     const int64_t n_strips = p->n_bins / kStrip;
