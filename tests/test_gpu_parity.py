@@ -208,6 +208,39 @@ def test_ragged_hit_counts(H, oracle_mod):
         check_full(H, oracle_mod, cfg, ev, max_hits=n)
 
 
+def test_bucket_sort_limit_and_crowded_cells(H, oracle_mod):
+    """Events at and just past the size the bucketing workgroup sorts in its LDS (16384 hits;
+    larger ones go through the separate rank pass), with crowded cells (more than 8 hits, the
+    in-cell ranking's first round) and hits at identical angles (ties broken by hit index); alone
+    against the oracle, and mixed in one batch against the single-event path."""
+    cfg = configs.small_variant(configs.C2, n_phi=256, n_qpt=64, n_d0=2).with_(threshold=30)
+    rng = np.random.default_rng(26)
+    r = np.asarray(configs.RADII_CM)
+
+    def event(n):
+        lay = rng.integers(0, 10, n).astype(np.uint8)
+        phi = rng.uniform(0, 2 * np.pi, n)
+        phi[: n // 8] = rng.uniform(1.0, 1.02, n // 8)  # crowded cells
+        phi[n // 8: n // 8 + 40] = 2.5                    # identical angles
+        lay[n // 8: n // 8 + 40] = 3
+        return _event(r[lay] * np.cos(phi), r[lay] * np.sin(phi), lay)
+
+    events = [event(n) for n in (16383, 16384, 16385)]
+    for ev in events:
+        check_full(H, oracle_mod, cfg, ev, max_hits=20000, cap_peaks=1 << 16, cap_pairs=1 << 23)
+    plan = H.Plan(cfg, max_hits=20000)
+    mixed = [events[2], events[0], synth.make_event(cfg.with_(n_tracks=20, track_dist="fixed"), 5), events[1]]
+    bufs = H.BatchBuffers(plan, len(mixed), sum(e.n for e in mixed), 1 << 16, 1 << 23)
+    bufs.load(mixed)
+    bufs.run(cfg.threshold)
+    torch.cuda.synchronize()
+    for e, ev in enumerate(mixed):
+        single = run_gpu(H, cfg, ev, cap_peaks=1 << 16, cap_pairs=1 << 23, plan=plan)
+        got = bufs.results(e)
+        np.testing.assert_array_equal(got["peaks"], single["peaks"])
+        np.testing.assert_array_equal(got["hit_idx"], single["hit_idx"])
+
+
 def test_large_events_take_the_long_paths(H, oracle_mod):
     """Events beyond what the fast paths hold: more hits than the bucketing keeps in registers
     (16384), more valid hits than the assignment stages in LDS, more than 65535 hits with 32-bit
