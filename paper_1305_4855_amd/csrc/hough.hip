@@ -898,12 +898,16 @@ __global__ __launch_bounds__(kMarkThreads) void k_peaks_mark(Events ev, const ch
     }
 }
 
-// One workgroup per event: exclusive scans of the per-group candidate counts and vote sums into
-// grp_off / grp_voff (the CSR base of each group), the candidate total into the status and the
-// number of listed candidates into `misc`.  Each thread owns kPScanPer consecutive groups (vector
-// loads and stores); the next tile's loads are issued before the current tile is scanned.
+// Exclusive scans of the per-group candidate counts and vote sums into grp_off / grp_voff (the
+// CSR base of each group), the candidate total into the status and the number of listed
+// candidates into `misc`.  grid = (chunks, events): workgroup x scans the x-th of `chunks` equal
+// ranges of the event's groups, starting from the sum of all groups before its range (loaded at
+// once and reduced; a single event spreads over many CUs this way, a large batch uses one
+// workgroup per event).  Each thread owns kPScanPer consecutive groups of a tile (vector loads and
+// stores); the next tile's loads are issued before the current tile is scanned.
 constexpr int kPScanPer = 8;
 constexpr int kPScanThreads = 512;  // (1024 would cap the registers at 128 and spill)
+constexpr int kPScanPrefixUnroll = 8;  // 16-byte loads per thread and round of the carry-in sum
 
 __device__ __forceinline__ void load_groups(const int32_t* __restrict__ src, int64_t i0, int64_t n,
                                             int32_t (&v)[kPScanPer]) {
@@ -939,11 +943,51 @@ __global__ __launch_bounds__(kPScanThreads) void k_peaks_scan(Events ev, int64_t
     const int lane = tid & 63;
     const int wv = tid >> 6;
     constexpr int64_t tile = (int64_t)kPScanThreads * kPScanPer;
-    int64_t carry_c = 0, carry_v = 0;
+    // this workgroup's range [g0, g1) (a multiple of kPScanPer long, so vector loads stay aligned)
+    const int64_t per = ((n_groups + gridDim.x - 1) / gridDim.x + kPScanPer - 1) / kPScanPer * kPScanPer;
+    const int64_t g0 = min(n_groups, (int64_t)blockIdx.x * per);
+    const int64_t g1 = min(n_groups, g0 + per);
     int32_t c[kPScanPer], v[kPScanPer];
-    load_groups(grp_count, (int64_t)tid * kPScanPer, n_groups, c);
-    load_groups(grp_votes, (int64_t)tid * kPScanPer, n_groups, v);
-    for (int64_t base = 0; base < n_groups; base += tile) {
+    load_groups(grp_count, g0 + (int64_t)tid * kPScanPer, g1, c);
+    load_groups(grp_votes, g0 + (int64_t)tid * kPScanPer, g1, v);
+    // carry in: the sums over [0, g0), every load issued before the reduction
+    int64_t carry_c = 0, carry_v = 0;
+    if (g0 > 0) {
+        int64_t pc = 0, pv = 0;
+        for (int64_t i0 = 4 * (int64_t)tid; i0 < g0; i0 += 4 * kPScanThreads * kPScanPrefixUnroll) {
+            int4 a[kPScanPrefixUnroll], b[kPScanPrefixUnroll];
+#pragma unroll
+            for (int u = 0; u < kPScanPrefixUnroll; ++u) {
+                const int64_t j = min(i0 + 4 * (int64_t)kPScanThreads * u, g0 - 4);  // g0 is a multiple of 4
+                a[u] = *reinterpret_cast<const int4*>(grp_count + j);
+                b[u] = *reinterpret_cast<const int4*>(grp_votes + j);
+            }
+#pragma unroll
+            for (int u = 0; u < kPScanPrefixUnroll; ++u) {
+                if (i0 + 4 * (int64_t)kPScanThreads * u < g0) {
+                    pc += (int64_t)a[u].x + a[u].y + a[u].z + a[u].w;
+                    pv += (int64_t)b[u].x + b[u].y + b[u].z + b[u].w;
+                }
+            }
+        }
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) {
+            pc += __shfl_xor(pc, o, 64);
+            pv += __shfl_xor(pv, o, 64);
+        }
+        if (lane == 0) {
+            wsum_c[wv] = pc;
+            wsum_v[wv] = pv;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < kPScanThreads / 64; ++k) {
+            carry_c += wsum_c[k];
+            carry_v += wsum_v[k];
+        }
+        __syncthreads();  // wsum is reused by the scan
+    }
+    for (int64_t base = g0; base < g1; base += tile) {
         const int64_t i0 = base + (int64_t)tid * kPScanPer;
         int32_t sc = 0, sv = 0;  // a thread's groups hold < 2^31 candidates and votes
 #pragma unroll
@@ -980,7 +1024,7 @@ __global__ __launch_bounds__(kPScanThreads) void k_peaks_scan(Events ev, int64_t
         __syncthreads();  // wsum is rewritten by the next tile
         int64_t rc = carry_c + pc + ic - sc;
         int64_t rv = carry_v + pv + iv - sv;
-        if (i0 + kPScanPer <= n_groups) {
+        if (i0 + kPScanPer <= g1) {
 #pragma unroll
             for (int q = 0; q < kPScanPer / 4; ++q) {
                 int4 o4;
@@ -996,7 +1040,7 @@ __global__ __launch_bounds__(kPScanThreads) void k_peaks_scan(Events ev, int64_t
         } else {
 #pragma unroll
             for (int j = 0; j < kPScanPer; ++j) {
-                if (i0 + j < n_groups) {
+                if (i0 + j < g1) {
                     grp_off[i0 + j] = (int32_t)min(rc, (int64_t)INT32_MAX);
                     grp_voff[i0 + j] = rv;
                 }
@@ -1006,12 +1050,12 @@ __global__ __launch_bounds__(kPScanThreads) void k_peaks_scan(Events ev, int64_t
         }
         carry_c += tc;
         carry_v += tv;
-        if (base + tile < n_groups) {  // the next tile
-            load_groups(grp_count, i0 + tile, n_groups, c);
-            load_groups(grp_votes, i0 + tile, n_groups, v);
+        if (base + tile < g1) {  // the next tile
+            load_groups(grp_count, i0 + tile, g1, c);
+            load_groups(grp_votes, i0 + tile, g1, v);
         }
     }
-    if (tid == 0) {
+    if (tid == 0 && g1 == n_groups && (g0 < g1 || g0 == 0)) {  // the workgroup holding the last group
         grp_off[n_groups] = (int32_t)min(carry_c, (int64_t)INT32_MAX);
         grp_voff[n_groups] = carry_v;
         st->n_peaks = (int32_t)min(carry_c, (int64_t)INT32_MAX);
@@ -1732,7 +1776,14 @@ void launch_peaks(const hough_plan* p, const Events& ev, int n_events, const voi
     else
         hipLaunchKernelGGL((k_peaks_mark<int16_t, false>), gm, mb, 0, stream, ev, a, acc_stride, z16, threshold, nd,
                            nq, nph, gl, planes, ws, O);
-    hipLaunchKernelGGL(k_peaks_scan, dim3(1, n_events), dim3(kPScanThreads), 0, stream, ev, groups, cap, ws, O, st);
+    // workgroups per event: enough to spread a small batch over the CUs, each with >= one tile
+    int64_t chunks = 2 * (int64_t)p->n_cu / n_events;
+    const int64_t by_size = groups / ((int64_t)kPScanThreads * kPScanPer);
+    chunks = chunks < by_size ? chunks : by_size;
+    chunks = chunks < 16 ? chunks : 16;
+    chunks = chunks > 1 ? chunks : 1;
+    hipLaunchKernelGGL(k_peaks_scan, dim3((unsigned)chunks, n_events), dim3(kPScanThreads), 0, stream, ev, groups,
+                       cap, ws, O, st);
     if (p->g.acc_bits == 32)
         hipLaunchKernelGGL(k_peaks_write<int32_t>, gw, dim3(256), 0, stream, ev, a, acc_stride, groups, p->g.n_qpt,
                            p->g.n_phi, gl, n_strips, ws, O, peaks, cap);
