@@ -57,7 +57,8 @@ constexpr int kStrip = 8;           // phi0 bins per peak-finder thread
 constexpr int kScanThreads = 1024;
 constexpr int kMaxCells = 32768;    // LDS histogram of the prep bucketing (128 KiB)
 constexpr int kAssignThreads = 1024;
-constexpr int kAssignBufMax = 512;  // words of CSR list buffered per wave (less if the cell table is large)
+constexpr int kAssignBufMax = 2048;  // words of CSR list buffered per wave (less when the LDS is short)
+constexpr int kAssignBufMin = 256;   // buffer below which an event's hits are not staged in LDS
 constexpr int kLdsBytes = 160 * 1024;
 constexpr int kZvoteThreads = 256;
 constexpr int kZvoteSlots = 8;      // rows of the r-z grid one wave votes at once
@@ -1165,38 +1166,59 @@ __global__ __launch_bounds__(256) void k_peaks_write(Events ev, const char* __re
 typedef __attribute__((address_space(3))) const uint32_t lds_cu32;
 typedef __attribute__((address_space(3))) const int32_t lds_ci32;
 
+// Views of the event's sorted hits (angle and hit index at a sorted position): two LDS arrays,
+// one packed LDS word per hit (angle in the low 16 bits, hit index in the high 16 bits: plans with
+// M <= 16 angle bits, whose events have at most 65535 hits), or the workspace arrays.
+struct HitsSplit {
+    lds_cu32* phi;
+    lds_ci32* h;
+    __device__ __forceinline__ uint32_t angle(int i) const { return phi[i]; }
+    __device__ __forceinline__ int32_t hit(int i) const { return h[i]; }
+};
+struct HitsPacked {
+    lds_cu32* w;
+    __device__ __forceinline__ uint32_t angle(int i) const { return w[i] & 0xFFFFu; }
+    __device__ __forceinline__ int32_t hit(int i) const { return (int32_t)(w[i] >> 16); }
+};
+struct HitsGlobal {
+    const uint32_t* __restrict__ phi;
+    const int32_t* __restrict__ h;
+    __device__ __forceinline__ uint32_t angle(int i) const { return phi[i]; }
+    __device__ __forceinline__ int32_t hit(int i) const { return h[i]; }
+};
+
 // The list of one candidate, layer by layer: the run(s) of sorted hits with angle in
 // [lo, lo + 2^F) (mod 2^M), lo = E + b * 2^F, found from the cell table and a short scan, copied in
-// order to the wave's LDS buffer (or straight to memory beyond it).  PhiT/HT: global or LDS arrays.
+// order to the wave's LDS buffer (or straight to memory beyond it).
 // First index of cell c (hits [cs[c], cs[c+1]) sorted by angle) whose angle is >= x.  SCAN8 (LDS
-// arrays only): the first 8 entries of the cell are compared at once (independent loads, no
+// views only): the first 8 entries of the cell are compared at once (independent loads, no
 // divergent loop; the cells hold about two hits on average), a longer cell continues one by one.
-template <bool SCAN8, typename PhiT>
-__device__ __forceinline__ int cell_lower_bound(const int32_t* cs, int c, PhiT phi, uint32_t x) {
+template <bool SCAN8, typename View>
+__device__ __forceinline__ int cell_lower_bound(const int32_t* cs, int c, const View& hv, uint32_t x) {
     const int a = cs[c];
     const int n_in = cs[c + 1] - a;
     if (!SCAN8) {
         int q = a;
-        while (q < a + n_in && phi[q] < x) ++q;
+        while (q < a + n_in && hv.angle(q) < x) ++q;
         return q;
     }
     // all eight loads are issued before any compare (a load under `i < n_in` would wait on its
     // own); the staged arrays leave room for reads up to 8 entries past the last hit
     uint32_t v[8];
 #pragma unroll
-    for (int i = 0; i < 8; ++i) v[i] = phi[a + i];
+    for (int i = 0; i < 8; ++i) v[i] = hv.angle(a + i);
     int cnt = 0;
 #pragma unroll
     for (int i = 0; i < 8; ++i) cnt += (int)((i < n_in) & (v[i] < x));
     if (n_in > 8 && cnt == 8)
-        while (cnt < n_in && phi[a + cnt] < x) ++cnt;
+        while (cnt < n_in && hv.angle(a + cnt) < x) ++cnt;
     return a + cnt;
 }
 
-template <bool SCAN8, typename PhiT, typename HT>
+template <bool SCAN8, typename View>
 __device__ __forceinline__ void assign_candidate(const hough_peak_t& pk, int64_t off, int64_t o0, const int32_t* Ec,
                                                  int n_layers, int cell_bits, int n_cols, int M, int F,
-                                                 const int32_t* cell_start, PhiT sorted_phi, HT sorted_h,
+                                                 const int32_t* cell_start, const View& hv,
                                                  int32_t* buf, int buf_words, int32_t* hit_idx, int32_t cap_pairs) {
     const uint32_t span = 1u << M;
     const uint32_t W = 1u << F;
@@ -1205,7 +1227,9 @@ __device__ __forceinline__ void assign_candidate(const hough_peak_t& pk, int64_t
 #pragma unroll
     for (int L = 0; L < kMaxLayers; ++L) ev_l[L] = L < n_layers ? Ec[(size_t)L * n_cols] : INT32_MIN;
     int64_t wpos = off;
-    for (int L = 0; L < n_layers && wpos < cap_pairs; ++L) {
+#pragma unroll
+    for (int L = 0; L < kMaxLayers; ++L) {
+        if (L >= n_layers || wpos >= cap_pairs) break;
         if (ev_l[L] == INT32_MIN) continue;
         const uint32_t lo = ((uint32_t)ev_l[L] + ((uint32_t)pk.b << F)) & (span - 1u);
         const uint32_t hi = lo + W;  // may exceed 2^M: the window wraps
@@ -1213,14 +1237,14 @@ __device__ __forceinline__ void assign_candidate(const hough_peak_t& pk, int64_t
         // cell has a larger angle than the window's start, every hit of an earlier cell a smaller one
         const int32_t* cs = cell_start + (L << cell_bits);
         const int lay_end = cs[1 << cell_bits];
-        const int q = cell_lower_bound<SCAN8>(cs, (int)(lo >> cshift), sorted_phi, lo);
+        const int q = cell_lower_bound<SCAN8>(cs, (int)(lo >> cshift), hv, lo);
         const uint32_t he = hi <= span ? hi : span;
-        const int z = he < span ? cell_lower_bound<SCAN8>(cs, (int)(he >> cshift), sorted_phi, he) : lay_end;
-        int r = 0, z2 = 0;
+        const int z = he < span ? cell_lower_bound<SCAN8>(cs, (int)(he >> cshift), hv, he) : lay_end;
+        int r = -1, z2 = -1;
         if (hi > span) {
             const uint32_t hw = hi - span;
             r = cs[0];
-            z2 = cell_lower_bound<SCAN8>(cs, (int)(hw >> cshift), sorted_phi, hw);
+            z2 = cell_lower_bound<SCAN8>(cs, (int)(hw >> cshift), hv, hw);
         }
         // copy the run(s) four entries at a time: the four loads go out before the four stores
         for (int seg = 0; seg < 2; ++seg) {
@@ -1229,7 +1253,7 @@ __device__ __forceinline__ void assign_candidate(const hough_peak_t& pk, int64_t
             for (int j = a0; j < a1; j += 4) {
                 int32_t h[4];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) h[u] = sorted_h[min(j + u, a1 - 1)];
+                for (int u = 0; u < 4; ++u) h[u] = hv.hit(min(j + u, a1 - 1));
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
                     const int64_t wp = wpos + (j - a0) + u;
@@ -1245,37 +1269,53 @@ __device__ __forceinline__ void assign_candidate(const hough_peak_t& pk, int64_t
     }
 }
 
-// Copies the cell table (nc words) and, when staged, the event's sorted angles and hit indices
-// (nh words each) from global memory to LDS, 16 bytes per load, with all of a thread's loads of a
-// round issued before its first store (a load-then-store loop would wait on memory once per
-// element).  Sources and destinations are 16-byte aligned; a source is read up to the next
-// multiple of four words (inside its 256-byte padded workspace array).
+// Copies the cell table (nc words) and, when staged, the event's nh sorted angles and hit indices
+// from global memory to LDS: as two arrays, or (PACK) as one word per hit.  16 bytes per load,
+// with all of a thread's loads of a round issued before its first store (a load-then-store loop
+// would wait on memory once per element).  Sources and destinations are 16-byte aligned; a source
+// is read up to the next multiple of four words (inside its 256-byte padded workspace array).
 constexpr int kStageUnroll = 8;  // 16-byte loads per thread and round: 128 KiB per round at 1024 threads
 
+template <bool PACK>
 __device__ __forceinline__ void assign_stage(int32_t* d_cells, const int32_t* __restrict__ g_cells, int nc,
-                                             uint32_t* d_phi, const uint32_t* __restrict__ g_phi,
-                                             int32_t* d_h, const int32_t* __restrict__ g_h, int nh, int tid) {
+                                             uint32_t* d_stage, int stage_stride, const uint32_t* __restrict__ g_phi,
+                                             const int32_t* __restrict__ g_h, int nh, int tid) {
     const int c4 = (nc + 3) >> 2;
     const int h4 = (nh + 3) >> 2;
-    const int total = c4 + 2 * h4;
+    const int total = c4 + (PACK ? h4 : 2 * h4);
     for (int r0 = tid; r0 < total; r0 += kStageUnroll * kAssignThreads) {
-        uint4 v[kStageUnroll];
+        uint4 v[kStageUnroll], w[kStageUnroll];
 #pragma unroll
         for (int u = 0; u < kStageUnroll; ++u) {
             const int c = min(r0 + u * kAssignThreads, total - 1);
-            const uint4* src = c < c4 ? reinterpret_cast<const uint4*>(g_cells) + c
-                             : c < c4 + h4 ? reinterpret_cast<const uint4*>(g_phi) + (c - c4)
-                                           : reinterpret_cast<const uint4*>(g_h) + (c - c4 - h4);
-            v[u] = *src;
+            if (PACK) {
+                const int k = c < c4 ? 0 : c - c4;
+                v[u] = c < c4 ? reinterpret_cast<const uint4*>(g_cells)[c] : reinterpret_cast<const uint4*>(g_phi)[k];
+                w[u] = reinterpret_cast<const uint4*>(g_h)[k];
+            } else {
+                const uint4* src = c < c4 ? reinterpret_cast<const uint4*>(g_cells) + c
+                                 : c < c4 + h4 ? reinterpret_cast<const uint4*>(g_phi) + (c - c4)
+                                               : reinterpret_cast<const uint4*>(g_h) + (c - c4 - h4);
+                v[u] = *src;
+            }
         }
 #pragma unroll
         for (int u = 0; u < kStageUnroll; ++u) {
             const int c = r0 + u * kAssignThreads;
             if (c < total) {
-                uint4* dst = c < c4 ? reinterpret_cast<uint4*>(d_cells) + c
-                           : c < c4 + h4 ? reinterpret_cast<uint4*>(d_phi) + (c - c4)
-                                         : reinterpret_cast<uint4*>(d_h) + (c - c4 - h4);
-                *dst = v[u];
+                if (c < c4) {
+                    reinterpret_cast<uint4*>(d_cells)[c] = v[u];
+                } else if (PACK) {
+                    uint4 o;
+                    o.x = v[u].x | (w[u].x << 16);
+                    o.y = v[u].y | (w[u].y << 16);
+                    o.z = v[u].z | (w[u].z << 16);
+                    o.w = v[u].w | (w[u].w << 16);
+                    reinterpret_cast<uint4*>(d_stage)[c - c4] = o;
+                } else {
+                    const int k = c - c4;  // angles, then the hit indices stage_stride words later
+                    reinterpret_cast<uint4*>(d_stage + (k < h4 ? 0 : stage_stride))[k < h4 ? k : k - h4] = v[u];
+                }
             }
         }
     }
@@ -1284,18 +1324,20 @@ __device__ __forceinline__ void assign_stage(int32_t* d_cells, const int32_t* __
 // One thread per listed candidate (the first min(listed, cap_peaks) written by the peaks pass;
 // grid.y = event): CSR offset from the peaks pass, then its list (assign_candidate).  The 64
 // candidates of a wave own one contiguous stretch of the CSR list: it is assembled in an LDS
-// buffer of the wave and then written with coalesced stores.  The cell table and, when they fit
-// (stage_hits), the event's sorted angles and hit indices are staged in LDS, so the scans and
-// copies do not wait on memory; the per-layer sample values of a candidate are loaded together,
-// and a wave's next 64 candidates are loaded while it works on the current ones.
+// buffer of the wave and then written with coalesced stores.  Each workgroup lays out its LDS
+// from its event's hit count: the cell table, the event's sorted hits when they fit (one word per
+// hit with PACK, else two), and the 16 wave buffers in what is left, up to kAssignBufMax words
+// each (a longer stretch goes on straight to memory); so the scans and copies do not wait on
+// memory.  The per-layer sample values of a candidate are loaded together, and a wave's next 64
+// candidates are loaded while it works on the current ones.
+template <bool PACK>
 __global__ __launch_bounds__(kAssignThreads) void k_assign_fill(
     Events ev, const hough_peak_t* __restrict__ peaks_base, int32_t peak_stride, int32_t cap_peaks,
     hough_status_t* __restrict__ st_base, const int32_t* __restrict__ E, int n_layers, int cell_bits, int n_cols,
     int n_qpt, int M, int F, char* __restrict__ ws, WsOff O, int32_t* __restrict__ offsets_base,
-    int32_t* __restrict__ hit_idx_base, int32_t cap_pairs, int buf_words, int cells_words, int stage_hits) {
-    // LDS: [waves][buf_words] buffers, the cell table (cells_words), then [stage_hits] angles and
-    // [stage_hits] hit indices; every part starts on a 16-byte boundary
+    int32_t* __restrict__ hit_idx_base, int32_t cap_pairs, int lds_words, int cells_words) {
     extern __shared__ int32_t sm_i32[];
+    constexpr int kWaves = kAssignThreads / 64;
     const int e = blockIdx.y;
     char* w = event_ws(ws, ev, e);
     const hough_peak_t* peaks = peaks_base + (size_t)e * peak_stride;
@@ -1318,12 +1360,17 @@ __global__ __launch_bounds__(kAssignThreads) void k_assign_fill(
     }
     if ((int)blockIdx.x * kAssignThreads >= n) return;  // uniform per block
     const int n_cells = n_layers << cell_bits;
-    int32_t* buf = sm_i32 + wave * buf_words;
-    int32_t* cell_start = sm_i32 + (kAssignThreads / 64) * buf_words;
-    uint32_t* s_phi = reinterpret_cast<uint32_t*>(cell_start + cells_words);
-    int32_t* s_h = cell_start + cells_words + stage_hits;
     const int n_valid = g_cell_start[n_cells];
-    const bool staged = n_valid <= stage_hits;
+    // LDS layout of this event: cells [cells_words] | staged hits [stage_words] | 16 buffers; the
+    // staged arrays hold n_pad >= n_valid + 8 entries (the 8-entry scan reads past the last hit)
+    const int n_pad = ((n_valid + 3) & ~3) + 8;
+    const int stage_words = PACK ? n_pad : 2 * n_pad;
+    int buf_words = min(kAssignBufMax, (lds_words - cells_words - stage_words) / kWaves) & ~63;
+    const bool staged = buf_words >= kAssignBufMin;
+    if (!staged) buf_words = min(kAssignBufMax, (lds_words - cells_words) / kWaves) & ~63;
+    int32_t* cell_start = sm_i32;
+    uint32_t* s_stage = reinterpret_cast<uint32_t*>(sm_i32 + cells_words);
+    int32_t* buf = sm_i32 + cells_words + (staged ? stage_words : 0) + wave * buf_words;
     const int stride = gridDim.x * kAssignThreads;
     int base = blockIdx.x * kAssignThreads + wave * 64;
     // the wave's first candidates: their loads overlap the staging
@@ -1334,7 +1381,8 @@ __global__ __launch_bounds__(kAssignThreads) void k_assign_fill(
         pk = peaks[i];
         off = peak_voff[i];
     }
-    assign_stage(cell_start, g_cell_start, n_cells + 1, s_phi, sorted_phi, s_h, sorted_h, staged ? n_valid : 0, tid);
+    assign_stage<PACK>(cell_start, g_cell_start, n_cells + 1, s_stage, n_pad, sorted_phi, sorted_h,
+                       staged ? n_valid : 0, tid);
     __syncthreads();
     for (; base < n; base += stride) {
         const int i = base + lane;
@@ -1352,12 +1400,16 @@ __global__ __launch_bounds__(kAssignThreads) void k_assign_fill(
         if (i < n) {
             offsets[i] = (int32_t)min(cur_off, (int64_t)INT32_MAX);
             const int32_t* Ec = E + (size_t)cur.l * n_qpt + cur.k;
-            if (staged)
+            if (staged && PACK)
                 assign_candidate<true>(cur, cur_off, o0, Ec, n_layers, cell_bits, n_cols, M, F, cell_start,
-                                       (lds_cu32*)s_phi, (lds_ci32*)s_h, buf, buf_words, hit_idx, cap_pairs);
+                                       HitsPacked{(lds_cu32*)s_stage}, buf, buf_words, hit_idx, cap_pairs);
+            else if (staged)
+                assign_candidate<true>(cur, cur_off, o0, Ec, n_layers, cell_bits, n_cols, M, F, cell_start,
+                                       HitsSplit{(lds_cu32*)s_stage, (lds_ci32*)(s_stage + n_pad)}, buf, buf_words,
+                                       hit_idx, cap_pairs);
             else
                 assign_candidate<false>(cur, cur_off, o0, Ec, n_layers, cell_bits, n_cols, M, F, cell_start,
-                                        sorted_phi, sorted_h, buf, buf_words, hit_idx, cap_pairs);
+                                        HitsGlobal{sorted_phi, sorted_h}, buf, buf_words, hit_idx, cap_pairs);
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
@@ -1798,21 +1850,18 @@ void launch_assign(const hough_plan* p, const Events& ev, int n_events, const ho
     const int64_t want = ((int64_t)cap_peaks + kAssignThreads - 1) / kAssignThreads;
     const int per_event_cap = n_events > 1 ? 64 : 2 * 256;
     const unsigned nblk = (unsigned)(want < per_event_cap ? want : per_event_cap);
-    // LDS: per-wave list buffers, the cell table, then the staged sorted hits (8 bytes each) in
-    // what is left; every part a multiple of 16 bytes
+    // the kernel lays out its LDS per event (cell table, staged hits, wave buffers)
     const int cells_words = (p->n_cells + 1 + 3) & ~3;
-    const size_t cells_bytes = 4 * (size_t)cells_words;
-    int buf_words = (int)((kLdsBytes - cells_bytes) / 4 / (kAssignThreads / 64)) & ~63;
-    buf_words = buf_words > kAssignBufMax ? kAssignBufMax : buf_words;
-    const size_t used = 4 * (size_t)(kAssignThreads / 64) * buf_words + cells_bytes;
-    // (the 8-entry window scan reads up to 7 entries past the last staged angle, into the hit
-    // indices that follow: at least 16 of them)
-    int stage_hits = used < (size_t)kLdsBytes ? (int)(((size_t)kLdsBytes - used) / 8) & ~3 : 0;
-    if (stage_hits < 16) stage_hits = 0;
-    const size_t lds = used + 8 * (size_t)stage_hits;
-    hipLaunchKernelGGL(k_assign_fill, dim3(nblk, n_events), dim3(kAssignThreads), lds, stream, ev, peaks, peak_stride,
-                       cap_peaks, st, p->d_E, p->n_layers, p->cell_bits, p->n_cols, p->g.n_qpt, p->M, p->F, ws, O,
-                       offsets, hit_idx, cap_pairs, buf_words, cells_words, stage_hits);
+    const int lds_words = kLdsBytes / 4;
+    // one packed word per staged hit: angles of at most 16 bits and hit indices below 2^16
+    if (p->M <= 16 && p->g.max_hits_per_event <= 65536)
+        hipLaunchKernelGGL(k_assign_fill<true>, dim3(nblk, n_events), dim3(kAssignThreads), kLdsBytes, stream, ev,
+                           peaks, peak_stride, cap_peaks, st, p->d_E, p->n_layers, p->cell_bits, p->n_cols,
+                           p->g.n_qpt, p->M, p->F, ws, O, offsets, hit_idx, cap_pairs, lds_words, cells_words);
+    else
+        hipLaunchKernelGGL(k_assign_fill<false>, dim3(nblk, n_events), dim3(kAssignThreads), kLdsBytes, stream, ev,
+                           peaks, peak_stride, cap_peaks, st, p->d_E, p->n_layers, p->cell_bits, p->n_cols,
+                           p->g.n_qpt, p->M, p->F, ws, O, offsets, hit_idx, cap_pairs, lds_words, cells_words);
 }
 
 void launch_zvote(const hough_plan* p, const Events& ev, int n_events, const float* z, const uint8_t* layer,
@@ -2058,7 +2107,11 @@ int hough_plan_create(const hough_geometry_t* geom, const hough_grid_t* grid, ho
         ae = hipFuncSetAttribute((const void*)k_vote<true, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                  kLdsBytes);
     if (ae == hipSuccess)
-        ae = hipFuncSetAttribute((const void*)k_assign_fill, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
+        ae = hipFuncSetAttribute((const void*)k_assign_fill<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 kLdsBytes);
+    if (ae == hipSuccess)
+        ae = hipFuncSetAttribute((const void*)k_assign_fill<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 kLdsBytes);
     if (ae == hipSuccess)
         ae = hipFuncSetAttribute((const void*)k_prep_bucket, hipFuncAttributeMaxDynamicSharedMemorySize,
                                  kLdsBytes - 1024);
