@@ -293,24 +293,27 @@ __global__ __launch_bounds__(256) void k_prep_hits(Events ev, const float* __res
     if (phi_out) phi_out[h0 + h] = phi;
 }
 
-// One workgroup per event: bucket the valid hits by cell (layer, top `cell_bits` bits of the angle)
-// and reset the event's status.
-//   1. LDS histogram over cells, counting bad hits;
-//   2. exclusive scan -> cell_start, hit-vote total from the per-layer counts;
-//   3. scatter into cell order (LDS cursors; arbitrary order inside a cell) of (angle, key),
-//      key = (layer << 24) | hit index: for an event of at most cap_h hits into LDS, where each
-//      hit is then ranked inside its cell by (angle, hit index) and written to sorted_phi /
-//      sorted_h (the event is then flagged sorted in misc word 1; a scatter of single words to
-//      random global addresses from one workgroup is slow); a larger event goes to tmp_phi /
-//      tmp_key for k_prep_rank.
+// Bucket the valid hits of an event by cell (layer, top `cell_bits` bits of the angle), sort them
+// by (layer, angle, hit index) and reset the event's status.  grid = (n_layers, events).
+// An event of at most cap_h hits (one pass in registers) is split by layer: workgroup L reads all
+// hits, counts those of earlier layers (its base) with wave ballots, histograms its layer's hits
+// over the layer's cells in LDS, scans the histogram -> cell_start, scatters its hits into LDS,
+// ranks each inside its cell by (angle, hit index) -- kRankBatch hits of a thread at a time, the
+// first 8 entries of their cells loaded together -- and writes sorted_phi / sorted_h nearly in
+// order; workgroup 0 also writes the status and flags the event sorted (misc word 1).
+// A larger event is bucketed by workgroup 0 alone: LDS histogram over all cells, scan, scatter
+// into cell order (arbitrary inside a cell) -> tmp_phi, tmp_key = (layer << 24) | hit index, for
+// k_prep_rank (a scatter of single words to random addresses from one workgroup is slow, which
+// is why small events do not take this path).
 // An event with more than max_hits hits is treated as empty and flagged.
 constexpr int kBucketUnroll = 16;  // hits per thread and pass: events up to 16384 hits stay in registers
 constexpr int kRankBatch = 4;      // hits a thread ranks inside their cells at once
+
 __global__ __launch_bounds__(kScanThreads) void k_prep_bucket(Events ev, int n_layers, int cell_bits, int M,
                                                               LayerTable LT, char* __restrict__ ws, WsOff O,
-                                                              hough_status_t* __restrict__ st_base, int cells_pad,
-                                                              int cap_h) {
-    // LDS: cursors [cells_pad], then (cap_h > 0) angles [cap_h + 8] and keys [cap_h + 8]
+                                                              hough_status_t* __restrict__ st_base, int cap_h) {
+    // LDS: cursors (all cells, or one layer's), then (per-layer path) angles [cap_h + 8] and hit
+    // indices [cap_h + 8]
     extern __shared__ int32_t cur[];
     __shared__ int64_t wsum[kScanThreads / 64];
     __shared__ int32_t layer_n[kMaxLayers];
@@ -323,14 +326,14 @@ __global__ __launch_bounds__(kScanThreads) void k_prep_bucket(Events ev, int n_l
     const uint32_t* phi32 = at<uint32_t>(w, O.phi32);
     const uint8_t* lay = at<uint8_t>(w, O.lay);
     int32_t* cell_start = at<int32_t>(w, O.cell_start);
-    uint32_t* tmp_phi = at<uint32_t>(w, O.tmp_phi);
-    int32_t* tmp_key = at<int32_t>(w, O.tmp_key);
     hough_status_t* st = st_base + e;
     const int tid = threadIdx.x;
     const int n_cells = n_layers << cell_bits;
+    const int cpl = 1 << cell_bits;  // cells per layer (<= 1024)
     const int cshift = 32 - cell_bits;
-    const bool resident = n <= kScanThreads * kBucketUnroll;  // one pass holds every hit
-    for (int i = tid; i < n_cells; i += kScanThreads) cur[i] = 0;
+    const bool per_layer = n <= kScanThreads * kBucketUnroll && n <= cap_h;
+    if (!per_layer && blockIdx.x != 0) return;
+    int32_t* sorted_flag = at<int32_t>(w, O.misc) + 1;
     uint8_t L[kBucketUnroll];
     uint32_t ph[kBucketUnroll];
     auto load = [&](int base) {
@@ -341,6 +344,116 @@ __global__ __launch_bounds__(kScanThreads) void k_prep_bucket(Events ev, int n_l
             ph[j] = h < n ? phi32[h] : 0u;
         }
     };
+    auto write_status = [&](int64_t bad_tot) {  // thread 0; layer_n holds every layer's count
+        int64_t votes = 0;
+        for (int Ly = 0; Ly < n_layers; ++Ly) votes += (int64_t)layer_n[Ly] * LT.valid_cols[Ly];
+        st->n_hits = n_given;
+        st->n_bad_hits = (int32_t)bad_tot;
+        st->n_votes = votes;
+        st->n_peaks = 0;
+        st->flags = n_given > ev.max_hits ? HOUGH_F_EVENT_TOO_LARGE : 0;
+        st->n_pairs = 0;
+    };
+    if (per_layer) {
+        const int myL = blockIdx.x;
+        for (int i = tid; i < cpl; i += kScanThreads) cur[i] = 0;
+        if (tid < kMaxLayers) layer_n[tid] = 0;
+        load(0);
+        __syncthreads();
+        int before = 0, bad = 0;
+#pragma unroll
+        for (int j = 0; j < kBucketUnroll; ++j) {
+            const int l = L[j];
+            bad += l == 0xFF ? 1 : 0;
+            before += l < myL ? 1 : 0;  // valid layers are < n_layers <= 32 < 0xFE
+            if (l == myL) atomicAdd(&cur[ph[j] >> cshift], 1);
+            if (blockIdx.x == 0 && l < n_layers) atomicAdd(&layer_n[l], 1);
+        }
+        __syncthreads();
+        // both counts in one workgroup sum (each < 2^31)
+        int64_t t_packed;
+        block_inclusive_scan((int64_t)before | ((int64_t)bad << 32), wsum, &t_packed);
+        const int64_t t_before = t_packed & 0xFFFFFFFFll, t_bad = t_packed >> 32;
+        // exclusive scan of the layer's histogram (one cell per thread) -> local cursors, cell_start
+        const int v = tid < cpl ? cur[tid] : 0;
+        int64_t t_mine;
+        const int excl = (int)(block_inclusive_scan(v, wsum, &t_mine) - v);
+        const int base = (int)t_before;
+        if (tid < cpl) {
+            cur[tid] = excl;
+            cell_start[myL * cpl + tid] = base + excl;
+        }
+        if (tid == 0 && myL == n_layers - 1) cell_start[n_cells] = base + (int)t_mine;
+        if (tid == 0 && blockIdx.x == 0) {
+            write_status(t_bad);
+            *sorted_flag = 1;
+        }
+        __syncthreads();
+        // scatter the layer's hits into LDS (positions relative to the layer's start)
+        uint32_t* s_phi = reinterpret_cast<uint32_t*>(cur + ((cpl + 3) & ~3));
+        int32_t* s_h = reinterpret_cast<int32_t*>(s_phi + cap_h + 8);
+#pragma unroll
+        for (int j = 0; j < kBucketUnroll; ++j) {
+            if (L[j] != myL) continue;
+            const int pos = atomicAdd(&cur[ph[j] >> cshift], 1);
+            s_phi[pos] = ph[j] >> (32 - M);
+            s_h[pos] = j * kScanThreads + tid;
+        }
+        __syncthreads();
+        // every cursor now holds the end of its cell, i.e. the start of the next one
+        uint32_t* sorted_phi = at<uint32_t>(w, O.sorted_phi) + base;
+        int32_t* sorted_h = at<int32_t>(w, O.sorted_h) + base;
+        const int nt = (int)t_mine;
+        const int lshift = M - cell_bits;
+        for (int q0 = tid; q0 < nt; q0 += kRankBatch * kScanThreads) {
+            uint32_t a[kRankBatch];
+            int32_t hh[kRankBatch], c0[kRankBatch], n_in[kRankBatch], rank[kRankBatch];
+#pragma unroll
+            for (int u = 0; u < kRankBatch; ++u) {
+                const int q = min(q0 + u * kScanThreads, nt - 1);
+                a[u] = s_phi[q];
+                hh[u] = s_h[q];
+            }
+#pragma unroll
+            for (int u = 0; u < kRankBatch; ++u) {
+                const int c = (int)(a[u] >> lshift);
+                c0[u] = c > 0 ? cur[c - 1] : 0;
+                n_in[u] = cur[c] - c0[u];
+            }
+#pragma unroll
+            for (int u = 0; u < kRankBatch; ++u) {
+                uint32_t b[8];
+                int32_t k2[8];
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    b[i] = s_phi[c0[u] + i];
+                    k2[i] = s_h[c0[u] + i];
+                }
+                int r = 0;
+#pragma unroll
+                for (int i = 0; i < 8; ++i)
+                    r += (int)((i < n_in[u]) & ((b[i] < a[u]) | ((b[i] == a[u]) & (k2[i] < hh[u]))));
+                rank[u] = r;
+            }
+#pragma unroll
+            for (int u = 0; u < kRankBatch; ++u) {
+                for (int j = 8; j < n_in[u]; ++j) {
+                    const uint32_t b = s_phi[c0[u] + j];
+                    rank[u] += (b < a[u] || (b == a[u] && s_h[c0[u] + j] < hh[u])) ? 1 : 0;
+                }
+                if (q0 + u * kScanThreads < nt) {
+                    sorted_phi[c0[u] + rank[u]] = a[u];
+                    sorted_h[c0[u] + rank[u]] = hh[u];
+                }
+            }
+        }
+        return;
+    }
+    // one workgroup for a larger event
+    uint32_t* tmp_phi = at<uint32_t>(w, O.tmp_phi);
+    int32_t* tmp_key = at<int32_t>(w, O.tmp_key);
+    const bool resident = n <= kScanThreads * kBucketUnroll;  // one pass holds every hit
+    for (int i = tid; i < n_cells; i += kScanThreads) cur[i] = 0;
     if (resident) load(0);
     __syncthreads();
     int32_t bad = 0;
@@ -377,83 +490,9 @@ __global__ __launch_bounds__(kScanThreads) void k_prep_bucket(Events ev, int n_l
     }
     __syncthreads();
     if (tid == 0) {
-        int64_t votes = 0;
-        for (int Ly = 0; Ly < n_layers; ++Ly) votes += (int64_t)layer_n[Ly] * LT.valid_cols[Ly];
-        st->n_hits = n_given;
-        st->n_bad_hits = (int32_t)bad_tot;
-        st->n_votes = votes;
-        st->n_peaks = 0;
-        st->flags = n_given > ev.max_hits ? HOUGH_F_EVENT_TOO_LARGE : 0;
-        st->n_pairs = 0;
+        write_status(bad_tot);
+        *sorted_flag = 0;
     }
-    int32_t* sorted_flag = at<int32_t>(w, O.misc) + 1;
-    if (resident && n <= cap_h) {
-        // scatter into LDS, rank inside the cell, write the sorted arrays (nearly in order)
-        uint32_t* s_phi = reinterpret_cast<uint32_t*>(cur + cells_pad);
-        int32_t* s_key = cur + cells_pad + cap_h + 8;
-#pragma unroll
-        for (int j = 0; j < kBucketUnroll; ++j) {
-            if (L[j] >= 0xFE) continue;
-            const int h = j * kScanThreads + tid;
-            const int pos = atomicAdd(&cur[((int)L[j] << cell_bits) | (int)(ph[j] >> cshift)], 1);
-            s_phi[pos] = ph[j] >> (32 - M);
-            s_key[pos] = ((int32_t)L[j] << 24) | h;
-        }
-        __syncthreads();
-        // every cursor now holds the end of its cell, i.e. the start of the next one.  Rank
-        // kRankBatch hits of a thread at a time, with the first 8 entries of each of their cells
-        // loaded together (the arrays keep 8 entries of slack); a longer cell continues one by one.
-        uint32_t* sorted_phi = at<uint32_t>(w, O.sorted_phi);
-        int32_t* sorted_h = at<int32_t>(w, O.sorted_h);
-        const int nt = (int)tot;
-        for (int q0 = tid; q0 < nt; q0 += kRankBatch * kScanThreads) {
-            uint32_t a[kRankBatch];
-            int32_t hh[kRankBatch], c0[kRankBatch], n_in[kRankBatch], rank[kRankBatch];
-#pragma unroll
-            for (int u = 0; u < kRankBatch; ++u) {
-                const int q = min(q0 + u * kScanThreads, nt - 1);
-                a[u] = s_phi[q];
-                const int32_t key = s_key[q];
-                hh[u] = key & 0xFFFFFF;
-                c0[u] = ((key >> 24) << cell_bits) | (int)(a[u] >> (M - cell_bits));  // the cell, for now
-            }
-#pragma unroll
-            for (int u = 0; u < kRankBatch; ++u) {
-                const int c = c0[u];
-                c0[u] = c > 0 ? cur[c - 1] : 0;
-                n_in[u] = cur[c] - c0[u];
-            }
-#pragma unroll
-            for (int u = 0; u < kRankBatch; ++u) {
-                uint32_t b[8];
-                int32_t k2[8];
-#pragma unroll
-                for (int i = 0; i < 8; ++i) {
-                    b[i] = s_phi[c0[u] + i];
-                    k2[i] = s_key[c0[u] + i];
-                }
-                int r = 0;
-#pragma unroll
-                for (int i = 0; i < 8; ++i)
-                    r += (int)((i < n_in[u]) & ((b[i] < a[u]) | ((b[i] == a[u]) & ((k2[i] & 0xFFFFFF) < hh[u]))));
-                rank[u] = r;
-            }
-#pragma unroll
-            for (int u = 0; u < kRankBatch; ++u) {
-                for (int j = 8; j < n_in[u]; ++j) {
-                    const uint32_t b = s_phi[c0[u] + j];
-                    rank[u] += (b < a[u] || (b == a[u] && (s_key[c0[u] + j] & 0xFFFFFF) < hh[u])) ? 1 : 0;
-                }
-                if (q0 + u * kScanThreads < nt) {
-                    sorted_phi[c0[u] + rank[u]] = a[u];
-                    sorted_h[c0[u] + rank[u]] = hh[u];
-                }
-            }
-        }
-        if (tid == 0) *sorted_flag = 1;
-        return;
-    }
-    if (tid == 0) *sorted_flag = 0;
     // scatter into cell order
     for (int base = 0; base < n; base += kScanThreads * kBucketUnroll) {
         if (!resident) load(base);
@@ -1729,8 +1768,8 @@ int launch_status() { return hipGetLastError() == hipSuccess ? HOUGH_OK : HOUGH_
 // Largest event (hits) the bucketing workgroup sorts in LDS: resident in one pass and with its
 // angles and keys beside the cell cursors in the LDS (0: none).
 int bucket_cap_hits(const hough_plan* p) {
-    const int cells_pad = (p->n_cells + 3) & ~3;
-    const long room = ((long)kLdsBytes - 4L * cells_pad - 1024) / 8 - 8;  // static LDS aside, 8 entries of slack
+    const int cpl_pad = ((1 << p->cell_bits) + 3) & ~3;
+    const long room = ((long)kLdsBytes - 4L * cpl_pad - 1024) / 8 - 8;  // static LDS aside, 8 entries of slack
     long cap = room < (long)kScanThreads * kBucketUnroll ? room : (long)kScanThreads * kBucketUnroll;
     cap = cap < p->g.max_hits_per_event ? cap : p->g.max_hits_per_event;
     return cap >= 64 ? (int)cap : 0;
@@ -1743,13 +1782,15 @@ void launch_prep(const hough_plan* p, const Events& ev, int n_events, int max_n,
     if (max_n > 0)
         hipLaunchKernelGGL(k_prep_hits, dim3((max_n + 255) / 256, n_events), dim3(256), 0, stream, ev, x, y, layer,
                            p->n_layers, p->cordic, ws, O, phi_out);
-    // events of at most cap_h hits are sorted inside the bucketing workgroup (LDS); the rank pass
+    // events of at most cap_h hits are sorted by one workgroup per layer (LDS); the rank pass
     // runs only if a larger event is possible
-    const int cells_pad = (p->n_cells + 3) & ~3;
     const int cap_h = bucket_cap_hits(p);
-    const size_t lds = 4 * (size_t)cells_pad + (cap_h > 0 ? 8 * ((size_t)cap_h + 8) : 0);
-    hipLaunchKernelGGL(k_prep_bucket, dim3(1, n_events), dim3(kScanThreads), lds, stream, ev, p->n_layers,
-                       p->cell_bits, p->M, p->layers, ws, O, st, cells_pad, cap_h);
+    const size_t lds_layer = cap_h > 0 ? 4 * ((((size_t)1 << p->cell_bits) + 3) & ~(size_t)3) + 8 * ((size_t)cap_h + 8)
+                                       : 0;
+    const size_t lds_all = 4 * (size_t)p->n_cells;
+    const size_t lds = lds_layer > lds_all ? lds_layer : lds_all;
+    hipLaunchKernelGGL(k_prep_bucket, dim3(p->n_layers, n_events), dim3(kScanThreads), lds, stream, ev,
+                       p->n_layers, p->cell_bits, p->M, p->layers, ws, O, st, cap_h);
     if (max_n > cap_h)
         hipLaunchKernelGGL(k_prep_rank, dim3((max_n + 255) / 256, n_events), dim3(256), 0, stream, ev, p->n_cells,
                            p->cell_bits, p->M, ws, O);
