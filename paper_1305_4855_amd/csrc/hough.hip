@@ -1110,62 +1110,60 @@ __global__ __launch_bounds__(kPScanThreads) void k_peaks_scan(Events ev, int64_t
 // the group's threads, and writes its candidates and their CSR offsets in linear order.
 constexpr int kWriteStrips = 8;
 constexpr int kWriteFirst = 4;  // candidates per thread whose values are loaded together
+constexpr int kWriteThreads = 256;
 
+// The flagged bins of one thread's strips and the values of its first kWriteFirst candidates
+// (their loads go out together; a bin with no candidate loads bin 0 of the range, unused).
 template <typename T>
-__global__ __launch_bounds__(256) void k_peaks_write(Events ev, const char* __restrict__ acc_base,
-                                                     size_t acc_stride, int64_t n_groups, int n_qpt, int n_phi,
-                                                     int group_lanes, int64_t n_strips, char* __restrict__ ws,
-                                                     WsOff O, hough_peak_t* __restrict__ peaks_base, int32_t cap) {
-    const int e = blockIdx.y;
-    const T* acc = reinterpret_cast<const T*>(acc_base + (size_t)e * acc_stride);
-    char* w = event_ws(ws, ev, e);
-    const uint8_t* flags = at<uint8_t>(w, O.flags);
-    const int32_t* grp_off = at<int32_t>(w, O.grp_off);
-    const int64_t* grp_voff = at<int64_t>(w, O.grp_voff);
-    int64_t* peak_voff = at<int64_t>(w, O.peak_voff);
-    hough_peak_t* peaks = peaks_base + (size_t)e * cap;
-    const int strips = n_phi / kStrip;
-    const int sp = min(kWriteStrips, group_lanes);  // strips per thread (both powers of two)
-    const int tpg = group_lanes / sp;              // threads per group (1..8)
-    const int64_t n_thr = n_strips / sp;
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const bool live = t < n_thr;
-    const int64_t strip0 = (live ? t : n_thr - 1) * sp;
-    // the group's CSR bases do not depend on the flags: load them together
-    const int64_t g = strip0 / group_lanes;
-    const int32_t g_off = grp_off[g];
-    const int64_t g_voff = grp_voff[g];
-    uint64_t bits = 0;
-    if (live) {
-        if (sp == kWriteStrips) {
-            bits = *reinterpret_cast<const uint64_t*>(flags + strip0);
-        } else {
-            for (int i = 0; i < sp; ++i) bits |= (uint64_t)flags[strip0 + i] << (8 * i);
-        }
-    }
-    const int64_t row = strip0 / strips;
-    const int s0 = (int)(strip0 - row * strips);
-    const T* r = acc + row * n_phi + s0 * kStrip;
-    const int32_t cnt = __popcll(bits);
-    // the first kWriteFirst candidates' bins and values: their loads go out together (a bin with
-    // no candidate loads bin 0 of the thread's range and is not used)
+struct WriteItem {
+    bool live;
+    uint64_t bits, rest;
+    int64_t row;
+    int s0;
+    const T* r;
+    int32_t cnt, vsum;
     int idx[kWriteFirst];
     int32_t val[kWriteFirst];
-    uint64_t rest = bits;
+};
+
+template <typename T>
+__device__ __forceinline__ void write_load(const T* acc, const uint8_t* flags, int64_t t, int64_t n_thr, int sp,
+                                           int strips, int n_phi, WriteItem<T>& it) {
+    it.live = t < n_thr;
+    const int64_t strip0 = (it.live ? t : n_thr - 1) * sp;
+    it.bits = 0;
+    if (it.live) {
+        if (sp == kWriteStrips) {
+            it.bits = *reinterpret_cast<const uint64_t*>(flags + strip0);
+        } else {
+            for (int i = 0; i < sp; ++i) it.bits |= (uint64_t)flags[strip0 + i] << (8 * i);
+        }
+    }
+    it.row = strip0 / strips;
+    it.s0 = (int)(strip0 - it.row * strips);
+    it.r = acc + it.row * n_phi + it.s0 * kStrip;
+    it.cnt = __popcll(it.bits);
+    it.rest = it.bits;
 #pragma unroll
     for (int j = 0; j < kWriteFirst; ++j) {
-        idx[j] = rest ? __ffsll((long long)rest) - 1 : 0;
-        rest &= rest - 1;
+        it.idx[j] = it.rest ? __ffsll((long long)it.rest) - 1 : 0;
+        it.rest &= it.rest - 1;
     }
 #pragma unroll
-    for (int j = 0; j < kWriteFirst; ++j) val[j] = (int32_t)r[idx[j]];
-    int32_t vsum = 0;
+    for (int j = 0; j < kWriteFirst; ++j) it.val[j] = (int32_t)it.r[it.idx[j]];
+    it.vsum = 0;
 #pragma unroll
-    for (int j = 0; j < kWriteFirst; ++j) vsum += j < cnt ? val[j] : 0;
-    for (uint64_t b = rest; b; b &= b - 1) vsum += (int32_t)r[__ffsll((long long)b) - 1];
-    // inclusive prefix of candidate and vote counts over the group's threads
+    for (int j = 0; j < kWriteFirst; ++j) it.vsum += j < it.cnt ? it.val[j] : 0;
+    for (uint64_t b = it.rest; b; b &= b - 1) it.vsum += (int32_t)it.r[__ffsll((long long)b) - 1];
+}
+
+// In-group prefix over the group's tpg threads (consecutive lanes, all active), then the
+// thread's candidates written from the group's CSR bases.
+template <typename T>
+__device__ __forceinline__ void write_emit(const WriteItem<T>& it, int32_t g_off, int64_t g_voff, int tpg, int n_qpt,
+                                           hough_peak_t* peaks, int64_t* peak_voff, int32_t cap) {
     const int gl = threadIdx.x & (tpg - 1);
-    int32_t inc = cnt, vinc = vsum;
+    int32_t inc = it.cnt, vinc = it.vsum;
     for (int o = 1; o < tpg; o <<= 1) {
         const int32_t a = __shfl_up(inc, o, tpg);
         const int32_t c = __shfl_up(vinc, o, tpg);
@@ -1174,17 +1172,17 @@ __global__ __launch_bounds__(256) void k_peaks_write(Events ev, const char* __re
             vinc += c;
         }
     }
-    if (!live || bits == 0) return;
-    int32_t pos = g_off + inc - cnt;
-    int64_t voff = g_voff + vinc - vsum;
-    const int k = (int)(row % n_qpt);
-    const int l = (int)(row / n_qpt);
+    if (!it.live || it.bits == 0) return;
+    int32_t pos = g_off + inc - it.cnt;
+    int64_t voff = g_voff + vinc - it.vsum;
+    const int k = (int)(it.row % n_qpt);
+    const int l = (int)(it.row / n_qpt);
     auto emit = [&](int i, int32_t v) {
         if (pos < cap) {
             hough_peak_t pk;
             pk.l = l;
             pk.k = k;
-            pk.b = s0 * kStrip + i;
+            pk.b = it.s0 * kStrip + i;
             pk.votes = v;
             peaks[pos] = pk;
             peak_voff[pos] = voff;
@@ -1194,11 +1192,146 @@ __global__ __launch_bounds__(256) void k_peaks_write(Events ev, const char* __re
     };
 #pragma unroll
     for (int j = 0; j < kWriteFirst; ++j)
-        if (j < cnt) emit(idx[j], val[j]);
-    for (uint64_t b = rest; b; b &= b - 1) {
+        if (j < it.cnt) emit(it.idx[j], it.val[j]);
+    for (uint64_t b = it.rest; b; b &= b - 1) {
         const int i = __ffsll((long long)b) - 1;
-        emit(i, (int32_t)r[i]);
+        emit(i, (int32_t)it.r[i]);
     }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kWriteThreads) void k_peaks_write(Events ev, const char* __restrict__ acc_base,
+                                                               size_t acc_stride, int64_t n_groups, int n_qpt,
+                                                               int n_phi, int group_lanes, int64_t n_strips,
+                                                               char* __restrict__ ws, WsOff O,
+                                                               hough_peak_t* __restrict__ peaks_base, int32_t cap) {
+    const int e = blockIdx.y;
+    const T* acc = reinterpret_cast<const T*>(acc_base + (size_t)e * acc_stride);
+    char* w = event_ws(ws, ev, e);
+    const uint8_t* flags = at<uint8_t>(w, O.flags);
+    const int32_t* grp_off = at<int32_t>(w, O.grp_off);
+    const int64_t* grp_voff = at<int64_t>(w, O.grp_voff);
+    const int strips = n_phi / kStrip;
+    const int sp = min(kWriteStrips, group_lanes);  // strips per thread (both powers of two)
+    const int tpg = group_lanes / sp;              // threads per group (1..8)
+    const int64_t n_thr = n_strips / sp;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    // the group's CSR bases do not depend on the flags: load them together
+    const int64_t g = (t < n_thr ? t : n_thr - 1) / tpg;
+    const int32_t g_off = grp_off[g];
+    const int64_t g_voff = grp_voff[g];
+    WriteItem<T> it;
+    write_load(acc, flags, t, n_thr, sp, strips, n_phi, it);
+    write_emit(it, g_off, g_voff, tpg, n_qpt, peaks_base + (size_t)e * cap, at<int64_t>(w, O.peak_voff), cap);
+}
+
+// The CSR scan and the writer in one pass for a single event or a small batch (grid as the
+// writer's): a workgroup owns kWriteThreads / tpg whole groups; it sums the candidate counts
+// and votes of every group before its own (all loads issued at once, then one workgroup
+// reduction), scans its own groups in LDS, and writes their candidates.  The workgroup holding
+// the last group sets the event's totals.  Every workgroup re-reads the counts before it, which
+// is cheap for one event and not for hundreds, so large batches use the two kernels above.
+constexpr int kCarryUnroll = 8;         // 16-byte loads per thread and round of the carry-in sum
+constexpr int kScanWriteMaxEvents = 4;  // batches up to this size take the one-pass form
+
+template <typename T>
+__global__ __launch_bounds__(kWriteThreads) void k_peaks_scan_write(Events ev, const char* __restrict__ acc_base,
+                                                                    size_t acc_stride, int64_t n_groups, int n_qpt,
+                                                                    int n_phi, int group_lanes, int64_t n_strips,
+                                                                    char* __restrict__ ws, WsOff O,
+                                                                    hough_peak_t* __restrict__ peaks_base,
+                                                                    int32_t cap, hough_status_t* __restrict__ st_base) {
+    __shared__ int64_t red_c[kWriteThreads / 64], red_v[kWriteThreads / 64];
+    __shared__ int32_t s_off[kWriteThreads];
+    __shared__ int64_t s_voff[kWriteThreads];
+    const int e = blockIdx.y;
+    const T* acc = reinterpret_cast<const T*>(acc_base + (size_t)e * acc_stride);
+    char* w = event_ws(ws, ev, e);
+    const uint8_t* flags = at<uint8_t>(w, O.flags);
+    const int32_t* grp_count = at<int32_t>(w, O.grp_count);
+    const int32_t* grp_votes = at<int32_t>(w, O.grp_votes);
+    const int strips = n_phi / kStrip;
+    const int sp = min(kWriteStrips, group_lanes);
+    const int tpg = group_lanes / sp;
+    const int64_t n_thr = n_strips / sp;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wv = tid >> 6;
+    const int gpb = kWriteThreads / tpg;                 // groups per workgroup (a multiple of 32)
+    const int64_t gb = (int64_t)blockIdx.x * gpb;        // first group of this workgroup
+    const int64_t t = (int64_t)blockIdx.x * kWriteThreads + tid;
+    WriteItem<T> it;
+    write_load(acc, flags, t, n_thr, sp, strips, n_phi, it);
+    // own groups' counts, and the carry-in over [0, gb) (gb is a multiple of 4)
+    const bool own = tid < gpb && gb + tid < n_groups;
+    const int32_t oc = own ? grp_count[gb + tid] : 0;
+    const int32_t ov = own ? grp_votes[gb + tid] : 0;
+    int64_t pc = 0, pv = 0;
+    for (int64_t i0 = 4 * (int64_t)tid; i0 < gb; i0 += 4 * kWriteThreads * kCarryUnroll) {
+        int4 a[kCarryUnroll], b[kCarryUnroll];
+#pragma unroll
+        for (int u = 0; u < kCarryUnroll; ++u) {
+            const int64_t j = min(i0 + 4 * (int64_t)kWriteThreads * u, gb - 4);
+            a[u] = *reinterpret_cast<const int4*>(grp_count + j);
+            b[u] = *reinterpret_cast<const int4*>(grp_votes + j);
+        }
+#pragma unroll
+        for (int u = 0; u < kCarryUnroll; ++u) {
+            if (i0 + 4 * (int64_t)kWriteThreads * u < gb) {
+                pc += (int64_t)a[u].x + a[u].y + a[u].z + a[u].w;
+                pv += (int64_t)b[u].x + b[u].y + b[u].z + b[u].w;
+            }
+        }
+    }
+    // inclusive scans of the own counts inside each wave, totals of the carry per wave
+    int32_t ic = oc;
+    int64_t iv = ov;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int32_t uc = __shfl_up(ic, o, 64);
+        const int64_t uv = __shfl_up(iv, o, 64);
+        if (lane >= o) {
+            ic += uc;
+            iv += uv;
+        }
+        pc += __shfl_xor(pc, o, 64);
+        pv += __shfl_xor(pv, o, 64);
+    }
+    __shared__ int64_t wown_c[kWriteThreads / 64], wown_v[kWriteThreads / 64];
+    if (lane == 63) {
+        wown_c[wv] = ic;
+        wown_v[wv] = iv;
+    }
+    if (lane == 0) {
+        red_c[wv] = pc;
+        red_v[wv] = pv;
+    }
+    __syncthreads();
+    int64_t carry_c = 0, carry_v = 0, pre_c = 0, pre_v = 0, tot_c = 0, tot_v = 0;
+#pragma unroll
+    for (int k = 0; k < kWriteThreads / 64; ++k) {
+        carry_c += red_c[k];
+        carry_v += red_v[k];
+        pre_c += k < wv ? wown_c[k] : 0;
+        pre_v += k < wv ? wown_v[k] : 0;
+        tot_c += wown_c[k];
+        tot_v += wown_v[k];
+    }
+    if (tid < gpb) {
+        s_off[tid] = (int32_t)min(carry_c + pre_c + ic - oc, (int64_t)INT32_MAX);
+        s_voff[tid] = carry_v + pre_v + iv - ov;
+    }
+    if (tid == 0 && gb < n_groups && gb + gpb >= n_groups) {  // the workgroup holding the last group
+        const int64_t total = carry_c + tot_c;
+        hough_status_t* st = st_base + e;
+        st->n_peaks = (int32_t)min(total, (int64_t)INT32_MAX);
+        *at<int32_t>(w, O.misc) = (int32_t)min(total, (int64_t)cap);
+        if (total > cap) atomicOr(&st->flags, HOUGH_F_PEAK_OVERFLOW);
+    }
+    __syncthreads();
+    const int gi = (int)(((t < n_thr ? t : n_thr - 1) / tpg) - gb);  // this thread's group, local
+    const int gl = min(max(gi, 0), gpb - 1);
+    write_emit(it, s_off[gl], s_voff[gl], tpg, n_qpt, peaks_base + (size_t)e * cap, at<int64_t>(w, O.peak_voff), cap);
 }
 
 // ------------------------------------------------------------------ assign
@@ -1851,7 +1984,7 @@ void launch_peaks(const hough_plan* p, const Events& ev, int n_events, const voi
     const int64_t groups = peak_groups(p);
     const dim3 gm((unsigned)(((mark_threads + kMarkThreads - 1) / kMarkThreads + 7) / 8 * 8), n_events);  // multiple of 8: see k_peaks_mark
     const int wsp = gl < kWriteStrips ? gl : kWriteStrips;
-    const dim3 gw((unsigned)((n_strips / wsp + 255) / 256), n_events);
+    const dim3 gw((unsigned)((n_strips / wsp + kWriteThreads - 1) / kWriteThreads), n_events);
     const char* a = static_cast<const char*>(acc);
     const int16_t* z16 = static_cast<const int16_t*>(p->d_zero);
     const int32_t* z32 = static_cast<const int32_t*>(p->d_zero);
@@ -1869,6 +2002,15 @@ void launch_peaks(const hough_plan* p, const Events& ev, int n_events, const voi
     else
         hipLaunchKernelGGL((k_peaks_mark<int16_t, false>), gm, mb, 0, stream, ev, a, acc_stride, z16, threshold, nd,
                            nq, nph, gl, planes, ws, O);
+    if (n_events <= kScanWriteMaxEvents) {  // scan and writer in one pass
+        if (p->g.acc_bits == 32)
+            hipLaunchKernelGGL(k_peaks_scan_write<int32_t>, gw, dim3(kWriteThreads), 0, stream, ev, a, acc_stride,
+                               groups, p->g.n_qpt, p->g.n_phi, gl, n_strips, ws, O, peaks, cap, st);
+        else
+            hipLaunchKernelGGL(k_peaks_scan_write<int16_t>, gw, dim3(kWriteThreads), 0, stream, ev, a, acc_stride,
+                               groups, p->g.n_qpt, p->g.n_phi, gl, n_strips, ws, O, peaks, cap, st);
+        return;
+    }
     // workgroups per event: enough to spread a small batch over the CUs, each with >= one tile
     int64_t chunks = 2 * (int64_t)p->n_cu / n_events;
     const int64_t by_size = groups / ((int64_t)kPScanThreads * kPScanPer);
@@ -1878,10 +2020,10 @@ void launch_peaks(const hough_plan* p, const Events& ev, int n_events, const voi
     hipLaunchKernelGGL(k_peaks_scan, dim3((unsigned)chunks, n_events), dim3(kPScanThreads), 0, stream, ev, groups,
                        cap, ws, O, st);
     if (p->g.acc_bits == 32)
-        hipLaunchKernelGGL(k_peaks_write<int32_t>, gw, dim3(256), 0, stream, ev, a, acc_stride, groups, p->g.n_qpt,
+        hipLaunchKernelGGL(k_peaks_write<int32_t>, gw, dim3(kWriteThreads), 0, stream, ev, a, acc_stride, groups, p->g.n_qpt,
                            p->g.n_phi, gl, n_strips, ws, O, peaks, cap);
     else
-        hipLaunchKernelGGL(k_peaks_write<int16_t>, gw, dim3(256), 0, stream, ev, a, acc_stride, groups, p->g.n_qpt,
+        hipLaunchKernelGGL(k_peaks_write<int16_t>, gw, dim3(kWriteThreads), 0, stream, ev, a, acc_stride, groups, p->g.n_qpt,
                            p->g.n_phi, gl, n_strips, ws, O, peaks, cap);
 }
 
