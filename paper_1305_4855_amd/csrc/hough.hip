@@ -5,36 +5,40 @@
 // implementation.  Every kernel handles a batch of events (blockIdx.y or a
 // work queue selects the event); a single-event call is the batch of one.
 //   prep    per-hit Q16.16 + integer CORDIC azimuth (one thread per hit), then
-//           one workgroup per event buckets the valid hits by (layer, azimuth
-//           cell) in LDS (histogram, scan, scatter) and one thread per hit
-//           ranks it inside its cell by (angle, hit index): the hits end up
-//           sorted by (layer, angle, hit); the vote reads each layer's hits as
-//           one contiguous run, the assignment finds a bin's hits as one run;
+//           the valid hits are sorted by (layer, angle, hit) through cells
+//           (layer, top azimuth bits): an event of one pass gets one workgroup
+//           per layer (LDS histogram, scan, scatter, in-cell rank); a larger one
+//           is bucketed by one workgroup and ranked by one thread per hit.  The
+//           vote reads each layer's hits as one contiguous run, the assignment
+//           finds a bin's hits as one run;
 //   vote    one workgroup per (event, slab of 64 (l, k) columns) holds the
-//           whole phi0 range of its columns in LDS as [bin][column] (one
-//           256-byte row per bin), loops over all hits of the event layer by
-//           layer and adds each vote with a conflict-free ds_add_u32: one lane
-//           per column, one hit per instruction, 2 VALU ops + 1 LDS atomic per
-//           vote; the slab is then written once to HBM (no global atomics,
-//           slabs are disjoint, integer sums are order independent).  Batches
-//           run it as a persistent kernel pulling (event, slab) items from a
-//           device work queue, largest events first;
+//           whole phi0 range of its columns in LDS as [bin][column] (16-bit
+//           counters, columns c and c + 32 sharing a dword: one 128-byte row per
+//           bin), loops over all hits of the event layer by layer and adds each
+//           vote with a conflict-free ds_add_u32: one lane per column, one hit
+//           per instruction (v_readlane broadcast, subtract, and-or, atomic);
+//           the slab is then written once to HBM through a padded LDS tile (no
+//           global atomics, slabs are disjoint, integer sums are order
+//           independent).  Batches run it as a persistent kernel pulling
+//           (event, slab) items from a device work queue, largest events first;
 //   peaks   one thread per 8-bin strip of a column walks a range of d0 planes
-//           keeping a 3-plane window in registers (separable 3-wide maxima),
-//           writes one flag byte per strip and per-group candidate and vote
-//           counts; one tiled scan per event and a write pass compact the
-//           candidates in increasing linear index together with their CSR
-//           offsets (the prefix sums of their vote counts);
+//           keeping a 3-plane window in registers (separable 3-wide maxima,
+//           edge bins from the neighbouring lanes), writes one flag byte per
+//           strip and per-group candidate and vote counts; a scan of the group
+//           counts and a write pass (one fused pass for single events and small
+//           batches) compact the candidates in increasing linear index together
+//           with their CSR offsets (the prefix sums of their vote counts);
 //   assign  each candidate copies, layer by layer, the run of sorted hits
-//           whose angle falls into its phi0 window; the candidates of a wave
-//           assemble their stretch of the CSR list in LDS and store it
-//           coalesced;
-//   zvote   (second stage in r-z) one wave per candidate: with H <= 64 hits,
-//           min(16, 64 / H) rows of the cot(theta) x z0 grid are voted at once,
-//           one lane per (row, hit), into per-row LDS histograms whose words
-//           carry their own tie-break key, so the argmax is tracked from the
-//           atomic's return value and each touched word is restored right
-//           after the vote (no clearing pass, no scan of the grid).
+//           whose angle falls into its phi0 window, from hits staged in LDS
+//           (one packed word per hit on grids of at most 16 angle bits); the
+//           candidates of a wave assemble their stretch of the CSR list in LDS
+//           and store it coalesced;
+//   zvote   (second stage in r-z) a wave takes two candidates at a time: with
+//           H <= 64 hits, min(8, 64 / H) rows of the cot(theta) x z0 grid are
+//           voted at once, one lane per (row, hit), into per-row LDS histograms
+//           whose words carry their own tie-break key, so the argmax is tracked
+//           from the atomic's return value and each touched word is restored
+//           right after the vote (no clearing pass, no scan of the grid).
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
@@ -55,7 +59,7 @@ constexpr int kVoteMaxThreads = 1024;
 constexpr int kVoteCols = 64;       // columns per vote slab (one per lane)
 constexpr int kStrip = 8;           // phi0 bins per peak-finder thread
 constexpr int kScanThreads = 1024;
-constexpr int kMaxCells = 32768;    // LDS histogram of the prep bucketing (128 KiB)
+constexpr int kMaxCells = 32768;    // cells of a plan: the one-workgroup bucketing keeps all in LDS (128 KiB)
 constexpr int kAssignThreads = 1024;
 constexpr int kAssignBufMax = 2048;  // words of CSR list buffered per wave (less when the LDS is short)
 constexpr int kAssignBufMin = 256;   // buffer below which an event's hits are not staged in LDS
