@@ -464,3 +464,58 @@ void or_zvote(const or_cfg_t* g, int32_t n, const float* z, const uint8_t* layer
     free(zacc);
     free(C);
 }
+
+/* Track fit of each candidate's hits (Sec. "Preliminary Results", fitting paragraph: the hits
+ * of a candidate go on to a fit; the paper names no method).  Reading: the algebraic circle fit
+ * of Kasa (I. Kasa, "A circle fitting procedure and its error analysis", IEEE Trans. Instrum.
+ * Meas. 25 (1976) 8-14): the circle x^2 + y^2 + a x + b y + c = 0 minimising
+ *     sum_i (x_i^2 + y_i^2 + a x_i + b y_i + c)^2,
+ * i.e. the 3x3 normal equations
+ *     | Sxx Sxy Sx | |a|     | Sxz |
+ *     | Sxy Syy Sy | |b| = - | Syz |      (z = x^2 + y^2, S = sum over the hits)
+ *     | Sx  Sy  N  | |c|     | Sz  |
+ * solved by Cramer's rule; centre (-a/2, -b/2), R^2 = xc^2 + yc^2 - c.  The sums run over the
+ * candidate's hit list in its order, hits in cm (float32 converted to double).  Fewer than 3 hits
+ * or a zero determinant: centre (0, 0), R^2 = -1.  out[4 p .. 4 p + 3] = xc, yc, R^2, N. */
+void or_fit(const float* x, const float* y, int32_t n_peaks, const int64_t* offsets, const int32_t* hit_idx,
+            double* out)
+{
+    int32_t p;
+    for (p = 0; p < n_peaks; p++) {
+        double sx = 0.0, sy = 0.0, sxx = 0.0, sxy = 0.0, syy = 0.0, sz = 0.0, sxz = 0.0, syz = 0.0;
+        double N, det, r0, r1, r2, a, b, c, xc, yc;
+        int64_t q;
+        for (q = offsets[p]; q < offsets[p + 1]; q++) {
+            double X = (double)x[hit_idx[q]], Y = (double)y[hit_idx[q]];
+            double Z = X * X + Y * Y;
+            sx += X;
+            sy += Y;
+            sxx += X * X;
+            sxy += X * Y;
+            syy += Y * Y;
+            sz += Z;
+            sxz += X * Z;
+            syz += Y * Z;
+        }
+        N = (double)(offsets[p + 1] - offsets[p]);
+        det = sxx * (syy * N - sy * sy) - sxy * (sxy * N - sy * sx) + sx * (sxy * sy - syy * sx);
+        out[4 * p + 3] = N;
+        if (N < 3.0 || det == 0.0) {
+            out[4 * p + 0] = 0.0;
+            out[4 * p + 1] = 0.0;
+            out[4 * p + 2] = -1.0;
+            continue;
+        }
+        r0 = -sxz;
+        r1 = -syz;
+        r2 = -sz;
+        a = (r0 * (syy * N - sy * sy) - sxy * (r1 * N - sy * r2) + sx * (r1 * sy - syy * r2)) / det;
+        b = (sxx * (r1 * N - r2 * sy) - r0 * (sxy * N - sy * sx) + sx * (sxy * r2 - r1 * sx)) / det;
+        c = (sxx * (syy * r2 - sy * r1) - sxy * (sxy * r2 - r1 * sx) + r0 * (sxy * sy - syy * sx)) / det;
+        xc = -a / 2.0;
+        yc = -b / 2.0;
+        out[4 * p + 0] = xc;
+        out[4 * p + 1] = yc;
+        out[4 * p + 2] = xc * xc + yc * yc - c;
+    }
+}

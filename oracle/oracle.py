@@ -87,6 +87,8 @@ def load(path: str) -> C.CDLL:
     L.or_cot_centre_q16.restype = C.c_int64; L.or_cot_centre_q16.argtypes = [P, C.c_int32]
     L.or_zvote.restype = None
     L.or_zvote.argtypes = [P, C.c_int32, P, P, C.c_int32, P, P, P, P]
+    L.or_fit.restype = None
+    L.or_fit.argtypes = [P, P, C.c_int32, P, P, P]
     return L
 
 
@@ -229,3 +231,28 @@ def zvote(cfg: Cfg, ev, pk: np.ndarray, offs: np.ndarray, hit_idx: np.ndarray):
     out = np.zeros((pk.shape[0], 3), dtype=np.int32)
     lib().or_zvote(cfg.ptr, z.shape[0], _p(z), _p(lay), pk.shape[0], _p(pk), _p(offs), _p(hit_idx), _p(out))
     return out
+
+
+def fit(ev, offs: np.ndarray, hit_idx: np.ndarray) -> np.ndarray:
+    """Algebraic (Kasa) circle fit of each candidate's hit list: rows (xc, yc, R^2, n_hits);
+    R^2 = -1 for fewer than 3 hits or a singular system."""
+    x, y, _ = _hits(ev)
+    offs = np.ascontiguousarray(offs, dtype=np.int64)
+    hit_idx = np.ascontiguousarray(hit_idx, dtype=np.int32)
+    n = offs.shape[0] - 1
+    out = np.zeros((max(n, 0), 4), dtype=np.float64)
+    if n > 0:
+        lib().or_fit(_p(x), _p(y), n, _p(offs), _p(hit_idx), _p(out))
+    return out
+
+
+def fit_points(x, y) -> np.ndarray:
+    """The fit of one list made of the given points (float32 coordinates)."""
+    x = np.ascontiguousarray(x, dtype=np.float32)
+    y = np.ascontiguousarray(y, dtype=np.float32)
+    offs = np.array([0, x.shape[0]], dtype=np.int64)
+    idx = np.arange(x.shape[0], dtype=np.int32)
+    out = np.zeros((1, 4), dtype=np.float64)
+    lib().or_fit(_p(x), _p(y), 1, _p(offs), _p(idx if idx.size else np.zeros(1, np.int32)), _p(out))
+    return out[0]
+

@@ -45,6 +45,10 @@ MUTATIONS = {
     "arclen_half": ("s = (2.0 / fabs(c)) * asin(u);", "s = (1.0 / fabs(c)) * asin(u);"),
     "arclen_chord_sign": ("Lc2 = r * r + d * d - 2.0 * d * r * A;", "Lc2 = r * r + d * d + 2.0 * d * r * A;"),
     "zvote_tie_last": ("if (zacc[i] > bestv) {", "if (zacc[i] >= bestv && zacc[i] > 0) {"),
+    "fit_det_sign": ("det = sxx * (syy * N - sy * sy) - sxy * (sxy * N - sy * sx)",
+                     "det = sxx * (syy * N - sy * sy) + sxy * (sxy * N - sy * sx)"),
+    "fit_rhs_sign": ("r0 = -sxz;", "r0 = sxz;"),
+    "fit_centre_factor": ("xc = -a / 2.0;", "xc = -a;"),
 }
 
 SKIP = {"test_sample_table_vs_mpmath_c2"}  # slow; the c1 and sampled c4 tables run instead

@@ -652,3 +652,103 @@ def test_zvote_single_hit_tie_rule(oracle_mod):
     out = O.zvote(g, ev, np.array([[l, k, 0, 1]], np.int32), np.array([0, 1], np.int64),
                   np.array([0], np.int32))
     assert tuple(out[0]) == (0, j, 1)
+
+
+# -------------------------------------------------------------------- fit --
+# The track fit (fitting paragraph of Sec. "Preliminary Results"; reading: Kasa's algebraic
+# circle fit).  Pins: exact results on integer points of a circle, the circumcircle of three
+# points, an independent least-squares solve (numpy's SVD-based lstsq of the same algebraic
+# problem), translation covariance, degenerate lists, and generated prompt tracks.
+def test_fit_integer_points_exact(oracle_mod):
+    O = oracle_mod
+    # points with integer coordinates on circles of radius 5 and 13: every sum, determinant and
+    # quotient of the fit is exact in double
+    base5 = [(3, 4), (4, 3), (5, 0), (0, 5), (-3, 4), (-4, -3), (0, -5)]
+    base13 = [(5, 12), (12, 5), (13, 0), (-5, 12), (-12, -5), (0, -13)]
+    for pts, r2 in ((base5, 25.0), (base13, 169.0)):
+        for cx, cy in ((0, 0), (10, -7), (-40, 33)):
+            x = [px + cx for px, _ in pts]
+            y = [py + cy for _, py in pts]
+            xc, yc, R2, n = O.fit_points(x, y)
+            assert (xc, yc, R2, n) == (cx, cy, r2, len(pts))
+
+
+def test_fit_three_points_is_circumcircle(oracle_mod):
+    O = oracle_mod
+    rng = np.random.default_rng(41)
+    for _ in range(200):
+        p = rng.uniform(-80, 80, size=(3, 2)).astype(np.float32).astype(np.float64)
+        (ax, ay), (bx, by), (cx, cy) = p
+        d = 2.0 * (ax * (by - cy) + bx * (cy - ay) + cx * (ay - by))
+        if abs(d) < 1.0:
+            continue
+        ux = ((ax * ax + ay * ay) * (by - cy) + (bx * bx + by * by) * (cy - ay) + (cx * cx + cy * cy) * (ay - by)) / d
+        uy = ((ax * ax + ay * ay) * (cx - bx) + (bx * bx + by * by) * (ax - cx) + (cx * cx + cy * cy) * (bx - ax)) / d
+        r2 = (ax - ux) ** 2 + (ay - uy) ** 2
+        xc, yc, R2, n = O.fit_points(p[:, 0], p[:, 1])
+        assert n == 3
+        scale = max(1.0, abs(ux), abs(uy))
+        assert abs(xc - ux) <= 1e-6 * scale and abs(yc - uy) <= 1e-6 * scale
+        assert abs(R2 - r2) <= 1e-6 * max(1.0, r2)
+
+
+def test_fit_matches_library_least_squares(oracle_mod):
+    O = oracle_mod
+    rng = np.random.default_rng(42)
+    for trial in range(100):
+        n = int(rng.integers(3, 40))
+        cx, cy, R = rng.uniform(-300, 300), rng.uniform(-300, 300), rng.uniform(5, 400)
+        t = rng.uniform(0, 2 * np.pi, n)
+        x = (cx + R * np.cos(t) + rng.normal(0, 0.05, n)).astype(np.float32)
+        y = (cy + R * np.sin(t) + rng.normal(0, 0.05, n)).astype(np.float32)
+        X, Y = x.astype(np.float64), y.astype(np.float64)
+        A = np.stack([X, Y, np.ones(n)], axis=1)
+        sol, *_ = np.linalg.lstsq(A, -(X * X + Y * Y), rcond=None)
+        a, b, c = sol
+        want = (-a / 2, -b / 2, a * a / 4 + b * b / 4 - c)
+        got = O.fit_points(x, y)
+        assert got[3] == n
+        for g_, w_ in zip(got[:3], want):
+            assert abs(g_ - w_) <= 1e-6 * max(1.0, abs(w_)), (trial, got, want)
+
+
+def test_fit_translation_and_degenerate_lists(oracle_mod):
+    O = oracle_mod
+    rng = np.random.default_rng(43)
+    t = rng.uniform(0, 2 * np.pi, 12)
+    x = (20.0 + 40.0 * np.cos(t) + rng.normal(0, 0.1, 12)).astype(np.float32)
+    y = (-10.0 + 40.0 * np.sin(t) + rng.normal(0, 0.1, 12)).astype(np.float32)
+    xc, yc, R2, _ = O.fit_points(x, y)
+    xs, ys, R2s, _ = O.fit_points(x + np.float32(64.0), y - np.float32(32.0))  # exact shifts in float32
+    assert abs(xs - (xc + 64.0)) < 1e-8 * 100 and abs(ys - (yc - 32.0)) < 1e-8 * 100
+    assert abs(R2s - R2) < 1e-8 * R2
+    # fewer than three hits, or collinear ones: no circle
+    assert tuple(O.fit_points([], [])) == (0.0, 0.0, -1.0, 0.0)
+    assert tuple(O.fit_points([1.0, 2.0], [3.0, 5.0])) == (0.0, 0.0, -1.0, 2.0)
+    assert tuple(O.fit_points([0.0, 1.0, 2.0, 4.0], [0.0, 1.0, 2.0, 4.0])) == (0.0, 0.0, -1.0, 4.0)
+    # a list of several candidates: each row is the fit of its own slice
+    offs = np.array([0, 3, 3, 12], dtype=np.int64)
+    idx = np.arange(12, dtype=np.int32)[::-1].copy()
+    ev = synth.Event(x=x, y=y, z=None, layer=np.zeros(12, np.uint8), track_id=np.full(12, -1, np.int32), truth={})
+    out = O.fit(ev, offs, idx)
+    np.testing.assert_array_equal(out[0], O.fit_points(x[idx[:3]], y[idx[:3]]))
+    assert tuple(out[1]) == (0.0, 0.0, -1.0, 0.0)
+    np.testing.assert_array_equal(out[2], O.fit_points(x[idx[3:]], y[idx[3:]]))
+
+
+def test_fit_generated_prompt_tracks(oracle_mod):
+    """The hits of one generated prompt track (d0 = 0, 20 um smear) fit a circle through the
+    origin of radius 1/|c| = pT / (0.3 B) within the smear's effect."""
+    O = oracle_mod
+    cfg = configs.C1.with_(n_tracks=10)
+    ev = synth.make_event(cfg, 3)
+    kappa = 0.299792458e-2 * cfg.B_tesla
+    for t in range(10):
+        sel = np.flatnonzero(ev.track_id == t)
+        if sel.size < 8:
+            continue
+        xc, yc, R2, n = O.fit_points(ev.x[sel], ev.y[sel])
+        R = math.sqrt(R2)
+        assert n == sel.size
+        assert abs(math.hypot(xc, yc) - R) < 0.02 * R  # the circle passes near the origin
+        assert abs(R - 1.0 / (kappa * float(ev.truth["inv_pt"][t]))) < 0.05 * R
