@@ -219,6 +219,23 @@ int hough_zvote(const hough_plan_t* plan, const hough_hits_t* hits, const hough_
                 const int32_t* offsets, const int32_t* hit_idx, int32_t cap_pairs, const hough_status_t* st,
                 int32_t* out, hipStream_t stream);
 
+/* Track fit of every listed candidate's hits (Sec. "Preliminary Results",
+ * fitting paragraph: the hits of each candidate go on to a fit; the paper
+ * names no method).  The fit is the algebraic circle fit of Kasa (IEEE Trans.
+ * Instrum. Meas. 25 (1976) 8): the circle x^2 + y^2 + a x + b y + c = 0
+ * minimising sum_i (x_i^2 + y_i^2 + a x_i + b y_i + c)^2 over the hits of
+ * the candidate's CSR list (hits->x, y in cm, converted to double), the
+ * eight moments summed in list order and the 3x3 normal equations solved by
+ * Cramer's rule, in IEEE double without contraction (so the result is
+ * reproducible bit for bit).  out (dev) [cap_peaks][4] doubles: (xc, yc, R^2,
+ * n) = (-a/2, -b/2, xc^2 + yc^2 - c, hits in the list); R^2 = -1 (centre 0)
+ * for fewer than 3 hits or a zero determinant; R^2 = -2 when the list was
+ * cut by cap_pairs.  Candidates: the first min(st->n_peaks, cap_peaks), st
+ * read on the device; offsets / hit_idx as written by hough_assign.
+ * Async, stream-ordered; hits->layer and z are not read. */
+int hough_fit(const hough_plan_t* plan, const hough_hits_t* hits, const int32_t* offsets, const int32_t* hit_idx,
+              int32_t cap_peaks, int32_t cap_pairs, const hough_status_t* st, double* out, hipStream_t stream);
+
 /* Copy the arc-length table S[L][l][k] (int32 Q16.16, -1 = invalid) of a
  * plan with an r-z grid to host memory `out` (n_layers*n_d0*n_qpt entries).
  * Synchronous; for tests. */

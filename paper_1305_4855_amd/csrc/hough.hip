@@ -1599,6 +1599,85 @@ __global__ __launch_bounds__(kAssignThreads) void k_assign_fill(
     }
 }
 
+// ------------------------------------------------------------------ fit
+// Track fit of each listed candidate (grid.y = event), one thread per candidate: the algebraic
+// (Kasa) circle x^2 + y^2 + a x + b y + c = 0 through its hits in the least-squares sense.  The
+// eight moments of the normal equations are summed over the candidate's hit list in list order
+// (double, four hits' loads issued together), the 3x3 system is solved by Cramer's rule, and the
+// row (xc, yc, R^2, n) = (-a/2, -b/2, xc^2 + yc^2 - c, n) is written; R^2 = -1 for fewer than 3 hits
+// or a zero determinant, -2 for a list cut by the pair capacity.
+constexpr int kFitThreads = 256;
+
+__global__ __launch_bounds__(kFitThreads) void k_fit(Events ev, const float* __restrict__ hx,
+                                                    const float* __restrict__ hy,
+                                                    const int32_t* __restrict__ offsets_base,
+                                                    const int32_t* __restrict__ hit_idx_base, int32_t cap_peaks,
+                                                    int32_t cap_pairs, const hough_status_t* __restrict__ st_base,
+                                                    double* __restrict__ out_base) {
+    const int e = blockIdx.y;
+    const int n = min(st_base[e].n_peaks, cap_peaks);
+    const int p = blockIdx.x * kFitThreads + threadIdx.x;
+    if (p >= n) return;
+    int h0, nh;
+    event_hits(ev, e, h0, nh);
+    const int32_t* offsets = offsets_base + (size_t)e * (cap_peaks + 1);
+    const int32_t* hit_idx = hit_idx_base + (size_t)e * cap_pairs;
+    double* o = out_base + ((size_t)e * cap_peaks + p) * 4;
+    const int32_t q0 = offsets[p], q1 = offsets[p + 1];
+    const double N = (double)(q1 - q0);
+    if (q1 > cap_pairs) {  // the list was cut: no fit
+        o[0] = 0.0;
+        o[1] = 0.0;
+        o[2] = -2.0;
+        o[3] = N;
+        return;
+    }
+    double sx = 0.0, sy = 0.0, sxx = 0.0, sxy = 0.0, syy = 0.0, sz = 0.0, sxz = 0.0, syz = 0.0;
+    for (int q = q0; q < q1; q += 4) {
+        double X[4], Y[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int h = hit_idx[min(q + u, q1 - 1)];
+            X[u] = (double)hx[h0 + h];
+            Y[u] = (double)hy[h0 + h];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            if (q + u < q1) {
+                const double Z = X[u] * X[u] + Y[u] * Y[u];
+                sx += X[u];
+                sy += Y[u];
+                sxx += X[u] * X[u];
+                sxy += X[u] * Y[u];
+                syy += Y[u] * Y[u];
+                sz += Z;
+                sxz += X[u] * Z;
+                syz += Y[u] * Z;
+            }
+        }
+    }
+    // normal matrix [[sxx, sxy, sx], [sxy, syy, sy], [sx, sy, N]], right-hand side -(sxz, syz, sz)
+    const double m_yy = syy * N - sy * sy;  // cofactors shared by the determinants
+    const double m_xy = sxy * N - sy * sx;
+    const double m_c = sxy * sy - syy * sx;
+    const double det = sxx * m_yy - sxy * m_xy + sx * m_c;
+    o[3] = N;
+    if (N < 3.0 || det == 0.0) {
+        o[0] = 0.0;
+        o[1] = 0.0;
+        o[2] = -1.0;
+        return;
+    }
+    const double r0 = -sxz, r1 = -syz, r2 = -sz;
+    const double a = (r0 * m_yy - sxy * (r1 * N - sy * r2) + sx * (r1 * sy - syy * r2)) / det;
+    const double b = (sxx * (r1 * N - r2 * sy) - r0 * m_xy + sx * (sxy * r2 - r1 * sx)) / det;
+    const double c = (sxx * (syy * r2 - sy * r1) - sxy * (sxy * r2 - r1 * sx) + r0 * m_c) / det;
+    const double xc = -a / 2.0, yc = -b / 2.0;
+    o[0] = xc;
+    o[1] = yc;
+    o[2] = xc * xc + yc * yc - c;
+}
+
 // ------------------------------------------------------------------ zvote
 // Per candidate p (grid.y = event): every hit h of its list with a usable z votes, for each
 // cot(theta) row m, into z0 bin j(m) = (Z_h * 2^16 - S_h * C_m - z0min) >> shift, where S_h is the
@@ -2051,6 +2130,14 @@ void launch_assign(const hough_plan* p, const Events& ev, int n_events, const ho
                            p->g.n_qpt, p->M, p->F, ws, O, offsets, hit_idx, cap_pairs, lds_words, cells_words);
 }
 
+void launch_fit(const Events& ev, int n_events, const float* x, const float* y, const int32_t* offsets,
+                const int32_t* hit_idx, int32_t cap_peaks, int32_t cap_pairs, const hough_status_t* st, double* out,
+                hipStream_t stream) {
+    const dim3 grid((unsigned)(((int64_t)cap_peaks + kFitThreads - 1) / kFitThreads), n_events);
+    hipLaunchKernelGGL(k_fit, grid, dim3(kFitThreads), 0, stream, ev, x, y, offsets, hit_idx, cap_peaks, cap_pairs,
+                       st, out);
+}
+
 void launch_zvote(const hough_plan* p, const Events& ev, int n_events, const float* z, const uint8_t* layer,
                   const hough_peak_t* peaks, int32_t cap_peaks, const int32_t* offsets, const int32_t* hit_idx,
                   int32_t cap_pairs, const hough_status_t* st, int32_t* out, hipStream_t stream) {
@@ -2428,6 +2515,16 @@ int hough_zvote(const hough_plan_t* p, const hough_hits_t* hits, const hough_pea
     if (hits->n > 0 && (!hits->z || !hits->layer)) return HOUGH_E_INVAL;
     launch_zvote(p, single_event(p, hits->n), 1, hits->z, hits->layer, peaks, cap_peaks, offsets, hit_idx, cap_pairs,
                  st, out, stream);
+    return launch_status();
+}
+
+int hough_fit(const hough_plan_t* p, const hough_hits_t* hits, const int32_t* offsets, const int32_t* hit_idx,
+              int32_t cap_peaks, int32_t cap_pairs, const hough_status_t* st, double* out, hipStream_t stream) {
+    if (!p || !hits || !offsets || !hit_idx || !st || !out || cap_peaks < 1 || cap_pairs < 1) return HOUGH_E_INVAL;
+    if (hits->n < 0 || hits->n > p->g.max_hits_per_event) return HOUGH_E_INVAL;
+    if (hits->n > 0 && (!hits->x || !hits->y)) return HOUGH_E_INVAL;
+    launch_fit(single_event(p, hits->n), 1, hits->x, hits->y, offsets, hit_idx, cap_peaks, cap_pairs, st, out,
+               stream);
     return launch_status();
 }
 

@@ -80,6 +80,8 @@ def _load() -> C.CDLL:
     L.hough_assign.argtypes = [P, P, C.c_int32, P, P, C.c_int32, P, S, P, P]
     L.hough_zvote.restype = C.c_int
     L.hough_zvote.argtypes = [P, C.POINTER(Hits), P, C.c_int32, P, P, C.c_int32, P, P, P]
+    L.hough_fit.restype = C.c_int
+    L.hough_fit.argtypes = [P, C.POINTER(Hits), P, P, C.c_int32, C.c_int32, P, P, P]
     L.hough_plan_arclen_table.restype = C.c_int; L.hough_plan_arclen_table.argtypes = [P, P]
     L.hough_strerror.restype = C.c_char_p; L.hough_strerror.argtypes = [C.c_int]
     L.hough_plan_set_tuning.restype = C.c_int; L.hough_plan_set_tuning.argtypes = [P, C.POINTER(Tuning)]
@@ -98,7 +100,7 @@ lib = _load()
 
 EXPORTED = ["hough_plan_create", "hough_plan_destroy", "hough_acc_bytes", "hough_event_ws_bytes",
             "hough_angle_bits", "hough_plan_table", "hough_prep", "hough_vote", "hough_vote_prepared", "hough_peaks",
-            "hough_assign", "hough_zvote", "hough_plan_arclen_table", "hough_strerror", "hough_plan_set_tuning", "hough_plan_get_tuning", "hough_plan_set_vote_events",
+            "hough_assign", "hough_zvote", "hough_fit", "hough_plan_arclen_table", "hough_strerror", "hough_plan_set_tuning", "hough_plan_get_tuning", "hough_plan_set_vote_events",
             "hough_batch_ws_bytes", "hough_run_batch", "hough_batch_graph_create", "hough_graph_launch",
             "hough_graph_destroy"]
 
@@ -260,6 +262,16 @@ def zvote(plan: Plan, hits: Hits, pk: torch.Tensor, offsets: torch.Tensor, hit_i
                            int(hit_idx.numel()), _ptr(status), _ptr(out), _stream(stream)), "hough_zvote")
 
 
+def fit(plan: Plan, hits: Hits, offsets: torch.Tensor, hit_idx: torch.Tensor, status: torch.Tensor,
+        out: torch.Tensor, stream=None) -> None:
+    """Circle fit of every listed candidate's hit list: out [cap_peaks][4] float64 rows (xc, yc, R^2, n)."""
+    cap_peaks = out.shape[0]
+    if out.dtype != torch.float64 or out.dim() != 2 or out.shape[1] != 4 or offsets.numel() < cap_peaks + 1:
+        raise HoughError("out needs [cap_peaks][4] float64 and offsets cap_peaks + 1 entries")
+    _check(lib.hough_fit(plan.handle, C.byref(hits), _ptr(offsets), _ptr(hit_idx), int(cap_peaks),
+                         int(hit_idx.numel()), _ptr(status), _ptr(out), _stream(stream)), "hough_fit")
+
+
 def status_dict(status: torch.Tensor) -> dict:
     b = status.detach().to("cpu").numpy().view(np.uint8)[:STATUS_BYTES].tobytes()
     n_hits, n_bad = np.frombuffer(b[0:8], dtype=np.int32)
@@ -284,6 +296,13 @@ class EventBuffers:
         self.offsets = torch.empty(cap_peaks + 1, dtype=torch.int32, device=device)
         self.hit_idx = torch.empty(cap_pairs, dtype=torch.int32, device=device)
         self.zv = torch.empty((cap_peaks, 3), dtype=torch.int32, device=device) if plan.has_zvote else None
+        self.fit = None  # [cap_peaks][4] float64 once run_fit has been called
+
+    def run_fit(self, hits: Hits, stream=None) -> None:
+        """The circle fit of every listed candidate (after run)."""
+        if self.fit is None:
+            self.fit = torch.empty((self.peaks.shape[0], 4), dtype=torch.float64, device=self.peaks.device)
+        fit(self.plan, hits, self.offsets, self.hit_idx, self.status, self.fit, stream)
 
     def run(self, hits: Hits, threshold: int, stream=None, do_assign: bool = True) -> None:
         vote(self.plan, hits, self.acc, self.ws, self.status, stream)
@@ -303,6 +322,8 @@ class EventBuffers:
         out = dict(status=st, peaks=pk, offsets=offs, hit_idx=hit_idx)
         if self.zv is not None:
             out["zvote"] = self.zv[:n].cpu().numpy()
+        if self.fit is not None:
+            out["fit"] = self.fit[:n].cpu().numpy()
         return out
 
 
