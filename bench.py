@@ -285,6 +285,29 @@ def bench_plain(H, torch, args):
     vote_ms = vote_kernel_ms
     st = H.status_dict(bufs.status)
 
+    # Track fit of every candidate (the next step after the assignment, outside the timed chain):
+    # launched `reps` times back to back; HBM-bound work per launch = the CSR lists and offsets
+    # read, the fitted rows written (the hit coordinates are L2-resident)
+    H.assign(plan, bufs.peaks, bufs.offsets, bufs.hit_idx, bufs.ws, bufs.status, stream)
+    bufs.run_fit(hits, stream)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    for _ in range(reps):
+        bufs.run_fit(hits, stream)
+    b.record(stream)
+    torch.cuda.synchronize()
+    fit_ms = a.elapsed_time(b) / reps
+    n_fit = min(st["n_peaks"], bufs.peaks.shape[0])
+    fit_bytes = 4 * st["n_pairs"] + 4 * (n_fit + 1) + 32 * n_fit + 8 * ev.n
+    fit_gbs = fit_bytes / (fit_ms * 1e-3) / 1e9
+    fit = {"workload": "algebraic circle fit of every candidate of the dense event (c2)",
+           "candidates": n_fit, "pairs": st["n_pairs"], "ms_per_launch": round(fit_ms, 5),
+           "candidates_per_s": round(n_fit / (fit_ms * 1e-3), 1),
+           "roofline": {"kernel": "k_fit", "bound": "hbm", "achieved": round(fit_gbs, 1), "peak": 8000.0,
+                        "unit": "GB/s", "frac": round(fit_gbs / 8000.0, 4), "traffic": None,
+                        "bytes_per_launch": fit_bytes},
+           "note": "per-launch time of back-to-back launches (kernel plus launch gap)"}
+
     ms_per_step = (t1 - t0) * 1e3 / args.steps
     events_per_s = 1e3 / ms_per_step
     achieved = st["n_votes"] / (vote_ms * 1e-3) / 1e9
@@ -318,6 +341,7 @@ def bench_plain(H, torch, args):
                      "peak": LDS_ATOMIC_PEAK_GVOTES, "unit": "Gvote/s (LDS atomic adds)",
                      "frac": round(achieved / LDS_ATOMIC_PEAK_GVOTES, 4), "traffic": traffic,
                      "avg_launch_ms": round(vote_ms, 5), "votes_per_launch": st["n_votes"]},
+        "fit": fit,
     }
     return out
 
