@@ -14,7 +14,9 @@
  *     with; votes of all hits are summed in a binned parameter space;
  *   - local maxima of that space are the track candidates;
  *   - the hits that voted for a candidate are the input of the track fit
- *     (Sec. "Preliminary Results", fitting paragraph).
+ *     (Sec. "Preliminary Results", fitting paragraph);
+ *   - a second transform of the candidates themselves finds the vertices of
+ *     displaced jets (Sec. "New Trigger Capabilities").
  * The paper gives no parameterisation, grid, binning or tie rule.  The
  * discretisation used here is the "fixed-point transform" written out step by
  * step below (one reading of the silent points; the same reading is stated in
@@ -518,4 +520,60 @@ void or_fit(const float* x, const float* y, int32_t n_peaks, const int64_t* offs
         out[4 * p + 1] = yc;
         out[4 * p + 2] = xc * xc + yc * yc - c;
     }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Step 10 (second Hough transform, Sec. "New Trigger Capabilities" and its  */
+/* displaced-jet figures): the candidates of the first transform are the    */
+/* input; tracks from one displaced vertex are candidates whose curves all   */
+/* pass through that vertex, so each candidate votes for every vertex        */
+/* position its own helix passes through, and local maxima of that vertex    */
+/* space are the vertices.                                                   */
+/*   Vertex space: radius rows j, centres r_j = r_min + (j + 0.5) *          */
+/*   ((r_max - r_min) / n_vr), times n_vphi azimuth bins (a power of two);   */
+/*   an azimuth bin holds 2^(M - log2 n_vphi) values of the first           */
+/*   transform's M-bit angle.                                                */
+/*   A candidate (l, k, b) stands for the helix of its bin centres: d0 and   */
+/*   q/pT centres of l and k, and phi0 = the centre of bin b, the M-bit      */
+/*   angle b * 2^F + 2^(F-1).  On the branch leaving its PCA the helix meets */
+/*   radius r_j at azimuth phi0 + asin(A(r_j, c, d0)) (step 4 solved for phi */
+/*   instead of phi0), so with E_j = the step-4 sample at radius r_j:        */
+/*       vertex azimuth (M-bit) = (phi0 + E_j) mod 2^M,                      */
+/*       bin = that >> (M - log2 n_vphi).                                    */
+/*   One vote per row whose sample is valid, for every candidate with at     */
+/*   least min_votes first-stage votes.  acc_v[j][bin] (bin fastest), fully   */
+/*   overwritten.  Returns the number of votes cast.                         */
+/* Vertex peaks are step 6 on the grid (1 x n_vr x n_vphi): radius rows take */
+/* the place of q/pT rows (clipped), azimuth that of phi0 (cyclic).          */
+/* ------------------------------------------------------------------------ */
+double or_vertex_radius(int32_t n_vr, double r_min, double r_max, int32_t j)
+{
+    return r_min + ((double)j + 0.5) * ((r_max - r_min) / (double)n_vr);
+}
+
+int64_t or_vertex_vote(const or_cfg_t* g, int32_t n_vr, int32_t n_vphi, double r_min, double r_max,
+                       int32_t min_votes, int32_t n_peaks, const int32_t* pk, int32_t* acc_v)
+{
+    int32_t M = or_angle_bits(g), F = g->frac_bits, lv = or_log2(n_vphi), p, j;
+    uint32_t mask = (M >= 32) ? 0xffffffffu : ((1u << M) - 1u);
+    int64_t votes = 0;
+    memset(acc_v, 0, sizeof(int32_t) * (size_t)n_vr * (size_t)n_vphi);
+    for (p = 0; p < n_peaks; p++) {
+        int32_t l = pk[4 * p + 0], k = pk[4 * p + 1], b = pk[4 * p + 2];
+        double c, d;
+        uint32_t phi0;
+        if (pk[4 * p + 3] < min_votes) continue;
+        c = or_curvature(g, k);
+        d = or_d0_centre(g, l);
+        phi0 = ((uint32_t)b << F) + (1u << (F - 1));
+        for (j = 0; j < n_vr; j++) {
+            int32_t E;
+            uint32_t v;
+            if (!or_sample(or_vertex_radius(n_vr, r_min, r_max, j), c, d, M, &E)) continue;
+            v = (phi0 + (uint32_t)E) & mask;
+            acc_v[(int64_t)j * n_vphi + (int32_t)(v >> (M - lv))]++;
+            votes++;
+        }
+    }
+    return votes;
 }

@@ -89,6 +89,10 @@ def load(path: str) -> C.CDLL:
     L.or_zvote.argtypes = [P, C.c_int32, P, P, C.c_int32, P, P, P, P]
     L.or_fit.restype = None
     L.or_fit.argtypes = [P, P, C.c_int32, P, P, P]
+    L.or_vertex_radius.restype = C.c_double
+    L.or_vertex_radius.argtypes = [C.c_int32, C.c_double, C.c_double, C.c_int32]
+    L.or_vertex_vote.restype = C.c_int64
+    L.or_vertex_vote.argtypes = [P, C.c_int32, C.c_int32, C.c_double, C.c_double, C.c_int32, C.c_int32, P, P]
     return L
 
 
@@ -256,3 +260,45 @@ def fit_points(x, y) -> np.ndarray:
     lib().or_fit(_p(x), _p(y), 1, _p(offs), _p(idx if idx.size else np.zeros(1, np.int32)), _p(out))
     return out[0]
 
+
+
+# ---------------------------------------------------------------- second transform (vertices)
+class VertexGrid:
+    """Vertex space of the second transform: n_vr radius rows over [r_min, r_max) cm times
+    n_vphi azimuth bins; candidates with fewer than min_votes first-stage votes do not vote."""
+
+    def __init__(self, n_vr: int, n_vphi: int, r_min: float, r_max: float, min_votes: int = 1):
+        self.n_vr, self.n_vphi = int(n_vr), int(n_vphi)
+        self.r_min, self.r_max = float(r_min), float(r_max)
+        self.min_votes = int(min_votes)
+
+    @classmethod
+    def of(cls, cfg) -> "VertexGrid":
+        mv = cfg.v_min_votes if cfg.v_min_votes > 0 else cfg.threshold
+        return cls(cfg.n_vr, cfg.n_vphi, cfg.vr_min, cfg.vr_max, mv)
+
+
+def vertex_radius(vg: VertexGrid, j: int) -> float:
+    return float(lib().or_vertex_radius(vg.n_vr, vg.r_min, vg.r_max, int(j)))
+
+
+def vertex_vote(cfg: Cfg, vg: VertexGrid, pk: np.ndarray):
+    """Vertex accumulator acc_v[n_vr][n_vphi] of a candidate list (rows l, k, b, votes)."""
+    pk = np.ascontiguousarray(pk, dtype=np.int32).reshape(-1, 4)
+    acc = np.zeros((vg.n_vr, vg.n_vphi), dtype=np.int32)
+    nv = lib().or_vertex_vote(cfg.ptr, vg.n_vr, vg.n_vphi, vg.r_min, vg.r_max, vg.min_votes, pk.shape[0],
+                              _p(pk if pk.size else np.zeros(4, np.int32)), _p(acc))
+    return acc, int(nv)
+
+
+def vertex_peaks(vg: VertexGrid, acc_v: np.ndarray, thr: int, cap: int = 1 << 20):
+    """Local maxima of the vertex space: the peak rule of the first transform on the grid
+    (1 x n_vr x n_vphi).  Rows (0, j, azimuth bin, votes)."""
+    acc_v = np.ascontiguousarray(acc_v, dtype=np.int32)
+    assert acc_v.size == vg.n_vr * vg.n_vphi
+    g = _Cfg(n_layers=0, B_tesla=0.0, n_phi=vg.n_vphi, n_qpt=vg.n_vr, n_d0=1, frac_bits=0,
+             qpt_min=0.0, qpt_max=0.0, d0_min=0.0, d0_max=0.0, n_cot=0, n_z0=0,
+             cot_min=0.0, cot_max=0.0, z0_min=0.0, z0_max=0.0)
+    out = np.zeros((cap, 4), dtype=np.int32)
+    n = int(lib().or_peaks(C.addressof(g), _p(acc_v), int(thr), int(cap), _p(out)))
+    return n, out[: min(n, cap)].copy()

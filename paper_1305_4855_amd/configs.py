@@ -44,6 +44,15 @@ class HoughConfig:
     cot_max: float = 2.0
     z0_min: float = -32.0
     z0_max: float = 32.0
+    # second transform over the candidates (displaced-jet vertices): n_vr radius rows over
+    # [vr_min, vr_max) cm times n_vphi azimuth bins (0 = none); candidates with fewer than
+    # v_min_votes votes (0 = the first-stage threshold, i.e. all) do not vote
+    n_vr: int = 0
+    n_vphi: int = 0
+    vr_min: float = 0.0
+    vr_max: float = 32.0
+    v_min_votes: int = 0
+    v_threshold: int = 3
     # event generator
     n_events: int = 1
     n_tracks: int = 1000            # fixed count (when track_dist == "fixed")
@@ -99,7 +108,7 @@ C4 = HoughConfig(
     name="c4_llp_search", cfg_id=4, n_phi=1024, n_qpt=512, n_d0=128, frac_bits=7,
     d0_min=-20.0, d0_max=20.0, acc_bits=16, threshold=7, n_cot=128, n_z0=128,
     n_events=64, n_tracks=600, noise_frac=0.2, displaced_frac=0.0, with_z=True,
-    n_llp_vertices=2)
+    n_llp_vertices=2, n_vr=64, n_vphi=512)
 
 C5 = HoughConfig(
     name="c5_streaming_trigger", cfg_id=5, n_phi=512, n_qpt=256, n_d0=64, threshold=7,

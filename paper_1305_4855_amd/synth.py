@@ -34,7 +34,8 @@ class Event:
     z: Optional[np.ndarray]  # float32 [n] or None
     layer: np.ndarray        # uint8 [n]
     track_id: np.ndarray     # int32 [n], -1 for noise
-    truth: dict              # per-track arrays: q, inv_pt, phi0, d0, z0, cot, kind
+    truth: dict              # per-track arrays: q, inv_pt, phi0, d0, z0, cot, kind, vertex
+                             # (-1 or the index of the track's decay vertex); vertices [n][2]
 
     @property
     def n(self) -> int:
@@ -178,6 +179,8 @@ def make_event(cfg, event_id: int = 0) -> Event:
     truth_q, truth_ipt, truth_phi0, truth_d0, truth_z0, truth_cot = [q], [inv_pt], [phi0], [d0], [z0], [cot]
     parts = [(xs, ys, zs, ls, ts)]
     n_tracks_total = nt
+    vert_of = [np.full(nt, -1, dtype=np.int32)]
+    vertices = []
     if cfg.n_llp_vertices > 0:
         zpv = rng.normal(0.0, 5.0)
         for _ in range(cfg.n_llp_vertices):
@@ -188,6 +191,8 @@ def make_event(cfg, event_id: int = 0) -> Event:
             lo, hi = cfg.llp_daughters
             nd_ = int(rng.integers(lo, hi + 1))
             vx, vy = rv * np.cos(phiv), rv * np.sin(phiv)
+            vert_of.append(np.full(nd_, len(vertices), dtype=np.int32))
+            vertices.append((vx, vy))
             dq, dipt, dalpha, dphi0, dd0 = [], [], [], [], []
             while len(dq) < nd_:
                 qq = float(rng.choice(np.array([-1.0, 1.0])))
@@ -236,7 +241,8 @@ def make_event(cfg, event_id: int = 0) -> Event:
     truth = dict(q=np.concatenate(truth_q), inv_pt=np.concatenate(truth_ipt),
                  phi0=np.concatenate(truth_phi0), d0=np.concatenate(truth_d0),
                  z0=np.concatenate(truth_z0), cot=np.concatenate(truth_cot),
-                 kind=np.concatenate(kinds))
+                 kind=np.concatenate(kinds), vertex=np.concatenate(vert_of),
+                 vertices=np.asarray(vertices, dtype=np.float64).reshape(-1, 2))
     return Event(
         x=np.ascontiguousarray(x[perm], dtype=np.float32),
         y=np.ascontiguousarray(y[perm], dtype=np.float32),
@@ -263,3 +269,21 @@ def pack_events(events):
     if events and events[0].z is not None:
         z = np.concatenate([e.z for e in events])
     return x, y, z, lay, offs
+
+
+def make_candidates(cfg, n: int, seed: int = 0, votes=(7, 12)) -> np.ndarray:
+    """A synthetic candidate list of the first transform's shape: n distinct bins (l, k, b)
+    of the config's grid in increasing linear index, each with a vote count drawn uniformly
+    from [votes[0], votes[1]].  Rows (l, k, b, votes), int32.  Input of the second transform
+    at full size without running the first one."""
+    cfg = get(cfg)
+    rng = np.random.default_rng([13054855, cfg.cfg_id, 1 << 20, seed])
+    nb = cfg.n_bins
+    n = int(min(n, nb))
+    lin = np.sort(rng.choice(nb, size=n, replace=False)) if n else np.zeros(0, np.int64)
+    out = np.empty((n, 4), dtype=np.int32)
+    out[:, 0] = lin // (cfg.n_qpt * cfg.n_phi)
+    out[:, 1] = (lin // cfg.n_phi) % cfg.n_qpt
+    out[:, 2] = lin % cfg.n_phi
+    out[:, 3] = rng.integers(votes[0], votes[1] + 1, size=n)
+    return out

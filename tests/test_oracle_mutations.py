@@ -49,6 +49,10 @@ MUTATIONS = {
                      "det = sxx * (syy * N - sy * sy) + sxy * (sxy * N - sy * sx)"),
     "fit_rhs_sign": ("r0 = -sxz;", "r0 = sxz;"),
     "fit_centre_factor": ("xc = -a / 2.0;", "xc = -a;"),
+    "vertex_phi0_bin_edge": ("phi0 = ((uint32_t)b << F) + (1u << (F - 1));", "phi0 = ((uint32_t)b << F);"),
+    "vertex_sign": ("v = (phi0 + (uint32_t)E) & mask;", "v = (phi0 - (uint32_t)E) & mask;"),
+    "vertex_row_edge": ("return r_min + ((double)j + 0.5)", "return r_min + ((double)j + 0.0)"),
+    "vertex_min_votes_strict": ("if (pk[4 * p + 3] < min_votes) continue;", "if (pk[4 * p + 3] <= min_votes) continue;"),
 }
 
 SKIP = {"test_sample_table_vs_mpmath_c2"}  # slow; the c1 and sampled c4 tables run instead

@@ -752,3 +752,187 @@ def test_fit_generated_prompt_tracks(oracle_mod):
         assert n == sel.size
         assert abs(math.hypot(xc, yc) - R) < 0.02 * R  # the circle passes near the origin
         assert abs(R - 1.0 / (kappa * float(ev.truth["inv_pt"][t]))) < 0.05 * R
+
+
+# ------------------------------------------------- second transform (vertices) --
+def _vcfg(B=3.8, n_phi=64, n_qpt=64, n_d0=8, d0=10.0, qpt=1.0):
+    return configs.C2.with_(B_tesla=B, n_phi=n_phi, n_qpt=n_qpt, n_d0=n_d0, d0_min=-d0, d0_max=d0,
+                            qpt_min=-qpt, qpt_max=qpt)
+
+
+def _crossing_azimuth(c, d, phi0, r):
+    """Azimuth where the circle of signed curvature c, impact parameter d and direction phi0 at
+    its PCA (PCA = d (-sin phi0, cos phi0)) meets the circle of radius r about the origin, on
+    the half leaving the PCA; None when they do not meet.  Plane geometry: intersection of two
+    circles (or a line and a circle), the half picked by the sign of the component along the
+    direction at the PCA."""
+    n = np.array([-math.sin(phi0), math.cos(phi0)])
+    u = np.array([math.cos(phi0), math.sin(phi0)])
+    if c == 0.0:
+        if abs(d) > r:
+            return None
+        P = d * n + math.sqrt(r * r - d * d) * u
+        return math.atan2(P[1], P[0])
+    rho = 1.0 / abs(c)
+    Cc = (d + 1.0 / c) * n            # centre: a radius from the PCA, on the side the track turns to
+    D = float(np.hypot(*Cc))
+    if D > r + rho or D < abs(r - rho) or D == 0.0:
+        return None
+    a = (r * r - rho * rho + D * D) / (2.0 * D)
+    h = math.sqrt(max(r * r - a * a, 0.0))
+    e = Cc / D
+    perp = np.array([-e[1], e[0]])
+    for s in (1.0, -1.0):
+        P = a * e + s * h * perp
+        if float(P @ u) >= 0.0:
+            return math.atan2(P[1], P[0])
+    return None
+
+
+def test_vertex_vote_brute_force_geometry(oracle_mod):
+    """Every vote of every candidate equals the bin of the plane-geometry crossing of its helix
+    with the row's radius (intersection of two circles, a different formulation from the
+    transform's arcsine), except where the crossing lies within rounding of a bin edge; and a
+    row gets no vote exactly where the circles do not meet."""
+    O = oracle_mod
+    cfg = _vcfg()
+    g = O.Cfg(cfg)
+    M = O.angle_bits(g)
+    vg = O.VertexGrid(16, 32, 0.0, 32.0, 1)
+    rng = np.random.default_rng(101)
+    checked = ambiguous = 0
+    for _ in range(250):
+        l, k, b = int(rng.integers(cfg.n_d0)), int(rng.integers(cfg.n_qpt)), int(rng.integers(cfg.n_phi))
+        acc, nv = O.vertex_vote(g, vg, np.array([[l, k, b, 9]]))
+        c, d = O.curvature(g, k), O.d0_centre(g, l)
+        assert 1.0 + c * d > 0.0
+        phi0 = 2.0 * math.pi * (b + 0.5) / cfg.n_phi
+        expect_votes = 0
+        for j in range(vg.n_vr):
+            row = acc[j]
+            r = vg.r_min + (j + 0.5) * (vg.r_max - vg.r_min) / vg.n_vr   # row centre
+            assert abs(O.vertex_radius(vg, j) - r) < 1e-12
+            phi = _crossing_azimuth(c, d, phi0, r)
+            if phi is None:
+                assert row.sum() == 0
+                continue
+            expect_votes += 1
+            assert row.sum() == 1
+            got = int(np.flatnonzero(row)[0])
+            pos = (phi / (2.0 * math.pi)) % 1.0 * vg.n_vphi    # azimuth in bins
+            want = int(math.floor(pos)) % vg.n_vphi
+            frac = pos - math.floor(pos)
+            edge = 1.0 * vg.n_vphi / (1 << M)                  # one M-bit unit, in bins
+            if min(frac, 1.0 - frac) < edge:
+                ambiguous += 1
+                assert got in (want, (want + 1) % vg.n_vphi, (want - 1) % vg.n_vphi)
+            else:
+                assert got == want, (l, k, b, j, got, want)
+                checked += 1
+        assert nv == expect_votes
+    assert checked > 1500 and ambiguous < checked // 50
+
+
+def test_vertex_vote_straight_line_row(oracle_mod):
+    """B = 0 (straight lines): the vote of candidate (d, phi0) in a row of radius r is the bin
+    of phi0 + asin(d / r) -- the textbook (phi, rho) line Hough read backwards -- checked
+    against the geometric crossing for lines at the bin centres."""
+    O = oracle_mod
+    cfg = _vcfg(B=0.0, n_phi=128, n_d0=32, d0=12.0)
+    g = O.Cfg(cfg)
+    vg = O.VertexGrid(8, 128, 2.0, 34.0, 1)
+    for l in range(cfg.n_d0):
+        for b in (0, 17, 64, 127):
+            acc, _ = O.vertex_vote(g, vg, np.array([[l, 5, b, 9]]))
+            d = O.d0_centre(g, l)
+            phi0 = 2.0 * math.pi * (b + 0.5) / cfg.n_phi
+            for j in range(vg.n_vr):
+                r = O.vertex_radius(vg, j)
+                if abs(d) > r:
+                    assert acc[j].sum() == 0
+                    continue
+                # the point of the line at distance r from the origin, leaving the PCA
+                px = -d * math.sin(phi0) + math.sqrt(r * r - d * d) * math.cos(phi0)
+                py = d * math.cos(phi0) + math.sqrt(r * r - d * d) * math.sin(phi0)
+                pos = (math.atan2(py, px) / (2.0 * math.pi)) % 1.0 * vg.n_vphi
+                assert abs(math.hypot(px, py) - r) < 1e-9
+                got = int(np.flatnonzero(acc[j])[0])
+                if min(pos % 1.0, 1.0 - pos % 1.0) > 1e-3:
+                    assert got == int(pos) % vg.n_vphi
+
+
+def test_vertex_tracks_from_one_point(oracle_mod):
+    for B in (0.0, 3.8):
+        _tracks_from_one_point(oracle_mod, B)
+
+
+def _tracks_from_one_point(oracle_mod, B):
+    """Tracks leaving one point V, each turned into its nearest candidate bin: in V's radius
+    row every candidate votes within one azimuth bin of V, and the fullest bin of the vertex
+    space (and a vertex peak) lies next to V.  The perigees come from plane geometry (the
+    generator's circle through a point with a direction), not from the transform."""
+    O = oracle_mod
+    cfg = _vcfg(B=B, n_phi=1024, n_qpt=64, n_d0=256, d0=20.0)
+    g = O.Cfg(cfg)
+    vg = O.VertexGrid(64, 256, 0.0, 32.0, 1)
+    rng = np.random.default_rng(7 + int(B))
+    for trial in range(4):
+        rv, phiv = float(rng.uniform(4.0, 28.0)), float(rng.uniform(0.0, 2.0 * math.pi))
+        vx, vy = rv * math.cos(phiv), rv * math.sin(phiv)
+        rows = []
+        while len(rows) < 12:
+            alpha = phiv + float(rng.uniform(-0.6, 0.6))
+            q = float(rng.choice([-1.0, 1.0]))
+            ipt = float(rng.uniform(0.05, 0.9))
+            if B == 0.0:
+                phi0, d0, qpt = alpha % (2.0 * math.pi), -vx * math.sin(alpha) + vy * math.cos(alpha), 0.0
+            else:
+                p0, dd = synth._perigee_from_vertex(np.array([vx]), np.array([vy]), np.array([alpha]),
+                                                    np.array([q]), np.array([ipt]), B)
+                phi0, d0, qpt = float(p0[0]), float(dd[0]), q * ipt
+            l = int(math.floor((d0 - cfg.d0_min) / (cfg.d0_max - cfg.d0_min) * cfg.n_d0))
+            k = int(math.floor((qpt - cfg.qpt_min) / (cfg.qpt_max - cfg.qpt_min) * cfg.n_qpt))
+            b = int(math.floor(phi0 / (2.0 * math.pi) * cfg.n_phi)) % cfg.n_phi
+            if 0 <= l < cfg.n_d0 and 0 <= k < cfg.n_qpt:
+                rows.append((l, k, b, 10))
+        pk = np.array(sorted(rows, key=lambda t: (t[0], t[1], t[2])), dtype=np.int32)
+        jv = int(rv / 32.0 * vg.n_vr)
+        bv = int((phiv / (2.0 * math.pi)) % 1.0 * vg.n_vphi)
+        for row in pk:
+            acc1, _ = O.vertex_vote(g, vg, row[None, :])
+            hit = np.flatnonzero(acc1[jv])
+            assert hit.size == 1
+            assert circ_diff(hit[0], bv, vg.n_vphi) <= 1, (trial, row, hit, bv)
+        acc, _ = O.vertex_vote(g, vg, pk)
+        j_max, b_max = np.unravel_index(int(np.argmax(acc)), acc.shape)
+        assert abs(int(j_max) - jv) <= 1 and circ_diff(b_max, bv, vg.n_vphi) <= 1
+        window = [acc[jv, (bv + db) % vg.n_vphi] for db in (-1, 0, 1)]
+        assert sum(window) == len(pk) and acc.max() >= 4
+        n, vp = O.vertex_peaks(vg, acc, 4)
+        assert any(abs(int(r[1]) - jv) <= 1 and circ_diff(r[2], bv, vg.n_vphi) <= 1 for r in vp)
+
+
+def test_vertex_vote_rotation_and_filter(oracle_mod):
+    """Turning every candidate by s phi0 bins turns the vertex space by the same angle: with as
+    many azimuth bins as phi0 bins it rolls by s bins exactly, with half as many by s / 2 (s
+    even).  Candidates below min_votes cast nothing; the accumulator sums to the votes cast."""
+    O = oracle_mod
+    cfg = _vcfg(n_phi=64, n_qpt=64, n_d0=8)
+    g = O.Cfg(cfg)
+    pk = synth.make_candidates(cfg, 400, seed=3, votes=(5, 12))
+    for nvphi, s in ((64, 5), (64, 40), (32, 6)):
+        vg = O.VertexGrid(24, nvphi, 1.0, 30.0, 1)
+        a0, n0 = O.vertex_vote(g, vg, pk)
+        rot = pk.copy()
+        rot[:, 2] = (rot[:, 2] + s) % cfg.n_phi
+        a1, n1 = O.vertex_vote(g, vg, rot)
+        assert n0 == n1 == int(a0.sum()) and n0 > 0
+        np.testing.assert_array_equal(a1, np.roll(a0, s * nvphi // cfg.n_phi, axis=1))
+    vg8 = O.VertexGrid(24, 64, 1.0, 30.0, 8)
+    a8, n8 = O.vertex_vote(g, vg8, pk)
+    keep = pk[pk[:, 3] >= 8]
+    a8b, n8b = O.vertex_vote(g, O.VertexGrid(24, 64, 1.0, 30.0, 1), keep)
+    np.testing.assert_array_equal(a8, a8b)
+    assert n8 == n8b and 0 < keep.shape[0] < pk.shape[0]
+    empty, ne = O.vertex_vote(g, vg8, np.zeros((0, 4), np.int32))
+    assert ne == 0 and not empty.any()
