@@ -236,6 +236,62 @@ int hough_zvote(const hough_plan_t* plan, const hough_hits_t* hits, const hough_
 int hough_fit(const hough_plan_t* plan, const hough_hits_t* hits, const int32_t* offsets, const int32_t* hit_idx,
               int32_t cap_peaks, int32_t cap_pairs, const hough_status_t* st, double* out, hipStream_t stream);
 
+/* Second Hough transform over the candidates (Sec. "New Trigger Capabilities"
+ * and its displaced-jet figures: tracks from one displaced vertex are maxima
+ * of the first space lying on one curve, the curve of the vertex; a second
+ * transform of the maxima finds it).  Vertex space: n_vr radius rows with
+ * centres r_j = r_min + (j + 0.5) * ((r_max - r_min) / n_vr) times n_vphi
+ * azimuth bins; bin b_v holds the M-bit angles [b_v, b_v + 1) * 2^(M - log2
+ * n_vphi) (M = hough_angle_bits of the first plan).  A first-stage candidate
+ * (l, k, b) with votes >= min_votes stands for the helix of its bin centres
+ * (d0, q/pT centres; phi0 = M-bit angle b * 2^F + 2^(F-1)); in every row whose
+ * sample T = llrint(asin(A(r_j, c, d0)) * 2^(M-1) / pi) is valid (A, validity
+ * and operation order as for the first table) it casts one vote for the bin
+ * of (phi0 + T) mod 2^M: the azimuth at which the helix, leaving its PCA,
+ * meets radius r_j.  acc_v (dev) int32 [n_vr][n_vphi] (azimuth fastest).
+ * Vertex peaks: the first stage's peak rule on the grid (1 x n_vr x n_vphi),
+ * radius rows clipped, azimuth cyclic; output rows (0, j, b_v, votes). */
+typedef struct {
+    int32_t n_vr;              /* radius rows: multiple of 64, 64..4096                */
+    int32_t n_vphi;            /* azimuth bins: power of two, 16..1024, <= 2^M         */
+    double r_min, r_max;       /* cm, 0 <= r_min < r_max <= 32768                      */
+    int32_t min_votes;         /* candidates with fewer first-stage votes cast none (>= 1) */
+} hough_vertex_grid_t;
+
+typedef struct hough_vertex_plan hough_vertex_plan_t;
+
+/* Builds the table T[l][k][j] (device, n_d0 * n_qpt * n_vr int32) on the
+ * current device.  The first plan must outlive the vertex plan.  Synchronous.
+ * HOUGH_E_UNSUPPORTED for grids outside the limits above. */
+int hough_vertex_plan_create(const hough_plan_t* plan, const hough_vertex_grid_t* vgrid, hough_vertex_plan_t** out);
+void hough_vertex_plan_destroy(hough_vertex_plan_t* vplan);
+/* Candidate ranges counted apart and then added (launch shape only: results
+ * are identical for every value; raised to ceil(cap_peaks / 65535) when
+ * smaller).  Default: enough workgroups for every compute unit. */
+int hough_vertex_set_groups(hough_vertex_plan_t* vplan, int32_t groups);
+int32_t hough_vertex_get_groups(const hough_vertex_plan_t* vplan);
+/* Workspace of hough_vertex_vote for a candidate capacity, and of
+ * hough_vertex_peaks for a vertex-candidate capacity (two separate buffers
+ * or one reused in stream order). */
+size_t hough_vertex_vote_ws_bytes(const hough_vertex_plan_t* vplan, int32_t cap_peaks);
+size_t hough_vertex_peaks_ws_bytes(const hough_vertex_plan_t* vplan, int32_t cap_vpeaks);
+/* Vote the first min(st->n_peaks, cap_peaks) candidates of `peaks` (dev, as
+ * written by hough_peaks on the first plan; st read on the device) into acc_v
+ * (dev, fully overwritten).  Candidates whose (l, k, b) lies outside the first
+ * grid cast nothing.  st_v (dev) is reset: n_hits = candidates given, n_votes
+ * = votes cast = sum of acc_v, other fields 0.  Async, stream-ordered. */
+int hough_vertex_vote(const hough_vertex_plan_t* vplan, const hough_peak_t* peaks, int32_t cap_peaks,
+                      const hough_status_t* st, int32_t* acc_v, void* ws, size_t ws_bytes, hough_status_t* st_v,
+                      hipStream_t stream);
+/* Local maxima of acc_v with acc_v >= threshold (>= 1): vpeaks (dev) [cap] in
+ * increasing j * n_vphi + b_v; st_v->n_peaks = true count, flags as for
+ * hough_peaks.  ws of hough_vertex_peaks_ws_bytes(vplan, cap) bytes. */
+int hough_vertex_peaks(const hough_vertex_plan_t* vplan, const int32_t* acc_v, int32_t threshold,
+                       hough_peak_t* vpeaks, int32_t cap, void* ws, size_t ws_bytes, hough_status_t* st_v,
+                       hipStream_t stream);
+/* Copy T to host memory `out` (n_d0 * n_qpt * n_vr entries).  Synchronous; for tests. */
+int hough_vertex_table(const hough_vertex_plan_t* vplan, int32_t* out);
+
 /* Copy the arc-length table S[L][l][k] (int32 Q16.16, -1 = invalid) of a
  * plan with an r-z grid to host memory `out` (n_layers*n_d0*n_qpt entries).
  * Synchronous; for tests. */

@@ -2152,6 +2152,159 @@ void launch_zvote(const hough_plan* p, const Events& ev, int n_events, const flo
                        peaks, cap_peaks, offsets, hit_idx, cap_pairs, st, p->d_S, p->g.n_d0, p->g.n_qpt, p->zg, out);
 }
 
+// ------------------------------------------------------------------ second transform (vertices)
+// Vertex space: rows j (radius centres) x n_vphi azimuth bins.  A first-stage candidate (l, k, b)
+// votes, in every row whose sample T[l][k][j] is valid, for the azimuth bin of
+// (b * 2^F + 2^(F-1) + T) mod 2^M, i.e. where its bin-centre helix meets the row's radius.
+//
+// k_vvote: workgroup (g, s) counts the votes of candidate range g into rows [64 s, 64 s + 64) in
+// LDS, lane = row, exactly like the first transform's slab (16-bit halves: rows c and c + 32 share
+// the dword (bin * 32 + c), so a 32-lane half of a ds_add touches 32 distinct dwords), and copies
+// its slab to its own partial in ws.  A half never carries: a row counts at most one vote per
+// candidate and a range holds at most 65535 candidates.  k_vreduce adds the partials.
+constexpr int kVvoteThreads = 512;
+constexpr int kVvoteUnroll = 8;
+constexpr int kVreduceThreads = 1024;
+constexpr int kVertexMaxRange = 65535;  // candidates per partial (16-bit halves)
+
+struct VGrid {
+    int32_t n_d0, n_qpt, n_phi, n_vr, n_vphi, F, min_votes, groups;
+    uint32_t mask_m;   // 2^M - 1
+    int32_t shift;     // M - log2(n_vphi): bits of the M-bit angle below one vertex bin
+};
+
+// Candidates listed by the first stage and the split into ranges of the vertex vote; identical in
+// both kernels so that the reduction reads exactly the partials that were written.
+__device__ __forceinline__ void vertex_ranges(const hough_status_t* st, int32_t cap, int32_t groups, int& n,
+                                              int& chunk, int& active) {
+    n = min(st->n_peaks, cap);
+    n = n > 0 ? n : 0;
+    chunk = (n + groups - 1) / groups;
+    active = chunk > 0 ? (n + chunk - 1) / chunk : 0;
+}
+
+__global__ __launch_bounds__(kVvoteThreads) void k_vvote(const hough_peak_t* __restrict__ peaks, int32_t cap,
+                                                         const hough_status_t* __restrict__ st,
+                                                         const int32_t* __restrict__ T, VGrid vg,
+                                                         uint32_t* __restrict__ partial,
+                                                         hough_status_t* __restrict__ st_v) {
+    extern __shared__ uint32_t slab[];
+    const int g = blockIdx.x, s = blockIdx.y, tid = threadIdx.x;
+    int n, chunk, active;
+    vertex_ranges(st, cap, vg.groups, n, chunk, active);
+    if (g == 0 && s == 0 && tid == 0) {
+        st_v->n_hits = n;
+        st_v->n_bad_hits = 0;
+        st_v->n_votes = 0;
+        st_v->n_peaks = 0;
+        st_v->flags = 0;
+        st_v->n_pairs = 0;
+    }
+    if (g >= active) return;
+    const int p0 = g * chunk, p1 = min(n, p0 + chunk);
+    const int words = vg.n_vphi * 32;
+    for (int i = tid; i < words / 4; i += kVvoteThreads) reinterpret_cast<uint4*>(slab)[i] = make_uint4(0, 0, 0, 0);
+    __syncthreads();
+    const int lane = tid & 63, wave = tid >> 6;
+    const uint32_t inc = lane < 32 ? 1u : 65536u;
+    const int32_t* Trow = T + s * 64 + lane;
+    const uint32_t half = 1u << (vg.F - 1);
+    const int bin_shift = vg.shift;
+    const uint32_t bin_mask = (uint32_t)vg.n_vphi - 1u;
+    for (int base = p0 + wave * 64; base < p1; base += (kVvoteThreads / 64) * 64) {
+        int4 c4 = make_int4(0, 0, 0, 0);  // votes 0 < min_votes: lanes past the range cast nothing
+        if (base + lane < p1) c4 = *reinterpret_cast<const int4*>(peaks + base + lane);
+        const int cnt = min(64, p1 - base);
+        for (int i0 = 0; i0 < cnt; i0 += kVvoteUnroll) {
+            int32_t e[kVvoteUnroll];
+            uint32_t ph[kVvoteUnroll];
+#pragma unroll
+            for (int u = 0; u < kVvoteUnroll; ++u) {
+                const int i = i0 + u;
+                const int v = __builtin_amdgcn_readlane(c4.w, i);
+                const int l = __builtin_amdgcn_readlane(c4.x, i);
+                const int k = __builtin_amdgcn_readlane(c4.y, i);
+                const int b = __builtin_amdgcn_readlane(c4.z, i);
+                // a bin outside the first grid (not one the peak finder writes) casts nothing
+                const bool on = v >= vg.min_votes && (unsigned)l < (unsigned)vg.n_d0 &&
+                                (unsigned)k < (unsigned)vg.n_qpt && (unsigned)b < (unsigned)vg.n_phi;
+                const size_t off = on ? ((size_t)l * vg.n_qpt + k) * vg.n_vr : 0;
+                const int32_t t = Trow[off];
+                e[u] = on ? t : INT32_MIN;
+                ph[u] = ((uint32_t)b << vg.F) + half;
+            }
+#pragma unroll
+            for (int u = 0; u < kVvoteUnroll; ++u) {
+                if (e[u] != INT32_MIN) {
+                    const uint32_t a = (ph[u] + (uint32_t)e[u]) & vg.mask_m;
+                    const uint32_t w = (((a >> bin_shift) & bin_mask) << 5) | (uint32_t)(lane & 31);
+                    __hip_atomic_fetch_add(slab + w, inc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                }
+            }
+        }
+    }
+    __syncthreads();
+    uint4* dst = reinterpret_cast<uint4*>(partial + ((size_t)s * vg.groups + g) * words);
+    for (int i = tid; i < words / 4; i += kVvoteThreads) dst[i] = reinterpret_cast<const uint4*>(slab)[i];
+}
+
+// One workgroup per 64 dwords of the slab layout (all rows' partials of 32 rows x 2 bins); wave w
+// adds ranges w, w + 16, ...; the sums are combined in LDS and split into the two rows of a dword.
+__global__ __launch_bounds__(kVreduceThreads) void k_vreduce(const hough_status_t* __restrict__ st, int32_t cap,
+                                                             VGrid vg, const uint32_t* __restrict__ partial,
+                                                             int32_t* __restrict__ acc_v,
+                                                             hough_status_t* __restrict__ st_v) {
+    __shared__ uint32_t lo_s[kVreduceThreads / 64][64], hi_s[kVreduceThreads / 64][64];
+    int n, chunk, active;
+    vertex_ranges(st, cap, vg.groups, n, chunk, active);
+    const int words = vg.n_vphi * 32;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t d = (int64_t)blockIdx.x * 64 + lane;  // dword of all slabs: s * words + w
+    const int s = (int)(d / words), w = (int)(d % words);
+    const uint32_t* src = partial + (size_t)s * vg.groups * words + w;
+    uint32_t lo = 0, hi = 0;
+    constexpr int kW = kVreduceThreads / 64;
+    int g = wave;
+    for (; g + 3 * kW < active; g += 4 * kW) {
+        const uint32_t a0 = src[(size_t)g * words], a1 = src[(size_t)(g + kW) * words];
+        const uint32_t a2 = src[(size_t)(g + 2 * kW) * words], a3 = src[(size_t)(g + 3 * kW) * words];
+        lo += (a0 & 0xFFFFu) + (a1 & 0xFFFFu) + (a2 & 0xFFFFu) + (a3 & 0xFFFFu);
+        hi += (a0 >> 16) + (a1 >> 16) + (a2 >> 16) + (a3 >> 16);
+    }
+    for (; g < active; g += kW) {
+        const uint32_t a = src[(size_t)g * words];
+        lo += a & 0xFFFFu;
+        hi += a >> 16;
+    }
+    lo_s[wave][lane] = lo;
+    hi_s[wave][lane] = hi;
+    __syncthreads();
+    if (wave == 0) {
+        uint32_t L = 0, H = 0;
+#pragma unroll
+        for (int i = 0; i < kW; ++i) {
+            L += lo_s[i][lane];
+            H += hi_s[i][lane];
+        }
+        const int bin = w >> 5, c = w & 31;
+        acc_v[((size_t)s * 64 + c) * vg.n_vphi + bin] = (int32_t)L;
+        acc_v[((size_t)s * 64 + c + 32) * vg.n_vphi + bin] = (int32_t)H;
+        unsigned long long t = (unsigned long long)L + H;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
+        if (lane == 0) atomicAdd(reinterpret_cast<unsigned long long*>(&st_v->n_votes), t);
+    }
+}
+
+void launch_vertex_vote(const VGrid& vg, int slabs, const hough_peak_t* peaks, int32_t cap, const hough_status_t* st,
+                        const int32_t* T, uint32_t* partial, int32_t* acc_v, hough_status_t* st_v, hipStream_t stream) {
+    const size_t lds = (size_t)vg.n_vphi * 128;
+    hipLaunchKernelGGL(k_vvote, dim3((unsigned)vg.groups, (unsigned)slabs), dim3(kVvoteThreads), lds, stream, peaks,
+                       cap, st, T, vg, partial, st_v);
+    const unsigned rblocks = (unsigned)((int64_t)slabs * vg.n_vphi * 32 / 64);
+    hipLaunchKernelGGL(k_vreduce, dim3(rblocks), dim3(kVreduceThreads), 0, stream, st, cap, vg, partial, acc_v, st_v);
+}
+
 int check_hits(const hough_plan* p, const hough_hits_t* hits) {
     if (!p || !hits) return HOUGH_E_INVAL;
     if (hits->n < 0 || hits->n > p->g.max_hits_per_event) return HOUGH_E_INVAL;
@@ -2161,6 +2314,43 @@ int check_hits(const hough_plan* p, const hough_hits_t* hits) {
 
 Events single_event(const hough_plan* p, int n) { return Events{nullptr, n, p->g.max_hits_per_event, 0}; }
 
+}  // namespace
+
+// Second transform (vertex space) of one first-stage plan.
+struct hough_vertex_plan {
+    const hough_plan* first;  // not owned
+    hough_plan* grid;         // the vertex space as a (1 x n_vr x n_vphi) plan: its peak finder
+    hough_vertex_grid_t vg;
+    int32_t* d_T;             // [n_d0][n_qpt][n_vr] sample at each row radius, INT32_MIN = invalid
+    int slabs;                // n_vr / 64
+    int groups;               // candidate ranges (partials) per slab, at least
+};
+
+namespace {
+int vertex_groups(const hough_vertex_plan* vp, int32_t cap) {
+    const int64_t need = ((int64_t)cap + kVertexMaxRange - 1) / kVertexMaxRange;
+    return (int)(need > vp->groups ? need : vp->groups);
+}
+
+size_t vertex_partial_bytes(const hough_vertex_plan* vp, int32_t cap) {
+    return (size_t)vp->slabs * vertex_groups(vp, cap) * vp->vg.n_vphi * 128;
+}
+
+VGrid vertex_vgrid(const hough_vertex_plan* vp, int32_t cap) {
+    const hough_plan* p = vp->first;
+    VGrid v{};
+    v.n_d0 = p->g.n_d0;
+    v.n_qpt = p->g.n_qpt;
+    v.n_phi = p->g.n_phi;
+    v.n_vr = vp->vg.n_vr;
+    v.n_vphi = vp->vg.n_vphi;
+    v.F = p->F;
+    v.min_votes = vp->vg.min_votes;
+    v.groups = vertex_groups(vp, cap);
+    v.mask_m = p->M >= 32 ? 0xFFFFFFFFu : ((1u << p->M) - 1u);
+    v.shift = p->M - ilog2_exact(vp->vg.n_vphi);
+    return v;
+}
 }  // namespace
 
 // ====================================================================== C ABI
@@ -2611,6 +2801,142 @@ void hough_graph_destroy(hough_graph_t* g) {
     (void)hipGraphExecDestroy(g->exec);
     (void)hipGraphDestroy(g->graph);
     delete g;
+}
+
+
+// ---------------------------------------------------------------------- second transform
+int hough_vertex_plan_create(const hough_plan_t* p, const hough_vertex_grid_t* vgrid, hough_vertex_plan_t** out) {
+    if (!p || !vgrid || !out) return HOUGH_E_INVAL;
+    *out = nullptr;
+    const hough_vertex_grid_t& v = *vgrid;
+    if (v.min_votes < 1 || !std::isfinite(v.r_min) || !std::isfinite(v.r_max) || !(v.r_min >= 0.0) ||
+        !(v.r_max > v.r_min))
+        return HOUGH_E_INVAL;
+    if (v.r_max > 32768.0) return HOUGH_E_UNSUPPORTED;
+    if (v.n_vr < 64 || v.n_vr % 64 || v.n_vr > 4096) return HOUGH_E_UNSUPPORTED;
+    const int lv = ilog2_exact(v.n_vphi);
+    if (lv < 4 || v.n_vphi > 1024 || lv > p->M) return HOUGH_E_UNSUPPORTED;
+    if ((int64_t)p->g.n_d0 * p->g.n_qpt * v.n_vr > ((int64_t)1 << 31)) return HOUGH_E_UNSUPPORTED;
+
+    hough_vertex_plan* vp = new (std::nothrow) hough_vertex_plan();
+    if (!vp) return HOUGH_E_NOMEM;
+    vp->first = p;
+    vp->vg = v;
+    vp->slabs = v.n_vr / 64;
+    // workgroups resident per CU: LDS of one slab, at most 32 waves
+    int per_cu = (int)((size_t)kLdsBytes / ((size_t)v.n_vphi * 128));
+    const int by_waves = 32 / (kVvoteThreads / 64);
+    per_cu = per_cu < by_waves ? per_cu : by_waves;
+    per_cu = per_cu > 1 ? per_cu : 1;
+    vp->groups = (p->n_cu * per_cu + vp->slabs - 1) / vp->slabs;
+
+    // the vertex space's own grid, for its peak finder (threshold and tie rule of the first stage)
+    const double r1 = 1.0;
+    hough_geometry_t geo{1, &r1, nullptr, 0.0};
+    hough_grid_t gg{};
+    gg.n_phi = v.n_vphi;
+    gg.n_qpt = v.n_vr;
+    gg.n_d0 = 1;
+    gg.frac_bits = 7;
+    gg.acc_bits = 32;
+    gg.max_hits_per_event = 1;
+    int rc = hough_plan_create(&geo, &gg, &vp->grid);
+    if (rc) {
+        delete vp;
+        return rc;
+    }
+    vp->grid->tuning = p->tuning;
+
+    // sample table at the row radii, in IEEE double in the operation order of the first table
+    const hough_grid_t& g = p->g;
+    const size_t ntab = (size_t)g.n_d0 * g.n_qpt * v.n_vr;
+    int32_t* T = (int32_t*)malloc(ntab * sizeof(int32_t));
+    if (!T) {
+        hough_plan_destroy(vp->grid);
+        delete vp;
+        return HOUGH_E_NOMEM;
+    }
+    const double kappa = 0.299792458e-2 * p->B;
+    const double K = ldexp(1.0, p->M - 1) / M_PI;
+    for (int l = 0; l < g.n_d0; ++l) {
+        const double d = g.d0_min + ((double)l + 0.5) * ((g.d0_max - g.d0_min) / (double)g.n_d0);
+        for (int k = 0; k < g.n_qpt; ++k) {
+            const double q = g.qpt_min + ((double)k + 0.5) * ((g.qpt_max - g.qpt_min) / (double)g.n_qpt);
+            const double c = -kappa * q;
+            for (int j = 0; j < v.n_vr; ++j) {
+                const double r = v.r_min + ((double)j + 0.5) * ((v.r_max - v.r_min) / (double)v.n_vr);
+                const double num = c * (r * r + d * d) + 2.0 * d;
+                const double den = 2.0 * r * (1.0 + c * d);
+                int32_t e = INT32_MIN;
+                if (den > 0.0) {
+                    const double A = num / den;
+                    if (fabs(A) <= 1.0) e = (int32_t)llrint(asin(A) * K);
+                }
+                T[((size_t)l * g.n_qpt + k) * v.n_vr + j] = e;
+            }
+        }
+    }
+    hipError_t e = hipMalloc(&vp->d_T, ntab * sizeof(int32_t));
+    if (e == hipSuccess) e = hipMemcpy(vp->d_T, T, ntab * sizeof(int32_t), hipMemcpyHostToDevice);
+    free(T);
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute((const void*)k_vvote, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
+    if (e != hipSuccess) {
+        if (vp->d_T) (void)hipFree(vp->d_T);
+        hough_plan_destroy(vp->grid);
+        delete vp;
+        return e == hipErrorOutOfMemory ? HOUGH_E_NOMEM : HOUGH_E_HIP;
+    }
+    *out = vp;
+    return HOUGH_OK;
+}
+
+void hough_vertex_plan_destroy(hough_vertex_plan_t* vp) {
+    if (!vp) return;
+    if (vp->d_T) (void)hipFree(vp->d_T);
+    hough_plan_destroy(vp->grid);
+    delete vp;
+}
+
+int hough_vertex_set_groups(hough_vertex_plan_t* vp, int32_t groups) {
+    if (!vp || groups < 1 || groups > 65536) return HOUGH_E_INVAL;
+    vp->groups = groups;
+    return HOUGH_OK;
+}
+
+int32_t hough_vertex_get_groups(const hough_vertex_plan_t* vp) { return vp ? vp->groups : -1; }
+
+size_t hough_vertex_vote_ws_bytes(const hough_vertex_plan_t* vp, int32_t cap_peaks) {
+    if (!vp || cap_peaks < 1) return 0;
+    return vertex_partial_bytes(vp, cap_peaks);
+}
+
+size_t hough_vertex_peaks_ws_bytes(const hough_vertex_plan_t* vp, int32_t cap_vpeaks) {
+    if (!vp || cap_vpeaks < 1) return 0;
+    return ws_layout(vp->grid, cap_vpeaks).total;
+}
+
+int hough_vertex_table(const hough_vertex_plan_t* vp, int32_t* out) {
+    if (!vp || !out) return HOUGH_E_INVAL;
+    const size_t n = (size_t)vp->first->g.n_d0 * vp->first->g.n_qpt * vp->vg.n_vr;
+    return hipMemcpy(out, vp->d_T, n * sizeof(int32_t), hipMemcpyDeviceToHost) == hipSuccess ? HOUGH_OK
+                                                                                              : HOUGH_E_HIP;
+}
+
+int hough_vertex_vote(const hough_vertex_plan_t* vp, const hough_peak_t* peaks, int32_t cap_peaks,
+                      const hough_status_t* st, int32_t* acc_v, void* ws, size_t ws_bytes, hough_status_t* st_v,
+                      hipStream_t stream) {
+    if (!vp || !peaks || !st || !acc_v || !ws || !st_v || cap_peaks < 1) return HOUGH_E_INVAL;
+    if (ws_bytes < vertex_partial_bytes(vp, cap_peaks)) return HOUGH_E_SMALL_WS;
+    launch_vertex_vote(vertex_vgrid(vp, cap_peaks), vp->slabs, peaks, cap_peaks, st, vp->d_T,
+                       static_cast<uint32_t*>(ws), acc_v, st_v, stream);
+    return launch_status();
+}
+
+int hough_vertex_peaks(const hough_vertex_plan_t* vp, const int32_t* acc_v, int32_t threshold, hough_peak_t* vpeaks,
+                       int32_t cap, void* ws, size_t ws_bytes, hough_status_t* st_v, hipStream_t stream) {
+    if (!vp) return HOUGH_E_INVAL;
+    return hough_peaks(vp->grid, acc_v, threshold, vpeaks, cap, ws, ws_bytes, st_v, stream);
 }
 
 }  // extern "C"

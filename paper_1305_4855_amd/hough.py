@@ -46,6 +46,11 @@ class Tuning(C.Structure):
     _fields_ = [("vote_threads", C.c_int32), ("vote_grid", C.c_int32), ("peak_planes", C.c_int32)]
 
 
+class VertexGrid(C.Structure):
+    _fields_ = [("n_vr", C.c_int32), ("n_vphi", C.c_int32), ("r_min", C.c_double), ("r_max", C.c_double),
+                ("min_votes", C.c_int32)]
+
+
 class Batch(C.Structure):
     _fields_ = [("x", C.c_void_p), ("y", C.c_void_p), ("z", C.c_void_p), ("layer", C.c_void_p),
                 ("hit_offsets", C.c_void_p), ("n_events", C.c_int32), ("threshold", C.c_int32),
@@ -84,6 +89,18 @@ def _load() -> C.CDLL:
     L.hough_fit.argtypes = [P, C.POINTER(Hits), P, P, C.c_int32, C.c_int32, P, P, P]
     L.hough_plan_arclen_table.restype = C.c_int; L.hough_plan_arclen_table.argtypes = [P, P]
     L.hough_strerror.restype = C.c_char_p; L.hough_strerror.argtypes = [C.c_int]
+    L.hough_vertex_plan_create.restype = C.c_int
+    L.hough_vertex_plan_create.argtypes = [P, C.POINTER(VertexGrid), C.POINTER(C.c_void_p)]
+    L.hough_vertex_plan_destroy.restype = None; L.hough_vertex_plan_destroy.argtypes = [P]
+    L.hough_vertex_set_groups.restype = C.c_int; L.hough_vertex_set_groups.argtypes = [P, C.c_int32]
+    L.hough_vertex_get_groups.restype = C.c_int32; L.hough_vertex_get_groups.argtypes = [P]
+    L.hough_vertex_vote_ws_bytes.restype = S; L.hough_vertex_vote_ws_bytes.argtypes = [P, C.c_int32]
+    L.hough_vertex_peaks_ws_bytes.restype = S; L.hough_vertex_peaks_ws_bytes.argtypes = [P, C.c_int32]
+    L.hough_vertex_vote.restype = C.c_int
+    L.hough_vertex_vote.argtypes = [P, P, C.c_int32, P, P, P, S, P, P]
+    L.hough_vertex_peaks.restype = C.c_int
+    L.hough_vertex_peaks.argtypes = [P, P, C.c_int32, P, C.c_int32, P, S, P, P]
+    L.hough_vertex_table.restype = C.c_int; L.hough_vertex_table.argtypes = [P, P]
     L.hough_plan_set_tuning.restype = C.c_int; L.hough_plan_set_tuning.argtypes = [P, C.POINTER(Tuning)]
     L.hough_plan_get_tuning.restype = C.c_int; L.hough_plan_get_tuning.argtypes = [P, C.POINTER(Tuning)]
     L.hough_plan_set_vote_events.restype = C.c_int; L.hough_plan_set_vote_events.argtypes = [P, P, P]
@@ -102,7 +119,9 @@ EXPORTED = ["hough_plan_create", "hough_plan_destroy", "hough_acc_bytes", "hough
             "hough_angle_bits", "hough_plan_table", "hough_prep", "hough_vote", "hough_vote_prepared", "hough_peaks",
             "hough_assign", "hough_zvote", "hough_fit", "hough_plan_arclen_table", "hough_strerror", "hough_plan_set_tuning", "hough_plan_get_tuning", "hough_plan_set_vote_events",
             "hough_batch_ws_bytes", "hough_run_batch", "hough_batch_graph_create", "hough_graph_launch",
-            "hough_graph_destroy"]
+            "hough_graph_destroy", "hough_vertex_plan_create", "hough_vertex_plan_destroy", "hough_vertex_set_groups",
+            "hough_vertex_get_groups", "hough_vertex_vote_ws_bytes", "hough_vertex_peaks_ws_bytes",
+            "hough_vertex_vote", "hough_vertex_peaks", "hough_vertex_table"]
 
 
 def _check(rc: int, what: str) -> None:
@@ -270,6 +289,95 @@ def fit(plan: Plan, hits: Hits, offsets: torch.Tensor, hit_idx: torch.Tensor, st
         raise HoughError("out needs [cap_peaks][4] float64 and offsets cap_peaks + 1 entries")
     _check(lib.hough_fit(plan.handle, C.byref(hits), _ptr(offsets), _ptr(hit_idx), int(cap_peaks),
                          int(hit_idx.numel()), _ptr(status), _ptr(out), _stream(stream)), "hough_fit")
+
+
+class VertexPlan:
+    """The second transform (vertex space) of a first-stage plan; keeps the plan alive."""
+
+    def __init__(self, plan: Plan, n_vr: int, n_vphi: int, r_min: float, r_max: float, min_votes: int):
+        self.plan = plan
+        self.n_vr, self.n_vphi = int(n_vr), int(n_vphi)
+        vg = VertexGrid(self.n_vr, self.n_vphi, float(r_min), float(r_max), int(min_votes))
+        h = C.c_void_p()
+        _check(lib.hough_vertex_plan_create(plan.handle, C.byref(vg), C.byref(h)), "hough_vertex_plan_create")
+        self.handle = h.value
+
+    @classmethod
+    def of(cls, plan: Plan) -> "VertexPlan":
+        c = plan.cfg
+        mv = c.v_min_votes if c.v_min_votes > 0 else c.threshold
+        return cls(plan, c.n_vr, c.n_vphi, c.vr_min, c.vr_max, mv)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib.hough_vertex_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def groups(self) -> int:
+        return int(lib.hough_vertex_get_groups(self.handle))
+
+    def set_groups(self, groups: int) -> None:
+        _check(lib.hough_vertex_set_groups(self.handle, int(groups)), "hough_vertex_set_groups")
+
+    def vote_ws_bytes(self, cap_peaks: int) -> int:
+        return int(lib.hough_vertex_vote_ws_bytes(self.handle, int(cap_peaks)))
+
+    def peaks_ws_bytes(self, cap_vpeaks: int) -> int:
+        return int(lib.hough_vertex_peaks_ws_bytes(self.handle, int(cap_vpeaks)))
+
+    def table(self) -> np.ndarray:
+        c = self.plan.cfg
+        out = np.zeros((c.n_d0, c.n_qpt, self.n_vr), dtype=np.int32)
+        _check(lib.hough_vertex_table(self.handle, out.ctypes.data), "hough_vertex_table")
+        return out
+
+
+def vertex_vote(vp: VertexPlan, pk: torch.Tensor, status: torch.Tensor, acc_v: torch.Tensor, ws: torch.Tensor,
+                status_v: torch.Tensor, stream=None) -> None:
+    """Vote the candidates pk [cap][4] (count from the device status) into acc_v [n_vr][n_vphi] int32."""
+    if acc_v.dtype != torch.int32 or acc_v.numel() != vp.n_vr * vp.n_vphi or pk.dim() != 2 or pk.shape[1] != 4:
+        raise HoughError("acc_v needs n_vr * n_vphi int32 and pk [cap][4]")
+    _check(lib.hough_vertex_vote(vp.handle, _ptr(pk), int(pk.shape[0]), _ptr(status), _ptr(acc_v), _ptr(ws),
+                                 int(ws.numel() * ws.element_size()), _ptr(status_v), _stream(stream)),
+           "hough_vertex_vote")
+
+
+def vertex_peaks(vp: VertexPlan, acc_v: torch.Tensor, threshold: int, out: torch.Tensor, ws: torch.Tensor,
+                 status_v: torch.Tensor, stream=None) -> None:
+    if acc_v.dtype != torch.int32 or acc_v.numel() != vp.n_vr * vp.n_vphi:
+        raise HoughError("acc_v needs n_vr * n_vphi int32")
+    _check(lib.hough_vertex_peaks(vp.handle, _ptr(acc_v), int(threshold), _ptr(out), int(out.shape[0]), _ptr(ws),
+                                  int(ws.numel() * ws.element_size()), _ptr(status_v), _stream(stream)),
+           "hough_vertex_peaks")
+
+
+class VertexBuffers:
+    """Device buffers of the second transform for one event: vertex accumulator, the two
+    workspaces, status and vertex-candidate list."""
+
+    def __init__(self, vp: VertexPlan, cap_peaks: int, cap_vpeaks: int, device="cuda"):
+        self.vp = vp
+        self.acc = torch.empty((vp.n_vr, vp.n_vphi), dtype=torch.int32, device=device)
+        self.ws_vote = torch.empty(max(vp.vote_ws_bytes(cap_peaks), 1), dtype=torch.uint8, device=device)
+        self.ws_peaks = torch.empty(vp.peaks_ws_bytes(cap_vpeaks), dtype=torch.uint8, device=device)
+        self.status = torch.zeros(STATUS_BYTES // 4, dtype=torch.int32, device=device)
+        self.peaks = torch.empty((cap_vpeaks, PEAK_INTS), dtype=torch.int32, device=device)
+
+    def run(self, pk: torch.Tensor, status: torch.Tensor, threshold: int, stream=None) -> None:
+        vertex_vote(self.vp, pk, status, self.acc, self.ws_vote, self.status, stream)
+        vertex_peaks(self.vp, self.acc, threshold, self.peaks, self.ws_peaks, self.status, stream)
+
+    def results(self) -> dict:
+        st = status_dict(self.status)
+        n = min(st["n_peaks"], self.peaks.shape[0])
+        return dict(status=st, acc=self.acc.cpu().numpy(), peaks=self.peaks[:n].cpu().numpy())
 
 
 def status_dict(status: torch.Tensor) -> dict:

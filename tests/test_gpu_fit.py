@@ -37,7 +37,12 @@ def test_fit_small_events_equal_oracle(H, oracle_mod, shape, tracks, eid):
     ev = synth.make_event(cfg, eid)
     res = _chain_with_fit(H, cfg, ev, 1 << 16, 1 << 20)
     assert res["status"]["n_peaks"] > 0
-    ref = O.fit(ev, res["offsets"], res["hit_idx"])  # the oracle fit of the (oracle-checked) lists
+    g = O.Cfg(cfg)
+    _, pk = O.peaks(g, O.vote(g, ev)[0], cfg.threshold)
+    offs, hit_idx, _ = O.assign(g, ev, pk)  # the oracle's own lists, equal to the GPU's
+    np.testing.assert_array_equal(res["offsets"], offs)
+    np.testing.assert_array_equal(res["hit_idx"], hit_idx)
+    ref = O.fit(ev, offs, hit_idx)
     np.testing.assert_array_equal(res["fit"], ref)
     assert (ref[:, 2] > 0).any()
 
