@@ -185,6 +185,58 @@ def bench_large_grid(H, torch, reps: int):
     }
 
 
+def bench_vertex(H, torch, reps: int):
+    """The second transform (vertex space of the candidates) on one large-grid event: the event's
+    first stage (prep, vote, peaks) gives its candidate list on the device; every candidate
+    (votes >= the first-stage threshold) votes into 64 radius rows x 512 azimuth bins; then the
+    vertex peaks.  The first stage of the same event is timed beside it (the paper counts the
+    second transform as a second cost of the same kind)."""
+    from paper_1305_4855_amd import configs, synth
+
+    cfg = configs.C4
+    ev = synth.make_event(cfg, 0)
+    plan = H.Plan(cfg, max_hits=cfg.max_hits_per_event)
+    bufs = H.EventBuffers(plan, cap_peaks=1 << 21, cap_pairs=1 << 20)
+    x, y, lay, _ = H.hits_to_device(ev)
+    hits = H.make_hits(x, y, lay)
+    vp = H.VertexPlan.of(plan)
+    vb = H.VertexBuffers(vp, cap_peaks=1 << 21, cap_vpeaks=1 << 16)
+    stream = torch.cuda.current_stream()
+    bufs.run(hits, cfg.threshold, stream, do_assign=False)
+    vb.run(bufs.peaks, bufs.status, cfg.v_threshold, stream)
+    torch.cuda.synchronize()
+
+    def timed(fn):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(reps):
+            fn()
+        b.record(stream)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps
+
+    first_ms = timed(lambda: bufs.run(hits, cfg.threshold, stream, do_assign=False))
+    vote_ms = timed(lambda: H.vertex_vote(vp, bufs.peaks, bufs.status, vb.acc, vb.ws_vote, vb.status, stream))
+    peaks_ms = timed(lambda: H.vertex_peaks(vp, vb.acc, cfg.v_threshold, vb.peaks, vb.ws_peaks, vb.status, stream))
+    st1 = H.status_dict(bufs.status)
+    stv = H.status_dict(vb.status)
+    votes = stv["n_votes"]
+    achieved = votes / (vote_ms * 1e-3) / 1e9
+    peak = 256 * 2.4e9 * 16 / 1e9  # LDS atomic lanes per second, as for the first vote
+    return {
+        "workload": "vertex space of one large-grid event (c4 event 0): every first-stage candidate votes into "
+                    f"{cfg.n_vr} radius rows x {cfg.n_vphi} azimuth bins over [{cfg.vr_min}, {cfg.vr_max}) cm, "
+                    f"then vertex peaks (threshold {cfg.v_threshold})",
+        "hits": ev.n, "candidates": st1["n_peaks"], "vertex_votes": votes, "vertex_candidates": stv["n_peaks"],
+        "groups": vp.groups, "first_stage_ms": round(first_ms, 4), "vertex_vote_ms": round(vote_ms, 4),
+        "vertex_peaks_ms": round(peaks_ms, 4), "second_over_first": round((vote_ms + peaks_ms) / first_ms, 3),
+        "roofline": {"kernel": "k_vvote + k_vreduce", "bound": "alu", "achieved": round(achieved, 1),
+                     "peak": peak, "unit": "Gvote/s", "frac": round(achieved / peak, 4), "traffic": None},
+        "note": "per-call time of back-to-back calls; the vote time includes the reduction of the partial "
+                "vertex spaces (split in the kernel trace)",
+    }
+
+
 def bench_serving(H, torch, runs, pool_size: int = 256):
     """Streaming trigger serving: for each (rate_hz, duration_s) of `runs`, Poisson arrivals at that
     rate, event sizes as in the batched workload, admitted into device-resident slots within a
@@ -357,6 +409,7 @@ def main() -> int:
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-plain", action="store_true", help="skip the single-event section (profiling runs)")
     ap.add_argument("--no-large-grid", action="store_true")
+    ap.add_argument("--no-vertex", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=60.0)
     ap.add_argument("--serve-rate", type=float, default=20000.0)
     ap.add_argument("--serve-rate-low", type=float, default=14000.0,
@@ -385,6 +438,9 @@ def main() -> int:
         out["batched"] = bench_batched(H, torch, args.batch_events, reps=10)
     if not args.no_large_grid:
         out["large_grid"] = bench_large_grid(H, torch, reps=3)
+    if not args.no_vertex:
+        torch.cuda.empty_cache()
+        out["vertex"] = bench_vertex(H, torch, reps=20)
     if not args.no_serving:
         torch.cuda.empty_cache()
         runs = [(args.serve_rate, args.serve_seconds)]

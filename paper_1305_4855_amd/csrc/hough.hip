@@ -1237,6 +1237,7 @@ __global__ __launch_bounds__(kWriteThreads) void k_peaks_write(Events ev, const 
 // is cheap for one event and not for hundreds, so large batches use the two kernels above.
 constexpr int kCarryUnroll = 8;         // 16-byte loads per thread and round of the carry-in sum
 constexpr int kScanWriteMaxEvents = 4;  // batches up to this size take the one-pass form
+constexpr int64_t kScanWriteMaxGroups = 32768;  // groups of a 512x256x64 grid: 16384; of 1024x512x128: 131072
 
 template <typename T>
 __global__ __launch_bounds__(kWriteThreads) void k_peaks_scan_write(Events ev, const char* __restrict__ acc_base,
@@ -2085,7 +2086,9 @@ void launch_peaks(const hough_plan* p, const Events& ev, int n_events, const voi
     else
         hipLaunchKernelGGL((k_peaks_mark<int16_t, false>), gm, mb, 0, stream, ev, a, acc_stride, z16, threshold, nd,
                            nq, nph, gl, planes, ws, O);
-    if (n_events <= kScanWriteMaxEvents) {  // scan and writer in one pass
+    // scan and writer in one pass: each writer workgroup re-reads the counts of all groups before
+    // it, so only while that is cheaper than a separate scan (few events, not too many groups)
+    if (n_events <= kScanWriteMaxEvents && groups <= kScanWriteMaxGroups) {
         if (p->g.acc_bits == 32)
             hipLaunchKernelGGL(k_peaks_scan_write<int32_t>, gw, dim3(kWriteThreads), 0, stream, ev, a, acc_stride,
                                groups, p->g.n_qpt, p->g.n_phi, gl, n_strips, ws, O, peaks, cap, st);
@@ -2162,7 +2165,7 @@ void launch_zvote(const hough_plan* p, const Events& ev, int n_events, const flo
 // the dword (bin * 32 + c), so a 32-lane half of a ds_add touches 32 distinct dwords), and copies
 // its slab to its own partial in ws.  A half never carries: a row counts at most one vote per
 // candidate and a range holds at most 65535 candidates.  k_vreduce adds the partials.
-constexpr int kVvoteThreads = 512;
+constexpr int kVvoteThreads = 1024;
 constexpr int kVvoteUnroll = 8;
 constexpr int kVreduceThreads = 1024;
 constexpr int kVertexMaxRange = 65535;  // candidates per partial (16-bit halves)
@@ -2209,40 +2212,79 @@ __global__ __launch_bounds__(kVvoteThreads) void k_vvote(const hough_peak_t* __r
     const uint32_t inc = lane < 32 ? 1u : 65536u;
     const int32_t* Trow = T + s * 64 + lane;
     const uint32_t half = 1u << (vg.F - 1);
-    const int bin_shift = vg.shift;
-    const uint32_t bin_mask = (uint32_t)vg.n_vphi - 1u;
-    for (int base = p0 + wave * 64; base < p1; base += (kVvoteThreads / 64) * 64) {
-        int4 c4 = make_int4(0, 0, 0, 0);  // votes 0 < min_votes: lanes past the range cast nothing
-        if (base + lane < p1) c4 = *reinterpret_cast<const int4*>(peaks + base + lane);
-        const int cnt = min(64, p1 - base);
-        for (int i0 = 0; i0 < cnt; i0 += kVvoteUnroll) {
-            int32_t e[kVvoteUnroll];
-            uint32_t ph[kVvoteUnroll];
+    // Candidates come sorted by linear index, so runs of them share a (l, k) column and with it the
+    // table row (lane = radius row).  A wave takes 64 candidates (lane = candidate), marks the first
+    // of each run (a head), loads the rows of up to kVvoteUnroll heads at once and then votes every
+    // candidate of those runs (lane = row again) with the candidate's angle broadcast by readlane.
+    // The next 64 candidates are loaded after the rows, so waiting for a row never waits for them.
+    // Angles are held left-aligned in 32 bits (M-bit angle << (32 - M)), so the angle sum wraps
+    // mod 2^M by itself and the azimuth bin is its top log2(n_vphi) bits.  Per vote: readlane,
+    // add, shift, and-or into the LDS byte address, ds_add; a row without a valid sample adds 0.
+    constexpr int kStride = (kVvoteThreads / 64) * 64;
+    const uint32_t lv = 32u - (uint32_t)__builtin_clz((uint32_t)vg.n_vphi) - 1u;  // log2 n_vphi
+    const uint32_t lsh = 32u - (uint32_t)vg.shift - lv;                                // 32 - M (M = shift + lv)
+    const uint32_t to_row = 25u - lv;   // (sum >> to_row) & ~127 = bin * 128 (a 128-byte slab row)
+    const uint32_t loff = (uint32_t)(lane & 31) << 2;
+    const uint32_t row_mask = __builtin_amdgcn_readfirstlane(0xFFFFFF80u);
+    int base = p0 + wave * 64;
+    int4 c4 = make_int4(0, 0, 0, 0);  // votes 0 < min_votes: lanes past the range cast nothing
+    if (base + lane < p1) c4 = *reinterpret_cast<const int4*>(peaks + base + lane);
+    for (; base < p1; base += kStride) {
+        // a bin outside the first grid (not one the peak finder writes) casts nothing
+        const bool on = c4.w >= vg.min_votes && (unsigned)c4.x < (unsigned)vg.n_d0 &&
+                        (unsigned)c4.y < (unsigned)vg.n_qpt && (unsigned)c4.z < (unsigned)vg.n_phi;
+        const int key = on ? c4.x * vg.n_qpt + c4.y : -1;
+        const int prev = __shfl_up(key, 1, 64);
+        uint64_t heads = __ballot(on && (lane == 0 || key != prev));
+        const uint64_t onm = __ballot(on);
+        // the candidate's phi0 centre, left-aligned
+        const uint32_t ang = (((uint32_t)c4.z << vg.F) + half) << lsh;
+        bool fetched = false;
+        while (heads) {
+            int h[kVvoteUnroll + 1];
+            uint32_t e[kVvoteUnroll];
 #pragma unroll
             for (int u = 0; u < kVvoteUnroll; ++u) {
-                const int i = i0 + u;
-                const int v = __builtin_amdgcn_readlane(c4.w, i);
-                const int l = __builtin_amdgcn_readlane(c4.x, i);
-                const int k = __builtin_amdgcn_readlane(c4.y, i);
-                const int b = __builtin_amdgcn_readlane(c4.z, i);
-                // a bin outside the first grid (not one the peak finder writes) casts nothing
-                const bool on = v >= vg.min_votes && (unsigned)l < (unsigned)vg.n_d0 &&
-                                (unsigned)k < (unsigned)vg.n_qpt && (unsigned)b < (unsigned)vg.n_phi;
-                const size_t off = on ? ((size_t)l * vg.n_qpt + k) * vg.n_vr : 0;
-                const int32_t t = Trow[off];
-                e[u] = on ? t : INT32_MIN;
-                ph[u] = ((uint32_t)b << vg.F) + half;
+                h[u] = heads ? (int)__builtin_ctzll(heads) : 64;
+                heads &= heads - 1;  // (no-op once empty)
+                const int kk = __builtin_amdgcn_readlane(key, h[u] < 64 ? h[u] : 0);
+                e[u] = (uint32_t)Trow[(size_t)(h[u] < 64 ? kk : 0) * vg.n_vr];
+            }
+            h[kVvoteUnroll] = heads ? (int)__builtin_ctzll(heads) : 64;  // end of the last run
+            if (!fetched) {
+                fetched = true;
+                const int nb = base + kStride;
+                int4 t = make_int4(0, 0, 0, 0);
+                if (nb + lane < p1) t = *reinterpret_cast<const int4*>(peaks + nb + lane);
+                c4 = t;
             }
 #pragma unroll
             for (int u = 0; u < kVvoteUnroll; ++u) {
-                if (e[u] != INT32_MIN) {
-                    const uint32_t a = (ph[u] + (uint32_t)e[u]) & vg.mask_m;
-                    const uint32_t w = (((a >> bin_shift) & bin_mask) << 5) | (uint32_t)(lane & 31);
-                    __hip_atomic_fetch_add(slab + w, inc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                if (h[u] >= 64) break;
+                const uint32_t data = e[u] != (uint32_t)INT32_MIN ? inc : 0u;
+                const uint32_t el = e[u] << lsh;
+                const int span = h[u + 1] - h[u];
+                uint64_t m = onm & (span >= 64 ? ~0ull : (((1ull << span) - 1ull) << h[u]));
+                while (m) {
+                    const int i = (int)__builtin_ctzll(m);
+                    m &= m - 1;
+                    const uint32_t sum = (uint32_t)__builtin_amdgcn_readlane((int)ang, i) + el;
+                    // byte address in the slab (which starts at LDS address 0: the kernel has no static LDS)
+                    uint32_t off;  // one and-or (the compiler otherwise splits it into an and and an add)
+                    asm("v_and_or_b32 %0, %1, %2, %3" : "=v"(off) : "v"(sum >> to_row), "s"(row_mask), "v"(loff));
+                    asm volatile("ds_add_u32 %0, %1" ::"v"(off), "v"(data) : "memory");
                 }
             }
         }
+        if (!fetched) {  // no candidate of this chunk votes
+            const int nb = base + kStride;
+            int4 t = make_int4(0, 0, 0, 0);
+            if (nb + lane < p1) t = *reinterpret_cast<const int4*>(peaks + nb + lane);
+            c4 = t;
+        }
     }
+    // the atomics above are inline asm, which the compiler's wait counting does not see
+    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
     __syncthreads();
     uint4* dst = reinterpret_cast<uint4*>(partial + ((size_t)s * vg.groups + g) * words);
     for (int i = tid; i < words / 4; i += kVvoteThreads) dst[i] = reinterpret_cast<const uint4*>(slab)[i];
