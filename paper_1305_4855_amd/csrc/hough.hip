@@ -1601,30 +1601,86 @@ __global__ __launch_bounds__(kAssignThreads) void k_assign_fill(
 }
 
 // ------------------------------------------------------------------ fit
-// Track fit of each listed candidate (grid.y = event), one thread per candidate: the algebraic
+// Track fit of each listed candidate (grid.y = event), one lane per candidate: the algebraic
 // (Kasa) circle x^2 + y^2 + a x + b y + c = 0 through its hits in the least-squares sense.  The
 // eight moments of the normal equations are summed over the candidate's hit list in list order
-// (double, four hits' loads issued together), the 3x3 system is solved by Cramer's rule, and the
+// (double), the 3x3 system is solved by Cramer's rule, and the
 // row (xc, yc, R^2, n) = (-a/2, -b/2, xc^2 + yc^2 - c, n) is written; R^2 = -1 for fewer than 3 hits
 // or a zero determinant, -2 for a list cut by the pair capacity.
 constexpr int kFitThreads = 256;
+constexpr int kFitBuf = 1024;  // list entries staged per wave (coordinates, 8 KiB)
 
+// A wave fits 64 consecutive candidates, whose lists are one contiguous stretch of the CSR list.
+// The stretch is staged in pieces of kFitBuf entries: hit indices loaded coalesced, coordinates
+// gathered (four per lane in flight) into the wave's LDS buffer; then every lane adds the entries of
+// its own list that lie in the piece, in list order, so the sums are those of a plain loop over the
+// list.
 __global__ __launch_bounds__(kFitThreads) void k_fit(Events ev, const float* __restrict__ hx,
                                                     const float* __restrict__ hy,
                                                     const int32_t* __restrict__ offsets_base,
                                                     const int32_t* __restrict__ hit_idx_base, int32_t cap_peaks,
                                                     int32_t cap_pairs, const hough_status_t* __restrict__ st_base,
                                                     double* __restrict__ out_base) {
+    __shared__ float2 stage[kFitThreads / 64][kFitBuf];
     const int e = blockIdx.y;
     const int n = min(st_base[e].n_peaks, cap_peaks);
-    const int p = blockIdx.x * kFitThreads + threadIdx.x;
-    if (p >= n) return;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int pw = (blockIdx.x * (kFitThreads / 64) + wave) * 64;  // the wave's first candidate
+    if (pw >= n) return;
+    const int p = pw + lane;
+    const bool valid = p < n;
     int h0, nh;
     event_hits(ev, e, h0, nh);
     const int32_t* offsets = offsets_base + (size_t)e * (cap_peaks + 1);
     const int32_t* hit_idx = hit_idx_base + (size_t)e * cap_pairs;
+    const int32_t q0 = valid ? offsets[p] : 0, q1 = valid ? offsets[p + 1] : 0;
+    const int32_t s0 = offsets[pw];
+    const int32_t s1 = min(offsets[min(pw + 64, n)], cap_pairs);  // entries past the capacity were not written
+    float2* buf = stage[wave];
+    double sx = 0.0, sy = 0.0, sxx = 0.0, sxy = 0.0, syy = 0.0, sz = 0.0, sxz = 0.0, syz = 0.0;
+    for (int ps = s0; ps < s1; ps += kFitBuf) {
+        const int len = min(kFitBuf, s1 - ps);
+        {  // all of a lane's indices, then all its gathers: two dependent memory steps per piece
+            constexpr int kPer = kFitBuf / 64;
+            int hh[kPer];
+#pragma unroll
+            for (int u = 0; u < kPer; ++u) hh[u] = lane + 64 * u < len ? hit_idx[ps + lane + 64 * u] : 0;
+#pragma unroll
+            for (int u = 0; u < kPer; ++u) {
+                const float xv = hx[h0 + hh[u]], yv = hy[h0 + hh[u]];
+                if (lane + 64 * u < len) buf[lane + 64 * u] = make_float2(xv, yv);
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const int qa = max(q0, ps), qb = min(q1, ps + len);
+        for (int q = qa; q < qb; q += 4) {  // four entries read at once, added in order
+            float2 v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) v[u] = buf[min(q + u, qb - 1) - ps];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                if (q + u < qb) {
+                    const double X = (double)v[u].x, Y = (double)v[u].y;
+                    const double Z = X * X + Y * Y;
+                    sx += X;
+                    sy += Y;
+                    sxx += X * X;
+                    sxy += X * Y;
+                    syy += Y * Y;
+                    sz += Z;
+                    sxz += X * Z;
+                    syz += Y * Z;
+                }
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();  // every lane is done with the piece before it is overwritten
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+    if (!valid) return;
     double* o = out_base + ((size_t)e * cap_peaks + p) * 4;
-    const int32_t q0 = offsets[p], q1 = offsets[p + 1];
     const double N = (double)(q1 - q0);
     if (q1 > cap_pairs) {  // the list was cut: no fit
         o[0] = 0.0;
@@ -1632,30 +1688,6 @@ __global__ __launch_bounds__(kFitThreads) void k_fit(Events ev, const float* __r
         o[2] = -2.0;
         o[3] = N;
         return;
-    }
-    double sx = 0.0, sy = 0.0, sxx = 0.0, sxy = 0.0, syy = 0.0, sz = 0.0, sxz = 0.0, syz = 0.0;
-    for (int q = q0; q < q1; q += 4) {
-        double X[4], Y[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int h = hit_idx[min(q + u, q1 - 1)];
-            X[u] = (double)hx[h0 + h];
-            Y[u] = (double)hy[h0 + h];
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            if (q + u < q1) {
-                const double Z = X[u] * X[u] + Y[u] * Y[u];
-                sx += X[u];
-                sy += Y[u];
-                sxx += X[u] * X[u];
-                sxy += X[u] * Y[u];
-                syy += Y[u] * Y[u];
-                sz += Z;
-                sxz += X[u] * Z;
-                syz += Y[u] * Z;
-            }
-        }
     }
     // normal matrix [[sxx, sxy, sx], [sxy, syy, sy], [sx, sy, N]], right-hand side -(sxz, syz, sz)
     const double m_yy = syy * N - sy * sy;  // cofactors shared by the determinants
