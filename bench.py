@@ -338,8 +338,11 @@ def bench_plain(H, torch, args):
     st = H.status_dict(bufs.status)
 
     # Track fit of every candidate (the next step after the assignment, outside the timed chain):
-    # launched `reps` times back to back; HBM-bound work per launch = the CSR lists and offsets
-    # read, the fitted rows written (the hit coordinates are L2-resident)
+    # launched `reps` times back to back.  The fit is bound by its IEEE double arithmetic (the
+    # moments are summed in double, in list order): 16 flops per list entry (three products and
+    # three additions for the squares and cross term, eight moment updates with two more
+    # products) and about 60 per candidate for the 3x3 solve; HBM bytes (lists, offsets, rows)
+    # are reported beside it
     H.assign(plan, bufs.peaks, bufs.offsets, bufs.hit_idx, bufs.ws, bufs.status, stream)
     bufs.run_fit(hits, stream)
     a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -352,12 +355,16 @@ def bench_plain(H, torch, args):
     n_fit = min(st["n_peaks"], bufs.peaks.shape[0])
     fit_bytes = 4 * st["n_pairs"] + 4 * (n_fit + 1) + 32 * n_fit + 8 * ev.n
     fit_gbs = fit_bytes / (fit_ms * 1e-3) / 1e9
+    fit_flops = 16 * st["n_pairs"] + 60 * n_fit
+    fit_tf = fit_flops / (fit_ms * 1e-3) / 1e12
     fit = {"workload": "algebraic circle fit of every candidate of the dense event (c2)",
            "candidates": n_fit, "pairs": st["n_pairs"], "ms_per_launch": round(fit_ms, 5),
            "candidates_per_s": round(n_fit / (fit_ms * 1e-3), 1),
-           "roofline": {"kernel": "k_fit", "bound": "hbm", "achieved": round(fit_gbs, 1), "peak": 8000.0,
-                        "unit": "GB/s", "frac": round(fit_gbs / 8000.0, 4), "traffic": None,
-                        "bytes_per_launch": fit_bytes},
+           "roofline": {"kernel": "k_fit_res", "bound": "alu", "achieved": round(fit_tf, 3), "peak": 78.6,
+                        "unit": "TFLOP/s (fp64)", "frac": round(fit_tf / 78.6, 4), "traffic": None,
+                        "flops_per_launch": fit_flops},
+           "hbm": {"bytes_per_launch": fit_bytes, "achieved_gbs": round(fit_gbs, 1),
+                   "frac_of_8000": round(fit_gbs / 8000.0, 4)},
            "note": "per-launch time of back-to-back launches (kernel plus launch gap)"}
 
     ms_per_step = (t1 - t0) * 1e3 / args.steps

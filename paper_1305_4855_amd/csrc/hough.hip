@@ -1607,6 +1607,56 @@ __global__ __launch_bounds__(kAssignThreads) void k_assign_fill(
 // (double), the 3x3 system is solved by Cramer's rule, and the
 // row (xc, yc, R^2, n) = (-a/2, -b/2, xc^2 + yc^2 - c, n) is written; R^2 = -1 for fewer than 3 hits
 // or a zero determinant, -2 for a list cut by the pair capacity.
+// The moments of one list entry, added in the fixed order of a plain loop over the list.
+struct FitSums {
+    double sx = 0.0, sy = 0.0, sxx = 0.0, sxy = 0.0, syy = 0.0, sz = 0.0, sxz = 0.0, syz = 0.0;
+    __device__ __forceinline__ void add(float xf, float yf) {
+        const double X = (double)xf, Y = (double)yf;
+        const double Z = X * X + Y * Y;
+        sx += X;
+        sy += Y;
+        sxx += X * X;
+        sxy += X * Y;
+        syy += Y * Y;
+        sz += Z;
+        sxz += X * Z;
+        syz += Y * Z;
+    }
+};
+
+// Solve and store the row of a list [q0, q1) (cut when q1 > cap_pairs).
+__device__ __forceinline__ void fit_store(double* o, int32_t q0, int32_t q1, int32_t cap_pairs, const FitSums& m) {
+    const double N = (double)(q1 - q0);
+    if (q1 > cap_pairs) {  // the list was cut: no fit
+        o[0] = 0.0;
+        o[1] = 0.0;
+        o[2] = -2.0;
+        o[3] = N;
+        return;
+    }
+    const double sx = m.sx, sy = m.sy, sxx = m.sxx, sxy = m.sxy, syy = m.syy, sz = m.sz, sxz = m.sxz, syz = m.syz;
+    // normal matrix [[sxx, sxy, sx], [sxy, syy, sy], [sx, sy, N]], right-hand side -(sxz, syz, sz)
+    const double m_yy = syy * N - sy * sy;  // cofactors shared by the determinants
+    const double m_xy = sxy * N - sy * sx;
+    const double m_c = sxy * sy - syy * sx;
+    const double det = sxx * m_yy - sxy * m_xy + sx * m_c;
+    o[3] = N;
+    if (N < 3.0 || det == 0.0) {
+        o[0] = 0.0;
+        o[1] = 0.0;
+        o[2] = -1.0;
+        return;
+    }
+    const double r0 = -sxz, r1 = -syz, r2 = -sz;
+    const double a = (r0 * m_yy - sxy * (r1 * N - sy * r2) + sx * (r1 * sy - syy * r2)) / det;
+    const double b = (sxx * (r1 * N - r2 * sy) - r0 * m_xy + sx * (sxy * r2 - r1 * sx)) / det;
+    const double c = (sxx * (syy * r2 - sy * r1) - sxy * (sxy * r2 - r1 * sx) + r0 * m_c) / det;
+    const double xc = -a / 2.0, yc = -b / 2.0;
+    o[0] = xc;
+    o[1] = yc;
+    o[2] = xc * xc + yc * yc - c;
+}
+
 constexpr int kFitThreads = 256;
 constexpr int kFitBuf = 1024;  // list entries staged per wave (coordinates, 8 KiB)
 
@@ -1637,14 +1687,15 @@ __global__ __launch_bounds__(kFitThreads) void k_fit(Events ev, const float* __r
     const int32_t s0 = offsets[pw];
     const int32_t s1 = min(offsets[min(pw + 64, n)], cap_pairs);  // entries past the capacity were not written
     float2* buf = stage[wave];
-    double sx = 0.0, sy = 0.0, sxx = 0.0, sxy = 0.0, syy = 0.0, sz = 0.0, sxz = 0.0, syz = 0.0;
+    FitSums m;
     for (int ps = s0; ps < s1; ps += kFitBuf) {
         const int len = min(kFitBuf, s1 - ps);
         {  // all of a lane's indices, then all its gathers: two dependent memory steps per piece
             constexpr int kPer = kFitBuf / 64;
             int hh[kPer];
 #pragma unroll
-            for (int u = 0; u < kPer; ++u) hh[u] = lane + 64 * u < len ? hit_idx[ps + lane + 64 * u] : 0;
+            for (int u = 0; u < kPer; ++u)  // clamped, not skipped: a load under a branch waits on its own
+                hh[u] = hit_idx[ps + min(lane + 64 * u, len - 1)];
 #pragma unroll
             for (int u = 0; u < kPer; ++u) {
                 const float xv = hx[h0 + hh[u]], yv = hy[h0 + hh[u]];
@@ -1660,55 +1711,79 @@ __global__ __launch_bounds__(kFitThreads) void k_fit(Events ev, const float* __r
 #pragma unroll
             for (int u = 0; u < 4; ++u) v[u] = buf[min(q + u, qb - 1) - ps];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                if (q + u < qb) {
-                    const double X = (double)v[u].x, Y = (double)v[u].y;
-                    const double Z = X * X + Y * Y;
-                    sx += X;
-                    sy += Y;
-                    sxx += X * X;
-                    sxy += X * Y;
-                    syy += Y * Y;
-                    sz += Z;
-                    sxz += X * Z;
-                    syz += Y * Z;
-                }
-            }
+            for (int u = 0; u < 4; ++u)
+                if (q + u < qb) m.add(v[u].x, v[u].y);
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();  // every lane is done with the piece before it is overwritten
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
     if (!valid) return;
-    double* o = out_base + ((size_t)e * cap_peaks + p) * 4;
-    const double N = (double)(q1 - q0);
-    if (q1 > cap_pairs) {  // the list was cut: no fit
-        o[0] = 0.0;
-        o[1] = 0.0;
-        o[2] = -2.0;
-        o[3] = N;
-        return;
+    fit_store(out_base + ((size_t)e * cap_peaks + p) * 4, q0, q1, cap_pairs, m);
+}
+
+// Events of up to kFitResHits hits: the workgroup first copies all the event's coordinates into
+// LDS, so the per-entry gathers are LDS reads (from global memory each lane's gather touched its own
+// cache line, which bound the kernel above); the staged piece of the list holds hit indices only.
+// Workgroups loop over the event's 64-candidate chunks.
+constexpr int kFitResThreads = 1024;
+constexpr int kFitResBuf = 512;  // list entries staged per wave
+constexpr int kFitResIdxBytes = (kFitResThreads / 64) * kFitResBuf * 4;
+constexpr int kFitResHits = (kLdsBytes - kFitResIdxBytes) / 8;
+
+__global__ __launch_bounds__(kFitResThreads) void k_fit_res(Events ev, const float* __restrict__ hx,
+                                                           const float* __restrict__ hy,
+                                                           const int32_t* __restrict__ offsets_base,
+                                                           const int32_t* __restrict__ hit_idx_base,
+                                                           int32_t cap_peaks, int32_t cap_pairs,
+                                                           const hough_status_t* __restrict__ st_base,
+                                                           double* __restrict__ out_base, int32_t res_hits) {
+    extern __shared__ float2 xy[];  // [res_hits] coordinates, then the waves' index pieces
+    constexpr int kWaves = kFitResThreads / 64;
+    const int e = blockIdx.y;
+    const int n = min(st_base[e].n_peaks, cap_peaks);
+    if (blockIdx.x * kWaves * 64 >= n) return;
+    int h0, nh;
+    event_hits(ev, e, h0, nh);
+    if (nh > res_hits) return;  // (the launch sizes res_hits for every event it covers)
+    for (int i = threadIdx.x; i < nh; i += kFitResThreads) xy[i] = make_float2(hx[h0 + i], hy[h0 + i]);
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    int32_t* ib = reinterpret_cast<int32_t*>(xy + res_hits) + wave * kFitResBuf;
+    const int32_t* offsets = offsets_base + (size_t)e * (cap_peaks + 1);
+    const int32_t* hit_idx = hit_idx_base + (size_t)e * cap_pairs;
+    for (int chunk = blockIdx.x * kWaves + wave; chunk * 64 < n; chunk += gridDim.x * kWaves) {
+        const int pw = chunk * 64, p = pw + lane;
+        const bool valid = p < n;
+        const int32_t q0 = valid ? offsets[p] : 0, q1 = valid ? offsets[p + 1] : 0;
+        const int32_t s0 = offsets[pw];
+        const int32_t s1 = min(offsets[min(pw + 64, n)], cap_pairs);
+        FitSums m;
+        for (int ps = s0; ps < s1; ps += kFitResBuf) {
+            const int len = min(kFitResBuf, s1 - ps);
+            constexpr int kPer = kFitResBuf / 64;
+            int hh[kPer];
+#pragma unroll
+            for (int u = 0; u < kPer; ++u)  // clamped, not skipped: a load under a branch waits on its own
+                hh[u] = hit_idx[ps + min(lane + 64 * u, len - 1)];
+#pragma unroll
+            for (int u = 0; u < kPer; ++u)
+                if (lane + 64 * u < len) ib[lane + 64 * u] = hh[u];
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            const int qa = max(q0, ps) - ps, qb = min(q1, ps + len) - ps;
+#pragma unroll 1
+            for (int q = qa; q < qb; ++q) {
+                const float2 v = xy[ib[q]];
+                m.add(v.x, v.y);
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();  // every lane is done with the piece before it is overwritten
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
+        if (valid) fit_store(out_base + ((size_t)e * cap_peaks + p) * 4, q0, q1, cap_pairs, m);
     }
-    // normal matrix [[sxx, sxy, sx], [sxy, syy, sy], [sx, sy, N]], right-hand side -(sxz, syz, sz)
-    const double m_yy = syy * N - sy * sy;  // cofactors shared by the determinants
-    const double m_xy = sxy * N - sy * sx;
-    const double m_c = sxy * sy - syy * sx;
-    const double det = sxx * m_yy - sxy * m_xy + sx * m_c;
-    o[3] = N;
-    if (N < 3.0 || det == 0.0) {
-        o[0] = 0.0;
-        o[1] = 0.0;
-        o[2] = -1.0;
-        return;
-    }
-    const double r0 = -sxz, r1 = -syz, r2 = -sz;
-    const double a = (r0 * m_yy - sxy * (r1 * N - sy * r2) + sx * (r1 * sy - syy * r2)) / det;
-    const double b = (sxx * (r1 * N - r2 * sy) - r0 * m_xy + sx * (sxy * r2 - r1 * sx)) / det;
-    const double c = (sxx * (syy * r2 - sy * r1) - sxy * (sxy * r2 - r1 * sx) + r0 * m_c) / det;
-    const double xc = -a / 2.0, yc = -b / 2.0;
-    o[0] = xc;
-    o[1] = yc;
-    o[2] = xc * xc + yc * yc - c;
 }
 
 // ------------------------------------------------------------------ zvote
@@ -2165,9 +2240,21 @@ void launch_assign(const hough_plan* p, const Events& ev, int n_events, const ho
                            p->g.n_qpt, p->M, p->F, ws, O, offsets, hit_idx, cap_pairs, lds_words, cells_words);
 }
 
-void launch_fit(const Events& ev, int n_events, const float* x, const float* y, const int32_t* offsets,
+void launch_fit(const Events& ev, int n_events, int n_cu, const float* x, const float* y, const int32_t* offsets,
                 const int32_t* hit_idx, int32_t cap_peaks, int32_t cap_pairs, const hough_status_t* st, double* out,
                 hipStream_t stream) {
+    const int max_hits = ev.hit_off ? ev.max_hits : ev.n_single;
+    if (max_hits <= kFitResHits) {  // coordinates resident in LDS
+        const int res = (max_hits + 1) & ~1;
+        const int64_t chunks = ((int64_t)cap_peaks + kFitResThreads - 1) / kFitResThreads;
+        int64_t per_event = (2 * (int64_t)n_cu + n_events - 1) / n_events;
+        per_event = per_event < chunks ? per_event : chunks;
+        const dim3 grid((unsigned)(per_event > 0 ? per_event : 1), n_events);
+        const size_t lds = (size_t)res * 8 + kFitResIdxBytes;
+        hipLaunchKernelGGL(k_fit_res, grid, dim3(kFitResThreads), lds, stream, ev, x, y, offsets, hit_idx, cap_peaks,
+                           cap_pairs, st, out, res);
+        return;
+    }
     const dim3 grid((unsigned)(((int64_t)cap_peaks + kFitThreads - 1) / kFitThreads), n_events);
     hipLaunchKernelGGL(k_fit, grid, dim3(kFitThreads), 0, stream, ev, x, y, offsets, hit_idx, cap_peaks, cap_pairs,
                        st, out);
@@ -2655,6 +2742,8 @@ int hough_plan_create(const hough_geometry_t* geom, const hough_grid_t* grid, ho
                                  kLdsBytes - 1024);
     if (ae == hipSuccess)
         ae = hipFuncSetAttribute((const void*)k_zvote, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
+    if (ae == hipSuccess)
+        ae = hipFuncSetAttribute((const void*)k_fit_res, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
     if (ae != hipSuccess) {
         (void)hipFree(p->d_E);
         (void)hipFree(p->d_zero);
@@ -2787,7 +2876,7 @@ int hough_fit(const hough_plan_t* p, const hough_hits_t* hits, const int32_t* of
     if (!p || !hits || !offsets || !hit_idx || !st || !out || cap_peaks < 1 || cap_pairs < 1) return HOUGH_E_INVAL;
     if (hits->n < 0 || hits->n > p->g.max_hits_per_event) return HOUGH_E_INVAL;
     if (hits->n > 0 && (!hits->x || !hits->y)) return HOUGH_E_INVAL;
-    launch_fit(single_event(p, hits->n), 1, hits->x, hits->y, offsets, hit_idx, cap_peaks, cap_pairs, st, out,
+    launch_fit(single_event(p, hits->n), 1, p->n_cu, hits->x, hits->y, offsets, hit_idx, cap_peaks, cap_pairs, st, out,
                stream);
     return launch_status();
 }

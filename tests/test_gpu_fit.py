@@ -76,12 +76,14 @@ def test_fit_cut_lists_marked(H, oracle_mod):
     np.testing.assert_array_equal(cut["fit"][~complete, 3], np.diff(offs)[~complete].astype(np.float64))
 
 
-def test_fit_hand_made_lists(H, oracle_mod):
+@pytest.mark.parametrize("n_hits", [400, 20000])
+def test_fit_hand_made_lists(H, oracle_mod, n_hits):
     """Lists given directly to hough_fit: empty, two hits, collinear hits, integer points on a
-    circle, and ordinary ones; the number of candidates comes from the status on the device."""
+    circle, and ordinary ones; the number of candidates comes from the status on the device.
+    400 hits: the coordinates are copied into LDS; 20000 hits: more than fit there, so they are
+    gathered from memory."""
     O = oracle_mod
     rng = np.random.default_rng(9)
-    n_hits = 400
     x = rng.uniform(-80, 80, n_hits).astype(np.float32)
     y = rng.uniform(-80, 80, n_hits).astype(np.float32)
     x[:5] = [13, 14, 15, 10, 7]  # on the circle of centre (10, -7), radius 5
