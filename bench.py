@@ -146,7 +146,8 @@ def bench_large_grid(H, torch, reps: int):
     """The large-grid workload: 64 events of 600 prompt tracks plus two displaced vertices, 20 %
     noise, with z, on a 1024x512x128 int16 grid, batched, followed by the second-stage
     cot(theta) x z0 (128 x 128) vote of every candidate.  The r-z stage's share is the
-    difference between the chain with and without it."""
+    difference between the chain with and without it.  The vertex transform of all events'
+    candidates (batched vote and peaks) is timed on its own."""
     from paper_1305_4855_amd import configs, synth
 
     cfg = configs.C4
@@ -167,6 +168,22 @@ def bench_large_grid(H, torch, reps: int):
         b.record(stream)
         torch.cuda.synchronize()
         times[with_z] = a.elapsed_time(b) / reps
+    # the second transform (vertex space) of every event's candidates, batched
+    vp = H.VertexPlan.of(plan)
+    vb = H.VertexBatchBuffers(vp, len(events), 1 << 21, 1 << 16)
+    vb.run(bufs.peaks, bufs.status, cfg.v_threshold, stream)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    for _ in range(reps):
+        vb.run(bufs.peaks, bufs.status, cfg.v_threshold, stream)
+    b.record(stream)
+    torch.cuda.synchronize()
+    vertex_ms = a.elapsed_time(b) / reps
+    stv = vb.status.cpu().numpy()
+    vertex_votes = int(stv.view("int64")[:, 1].sum())
+    vertex_cands = int(stv[:, 4].sum())
+    del vb
     st = bufs.status.cpu().numpy()
     votes = int(st.view("int64")[:, 1].sum())
     cands = int(st[:, 4].sum())
@@ -182,6 +199,9 @@ def bench_large_grid(H, torch, reps: int):
         "events_per_s": round(len(events) / times[True] * 1e3, 2),
         "events_per_s_without_zvote": round(len(events) / times[False] * 1e3, 2),
         "zvote_ms_per_event": round(zv_ms / len(events), 4),
+        "vertex_ms_per_batch": round(vertex_ms, 3), "vertex_ms_per_event": round(vertex_ms / len(events), 4),
+        "vertex_votes": vertex_votes, "vertex_candidates": vertex_cands,
+        "vertex_gvotes_per_s": round(vertex_votes / (vertex_ms * 1e-3) / 1e9, 1),
     }
 
 

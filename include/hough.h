@@ -289,6 +289,18 @@ int hough_vertex_vote(const hough_vertex_plan_t* vplan, const hough_peak_t* peak
 int hough_vertex_peaks(const hough_vertex_plan_t* vplan, const int32_t* acc_v, int32_t threshold,
                        hough_peak_t* vpeaks, int32_t cap, void* ws, size_t ws_bytes, hough_status_t* st_v,
                        hipStream_t stream);
+/* The same for n_events events at once (1..65535): candidate lists at peaks +
+ * e * cap_peaks with statuses st[e] (as hough_run_batch writes them), vertex
+ * spaces at acc_v + e * n_vr * n_vphi, statuses st_v[e]; vertex candidates at
+ * vpeaks + e * cap.  Results equal the single-event calls per event. */
+size_t hough_vertex_batch_vote_ws_bytes(const hough_vertex_plan_t* vplan, int32_t n_events, int32_t cap_peaks);
+size_t hough_vertex_batch_peaks_ws_bytes(const hough_vertex_plan_t* vplan, int32_t n_events, int32_t cap_vpeaks);
+int hough_vertex_vote_batch(const hough_vertex_plan_t* vplan, int32_t n_events, const hough_peak_t* peaks,
+                            int32_t cap_peaks, const hough_status_t* st, int32_t* acc_v, void* ws, size_t ws_bytes,
+                            hough_status_t* st_v, hipStream_t stream);
+int hough_vertex_peaks_batch(const hough_vertex_plan_t* vplan, int32_t n_events, const int32_t* acc_v,
+                             int32_t threshold, hough_peak_t* vpeaks, int32_t cap, void* ws, size_t ws_bytes,
+                             hough_status_t* st_v, hipStream_t stream);
 /* Copy T to host memory `out` (n_d0 * n_qpt * n_vr entries).  Synchronous; for tests. */
 int hough_vertex_table(const hough_vertex_plan_t* vplan, int32_t* out);
 

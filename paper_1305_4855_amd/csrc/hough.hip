@@ -2305,13 +2305,17 @@ __device__ __forceinline__ void vertex_ranges(const hough_status_t* st, int32_t 
     active = chunk > 0 ? (n + chunk - 1) / chunk : 0;
 }
 
-__global__ __launch_bounds__(kVvoteThreads) void k_vvote(const hough_peak_t* __restrict__ peaks, int32_t cap,
-                                                         const hough_status_t* __restrict__ st,
+__global__ __launch_bounds__(kVvoteThreads) void k_vvote(const hough_peak_t* __restrict__ peaks_base, int32_t cap,
+                                                         const hough_status_t* __restrict__ st_base,
                                                          const int32_t* __restrict__ T, VGrid vg,
-                                                         uint32_t* __restrict__ partial,
-                                                         hough_status_t* __restrict__ st_v) {
+                                                         uint32_t* __restrict__ partial_base, size_t partial_stride,
+                                                         hough_status_t* __restrict__ st_v_base) {
     extern __shared__ uint32_t slab[];
-    const int g = blockIdx.x, s = blockIdx.y, tid = threadIdx.x;
+    const int g = blockIdx.x, s = blockIdx.y, e = blockIdx.z, tid = threadIdx.x;
+    const hough_peak_t* peaks = peaks_base + (size_t)e * cap;
+    const hough_status_t* st = st_base + e;
+    uint32_t* partial = partial_base + (size_t)e * partial_stride;
+    hough_status_t* st_v = st_v_base + e;
     int n, chunk, active;
     vertex_ranges(st, cap, vg.groups, n, chunk, active);
     if (g == 0 && s == 0 && tid == 0) {
@@ -2411,11 +2415,16 @@ __global__ __launch_bounds__(kVvoteThreads) void k_vvote(const hough_peak_t* __r
 
 // One workgroup per 64 dwords of the slab layout (all rows' partials of 32 rows x 2 bins); wave w
 // adds ranges w, w + 16, ...; the sums are combined in LDS and split into the two rows of a dword.
-__global__ __launch_bounds__(kVreduceThreads) void k_vreduce(const hough_status_t* __restrict__ st, int32_t cap,
-                                                             VGrid vg, const uint32_t* __restrict__ partial,
-                                                             int32_t* __restrict__ acc_v,
-                                                             hough_status_t* __restrict__ st_v) {
+__global__ __launch_bounds__(kVreduceThreads) void k_vreduce(const hough_status_t* __restrict__ st_base, int32_t cap,
+                                                             VGrid vg, const uint32_t* __restrict__ partial_base,
+                                                             size_t partial_stride, int32_t* __restrict__ acc_v_base,
+                                                             hough_status_t* __restrict__ st_v_base) {
     __shared__ uint32_t lo_s[kVreduceThreads / 64][64], hi_s[kVreduceThreads / 64][64];
+    const int e = blockIdx.y;
+    const hough_status_t* st = st_base + e;
+    const uint32_t* partial = partial_base + (size_t)e * partial_stride;
+    int32_t* acc_v = acc_v_base + (size_t)e * vg.n_vr * vg.n_vphi;
+    hough_status_t* st_v = st_v_base + e;
     int n, chunk, active;
     vertex_ranges(st, cap, vg.groups, n, chunk, active);
     const int words = vg.n_vphi * 32;
@@ -2457,13 +2466,18 @@ __global__ __launch_bounds__(kVreduceThreads) void k_vreduce(const hough_status_
     }
 }
 
-void launch_vertex_vote(const VGrid& vg, int slabs, const hough_peak_t* peaks, int32_t cap, const hough_status_t* st,
-                        const int32_t* T, uint32_t* partial, int32_t* acc_v, hough_status_t* st_v, hipStream_t stream) {
+// n_events events: candidate lists at peaks + e * cap, statuses st[e] and st_v[e], vertex spaces at
+// acc_v + e * n_vr * n_vphi, partials at partial + e * (slabs * groups * n_vphi * 32) words.
+void launch_vertex_vote(const VGrid& vg, int slabs, int n_events, const hough_peak_t* peaks, int32_t cap,
+                        const hough_status_t* st, const int32_t* T, uint32_t* partial, int32_t* acc_v,
+                        hough_status_t* st_v, hipStream_t stream) {
     const size_t lds = (size_t)vg.n_vphi * 128;
-    hipLaunchKernelGGL(k_vvote, dim3((unsigned)vg.groups, (unsigned)slabs), dim3(kVvoteThreads), lds, stream, peaks,
-                       cap, st, T, vg, partial, st_v);
+    const size_t pstride = (size_t)slabs * vg.groups * vg.n_vphi * 32;
+    hipLaunchKernelGGL(k_vvote, dim3((unsigned)vg.groups, (unsigned)slabs, (unsigned)n_events), dim3(kVvoteThreads),
+                       lds, stream, peaks, cap, st, T, vg, partial, pstride, st_v);
     const unsigned rblocks = (unsigned)((int64_t)slabs * vg.n_vphi * 32 / 64);
-    hipLaunchKernelGGL(k_vreduce, dim3(rblocks), dim3(kVreduceThreads), 0, stream, st, cap, vg, partial, acc_v, st_v);
+    hipLaunchKernelGGL(k_vreduce, dim3(rblocks, (unsigned)n_events), dim3(kVreduceThreads), 0, stream, st, cap, vg,
+                       partial, pstride, acc_v, st_v);
 }
 
 int check_hits(const hough_plan* p, const hough_hits_t* hits) {
@@ -2488,16 +2502,19 @@ struct hough_vertex_plan {
 };
 
 namespace {
-int vertex_groups(const hough_vertex_plan* vp, int32_t cap) {
+// Candidate ranges per event: the plan's count spread over the events of a launch, and at least
+// enough that no range holds more than kVertexMaxRange candidates.
+int vertex_groups(const hough_vertex_plan* vp, int32_t cap, int32_t n_events = 1) {
     const int64_t need = ((int64_t)cap + kVertexMaxRange - 1) / kVertexMaxRange;
-    return (int)(need > vp->groups ? need : vp->groups);
+    const int64_t spread = ((int64_t)vp->groups + n_events - 1) / n_events;
+    return (int)(need > spread ? need : spread);
 }
 
-size_t vertex_partial_bytes(const hough_vertex_plan* vp, int32_t cap) {
-    return (size_t)vp->slabs * vertex_groups(vp, cap) * vp->vg.n_vphi * 128;
+size_t vertex_partial_bytes(const hough_vertex_plan* vp, int32_t cap, int32_t n_events = 1) {
+    return (size_t)n_events * vp->slabs * vertex_groups(vp, cap, n_events) * vp->vg.n_vphi * 128;
 }
 
-VGrid vertex_vgrid(const hough_vertex_plan* vp, int32_t cap) {
+VGrid vertex_vgrid(const hough_vertex_plan* vp, int32_t cap, int32_t n_events = 1) {
     const hough_plan* p = vp->first;
     VGrid v{};
     v.n_d0 = p->g.n_d0;
@@ -2507,7 +2524,7 @@ VGrid vertex_vgrid(const hough_vertex_plan* vp, int32_t cap) {
     v.n_vphi = vp->vg.n_vphi;
     v.F = p->F;
     v.min_votes = vp->vg.min_votes;
-    v.groups = vertex_groups(vp, cap);
+    v.groups = vertex_groups(vp, cap, n_events);
     v.mask_m = p->M >= 32 ? 0xFFFFFFFFu : ((1u << p->M) - 1u);
     v.shift = p->M - ilog2_exact(vp->vg.n_vphi);
     return v;
@@ -3091,8 +3108,42 @@ int hough_vertex_vote(const hough_vertex_plan_t* vp, const hough_peak_t* peaks, 
                       hipStream_t stream) {
     if (!vp || !peaks || !st || !acc_v || !ws || !st_v || cap_peaks < 1) return HOUGH_E_INVAL;
     if (ws_bytes < vertex_partial_bytes(vp, cap_peaks)) return HOUGH_E_SMALL_WS;
-    launch_vertex_vote(vertex_vgrid(vp, cap_peaks), vp->slabs, peaks, cap_peaks, st, vp->d_T,
+    launch_vertex_vote(vertex_vgrid(vp, cap_peaks), vp->slabs, 1, peaks, cap_peaks, st, vp->d_T,
                        static_cast<uint32_t*>(ws), acc_v, st_v, stream);
+    return launch_status();
+}
+
+size_t hough_vertex_batch_vote_ws_bytes(const hough_vertex_plan_t* vp, int32_t n_events, int32_t cap_peaks) {
+    if (!vp || n_events < 1 || cap_peaks < 1) return 0;
+    return vertex_partial_bytes(vp, cap_peaks, n_events);
+}
+
+size_t hough_vertex_batch_peaks_ws_bytes(const hough_vertex_plan_t* vp, int32_t n_events, int32_t cap_vpeaks) {
+    if (!vp || n_events < 1 || cap_vpeaks < 1) return 0;
+    return (size_t)n_events * ws_layout(vp->grid, cap_vpeaks).total;
+}
+
+int hough_vertex_vote_batch(const hough_vertex_plan_t* vp, int32_t n_events, const hough_peak_t* peaks,
+                            int32_t cap_peaks, const hough_status_t* st, int32_t* acc_v, void* ws, size_t ws_bytes,
+                            hough_status_t* st_v, hipStream_t stream) {
+    if (!vp || !peaks || !st || !acc_v || !ws || !st_v || cap_peaks < 1 || n_events < 1 || n_events > 65535)
+        return HOUGH_E_INVAL;
+    if (ws_bytes < vertex_partial_bytes(vp, cap_peaks, n_events)) return HOUGH_E_SMALL_WS;
+    launch_vertex_vote(vertex_vgrid(vp, cap_peaks, n_events), vp->slabs, n_events, peaks, cap_peaks, st, vp->d_T,
+                       static_cast<uint32_t*>(ws), acc_v, st_v, stream);
+    return launch_status();
+}
+
+int hough_vertex_peaks_batch(const hough_vertex_plan_t* vp, int32_t n_events, const int32_t* acc_v,
+                             int32_t threshold, hough_peak_t* vpeaks, int32_t cap, void* ws, size_t ws_bytes,
+                             hough_status_t* st_v, hipStream_t stream) {
+    if (!vp || !acc_v || !vpeaks || !ws || !st_v || cap < 1 || threshold < 1 || n_events < 1 || n_events > 65535)
+        return HOUGH_E_INVAL;
+    const WsLayout L = ws_layout(vp->grid, cap);
+    if (ws_bytes < (size_t)n_events * L.total) return HOUGH_E_SMALL_WS;
+    const Events ev{nullptr, 0, 1, L.total};
+    launch_peaks(vp->grid, ev, n_events, acc_v, (size_t)vp->vg.n_vr * vp->vg.n_vphi * 4, threshold, vpeaks, cap,
+                 static_cast<char*>(ws), ws_off(L), st_v, stream);
     return launch_status();
 }
 

@@ -101,6 +101,14 @@ def _load() -> C.CDLL:
     L.hough_vertex_peaks.restype = C.c_int
     L.hough_vertex_peaks.argtypes = [P, P, C.c_int32, P, C.c_int32, P, S, P, P]
     L.hough_vertex_table.restype = C.c_int; L.hough_vertex_table.argtypes = [P, P]
+    L.hough_vertex_batch_vote_ws_bytes.restype = S
+    L.hough_vertex_batch_vote_ws_bytes.argtypes = [P, C.c_int32, C.c_int32]
+    L.hough_vertex_batch_peaks_ws_bytes.restype = S
+    L.hough_vertex_batch_peaks_ws_bytes.argtypes = [P, C.c_int32, C.c_int32]
+    L.hough_vertex_vote_batch.restype = C.c_int
+    L.hough_vertex_vote_batch.argtypes = [P, C.c_int32, P, C.c_int32, P, P, P, S, P, P]
+    L.hough_vertex_peaks_batch.restype = C.c_int
+    L.hough_vertex_peaks_batch.argtypes = [P, C.c_int32, P, C.c_int32, P, C.c_int32, P, S, P, P]
     L.hough_plan_set_tuning.restype = C.c_int; L.hough_plan_set_tuning.argtypes = [P, C.POINTER(Tuning)]
     L.hough_plan_get_tuning.restype = C.c_int; L.hough_plan_get_tuning.argtypes = [P, C.POINTER(Tuning)]
     L.hough_plan_set_vote_events.restype = C.c_int; L.hough_plan_set_vote_events.argtypes = [P, P, P]
@@ -121,7 +129,8 @@ EXPORTED = ["hough_plan_create", "hough_plan_destroy", "hough_acc_bytes", "hough
             "hough_batch_ws_bytes", "hough_run_batch", "hough_batch_graph_create", "hough_graph_launch",
             "hough_graph_destroy", "hough_vertex_plan_create", "hough_vertex_plan_destroy", "hough_vertex_set_groups",
             "hough_vertex_get_groups", "hough_vertex_vote_ws_bytes", "hough_vertex_peaks_ws_bytes",
-            "hough_vertex_vote", "hough_vertex_peaks", "hough_vertex_table"]
+            "hough_vertex_vote", "hough_vertex_peaks", "hough_vertex_table", "hough_vertex_batch_vote_ws_bytes",
+            "hough_vertex_batch_peaks_ws_bytes", "hough_vertex_vote_batch", "hough_vertex_peaks_batch"]
 
 
 def _check(rc: int, what: str) -> None:
@@ -378,6 +387,39 @@ class VertexBuffers:
         st = status_dict(self.status)
         n = min(st["n_peaks"], self.peaks.shape[0])
         return dict(status=st, acc=self.acc.cpu().numpy(), peaks=self.peaks[:n].cpu().numpy())
+
+
+class VertexBatchBuffers:
+    """Device buffers of the second transform for a batch: per-event vertex spaces, statuses and
+    vertex-candidate lists, and the two workspaces."""
+
+    def __init__(self, vp: VertexPlan, n_events: int, cap_peaks: int, cap_vpeaks: int, device="cuda"):
+        self.vp, self.n_events, self.cap_peaks = vp, int(n_events), int(cap_peaks)
+        self.acc = torch.empty((n_events, vp.n_vr, vp.n_vphi), dtype=torch.int32, device=device)
+        self.ws_vote = torch.empty(int(lib.hough_vertex_batch_vote_ws_bytes(vp.handle, n_events, cap_peaks)),
+                                   dtype=torch.uint8, device=device)
+        self.ws_peaks = torch.empty(int(lib.hough_vertex_batch_peaks_ws_bytes(vp.handle, n_events, cap_vpeaks)),
+                                    dtype=torch.uint8, device=device)
+        self.status = torch.zeros((n_events, STATUS_BYTES // 4), dtype=torch.int32, device=device)
+        self.peaks = torch.empty((n_events, cap_vpeaks, PEAK_INTS), dtype=torch.int32, device=device)
+
+    def run(self, pk: torch.Tensor, status: torch.Tensor, threshold: int, stream=None) -> None:
+        """pk: [n_events * cap_peaks][4] (or [n_events][cap_peaks][4]) candidate lists; status: the
+        per-event statuses of the first stage."""
+        if pk.numel() != self.n_events * self.cap_peaks * 4:
+            raise HoughError("pk needs n_events * cap_peaks rows")
+        _check(lib.hough_vertex_vote_batch(self.vp.handle, self.n_events, _ptr(pk), self.cap_peaks, _ptr(status),
+                                           _ptr(self.acc), _ptr(self.ws_vote), int(self.ws_vote.numel()),
+                                           _ptr(self.status), _stream(stream)), "hough_vertex_vote_batch")
+        _check(lib.hough_vertex_peaks_batch(self.vp.handle, self.n_events, _ptr(self.acc), int(threshold),
+                                            _ptr(self.peaks), int(self.peaks.shape[1]), _ptr(self.ws_peaks),
+                                            int(self.ws_peaks.numel()), _ptr(self.status), _stream(stream)),
+               "hough_vertex_peaks_batch")
+
+    def results(self, e: int) -> dict:
+        st = status_dict(self.status[e])
+        n = min(st["n_peaks"], self.peaks.shape[1])
+        return dict(status=st, acc=self.acc[e].cpu().numpy(), peaks=self.peaks[e, :n].cpu().numpy())
 
 
 def status_dict(status: torch.Tensor) -> dict:

@@ -173,3 +173,53 @@ def test_vertex_after_gpu_chain_finds_llp_vertices(H, oracle_mod):
     bv = int((np.arctan2(v[1], v[0]) / (2 * np.pi)) % 1.0 * cfg.n_vphi)
     top = res["peaks"][np.argmax(res["peaks"][:, 3])]
     assert abs(int(top[1]) - jv) <= 1 and min((int(top[2]) - bv) % cfg.n_vphi, (bv - int(top[2])) % cfg.n_vphi) <= 1
+
+
+def test_vertex_batch_equals_oracle(H, oracle_mod):
+    """Several events at once (hough_vertex_vote_batch / hough_vertex_peaks_batch): uneven
+    candidate counts, an event with no candidates and one whose count exceeds the capacity;
+    every event equals the oracle's vertex space and vertex candidates."""
+    O = oracle_mod
+    cfg = configs.small_variant(configs.C4, n_phi=256, n_qpt=64, n_d0=8).with_(n_vr=128, n_vphi=64, v_threshold=3)
+    lists = [synth.make_candidates(cfg, n, seed=20 + i) for i, n in enumerate((3000, 0, 800, 5000, 40))]
+    cap = 4000
+    n_ev = len(lists)
+    plan = H.Plan(cfg, max_hits=1024)
+    vp = H.VertexPlan.of(plan)
+    vg = O.VertexGrid.of(cfg)
+    pk = torch.zeros((n_ev, cap, 4), dtype=torch.int32, device="cuda")
+    st = torch.zeros((n_ev, H.STATUS_BYTES // 4), dtype=torch.int32, device="cuda")
+    for e, l in enumerate(lists):
+        m = min(len(l), cap)
+        if m:
+            pk[e, :m] = torch.from_numpy(l[:m]).cuda()
+        st[e, 4] = len(l)
+    vb = H.VertexBatchBuffers(vp, n_ev, cap, 1 << 12)
+    vb.acc.fill_(-5)
+    vb.run(pk, st, cfg.v_threshold)
+    torch.cuda.synchronize()
+    for e, l in enumerate(lists):
+        print(f"[vertex batch] event {e} candidates {len(l)}", flush=True)
+        _check(vb.results(e), _oracle_vertex(O, cfg, vg, l[:cap], cfg.v_threshold), min(len(l), cap))
+
+
+def test_vertex_batch_after_gpu_batch_chain(H, oracle_mod):
+    """The batched first stage's device candidate lists and statuses feed the batched vertex stage
+    directly; each event equals the oracle's chain."""
+    O = oracle_mod
+    cfg = configs.small_variant(configs.C4, n_tracks=25, n_phi=256, n_qpt=64, n_d0=8).with_(
+        n_vr=64, n_vphi=128, v_threshold=3)
+    events = [synth.make_event(cfg, i) for i in range(3)]
+    plan = H.Plan(cfg, max_hits=1024)
+    bufs = H.BatchBuffers(plan, len(events), sum(e.n for e in events), cap_peaks=1 << 13, cap_pairs=1 << 16)
+    bufs.load(events)
+    bufs.run(cfg.threshold, zvote=False)
+    vp = H.VertexPlan.of(plan)
+    vb = H.VertexBatchBuffers(vp, len(events), 1 << 13, 1 << 12)
+    vb.run(bufs.peaks, bufs.status, cfg.v_threshold)
+    torch.cuda.synchronize()
+    g = O.Cfg(cfg)
+    vg = O.VertexGrid.of(cfg)
+    for e, ev in enumerate(events):
+        n, pk = O.peaks(g, O.vote(g, ev)[0], cfg.threshold)
+        _check(vb.results(e), _oracle_vertex(O, cfg, vg, pk, cfg.v_threshold), n)
