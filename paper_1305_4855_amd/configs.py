@@ -63,6 +63,7 @@ class HoughConfig:
     displaced_frac: float = 0.1
     displaced_d0_max: float = 10.0
     smear_rphi_cm: float = 20e-4
+    smear_xy_cm: float = 0.0        # Gaussian smear of x and y each (the paper's own detector model)
     smear_z_cm: float = 50e-4
     with_z: bool = False
     n_llp_vertices: int = 0
@@ -115,7 +116,27 @@ C5 = HoughConfig(
     track_dist="gamma_poisson", track_mean=500.0, noise_frac=0.2, displaced_frac=0.05,
     rate_hz=20000.0, duration_s=60.0, hbm_budget_bytes=64 << 30)
 
-CONFIGS = {c.cfg_id: c for c in (C1, C2, C3, C4, C5)}
+# The paper's own detector model (Sec. "Preliminary Results", detector paragraph): a 3.0 cm beam pipe
+# and ten concentric, evenly spaced layers, the last at 110.0 cm (read as 11, 22, ..., 110 cm), hit
+# resolution 0.4 mm in x and in y.
+PAPER_RADII_CM: Tuple[float, ...] = tuple(11.0 * (i + 1) for i in range(10))
+
+# Fig. "hough": 50 straight-line tracks with 10 hits each (B = 0; lines with |d0| up to the beam pipe
+# radius).  Straight lines have no curvature, so every q/pT row of the grid is the same line space.
+C6 = HoughConfig(
+    name="c6_paper_straight_lines", cfg_id=6, radii_cm=PAPER_RADII_CM, halflen_cm=(110.0,) * 10, B_tesla=0.0,
+    n_phi=256, n_qpt=64, n_d0=64, d0_min=-4.0, d0_max=4.0, threshold=8, n_tracks=50, noise_frac=0.0,
+    displaced_frac=1.0, displaced_d0_max=3.0, smear_rphi_cm=0.0, smear_xy_cm=0.04)
+
+# The curved-track example (Sec. "Preliminary Results", curved-track paragraph): prompt tracks, the
+# two-parameter phi0 x q/pT space, on the paper's detector; track count varied for the efficiency
+# and purity against the number of tracks.
+C7 = HoughConfig(
+    name="c7_paper_curved_prompt", cfg_id=7, radii_cm=PAPER_RADII_CM, halflen_cm=(110.0,) * 10, B_tesla=B_TESLA,
+    n_phi=256, n_qpt=256, n_d0=1, d0_min=0.0, d0_max=0.0, threshold=8, n_tracks=1000, noise_frac=0.0,
+    displaced_frac=0.0, smear_rphi_cm=0.0, smear_xy_cm=0.04)
+
+CONFIGS = {c.cfg_id: c for c in (C1, C2, C3, C4, C5, C6, C7)}
 
 
 def get(cfg: "int | str | HoughConfig") -> HoughConfig:

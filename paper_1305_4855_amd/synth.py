@@ -108,6 +108,8 @@ def _helix_hits(rng, cfg, q, inv_pt, phi0, d0, z0, cot, start=None, r_min=None):
     is given, tracks are followed from that point (decay vertex) and only layers
     with radius > r_min are crossed."""
     B = cfg.B_tesla
+    if B == 0.0:
+        return _line_hits(rng, cfg, phi0, d0)
     R = _radius_cm(inv_pt, B)
     nx, ny = -np.sin(phi0), np.cos(phi0)
     px, py = d0 * nx, d0 * ny
@@ -123,6 +125,9 @@ def _helix_hits(rng, cfg, q, inv_pt, phi0, d0, z0, cot, start=None, r_min=None):
         ok &= np.asarray(cfg.radii_cm)[None, :] > r_min[:, None]
     T, L = X.shape
     X, Y = _smear_rphi(rng, X, Y, cfg.smear_rphi_cm)
+    if cfg.smear_xy_cm > 0.0:
+        X = X + rng.normal(0.0, cfg.smear_xy_cm, size=X.shape)
+        Y = Y + rng.normal(0.0, cfg.smear_xy_cm, size=Y.shape)
     Z = None
     if cfg.with_z:
         if start is not None:
@@ -135,6 +140,27 @@ def _helix_hits(rng, cfg, q, inv_pt, phi0, d0, z0, cot, start=None, r_min=None):
         ok &= np.abs(Z) <= np.asarray(cfg.halflen_cm)[None, :]
     lay = np.broadcast_to(np.arange(L, dtype=np.uint8)[None, :], (T, L))
     tid = np.broadcast_to(np.arange(T, dtype=np.int32)[:, None], (T, L))
+    return X[ok], Y[ok], (Z[ok] if Z is not None else None), lay[ok], tid[ok]
+
+
+def _line_hits(rng, cfg, phi0, d0):
+    """Hits of straight lines (no field): the line through the PCA d0 * (-sin phi0, cos phi0) with
+    direction phi0 meets each layer it reaches once on its way out; smeared in x and y."""
+    r = np.asarray(cfg.radii_cm, dtype=np.float64)[None, :]
+    d = d0[:, None]
+    ok = r > np.abs(d)
+    t = np.sqrt(np.where(ok, r * r - d * d, 0.0))
+    X = -d * np.sin(phi0)[:, None] + t * np.cos(phi0)[:, None]
+    Y = d * np.cos(phi0)[:, None] + t * np.sin(phi0)[:, None]
+    if cfg.smear_xy_cm > 0.0:
+        X = X + rng.normal(0.0, cfg.smear_xy_cm, size=X.shape)
+        Y = Y + rng.normal(0.0, cfg.smear_xy_cm, size=Y.shape)
+    T, L = X.shape
+    lay = np.broadcast_to(np.arange(L, dtype=np.uint8)[None, :], (T, L))
+    tid = np.broadcast_to(np.arange(T, dtype=np.int32)[:, None], (T, L))
+    Z = None
+    if cfg.with_z:
+        Z = np.zeros_like(X)
     return X[ok], Y[ok], (Z[ok] if Z is not None else None), lay[ok], tid[ok]
 
 

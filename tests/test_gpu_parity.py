@@ -121,6 +121,15 @@ def test_c2_family_small_full_parity(H, oracle_mod, shape, tracks, eid, frac):
     check_full(H, oracle_mod, cfg, synth.make_event(cfg, eid))
 
 
+@pytest.mark.parametrize("cfg,tracks", [(configs.C6, 50), (configs.C7, 300)])
+def test_paper_detector_full_parity(H, oracle_mod, cfg, tracks):
+    """The paper's own detector (layers at 11..110 cm, 0.4 mm x/y smear): the 50 straight lines of
+    its first figure (B = 0: every q/pT row holds the same line space) and curved prompt tracks in
+    the two-parameter space."""
+    cfg = cfg.with_(n_tracks=tracks)
+    check_full(H, oracle_mod, cfg, synth.make_event(cfg, 0))
+
+
 def test_c4_family_int16_small_full_parity(H, oracle_mod):
     cfg = configs.small_variant(configs.C4, n_tracks=60, n_phi=1024, n_qpt=64, n_d0=6)
     ev = synth.make_event(cfg, 0)
