@@ -223,3 +223,23 @@ def test_vertex_batch_after_gpu_batch_chain(H, oracle_mod):
     for e, ev in enumerate(events):
         n, pk = O.peaks(g, O.vote(g, ev)[0], cfg.threshold)
         _check(vb.results(e), _oracle_vertex(O, cfg, vg, pk, cfg.v_threshold), n)
+
+
+def test_vertex_plan_rejects_unsupported_grids(H):
+    """Vertex grids outside the stated limits are refused at plan time, with the documented code."""
+    cfg = configs.small_variant(configs.C4, n_phi=256, n_qpt=64, n_d0=8)  # M = 8 + 7 = 15
+    plan = H.Plan(cfg, max_hits=1024)
+    bad = [((63, 64, 0.0, 32.0, 1), "unsupported"),     # rows not a multiple of 64
+           ((64, 2048, 0.0, 32.0, 1), "unsupported"),   # more than 1024 azimuth bins
+           ((64, 96, 0.0, 32.0, 1), "unsupported"),     # not a power of two
+           ((64, 8, 0.0, 32.0, 1), "unsupported"),      # fewer than 16 bins
+           ((64, 64, 5.0, 5.0, 1), "invalid"),          # empty radius range
+           ((64, 64, -1.0, 32.0, 1), "invalid"),        # negative radius
+           ((64, 64, 0.0, 32.0, 0), "invalid")]         # min_votes below 1
+    for args, what in bad:
+        with pytest.raises(H.HoughError, match=what):
+            H.VertexPlan(plan, *args)
+    vp = H.VertexPlan(plan, 128, 1024, 0.5, 40.0, 3)  # at the limits: accepted
+    assert vp.groups >= 1
+    with pytest.raises(H.HoughError, match="invalid"):
+        vp.set_groups(0)
