@@ -16,7 +16,9 @@
  *   - the hits that voted for a candidate are the input of the track fit
  *     (Sec. "Preliminary Results", fitting paragraph);
  *   - a second transform of the candidates themselves finds the vertices of
- *     displaced jets (Sec. "New Trigger Capabilities").
+ *     displaced jets (Sec. "New Trigger Capabilities");
+ *   - for the paper's own detector (x/y smear), a variant of the transform
+ *     with each hit's own radius and an integer arcsine.
  * The paper gives no parameterisation, grid, binning or tie rule.  The
  * discretisation used here is the "fixed-point transform" written out step by
  * step below (one reading of the silent points; the same reading is stated in
@@ -573,6 +575,85 @@ int64_t or_vertex_vote(const or_cfg_t* g, int32_t n_vr, int32_t n_vphi, double r
             v = (phi0 + (uint32_t)E) & mask;
             acc_v[(int64_t)j * n_vphi + (int32_t)(v >> (M - lv))]++;
             votes++;
+        }
+    }
+    return votes;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Step 11 (per-hit radius, the paper's detector with its x/y smear): the    */
+/* transform of step 4-5 with each hit's own radius instead of its layer's,  */
+/* and the arcsine taken in integers so that any two implementations agree: */
+/*   R  = floor(sqrt(X^2 + Y^2)) in Q16.16 (exact integer square root),      */
+/*        r = R / 2^16;                                                      */
+/*   A  as in step 4 (IEEE double, same operation order, same validity);     */
+/*   a  = llrint(A * 2^30) (Q2.30), b = floor(sqrt(2^60 - a^2)),             */
+/*   t  = the step-2 CORDIC angle of the vector (b, a), read as a signed      */
+/*        32-bit binary angle (= asin(A), |t| <= 2^30);                      */
+/*   E  = floor((t + 2^(31-M)) / 2^(32-M))   (round half up to M bits).      */
+/* Votes as in step 5 with this E; the layer only decides validity.         */
+/* ------------------------------------------------------------------------ */
+uint64_t or_isqrt(uint64_t v)
+{
+    /* digit-by-digit square root in base 4: exact floor(sqrt(v)) */
+    uint64_t rem = v, root = 0, bit = (uint64_t)1 << 62;
+    while (bit > rem) bit >>= 2;
+    while (bit) {
+        if (rem >= root + bit) {
+            rem -= root + bit;
+            root = (root >> 1) + bit;
+        } else {
+            root >>= 1;
+        }
+        bit >>= 2;
+    }
+    return root;
+}
+
+int or_sample_cr(double r, double c, double d, int32_t M, int32_t* E)
+{
+    double num = c * (r * r + d * d) + 2.0 * d;
+    double den = 2.0 * r * (1.0 + c * d);
+    double A;
+    int64_t a, b, t;
+    int32_t s = 32 - M;
+    if (!(den > 0.0)) return 0;
+    A = num / den;
+    if (!(fabs(A) <= 1.0)) return 0;
+    a = llrint(A * 1073741824.0);
+    b = (int64_t)or_isqrt((uint64_t)(((int64_t)1 << 60) - a * a));
+    t = (int64_t)(int32_t)or_azimuth((int32_t)b, (int32_t)a);
+    *E = (int32_t)((t + ((int64_t)1 << (s - 1))) >> s);
+    return 1;
+}
+
+double or_hit_radius(int32_t X, int32_t Y)
+{
+    uint64_t R2 = (uint64_t)((int64_t)X * X) + (uint64_t)((int64_t)Y * Y);
+    return (double)or_isqrt(R2) / 65536.0;
+}
+
+int64_t or_vote_cr(const or_cfg_t* g, int32_t n, const float* x, const float* y, const uint8_t* layer,
+                   int32_t* acc)
+{
+    int32_t M = or_angle_bits(g), F = g->frac_bits, h, l, k;
+    int64_t votes = 0;
+    memset(acc, 0, sizeof(int32_t) * (size_t)g->n_d0 * g->n_qpt * g->n_phi);
+    for (h = 0; h < n; h++) {
+        int32_t X, Y;
+        uint32_t phiM;
+        double r;
+        if (!or_hit(x[h], y[h], layer[h], g->n_layers, &X, &Y)) continue;
+        phiM = or_azimuth(X, Y) >> (32 - M);
+        r = or_hit_radius(X, Y);
+        for (l = 0; l < g->n_d0; l++) {
+            double d = or_d0_centre(g, l);
+            for (k = 0; k < g->n_qpt; k++) {
+                int32_t E;
+                if (!or_sample_cr(r, or_curvature(g, k), d, M, &E)) continue;
+                acc[((int64_t)l * g->n_qpt + k) * g->n_phi + or_bin(phiM, E, M, F)] += 1;
+                votes++;
+            }
         }
     }
     return votes;

@@ -89,6 +89,11 @@ def load(path: str) -> C.CDLL:
     L.or_zvote.argtypes = [P, C.c_int32, P, P, C.c_int32, P, P, P, P]
     L.or_fit.restype = None
     L.or_fit.argtypes = [P, P, C.c_int32, P, P, P]
+    L.or_isqrt.restype = C.c_uint64; L.or_isqrt.argtypes = [C.c_uint64]
+    L.or_sample_cr.restype = C.c_int
+    L.or_sample_cr.argtypes = [C.c_double, C.c_double, C.c_double, C.c_int32, P]
+    L.or_hit_radius.restype = C.c_double; L.or_hit_radius.argtypes = [C.c_int32, C.c_int32]
+    L.or_vote_cr.restype = C.c_int64; L.or_vote_cr.argtypes = [P, C.c_int32, P, P, P, P]
     L.or_vertex_radius.restype = C.c_double
     L.or_vertex_radius.argtypes = [C.c_int32, C.c_double, C.c_double, C.c_int32]
     L.or_vertex_vote.restype = C.c_int64
@@ -302,3 +307,26 @@ def vertex_peaks(vg: VertexGrid, acc_v: np.ndarray, thr: int, cap: int = 1 << 20
     out = np.zeros((cap, 4), dtype=np.int32)
     n = int(lib().or_peaks(C.addressof(g), _p(acc_v), int(thr), int(cap), _p(out)))
     return n, out[: min(n, cap)].copy()
+
+
+# ---------------------------------------------------------------- per-hit radius transform
+def isqrt(v: int) -> int:
+    return int(lib().or_isqrt(int(v)))
+
+
+def sample_cr(r: float, c: float, d: float, M: int):
+    E = C.c_int32()
+    ok = lib().or_sample_cr(float(r), float(c), float(d), int(M), C.addressof(E))
+    return bool(ok), E.value
+
+
+def hit_radius(X: int, Y: int) -> float:
+    return float(lib().or_hit_radius(int(X), int(Y)))
+
+
+def vote_cr(cfg: Cfg, ev):
+    """Accumulator of the transform with each hit's own radius (integer arcsine)."""
+    x, y, lay = _hits(ev)
+    acc = np.zeros((cfg.n_d0, cfg.n_qpt, cfg.n_phi), dtype=np.int32)
+    nv = lib().or_vote_cr(cfg.ptr, x.shape[0], _p(x), _p(y), _p(lay), _p(acc))
+    return acc, int(nv)

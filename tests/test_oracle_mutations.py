@@ -52,6 +52,11 @@ MUTATIONS = {
     "vertex_phi0_bin_edge": ("phi0 = ((uint32_t)b << F) + (1u << (F - 1));", "phi0 = ((uint32_t)b << F);"),
     "vertex_sign": ("v = (phi0 + (uint32_t)E) & mask;", "v = (phi0 - (uint32_t)E) & mask;"),
     "vertex_row_edge": ("return r_min + ((double)j + 0.5)", "return r_min + ((double)j + 0.0)"),
+    "cr_round_down": ("*E = (int32_t)((t + ((int64_t)1 << (s - 1))) >> s);", "*E = (int32_t)(t >> s);"),
+    "cr_isqrt_step": ("            root = (root >> 1) + bit;", "            root = (root >> 1) + bit + 1;"),
+    "cr_layer_radius": ("        r = or_hit_radius(X, Y);", "        r = g->r_cm[layer[h]];"),
+    "cr_sqrt_operand": ("b = (int64_t)or_isqrt((uint64_t)(((int64_t)1 << 60) - a * a));",
+                        "b = (int64_t)or_isqrt((uint64_t)(((int64_t)1 << 60) + a * a));"),
     "vertex_min_votes_strict": ("if (pk[4 * p + 3] < min_votes) continue;", "if (pk[4 * p + 3] <= min_votes) continue;"),
 }
 

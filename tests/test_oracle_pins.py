@@ -936,3 +936,110 @@ def test_vertex_vote_rotation_and_filter(oracle_mod):
     assert n8 == n8b and 0 < keep.shape[0] < pk.shape[0]
     empty, ne = O.vertex_vote(g, vg8, np.zeros((0, 4), np.int32))
     assert ne == 0 and not empty.any()
+
+
+# ------------------------------------------------- per-hit radius (integer arcsine) --
+def test_isqrt_exact(oracle_mod):
+    O = oracle_mod
+    rng = np.random.default_rng(61)
+    vals = [0, 1, 2, 3, 4, 15, 16, 17, (1 << 60), (1 << 60) - 1, (1 << 62) - 1, (1 << 63) + 12345,
+            (1 << 64) - 1] + [int(v) for v in rng.integers(0, 1 << 62, 2000, dtype=np.int64)]
+    vals += [s * s + o for s in (3, 1 << 20, 3037000499) for o in (-1, 0, 1)]
+    for v in vals:
+        assert O.isqrt(v) == math.isqrt(v), v
+
+
+def test_sample_cr_vs_mpmath(oracle_mod):
+    """The integer arcsine (Q2.30 argument, integer square root, CORDIC angle, rounded to M bits)
+    equals round(asin(A) * 2^(M-1) / pi) from a 40-digit evaluation except within its error bound
+    of a rounding tie; validity as in the table sample."""
+    O = oracle_mod
+    mp.mp.dps = 40
+    rng = np.random.default_rng(62)
+    M = 15
+    near = 0
+    for _ in range(3000):
+        r = float(rng.uniform(3.0, 110.0))
+        c = float(rng.uniform(-0.012, 0.012))
+        d = float(rng.uniform(-10.0, 10.0))
+        ok, E = O.sample_cr(r, c, d, M)
+        ok2, _ = O.sample(r, c, d, M)
+        assert ok == ok2
+        if not ok:
+            continue
+        num = mp.mpf(c) * (mp.mpf(r) ** 2 + mp.mpf(d) ** 2) + 2 * mp.mpf(d)
+        den = 2 * mp.mpf(r) * (1 + mp.mpf(c) * mp.mpf(d))
+        A = num / den
+        if abs(A) > mp.mpf("0.9999"):
+            continue
+        exact = mp.asin(A) * mp.mpf(2) ** (M - 1) / mp.pi
+        frac = exact - mp.floor(exact)
+        # error bound: Q2.30 rounding of A (2^-31 / sqrt(1 - A^2)) and the CORDIC angle (2^-29 rad)
+        bound = (mp.mpf(2) ** -31 / mp.sqrt(1 - A * A) + mp.mpf(2) ** -29) * mp.mpf(2) ** (M - 1) / mp.pi
+        if abs(frac - mp.mpf("0.5")) <= bound + mp.mpf(2) ** -40:
+            near += 1
+            assert E in (int(mp.floor(exact)), int(mp.floor(exact)) + 1)
+        else:
+            assert E == int(mp.nint(exact)), (r, c, d, E, exact)
+    assert near < 10
+
+
+def test_hit_radius_and_cr_vote_on_layer_circles(oracle_mod):
+    """Hits on their layer's circle (no smear): each hit's integer radius is its layer radius to
+    2^-16 cm, and the per-hit-radius vote equals the layer-table vote except where a sample sits
+    within rounding of a bin edge; both conserve votes."""
+    O = oracle_mod
+    cfg = configs.C7.with_(n_phi=128, n_qpt=64, smear_xy_cm=0.0, n_tracks=12)
+    ev = synth.make_event(cfg, 2)
+    g = O.Cfg(cfg)
+    for h in range(0, ev.n, 7):
+        ok, X, Y = O.hit(float(ev.x[h]), float(ev.y[h]), int(ev.layer[h]), cfg.n_layers)
+        assert ok
+        r = O.hit_radius(X, Y)
+        assert abs(r - math.hypot(X / 65536.0, Y / 65536.0)) <= 2.0 ** -16
+        assert abs(r - cfg.radii_cm[ev.layer[h]]) < 1e-3
+    a_cr, n_cr = O.vote_cr(g, ev)
+    a_l, n_l = O.vote(g, ev)
+    assert n_cr == int(a_cr.sum()) and n_l == int(a_l.sum())
+    assert abs(n_cr - n_l) <= n_l // 1000
+    assert np.count_nonzero(a_cr != a_l) <= a_l.size // 200
+
+
+def test_cr_vote_rotation_covariance(oracle_mod):
+    """Rotating the hits by a quarter turn (exact in float: (x, y) -> (-y, x)) rolls the
+    per-hit-radius accumulator by n_phi / 4 bins."""
+    O = oracle_mod
+    cfg = configs.C6.with_(n_phi=64, n_d0=16)
+    ev = synth.make_event(cfg, 3)
+    g = O.Cfg(cfg)
+    a0, n0 = O.vote_cr(g, ev)
+    rot = synth.Event(x=(-ev.y).astype(np.float32), y=ev.x.copy(), z=None, layer=ev.layer, track_id=ev.track_id,
+                      truth=ev.truth)
+    a1, n1 = O.vote_cr(g, rot)
+    assert n0 == n1 and n0 > 0
+    np.testing.assert_array_equal(a1, np.roll(a0, cfg.n_phi // 4, axis=2))
+
+
+def test_cr_vote_uses_each_hits_radius(oracle_mod):
+    """A hit off its layer's circle votes as the table transform votes for a detector whose layer
+    lies at that hit's own radius (the same samples through the library arcsine instead of the
+    integer one): equal but for samples within rounding of a bin edge."""
+    O = oracle_mod
+    rng = np.random.default_rng(64)
+    base = configs.C7.with_(n_phi=128, n_qpt=64)
+    diff = total = 0
+    for _ in range(12):
+        rr = float(rng.uniform(5.0, 100.0))
+        ph = float(rng.uniform(0, 2 * math.pi))
+        x, y = np.float32(rr * math.cos(ph)), np.float32(rr * math.sin(ph))
+        ev = synth.Event(x=np.array([x]), y=np.array([y]), z=None, layer=np.array([3], np.uint8),
+                         track_id=np.array([0], np.int32), truth={})
+        ok, X, Y = O.hit(float(x), float(y), 3, base.n_layers)
+        radii = list(base.radii_cm)
+        radii[3] = O.hit_radius(X, Y)
+        a_cr, n_cr = O.vote_cr(O.Cfg(base), ev)
+        a_l, n_l = O.vote(O.Cfg(base.with_(radii_cm=tuple(radii))), ev)
+        assert abs(n_cr - n_l) <= 1
+        diff += int(np.count_nonzero(a_cr != a_l))
+        total += n_l
+    assert total > 500 and diff <= total // 100
