@@ -288,6 +288,55 @@ def bench_quality(H, torch):
             "runs": out}
 
 
+# VALU lane-instructions per sample of k_vote_cr (SQ_INSTS_VALU x 64 / samples, counted on the
+# kernel as built: 7.9e7 wave instructions for 1.024e7 samples), and the chip's 32-bit VALU issue
+# rate: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz.
+CR_VALU_PER_SAMPLE = 495
+VALU_PEAK_T = 256 * 4 * 16 * 2.4e9 / 1e12
+
+
+def bench_cr(H, torch, reps: int):
+    """The vote with each hit's own radius on the paper's detector (x/y smear): 4000 curved prompt
+    tracks (40 000 hits) on the 256 x 256 phi0 x q/pT grid, every sample computed (integer
+    arcsine); then the unchanged peak finder."""
+    from paper_1305_4855_amd import configs, synth
+
+    cfg = configs.C7.with_(n_tracks=4000)
+    ev = synth.make_event(cfg, 0)
+    plan = H.Plan(cfg, max_hits=ev.n)
+    acc = torch.empty((cfg.n_d0, cfg.n_qpt, cfg.n_phi), dtype=torch.int32, device="cuda")
+    st = torch.zeros(H.STATUS_BYTES // 4, dtype=torch.int32, device="cuda")
+    ws = torch.empty(plan.ws_bytes(1 << 16), dtype=torch.uint8, device="cuda")
+    pk = torch.empty((1 << 16, 4), dtype=torch.int32, device="cuda")
+    x, y, lay, _ = H.hits_to_device(ev)
+    hits = H.make_hits(x, y, lay)
+    stream = torch.cuda.current_stream()
+    H.vote_cr(plan, hits, acc, st, stream)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    for _ in range(reps):
+        H.vote_cr(plan, hits, acc, st, stream)
+    b.record(stream)
+    torch.cuda.synchronize()
+    vote_ms = a.elapsed_time(b) / reps
+    H.peaks(plan, acc, cfg.threshold, pk, ws, st, stream)
+    torch.cuda.synchronize()
+    s = H.status_dict(st)
+    samples = ev.n * cfg.n_qpt * cfg.n_d0
+    return {"workload": "paper detector (layers 11..110 cm, 0.4 mm x/y smear), 4000 curved prompt tracks, "
+                        "256x256 phi0 x q/pT, per-hit radius with integer arcsine",
+            "hits": ev.n, "samples": samples, "votes": s["n_votes"], "candidates": s["n_peaks"],
+            "vote_ms": round(vote_ms, 4), "samples_per_s": round(samples / (vote_ms * 1e-3), 1),
+            "roofline": {"kernel": "k_vote_cr", "bound": "alu",
+                         "achieved": round(samples * CR_VALU_PER_SAMPLE / (vote_ms * 1e-3) / 1e12, 3),
+                         "peak": VALU_PEAK_T, "unit": "T VALU lane-instructions/s",
+                         "frac": round(samples * CR_VALU_PER_SAMPLE / (vote_ms * 1e-3) / 1e12 / VALU_PEAK_T, 4),
+                         "traffic": None, "valu_per_sample": CR_VALU_PER_SAMPLE},
+            "note": "ALU-bound: a 30-step CORDIC, an integer square root and a double division per sample; "
+                    "VALU instructions per sample from SQ_INSTS_VALU of this kernel"}
+
+
 def bench_serving(H, torch, runs, pool_size: int = 256):
     """Streaming trigger serving: for each (rate_hz, duration_s) of `runs`, Poisson arrivals at that
     rate, event sizes as in the batched workload, admitted into device-resident slots within a
@@ -469,6 +518,7 @@ def main() -> int:
     ap.add_argument("--no-large-grid", action="store_true")
     ap.add_argument("--no-vertex", action="store_true")
     ap.add_argument("--no-quality", action="store_true")
+    ap.add_argument("--no-cr", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=60.0)
     ap.add_argument("--serve-rate", type=float, default=20000.0)
     ap.add_argument("--serve-rate-low", type=float, default=14000.0,
@@ -502,6 +552,8 @@ def main() -> int:
         out["vertex"] = bench_vertex(H, torch, reps=20)
     if not args.no_quality:
         out["quality"] = bench_quality(H, torch)
+    if not args.no_cr:
+        out["per_hit_radius"] = bench_cr(H, torch, reps=5)
     if not args.no_serving:
         torch.cuda.empty_cache()
         runs = [(args.serve_rate, args.serve_seconds)]

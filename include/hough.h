@@ -236,6 +236,23 @@ int hough_zvote(const hough_plan_t* plan, const hough_hits_t* hits, const hough_
 int hough_fit(const hough_plan_t* plan, const hough_hits_t* hits, const int32_t* offsets, const int32_t* hit_idx,
               int32_t cap_peaks, int32_t cap_pairs, const hough_status_t* st, double* out, hipStream_t stream);
 
+/* The vote with each hit's own radius instead of its layer's (a detector
+ * whose hits are smeared off the layer circles, like the paper's model with a
+ * 0.4 mm resolution in x and in y, Sec. "Preliminary Results").  Per valid hit
+ * (validity and X, Y as for hough_vote): R = floor(sqrt(X^2 + Y^2)) (Q16.16),
+ * r = R / 2^16 cm; per (l, k) the sample's A as for the table (IEEE double,
+ * same operation order and validity), its arcsine in integers: a =
+ * llrint(A * 2^30), b = floor(sqrt(2^60 - a^2)), t = the CORDIC angle of the
+ * vector (b, a) as a signed 32-bit binary angle, E = floor((t + 2^(31-M)) /
+ * 2^(32-M)); one vote into bin ((PhiM - E) mod 2^M) >> frac_bits.  acc (dev)
+ * int32, fully overwritten; st (dev): n_hits, n_bad_hits, n_votes set.  The
+ * plan's sample table is not used (the layer only decides validity).
+ * Requires acc_bits 32 (HOUGH_E_UNSUPPORTED otherwise).  ALU-bound: every
+ * sample is computed, no table.  hough_peaks applies unchanged; hough_assign
+ * (which follows the layer table) does not. */
+int hough_vote_cr(const hough_plan_t* plan, const hough_hits_t* hits, int32_t* acc, hough_status_t* st,
+                  hipStream_t stream);
+
 /* Second Hough transform over the candidates (Sec. "New Trigger Capabilities"
  * and its displaced-jet figures: tracks from one displaced vertex are maxima
  * of the first space lying on one curve, the curve of the vertex; a second

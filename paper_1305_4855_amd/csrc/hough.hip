@@ -1786,6 +1786,104 @@ __global__ __launch_bounds__(kFitResThreads) void k_fit_res(Events ev, const flo
     }
 }
 
+// ------------------------------------------------------------------ per-hit radius vote
+// The transform with each hit's own radius (a detector smeared in x and y): R = floor(sqrt(X^2 +
+// Y^2)) in Q16.16, the sample's A in IEEE double as for the table, its arcsine in integers (A as
+// Q2.30, b = floor(sqrt(2^60 - a^2)), the CORDIC angle of (b, a) as a signed 32-bit binary angle,
+// rounded half up to M bits).  One thread per (hit, kCrCols columns); every sample is computed on
+// the fly (ALU-bound: a 30-step CORDIC per sample) and voted with a global atomic.
+constexpr int kCrThreads = 256;
+constexpr int kCrCols = 16;
+
+// floor(sqrt(v)) for v < 2^63: a double estimate corrected to the exact integer (at most a step or
+// two: the estimate is within one of the root)
+__device__ __forceinline__ uint64_t isqrt_u64(uint64_t v) {
+    uint64_t s = (uint64_t)sqrt((double)v);
+    while (s * s > v) --s;
+    while ((s + 1) * (s + 1) <= v) ++s;
+    return s;
+}
+
+struct CrGrid {
+    int32_t n_layers, n_qpt, n_cols, n_phi, M, F;
+    double qpt_min, qstep, d0_min, dstep, kappa;
+};
+
+__global__ __launch_bounds__(256) void k_cr_init(int32_t* __restrict__ acc, int64_t n_bins, int32_t n_hits,
+                                                hough_status_t* __restrict__ st) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n_bins / 4) reinterpret_cast<int4*>(acc)[i] = make_int4(0, 0, 0, 0);
+    if (i == 0) {
+        for (int64_t j = n_bins / 4 * 4; j < n_bins; ++j) acc[j] = 0;
+        st->n_hits = n_hits;
+        st->n_bad_hits = 0;
+        st->n_votes = 0;
+        st->n_peaks = 0;
+        st->flags = 0;
+        st->n_pairs = 0;
+    }
+}
+
+__global__ __launch_bounds__(kCrThreads) void k_vote_cr(const float* __restrict__ hx, const float* __restrict__ hy,
+                                                        const uint8_t* __restrict__ hl, int32_t n, CrGrid g,
+                                                        CordicTable T, int32_t* __restrict__ acc,
+                                                        hough_status_t* __restrict__ st) {
+    const int chunks = (g.n_cols + kCrCols - 1) / kCrCols;
+    const int64_t t = (int64_t)blockIdx.x * kCrThreads + threadIdx.x;
+    const int h = (int)(t / chunks), ch = (int)(t % chunks);
+    uint32_t votes = 0, bad = 0;
+    if (h < n) {
+        const float x = hx[h], y = hy[h];
+        const uint8_t L = hl[h];
+        bool ok = (int)L < g.n_layers && isfinite(x) && isfinite(y) && fabsf(x) < 32768.0f && fabsf(y) < 32768.0f;
+        int32_t X = 0, Y = 0;
+        if (ok) {
+            X = __float2int_rn(x * 65536.0f);  // exact scaling, round half to even
+            Y = __float2int_rn(y * 65536.0f);
+            ok = !(X == 0 && Y == 0);
+        }
+        if (!ok) {
+            bad = ch == 0 ? 1u : 0u;
+        } else {
+            const int s = 32 - g.M;
+            const uint32_t maskM = g.M >= 32 ? 0xFFFFFFFFu : ((1u << g.M) - 1u);
+            const uint32_t phiM = cordic_azimuth(X, Y, T) >> s;
+            const uint64_t R2 = (uint64_t)((int64_t)X * X) + (uint64_t)((int64_t)Y * Y);
+            const double r = (double)isqrt_u64(R2) / 65536.0;
+            const int c0 = ch * kCrCols;
+            const int c1 = min(g.n_cols, c0 + kCrCols);
+            for (int col = c0; col < c1; ++col) {
+                const int l = col / g.n_qpt, k = col % g.n_qpt;
+                const double q = g.qpt_min + ((double)k + 0.5) * g.qstep;
+                const double c = -g.kappa * q;
+                const double d = g.d0_min + ((double)l + 0.5) * g.dstep;
+                const double num = c * (r * r + d * d) + 2.0 * d;
+                const double den = 2.0 * r * (1.0 + c * d);
+                if (!(den > 0.0)) continue;
+                const double A = num / den;
+                if (!(fabs(A) <= 1.0)) continue;
+                const int64_t a = llrint(A * 1073741824.0);
+                const int64_t b = (int64_t)isqrt_u64((uint64_t)(((int64_t)1 << 60) - a * a));
+                const int64_t th = (int64_t)(int32_t)cordic_azimuth((int32_t)b, (int32_t)a, T);
+                const int32_t E = (int32_t)((th + ((int64_t)1 << (s - 1))) >> s);
+                const uint32_t bin = ((phiM - (uint32_t)E) & maskM) >> g.F;
+                atomicAdd(acc + (size_t)col * g.n_phi + bin, 1);
+                ++votes;
+            }
+        }
+    }
+    // one atomic per wave for each count
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        votes += __shfl_xor(votes, o, 64);
+        bad += __shfl_xor(bad, o, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        if (votes) atomicAdd(reinterpret_cast<unsigned long long*>(&st->n_votes), (unsigned long long)votes);
+        if (bad) atomicAdd(&st->n_bad_hits, (int)bad);
+    }
+}
+
 // ------------------------------------------------------------------ zvote
 // Per candidate p (grid.y = event): every hit h of its list with a usable z votes, for each
 // cot(theta) row m, into z0 bin j(m) = (Z_h * 2^16 - S_h * C_m - z0min) >> shift, where S_h is the
@@ -2983,6 +3081,38 @@ void hough_graph_destroy(hough_graph_t* g) {
     delete g;
 }
 
+
+// ---------------------------------------------------------------------- per-hit radius
+int hough_vote_cr(const hough_plan_t* p, const hough_hits_t* hits, int32_t* acc, hough_status_t* st,
+                  hipStream_t stream) {
+    int rc = check_hits(p, hits);
+    if (rc) return rc;
+    if (!acc || !st) return HOUGH_E_INVAL;
+    if (p->g.acc_bits != 32) return HOUGH_E_UNSUPPORTED;
+    CrGrid g{};
+    g.n_layers = p->n_layers;
+    g.n_qpt = p->g.n_qpt;
+    g.n_cols = p->n_cols;
+    g.n_phi = p->g.n_phi;
+    g.M = p->M;
+    g.F = p->F;
+    g.qpt_min = p->g.qpt_min;
+    g.qstep = (p->g.qpt_max - p->g.qpt_min) / (double)p->g.n_qpt;
+    g.d0_min = p->g.d0_min;
+    g.dstep = (p->g.d0_max - p->g.d0_min) / (double)p->g.n_d0;
+    g.kappa = 0.299792458e-2 * p->B;
+    const int64_t n_bins = p->n_bins;
+    const unsigned iblocks = (unsigned)((n_bins / 4 + 255) / 256 + 1);
+    hipLaunchKernelGGL(k_cr_init, dim3(iblocks), dim3(256), 0, stream, acc, n_bins, hits->n, st);
+    const int chunks = (p->n_cols + kCrCols - 1) / kCrCols;
+    const int64_t threads = (int64_t)hits->n * chunks;
+    if (threads > 0) {
+        const unsigned blocks = (unsigned)((threads + kCrThreads - 1) / kCrThreads);
+        hipLaunchKernelGGL(k_vote_cr, dim3(blocks), dim3(kCrThreads), 0, stream, hits->x, hits->y, hits->layer,
+                           hits->n, g, p->cordic, acc, st);
+    }
+    return launch_status();
+}
 
 // ---------------------------------------------------------------------- second transform
 int hough_vertex_plan_create(const hough_plan_t* p, const hough_vertex_grid_t* vgrid, hough_vertex_plan_t** out) {

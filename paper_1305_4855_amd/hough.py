@@ -89,6 +89,7 @@ def _load() -> C.CDLL:
     L.hough_fit.argtypes = [P, C.POINTER(Hits), P, P, C.c_int32, C.c_int32, P, P, P]
     L.hough_plan_arclen_table.restype = C.c_int; L.hough_plan_arclen_table.argtypes = [P, P]
     L.hough_strerror.restype = C.c_char_p; L.hough_strerror.argtypes = [C.c_int]
+    L.hough_vote_cr.restype = C.c_int; L.hough_vote_cr.argtypes = [P, C.POINTER(Hits), P, P, P]
     L.hough_vertex_plan_create.restype = C.c_int
     L.hough_vertex_plan_create.argtypes = [P, C.POINTER(VertexGrid), C.POINTER(C.c_void_p)]
     L.hough_vertex_plan_destroy.restype = None; L.hough_vertex_plan_destroy.argtypes = [P]
@@ -127,7 +128,7 @@ EXPORTED = ["hough_plan_create", "hough_plan_destroy", "hough_acc_bytes", "hough
             "hough_angle_bits", "hough_plan_table", "hough_prep", "hough_vote", "hough_vote_prepared", "hough_peaks",
             "hough_assign", "hough_zvote", "hough_fit", "hough_plan_arclen_table", "hough_strerror", "hough_plan_set_tuning", "hough_plan_get_tuning", "hough_plan_set_vote_events",
             "hough_batch_ws_bytes", "hough_run_batch", "hough_batch_graph_create", "hough_graph_launch",
-            "hough_graph_destroy", "hough_vertex_plan_create", "hough_vertex_plan_destroy", "hough_vertex_set_groups",
+            "hough_graph_destroy", "hough_vote_cr", "hough_vertex_plan_create", "hough_vertex_plan_destroy", "hough_vertex_set_groups",
             "hough_vertex_get_groups", "hough_vertex_vote_ws_bytes", "hough_vertex_peaks_ws_bytes",
             "hough_vertex_vote", "hough_vertex_peaks", "hough_vertex_table", "hough_vertex_batch_vote_ws_bytes",
             "hough_vertex_batch_peaks_ws_bytes", "hough_vertex_vote_batch", "hough_vertex_peaks_batch"]
@@ -255,6 +256,13 @@ def vote(plan: Plan, hits: Hits, acc: torch.Tensor, ws: torch.Tensor, status: to
         raise HoughError("accumulator too small")
     _check(lib.hough_vote(plan.handle, C.byref(hits), _ptr(acc), _ptr(ws), ws.numel(), _ptr(status),
                           _stream(stream)), "hough_vote")
+
+
+def vote_cr(plan: Plan, hits: Hits, acc: torch.Tensor, status: torch.Tensor, stream=None) -> None:
+    """The vote with each hit's own radius (integer arcsine, every sample computed)."""
+    if acc.dtype != torch.int32:
+        raise HoughError("hough_vote_cr needs an int32 accumulator")
+    _check(lib.hough_vote_cr(plan.handle, C.byref(hits), _ptr(acc), _ptr(status), _stream(stream)), "hough_vote_cr")
 
 
 def vote_prepared(plan: Plan, acc: torch.Tensor, ws: torch.Tensor, status: torch.Tensor, stream=None) -> None:
