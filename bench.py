@@ -261,7 +261,8 @@ def bench_quality(H, torch):
     """Track-finding quality on the paper's own detector (layers at 11..110 cm, 0.4 mm x/y smear):
     the 50-straight-line example and curved prompt tracks at several track counts.  GPU chain
     outputs against the generator's truth, by hit share (a candidate is a track when 75 % of its
-    list comes from it) and in parameter space (a candidate within one bin of a track's true bin)."""
+    list comes from it) and in parameter space (a candidate within one bin of a track's true bin);
+    with the plain chain's time per event at each track count."""
     from paper_1305_4855_amd import configs, quality, synth
 
     out = []
@@ -272,14 +273,25 @@ def bench_quality(H, torch):
         plan = H.Plan(cfg, max_hits=max(ev.n, 1))
         bufs = H.EventBuffers(plan, cap_peaks=1 << 18, cap_pairs=1 << 23)
         x, y, lay, _ = H.hits_to_device(ev)
-        bufs.run(H.make_hits(x, y, lay), cfg.threshold)
+        hits = H.make_hits(x, y, lay)
+        bufs.run(hits, cfg.threshold)
         torch.cuda.synchronize()
         r = bufs.results()
+        # time per event of the plain chain (prep, vote, peaks, assign) against the number of tracks,
+        # the quantity of the paper's timing figure
+        stream = torch.cuda.current_stream()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(20):
+            bufs.run(hits, cfg.threshold, stream)
+        b.record(stream)
+        torch.cuda.synchronize()
+        chain_ms = a.elapsed_time(b) / 20
         share = quality.quality(r["offsets"], r["hit_idx"], ev.track_id, ntr, cfg.threshold)
         param = quality.quality_params(cfg, ev.truth, ev.track_id, r["peaks"], cfg.threshold)
         out.append({"workload": cfg.name, "tracks": ntr, "hits": ev.n,
                     "grid": f"{cfg.n_phi}x{cfg.n_qpt}x{cfg.n_d0}", "threshold": cfg.threshold,
-                    "candidates": r["status"]["n_peaks"],
+                    "candidates": r["status"]["n_peaks"], "chain_ms_per_event": round(chain_ms, 4),
                     "hit_share": {k: share[k] for k in ("efficiency", "purity", "duplicates_per_found_track")},
                     "parameter_space": {k: param[k] for k in ("efficiency", "purity")}})
         del bufs, plan
