@@ -11,7 +11,12 @@
  *     tracks need a third parameter (here: the transverse impact parameter
  *     d0, so the space is phi0 x q/pT x d0);
  *   Sec. "Preliminary Results", fitting paragraph: the hits of each
- *     candidate are handed to a track fit (here: hough_assign lists them);
+ *     candidate are handed to a track fit (here: hough_assign lists them,
+ *     hough_fit fits a circle to each list);
+ *   Sec. "New Trigger Capabilities": a second transform of the candidates
+ *     finds displaced-jet vertices (hough_vertex_*);
+ *   Sec. "Preliminary Results", detector paragraph: hits smeared in x and y
+ *     (hough_vote_cr: the transform with each hit's own radius);
  *   Sec. "Preliminary Results", data paragraph: hits, parameter space and
  *     peak detection stay resident in GPU memory for the whole event.
  *

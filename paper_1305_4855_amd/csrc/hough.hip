@@ -38,7 +38,18 @@
 //           voted at once, one lane per (row, hit), into per-row LDS histograms
 //           whose words carry their own tie-break key, so the argmax is tracked
 //           from the atomic's return value and each touched word is restored
-//           right after the vote (no clearing pass, no scan of the grid).
+//           right after the vote (no clearing pass, no scan of the grid);
+//   fit     one lane per candidate sums the moments of the algebraic circle
+//           fit over its list in list order (double), the wave's list stretch
+//           staged in LDS (with the event's coordinates when they fit there),
+//           and solves the 3x3 normal equations by Cramer's rule;
+//   vertex  the second transform of the candidates: lane = radius row of an
+//           LDS slab of the vertex space, one table-row load per run of
+//           candidates sharing a column, candidate ranges counted apart and
+//           added by a reduction kernel; its peaks reuse the peak finder;
+//   cr      the vote with each hit's own radius: one thread per (hit, 16
+//           columns), every sample computed (integer square root and integer
+//           arcsine by CORDIC), global atomics.
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
