@@ -50,10 +50,24 @@ def cpu_baseline(cfg, ev):
     O.assign(g, ev, pk)
     dt = time.perf_counter() - t0
     cores = int(os.environ.get("OMP_NUM_THREADS") or os.cpu_count() or 1)
+    # the same oracle chain on the paper detector's curved events against the number of tracks (the
+    # quantity of the paper's CPU/GPU timing figure; the GPU side is in the quality section)
+    from paper_1305_4855_amd import configs, synth
+    vs_tracks = []
+    for ntr in (50, 500, 2000, 4000):
+        c7 = configs.C7.with_(n_tracks=ntr)
+        e7 = synth.make_event(c7, 0)
+        g7 = O.Cfg(c7)
+        t1 = time.perf_counter()
+        a7, _ = O.vote(g7, e7)
+        n7, p7 = O.peaks(g7, a7, c7.threshold)
+        O.assign(g7, e7, p7)
+        vs_tracks.append({"tracks": ntr, "hits": e7.n, "oracle_ms_per_event": round((time.perf_counter() - t1) * 1e3, 2)})
     return {"value": round(1.0 / dt, 4), "unit": "events/s", "cores": cores, "kind": "oracle",
             "sample": (f"1 full event of the same workload ({ev.n} hits, {nv} hit-votes, {n} candidates): "
                        f"vote on {cores} OpenMP threads, peaks and assign single-threaded; {dt:.1f} s"),
-            "hit_votes_per_s": round(nv / dt, 1)}
+            "hit_votes_per_s": round(nv / dt, 1),
+            "paper_detector_vs_tracks": vs_tracks}
 
 
 def bench_batched(H, torch, n_events: int, reps: int):
