@@ -2496,15 +2496,30 @@ __global__ __launch_bounds__(kVvoteThreads) void k_vvote(const hough_peak_t* __r
                 const uint32_t data = e[u] != (uint32_t)INT32_MIN ? inc : 0u;
                 const uint32_t el = e[u] << lsh;
                 const int span = h[u + 1] - h[u];
-                uint64_t m = onm & (span >= 64 ? ~0ull : (((1ull << span) - 1ull) << h[u]));
-                while (m) {
-                    const int i = (int)__builtin_ctzll(m);
-                    m &= m - 1;
+                const uint64_t rmask = span >= 64 ? ~0ull : (((1ull << span) - 1ull) << h[u]);
+                uint64_t m = onm & rmask;
+                // one vote: the candidate's angle by readlane, the slab byte address (the slab starts at
+                // LDS address 0: the kernel has no static LDS) by one and-or, the atomic
+                auto vote = [&](int i) {
                     const uint32_t sum = (uint32_t)__builtin_amdgcn_readlane((int)ang, i) + el;
-                    // byte address in the slab (which starts at LDS address 0: the kernel has no static LDS)
                     uint32_t off;  // one and-or (the compiler otherwise splits it into an and and an add)
                     asm("v_and_or_b32 %0, %1, %2, %3" : "=v"(off) : "v"(sum >> to_row), "s"(row_mask), "v"(loff));
                     asm volatile("ds_add_u32 %0, %1" ::"v"(off), "v"(data) : "memory");
+                };
+                if (m == rmask) {  // every candidate of the run votes (the usual case): a counted loop
+                    const int i1 = h[u + 1];
+                    int i = h[u];
+                    for (; i + 1 < i1; i += 2) {
+                        vote(i);
+                        vote(i + 1);
+                    }
+                    if (i < i1) vote(i);
+                } else {
+                    while (m) {
+                        const int i = (int)__builtin_ctzll(m);
+                        m &= m - 1;
+                        vote(i);
+                    }
                 }
             }
         }
