@@ -363,6 +363,12 @@ typedef struct {
 size_t hough_batch_ws_bytes(const hough_plan_t* plan, int32_t n_events, int32_t cap_peaks);
 int hough_run_batch(const hough_plan_t* plan, const hough_batch_t* batch, hipStream_t stream);
 
+/* Track fit (as hough_fit) of every listed candidate of every event of a
+ * batch after hough_run_batch: hits, offsets, hit lists and statuses taken
+ * from `batch`; out (dev) [n_events][cap_peaks][4] doubles.  Results equal
+ * hough_fit on each event alone. */
+int hough_fit_batch(const hough_plan_t* plan, const hough_batch_t* batch, double* out, hipStream_t stream);
+
 /* The batched chain captured once into a hipGraph and replayed: buffers are
  * bound at capture time (refill the same buffers with new events between
  * launches).  `stream` must not be the NULL stream. */

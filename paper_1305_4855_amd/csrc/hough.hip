@@ -3122,6 +3122,16 @@ void hough_graph_destroy(hough_graph_t* g) {
 }
 
 
+int hough_fit_batch(const hough_plan_t* p, const hough_batch_t* b, double* out, hipStream_t stream) {
+    if (!p || !b || !out) return HOUGH_E_INVAL;
+    if (b->n_events < 1 || b->n_events > 65535 || b->cap_peaks < 1 || b->cap_pairs < 1) return HOUGH_E_INVAL;
+    if (!b->hit_offsets || !b->x || !b->y || !b->offsets || !b->hit_idx || !b->status) return HOUGH_E_INVAL;
+    const Events ev{b->hit_offsets, 0, p->g.max_hits_per_event, 0};
+    launch_fit(ev, b->n_events, p->n_cu, b->x, b->y, b->offsets, b->hit_idx, b->cap_peaks, b->cap_pairs, b->status,
+               out, stream);
+    return launch_status();
+}
+
 // ---------------------------------------------------------------------- per-hit radius
 int hough_vote_cr(const hough_plan_t* p, const hough_hits_t* hits, int32_t* acc, hough_status_t* st,
                   hipStream_t stream) {

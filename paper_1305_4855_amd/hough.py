@@ -90,6 +90,7 @@ def _load() -> C.CDLL:
     L.hough_plan_arclen_table.restype = C.c_int; L.hough_plan_arclen_table.argtypes = [P, P]
     L.hough_strerror.restype = C.c_char_p; L.hough_strerror.argtypes = [C.c_int]
     L.hough_vote_cr.restype = C.c_int; L.hough_vote_cr.argtypes = [P, C.POINTER(Hits), P, P, P]
+    L.hough_fit_batch.restype = C.c_int; L.hough_fit_batch.argtypes = [P, C.POINTER(Batch), P, P]
     L.hough_vertex_plan_create.restype = C.c_int
     L.hough_vertex_plan_create.argtypes = [P, C.POINTER(VertexGrid), C.POINTER(C.c_void_p)]
     L.hough_vertex_plan_destroy.restype = None; L.hough_vertex_plan_destroy.argtypes = [P]
@@ -128,7 +129,7 @@ EXPORTED = ["hough_plan_create", "hough_plan_destroy", "hough_acc_bytes", "hough
             "hough_angle_bits", "hough_plan_table", "hough_prep", "hough_vote", "hough_vote_prepared", "hough_peaks",
             "hough_assign", "hough_zvote", "hough_fit", "hough_plan_arclen_table", "hough_strerror", "hough_plan_set_tuning", "hough_plan_get_tuning", "hough_plan_set_vote_events",
             "hough_batch_ws_bytes", "hough_run_batch", "hough_batch_graph_create", "hough_graph_launch",
-            "hough_graph_destroy", "hough_vote_cr", "hough_vertex_plan_create", "hough_vertex_plan_destroy", "hough_vertex_set_groups",
+            "hough_graph_destroy", "hough_fit_batch", "hough_vote_cr", "hough_vertex_plan_create", "hough_vertex_plan_destroy", "hough_vertex_set_groups",
             "hough_vertex_get_groups", "hough_vertex_vote_ws_bytes", "hough_vertex_peaks_ws_bytes",
             "hough_vertex_vote", "hough_vertex_peaks", "hough_vertex_table", "hough_vertex_batch_vote_ws_bytes",
             "hough_vertex_batch_peaks_ws_bytes", "hough_vertex_vote_batch", "hough_vertex_peaks_batch"]
@@ -515,6 +516,7 @@ class BatchBuffers:
         self.status = torch.zeros((self.n_events, STATUS_BYTES // 4), dtype=torch.int32, device=device)
         self.zv = (torch.empty((self.n_events, cap_peaks, 3), dtype=torch.int32, device=device)
                    if plan.has_zvote else None)
+        self.fit = None  # [n_events][cap_peaks][4] float64 once run_fit has been called
 
     def load(self, events, stream=None) -> None:
         """Copy the packed hits of `events` (at most n_events) into the device buffers."""
@@ -544,6 +546,13 @@ class BatchBuffers:
         b = self.struct(threshold, n_events, zvote)
         _check(lib.hough_run_batch(self.plan.handle, C.byref(b), _stream(stream)), "hough_run_batch")
 
+    def run_fit(self, stream=None, n_events: Optional[int] = None) -> None:
+        """Circle fit of every listed candidate of every event (after run)."""
+        if self.fit is None:
+            self.fit = torch.empty((self.n_events, self.cap_peaks, 4), dtype=torch.float64, device=self.x.device)
+        b = self.struct(1, n_events)
+        _check(lib.hough_fit_batch(self.plan.handle, C.byref(b), _ptr(self.fit), _stream(stream)), "hough_fit_batch")
+
     def results(self, e: int) -> dict:
         st = status_dict(self.status[e])
         n = min(st["n_peaks"], self.cap_peaks)
@@ -553,6 +562,8 @@ class BatchBuffers:
         out = dict(status=st, peaks=pk, offsets=offs, hit_idx=self.hit_idx[e, :npairs].cpu().numpy())
         if self.zv is not None:
             out["zvote"] = self.zv[e, :n].cpu().numpy()
+        if self.fit is not None:
+            out["fit"] = self.fit[e, :n].cpu().numpy()
         return out
 
 

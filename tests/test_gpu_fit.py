@@ -114,3 +114,32 @@ def test_fit_hand_made_lists(H, oracle_mod, n_hits):
     assert tuple(got[3]) == (10.0, -7.0, 25.0, 5.0)
     assert tuple(got[0]) == (0.0, 0.0, -1.0, 0.0) and got[1][2] == -1.0 and got[2][2] == -1.0
     assert (got[len(lists):] == 7.0).all()  # rows past the listed candidates are not written
+
+
+def test_fit_batch_equals_oracle(H, oracle_mod):
+    """hough_fit_batch after the batched chain: uneven events (one without hits, one cut by the
+    pair capacity), each event's rows equal the oracle's fit of its own lists; the batch's plan
+    allows 32767 hits per event, so the coordinates are gathered from memory (not staged in LDS)."""
+    O = oracle_mod
+    cfg = configs.small_variant(configs.C2, n_phi=256, n_qpt=64, n_d0=4)
+    events = [synth.make_event(cfg.with_(n_tracks=t), i) for i, t in enumerate((30, 0, 55, 12))]
+    plan = H.Plan(cfg, max_hits=32767)
+    cap_pairs = 3000  # the 55-track event has about 6600 pairs: its later lists are cut
+    bufs = H.BatchBuffers(plan, len(events), max(sum(e.n for e in events), 1), cap_peaks=1 << 12, cap_pairs=cap_pairs)
+    bufs.load(events)
+    bufs.run(cfg.threshold, zvote=False)
+    bufs.run_fit()
+    torch.cuda.synchronize()
+    g = O.Cfg(cfg)
+    cut_seen = False
+    for e, ev in enumerate(events):
+        r = bufs.results(e)
+        _, pk = O.peaks(g, O.vote(g, ev)[0], cfg.threshold)
+        offs, hit_idx, tot = O.assign(g, ev, pk)
+        np.testing.assert_array_equal(r["peaks"], pk)
+        ref = O.fit(ev, offs, hit_idx)
+        cut = offs[1:] > cap_pairs
+        cut_seen = cut_seen or bool(cut.any())
+        np.testing.assert_array_equal(r["fit"][~cut], ref[~cut])
+        assert (r["fit"][cut, 2] == -2.0).all()
+    assert cut_seen
