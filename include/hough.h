@@ -127,10 +127,13 @@ typedef struct hough_plan hough_plan_t;
 /* Launch shapes (results are identical for every valid choice). */
 typedef struct {
     int32_t vote_threads;      /* threads per vote workgroup: 256, 512 or 1024            */
-    int32_t vote_grid;         /* persistent vote workgroups of a batch (0 = 256)          */
+    int32_t vote_grid;         /* persistent vote workgroups of a batch (0 = automatic)    */
     int32_t peak_planes;       /* d0 planes walked by one peak-finder thread (1..32);
                                   halved while a launch would give a compute unit
                                   fewer than two workgroups                         */
+    int32_t vote_cols;         /* window-table vote: columns per work item, 4..64, a power
+                                  of two (0 = automatic)                                 */
+    int32_t assign_blocks;     /* assignment workgroups per event (0 = automatic)        */
 } hough_tuning_t;
 
 /* Create a plan on the current HIP device: validates geometry and grid and

@@ -131,13 +131,16 @@ struct hough_plan {
     hipEvent_t vote_start, vote_stop;  // recorded by every vote launch when set (kernel timing)
     int n_cu;        // compute units of the plan's device
     void* d_zero;    // one accumulator row of zeros (n_phi x 4 bytes): out-of-grid neighbours
+    bool pt;         // window-table path: prefix-count table per event, table vote and assignment
+    int pt_bpl;      // bins per lane of the table vote (n_phi / 64)
+    int pt_row;      // entries per window-count row (n_phi + pt_bpl + 2, rounded up to 8)
 };
 
 namespace {
 
 // ------------------------------------------------------------------ layout
 struct WsLayout {
-    size_t misc, phi32, lay, cell_start, tmp_phi, tmp_key, sorted_phi, sorted_h;
+    size_t misc, phi32, lay, cell_start, tmp_phi, tmp_key, sorted_phi, sorted_h, ptab, gtab;
     size_t flags, grp_count, grp_votes, grp_off, grp_voff, peak_voff, total;
 };
 
@@ -166,6 +169,8 @@ WsLayout ws_layout(const hough_plan* p, int32_t max_peaks) {
     L.tmp_key = take(4 * maxh);
     L.sorted_phi = take(4 * maxh);
     L.sorted_h = take(4 * maxh);
+    L.ptab = take(p->pt ? (size_t)p->n_layers * ((size_t)1 << p->F) * p->g.n_phi * 2 : 0);
+    L.gtab = take(p->pt ? (size_t)p->n_layers * ((size_t)1 << p->F) * p->pt_row * 2 : 0);
     L.flags = take((size_t)(p->n_bins / kStrip));
     L.grp_count = take(4 * (size_t)(peak_groups(p) + 1));
     L.grp_votes = take(4 * (size_t)(peak_groups(p) + 1));
@@ -253,13 +258,13 @@ __device__ __forceinline__ int64_t block_inclusive_scan(int64_t v, int64_t* wsum
 }
 
 struct WsOff {
-    size_t misc, phi32, lay, cell_start, tmp_phi, tmp_key, sorted_phi, sorted_h;
+    size_t misc, phi32, lay, cell_start, tmp_phi, tmp_key, sorted_phi, sorted_h, ptab, gtab;
     size_t flags, grp_count, grp_votes, grp_off, grp_voff, peak_voff;
 };
 
 WsOff ws_off(const WsLayout& L) {
-    return WsOff{L.misc,  L.phi32,     L.lay,       L.cell_start, L.tmp_phi, L.tmp_key, L.sorted_phi,
-                 L.sorted_h, L.flags, L.grp_count, L.grp_votes, L.grp_off,  L.grp_voff, L.peak_voff};
+    return WsOff{L.misc,     L.phi32,  L.lay,       L.cell_start, L.tmp_phi, L.tmp_key, L.sorted_phi, L.sorted_h,
+                 L.ptab,     L.gtab,   L.flags,     L.grp_count,  L.grp_votes, L.grp_off, L.grp_voff,  L.peak_voff};
 }
 
 // ------------------------------------------------------------------ batch set-up
@@ -546,6 +551,94 @@ __global__ __launch_bounds__(256) void k_prep_rank(Events ev, int n_cells, int c
     at<int32_t>(w, O.sorted_h)[c0 + rank] = h;
 }
 
+// ------------------------------------------------------------------ window tables
+// Prefix counts of an event's sorted hits at every angle the vote and the assignment ask about.
+// With W = 2^F and P_L(x) = the number of valid hits of layer L whose M-bit angle is < x, extended
+// past the full turn by P_L(x + 2^M) = P_L(x) + n_L, for every phase r in [0, W):
+//     PT[L][r][j] = P_L(j W + r)                          j in [0, n_phi)   (assignment)
+//     GT[L][r][j] = P_L((j + 1) W + r) - P_L(j W + r)     j in [0, row)     (vote)
+// GT[L][r][j] is the number of the layer's hits in the cyclic angle window [j W + r, (j + 1) W + r)
+// (at most 65535: 16 bits), and for j < n_phi - 1 the window's hits are the sorted positions
+// [PT[L][r][j], PT[L][r][j + 1]) of the layer.  A sample value E and a bin b of a column select the
+// window x = (E mod 2^M) + b W: the same phase r = E mod W for every bin, at j = (E mod 2^M) div W + b.
+// Window-count rows run `row` entries (past n_phi they repeat the turn) so that a lane of the vote
+// reads its bins without a wrap.
+// grid = (blocks over (layer, block of kPtPhases phases, pair of entries), events); a thread writes
+// entries j = 2 jp, 2 jp + 1 of both tables for kPtPhases phases.  P_L at an angle counts the hits of
+// the cells before the angle's cell plus those of its cell below the angle (a cell spans at least
+// one bin); each of the three cells involved is loaded once, eight sorted angles at a time.
+constexpr int kPtPhases = 16;
+
+struct PtCell {
+    int a, n_in;      // first sorted position and hit count of the cell
+    uint32_t e[8];    // its first eight sorted angles
+};
+
+__device__ __forceinline__ PtCell pt_cell(const int32_t* cs, int c, const uint32_t* __restrict__ sorted_phi) {
+    PtCell pc;
+    pc.a = cs[c];
+    pc.n_in = cs[c + 1] - pc.a;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) pc.e[i] = pc.n_in > 0 ? sorted_phi[pc.a + min(i, pc.n_in - 1)] : 0u;
+    return pc;
+}
+
+// hits of the cell with angle < x
+__device__ __forceinline__ int pt_count_below(const PtCell& pc, uint32_t x, const uint32_t* __restrict__ sorted_phi) {
+    int cnt = 0;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) cnt += (int)((i < pc.n_in) & (pc.e[i] < x));
+    if (pc.n_in > 8 && cnt == 8)
+        while (cnt < pc.n_in && sorted_phi[pc.a + cnt] < x) ++cnt;
+    return cnt;
+}
+
+__global__ __launch_bounds__(256) void k_ptab(Events ev, int n_layers, int cell_bits, int M, int F, int n_phi,
+                                              int row, int pairs_pad, char* __restrict__ ws, WsOff O) {
+    char* w = event_ws(ws, ev, blockIdx.y);
+    const int32_t* cell_start = at<int32_t>(w, O.cell_start);
+    const uint32_t* sorted_phi = at<uint32_t>(w, O.sorted_phi);
+    uint32_t* pt = at<uint32_t>(w, O.ptab);
+    uint32_t* gt = at<uint32_t>(w, O.gtab);
+    const int W = 1 << F;
+    const int n_rb = W / kPtPhases;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int jp = t % pairs_pad;
+    const int rest = t / pairs_pad;
+    const int rb = rest % n_rb;
+    const int L = rest / n_rb;
+    if (L >= n_layers || 2 * jp >= row) return;
+    const int cpl = 1 << cell_bits;
+    const int32_t* cs = cell_start + L * cpl;
+    const int lay0 = cs[0];
+    const int n_L = cs[cpl] - lay0;
+    const int lp = M - F;  // log2 n_phi
+    // P_L at entries 2 jp + i, i = 0, 1, 2: the entry taken mod n_phi, plus n_L per full turn
+    PtCell c[3];
+    uint32_t xb[3];
+    int base[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        const int e = 2 * jp + i;
+        const int je = e & (n_phi - 1);
+        c[i] = pt_cell(cs, je >> (lp - cell_bits), sorted_phi);
+        xb[i] = (uint32_t)je << F;
+        base[i] = c[i].a - lay0 + (e / n_phi) * n_L;
+    }
+    const bool wp = 2 * jp < n_phi;  // entries of the prefix table
+    uint32_t* po = pt + ((size_t)L * W + (size_t)rb * kPtPhases) * (n_phi / 2) + jp;
+    uint32_t* go = gt + ((size_t)L * W + (size_t)rb * kPtPhases) * (row / 2) + jp;
+#pragma unroll 4
+    for (int q = 0; q < kPtPhases; ++q) {
+        const uint32_t r = (uint32_t)(rb * kPtPhases + q);
+        uint32_t P[3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) P[i] = (uint32_t)(base[i] + pt_count_below(c[i], xb[i] + r, sorted_phi));
+        if (wp) po[(size_t)q * (n_phi / 2)] = (P[0] & 0xFFFFu) | (P[1] << 16);
+        go[(size_t)q * (row / 2)] = ((P[1] - P[0]) & 0xFFFFu) | ((P[2] - P[1]) << 16);
+    }
+}
+
 // ------------------------------------------------------------------ vote
 __device__ __forceinline__ void lds_vote(uint32_t phi, uint32_t e, uint32_t mask, uint32_t lanebits,
                                          uint32_t data) {
@@ -751,6 +844,108 @@ __global__ __launch_bounds__(kVoteMaxThreads) void k_vote(Events ev, const int32
             __syncthreads();
         } else {
             __syncthreads();
+            item += gridDim.x;
+        }
+    }
+}
+
+// The vote from the window tables (plans with at most 65535 hits per event and n_phi >= 128).
+// Column (l, k) gets, from each layer L whose sample E is valid, the layer's hits in the windows
+// [x_b, x_b + W), x_b = (E mod 2^M) + b W: with r = E mod W and s = (E mod 2^M) div W, bin b
+// receives GT[L][r][s + b] (index taken mod n_phi; the row's entries past n_phi repeat the turn).
+// So the accumulator column is the sum over layers of one window-count row each, rotated by s: no
+// atomics, and every read is a run of consecutive entries.
+// One wave per column at a time: lane i owns the BPL bins [i BPL, (i + 1) BPL), the entries
+// [i0, i0 + BPL) with i0 = (s + i BPL) mod n_phi, loaded as BPL/2 + 1 dwords from the dword boundary
+// at or below i0 (the parity of i0 is that of s, the same for the whole wave); a byte permute with a
+// wave-uniform selector aligns the pairs.  Counts are kept as 16-bit pairs in 32-bit words: a plain
+// add never carries between the halves, since no bin exceeds the event's hit count (<= 65535).
+// A layer without a valid sample reads a row of zeros (every load is issued unconditionally).
+// Work items are (event, block of `cpi` columns) as in k_vote: item = rank * blocks + block;
+// the 4 waves of a workgroup take `cpi` / 4 consecutive columns each.
+constexpr int kVotePtThreads = 256;
+
+template <int BPL, bool OUT16>
+__global__ __launch_bounds__(kVotePtThreads) void k_vote_pt(Events ev, const int32_t* __restrict__ E, int n_layers,
+                                                           int n_cols, int n_phi, int M, int F, int row,
+                                                           const uint32_t* __restrict__ zero_row,
+                                                           char* __restrict__ ws, WsOff O,
+                                                           char* __restrict__ acc_base, size_t acc_stride,
+                                                           int n_events, const int32_t* __restrict__ order,
+                                                           int32_t* __restrict__ queue, int cpi) {
+    constexpr int NP = BPL / 2;                       // bin pairs per lane
+    constexpr int ND = NP + 1;                        // dwords loaded per layer
+    constexpr int LG = ND * 10 <= 60 ? 10 : (60 / ND > 0 ? 60 / ND : 1);  // layers per load group
+    __shared__ int next_item;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int n_blocks = n_cols / cpi;
+    const int total = n_events * n_blocks;
+    const int cpw = cpi / (kVotePtThreads / 64);     // columns per wave
+    const uint32_t mmask = (1u << M) - 1u;
+    const uint32_t wmask = (1u << F) - 1u;
+    const int row2 = row / 2;                        // row length in dwords
+    int item = blockIdx.x;
+    while (item < total) {
+        const int rank = item / n_blocks;
+        const int e = order ? order[rank] : rank;
+        const int blk = item - rank * n_blocks;
+        const uint32_t* gt = at<const uint32_t>(event_ws(ws, ev, e), O.gtab);
+        char* acc_e = acc_base + (size_t)e * acc_stride;
+        for (int ci = 0; ci < cpw; ++ci) {
+            const int col = blk * cpi + wave * cpw + ci;
+            uint32_t acc[NP];
+#pragma unroll
+            for (int q = 0; q < NP; ++q) acc[q] = 0u;
+            for (int L0 = 0; L0 < n_layers; L0 += LG) {
+                uint32_t d[LG][ND];
+                uint32_t sel[LG];
+#pragma unroll
+                for (int u = 0; u < LG; ++u) {
+                    const int L = L0 + u;
+                    const int32_t ev_l = L < n_layers ? E[(size_t)L * n_cols + col] : INT32_MIN;
+                    const uint32_t ep = (uint32_t)ev_l & mmask;
+                    const uint32_t r = ep & wmask, sft = ep >> F;
+                    const uint32_t i0 = (sft + (uint32_t)(lane * BPL)) & (uint32_t)(n_phi - 1);
+                    const uint32_t* src = ev_l != INT32_MIN ? gt + ((size_t)L * (1u << F) + r) * row2 : zero_row;
+                    // byte selector: the pair starting at an odd entry spans two dwords
+                    sel[u] = (__builtin_amdgcn_readfirstlane(sft) & 1u) ? 0x05040302u : 0x03020100u;
+#pragma unroll
+                    for (int t = 0; t < ND; ++t) d[u][t] = src[(i0 >> 1) + t];
+                }
+#pragma unroll
+                for (int u = 0; u < LG; ++u) {
+#pragma unroll
+                    for (int q = 0; q < NP; ++q) acc[q] += __builtin_amdgcn_perm(d[u][q + 1], d[u][q], sel[u]);
+                }
+            }
+            // store the column's bins [lane * BPL, (lane + 1) * BPL)
+            if (OUT16) {
+                uint32_t* dst = reinterpret_cast<uint32_t*>(acc_e + ((size_t)col * n_phi + (size_t)lane * BPL) * 2);
+#pragma unroll
+                for (int q = 0; q < NP; q += 4) {
+                    if (q + 4 <= NP) *reinterpret_cast<uint4*>(dst + q) = make_uint4(acc[q], acc[q + 1], acc[q + 2], acc[q + 3]);
+                    else if (q + 2 <= NP) *reinterpret_cast<uint2*>(dst + q) = make_uint2(acc[q], acc[q + 1]);
+                    else dst[q] = acc[q];
+                }
+            } else {
+                uint32_t* dst = reinterpret_cast<uint32_t*>(acc_e + ((size_t)col * n_phi + (size_t)lane * BPL) * 4);
+#pragma unroll
+                for (int q = 0; q < NP; q += 2) {
+                    if (q + 2 <= NP)
+                        *reinterpret_cast<uint4*>(dst + 2 * q) = make_uint4(acc[q] & 0xFFFFu, acc[q] >> 16,
+                                                                            acc[q + 1] & 0xFFFFu, acc[q + 1] >> 16);
+                    else
+                        *reinterpret_cast<uint2*>(dst + 2 * q) = make_uint2(acc[q] & 0xFFFFu, acc[q] >> 16);
+                }
+            }
+        }
+        if (queue) {
+            __syncthreads();
+            if (threadIdx.x == 0) next_item = (int)gridDim.x + atomicAdd(queue, 1);
+            __syncthreads();
+            item = __builtin_amdgcn_readfirstlane(next_item);
+        } else {
             item += gridDim.x;
         }
     }
@@ -1611,6 +1806,183 @@ __global__ __launch_bounds__(kAssignThreads) void k_assign_fill(
     }
 }
 
+// Assignment from the window table (plans with the table, see k_ptab).  The hits of layer L in the
+// window of candidate (l, k, b) are sorted positions: with x = (E mod 2^M) + b * W = r + j * W,
+// the run [PT[L][r][j], PT[L][r][j + 1]) of the layer (relative to its first sorted hit); a window
+// that passes the turn (j = n_phi - 1) is the run from PT[L][r][j] to the layer's end followed by
+// [0, PT[L][r][0]) (the hits below angle r).  Two table loads per layer replace the searches of
+// k_assign_fill; the layers are taken eight at a time so that their loads are in flight together.
+typedef __attribute__((address_space(3))) const uint16_t lds_cu16;
+
+struct HitsU16 {
+    lds_cu16* h;
+    __device__ __forceinline__ int32_t hit(int i) const { return (int32_t)h[i]; }
+};
+struct HitsIdx {
+    const int32_t* __restrict__ h;
+    __device__ __forceinline__ int32_t hit(int i) const { return h[i]; }
+};
+
+constexpr int kAssignLayerChunk = 8;
+
+template <typename View>
+__device__ __forceinline__ void assign_candidate_pt(const hough_peak_t& pk, int64_t off, int64_t o0,
+                                                    const int32_t* __restrict__ Ec, int n_layers, int n_cols, int M,
+                                                    int F, int n_phi, int row, const uint16_t* __restrict__ pt,
+                                                    const int32_t* lay_start, const View& hv, int32_t* buf,
+                                                    int buf_words, int32_t* hit_idx, int32_t cap_pairs) {
+    constexpr int LC = kAssignLayerChunk;
+    const uint32_t mmask = (1u << M) - 1u, wmask = (1u << F) - 1u;
+    int64_t wpos = off;
+    for (int L0 = 0; L0 < n_layers; L0 += LC) {
+        if (wpos >= cap_pairs) break;
+        int32_t ev_l[LC];
+#pragma unroll
+        for (int u = 0; u < LC; ++u) ev_l[u] = L0 + u < n_layers ? Ec[(size_t)(L0 + u) * n_cols] : INT32_MIN;
+        uint32_t lo[LC], hi[LC];
+        bool wr[LC];
+#pragma unroll
+        for (int u = 0; u < LC; ++u) {
+            // every load is in bounds (an invalid sample still gives an angle below 2^M)
+            const uint32_t x = ((uint32_t)ev_l[u] + ((uint32_t)pk.b << F)) & mmask;
+            const uint32_t r = x & wmask, j = x >> F;
+            const int Lc = min(L0 + u, n_layers - 1);
+            const uint16_t* rp = pt + ((size_t)Lc * (wmask + 1u) + r) * n_phi;
+            wr[u] = (int)j == n_phi - 1;
+            lo[u] = rp[j];
+            hi[u] = rp[wr[u] ? 0u : j + 1u];
+        }
+#pragma unroll
+        for (int u = 0; u < LC; ++u) {
+            const int L = L0 + u;
+            if (L >= n_layers || ev_l[u] == INT32_MIN) continue;
+            const int base = lay_start[L];
+            for (int seg = 0; seg < 2; ++seg) {
+                if (seg == 1 && !wr[u]) break;
+                const int a0 = seg == 0 ? base + (int)lo[u] : base;
+                const int a1 = seg == 0 ? (wr[u] ? lay_start[L + 1] : base + (int)hi[u]) : base + (int)hi[u];
+                // four entries at a time: the four loads go out before the four stores
+                for (int q = a0; q < a1; q += 4) {
+                    int32_t h[4];
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) h[v] = hv.hit(min(q + v, a1 - 1));
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int64_t wp = wpos + (q - a0) + v;
+                        if (q + v < a1 && wp < cap_pairs) {
+                            const int64_t rel = wp - o0;
+                            if (rel < buf_words) buf[rel] = h[v];
+                            else hit_idx[wp] = h[v];
+                        }
+                    }
+                }
+                wpos += a1 > a0 ? a1 - a0 : 0;
+            }
+        }
+    }
+}
+
+// One thread per listed candidate (grid.y = event), as k_assign_fill: the 64 candidates of a wave
+// own one contiguous stretch of the CSR list, assembled in the wave's LDS buffer and stored
+// coalesced.  LDS: the layers' first sorted positions, then the event's sorted hit indices as 16-bit
+// values (staged when they leave room for buffers of kAssignBufMin words), then 16 wave buffers.
+__global__ __launch_bounds__(kAssignThreads) void k_assign_pt(
+    Events ev, const hough_peak_t* __restrict__ peaks_base, int32_t peak_stride, int32_t cap_peaks,
+    hough_status_t* __restrict__ st_base, const int32_t* __restrict__ E, int n_layers, int cell_bits, int n_cols,
+    int n_qpt, int M, int F, int n_phi, int row, char* __restrict__ ws, WsOff O,
+    int32_t* __restrict__ offsets_base, int32_t* __restrict__ hit_idx_base, int32_t cap_pairs, int lds_words) {
+    extern __shared__ int32_t sm_i32[];
+    constexpr int kWaves = kAssignThreads / 64;
+    constexpr int kHead = 64;  // words for the layer starts (n_layers + 1 <= 33)
+    const int e = blockIdx.y;
+    char* w = event_ws(ws, ev, e);
+    const hough_peak_t* peaks = peaks_base + (size_t)e * peak_stride;
+    const int64_t* peak_voff = at<int64_t>(w, O.peak_voff);
+    const int32_t* g_cell_start = at<int32_t>(w, O.cell_start);
+    const int32_t* sorted_h = at<int32_t>(w, O.sorted_h);
+    const uint16_t* pt = at<const uint16_t>(w, O.ptab);
+    int32_t* offsets = offsets_base + (size_t)e * (cap_peaks + 1);
+    int32_t* hit_idx = hit_idx_base + (size_t)e * cap_pairs;
+    hough_status_t* st = st_base + e;
+    const int n = min(*at<int32_t>(w, O.misc), cap_peaks);
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    if (blockIdx.x == 0 && tid == 0) {
+        const int64_t tot = n > 0 ? peak_voff[n - 1] + peaks[n - 1].votes : 0;
+        offsets[n] = (int32_t)min(tot, (int64_t)INT32_MAX);
+        st->n_pairs = tot;
+        if (tot > cap_pairs) atomicOr(&st->flags, HOUGH_F_PAIR_OVERFLOW);
+    }
+    if ((int)blockIdx.x * kAssignThreads >= n) return;  // uniform per block
+    const int n_valid = g_cell_start[n_layers << cell_bits];
+    const int h4 = (n_valid + 3) >> 2;          // 16-byte chunks of sorted hit indices
+    const int stage_words = (2 * h4 + 3) & ~3;  // as 16-bit values
+    int buf_words = min(kAssignBufMax, (lds_words - kHead - stage_words) / kWaves) & ~63;
+    const bool staged = buf_words >= kAssignBufMin;
+    if (!staged) buf_words = min(kAssignBufMax, (lds_words - kHead) / kWaves) & ~63;
+    int32_t* lay_start = sm_i32;
+    uint32_t* s16 = reinterpret_cast<uint32_t*>(sm_i32 + kHead);
+    int32_t* buf = sm_i32 + kHead + (staged ? stage_words : 0) + wave * buf_words;
+    const int stride = gridDim.x * kAssignThreads;
+    int base = blockIdx.x * kAssignThreads + wave * 64;
+    hough_peak_t pk{};
+    int64_t off = 0;
+    if (base < n) {
+        const int i = min(base + lane, n - 1);
+        pk = peaks[i];
+        off = peak_voff[i];
+    }
+    if (tid <= n_layers) lay_start[tid] = g_cell_start[tid << cell_bits];
+    if (staged) {
+        for (int c0 = tid; c0 < h4; c0 += kStageUnroll * kAssignThreads) {
+            uint4 v[kStageUnroll];
+#pragma unroll
+            for (int u = 0; u < kStageUnroll; ++u)
+                v[u] = reinterpret_cast<const uint4*>(sorted_h)[min(c0 + u * kAssignThreads, h4 - 1)];
+#pragma unroll
+            for (int u = 0; u < kStageUnroll; ++u) {
+                const int c = c0 + u * kAssignThreads;
+                if (c < h4)
+                    reinterpret_cast<uint2*>(s16)[c] =
+                        make_uint2((v[u].x & 0xFFFFu) | (v[u].y << 16), (v[u].z & 0xFFFFu) | (v[u].w << 16));
+            }
+        }
+    }
+    __syncthreads();
+    for (; base < n; base += stride) {
+        const int i = base + lane;
+        const int last = min(n, base + 64) - 1;
+        const int64_t o0 = __shfl(off, 0, 64);
+        const int64_t o1 = __shfl(off, last - base, 64) + __shfl(pk.votes, last - base, 64);
+        const hough_peak_t cur = pk;
+        const int64_t cur_off = off;
+        if (base + stride < n) {  // the wave's next candidates (wave-uniform)
+            const int i2 = min(base + stride + lane, n - 1);
+            pk = peaks[i2];
+            off = peak_voff[i2];
+        }
+        if (i < n) {
+            offsets[i] = (int32_t)min(cur_off, (int64_t)INT32_MAX);
+            const int32_t* Ec = E + (size_t)cur.l * n_qpt + cur.k;
+            if (staged)
+                assign_candidate_pt(cur, cur_off, o0, Ec, n_layers, n_cols, M, F, n_phi, row, pt, lay_start,
+                                    HitsU16{(lds_cu16*)s16}, buf, buf_words, hit_idx, cap_pairs);
+            else
+                assign_candidate_pt(cur, cur_off, o0, Ec, n_layers, n_cols, M, F, n_phi, row, pt, lay_start,
+                                    HitsIdx{sorted_h}, buf, buf_words, hit_idx, cap_pairs);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const int64_t fe = min(min(o1, o0 + buf_words), (int64_t)cap_pairs);
+        for (int64_t wq = o0 + lane; wq < fe; wq += 64) hit_idx[wq] = buf[wq - o0];
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+}
+
 // ------------------------------------------------------------------ fit
 // Track fit of each listed candidate (grid.y = event), one lane per candidate: the algebraic
 // (Kasa) circle x^2 + y^2 + a x + b y + c = 0 through its hits in the least-squares sense.  The
@@ -2241,6 +2613,12 @@ void launch_prep(const hough_plan* p, const Events& ev, int n_events, int max_n,
     if (max_n > cap_h)
         hipLaunchKernelGGL(k_prep_rank, dim3((max_n + 255) / 256, n_events), dim3(256), 0, stream, ev, p->n_cells,
                            p->cell_bits, p->M, ws, O);
+    if (p->pt) {
+        const int pairs_pad = ((p->pt_row / 2) + 63) & ~63;
+        const int64_t threads = (int64_t)p->n_layers * (((int64_t)1 << p->F) / kPtPhases) * pairs_pad;
+        hipLaunchKernelGGL(k_ptab, dim3((unsigned)((threads + 255) / 256), n_events), dim3(256), 0, stream, ev,
+                           p->n_layers, p->cell_bits, p->M, p->F, p->g.n_phi, p->pt_row, pairs_pad, ws, O);
+    }
 }
 
 // LDS of one vote workgroup: the slab, the queue word (padded to 256 bytes) and, for 16-bit slabs,
@@ -2252,9 +2630,55 @@ size_t vote_lds_bytes(const hough_plan* p) {
     return slab + 256 + 64 * (tb + 1) * 4;
 }
 
+// Columns per work item of the table vote: a single event takes the largest block that still gives
+// every CU four workgroups; a batch takes 64 (fewer queue atomics).
+int pt_cols_per_item(const hough_plan* p, bool single) {
+    int cpi = p->tuning.vote_cols > 0 ? p->tuning.vote_cols : 64;
+    if (p->tuning.vote_cols <= 0)
+        while (single && cpi > 4 && (int64_t)p->n_cols / cpi < 4 * (int64_t)p->n_cu) cpi /= 2;
+    while (p->n_cols % cpi) cpi /= 2;
+    return cpi;
+}
+
+template <int BPL>
+void launch_vote_pt_bpl(const hough_plan* p, const Events& ev, int n_events, char* ws, const WsOff& O, char* a,
+                        size_t acc_stride, const int32_t* order, int32_t* queue, int grid, int cpi,
+                        hipStream_t stream) {
+    const uint32_t* zr = static_cast<const uint32_t*>(p->d_zero);
+    if (p->g.acc_bits == 16)
+        hipExtLaunchKernelGGL((k_vote_pt<BPL, true>), dim3(grid), dim3(kVotePtThreads), 0, stream, p->vote_start,
+                              p->vote_stop, 0, ev, p->d_E, p->n_layers, p->n_cols, p->g.n_phi, p->M, p->F, p->pt_row,
+                              zr, ws, O, a, acc_stride, n_events, order, queue, cpi);
+    else
+        hipExtLaunchKernelGGL((k_vote_pt<BPL, false>), dim3(grid), dim3(kVotePtThreads), 0, stream, p->vote_start,
+                              p->vote_stop, 0, ev, p->d_E, p->n_layers, p->n_cols, p->g.n_phi, p->M, p->F, p->pt_row,
+                              zr, ws, O, a, acc_stride, n_events, order, queue, cpi);
+}
+
+void launch_vote_pt(const hough_plan* p, const Events& ev, int n_events, char* ws, const WsOff& O, void* acc,
+                    size_t acc_stride, const int32_t* order, int32_t* queue, int grid, hipStream_t stream) {
+    const int cpi = pt_cols_per_item(p, queue == nullptr);
+    const int64_t items = (int64_t)n_events * (p->n_cols / cpi);
+    if (queue != nullptr && grid <= 0) grid = 8 * p->n_cu;  // persistent: eight workgroups per CU
+    if (queue == nullptr || grid > items) grid = (int)items;
+    char* a = static_cast<char*>(acc);
+    switch (p->pt_bpl) {
+        case 2: launch_vote_pt_bpl<2>(p, ev, n_events, ws, O, a, acc_stride, order, queue, grid, cpi, stream); break;
+        case 4: launch_vote_pt_bpl<4>(p, ev, n_events, ws, O, a, acc_stride, order, queue, grid, cpi, stream); break;
+        case 8: launch_vote_pt_bpl<8>(p, ev, n_events, ws, O, a, acc_stride, order, queue, grid, cpi, stream); break;
+        case 16: launch_vote_pt_bpl<16>(p, ev, n_events, ws, O, a, acc_stride, order, queue, grid, cpi, stream); break;
+        case 32: launch_vote_pt_bpl<32>(p, ev, n_events, ws, O, a, acc_stride, order, queue, grid, cpi, stream); break;
+        default: launch_vote_pt_bpl<64>(p, ev, n_events, ws, O, a, acc_stride, order, queue, grid, cpi, stream); break;
+    }
+}
+
 void launch_vote(const hough_plan* p, const Events& ev, int n_events, char* ws, const WsOff& O, void* acc,
                  size_t acc_stride, const int32_t* order, int32_t* queue, int grid, hough_status_t* st,
                  hipStream_t stream) {
+    if (p->pt) {
+        launch_vote_pt(p, ev, n_events, ws, O, acc, acc_stride, order, queue, grid, stream);
+        return;
+    }
     int threads = p->tuning.vote_threads;
     char* a = static_cast<char*>(acc);
     const int32_t* E = p->d_E;
@@ -2347,11 +2771,17 @@ void launch_assign(const hough_plan* p, const Events& ev, int n_events, const ho
                    int32_t peak_stride, int32_t cap_peaks, int32_t* offsets, int32_t* hit_idx, int32_t cap_pairs,
                    char* ws, const WsOff& O, hough_status_t* st, hipStream_t stream) {
     const int64_t want = ((int64_t)cap_peaks + kAssignThreads - 1) / kAssignThreads;
-    const int per_event_cap = n_events > 1 ? 64 : 2 * 256;
+    const int per_event_cap = p->tuning.assign_blocks > 0 ? p->tuning.assign_blocks : n_events > 1 ? 64 : 2 * 256;
     const unsigned nblk = (unsigned)(want < per_event_cap ? want : per_event_cap);
     // the kernel lays out its LDS per event (cell table, staged hits, wave buffers)
     const int cells_words = (p->n_cells + 1 + 3) & ~3;
     const int lds_words = kLdsBytes / 4;
+    if (p->pt) {
+        hipLaunchKernelGGL(k_assign_pt, dim3(nblk, n_events), dim3(kAssignThreads), kLdsBytes, stream, ev, peaks,
+                           peak_stride, cap_peaks, st, p->d_E, p->n_layers, p->cell_bits, p->n_cols, p->g.n_qpt,
+                           p->M, p->F, p->g.n_phi, p->pt_row, ws, O, offsets, hit_idx, cap_pairs, lds_words);
+        return;
+    }
     // one packed word per staged hit: angles of at most 16 bits and hit indices below 2^16
     if (p->M <= 16 && p->g.max_hits_per_event <= 65536)
         hipLaunchKernelGGL(k_assign_fill<true>, dim3(nblk, n_events), dim3(kAssignThreads), kLdsBytes, stream, ev,
@@ -2768,12 +3198,19 @@ int hough_plan_create(const hough_geometry_t* geom, const hough_grid_t* grid, ho
     p->M = lp + g.frac_bits;
     // one azimuth cell per phi0 bin (at most 2^10 cells per layer): a bin's window spans <= 2 cells
     p->cell_bits = lp < 10 ? lp : 10;
+    // window-table path: every window count fits 16 bits (at most 65535 hits per event) and a
+    // column's bins split evenly over the 64 lanes of a wave in pairs
+    p->pt = g.max_hits_per_event <= 65535 && g.n_phi >= 128;
+    p->pt_bpl = g.n_phi / 64;
+    p->pt_row = ((g.n_phi + p->pt_bpl + 2) + 7) & ~7;  // window-count rows: entries a lane reads past the turn
     p->n_cols = g.n_d0 * g.n_qpt;
     p->n_cells = p->n_layers << p->cell_bits;
     p->n_bins = (int64_t)p->n_cols * g.n_phi;
     p->tuning.vote_threads = 1024;
     p->tuning.vote_grid = 0;
     p->tuning.peak_planes = 8;
+    p->tuning.vote_cols = 0;
+    p->tuning.assign_blocks = 0;
     for (int i = 0; i < kCordicSteps; ++i)
         p->cordic.t[i] = (int32_t)llrint(atan(ldexp(1.0, -i)) * (2147483648.0 / M_PI));
 
@@ -2896,6 +3333,8 @@ int hough_plan_create(const hough_geometry_t* geom, const hough_grid_t* grid, ho
         ae = hipFuncSetAttribute((const void*)k_prep_bucket, hipFuncAttributeMaxDynamicSharedMemorySize,
                                  kLdsBytes - 1024);
     if (ae == hipSuccess)
+        ae = hipFuncSetAttribute((const void*)k_assign_pt, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
+    if (ae == hipSuccess)
         ae = hipFuncSetAttribute((const void*)k_zvote, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
     if (ae == hipSuccess)
         ae = hipFuncSetAttribute((const void*)k_fit_res, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
@@ -2922,6 +3361,9 @@ int hough_plan_set_tuning(hough_plan_t* p, const hough_tuning_t* t) {
     if (!p || !t) return HOUGH_E_INVAL;
     if (t->vote_threads != 256 && t->vote_threads != 512 && t->vote_threads != 1024) return HOUGH_E_INVAL;
     if (t->vote_grid < 0 || t->peak_planes < 1 || t->peak_planes > kMaxPeakPlanes) return HOUGH_E_INVAL;
+    if (t->vote_cols != 0 && (t->vote_cols < 4 || t->vote_cols > 64 || (t->vote_cols & (t->vote_cols - 1))))
+        return HOUGH_E_INVAL;
+    if (t->assign_blocks < 0 || t->assign_blocks > 4096) return HOUGH_E_INVAL;
     p->tuning = *t;
     return HOUGH_OK;
 }
@@ -3062,9 +3504,11 @@ int hough_run_batch(const hough_plan_t* p, const hough_batch_t* b, hipStream_t s
     hipLaunchKernelGGL(k_batch_init, dim3(1), dim3(1024), 0, stream, b->hit_offsets, b->n_events, queue, order);
     launch_prep(p, ev, b->n_events, max_n, b->x, b->y, b->layer, nullptr, ev_ws, O, b->status, stream);
     int grid = p->tuning.vote_grid;
-    if (grid <= 0) grid = 256;
-    const int items = b->n_events * (p->n_cols / kVoteCols);
-    if (grid > items) grid = items;
+    if (!p->pt) {
+        if (grid <= 0) grid = 256;
+        const int items = b->n_events * (p->n_cols / kVoteCols);
+        if (grid > items) grid = items;
+    }
     launch_vote(p, ev, b->n_events, ev_ws, O, b->acc, hough_acc_bytes(p), order, queue, grid, b->status, stream);
     launch_peaks(p, ev, b->n_events, b->acc, hough_acc_bytes(p), b->threshold, b->peaks, b->cap_peaks, ev_ws, O,
                  b->status, stream);

@@ -43,7 +43,8 @@ class Hits(C.Structure):
 
 
 class Tuning(C.Structure):
-    _fields_ = [("vote_threads", C.c_int32), ("vote_grid", C.c_int32), ("peak_planes", C.c_int32)]
+    _fields_ = [("vote_threads", C.c_int32), ("vote_grid", C.c_int32), ("peak_planes", C.c_int32),
+                ("vote_cols", C.c_int32), ("assign_blocks", C.c_int32)]
 
 
 class VertexGrid(C.Structure):
@@ -204,10 +205,12 @@ class Plan:
     def tuning(self) -> dict:
         t = Tuning()
         _check(lib.hough_plan_get_tuning(self.handle, C.byref(t)), "hough_plan_get_tuning")
-        return dict(vote_threads=t.vote_threads, vote_grid=t.vote_grid, peak_planes=t.peak_planes)
+        return dict(vote_threads=t.vote_threads, vote_grid=t.vote_grid, peak_planes=t.peak_planes,
+                    vote_cols=t.vote_cols, assign_blocks=t.assign_blocks)
 
-    def set_tuning(self, vote_threads: int = 1024, vote_grid: int = 0, peak_planes: int = 8) -> None:
-        t = Tuning(int(vote_threads), int(vote_grid), int(peak_planes))
+    def set_tuning(self, vote_threads: int = 1024, vote_grid: int = 0, peak_planes: int = 8, vote_cols: int = 0,
+                   assign_blocks: int = 0) -> None:
+        t = Tuning(int(vote_threads), int(vote_grid), int(peak_planes), int(vote_cols), int(assign_blocks))
         _check(lib.hough_plan_set_tuning(self.handle, C.byref(t)), "hough_plan_set_tuning")
 
     def set_vote_events(self, start=None, stop=None) -> None:
