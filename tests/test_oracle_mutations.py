@@ -57,6 +57,12 @@ MUTATIONS = {
     "cr_layer_radius": ("        r = or_hit_radius(X, Y);", "        r = g->r_cm[layer[h]];"),
     "cr_sqrt_operand": ("b = (int64_t)or_isqrt((uint64_t)(((int64_t)1 << 60) - a * a));",
                         "b = (int64_t)or_isqrt((uint64_t)(((int64_t)1 << 60) + a * a));"),
+    "vote_columns_transposed": ("int32_t l = cols[2 * i], k = cols[2 * i + 1], hh, E;",
+                                "int32_t k = cols[2 * i], l = cols[2 * i + 1], hh, E;"),
+    "vote_columns_bin_edge": ("out[(int64_t)i * g->n_phi + or_bin(phiM[hh], E, M, F)] += 1;",
+                              "out[(int64_t)i * g->n_phi + (or_bin(phiM[hh], E, M, F) + 1) % g->n_phi] += 1;"),
+    "cot_centre_bin_edge": ("double v = g->cot_min + ((double)m + 0.5)", "double v = g->cot_min + ((double)m + 0.0)"),
+    "cot_centre_truncates": ("return llrint(v * 65536.0);", "return (int64_t)(v * 65536.0);"),
     "vertex_min_votes_strict": ("if (pk[4 * p + 3] < min_votes) continue;", "if (pk[4 * p + 3] <= min_votes) continue;"),
 }
 

@@ -308,6 +308,30 @@ def _centred_track_event(base, g, O, rng, n_tracks, displaced=True, smear=0.0):
     return ev, cells
 
 
+def test_vote_columns_equal_slices_of_vote(oracle_mod):
+    """The column-restricted vote (used to check large accumulators by sampling) equals the
+    corresponding columns of the full vote, for columns at the grid corners, repeated columns
+    and random ones, on a displaced and a prompt grid, and on an event with invalid hits."""
+    O = oracle_mod
+    rng = np.random.default_rng(41)
+    for base in (configs.small_variant(configs.C2, n_tracks=40, n_phi=256, n_qpt=32, n_d0=16),
+                 configs.small_variant(configs.C1, n_tracks=12)):
+        g = O.Cfg(base)
+        ev = synth.make_event(base, 3)
+        # plant invalid hits: a bad layer, the origin, a non-finite coordinate
+        ev = synth.Event(x=np.concatenate([ev.x, np.array([5.0, 0.0, np.nan], np.float32)]),
+                         y=np.concatenate([ev.y, np.array([5.0, 0.0, 1.0], np.float32)]),
+                         z=None, layer=np.concatenate([ev.layer, np.array([base.n_layers, 1, 2], np.uint8)]),
+                         track_id=np.concatenate([ev.track_id, -np.ones(3, np.int32)]), truth={})
+        acc, _ = O.vote(g, ev)
+        cols = [(0, 0), (base.n_d0 - 1, base.n_qpt - 1), (0, base.n_qpt - 1), (base.n_d0 - 1, 0)]
+        cols += [(int(rng.integers(0, base.n_d0)), int(rng.integers(0, base.n_qpt))) for _ in range(40)]
+        cols += cols[4:8]  # repeats
+        out = O.vote_columns(g, ev, np.array(cols, np.int32))
+        for i, (l, k) in enumerate(cols):
+            np.testing.assert_array_equal(out[i], acc[l, k], err_msg=f"{base.name} column {(l, k)}")
+
+
 def test_vote_bin_centred_tracks_land_in_their_bin(oracle_mod):
     """A noise-free helix with parameters at bin centres puts exactly one vote
     per crossed layer into its generating bin (hits from independent
@@ -590,7 +614,9 @@ def test_zvote_bin_centred_track(oracle_mod):
         l = int(rng.integers(base.n_d0 // 4, 3 * base.n_d0 // 4))
         d0 = O.d0_centre(g, l)
         m = int(rng.integers(32, 96)); j = int(rng.integers(16, 112))
-        cot = O.cot_centre_q16(g, m) / 65536.0
+        # the bin centre from exact rational arithmetic (not the oracle's own centre)
+        cot = float(Fraction(base.cot_min) + Fraction(2 * m + 1, 2) * (Fraction(base.cot_max) - Fraction(base.cot_min))
+                    / base.n_cot)
         z0 = base.z0_min + (j + 0.5) * (base.z0_max - base.z0_min) / base.n_z0
         b = int(rng.integers(0, base.n_phi))
         phi0 = (b + 0.5) * 2 * np.pi / base.n_phi
@@ -606,6 +632,27 @@ def test_zvote_bin_centred_track(oracle_mod):
         assert tot == ev.n  # every hit sits in the generating bin
         out = O.zvote(g, ev, pk, offs, hit_idx)
         assert tuple(out[0]) == (m, j, ev.n)
+
+
+def test_cot_centres_every_bin(oracle_mod):
+    """Every cot(theta) bin centre in Q16.16: exact dyadic values on the large-grid range
+    ([-2, 2] in 128 bins: C_m = (2m + 1) * 1024 - 131072), and on grids whose centres are not
+    dyadic, the exact rational centre rounded to the nearest Q16.16 value (within half a unit)."""
+    O = oracle_mod
+    g = O.Cfg(configs.C4)
+    assert configs.C4.n_cot == 128 and configs.C4.cot_min == -2.0 and configs.C4.cot_max == 2.0
+    for m in range(configs.C4.n_cot):
+        assert O.cot_centre_q16(g, m) == (2 * m + 1) * 1024 - 131072, m
+    for lo, hi, n in ((-1.3, 2.1, 100), (-3.0, 3.0, 7), (0.25, 0.75, 33)):
+        base = configs.C4.with_(cot_min=lo, cot_max=hi, n_cot=n)
+        gg = O.Cfg(base)
+        prev = None
+        for m in range(n):
+            exact = (Fraction(lo) + Fraction(2 * m + 1, 2) * (Fraction(hi) - Fraction(lo)) / n) * 65536
+            got = O.cot_centre_q16(gg, m)
+            assert abs(Fraction(got) - exact) <= Fraction(1, 2) + Fraction(1, 10 ** 6), (lo, hi, n, m, got)
+            assert prev is None or got > prev  # strictly increasing with m
+            prev = got
 
 
 def test_zvote_empty_candidate(oracle_mod):
