@@ -70,6 +70,65 @@ def cpu_baseline(cfg, ev):
             "paper_detector_vs_tracks": vs_tracks}
 
 
+def bench_roofline_probe():
+    """The ceilings the roofline fractions are taken against, measured on this device by the
+    micro-benchmarks of paper_1305_4855_amd/csrc/roofline_probe.hip: conflict-free LDS atomic adds
+    (no return, the slab votes' operation), 32-bit LDS reads and writes at the same addresses as
+    controls, 128-bit LDS reads (LDS bandwidth), and an HBM streaming copy and fill of 2 GiB."""
+    from paper_1305_4855_amd import probe
+
+    blocks = CUS * 4
+    lds = {k: probe.lds(k, blocks) for k in ("atomic", "read32", "write32", "read128")}
+    out = {}
+    for k, r in lds.items():
+        out[f"lds_{k}"] = {"lane_ops_per_s": round(r["lane_ops_per_s"], 1),
+                           "lanes_per_clk_per_cu_at_2.4GHz": round(r["lane_ops_per_s"] / (CUS * CLOCK_HZ), 2),
+                           "bytes_per_clk_per_cu_at_2.4GHz": round(r["bytes_per_s"] / (CUS * CLOCK_HZ), 1),
+                           "us_per_launch": r["us_per_launch"], "workgroups": blocks}
+    for k in ("copy", "fill"):
+        r = probe.hbm(k)
+        out[f"hbm_{k}"] = {"gb_per_s": r["gb_per_s"], "bytes": r["bytes"], "us_per_launch": r["us_per_launch"]}
+    out["note"] = ("LDS rates of 1024-thread workgroups, 16 independent instructions per loop iteration; "
+                   "the LDS-atomic rooflines use lds_atomic.lane_ops_per_s as their peak")
+    return out
+
+
+def bufs_max_pairs(st_i32: np.ndarray) -> int:
+    return int(st_i32.view(np.int64)[:, 3].max()) if st_i32.shape[0] else 0
+
+
+def check_flags(st_i32: np.ndarray, what: str) -> dict:
+    """Per-event status flags of a batch (int32 view of the status rows): the OR of all flags and the
+    number of events with any flag set.  Timed runs must not truncate work, so a set flag is an error."""
+    fl = st_i32[:, 5]
+    out = {"status_flags_or": int(np.bitwise_or.reduce(fl)) if fl.size else 0,
+           "events_flagged": int(np.count_nonzero(fl))}
+    if out["events_flagged"]:
+        raise RuntimeError(f"{what}: {out['events_flagged']} events flagged (flags {out['status_flags_or']}): "
+                           "candidate or pair capacity too small")
+    return out
+
+
+def sized_batch(H, torch, plan, events, threshold, stream, cap_peaks=1 << 18, cap_pairs=1 << 22):
+    """Batch buffers whose per-event capacities hold the largest event's candidates and pairs: one
+    sizing run, then buffers sized to the largest counts (rounded up to a power of two)."""
+    total = sum(e.n for e in events)
+    while True:
+        bufs = H.BatchBuffers(plan, len(events), total, cap_peaks=cap_peaks, cap_pairs=cap_pairs)
+        bufs.load(events)
+        bufs.run(threshold, stream)
+        torch.cuda.synchronize()
+        st = bufs.status.cpu().numpy().view("int32")
+        need_pk = int(st[:, 4].max()) if len(events) else 0
+        need_pr = bufs_max_pairs(st)
+        if need_pk <= cap_peaks and need_pr <= cap_pairs:
+            return bufs, cap_peaks, cap_pairs
+        del bufs
+        torch.cuda.empty_cache()
+        cap_peaks = max(cap_peaks, 1 << int(need_pk - 1).bit_length())
+        cap_pairs = max(cap_pairs, 1 << int(need_pr - 1).bit_length())
+
+
 def bench_batched(H, torch, n_events: int, reps: int):
     """The batched workload: n_events events with uneven hit counts (Gamma-Poisson track counts,
     mean 500, 5 % displaced, 20 % noise) on the same 512x256x64 int32 grid, in one persistent
@@ -82,9 +141,8 @@ def bench_batched(H, torch, n_events: int, reps: int):
     plan = H.Plan(cfg, max_hits=cfg.max_hits_per_event)
     tuning = tune.apply(plan)
     total = sum(e.n for e in events)
-    bufs = H.BatchBuffers(plan, n_events, total, cap_peaks=1 << 19, cap_pairs=1 << 24)
-    bufs.load(events)
     stream = torch.cuda.current_stream()
+    bufs, cap_peaks, cap_pairs = sized_batch(H, torch, plan, events, cfg.threshold, stream)
     for _ in range(2):
         bufs.run(cfg.threshold, stream)
     torch.cuda.synchronize()
@@ -96,6 +154,7 @@ def bench_batched(H, torch, n_events: int, reps: int):
     st = bufs.status.cpu().numpy().view("int32")
     votes = int(bufs.status.cpu().numpy().view("int64")[:, 1].sum())
     peaks = int(st[:, 4].sum())
+    flags = check_flags(st, "batched")
     # the persistent vote kernel of the batch, timed by its own start/end events
     vp = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
     for a, b in vp:
@@ -121,7 +180,7 @@ def bench_batched(H, torch, n_events: int, reps: int):
     t_graph = (time.perf_counter() - t0) / reps
     graph.close()
     # plain per-event chain over the same events
-    ev_bufs = H.EventBuffers(plan, cap_peaks=1 << 19, cap_pairs=1 << 24)
+    ev_bufs = H.EventBuffers(plan, cap_peaks=cap_peaks, cap_pairs=cap_pairs)
     dev_hits = []
     for e in events:
         x, y, lay, _ = H.hits_to_device(e)
@@ -136,12 +195,15 @@ def bench_batched(H, torch, n_events: int, reps: int):
             ev_bufs.run(h[3], cfg.threshold, stream)
     torch.cuda.synchronize()
     t_plain = (time.perf_counter() - t0) / plain_reps
+    check_flags(bufs.status.cpu().numpy().view("int32"), "batched (after the graph replays)")
     del bufs
     return {
         "workload": f"batch of {n_events} uneven events (c3): Gamma-Poisson tracks mean 500 in [50, 2000], "
                     f"5% displaced, 20% noise, 512x256x64 int32",
         "hits": total, "hits_min": min(e.n for e in events), "hits_max": max(e.n for e in events),
         "hit_votes": votes, "candidates": peaks, "tuning": tuning,
+        "cap_peaks": cap_peaks, "cap_pairs": cap_pairs, "max_candidates_per_event": int(st[:, 4].max()),
+        "max_pairs_per_event": int(bufs_max_pairs(st)), **flags,
         "events_per_s_batched": round(n_events / t_batch, 2),
         "events_per_s_graph": round(n_events / t_graph, 2),
         "events_per_s_plain": round(n_events / t_plain, 2),
@@ -168,11 +230,8 @@ def bench_large_grid(H, torch, reps: int):
     events = [synth.make_event(cfg, i) for i in range(cfg.n_events)]
     plan = H.Plan(cfg, max_hits=cfg.max_hits_per_event)
     total = sum(e.n for e in events)
-    bufs = H.BatchBuffers(plan, len(events), total, cap_peaks=1 << 21, cap_pairs=1 << 25)
-    bufs.load(events)
     stream = torch.cuda.current_stream()
-    bufs.run(cfg.threshold, stream)
-    torch.cuda.synchronize()
+    bufs, cap_peaks, cap_pairs = sized_batch(H, torch, plan, events, cfg.threshold, stream, 1 << 20, 1 << 24)
     times = {}
     for with_z in (False, True):
         a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -184,7 +243,7 @@ def bench_large_grid(H, torch, reps: int):
         times[with_z] = a.elapsed_time(b) / reps
     # the second transform (vertex space) of every event's candidates, batched
     vp = H.VertexPlan.of(plan)
-    vb = H.VertexBatchBuffers(vp, len(events), 1 << 21, 1 << 16)
+    vb = H.VertexBatchBuffers(vp, len(events), cap_peaks, 1 << 16)
     vb.run(bufs.peaks, bufs.status, cfg.v_threshold, stream)
     torch.cuda.synchronize()
     a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -202,13 +261,14 @@ def bench_large_grid(H, torch, reps: int):
     votes = int(st.view("int64")[:, 1].sum())
     cands = int(st[:, 4].sum())
     pairs = int(st.view("int64")[:, 3].sum())
-    flags = int(np.bitwise_or.reduce(st[:, 5]))
+    flags = check_flags(st, "large grid")
     del bufs
     zv_ms = times[True] - times[False]
     return {
         "workload": f"batch of {len(events)} events (c4): 600 prompt tracks + 2 displaced vertices, 20% noise, "
                     f"1024x512x128 int16, then 128x128 cot(theta) x z0 vote per candidate",
-        "hits": total, "hit_votes": votes, "candidates": cands, "pairs": pairs, "status_flags_or": flags,
+        "hits": total, "hit_votes": votes, "candidates": cands, "pairs": pairs, **flags,
+        "cap_peaks": cap_peaks, "cap_pairs": cap_pairs,
         "ms_per_batch": round(times[True], 3), "ms_per_batch_without_zvote": round(times[False], 3),
         "events_per_s": round(len(events) / times[True] * 1e3, 2),
         "events_per_s_without_zvote": round(len(events) / times[False] * 1e3, 2),
@@ -493,6 +553,8 @@ def bench_plain(H, torch, args):
                    "frac_of_8000": round(fit_gbs / 8000.0, 4)},
            "note": "per-launch time of back-to-back launches (kernel plus launch gap)"}
 
+    if st["flags"]:
+        raise RuntimeError(f"plain chain: status flags {st['flags']} (candidate or pair capacity too small)")
     ms_per_step = (t1 - t0) * 1e3 / args.steps
     events_per_s = 1e3 / ms_per_step
     achieved = st["n_votes"] / (vote_ms * 1e-3) / 1e9
@@ -537,6 +599,8 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=500)
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-roofline-probe", action="store_true",
+                    help="skip the LDS/HBM micro-benchmarks (the LDS-atomic peak then falls back to unit counts)")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batch-events", type=int, default=256)
     ap.add_argument("--no-serving", action="store_true")
@@ -566,6 +630,12 @@ def main() -> int:
     out = {"metric": METRIC, "value": None, "unit": "events/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
            "dtype": "int32", "data": "synthetic"}
+    probe_res = None
+    if not args.no_roofline_probe:
+        global LDS_ATOMIC_PEAK_GVOTES
+        probe_res = bench_roofline_probe()
+        LDS_ATOMIC_PEAK_GVOTES = probe_res["lds_atomic"]["lane_ops_per_s"] / 1e9
+        torch.cuda.empty_cache()
     if not args.no_plain:
         out = bench_plain(H, torch, args)
         torch.cuda.empty_cache()
@@ -589,6 +659,8 @@ def main() -> int:
         out["serving"] = res[0]
         if len(res) > 1:
             out["serving_below_capacity"] = res[1]
+    if probe_res is not None:
+        out["roofline_probe"] = probe_res
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(configs.C2, synth.make_event(configs.C2, 0))
     print(json.dumps(out, default=lambda o: o.item() if isinstance(o, np.generic) else str(o)), flush=True)

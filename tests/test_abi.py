@@ -60,3 +60,27 @@ def test_strerror_and_argument_errors_without_gpu(lib_path):
     lib.hough_plan_create.restype = ctypes.c_int
     lib.hough_plan_create.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
     assert lib.hough_plan_create(None, None, None) == -1
+
+
+PROBE_HEADER = os.path.join(ROOT, "include", "roofline_probe.h")
+PROBE_LIB = os.path.join(ROOT, "paper_1305_4855_amd", "libroofline_probe.so")
+
+
+def test_probe_library_exports_and_rejects_bad_arguments(lib_path):
+    """The roofline micro-benchmark library exports what its header declares and refuses invalid
+    arguments before any GPU call."""
+    text = re.sub(r"/\*.*?\*/", "", open(PROBE_HEADER).read(), flags=re.S)
+    names = sorted(set(re.findall(r"\b(probe_[a-z0-9_]+)\s*\(", text)))
+    assert names == ["probe_hbm", "probe_lds"]
+    assert os.path.exists(PROBE_LIB)
+    lib = ctypes.CDLL(PROBE_LIB)
+    out = subprocess.run(["nm", "-D", "--defined-only", PROBE_LIB], capture_output=True, text=True).stdout
+    assert set(names) <= set(re.findall(r"\bT (probe_[a-z0-9_]+)", out))
+    d, f = ctypes.c_double(), ctypes.c_float()
+    lib.probe_lds.restype = ctypes.c_int
+    assert lib.probe_lds(0, 0, 1, 1, None, ctypes.byref(d), ctypes.byref(f)) == -1
+    lib.probe_hbm.restype = ctypes.c_int
+    lib.probe_hbm.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int,
+                              ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]
+    assert lib.probe_hbm(0, None, None, 17, 1, 1, ctypes.byref(d), ctypes.byref(f)) == -1
+    assert b"amdgcn-amd-amdhsa--gfx950" in open(PROBE_LIB, "rb").read()

@@ -207,3 +207,47 @@ def test_zvote_in_captured_graph(H):
             np.testing.assert_array_equal(got["zvote"], ref["zvote"])
         del junk
     graph.close()
+
+
+def test_large_grid_batch_full_size_equals_oracle(H, oracle_mod):
+    """The large-grid workload as benchmarked: a batch of 8 of its events (600 prompt tracks plus
+    two displaced vertices, 20 % noise, with z) on the full 1024 x 512 x 128 int16 grid with the r-z
+    stage, in one batched chain.  For every event: the whole accumulator and the whole candidate
+    list equal the oracle's, every list length equals its candidate's votes, and sampled hit lists
+    and r-z results equal the oracle's for those candidates."""
+    O = oracle_mod
+    cfg = configs.C4
+    events = [synth.make_event(cfg, i) for i in range(8)]
+    print(f"[zvote] full-size large-grid batch: hits {[e.n for e in events]}", flush=True)
+    plan = H.Plan(cfg, max_hits=cfg.max_hits_per_event)
+    cap_peaks, cap_pairs = 1 << 20, 1 << 25
+    bufs = H.BatchBuffers(plan, len(events), sum(e.n for e in events), cap_peaks, cap_pairs)
+    bufs.load(events)
+    bufs.run(cfg.threshold)
+    torch.cuda.synchronize()
+    g = O.Cfg(cfg)
+    rng = np.random.default_rng(77)
+    for e, ev in enumerate(events):
+        got = bufs.results(e)
+        st = got["status"]
+        assert st["flags"] == 0, (e, st)
+        acc_ref, nv = O.vote(g, ev)
+        assert st["n_votes"] == nv
+        acc = bufs.acc[e].to(torch.int32).cpu().numpy()
+        np.testing.assert_array_equal(acc, acc_ref, err_msg=f"event {e} accumulator")
+        del acc
+        n, pk = O.peaks(g, acc_ref, cfg.threshold)
+        del acc_ref
+        assert st["n_peaks"] == n, e
+        np.testing.assert_array_equal(got["peaks"], pk, err_msg=f"event {e} candidates")
+        offs = got["offsets"]
+        np.testing.assert_array_equal(np.diff(offs), pk[:, 3], err_msg=f"event {e} list lengths")
+        assert st["n_pairs"] == int(pk[:, 3].sum())
+        sel = np.unique(rng.choice(n, min(n, 300), replace=False))
+        o_ref, h_ref, _ = O.assign(g, ev, pk[sel])
+        for i, p in enumerate(sel):
+            np.testing.assert_array_equal(got["hit_idx"][offs[p]:offs[p + 1]], h_ref[o_ref[i]:o_ref[i + 1]],
+                                          err_msg=f"event {e} list of candidate {p}")
+        z_ref = O.zvote(g, ev, pk[sel], o_ref, h_ref)
+        np.testing.assert_array_equal(got["zvote"][sel], z_ref, err_msg=f"event {e} r-z")
+        print(f"[zvote] event {e}: {ev.n} hits, {n} candidates, {st['n_pairs']} pairs equal the oracle", flush=True)
