@@ -434,10 +434,12 @@ def bench_serving(H, torch, runs, pool_size: int = 256):
     pool = [synth.make_event(cfg, i) for i in range(pool_size)]
     plan = H.Plan(cfg, max_hits=cfg.max_hits_per_event)
     tune.apply(plan)
-    srv = serve.Server(plan, cfg.threshold, acc_budget_bytes=cfg.hbm_budget_bytes, max_lanes=4,
-                       max_lane_events=512, cap_peaks=1 << 19, cap_pairs=1 << 23, hits_per_slot=8192, topk=64)
-    # warm up every lane once
-    warm = np.linspace(0.0, 0.01, srv.slots)
+    # per-event capacities hold the pool's largest event (2000 tracks: about 2.4e5 candidates and
+    # 1.3e7 hit-candidate pairs), so no served list is cut
+    srv = serve.Server(plan, cfg.threshold, budget_bytes=cfg.hbm_budget_bytes, n_contexts=4, max_batch=64,
+                       cap_peaks=1 << 19, cap_pairs=1 << 24, hits_per_event=8192, topk=64)
+    # warm up every context once
+    warm = np.linspace(0.0, 0.01, 4 * srv.max_batch)
     srv.serve(pool, warm, np.arange(len(warm)) % pool_size)
     results = []
     for i, (rate_hz, duration_s) in enumerate(runs):
@@ -445,14 +447,17 @@ def bench_serving(H, torch, runs, pool_size: int = 256):
         rng = np.random.default_rng([13054855, 5, 1 + i])
         pool_idx = rng.integers(0, pool_size, size=len(arrivals))
         print(f"[bench] serving {len(arrivals)} arrivals at {rate_hz:.0f} Hz over {duration_s:.0f} s in "
-              f"{srv.slots} slots", file=sys.stderr, flush=True)
+              f"{srv.n_slots} slots", file=sys.stderr, flush=True)
         stats = srv.serve(pool, arrivals, pool_idx, progress=lambda t, n, q: print(
             f"[bench] serving t={t:.0f}s served={n} queued={q}", file=sys.stderr, flush=True))
+        if stats["events_flagged"]:
+            raise RuntimeError(f"serving: {stats['events_flagged']} events flagged (flags {stats['status_flags_or']})")
         stats.update(workload=f"Poisson arrivals at {rate_hz:.0f} Hz for {duration_s:.0f} s, sizes as the batched "
-                              f"workload (pool of {pool_size} distinct events), 64 GiB accumulator budget "
-                              f"({srv.slots} slots in {srv.n_lanes} lanes), 512x256x64 int32",
-                     latency_definition="arrival -> candidate list complete on the device, status and first 64 "
-                                        "candidates on the host")
+                              f"workload (pool of {pool_size} distinct events), 64 GiB device budget "
+                              f"({srv.n_slots} resident slots, {len(srv.contexts)} launch contexts of up to "
+                              f"{srv.max_batch} events), 512x256x64 int32",
+                     latency_definition="arrival -> candidate list and hit lists complete in the event's device "
+                                        "slot, status and first 64 candidates on the host")
         results.append(stats)
     return results
 

@@ -168,7 +168,10 @@ int hough_plan_table(const hough_plan_t* plan, int32_t* out);
 int hough_prep(const hough_plan_t* plan, const hough_hits_t* hits, uint32_t* phi_out, void* ws,
                size_t ws_bytes, hough_status_t* st, hipStream_t stream);
 
-/* a1 + a2 -- vote: prep, then acc[l][k][b] (dev, fully overwritten; int32 or
+/* a1 + a2 -- vote (Sec. "Proposed Fast Tracking Algorithm", Fig. "hough"
+ * caption: each hit adds one count to every parameter bin it is compatible
+ * with; Sec. "Preliminary Results", curved-track paragraph: the third
+ * parameter d0): prep, then acc[l][k][b] (dev, fully overwritten; int32 or
  * int16 per acc_bits, b fastest).  The prepared hits stay in ws for
  * hough_assign.  If n > max_hits_per_event the call returns HOUGH_E_INVAL. */
 int hough_vote(const hough_plan_t* plan, const hough_hits_t* hits, void* acc, void* ws, size_t ws_bytes,
@@ -179,7 +182,10 @@ int hough_vote(const hough_plan_t* plan, const hough_hits_t* hits, void* acc, vo
 int hough_vote_prepared(const hough_plan_t* plan, void* acc, void* ws, size_t ws_bytes, hough_status_t* st,
                         hipStream_t stream);
 
-/* a3 -- peaks: bin (l,k,b) is a candidate iff acc >= threshold (>= 1) and,
+/* a3 -- peaks (Fig. "hough" caption: candidate tracks are the local maxima
+ * of the accumulated parameter space; the paper gives no neighbourhood, tie
+ * rule or threshold, these are readings): bin (l,k,b) is a candidate iff
+ * acc >= threshold (>= 1) and,
  * against each of its 3x3x3 neighbours j (phi0 cyclic, q/pT and d0 clipped),
  * acc > acc[j] when j precedes it and acc >= acc[j] otherwise; j precedes
  * when (l_j, k_j) < (l, k) lexicographically or j is bin b-1 (mod n_phi) of
@@ -190,7 +196,10 @@ int hough_vote_prepared(const hough_plan_t* plan, void* acc, void* ws, size_t ws
 int hough_peaks(const hough_plan_t* plan, const void* acc, int32_t threshold, hough_peak_t* peaks,
                 int32_t cap, void* ws, size_t ws_bytes, hough_status_t* st, hipStream_t stream);
 
-/* a4 -- assign: for each of the first min(listed, cap_peaks) candidates of the
+/* a4 -- assign (Sec. "Preliminary Results", fitting paragraph: the hits of
+ * each candidate are handed to a track fit; the paper does not say how hits
+ * are associated, this is the reading that a candidate owns exactly the hits
+ * that voted for its bin): for each of the first min(listed, cap_peaks) candidates of the
  * preceding hough_peaks call on this ws, the valid hits whose sample at (l, k)
  * falls in bin b (so each list has `votes` entries), ordered layer by layer
  * from the innermost layer, within a layer by the angle inside the bin

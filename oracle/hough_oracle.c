@@ -658,3 +658,55 @@ int64_t or_vote_cr(const or_cfg_t* g, int32_t n, const float* x, const float* y,
     }
     return votes;
 }
+
+/* Assignment with each hit's own radius (the step-7 lists for the step-11  */
+/* transform): for each candidate p = (l_p, k_p, b_p), the valid hits whose */
+/* per-hit-radius sample at (l_p, k_p) is valid and falls in phi0 bin b_p   */
+/* (so the list length equals the step-11 accumulator at the candidate),    */
+/* in the step-7 order: layer, angle inside the bin, hit index.             */
+int64_t or_assign_cr(const or_cfg_t* g, int32_t n, const float* x, const float* y, const uint8_t* layer,
+                     int32_t n_peaks, const int32_t* peaks, int64_t* offsets, int32_t* hit_idx,
+                     int64_t cap_pairs)
+{
+    int32_t M = or_angle_bits(g), F = g->frac_bits, p, h, L, i, m;
+    uint32_t mask = (M >= 32) ? 0xffffffffu : ((1u << M) - 1u);
+    uint32_t* phiM = (uint32_t*)malloc(sizeof(uint32_t) * (size_t)(n > 0 ? n : 1));
+    double* rad = (double*)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    uint8_t* ok = (uint8_t*)malloc((size_t)(n > 0 ? n : 1));
+    or_member_t* mem = (or_member_t*)malloc(sizeof(or_member_t) * (size_t)(n > 0 ? n : 1));
+    int64_t pos = 0;
+    for (h = 0; h < n; h++) {
+        int32_t X, Y;
+        ok[h] = (uint8_t)or_hit(x[h], y[h], layer[h], g->n_layers, &X, &Y);
+        phiM[h] = ok[h] ? or_azimuth(X, Y) >> (32 - M) : 0u;
+        rad[h] = ok[h] ? or_hit_radius(X, Y) : 0.0;
+    }
+    for (p = 0; p < n_peaks; p++) {
+        int32_t lp = peaks[4 * p], kp = peaks[4 * p + 1], bp = peaks[4 * p + 2];
+        double d = or_d0_centre(g, lp), c = or_curvature(g, kp);
+        offsets[p] = pos;
+        for (L = 0; L < g->n_layers; L++) {
+            m = 0;
+            for (h = 0; h < n; h++) {
+                int32_t E;
+                if (!ok[h] || layer[h] != L) continue;
+                if (!or_sample_cr(rad[h], c, d, M, &E)) continue;
+                if (bp != or_bin(phiM[h], E, M, F)) continue;
+                mem[m].rel = ((phiM[h] - (uint32_t)E) & mask) - ((uint32_t)bp << F);
+                mem[m].h = h;
+                m++;
+            }
+            qsort(mem, (size_t)m, sizeof(or_member_t), or_member_cmp);
+            for (i = 0; i < m; i++) {
+                if (pos < cap_pairs) hit_idx[pos] = mem[i].h;
+                pos++;
+            }
+        }
+    }
+    offsets[n_peaks] = pos;
+    free(phiM);
+    free(rad);
+    free(ok);
+    free(mem);
+    return pos;
+}

@@ -94,6 +94,8 @@ def load(path: str) -> C.CDLL:
     L.or_sample_cr.argtypes = [C.c_double, C.c_double, C.c_double, C.c_int32, P]
     L.or_hit_radius.restype = C.c_double; L.or_hit_radius.argtypes = [C.c_int32, C.c_int32]
     L.or_vote_cr.restype = C.c_int64; L.or_vote_cr.argtypes = [P, C.c_int32, P, P, P, P]
+    L.or_assign_cr.restype = C.c_int64
+    L.or_assign_cr.argtypes = [P, C.c_int32, P, P, P, C.c_int32, P, P, P, C.c_int64]
     L.or_vertex_radius.restype = C.c_double
     L.or_vertex_radius.argtypes = [C.c_int32, C.c_double, C.c_double, C.c_int32]
     L.or_vertex_vote.restype = C.c_int64
@@ -330,3 +332,16 @@ def vote_cr(cfg: Cfg, ev):
     acc = np.zeros((cfg.n_d0, cfg.n_qpt, cfg.n_phi), dtype=np.int32)
     nv = lib().or_vote_cr(cfg.ptr, x.shape[0], _p(x), _p(y), _p(lay), _p(acc))
     return acc, int(nv)
+
+
+def assign_cr(cfg: Cfg, ev, pk: np.ndarray, cap_pairs: int = 1 << 26):
+    """Hit lists of candidates of the per-hit-radius transform (same CSR layout and order as assign)."""
+    x, y, lay = _hits(ev)
+    pk = np.ascontiguousarray(pk, dtype=np.int32).reshape(-1, 4)
+    offs = np.zeros(pk.shape[0] + 1, dtype=np.int64)
+    total_guess = int(pk[:, 3].sum()) if pk.shape[0] else 0
+    cap = min(int(cap_pairs), max(total_guess, 1))
+    hit_idx = np.zeros(max(cap, 1), dtype=np.int32)
+    tot = int(lib().or_assign_cr(cfg.ptr, x.shape[0], _p(x), _p(y), _p(lay), pk.shape[0], _p(pk),
+                                 _p(offs), _p(hit_idx), cap))
+    return offs, hit_idx[: min(tot, cap)].copy(), tot

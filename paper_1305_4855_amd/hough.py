@@ -497,6 +497,11 @@ def hits_to_device(ev, device="cuda"):
     return x, y, lay, z
 
 
+def run_batch(plan: Plan, b: Batch, stream=None) -> None:
+    """hough_run_batch on a Batch whose pointers the caller set (e.g. outputs in slots of a larger arena)."""
+    _check(lib.hough_run_batch(plan.handle, C.byref(b), _stream(stream)), "hough_run_batch")
+
+
 class BatchBuffers:
     """Device buffers of a batch of up to `n_events` events (packed hits and strided outputs)."""
 

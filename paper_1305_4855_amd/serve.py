@@ -1,25 +1,26 @@
-"""Trigger-style serving loop with continuous batching.
+"""Trigger-style serving loop with continuous batching over resident slots.
 
-Events arrive as a Poisson process.  Admission is bounded by an accumulator
-budget in device memory: the budget divided by one event's accumulator gives
-the number of resident slots, each holding an accumulator together with that
-event's workspace, candidate list and CSR hit list (allocated once, reused
-without reallocation).  Slots are grouped into lanes; each lane owns a stream,
-pinned host staging buffers and one batched launch chain (`hough_run_batch`).
-Whenever a lane is free, the events that have arrived and are not yet admitted
-are admitted into it, oldest first, as many as its slots and its packed hit
-buffer hold: their hits are staged in pinned host memory and copied to the
-device on the lane's stream, the batched chain runs, and the per-event status
-plus the first `topk` candidates (in linear-index order) come back to pinned
-host memory.  Lanes run concurrently, so events copied in on one lane overlap
-the compute of another and the copy-out of a third (the event pipelining the
-paper proposes for its throughput figure, Sec. "Preliminary Results").
+Device memory holds two kinds of buffers, both allocated once:
 
-Latency of an event = time from its arrival to the moment its candidate list
-and hit lists are complete in device memory and its status and first
-candidates are on the host.  The full lists stay resident until the slot is
-reused (`on_complete` sees them): a flooded event has ~2e5 candidates, and
-copying every list back at the offered rate would exceed the host link.
+* resident slots: one event's accumulator, candidate list, CSR offsets, CSR hit list and status
+  (`slot_bytes`); as many slots as the memory budget holds after the launch contexts;
+* launch contexts: one stream each, with what one batched chain in flight needs besides the slots
+  (its workspace, the packed hits of its events, pinned host staging).
+
+Arriving events wait in a host queue, oldest first.  Whenever a launch context is idle and events are
+waiting, the oldest waiting events are admitted into it, as many as `max_batch`, the context's hit
+buffer and the longest run of free slots allow (the batched chain writes the events of one launch
+into consecutive slots).  Their hits are staged in pinned host memory and copied in on the context's
+stream, the batched chain (`hough_run_batch`) writes each event's results into its slot, and the
+statuses and first `topk` candidates come back to pinned host memory.  When a launch completes, its
+slots are handed to `on_complete` and then freed, while other launches are still running: admission
+is bounded by free slots (the memory budget) and idle contexts, never by another batch finishing.
+Contexts run concurrently, so the copy-in of one launch overlaps the compute of another and the
+copy-out of a third (the event pipelining of the paper's throughput figure, Sec. "Preliminary
+Results").
+
+Latency of an event = time from its arrival to the moment its candidate list and hit lists are
+complete in its device slot and its status and first candidates are on the host.
 """
 from __future__ import annotations
 
@@ -34,12 +35,26 @@ import torch
 from . import hough as H
 
 
+def slot_bytes(plan: H.Plan, cap_peaks: int, cap_pairs: int) -> int:
+    """Device bytes one resident event occupies: accumulator, candidates, CSR offsets and hit list, status."""
+    return plan.acc_bytes + cap_peaks * 16 + (cap_peaks + 1) * 4 + cap_pairs * 4 + H.STATUS_BYTES
+
+
+def context_bytes(plan: H.Plan, max_batch: int, cap_peaks: int, max_hits: int) -> int:
+    """Device bytes of one launch context: the batch workspace and the packed hits (x, y, layer, offsets)."""
+    return plan.batch_ws_bytes(max_batch, cap_peaks) + 9 * max_hits + 4 * (max_batch + 1)
+
+
 @dataclasses.dataclass
-class Lane:
+class Context:
     idx: int
-    bufs: H.BatchBuffers
     stream: torch.cuda.Stream
     done: torch.cuda.Event
+    ws: torch.Tensor
+    x: torch.Tensor
+    y: torch.Tensor
+    layer: torch.Tensor
+    hit_offsets: torch.Tensor
     x_h: torch.Tensor
     y_h: torch.Tensor
     lay_h: torch.Tensor
@@ -48,97 +63,147 @@ class Lane:
     top_h: torch.Tensor
     busy: bool = False
     ids: Optional[np.ndarray] = None
+    slot0: int = 0
     t_launch: float = 0.0
 
 
-def slot_bytes(plan: H.Plan, cap_peaks: int, cap_pairs: int) -> int:
-    """Device bytes one resident event occupies (accumulator, workspace, outputs, status)."""
-    return (plan.acc_bytes + plan.ws_bytes(cap_peaks) + cap_peaks * 16 + (cap_peaks + 1) * 4 + cap_pairs * 4 +
-            H.STATUS_BYTES)
+class Slots:
+    """Resident per-event outputs of `n` slots (consecutive slots form one launch's strided outputs)."""
+
+    def __init__(self, plan: H.Plan, n: int, cap_peaks: int, cap_pairs: int, device="cuda"):
+        c = plan.cfg
+        self.n, self.cap_peaks, self.cap_pairs = int(n), int(cap_peaks), int(cap_pairs)
+        self.acc = torch.empty((n, c.n_d0, c.n_qpt, c.n_phi), dtype=plan.acc_dtype, device=device)
+        self.peaks = torch.empty((n, cap_peaks, H.PEAK_INTS), dtype=torch.int32, device=device)
+        self.offsets = torch.empty((n, cap_peaks + 1), dtype=torch.int32, device=device)
+        self.hit_idx = torch.empty((n, cap_pairs), dtype=torch.int32, device=device)
+        self.status = torch.zeros((n, H.STATUS_BYTES // 4), dtype=torch.int32, device=device)
+        self.free = np.ones(n, dtype=bool)
+
+    def take(self, m: int) -> tuple:
+        """First run of at least one free slot, as long as possible up to m: (start, length), or (-1, 0)."""
+        f = self.free
+        if not f.any():
+            return -1, 0
+        d = np.diff(np.concatenate(([0], f.view(np.int8), [0])))
+        starts, ends = np.flatnonzero(d == 1), np.flatnonzero(d == -1)
+        lens = ends - starts
+        ok = np.flatnonzero(lens >= m)
+        i = int(ok[0]) if ok.size else int(np.argmax(lens))
+        s, n = int(starts[i]), int(min(m, lens[i]))
+        f[s:s + n] = False
+        return s, n
+
+    def release(self, s: int, n: int) -> None:
+        self.free[s:s + n] = True
+
+    def results(self, s: int) -> dict:
+        st = H.status_dict(self.status[s])
+        n = min(st["n_peaks"], self.cap_peaks)
+        npairs = min(st["n_pairs"], self.cap_pairs)
+        return dict(status=st, peaks=self.peaks[s, :n].cpu().numpy(),
+                    offsets=self.offsets[s, : n + 1].cpu().numpy().astype(np.int64),
+                    hit_idx=self.hit_idx[s, :npairs].cpu().numpy())
 
 
 class Server:
-    """Continuous-batching server over `acc_budget_bytes // plan.acc_bytes` resident slots split into
-    at most `max_lanes` lanes of at most `max_lane_events` slots each."""
+    """Continuous-batching server: `n_contexts` launch contexts of at most `max_batch` events each and
+    as many resident slots as `budget_bytes` holds after the contexts (at most `max_slots`)."""
 
-    def __init__(self, plan: H.Plan, threshold: int, acc_budget_bytes: int, max_lanes: int = 4,
-                 max_lane_events: int = 512, cap_peaks: int = 1 << 19, cap_pairs: int = 1 << 23,
-                 hits_per_slot: int = 8192, topk: int = 64):
+    def __init__(self, plan: H.Plan, threshold: int, budget_bytes: int, n_contexts: int = 4, max_batch: int = 64,
+                 cap_peaks: int = 1 << 19, cap_pairs: int = 1 << 24, hits_per_event: int = 8192, topk: int = 64,
+                 max_slots: Optional[int] = None):
         self.plan, self.threshold, self.topk = plan, int(threshold), int(topk)
         self.cap_peaks, self.cap_pairs = int(cap_peaks), int(cap_pairs)
-        slots = int(acc_budget_bytes // plan.acc_bytes)
-        if slots < 1:
-            raise ValueError("accumulator budget below one event's accumulator")
-        n_lanes = max(1, min(int(max_lanes), slots))
-        lane_events = max(1, min(int(max_lane_events), slots // n_lanes))
-        self.slot_bytes, self.lane_events, self.n_lanes = slot_bytes(plan, cap_peaks, cap_pairs), lane_events, n_lanes
-        # packed hit buffer of a lane: room for the largest event even if the lane holds one slot
-        self.max_total_hits = max(lane_events * int(hits_per_slot), plan.max_hits)
-        self.lanes: List[Lane] = []
-        for i in range(n_lanes):
-            bufs = H.BatchBuffers(plan, lane_events, self.max_total_hits, cap_peaks, cap_pairs)
-            n = self.max_total_hits
-            self.lanes.append(Lane(
-                idx=i, bufs=bufs, stream=torch.cuda.Stream(), done=torch.cuda.Event(),
-                x_h=torch.empty(n, dtype=torch.float32, pin_memory=True),
-                y_h=torch.empty(n, dtype=torch.float32, pin_memory=True),
-                lay_h=torch.empty(n, dtype=torch.uint8, pin_memory=True),
-                off_h=torch.empty(lane_events + 1, dtype=torch.int32, pin_memory=True),
-                status_h=torch.empty((lane_events, H.STATUS_BYTES // 4), dtype=torch.int32, pin_memory=True),
-                top_h=torch.empty((lane_events, max(1, topk), H.PEAK_INTS), dtype=torch.int32, pin_memory=True)))
+        self.max_batch = int(max_batch)
+        # packed hit buffer of a context: room for the largest event even when it is admitted alone
+        self.max_ctx_hits = max(self.max_batch * int(hits_per_event), plan.max_hits)
+        self.slot_bytes = slot_bytes(plan, cap_peaks, cap_pairs)
+        self.context_bytes = context_bytes(plan, self.max_batch, cap_peaks, self.max_ctx_hits)
+        n_slots = (int(budget_bytes) - int(n_contexts) * self.context_bytes) // self.slot_bytes
+        if max_slots is not None:
+            n_slots = min(n_slots, int(max_slots))
+        if n_slots < 1:
+            raise ValueError("memory budget below one launch context per stream plus one resident slot")
+        self.budget_bytes = int(budget_bytes)
+        self.slots = Slots(plan, int(n_slots), cap_peaks, cap_pairs)
+        self.contexts: List[Context] = []
+        nh = self.max_ctx_hits
+        for i in range(int(n_contexts)):
+            self.contexts.append(Context(
+                idx=i, stream=torch.cuda.Stream(), done=torch.cuda.Event(),
+                ws=torch.empty(plan.batch_ws_bytes(self.max_batch, cap_peaks), dtype=torch.uint8, device="cuda"),
+                x=torch.zeros(nh, dtype=torch.float32, device="cuda"),
+                y=torch.zeros(nh, dtype=torch.float32, device="cuda"),
+                layer=torch.zeros(nh, dtype=torch.uint8, device="cuda"),
+                hit_offsets=torch.zeros(self.max_batch + 1, dtype=torch.int32, device="cuda"),
+                x_h=torch.empty(nh, dtype=torch.float32, pin_memory=True),
+                y_h=torch.empty(nh, dtype=torch.float32, pin_memory=True),
+                lay_h=torch.empty(nh, dtype=torch.uint8, pin_memory=True),
+                off_h=torch.empty(self.max_batch + 1, dtype=torch.int32, pin_memory=True),
+                status_h=torch.empty((self.max_batch, H.STATUS_BYTES // 4), dtype=torch.int32, pin_memory=True),
+                top_h=torch.empty((self.max_batch, max(1, topk), H.PEAK_INTS), dtype=torch.int32,
+                                  pin_memory=True)))
 
     @property
-    def slots(self) -> int:
-        return self.n_lanes * self.lane_events
+    def n_slots(self) -> int:
+        return self.slots.n
 
-    # ------------------------------------------------------------------ one lane
-    def _launch(self, lane: Lane, ids: np.ndarray, pool_ids: np.ndarray, pool, now: float) -> None:
+    @property
+    def resident_bytes(self) -> int:
+        return self.slots.n * self.slot_bytes + len(self.contexts) * self.context_bytes
+
+    # ------------------------------------------------------------------ one launch
+    def _launch(self, ctx: Context, ids: np.ndarray, s0: int, pool_ids: np.ndarray, pool, now: float) -> None:
         evs = [pool[i] for i in pool_ids]
-        sizes = np.fromiter((e.n for e in evs), dtype=np.int64, count=len(evs))
-        offs = np.zeros(len(evs) + 1, dtype=np.int32)
-        np.cumsum(sizes, out=offs[1:])
-        n = int(offs[-1])
-        if n > self.max_total_hits:
-            raise RuntimeError("admitted events exceed the lane's hit buffer")
-        if n:
-            lane.x_h.numpy()[:n] = np.concatenate([e.x for e in evs])
-            lane.y_h.numpy()[:n] = np.concatenate([e.y for e in evs])
-            lane.lay_h.numpy()[:n] = np.concatenate([e.layer for e in evs])
-        lane.off_h.numpy()[: len(evs) + 1] = offs
-        b = lane.bufs
         m = len(evs)
-        with torch.cuda.stream(lane.stream):
+        offs = np.zeros(m + 1, dtype=np.int32)
+        np.cumsum(np.fromiter((e.n for e in evs), dtype=np.int64, count=m), out=offs[1:])
+        n = int(offs[-1])
+        if n > self.max_ctx_hits:
+            raise RuntimeError("admitted events exceed the context's hit buffer")
+        if n:
+            ctx.x_h.numpy()[:n] = np.concatenate([e.x for e in evs])
+            ctx.y_h.numpy()[:n] = np.concatenate([e.y for e in evs])
+            ctx.lay_h.numpy()[:n] = np.concatenate([e.layer for e in evs])
+        ctx.off_h.numpy()[: m + 1] = offs
+        S = self.slots
+        sl = slice(s0, s0 + m)
+        with torch.cuda.stream(ctx.stream):
             if n:
-                b.x[:n].copy_(lane.x_h[:n], non_blocking=True)
-                b.y[:n].copy_(lane.y_h[:n], non_blocking=True)
-                b.layer[:n].copy_(lane.lay_h[:n], non_blocking=True)
-            b.hit_offsets[: m + 1].copy_(lane.off_h[: m + 1], non_blocking=True)
-            b.run(self.threshold, lane.stream, n_events=m)
-            lane.status_h[:m].copy_(b.status[:m], non_blocking=True)
+                ctx.x[:n].copy_(ctx.x_h[:n], non_blocking=True)
+                ctx.y[:n].copy_(ctx.y_h[:n], non_blocking=True)
+                ctx.layer[:n].copy_(ctx.lay_h[:n], non_blocking=True)
+            ctx.hit_offsets[: m + 1].copy_(ctx.off_h[: m + 1], non_blocking=True)
+            b = H.Batch(H._ptr(ctx.x), H._ptr(ctx.y), None, H._ptr(ctx.layer), H._ptr(ctx.hit_offsets), m,
+                        self.threshold, self.cap_peaks, self.cap_pairs, H._ptr(S.acc[sl]), H._ptr(S.peaks[sl]),
+                        H._ptr(S.offsets[sl]), H._ptr(S.hit_idx[sl]), H._ptr(ctx.ws), ctx.ws.numel(),
+                        H._ptr(S.status[sl]), None)
+            H.run_batch(self.plan, b, ctx.stream)
+            ctx.status_h[:m].copy_(S.status[sl], non_blocking=True)
             if self.topk:
-                lane.top_h[:m].copy_(b.peaks[:m, : self.topk], non_blocking=True)
-            lane.done.record(lane.stream)
-        lane.busy, lane.ids, lane.t_launch = True, ids, now
+                ctx.top_h[:m].copy_(S.peaks[sl, : self.topk], non_blocking=True)
+            ctx.done.record(ctx.stream)
+        ctx.busy, ctx.ids, ctx.slot0, ctx.t_launch = True, ids, s0, now
 
     # ------------------------------------------------------------------ the loop
     def serve(self, pool, arrival_s: np.ndarray, pool_idx: np.ndarray,
-              on_complete: Optional[Callable[[Lane, np.ndarray, np.ndarray], None]] = None,
+              on_complete: Optional[Callable[["Server", Context, np.ndarray, np.ndarray], None]] = None,
               progress: Optional[Callable[[float, int, int], None]] = None, progress_every_s: float = 10.0) -> Dict:
         """Serve events arriving at `arrival_s` (seconds from the start, increasing), each a copy of
-        `pool[pool_idx[i]]`.  Paced in wall-clock time.  Returns latency and throughput figures.
-        `on_complete(lane, ids, pool_ids)` runs when a lane's batch is done, before the lane is reused;
-        `progress(t, served, queued)` runs every `progress_every_s` seconds."""
+        `pool[pool_idx[i]]`, paced in wall-clock time.  `on_complete(server, ctx, ids, pool_ids)` runs
+        when a launch is done, while its events' results are still in slots ctx.slot0 + j;
+        `progress(t, served, queued)` runs every `progress_every_s` seconds.  Returns latency and
+        throughput figures."""
         N = len(arrival_s)
         sizes = np.fromiter((e.n for e in pool), dtype=np.int64, count=len(pool))
         done_t = np.full(N, np.nan)
-        flags_or = 0
-        votes = 0
-        candidates = 0
+        flags_or, flagged, votes, candidates = 0, 0, 0, 0
         pending: collections.deque = collections.deque()
-        nxt = 0
-        served = 0
-        batch_sizes = []
-        max_batch_hits = 0
+        nxt, served = 0, 0
+        batch_sizes: List[int] = []
+        max_batch_hits, max_slots_used, slots_short = 0, 0, 0
+        S = self.slots
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         next_report = progress_every_s
@@ -152,39 +217,46 @@ class Server:
                 pending.extend(range(nxt, k))
                 nxt = k
             progressed = False
-            for lane in self.lanes:
-                if lane.busy and lane.done.query():
+            for ctx in self.contexts:
+                if ctx.busy and ctx.done.query():
                     tdone = time.perf_counter() - t0
-                    m = len(lane.ids)
-                    st = lane.status_h[:m].numpy()
-                    done_t[lane.ids] = tdone
+                    m = len(ctx.ids)
+                    st = ctx.status_h[:m].numpy()
+                    done_t[ctx.ids] = tdone
                     votes += int(st.view(np.int64)[:, 1].sum())
                     candidates += int(st[:, 4].sum())
-                    flags_or |= int(np.bitwise_or.reduce(st[:, 5])) if m else 0
+                    fl = st[:, 5]
+                    flags_or |= int(np.bitwise_or.reduce(fl)) if m else 0
+                    flagged += int(np.count_nonzero(fl))
                     if on_complete is not None:
-                        on_complete(lane, lane.ids, pool_idx[lane.ids])
+                        on_complete(self, ctx, ctx.ids, pool_idx[ctx.ids])
+                    S.release(ctx.slot0, m)
                     served += m
-                    lane.busy = False
+                    ctx.busy = False
                     progressed = True
-            for lane in self.lanes:
-                if not lane.busy and pending:
-                    # oldest first, as many as the lane's slots and hit buffer hold
-                    ids_l, hits = [], 0
-                    while pending and len(ids_l) < self.lane_events:
-                        h = sizes[pool_idx[pending[0]]]
-                        if ids_l and hits + h > self.max_total_hits:
-                            break
-                        ids_l.append(pending.popleft())
-                        hits += int(h)
-                    ids = np.asarray(ids_l, dtype=np.int64)
-                    m = len(ids)
-                    batch_sizes.append(m)
-                    max_batch_hits = max(max_batch_hits, hits)
-                    self._launch(lane, ids, pool_idx[ids], pool, time.perf_counter() - t0)
-                    progressed = True
-            if not progressed and nxt < N and not pending and all(not l.busy for l in self.lanes):
-                # idle until the next arrival
-                wait = arrival_s[nxt] - (time.perf_counter() - t0)
+            for ctx in self.contexts:
+                if ctx.busy or not pending:
+                    continue
+                # oldest first, as many as max_batch and the context's hit buffer hold
+                want, hits = 0, 0
+                for q in range(min(len(pending), self.max_batch)):
+                    h = int(sizes[pool_idx[pending[q]]])
+                    if want and hits + h > self.max_ctx_hits:
+                        break
+                    want += 1
+                    hits += h
+                s0, m = S.take(want)
+                if m == 0:
+                    slots_short += 1
+                    break  # no free slot: wait for a launch to complete
+                ids = np.fromiter((pending.popleft() for _ in range(m)), dtype=np.int64, count=m)
+                batch_sizes.append(m)
+                max_batch_hits = max(max_batch_hits, int(sizes[pool_idx[ids]].sum()))
+                max_slots_used = max(max_slots_used, int(S.n - S.free.sum()))
+                self._launch(ctx, ids, s0, pool_idx[ids], pool, time.perf_counter() - t0)
+                progressed = True
+            if not progressed and nxt < N and not pending and all(not c.busy for c in self.contexts):
+                wait = arrival_s[nxt] - (time.perf_counter() - t0)  # idle until the next arrival
                 if wait > 2e-4:
                     time.sleep(wait - 1e-4)
         lat = done_t - arrival_s
@@ -197,9 +269,11 @@ class Server:
             latency_ms_p99=round(float(np.percentile(lat, 99)) * 1e3, 4),
             latency_ms_max=round(float(np.max(lat)) * 1e3, 4),
             mean_batch=round(float(np.mean(batch_sizes)), 2) if batch_sizes else 0.0,
-            batches=len(batch_sizes), max_batch_hits=max_batch_hits, candidates=candidates, status_flags_or=flags_or,
-            lanes=self.n_lanes, slots=self.slots, slot_bytes=self.slot_bytes,
-            resident_bytes=self.slots * self.slot_bytes)
+            batches=len(batch_sizes), max_batch_hits=max_batch_hits, candidates=candidates,
+            status_flags_or=flags_or, events_flagged=flagged, contexts=len(self.contexts), max_batch=self.max_batch,
+            slots=S.n, max_slots_in_use=max_slots_used, admissions_short_of_slots=slots_short,
+            slot_bytes=self.slot_bytes, context_bytes=self.context_bytes, resident_bytes=self.resident_bytes,
+            budget_bytes=self.budget_bytes)
 
 
 def poisson_arrivals(rate_hz: float, duration_s: float, seed: int = 13054855) -> np.ndarray:

@@ -116,14 +116,16 @@ def test_fit_hand_made_lists(H, oracle_mod, n_hits):
     assert (got[len(lists):] == 7.0).all()  # rows past the listed candidates are not written
 
 
-def test_fit_batch_equals_oracle(H, oracle_mod):
+@pytest.mark.parametrize("max_hits", [4096, 32767])
+def test_fit_batch_equals_oracle(H, oracle_mod, max_hits):
     """hough_fit_batch after the batched chain: uneven events (one without hits, one cut by the
-    pair capacity), each event's rows equal the oracle's fit of its own lists; the batch's plan
-    allows 32767 hits per event, so the coordinates are gathered from memory (not staged in LDS)."""
+    pair capacity), each event's rows equal the oracle's fit of its own lists.  A plan of at most
+    16384 hits per event stages each event's coordinates in LDS (k_fit_res, per-event hit base);
+    one of 32767 gathers them from memory (k_fit)."""
     O = oracle_mod
     cfg = configs.small_variant(configs.C2, n_phi=256, n_qpt=64, n_d0=4)
     events = [synth.make_event(cfg.with_(n_tracks=t), i) for i, t in enumerate((30, 0, 55, 12))]
-    plan = H.Plan(cfg, max_hits=32767)
+    plan = H.Plan(cfg, max_hits=max_hits)
     cap_pairs = 3000  # the 55-track event has about 6600 pairs: its later lists are cut
     bufs = H.BatchBuffers(plan, len(events), max(sum(e.n for e in events), 1), cap_peaks=1 << 12, cap_pairs=cap_pairs)
     bufs.load(events)

@@ -220,7 +220,8 @@ def test_large_grid_batch_full_size_equals_oracle(H, oracle_mod):
     events = [synth.make_event(cfg, i) for i in range(8)]
     print(f"[zvote] full-size large-grid batch: hits {[e.n for e in events]}", flush=True)
     plan = H.Plan(cfg, max_hits=cfg.max_hits_per_event)
-    cap_peaks, cap_pairs = 1 << 20, 1 << 25
+    # about 1.5M candidates and 1.2e7 pairs per event
+    cap_peaks, cap_pairs = 1 << 21, 1 << 25
     bufs = H.BatchBuffers(plan, len(events), sum(e.n for e in events), cap_peaks, cap_pairs)
     bufs.load(events)
     bufs.run(cfg.threshold)

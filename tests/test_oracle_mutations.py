@@ -55,6 +55,12 @@ MUTATIONS = {
     "cr_round_down": ("*E = (int32_t)((t + ((int64_t)1 << (s - 1))) >> s);", "*E = (int32_t)(t >> s);"),
     "cr_isqrt_step": ("            root = (root >> 1) + bit;", "            root = (root >> 1) + bit + 1;"),
     "cr_layer_radius": ("        r = or_hit_radius(X, Y);", "        r = g->r_cm[layer[h]];"),
+    "cr_assign_layer_radius": ("if (!or_sample_cr(rad[h], c, d, M, &E)) continue;",
+                               "if (!or_sample_cr(g->r_cm[L], c, d, M, &E)) continue;"),
+    "cr_assign_wrong_bin": ("if (bp != or_bin(phiM[h], E, M, F)) continue;",
+                            "if ((bp + 1) % g->n_phi != or_bin(phiM[h], E, M, F)) continue;"),
+    "cr_assign_no_angle_order": ("            qsort(mem, (size_t)m, sizeof(or_member_t), or_member_cmp);\n            for (i = 0; i < m; i++) {\n                if (pos < cap_pairs) hit_idx[pos] = mem[i].h;\n                pos++;\n            }\n        }\n    }\n    offsets[n_peaks] = pos;\n    free(phiM);\n    free(rad);",
+                                 "            for (i = 0; i < m; i++) {\n                if (pos < cap_pairs) hit_idx[pos] = mem[i].h;\n                pos++;\n            }\n        }\n    }\n    offsets[n_peaks] = pos;\n    free(phiM);\n    free(rad);"),
     "cr_sqrt_operand": ("b = (int64_t)or_isqrt((uint64_t)(((int64_t)1 << 60) - a * a));",
                         "b = (int64_t)or_isqrt((uint64_t)(((int64_t)1 << 60) + a * a));"),
     "vote_columns_transposed": ("int32_t l = cols[2 * i], k = cols[2 * i + 1], hh, E;",

@@ -1090,3 +1090,115 @@ def test_cr_vote_uses_each_hits_radius(oracle_mod):
         diff += int(np.count_nonzero(a_cr != a_l))
         total += n_l
     assert total > 500 and diff <= total // 100
+
+
+def _cr_event(cfg, seed):
+    return synth.make_event(cfg, seed)
+
+
+def test_cr_assign_lengths_equal_cr_accumulator(oracle_mod):
+    """Per-hit-radius lists: on a smeared event of the paper's detector, every candidate's list
+    holds exactly as many hits as the per-hit-radius accumulator has votes in its bin (and so do
+    arbitrary bins, candidates or not): the lists follow each hit's own radius, which the
+    accumulator is pinned to above."""
+    O = oracle_mod
+    cfg = configs.C7.with_(n_phi=128, n_qpt=64, n_tracks=40)
+    ev = _cr_event(cfg, 5)
+    g = O.Cfg(cfg)
+    acc, nv = O.vote_cr(g, ev)
+    n, pk = O.peaks(g, acc, cfg.threshold)
+    assert n > 20
+    offs, hit_idx, tot = O.assign_cr(g, ev, pk)
+    np.testing.assert_array_equal(np.diff(offs), pk[:, 3])
+    assert tot == int(pk[:, 3].sum()) == hit_idx.size
+    # every nonzero bin of a few columns, as if each were a candidate
+    rng = np.random.default_rng(71)
+    cols = rng.integers(0, cfg.n_qpt, size=6)
+    bins = np.array([(0, k, b, acc[0, k, b]) for k in cols for b in range(cfg.n_phi) if acc[0, k, b] > 0],
+                    dtype=np.int32)
+    offs2, _, _ = O.assign_cr(g, ev, bins)
+    np.testing.assert_array_equal(np.diff(offs2), bins[:, 3])
+
+
+def test_cr_assign_brute_force_membership_and_order(oracle_mod):
+    """Brute force on a small event: for every candidate and hit, the hit's own integer radius and
+    the per-hit-radius sample give its angle relative to the candidate's window; membership is an
+    interval test on the unshifted angle, the order (layer, angle inside the window, hit index) a
+    Python sort."""
+    O = oracle_mod
+    cfg = configs.C7.with_(n_phi=64, n_qpt=64, n_tracks=30)
+    ev = _cr_event(cfg, 6)
+    g = O.Cfg(cfg)
+    M = O.angle_bits(g)
+    W = 1 << cfg.frac_bits
+    acc, _ = O.vote_cr(g, ev)
+    n, pk = O.peaks(g, acc, 3)
+    pk = pk[:: max(1, n // 60)]  # about 60 candidates, spread over the grid
+    n = pk.shape[0]
+    assert n > 20
+    offs, hit_idx, _ = O.assign_cr(g, ev, pk)
+    # lists with several hits of one layer exist, so the order inside a layer is tested
+    assert any(len(set(ev.layer[hit_idx[offs[p]:offs[p + 1]]])) < offs[p + 1] - offs[p] for p in range(n))
+    info = []
+    for h in range(ev.n):
+        ok, X, Y = O.hit(float(ev.x[h]), float(ev.y[h]), int(ev.layer[h]), cfg.n_layers)
+        info.append((ok, O.azimuth(X, Y) >> (32 - M) if ok else 0, O.hit_radius(X, Y) if ok else 0.0))
+    for p in range(n):
+        l, k, b, v = (int(t) for t in pk[p])
+        members = []
+        for h, (ok, phiM, r) in enumerate(info):
+            if not ok:
+                continue
+            okE, E = O.sample_cr(r, O.curvature(g, k), O.d0_centre(g, l), M)
+            if not okE:
+                continue
+            rel = (phiM - E) % (1 << M) - b * W
+            if 0 <= rel < W:
+                members.append((int(ev.layer[h]), rel, h))
+        want = [h for _, _, h in sorted(members)]
+        assert len(want) == v
+        np.testing.assert_array_equal(hit_idx[offs[p]:offs[p + 1]], want)
+
+
+def test_cr_assign_rotation_covariance(oracle_mod):
+    """A quarter turn of every hit ((x, y) -> (-y, x), exact) moves each list to the candidate
+    n_phi / 4 bins further on, in the same order."""
+    O = oracle_mod
+    cfg = configs.C7.with_(n_phi=128, n_qpt=64, n_tracks=25)
+    ev = _cr_event(cfg, 7)
+    g = O.Cfg(cfg)
+    acc, _ = O.vote_cr(g, ev)
+    n, pk = O.peaks(g, acc, cfg.threshold)
+    rot = synth.Event(x=(-ev.y).astype(np.float32), y=ev.x.copy(), z=None, layer=ev.layer, track_id=ev.track_id,
+                      truth=ev.truth)
+    pk_rot = pk.copy()
+    pk_rot[:, 2] = (pk[:, 2] + cfg.n_phi // 4) % cfg.n_phi
+    o0, h0, _ = O.assign_cr(g, ev, pk)
+    o1, h1, _ = O.assign_cr(g, rot, pk_rot)
+    np.testing.assert_array_equal(o0, o1)
+    np.testing.assert_array_equal(h0, h1)
+
+
+def test_cr_assign_track_hits_in_its_list(oracle_mod):
+    """A noise-free smeared prompt track whose parameters sit at a bin centre: the candidate at its
+    generating bin lists the track's hits (all ten layers, one hit each, innermost first)."""
+    O = oracle_mod
+    cfg = configs.C7.with_(n_phi=256, n_qpt=64, n_tracks=1, smear_xy_cm=0.004)
+    g = O.Cfg(cfg)
+    M = O.angle_bits(g)
+    k, b = 40, 77
+    # the bin centres from exact rational arithmetic (not the oracle's own centres)
+    qpt = float(Fraction(cfg.qpt_min) + Fraction(2 * k + 1, 2) * (Fraction(cfg.qpt_max) - Fraction(cfg.qpt_min))
+                / cfg.n_qpt)
+    phi0 = (b + 0.5) * 2 * math.pi / cfg.n_phi
+    rng = np.random.default_rng(3)
+    x, y, _, lay, tid = synth._helix_hits(rng, cfg, np.array([np.sign(qpt)]), np.array([abs(qpt)]),
+                                          np.array([phi0]), np.array([0.0]), np.zeros(1), np.zeros(1))
+    ev = synth.Event(x=x.astype(np.float32), y=y.astype(np.float32), z=None, layer=lay.astype(np.uint8),
+                     track_id=tid.astype(np.int32), truth={})
+    acc, _ = O.vote_cr(g, ev)
+    assert acc[0, k, b] == ev.n == cfg.n_layers
+    offs, hit_idx, _ = O.assign_cr(g, ev, np.array([[0, k, b, acc[0, k, b]]], dtype=np.int32))
+    lst = hit_idx[offs[0]:offs[1]]
+    assert sorted(lst.tolist()) == list(range(ev.n))
+    assert list(ev.layer[lst]) == list(range(cfg.n_layers))
