@@ -375,6 +375,23 @@ typedef struct {
 size_t hough_batch_ws_bytes(const hough_plan_t* plan, int32_t n_events, int32_t cap_peaks);
 int hough_run_batch(const hough_plan_t* plan, const hough_batch_t* batch, hipStream_t stream);
 
+/* hough_run_batch for callers that cannot allocate device memory (code under
+ * hipGraph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the workspace is a scratch array the library holds in device memory, one
+ * copy of HOUGH_NOALLOC_SCRATCH_BYTES per GPU, kept until the process ends
+ * (its address is looked up when a plan is created on that GPU).  The call
+ * allocates nothing.  batch->ws must be NULL and ws_bytes 0 (HOUGH_E_INVAL
+ * otherwise); hough_batch_ws_bytes(plan, n_events, cap_peaks) must not
+ * exceed HOUGH_NOALLOC_SCRATCH_BYTES (HOUGH_E_SMALL_WS otherwise; e.g. a few
+ * 512x256x64 events or one 1024x512x128 event).  HOUGH_E_HIP if the scratch
+ * array of the plan's GPU could not be located.  Every call on one GPU uses
+ * the same array, which keeps the last call's contents (the chain clears
+ * what it needs zeroed itself): calls that overlap in time on one GPU (on
+ * different streams or from different host threads) race and must be
+ * serialised by the caller.  Results equal hough_run_batch's. */
+#define HOUGH_NOALLOC_SCRATCH_BYTES (64 << 20)
+int hough_run_batch_noalloc(const hough_plan_t* plan, const hough_batch_t* batch, hipStream_t stream);
+
 /* Track fit (as hough_fit) of every listed candidate of every event of a
  * batch after hough_run_batch: hits, offsets, hit lists and statuses taken
  * from `batch`; out (dev) [n_events][cap_peaks][4] doubles.  Results equal

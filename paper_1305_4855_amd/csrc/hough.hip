@@ -53,11 +53,13 @@
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <climits>
 #include <cmath>
 #include <cstdint>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 
 #include "hough.h"
@@ -3100,6 +3102,36 @@ VGrid vertex_vgrid(const hough_vertex_plan* vp, int32_t cap, int32_t n_events = 
 }  // namespace
 
 // ====================================================================== C ABI
+// Workspace of hough_run_batch_noalloc: one copy per GPU, held until the process ends.
+static __device__ __align__(256) char scratch[HOUGH_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxScratchDevices = 64;
+std::atomic<void*> g_scratch_dev[kMaxScratchDevices];
+std::mutex g_scratch_mu;
+
+// With `device` current: look up the device address of that GPU's copy of `scratch` once and keep it.
+int noalloc_scratch_init(int device) {
+    if (device < 0 || device >= kMaxScratchDevices) return HOUGH_E_UNSUPPORTED;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_dev[device].load(std::memory_order_acquire)) return HOUGH_OK;
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) {
+        (void)hipGetLastError();  // a later launch check must not report this failure
+        return HOUGH_E_HIP;
+    }
+    g_scratch_dev[device].store(ptr, std::memory_order_release);
+    return HOUGH_OK;
+}
+
+void* noalloc_scratch_get(int device) {
+    if (device < 0 || device >= kMaxScratchDevices) return nullptr;
+    return g_scratch_dev[device].load(std::memory_order_acquire);
+}
+
+}  // namespace
+
 extern "C" {
 
 const char* hough_strerror(int code) {
@@ -3184,6 +3216,8 @@ int hough_plan_create(const hough_geometry_t* geom, const hough_grid_t* grid, ho
         delete p;
         return HOUGH_E_HIP;
     }
+    // set-up of the no-alloc entry point on this device (its failure only disables that entry point)
+    (void)noalloc_scratch_init(p->device);
     p->n_layers = geom->n_layers;
     for (int L = 0; L < p->n_layers; ++L) {
         p->r[L] = geom->r_cm[L];
@@ -3484,17 +3518,22 @@ size_t hough_batch_ws_bytes(const hough_plan_t* p, int32_t n_events, int32_t cap
     return batch_header_bytes(n_events) + (size_t)n_events * ws_layout(p, cap_peaks).total;
 }
 
-int hough_run_batch(const hough_plan_t* p, const hough_batch_t* b, hipStream_t stream) {
-    if (!p || !b) return HOUGH_E_INVAL;
+}  // extern "C"
+
+namespace {
+
+// The batched chain on the workspace `ws_base` of `ws_bytes` bytes (the caller's, or the scratch array).
+int run_batch_on(const hough_plan_t* p, const hough_batch_t* b, void* ws_base, size_t ws_bytes,
+                 hipStream_t stream) {
     if (b->n_events < 1 || b->cap_peaks < 1 || b->cap_pairs < 1 || b->threshold < 1) return HOUGH_E_INVAL;
     if (!b->hit_offsets || !b->x || !b->y || !b->layer || !b->acc || !b->peaks || !b->offsets || !b->hit_idx ||
-        !b->ws || !b->status)
+        !ws_base || !b->status)
         return HOUGH_E_INVAL;
     if (b->zvote && (!p->zvote || !b->z)) return p->zvote ? HOUGH_E_INVAL : HOUGH_E_UNSUPPORTED;
     const WsLayout L = ws_layout(p, b->cap_peaks);
     const size_t hdr = batch_header_bytes(b->n_events);
-    if (b->ws_bytes < hdr + (size_t)b->n_events * L.total) return HOUGH_E_SMALL_WS;
-    char* ws = static_cast<char*>(b->ws);
+    if (ws_bytes < hdr + (size_t)b->n_events * L.total) return HOUGH_E_SMALL_WS;
+    char* ws = static_cast<char*>(ws_base);
     int32_t* queue = reinterpret_cast<int32_t*>(ws);
     int32_t* order = reinterpret_cast<int32_t*>(ws + 256);
     char* ev_ws = ws + hdr;
@@ -3518,6 +3557,29 @@ int hough_run_batch(const hough_plan_t* p, const hough_batch_t* b, hipStream_t s
         launch_zvote(p, ev, b->n_events, b->z, b->layer, b->peaks, b->cap_peaks, b->offsets, b->hit_idx,
                      b->cap_pairs, b->status, b->zvote, stream);
     return launch_status();
+}
+
+}  // namespace
+
+extern "C" {
+
+int hough_run_batch(const hough_plan_t* p, const hough_batch_t* b, hipStream_t stream) {
+    if (!p || !b) return HOUGH_E_INVAL;
+    return run_batch_on(p, b, b->ws, b->ws_bytes, stream);
+}
+
+// The workspace of hough_run_batch_noalloc: a file-scope device array, one copy per GPU.  Host code
+// never uses its name as an address: the device address of each GPU's copy is looked up once per
+// device (noalloc_scratch_init, called by hough_plan_create with the plan's device current) and kept.
+int hough_run_batch_noalloc(const hough_plan_t* p, const hough_batch_t* b, hipStream_t stream) {
+    if (!p || !b) return HOUGH_E_INVAL;
+    if (b->ws || b->ws_bytes) return HOUGH_E_INVAL;
+    if (b->n_events < 1 || b->cap_peaks < 1) return HOUGH_E_INVAL;
+    if (hough_batch_ws_bytes(p, b->n_events, b->cap_peaks) > (size_t)HOUGH_NOALLOC_SCRATCH_BYTES)
+        return HOUGH_E_SMALL_WS;
+    void* scratch_ptr = noalloc_scratch_get(p->device);
+    if (!scratch_ptr) return HOUGH_E_HIP;
+    return run_batch_on(p, b, scratch_ptr, (size_t)HOUGH_NOALLOC_SCRATCH_BYTES, stream);
 }
 
 struct hough_graph {

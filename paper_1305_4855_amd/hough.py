@@ -61,6 +61,8 @@ class Batch(C.Structure):
 
 
 STATUS_BYTES = 32
+# workspace limit of hough_run_batch_noalloc (the library's per-GPU scratch array)
+NOALLOC_SCRATCH_BYTES = 64 << 20
 PEAK_INTS = 4
 HOUGH_F_EVENT_TOO_LARGE = 4
 
@@ -117,6 +119,7 @@ def _load() -> C.CDLL:
     L.hough_plan_set_vote_events.restype = C.c_int; L.hough_plan_set_vote_events.argtypes = [P, P, P]
     L.hough_batch_ws_bytes.restype = S; L.hough_batch_ws_bytes.argtypes = [P, C.c_int32, C.c_int32]
     L.hough_run_batch.restype = C.c_int; L.hough_run_batch.argtypes = [P, C.POINTER(Batch), P]
+    L.hough_run_batch_noalloc.restype = C.c_int; L.hough_run_batch_noalloc.argtypes = [P, C.POINTER(Batch), P]
     L.hough_batch_graph_create.restype = C.c_int
     L.hough_batch_graph_create.argtypes = [P, C.POINTER(Batch), P, C.POINTER(C.c_void_p)]
     L.hough_graph_launch.restype = C.c_int; L.hough_graph_launch.argtypes = [P, P]
@@ -129,7 +132,8 @@ lib = _load()
 EXPORTED = ["hough_plan_create", "hough_plan_destroy", "hough_acc_bytes", "hough_event_ws_bytes",
             "hough_angle_bits", "hough_plan_table", "hough_prep", "hough_vote", "hough_vote_prepared", "hough_peaks",
             "hough_assign", "hough_zvote", "hough_fit", "hough_plan_arclen_table", "hough_strerror", "hough_plan_set_tuning", "hough_plan_get_tuning", "hough_plan_set_vote_events",
-            "hough_batch_ws_bytes", "hough_run_batch", "hough_batch_graph_create", "hough_graph_launch",
+            "hough_batch_ws_bytes", "hough_run_batch", "hough_run_batch_noalloc", "hough_batch_graph_create",
+            "hough_graph_launch",
             "hough_graph_destroy", "hough_fit_batch", "hough_vote_cr", "hough_vertex_plan_create", "hough_vertex_plan_destroy", "hough_vertex_set_groups",
             "hough_vertex_get_groups", "hough_vertex_vote_ws_bytes", "hough_vertex_peaks_ws_bytes",
             "hough_vertex_vote", "hough_vertex_peaks", "hough_vertex_table", "hough_vertex_batch_vote_ws_bytes",
@@ -553,6 +557,14 @@ class BatchBuffers:
     def run(self, threshold: int, stream=None, n_events: Optional[int] = None, zvote: bool = True) -> None:
         b = self.struct(threshold, n_events, zvote)
         _check(lib.hough_run_batch(self.plan.handle, C.byref(b), _stream(stream)), "hough_run_batch")
+
+    def run_noalloc(self, threshold: int, stream=None, n_events: Optional[int] = None, zvote: bool = True) -> None:
+        """The same chain through hough_run_batch_noalloc: the library's scratch array is the workspace
+        (this object's `ws` is not used)."""
+        b = self.struct(threshold, n_events, zvote)
+        b.ws, b.ws_bytes = None, 0
+        _check(lib.hough_run_batch_noalloc(self.plan.handle, C.byref(b), _stream(stream)),
+               "hough_run_batch_noalloc")
 
     def run_fit(self, stream=None, n_events: Optional[int] = None) -> None:
         """Circle fit of every listed candidate of every event (after run)."""
