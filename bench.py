@@ -18,6 +18,7 @@ import argparse
 import hashlib
 import json
 import os
+import subprocess
 import sys
 import time
 
@@ -40,16 +41,38 @@ def src_hash() -> str:
     return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
 
 
+def physical_cores() -> int:
+    """Physical cores of the host (lscpu: distinct (core, socket) pairs); the logical CPU count
+    when lscpu is not there."""
+    try:
+        out = subprocess.run(["lscpu", "-p=CORE,SOCKET"], capture_output=True, text=True, timeout=10).stdout
+        pairs = {ln for ln in out.splitlines() if ln and not ln.startswith("#")}
+        if pairs:
+            return len(pairs)
+    except (OSError, subprocess.SubprocessError):
+        pass
+    return os.cpu_count() or 1
+
+
 def cpu_baseline(cfg, ev):
+    """The oracle as it stands on the host cores: one full event of the dense workload (vote with
+    OpenMP over d0 planes on every physical core, peaks and assign single-threaded), then the same
+    event with one thread; and the oracle chain on the paper detector's curved events against the
+    number of tracks."""
     from oracle import oracle as O
     O.build()
     g = O.Cfg(cfg)
-    t0 = time.perf_counter()
-    acc, nv = O.vote(g, ev)
-    n, pk = O.peaks(g, acc, cfg.threshold)
-    O.assign(g, ev, pk)
-    dt = time.perf_counter() - t0
-    cores = int(os.environ.get("OMP_NUM_THREADS") or os.cpu_count() or 1)
+    cores = physical_cores()
+    runs = {}
+    for threads in (cores, 1):
+        used = O.set_threads(threads)
+        t0 = time.perf_counter()
+        acc, nv = O.vote(g, ev)
+        n, pk = O.peaks(g, acc, cfg.threshold)
+        O.assign(g, ev, pk)
+        runs[used] = time.perf_counter() - t0
+    O.set_threads(cores)
+    dt = runs[max(runs)]
     # the same oracle chain on the paper detector's curved events against the number of tracks (the
     # quantity of the paper's CPU/GPU timing figure; the GPU side is in the quality section)
     from paper_1305_4855_amd import configs, synth
@@ -63,10 +86,13 @@ def cpu_baseline(cfg, ev):
         n7, p7 = O.peaks(g7, a7, c7.threshold)
         O.assign(g7, e7, p7)
         vs_tracks.append({"tracks": ntr, "hits": e7.n, "oracle_ms_per_event": round((time.perf_counter() - t1) * 1e3, 2)})
-    return {"value": round(1.0 / dt, 4), "unit": "events/s", "cores": cores, "kind": "oracle",
+    return {"value": round(1.0 / dt, 4), "unit": "events/s", "cores": max(runs), "kind": "oracle",
             "sample": (f"1 full event of the same workload ({ev.n} hits, {nv} hit-votes, {n} candidates): "
-                       f"vote on {cores} OpenMP threads, peaks and assign single-threaded; {dt:.1f} s"),
+                       f"vote on {max(runs)} OpenMP threads (the host's physical cores), peaks and assign "
+                       f"single-threaded; {dt:.1f} s"),
             "hit_votes_per_s": round(nv / dt, 1),
+            "one_thread": {"value": round(1.0 / runs[1], 4), "unit": "events/s", "cores": 1,
+                           "seconds": round(runs[1], 2)},
             "paper_detector_vs_tracks": vs_tracks}
 
 
@@ -78,7 +104,7 @@ def bench_roofline_probe():
     from paper_1305_4855_amd import probe
 
     blocks = CUS * 4
-    lds = {k: probe.lds(k, blocks) for k in ("atomic", "read32", "write32", "read128")}
+    lds = {k: probe.lds(k, blocks) for k in ("atomic", "read32", "write32", "read128", "atomic_rtn", "vote_pair")}
     out = {}
     for k, r in lds.items():
         out[f"lds_{k}"] = {"lane_ops_per_s": round(r["lane_ops_per_s"], 1),
@@ -139,7 +165,7 @@ def bench_batched(H, torch, n_events: int, reps: int):
     cfg = configs.C3
     events = [synth.make_event(cfg, i) for i in range(n_events)]
     plan = H.Plan(cfg, max_hits=cfg.max_hits_per_event)
-    tuning = tune.apply(plan)
+    tuning = tune.apply(plan, "batch")
     total = sum(e.n for e in events)
     stream = torch.cuda.current_stream()
     bufs, cap_peaks, cap_pairs = sized_batch(H, torch, plan, events, cfg.threshold, stream)
@@ -224,11 +250,12 @@ def bench_large_grid(H, torch, reps: int):
     cot(theta) x z0 (128 x 128) vote of every candidate.  The r-z stage's share is the
     difference between the chain with and without it.  The vertex transform of all events'
     candidates (batched vote and peaks) is timed on its own."""
-    from paper_1305_4855_amd import configs, synth
+    from paper_1305_4855_amd import configs, synth, tune
 
     cfg = configs.C4
     events = [synth.make_event(cfg, i) for i in range(cfg.n_events)]
     plan = H.Plan(cfg, max_hits=cfg.max_hits_per_event)
+    tuning = tune.apply(plan, "batch")
     total = sum(e.n for e in events)
     stream = torch.cuda.current_stream()
     bufs, cap_peaks, cap_pairs = sized_batch(H, torch, plan, events, cfg.threshold, stream, 1 << 20, 1 << 24)
@@ -241,6 +268,21 @@ def bench_large_grid(H, torch, reps: int):
         b.record(stream)
         torch.cuda.synchronize()
         times[with_z] = a.elapsed_time(b) / reps
+    # the plain per-event chain (prep, vote, peaks, assign, r-z stage) over the same events
+    ev_bufs = H.EventBuffers(plan, cap_peaks=cap_peaks, cap_pairs=cap_pairs)
+    dev_hits = []
+    for e in events:
+        x, y, lay, z = H.hits_to_device(e)
+        dev_hits.append((x, y, lay, z, H.make_hits(x, y, lay, z)))
+    ev_bufs.run(dev_hits[0][4], cfg.threshold, stream)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    for h in dev_hits:
+        ev_bufs.run(h[4], cfg.threshold, stream)
+    b.record(stream)
+    torch.cuda.synchronize()
+    plain_ms = a.elapsed_time(b)
+    del ev_bufs, dev_hits
     # the second transform (vertex space) of every event's candidates, batched
     vp = H.VertexPlan.of(plan)
     vb = H.VertexBatchBuffers(vp, len(events), cap_peaks, 1 << 16)
@@ -267,16 +309,48 @@ def bench_large_grid(H, torch, reps: int):
     return {
         "workload": f"batch of {len(events)} events (c4): 600 prompt tracks + 2 displaced vertices, 20% noise, "
                     f"1024x512x128 int16, then 128x128 cot(theta) x z0 vote per candidate",
-        "hits": total, "hit_votes": votes, "candidates": cands, "pairs": pairs, **flags,
+        "hits": total, "hit_votes": votes, "candidates": cands, "pairs": pairs, **flags, "tuning": tuning,
         "cap_peaks": cap_peaks, "cap_pairs": cap_pairs,
         "ms_per_batch": round(times[True], 3), "ms_per_batch_without_zvote": round(times[False], 3),
         "events_per_s": round(len(events) / times[True] * 1e3, 2),
         "events_per_s_without_zvote": round(len(events) / times[False] * 1e3, 2),
+        "events_per_s_plain": round(len(events) / plain_ms * 1e3, 2),
+        "speedup_batched_vs_plain": round(plain_ms / times[True], 3),
         "zvote_ms_per_event": round(zv_ms / len(events), 4),
         "vertex_ms_per_batch": round(vertex_ms, 3), "vertex_ms_per_event": round(vertex_ms / len(events), 4),
         "vertex_votes": vertex_votes, "vertex_candidates": vertex_cands,
         "vertex_gvotes_per_s": round(vertex_votes / (vertex_ms * 1e-3) / 1e9, 1),
     }
+
+
+def bench_small(H, torch, steps: int):
+    """The small single event (c1: 10 prompt tracks, 256 x 256 phi0 x q/pT, threshold 8), plain
+    chain per event: bound by launch latency, not by the GPU's throughput."""
+    from paper_1305_4855_amd import configs, synth
+
+    cfg = configs.C1
+    ev = synth.make_event(cfg, 0)
+    plan = H.Plan(cfg, max_hits=4096)
+    bufs = H.EventBuffers(plan, cap_peaks=1 << 14, cap_pairs=1 << 16)
+    x, y, lay, _ = H.hits_to_device(ev)
+    hits = H.make_hits(x, y, lay)
+    stream = torch.cuda.current_stream()
+    for _ in range(20):
+        bufs.run(hits, cfg.threshold, stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        bufs.run(hits, cfg.threshold, stream)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    st = H.status_dict(bufs.status)
+    if st["flags"]:
+        raise RuntimeError(f"small event: status flags {st['flags']}")
+    return {"workload": "single small event (c1): 10 prompt tracks, 100 hits, 256x256 int32, threshold 8",
+            "hits": ev.n, "hit_votes": st["n_votes"], "candidates": st["n_peaks"], "pairs": st["n_pairs"],
+            "events_per_s": round(1.0 / dt, 1), "us_per_event": round(dt * 1e6, 2),
+            "hit_votes_per_s": round(st["n_votes"] / dt, 1),
+            "note": "prep, vote, peaks and assign launched per event; bound by launch latency"}
 
 
 def bench_vertex(H, torch, reps: int):
@@ -433,7 +507,7 @@ def bench_serving(H, torch, runs, pool_size: int = 256):
     cfg = configs.C5
     pool = [synth.make_event(cfg, i) for i in range(pool_size)]
     plan = H.Plan(cfg, max_hits=cfg.max_hits_per_event)
-    tune.apply(plan)
+    tune.apply(plan, "batch")
     # per-event capacities hold the pool's largest event (2000 tracks: about 2.4e5 candidates and
     # 1.3e7 hit-candidate pairs), so no served list is cut
     srv = serve.Server(plan, cfg.threshold, budget_bytes=cfg.hbm_budget_bytes, n_contexts=4, max_batch=64,
@@ -469,7 +543,7 @@ def bench_plain(H, torch, args):
     cfg = configs.C2
     ev = synth.make_event(cfg, 0)
     plan = H.Plan(cfg, max_hits=16384)
-    tune.apply(plan)
+    tuning = tune.apply(plan, "single")
     bufs = H.EventBuffers(plan, cap_peaks=1 << 19, cap_pairs=1 << 24)
     x, y, lay, _ = H.hits_to_device(ev)
     hits = H.make_hits(x, y, lay)
@@ -585,6 +659,7 @@ def bench_plain(H, torch, args):
                    "tracks": 1000, "noise_frac": 0.2, "displaced_frac": 0.1, "hits": ev.n,
                    "grid": [cfg.n_phi, cfg.n_qpt, cfg.n_d0], "acc": "int32", "threshold": cfg.threshold},
         "hit_votes_per_s": round(st["n_votes"] * events_per_s, 1),
+        "tuning": tuning,
         "per_event": {"hit_votes": st["n_votes"], "candidates": st["n_peaks"], "pairs": st["n_pairs"],
                       "bad_hits": st["n_bad_hits"]},
         "stages_ms": {k: round(v, 5) for k, v in zip(("prep", "vote", "peaks", "assign"), stage_ms)},
@@ -644,6 +719,8 @@ def main() -> int:
     if not args.no_plain:
         out = bench_plain(H, torch, args)
         torch.cuda.empty_cache()
+    if not args.no_plain:
+        out["small_event"] = bench_small(H, torch, steps=500)
     if not args.no_batched:
         out["batched"] = bench_batched(H, torch, args.batch_events, reps=10)
     if not args.no_large_grid:

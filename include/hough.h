@@ -134,6 +134,8 @@ typedef struct {
     int32_t vote_cols;         /* window-table vote: columns per work item, 4..64, a power
                                   of two (0 = automatic)                                 */
     int32_t assign_blocks;     /* assignment workgroups per event (0 = automatic)        */
+    int32_t prep_rows;         /* window-table prep: phi0 rows per workgroup, a power of two
+                                  16..256 (0 = automatic)                               */
 } hough_tuning_t;
 
 /* Create a plan on the current HIP device: validates geometry and grid and
@@ -265,10 +267,27 @@ int hough_fit(const hough_plan_t* plan, const hough_hits_t* hits, const int32_t*
  * int32, fully overwritten; st (dev): n_hits, n_bad_hits, n_votes set.  The
  * plan's sample table is not used (the layer only decides validity).
  * Requires acc_bits 32 (HOUGH_E_UNSUPPORTED otherwise).  ALU-bound: every
- * sample is computed, no table.  hough_peaks applies unchanged; hough_assign
- * (which follows the layer table) does not. */
+ * sample is computed, no table.  hough_peaks applies unchanged; the lists
+ * come from hough_assign_cr (hough_assign follows the layer table). */
 int hough_vote_cr(const hough_plan_t* plan, const hough_hits_t* hits, int32_t* acc, hough_status_t* st,
                   hipStream_t stream);
+
+/* Assignment under the per-hit radius (Sec. "Preliminary Results": the hits
+ * of each candidate go on to the fit; here for the transform of
+ * hough_vote_cr): for each of the first min(listed, cap_peaks) candidates of
+ * the preceding hough_peaks call on `ws` (run on the accumulator that
+ * hough_vote_cr wrote for the same hits), the valid hits whose per-hit-radius
+ * sample at (l, k) falls in bin b (so each list has `votes` entries), in the
+ * order of hough_assign: layer, angle inside the bin, hit index.  CSR output,
+ * capacity handling and st->n_pairs as for hough_assign.  ws_cr (dev): a
+ * second workspace of hough_assign_cr_ws_bytes(plan, cap_peaks, cap_pairs)
+ * bytes (a bin -> candidate map, fill counters and sort keys).  The lists
+ * are collected by repeating the vote (same integer arithmetic), so the call
+ * costs about as much as hough_vote_cr.  hough_fit applies to its output. */
+size_t hough_assign_cr_ws_bytes(const hough_plan_t* plan, int32_t cap_peaks, int32_t cap_pairs);
+int hough_assign_cr(const hough_plan_t* plan, const hough_hits_t* hits, const hough_peak_t* peaks, int32_t cap_peaks,
+                    int32_t* offsets, int32_t* hit_idx, int32_t cap_pairs, void* ws, size_t ws_bytes, void* ws_cr,
+                    size_t ws_cr_bytes, hough_status_t* st, hipStream_t stream);
 
 /* Second Hough transform over the candidates (Sec. "New Trigger Capabilities"
  * and its displaced-jet figures: tracks from one displaced vertex are maxima

@@ -19,7 +19,8 @@ extern "C" {
 #endif
 
 /* LDS rate.  kind: 0 = atomic add without return (ds_add_u32), 1 = 32-bit read, 2 = 32-bit write,
- * 3 = 128-bit read.  `blocks` workgroups of 1024 threads, each wave issuing `iters` iterations of
+ * 3 = 128-bit read, 4 = atomic add with return (ds_add_rtn_u32), 5 = vote pair: an atomic add with
+ * return followed by an atomic subtract of the same word (counted as one lane-operation).  `blocks` workgroups of 1024 threads, each wave issuing `iters` iterations of
  * 16 independent conflict-free instructions (8 for kind 3: 64 consecutive words per instruction).
  * out: (dev) caller-owned, blocks * 1024 words, zero on entry; a kernel writes to it only if its own
  * self-check fails, so a non-zero word after the call means a wrong result.

@@ -37,6 +37,7 @@
  * All functions here are pinned; none is "parity unpinned".
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -709,4 +710,12 @@ int64_t or_assign_cr(const or_cfg_t* g, int32_t n, const float* x, const float* 
     free(ok);
     free(mem);
     return pos;
+}
+
+/* Threads of the OpenMP loops above (the vote over d0 planes); for timing the oracle at a chosen
+ * thread count.  Returns the count in effect. */
+int or_set_threads(int n)
+{
+    if (n > 0) omp_set_num_threads(n);
+    return omp_get_max_threads();
 }

@@ -94,6 +94,7 @@ def load(path: str) -> C.CDLL:
     L.or_sample_cr.argtypes = [C.c_double, C.c_double, C.c_double, C.c_int32, P]
     L.or_hit_radius.restype = C.c_double; L.or_hit_radius.argtypes = [C.c_int32, C.c_int32]
     L.or_vote_cr.restype = C.c_int64; L.or_vote_cr.argtypes = [P, C.c_int32, P, P, P, P]
+    L.or_set_threads.restype = C.c_int; L.or_set_threads.argtypes = [C.c_int]
     L.or_assign_cr.restype = C.c_int64
     L.or_assign_cr.argtypes = [P, C.c_int32, P, P, P, C.c_int32, P, P, P, C.c_int64]
     L.or_vertex_radius.restype = C.c_double
@@ -345,3 +346,8 @@ def assign_cr(cfg: Cfg, ev, pk: np.ndarray, cap_pairs: int = 1 << 26):
     tot = int(lib().or_assign_cr(cfg.ptr, x.shape[0], _p(x), _p(y), _p(lay), pk.shape[0], _p(pk),
                                  _p(offs), _p(hit_idx), cap))
     return offs, hit_idx[: min(tot, cap)].copy(), tot
+
+
+def set_threads(n: int) -> int:
+    """Threads of the oracle's OpenMP loops (0: leave as is); returns the count in effect."""
+    return int(lib().or_set_threads(int(n)))

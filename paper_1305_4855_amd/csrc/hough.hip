@@ -136,6 +136,7 @@ struct hough_plan {
     bool pt;         // window-table path: prefix-count table per event, table vote and assignment
     int pt_bpl;      // bins per lane of the table vote (n_phi / 64)
     int pt_row;      // entries per window-count row (n_phi + pt_bpl + 2, rounded up to 8)
+    bool stage;      // bin values fit 16 bits: the peak marker keeps each group's candidate values
 };
 
 namespace {
@@ -143,7 +144,7 @@ namespace {
 // ------------------------------------------------------------------ layout
 struct WsLayout {
     size_t misc, phi32, lay, cell_start, tmp_phi, tmp_key, sorted_phi, sorted_h, ptab, gtab;
-    size_t flags, grp_count, grp_votes, grp_off, grp_voff, peak_voff, total;
+    size_t flags, grp_count, grp_votes, grp_off, grp_voff, stage, peak_voff, total;
 };
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
@@ -156,6 +157,10 @@ int peak_group_lanes(const hough_plan* p) {
 int64_t peak_groups(const hough_plan* p) {
     return p->n_bins / ((int64_t)kStrip * peak_group_lanes(p));
 }
+
+// Candidate values the peak marker keeps per group (16-bit, in candidate order): three per four
+// strips; a group with more candidates is written from the accumulator instead.
+__host__ __device__ __forceinline__ int stage_cap(int group_lanes) { return group_lanes * 3 / 4; }
 
 // Workspace of one event.  `misc` holds the number of candidates listed by the peaks pass (int32).
 WsLayout ws_layout(const hough_plan* p, int32_t max_peaks) {
@@ -178,6 +183,7 @@ WsLayout ws_layout(const hough_plan* p, int32_t max_peaks) {
     L.grp_votes = take(4 * (size_t)(peak_groups(p) + 1));
     L.grp_off = take(4 * (size_t)(peak_groups(p) + 1));
     L.grp_voff = take(8 * (size_t)(peak_groups(p) + 1));
+    L.stage = take(p->stage ? 2 * (size_t)peak_groups(p) * stage_cap(peak_group_lanes(p)) : 0);
     L.peak_voff = take(8 * (size_t)(max_peaks > 0 ? max_peaks : 1));  // last: sized by max_peaks
     L.total = o;
     return L;
@@ -261,12 +267,13 @@ __device__ __forceinline__ int64_t block_inclusive_scan(int64_t v, int64_t* wsum
 
 struct WsOff {
     size_t misc, phi32, lay, cell_start, tmp_phi, tmp_key, sorted_phi, sorted_h, ptab, gtab;
-    size_t flags, grp_count, grp_votes, grp_off, grp_voff, peak_voff;
+    size_t flags, grp_count, grp_votes, grp_off, grp_voff, stage, peak_voff;
 };
 
 WsOff ws_off(const WsLayout& L) {
-    return WsOff{L.misc,     L.phi32,  L.lay,       L.cell_start, L.tmp_phi, L.tmp_key, L.sorted_phi, L.sorted_h,
-                 L.ptab,     L.gtab,   L.flags,     L.grp_count,  L.grp_votes, L.grp_off, L.grp_voff,  L.peak_voff};
+    return WsOff{L.misc,  L.phi32, L.lay,       L.cell_start, L.tmp_phi,  L.tmp_key, L.sorted_phi, L.sorted_h,
+                 L.ptab,  L.gtab,  L.flags,     L.grp_count,  L.grp_votes, L.grp_off, L.grp_voff,  L.stage,
+                 L.peak_voff};
 }
 
 // ------------------------------------------------------------------ batch set-up
@@ -553,6 +560,202 @@ __global__ __launch_bounds__(256) void k_prep_rank(Events ev, int n_cells, int c
     at<int32_t>(w, O.sorted_h)[c0 + rank] = h;
 }
 
+// ------------------------------------------------------------------ prep for the window tables
+// Plans with the window tables (see below) sort the hits and build both tables in one pass over a
+// fine histogram: one workgroup per (event, layer L, chunk of R consecutive phi0 rows of the
+// layer), R = min(n_phi, 128).  With W = 2^F angles per row, the workgroup counts the layer's hits
+// of every M-bit angle of its rows and of the row after them (the next chunk's first row, or the
+// turn's first row) in LDS (16-bit counters, two per word, rows padded to W/2 + 1 words so that
+// reads of one phase down consecutive rows hit distinct banks), scans the counts into prefix
+// counts P_L(x) (relative to the layer's first sorted hit; the layer's hits below the chunk come
+// from a count over all hits), writes PT and GT for its rows and every phase, and places each of
+// its hits at sorted position P_L(angle) (+ its rank among the hits of the same angle by hit
+// index: tied hits are collected in LDS and ranked there).  Chunk 0 also writes the window-count
+// entries past n_phi (the turn repeated) and the layer's start; workgroup 0 of the event writes the
+// status.  Every workgroup reads the event's prepared hits (k_prep_hits) twice from L2.
+constexpr int kFineRows = 128;     // phi0 rows per chunk
+constexpr int kFineTieCap = 1024;  // tied hits a workgroup ranks in LDS (more: all tied hits ranked from memory)
+constexpr int kFineUnroll = 16;    // hits per thread loaded at once
+
+__global__ __launch_bounds__(kScanThreads) void k_prep_fine(Events ev, int n_layers, int cell_bits, int M, int F,
+                                                            int n_phi, int row, int R, int n_chunks, LayerTable LT,
+                                                            char* __restrict__ ws, WsOff O,
+                                                            hough_status_t* __restrict__ st_base) {
+    extern __shared__ uint32_t fine_lds[];
+    __shared__ int64_t wsum[kScanThreads / 64];
+    __shared__ int32_t s_vc[kMaxLayers];  // valid (l, k) columns per layer: votes of one of its hits
+    __shared__ int32_t n_tie;
+    const int e = blockIdx.y;
+    const int L = blockIdx.x / n_chunks;
+    const int c = blockIdx.x - L * n_chunks;
+    int h0, n;
+    event_hits(ev, e, h0, n);
+    const int n_given = n;
+    if (n > ev.max_hits) n = 0;
+    char* w = event_ws(ws, ev, e);
+    const uint32_t* phi32 = at<uint32_t>(w, O.phi32);
+    const uint8_t* lay = at<uint8_t>(w, O.lay);
+    const int tid = threadIdx.x;
+    const int W = 1 << F;
+    const int wpr = W / 2 + 1;  // words per padded row
+    const int nwords = (R + 1) * wpr;
+    uint32_t* hist = fine_lds;
+    uint32_t* ties = fine_lds + nwords;  // (chunk angle << 16) | hit
+    const int row0 = c * R;
+    const uint32_t a_lo = (uint32_t)row0 << F;
+    const uint32_t a_hi = a_lo + ((uint32_t)R << F);
+    const uint32_t next_row = (uint32_t)((row0 + R) & (n_phi - 1));  // the row after the chunk
+    const int sh = 32 - M;
+    const bool counter = blockIdx.x == 0;
+    for (int i = tid; i < nwords; i += kScanThreads) hist[i] = 0u;
+    if (tid < kMaxLayers) s_vc[tid] = tid < n_layers ? LT.valid_cols[tid] : 0;
+    if (tid == 0) n_tie = 0;
+    __syncthreads();
+    // the hits are read kFineUnroll per thread at a time, all loads in flight together; an event of
+    // at most kScanThreads * kFineUnroll hits stays in registers for the placing pass
+    uint8_t lh[kFineUnroll];
+    uint32_t ah[kFineUnroll];
+    auto load_hits = [&](int hb) {
+#pragma unroll
+        for (int j = 0; j < kFineUnroll; ++j) {
+            const int h = hb + j * kScanThreads + tid;
+            lh[j] = h < n ? lay[h] : (uint8_t)0xFE;  // 0xFE: no hit, 0xFF: bad hit
+            ah[j] = h < n ? phi32[h] >> sh : 0u;
+        }
+    };
+    const bool resident = n <= kScanThreads * kFineUnroll;
+    int before = 0, bad = 0, below = 0, mine = 0;
+    int64_t votes = 0;  // workgroup 0: the event's hit-votes, one table lookup per hit (no atomics)
+    for (int hb = 0; hb < n; hb += kScanThreads * kFineUnroll) {
+        load_hits(hb);
+#pragma unroll
+        for (int j = 0; j < kFineUnroll; ++j) {
+            const int lj = lh[j];
+            bad += lj == 0xFF ? 1 : 0;
+            before += lj < L ? 1 : 0;
+            if (counter && lj < n_layers) votes += s_vc[lj];
+            if (lj != L) continue;
+            ++mine;
+            const uint32_t a = ah[j];
+            below += a < a_lo ? 1 : 0;
+            const uint32_t col = a & (uint32_t)(W - 1);
+            const uint32_t inc = 1u << (16 * (col & 1u));
+            if (a >= a_lo && a < a_hi) atomicAdd(&hist[(int)((a - a_lo) >> F) * wpr + (int)(col >> 1)], inc);
+            if ((a >> F) == next_row) atomicAdd(&hist[R * wpr + (int)(col >> 1)], inc);
+        }
+    }
+    int64_t t1, t2, t_votes = 0;
+    block_inclusive_scan((int64_t)before | ((int64_t)bad << 32), wsum, &t1);
+    block_inclusive_scan((int64_t)below | ((int64_t)mine << 32), wsum, &t2);
+    if (counter) block_inclusive_scan(votes, wsum, &t_votes);  // uniform per workgroup
+    const int base = (int)(t1 & 0xFFFFFFFFll), n_bad = (int)(t1 >> 32);
+    const int cbase = (int)(t2 & 0xFFFFFFFFll), n_L = (int)(t2 >> 32);
+    // exclusive scan of the counts in angle order -> prefix counts (16 bits: differences stay exact)
+    const int T = (R + 1) << F;
+    const int k = ((T + kScanThreads - 1) / kScanThreads + 1) & ~1;
+    const int lo = min(T, tid * k), hi = min(T, lo + k);
+    int32_t sum = 0;
+    for (int i = lo; i < hi; i += 2) {
+        const uint32_t v = hist[(i >> F) * wpr + ((i & (W - 1)) >> 1)];
+        sum += (int32_t)(v & 0xFFFFu) + (int32_t)(v >> 16);
+    }
+    int64_t tot;
+    uint32_t pre = (uint32_t)(cbase + (block_inclusive_scan(sum, wsum, &tot) - sum));
+    for (int i = lo; i < hi; i += 2) {
+        const int wi = (i >> F) * wpr + ((i & (W - 1)) >> 1);
+        const uint32_t v = hist[wi];
+        const uint32_t c0 = v & 0xFFFFu, c1 = v >> 16;
+        hist[wi] = (pre & 0xFFFFu) | ((pre + c0) << 16);
+        pre += c0 + c1;
+    }
+    __syncthreads();
+    auto P16 = [&](int rl, int cl) -> uint32_t {
+        const uint32_t v = hist[rl * wpr + (cl >> 1)];
+        return (cl & 1) ? v >> 16 : v & 0xFFFFu;
+    };
+    // tables: PT[L][r][j] = P(jW + r), GT[L][r][j] = P((j + 1)W + r) - P(jW + r), two rows per store
+    uint32_t* pt = reinterpret_cast<uint32_t*>(at<uint16_t>(w, O.ptab) + (size_t)L * W * n_phi);
+    uint32_t* gt = reinterpret_cast<uint32_t*>(at<uint16_t>(w, O.gtab) + (size_t)L * W * row);
+    const int RP = R / 2;
+    for (int t = tid; t < W * RP; t += kScanThreads) {
+        const int r = t / RP, jp = t - r * RP;
+        const uint32_t p0 = P16(2 * jp, r), p1 = P16(2 * jp + 1, r), p2 = P16(2 * jp + 2, r);
+        pt[((size_t)r * n_phi + row0) / 2 + jp] = (p0 & 0xFFFFu) | (p1 << 16);
+        gt[((size_t)r * row + row0) / 2 + jp] = ((p1 - p0) & 0xFFFFu) | ((p2 - p1) << 16);
+    }
+    if (c == 0) {  // window counts past the turn repeat its first rows
+        const int EP = (row - n_phi) / 2;
+        for (int t = tid; t < W * EP; t += kScanThreads) {
+            const int r = t / EP, jp = t - r * EP;
+            const uint32_t p0 = P16(2 * jp, r), p1 = P16(2 * jp + 1, r), p2 = P16(2 * jp + 2, r);
+            gt[((size_t)r * row + n_phi) / 2 + jp] = ((p1 - p0) & 0xFFFFu) | ((p2 - p1) << 16);
+        }
+    }
+    // sorted positions of the chunk's hits
+    int32_t* sorted_h = at<int32_t>(w, O.sorted_h) + base;
+    for (int hb = 0; hb < n; hb += kScanThreads * kFineUnroll) {
+        if (!resident) load_hits(hb);
+#pragma unroll
+        for (int j = 0; j < kFineUnroll; ++j) {
+            const uint32_t a = ah[j];
+            if (lh[j] != L || a < a_lo || a >= a_hi) continue;
+            const int h = hb + j * kScanThreads + tid;
+            const uint32_t x = a - a_lo;
+            const int rl = (int)(x >> F), cl = (int)(x & (uint32_t)(W - 1));
+            const uint32_t p = P16(rl, cl);
+            const uint32_t pn = cl + 1 < W ? P16(rl, cl + 1) : P16(rl + 1, 0);
+            if (((pn - p) & 0xFFFFu) == 1u) {
+                sorted_h[p] = h;
+            } else {
+                const int q = atomicAdd(&n_tie, 1);
+                if (q < kFineTieCap) ties[q] = (x << 16) | (uint32_t)h;
+            }
+        }
+    }
+    __syncthreads();
+    const int nt = n_tie;
+    if (nt <= kFineTieCap) {
+        for (int i = tid; i < nt; i += kScanThreads) {
+            const uint32_t me = ties[i];
+            const uint32_t x = me >> 16, hh = me & 0xFFFFu;
+            int rank = 0;
+            for (int j = 0; j < nt; ++j) {
+                const uint32_t o = ties[j];
+                rank += ((o >> 16) == x && (o & 0xFFFFu) < hh) ? 1 : 0;
+            }
+            sorted_h[P16((int)(x >> F), (int)(x & (uint32_t)(W - 1))) + rank] = (int32_t)hh;
+        }
+    } else {  // too many tied hits for LDS: each ranks itself against the event's hits
+        for (int h = tid; h < n; h += kScanThreads) {
+            if (lay[h] != L) continue;
+            const uint32_t a = phi32[h] >> sh;
+            if (a < a_lo || a >= a_hi) continue;
+            const uint32_t x = a - a_lo;
+            const int rl = (int)(x >> F), cl = (int)(x & (uint32_t)(W - 1));
+            const uint32_t p = P16(rl, cl);
+            const uint32_t pn = cl + 1 < W ? P16(rl, cl + 1) : P16(rl + 1, 0);
+            if (((pn - p) & 0xFFFFu) == 1u) continue;
+            int rank = 0;
+            for (int j = 0; j < h; ++j) rank += (lay[j] == L && (phi32[j] >> sh) == a) ? 1 : 0;
+            sorted_h[p + rank] = h;
+        }
+    }
+    if (tid == 0 && c == 0) {
+        int32_t* cell_start = at<int32_t>(w, O.cell_start);
+        cell_start[L << cell_bits] = base;
+        if (L == n_layers - 1) cell_start[n_layers << cell_bits] = base + n_L;
+    }
+    if (counter && tid == 0) {
+        hough_status_t* st = st_base + e;
+        st->n_hits = n_given;
+        st->n_bad_hits = n_bad;
+        st->n_votes = t_votes;
+        st->n_peaks = 0;
+        st->flags = n_given > ev.max_hits ? HOUGH_F_EVENT_TOO_LARGE : 0;
+        st->n_pairs = 0;
+    }
+}
+
 // ------------------------------------------------------------------ window tables
 // Prefix counts of an event's sorted hits at every angle the vote and the assignment ask about.
 // With W = 2^F and P_L(x) = the number of valid hits of layer L whose M-bit angle is < x, extended
@@ -564,82 +767,7 @@ __global__ __launch_bounds__(256) void k_prep_rank(Events ev, int n_cells, int c
 // [PT[L][r][j], PT[L][r][j + 1]) of the layer.  A sample value E and a bin b of a column select the
 // window x = (E mod 2^M) + b W: the same phase r = E mod W for every bin, at j = (E mod 2^M) div W + b.
 // Window-count rows run `row` entries (past n_phi they repeat the turn) so that a lane of the vote
-// reads its bins without a wrap.
-// grid = (blocks over (layer, block of kPtPhases phases, pair of entries), events); a thread writes
-// entries j = 2 jp, 2 jp + 1 of both tables for kPtPhases phases.  P_L at an angle counts the hits of
-// the cells before the angle's cell plus those of its cell below the angle (a cell spans at least
-// one bin); each of the three cells involved is loaded once, eight sorted angles at a time.
-constexpr int kPtPhases = 16;
-
-struct PtCell {
-    int a, n_in;      // first sorted position and hit count of the cell
-    uint32_t e[8];    // its first eight sorted angles
-};
-
-__device__ __forceinline__ PtCell pt_cell(const int32_t* cs, int c, const uint32_t* __restrict__ sorted_phi) {
-    PtCell pc;
-    pc.a = cs[c];
-    pc.n_in = cs[c + 1] - pc.a;
-#pragma unroll
-    for (int i = 0; i < 8; ++i) pc.e[i] = pc.n_in > 0 ? sorted_phi[pc.a + min(i, pc.n_in - 1)] : 0u;
-    return pc;
-}
-
-// hits of the cell with angle < x
-__device__ __forceinline__ int pt_count_below(const PtCell& pc, uint32_t x, const uint32_t* __restrict__ sorted_phi) {
-    int cnt = 0;
-#pragma unroll
-    for (int i = 0; i < 8; ++i) cnt += (int)((i < pc.n_in) & (pc.e[i] < x));
-    if (pc.n_in > 8 && cnt == 8)
-        while (cnt < pc.n_in && sorted_phi[pc.a + cnt] < x) ++cnt;
-    return cnt;
-}
-
-__global__ __launch_bounds__(256) void k_ptab(Events ev, int n_layers, int cell_bits, int M, int F, int n_phi,
-                                              int row, int pairs_pad, char* __restrict__ ws, WsOff O) {
-    char* w = event_ws(ws, ev, blockIdx.y);
-    const int32_t* cell_start = at<int32_t>(w, O.cell_start);
-    const uint32_t* sorted_phi = at<uint32_t>(w, O.sorted_phi);
-    uint32_t* pt = at<uint32_t>(w, O.ptab);
-    uint32_t* gt = at<uint32_t>(w, O.gtab);
-    const int W = 1 << F;
-    const int n_rb = W / kPtPhases;
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    const int jp = t % pairs_pad;
-    const int rest = t / pairs_pad;
-    const int rb = rest % n_rb;
-    const int L = rest / n_rb;
-    if (L >= n_layers || 2 * jp >= row) return;
-    const int cpl = 1 << cell_bits;
-    const int32_t* cs = cell_start + L * cpl;
-    const int lay0 = cs[0];
-    const int n_L = cs[cpl] - lay0;
-    const int lp = M - F;  // log2 n_phi
-    // P_L at entries 2 jp + i, i = 0, 1, 2: the entry taken mod n_phi, plus n_L per full turn
-    PtCell c[3];
-    uint32_t xb[3];
-    int base[3];
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-        const int e = 2 * jp + i;
-        const int je = e & (n_phi - 1);
-        c[i] = pt_cell(cs, je >> (lp - cell_bits), sorted_phi);
-        xb[i] = (uint32_t)je << F;
-        base[i] = c[i].a - lay0 + (e / n_phi) * n_L;
-    }
-    const bool wp = 2 * jp < n_phi;  // entries of the prefix table
-    uint32_t* po = pt + ((size_t)L * W + (size_t)rb * kPtPhases) * (n_phi / 2) + jp;
-    uint32_t* go = gt + ((size_t)L * W + (size_t)rb * kPtPhases) * (row / 2) + jp;
-#pragma unroll 4
-    for (int q = 0; q < kPtPhases; ++q) {
-        const uint32_t r = (uint32_t)(rb * kPtPhases + q);
-        uint32_t P[3];
-#pragma unroll
-        for (int i = 0; i < 3; ++i) P[i] = (uint32_t)(base[i] + pt_count_below(c[i], xb[i] + r, sorted_phi));
-        if (wp) po[(size_t)q * (n_phi / 2)] = (P[0] & 0xFFFFu) | (P[1] << 16);
-        go[(size_t)q * (row / 2)] = ((P[1] - P[0]) & 0xFFFFu) | ((P[2] - P[1]) << 16);
-    }
-}
+// reads its bins without a wrap.  Both tables are written by k_prep_fine.
 
 // ------------------------------------------------------------------ vote
 __device__ __forceinline__ void lds_vote(uint32_t phi, uint32_t e, uint32_t mask, uint32_t lanebits,
@@ -858,9 +986,12 @@ __global__ __launch_bounds__(kVoteMaxThreads) void k_vote(Events ev, const int32
 // So the accumulator column is the sum over layers of one window-count row each, rotated by s: no
 // atomics, and every read is a run of consecutive entries.
 // One wave per column at a time: lane i owns the BPL bins [i BPL, (i + 1) BPL), the entries
-// [i0, i0 + BPL) with i0 = (s + i BPL) mod n_phi, loaded as BPL/2 + 1 dwords from the dword boundary
-// at or below i0 (the parity of i0 is that of s, the same for the whole wave); a byte permute with a
-// wave-uniform selector aligns the pairs.  Counts are kept as 16-bit pairs in 32-bit words: a plain
+// [i0, i0 + BPL) with i0 = (s + i BPL) mod n_phi.  A lane loads the BPL/2 dwords from the dword
+// boundary at or below i0 with 16-byte loads (consecutive lanes read consecutive bytes of the row,
+// so a wave reads one contiguous stretch per layer); when i0 is odd (the parity of s, the same for
+// the whole wave) its last pair also needs the dword after them, which is the first dword of lane
+// i + 1 (mod 64): the row repeats the turn past n_phi, and lane 63's next entry is lane 0's first.
+// A byte permute with a wave-uniform selector aligns the pairs.  Counts are kept as 16-bit pairs in 32-bit words: a plain
 // add never carries between the halves, since no bin exceeds the event's hit count (<= 65535).
 // A layer without a valid sample reads a row of zeros (every load is issued unconditionally).
 // Work items are (event, block of `cpi` columns) as in k_vote: item = rank * blocks + block;
@@ -875,9 +1006,10 @@ __global__ __launch_bounds__(kVotePtThreads) void k_vote_pt(Events ev, const int
                                                            char* __restrict__ acc_base, size_t acc_stride,
                                                            int n_events, const int32_t* __restrict__ order,
                                                            int32_t* __restrict__ queue, int cpi) {
-    constexpr int NP = BPL / 2;                       // bin pairs per lane
-    constexpr int ND = NP + 1;                        // dwords loaded per layer
+    constexpr int NP = BPL / 2;                       // bin pairs per lane (= dwords loaded per layer)
+    constexpr int ND = NP + 1;                        // with the dword of the next lane
     constexpr int LG = ND * 10 <= 60 ? 10 : (60 / ND > 0 ? 60 / ND : 1);  // layers per load group
+    const int next4 = ((threadIdx.x + 1) & 63) * 4;   // byte address of lane + 1 (mod 64) for ds_bpermute
     __shared__ int next_item;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -902,6 +1034,7 @@ __global__ __launch_bounds__(kVotePtThreads) void k_vote_pt(Events ev, const int
             for (int L0 = 0; L0 < n_layers; L0 += LG) {
                 uint32_t d[LG][ND];
                 uint32_t sel[LG];
+                bool odd[LG];
 #pragma unroll
                 for (int u = 0; u < LG; ++u) {
                     const int L = L0 + u;
@@ -911,12 +1044,13 @@ __global__ __launch_bounds__(kVotePtThreads) void k_vote_pt(Events ev, const int
                     const uint32_t i0 = (sft + (uint32_t)(lane * BPL)) & (uint32_t)(n_phi - 1);
                     const uint32_t* src = ev_l != INT32_MIN ? gt + ((size_t)L * (1u << F) + r) * row2 : zero_row;
                     // byte selector: the pair starting at an odd entry spans two dwords
-                    sel[u] = (__builtin_amdgcn_readfirstlane(sft) & 1u) ? 0x05040302u : 0x03020100u;
-#pragma unroll
-                    for (int t = 0; t < ND; ++t) d[u][t] = src[(i0 >> 1) + t];
+                    odd[u] = (__builtin_amdgcn_readfirstlane(sft) & 1u) != 0u;
+                    sel[u] = odd[u] ? 0x05040302u : 0x03020100u;
+                    __builtin_memcpy(&d[u][0], src + (i0 >> 1), 4 * NP);  // dword-aligned 16-byte loads
                 }
 #pragma unroll
                 for (int u = 0; u < LG; ++u) {
+                    d[u][NP] = odd[u] ? (uint32_t)__builtin_amdgcn_ds_bpermute(next4, (int)d[u][0]) : 0u;
 #pragma unroll
                     for (int q = 0; q < NP; ++q) acc[q] += __builtin_amdgcn_perm(d[u][q + 1], d[u][q], sel[u]);
                 }
@@ -1072,17 +1206,24 @@ template <typename T, bool WIDE>
 __global__ __launch_bounds__(kMarkThreads) void k_peaks_mark(Events ev, const char* __restrict__ acc_base,
                                                              size_t acc_stride, const T* __restrict__ zero_row,
                                                              int32_t thr, int n_d0, int n_qpt, int n_phi,
-                                                             int group_lanes, int planes, char* __restrict__ ws,
-                                                             WsOff O) {
+                                                             int group_lanes, int planes, bool stage_on,
+                                                             char* __restrict__ ws, WsOff O) {
     __shared__ uint8_t s_flags[kMaxPeakPlanes][kMarkThreads];
     __shared__ int32_t s_cnt[kMaxPeakPlanes][kMarkThreads / 2];
     __shared__ int32_t s_vs[kMaxPeakPlanes][kMarkThreads / 2];
+    __shared__ uint16_t s_val[kMaxPeakPlanes][kMarkThreads * 3 / 4];  // staged values, stage_cap per group
     const int e = blockIdx.y;
     const T* acc = reinterpret_cast<const T*>(acc_base + (size_t)e * acc_stride);
     char* w = event_ws(ws, ev, e);
     uint8_t* flags = at<uint8_t>(w, O.flags);
     int32_t* grp_count = at<int32_t>(w, O.grp_count);
     int32_t* grp_votes = at<int32_t>(w, O.grp_votes);
+    uint16_t* stage = at<uint16_t>(w, O.stage);
+    const int capg = stage_cap(group_lanes);
+    const int gi = threadIdx.x / group_lanes;          // group of this thread inside the workgroup
+    const int gq = threadIdx.x & (group_lanes - 1);    // its strip inside the group
+    const uint64_t gmask = group_lanes == 64 ? ~0ull
+                                             : ((1ull << group_lanes) - 1ull) << ((threadIdx.x & 63) & ~(group_lanes - 1));
     const int strips = n_phi / kStrip;
     // Workgroups go to the 8 XCDs round-robin and each XCD has its own L2: block b works on tile
     // (b % 8) * (gridDim.x / 8) + b / 8 (gridDim.x is a multiple of 8), so the neighbouring q/pT
@@ -1122,8 +1263,23 @@ __global__ __launch_bounds__(kMarkThreads) void k_peaks_mark(Events ev, const ch
             }
         }
         s_flags[l - l0][threadIdx.x] = (uint8_t)bits;
-        // per-group sums: a group is `group_lanes` consecutive strips of one column
         int32_t cnt = __popc(bits);
+        if (stage_on) {  // the group's candidate values in candidate order, while they are in registers
+            // a strip holds at most 4 candidates (two adjacent bins cannot both win the tie rule):
+            // the group's exclusive prefix of the counts from three ballots of their bits
+            const uint64_t b0 = __ballot(cnt & 1), b1 = __ballot(cnt & 2), b2 = __ballot(cnt & 4);
+            const uint64_t below = gmask & ((1ull << (threadIdx.x & 63)) - 1ull);
+            int pos = __popcll(b0 & below) + 2 * __popcll(b1 & below) + 4 * __popcll(b2 & below);
+            uint16_t* sv = &s_val[l - l0][gi * capg];
+#pragma unroll
+            for (int i = 0; i < kStrip; ++i) {
+                if ((bits >> i) & 1u) {
+                    if (pos < capg) sv[pos] = (uint16_t)cur.mid[i + 1];
+                    ++pos;
+                }
+            }
+        }
+        // per-group sums: a group is `group_lanes` consecutive strips of one column
         for (int o = group_lanes >> 1; o >= 1; o >>= 1) {
             cnt += __shfl_xor(cnt, o, 64);
             vsum += __shfl_xor(vsum, o, 64);
@@ -1147,6 +1303,8 @@ __global__ __launch_bounds__(kMarkThreads) void k_peaks_mark(Events ev, const ch
             grp_count[strip_id / group_lanes] = s_cnt[l - l0][threadIdx.x / group_lanes];
             grp_votes[strip_id / group_lanes] = s_vs[l - l0][threadIdx.x / group_lanes];
         }
+        if (stage_on && gq < min(s_cnt[l - l0][gi], capg))
+            stage[(strip_id / group_lanes) * capg + gq] = s_val[l - l0][gi * capg + gq];
     }
 }
 
@@ -1411,11 +1569,106 @@ __device__ __forceinline__ void write_emit(const WriteItem<T>& it, int32_t g_off
     }
 }
 
+// The writer with the values the marker staged: a thread's first candidate inside its group comes
+// from a scan of the strips' counts over the group's threads, its values from the stage (a group
+// with more candidates than the stage holds reads them from the accumulator), then a scan of the
+// vote sums gives their CSR offsets.  Every thread of the workgroup takes part in the scans.
+template <typename T>
+struct StagedItem {
+    bool live, staged;
+    uint64_t bits, rest;
+    int cnt, pos0, s0;
+    int64_t row;
+    const T* r;
+    const uint16_t* sv;
+    int32_t val[kWriteFirst];
+    int32_t vsum, vpre;
+};
+
+template <typename T>
+__device__ __forceinline__ void staged_load(const T* acc, const uint8_t* flags, const uint16_t* stage, int capg,
+                                            int64_t t, int64_t n_thr, int sp, int tpg, int strips, int n_phi,
+                                            StagedItem<T>& it) {
+    it.live = t < n_thr;
+    const int64_t tc = it.live ? t : n_thr - 1;
+    const int64_t strip0 = tc * sp;
+    it.bits = 0;
+    if (it.live) {
+        if (sp == kWriteStrips) {
+            it.bits = *reinterpret_cast<const uint64_t*>(flags + strip0);
+        } else {
+            for (int i = 0; i < sp; ++i) it.bits |= (uint64_t)flags[strip0 + i] << (8 * i);
+        }
+    }
+    it.cnt = __popcll(it.bits);
+    const int gl = threadIdx.x & (tpg - 1);
+    int inc = it.cnt;
+    for (int o = 1; o < tpg; o <<= 1) {
+        const int a = __shfl_up(inc, o, tpg);
+        if (gl >= o) inc += a;
+    }
+    const int gtot = __shfl(inc, tpg - 1, tpg);
+    it.pos0 = inc - it.cnt;
+    it.staged = gtot <= capg;
+    it.row = strip0 / strips;
+    it.s0 = (int)(strip0 - it.row * strips);
+    it.r = acc + it.row * n_phi + it.s0 * kStrip;
+    it.sv = stage + (tc / tpg) * capg + it.pos0;
+    it.rest = it.bits;
+    int idx[kWriteFirst];
+#pragma unroll
+    for (int j = 0; j < kWriteFirst; ++j) {
+        idx[j] = it.rest ? __ffsll((long long)it.rest) - 1 : 0;
+        it.rest &= it.rest - 1;
+    }
+#pragma unroll
+    for (int j = 0; j < kWriteFirst; ++j)
+        it.val[j] = j < it.cnt ? (it.staged ? (int32_t)it.sv[j] : (int32_t)it.r[idx[j]]) : 0;
+    it.vsum = 0;
+#pragma unroll
+    for (int j = 0; j < kWriteFirst; ++j) it.vsum += it.val[j];
+    int j = kWriteFirst;
+    for (uint64_t b = it.rest; b; b &= b - 1, ++j)
+        it.vsum += it.staged ? (int32_t)it.sv[j] : (int32_t)it.r[__ffsll((long long)b) - 1];
+    int32_t vinc = it.vsum;
+    for (int o = 1; o < tpg; o <<= 1) {
+        const int32_t c = __shfl_up(vinc, o, tpg);
+        if (gl >= o) vinc += c;
+    }
+    it.vpre = vinc - it.vsum;
+}
+
+template <typename T>
+__device__ __forceinline__ void staged_emit(const StagedItem<T>& it, int32_t g_off, int64_t g_voff, int n_qpt,
+                                            hough_peak_t* peaks, int64_t* peak_voff, int32_t cap) {
+    if (!it.live || it.bits == 0) return;
+    int32_t pos = g_off + it.pos0;
+    int64_t voff = g_voff + it.vpre;
+    const int k = (int)(it.row % n_qpt);
+    const int l = (int)(it.row / n_qpt);
+    int j = 0;
+    for (uint64_t b = it.bits; b; b &= b - 1, ++j) {
+        const int i = __ffsll((long long)b) - 1;
+        const int32_t v = j < kWriteFirst ? it.val[j] : (it.staged ? (int32_t)it.sv[j] : (int32_t)it.r[i]);
+        if (pos < cap) {
+            hough_peak_t pk;
+            pk.l = l;
+            pk.k = k;
+            pk.b = it.s0 * kStrip + i;
+            pk.votes = v;
+            peaks[pos] = pk;
+            peak_voff[pos] = voff;
+        }
+        ++pos;
+        voff += v;
+    }
+}
+
 template <typename T>
 __global__ __launch_bounds__(kWriteThreads) void k_peaks_write(Events ev, const char* __restrict__ acc_base,
                                                                size_t acc_stride, int64_t n_groups, int n_qpt,
                                                                int n_phi, int group_lanes, int64_t n_strips,
-                                                               char* __restrict__ ws, WsOff O,
+                                                               bool stage_on, char* __restrict__ ws, WsOff O,
                                                                hough_peak_t* __restrict__ peaks_base, int32_t cap) {
     const int e = blockIdx.y;
     const T* acc = reinterpret_cast<const T*>(acc_base + (size_t)e * acc_stride);
@@ -1432,6 +1685,13 @@ __global__ __launch_bounds__(kWriteThreads) void k_peaks_write(Events ev, const 
     const int64_t g = (t < n_thr ? t : n_thr - 1) / tpg;
     const int32_t g_off = grp_off[g];
     const int64_t g_voff = grp_voff[g];
+    if (stage_on) {
+        StagedItem<T> it;
+        staged_load(acc, flags, at<const uint16_t>(w, O.stage), stage_cap(group_lanes), t, n_thr, sp, tpg, strips,
+                    n_phi, it);
+        staged_emit(it, g_off, g_voff, n_qpt, peaks_base + (size_t)e * cap, at<int64_t>(w, O.peak_voff), cap);
+        return;
+    }
     WriteItem<T> it;
     write_load(acc, flags, t, n_thr, sp, strips, n_phi, it);
     write_emit(it, g_off, g_voff, tpg, n_qpt, peaks_base + (size_t)e * cap, at<int64_t>(w, O.peak_voff), cap);
@@ -1451,7 +1711,7 @@ template <typename T>
 __global__ __launch_bounds__(kWriteThreads) void k_peaks_scan_write(Events ev, const char* __restrict__ acc_base,
                                                                     size_t acc_stride, int64_t n_groups, int n_qpt,
                                                                     int n_phi, int group_lanes, int64_t n_strips,
-                                                                    char* __restrict__ ws, WsOff O,
+                                                                    bool stage_on, char* __restrict__ ws, WsOff O,
                                                                     hough_peak_t* __restrict__ peaks_base,
                                                                     int32_t cap, hough_status_t* __restrict__ st_base) {
     __shared__ int64_t red_c[kWriteThreads / 64], red_v[kWriteThreads / 64];
@@ -1474,7 +1734,12 @@ __global__ __launch_bounds__(kWriteThreads) void k_peaks_scan_write(Events ev, c
     const int64_t gb = (int64_t)blockIdx.x * gpb;        // first group of this workgroup
     const int64_t t = (int64_t)blockIdx.x * kWriteThreads + tid;
     WriteItem<T> it;
-    write_load(acc, flags, t, n_thr, sp, strips, n_phi, it);
+    StagedItem<T> si;
+    if (stage_on)
+        staged_load(acc, flags, at<const uint16_t>(w, O.stage), stage_cap(group_lanes), t, n_thr, sp, tpg, strips,
+                    n_phi, si);
+    else
+        write_load(acc, flags, t, n_thr, sp, strips, n_phi, it);
     // own groups' counts, and the carry-in over [0, gb) (gb is a multiple of 4)
     const bool own = tid < gpb && gb + tid < n_groups;
     const int32_t oc = own ? grp_count[gb + tid] : 0;
@@ -1544,7 +1809,11 @@ __global__ __launch_bounds__(kWriteThreads) void k_peaks_scan_write(Events ev, c
     __syncthreads();
     const int gi = (int)(((t < n_thr ? t : n_thr - 1) / tpg) - gb);  // this thread's group, local
     const int gl = min(max(gi, 0), gpb - 1);
-    write_emit(it, s_off[gl], s_voff[gl], tpg, n_qpt, peaks_base + (size_t)e * cap, at<int64_t>(w, O.peak_voff), cap);
+    if (stage_on)
+        staged_emit(si, s_off[gl], s_voff[gl], n_qpt, peaks_base + (size_t)e * cap, at<int64_t>(w, O.peak_voff), cap);
+    else
+        write_emit(it, s_off[gl], s_voff[gl], tpg, n_qpt, peaks_base + (size_t)e * cap, at<int64_t>(w, O.peak_voff),
+                   cap);
 }
 
 // ------------------------------------------------------------------ assign
@@ -1808,12 +2077,13 @@ __global__ __launch_bounds__(kAssignThreads) void k_assign_fill(
     }
 }
 
-// Assignment from the window table (plans with the table, see k_ptab).  The hits of layer L in the
+// Assignment from the window table (plans with the table, see k_prep_fine).  The hits of layer L in the
 // window of candidate (l, k, b) are sorted positions: with x = (E mod 2^M) + b * W = r + j * W,
 // the run [PT[L][r][j], PT[L][r][j + 1]) of the layer (relative to its first sorted hit); a window
 // that passes the turn (j = n_phi - 1) is the run from PT[L][r][j] to the layer's end followed by
-// [0, PT[L][r][0]) (the hits below angle r).  Two table loads per layer replace the searches of
-// k_assign_fill; the layers are taken eight at a time so that their loads are in flight together.
+// [0, PT[L][r][0]) (the hits below angle r).  One 8-byte table load per layer (the dword pair
+// holding entries j and j + 1; a wrapping window loads entry 0 as well) replaces the searches of
+// k_assign_fill; the layers are taken ten at a time so that their loads are in flight together.
 typedef __attribute__((address_space(3))) const uint16_t lds_cu16;
 
 struct HitsU16 {
@@ -1825,7 +2095,7 @@ struct HitsIdx {
     __device__ __forceinline__ int32_t hit(int i) const { return h[i]; }
 };
 
-constexpr int kAssignLayerChunk = 8;
+constexpr int kAssignLayerChunk = 10;
 
 template <typename View>
 __device__ __forceinline__ void assign_candidate_pt(const hough_peak_t& pk, int64_t off, int64_t o0,
@@ -1845,14 +2115,26 @@ __device__ __forceinline__ void assign_candidate_pt(const hough_peak_t& pk, int6
         bool wr[LC];
 #pragma unroll
         for (int u = 0; u < LC; ++u) {
-            // every load is in bounds (an invalid sample still gives an angle below 2^M)
+            // every load is in bounds (an invalid sample still gives an angle below 2^M; the pair of
+            // a row's last entry reaches one dword past the row, into the next row or the window
+            // counts that follow the table in the workspace)
             const uint32_t x = ((uint32_t)ev_l[u] + ((uint32_t)pk.b << F)) & mmask;
             const uint32_t r = x & wmask, j = x >> F;
             const int Lc = min(L0 + u, n_layers - 1);
-            const uint16_t* rp = pt + ((size_t)Lc * (wmask + 1u) + r) * n_phi;
+            const uint32_t* rp = reinterpret_cast<const uint32_t*>(pt + ((size_t)Lc * (wmask + 1u) + r) * n_phi);
             wr[u] = (int)j == n_phi - 1;
-            lo[u] = rp[j];
-            hi[u] = rp[wr[u] ? 0u : j + 1u];
+            uint2 v;
+            __builtin_memcpy(&v, rp + (j >> 1), 8);
+            lo[u] = (j & 1u) ? v.x >> 16 : v.x & 0xFFFFu;
+            hi[u] = (j & 1u) ? v.y & 0xFFFFu : v.x >> 16;
+        }
+#pragma unroll
+        for (int u = 0; u < LC; ++u) {
+            if (wr[u]) {  // the window passes the turn: it ends at entry 0 of the row
+                const uint32_t r = ((uint32_t)ev_l[u] + ((uint32_t)pk.b << F)) & wmask;
+                const int Lc = min(L0 + u, n_layers - 1);
+                hi[u] = pt[((size_t)Lc * (wmask + 1u) + r) * n_phi];
+            }
         }
 #pragma unroll
         for (int u = 0; u < LC; ++u) {
@@ -2283,6 +2565,117 @@ __global__ __launch_bounds__(kCrThreads) void k_vote_cr(const float* __restrict_
     }
 }
 
+// Assignment under the per-hit radius: the lists of the candidates found in a per-hit-radius
+// accumulator (hough_vote_cr, then hough_peaks on it).  Each hit's bin in a column follows its own
+// radius, so the lists are collected by voting again: k_cra_init clears the bin -> candidate map
+// and the per-candidate fill counters, k_cra_map marks every listed candidate's bin, k_cra_vote
+// repeats the vote (same integer arithmetic as k_vote_cr) and appends, for a vote into a
+// candidate's bin, the key (layer << 32) | (angle inside the bin << 24) | hit at the candidate's
+// CSR offset plus an atomic slot, and k_cra_sort sorts each list's keys (the list order of the
+// assignment: layer, angle inside the bin, hit index) and writes the hit indices.  A list that
+// starts before the pair capacity is collected whole (its keys may run up to max_hits past it) so
+// that its first entries are the right ones.
+__global__ __launch_bounds__(256) void k_cra_init(int32_t* __restrict__ map, int64_t n_bins,
+                                                 int32_t* __restrict__ fill, int32_t cap_peaks) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n_bins) map[i] = -1;
+    if (i < cap_peaks) fill[i] = 0;
+}
+
+__global__ __launch_bounds__(256) void k_cra_map(const hough_peak_t* __restrict__ peaks, int32_t cap_peaks,
+                                                const char* __restrict__ ws, WsOff O, int n_qpt, int n_phi,
+                                                int32_t* __restrict__ map) {
+    const int n = min(*at<const int32_t>(const_cast<char*>(ws), O.misc), cap_peaks);
+    const int p = blockIdx.x * 256 + threadIdx.x;
+    if (p >= n) return;
+    const hough_peak_t pk = peaks[p];
+    map[((int64_t)pk.l * n_qpt + pk.k) * n_phi + pk.b] = p;
+}
+
+__global__ __launch_bounds__(kCrThreads) void k_cra_vote(const float* __restrict__ hx, const float* __restrict__ hy,
+                                                        const uint8_t* __restrict__ hl, int32_t n, CrGrid g,
+                                                        CordicTable T, const int32_t* __restrict__ map,
+                                                        const int64_t* __restrict__ peak_voff,
+                                                        int32_t* __restrict__ fill, uint64_t* __restrict__ keys,
+                                                        int32_t cap_pairs) {
+    const int chunks = (g.n_cols + kCrCols - 1) / kCrCols;
+    const int64_t t = (int64_t)blockIdx.x * kCrThreads + threadIdx.x;
+    const int h = (int)(t / chunks), ch = (int)(t % chunks);
+    if (h >= n) return;
+    const float x = hx[h], y = hy[h];
+    const uint8_t L = hl[h];
+    bool ok = (int)L < g.n_layers && isfinite(x) && isfinite(y) && fabsf(x) < 32768.0f && fabsf(y) < 32768.0f;
+    int32_t X = 0, Y = 0;
+    if (ok) {
+        X = __float2int_rn(x * 65536.0f);
+        Y = __float2int_rn(y * 65536.0f);
+        ok = !(X == 0 && Y == 0);
+    }
+    if (!ok) return;
+    const int s = 32 - g.M;
+    const uint32_t maskM = g.M >= 32 ? 0xFFFFFFFFu : ((1u << g.M) - 1u);
+    const uint32_t wmask = (1u << g.F) - 1u;
+    const uint32_t phiM = cordic_azimuth(X, Y, T) >> s;
+    const uint64_t R2 = (uint64_t)((int64_t)X * X) + (uint64_t)((int64_t)Y * Y);
+    const double r = (double)isqrt_u64(R2) / 65536.0;
+    const int c0 = ch * kCrCols;
+    const int c1 = min(g.n_cols, c0 + kCrCols);
+    for (int col = c0; col < c1; ++col) {
+        const int l = col / g.n_qpt, k = col % g.n_qpt;
+        const double q = g.qpt_min + ((double)k + 0.5) * g.qstep;
+        const double c = -g.kappa * q;
+        const double d = g.d0_min + ((double)l + 0.5) * g.dstep;
+        const double num = c * (r * r + d * d) + 2.0 * d;
+        const double den = 2.0 * r * (1.0 + c * d);
+        if (!(den > 0.0)) continue;
+        const double A = num / den;
+        if (!(fabs(A) <= 1.0)) continue;
+        const int64_t a = llrint(A * 1073741824.0);
+        const int64_t b = (int64_t)isqrt_u64((uint64_t)(((int64_t)1 << 60) - a * a));
+        const int64_t th = (int64_t)(int32_t)cordic_azimuth((int32_t)b, (int32_t)a, T);
+        const int32_t E = (int32_t)((th + ((int64_t)1 << (s - 1))) >> s);
+        const uint32_t rel = (phiM - (uint32_t)E) & maskM;
+        const int32_t p = map[(size_t)col * g.n_phi + (rel >> g.F)];
+        if (p < 0) continue;
+        const int64_t base = peak_voff[p];
+        if (base >= cap_pairs) continue;  // the list lies wholly past the capacity
+        const int slot = atomicAdd(fill + p, 1);
+        keys[base + slot] = ((uint64_t)L << 32) | ((uint64_t)(rel & wmask) << 24) | (uint64_t)h;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_cra_sort(const hough_peak_t* __restrict__ peaks, int32_t cap_peaks,
+                                                 const char* __restrict__ ws, WsOff O, uint64_t* __restrict__ keys,
+                                                 int32_t* __restrict__ offsets, int32_t* __restrict__ hit_idx,
+                                                 int32_t cap_pairs, hough_status_t* __restrict__ st) {
+    const int n = min(*at<const int32_t>(const_cast<char*>(ws), O.misc), cap_peaks);
+    const int64_t* peak_voff = at<const int64_t>(const_cast<char*>(ws), O.peak_voff);
+    const int p = blockIdx.x * 256 + threadIdx.x;
+    if (p == 0) {
+        const int64_t tot = n > 0 ? peak_voff[n - 1] + peaks[n - 1].votes : 0;
+        offsets[n] = (int32_t)min(tot, (int64_t)INT32_MAX);
+        st->n_pairs = tot;
+        if (tot > cap_pairs) atomicOr(&st->flags, HOUGH_F_PAIR_OVERFLOW);
+    }
+    if (p >= n) return;
+    const int64_t base = peak_voff[p];
+    offsets[p] = (int32_t)min(base, (int64_t)INT32_MAX);
+    if (base >= cap_pairs) return;
+    const int nv = peaks[p].votes;
+    uint64_t* kk = keys + base;
+    for (int i = 1; i < nv; ++i) {  // insertion sort of the list's keys (a few to a few hundred)
+        const uint64_t v = kk[i];
+        int j = i - 1;
+        while (j >= 0 && kk[j] > v) {
+            kk[j + 1] = kk[j];
+            --j;
+        }
+        kk[j + 1] = v;
+    }
+    const int m = (int)min((int64_t)nv, (int64_t)cap_pairs - base);
+    for (int i = 0; i < m; ++i) hit_idx[base + i] = (int32_t)(kk[i] & 0xFFFFFFu);
+}
+
 // ------------------------------------------------------------------ zvote
 // Per candidate p (grid.y = event): every hit h of its list with a usable z votes, for each
 // cot(theta) row m, into z0 bin j(m) = (Z_h * 2^16 - S_h * C_m - z0min) >> shift, where S_h is the
@@ -2290,10 +2683,12 @@ __global__ __launch_bounds__(kCrThreads) void k_vote_cr(const float* __restrict_
 // is the (m, j) with the most votes, lowest m * n_z0 + j on ties.  With A_h = Z_h * 2^16 - z0min -
 // S_h * C_0 and B_h = S_h * dC, the value for row m is A_h - m * B_h (exact int64).
 //
-// A wave takes groups of kZvoteGroup consecutive candidates.  It first stages (A_h, B_h) of all
+// A wave takes groups of kZvoteGroup consecutive candidates.  It first stages (Z_h, S_h) of all
 // hits of the group in its LDS (one pass of independent loads for the whole group: hit index,
-// then z and layer, then the arc length), then votes the candidates one by one: with H <= 64
-// hits, R = min(kZvoteSlots, 64 / H) rows at once, one lane per (row slot, hit).
+// then z and layer, then the arc length; A_h and B_h are formed when a lane fetches its hit), then
+// votes the candidates one by one: with H <= 64 hits, R = min(kZvoteSlots, 64 / H) rows at once,
+// one lane per (row slot, hit).  The row slots lie n_z0 + 1 words apart, so the same bin of
+// different slots falls into different LDS banks.
 //
 // Each LDS word of a row histogram holds (count << 16) | (0xFFFF - j).  Adding 1 << 16 returns the
 // old word, so old + 2^16 - m * n_z0 = (count << 16) | (0xFFFF - (m * n_z0 + j)) is a key whose
@@ -2303,23 +2698,32 @@ __global__ __launch_bounds__(kCrThreads) void k_vote_cr(const float* __restrict_
 // instruction of the wave, so the row is clean for the next row voted in that slot.  A group
 // holding a candidate of more than 64 hits is voted from memory instead, one row at a time in
 // chunks of 64 hits, restoring the row after its last chunk.
-constexpr int kZvoteGroup = 2;                    // candidates staged together by a wave
+constexpr int kZvoteGroup = 4;                    // candidates staged together by a wave
 constexpr int kZvoteUnroll = 4;                   // rows voted before their returned words are used
-constexpr int kZvoteStage = kZvoteGroup * 64;     // staged hits per wave (A, B: 16 bytes each)
+constexpr int kZvoteStage = kZvoteGroup * 64;     // staged hits per wave (Z, S: 8 bytes each)
 
-__device__ __forceinline__ void zvote_hit(int32_t h, const float* __restrict__ hz, const uint8_t* __restrict__ hl,
-                                          int h0, const int32_t* __restrict__ Sc, int n_layers, size_t s_layer,
-                                          const ZGrid& zg, int64_t& A, int64_t& B) {
+// Q16.16 z and arc length of a listed hit; S = -1 when the hit has no usable z or arc length
+__device__ __forceinline__ int2 zvote_zs(int32_t h, const float* __restrict__ hz, const uint8_t* __restrict__ hl,
+                                         int h0, const int32_t* __restrict__ Sc, int n_layers, size_t s_layer) {
     const float zf = hz[h0 + h];
     const int L = hl[h0 + h];
     bool ok = isfinite(zf) && fabsf(zf) < 32768.0f && L < n_layers;
     int32_t S = ok ? Sc[(size_t)L * s_layer] : -1;
     ok = ok && S >= 0;
-    const int32_t Z = ok ? __float2int_rn(zf * 65536.0f) : 0;
-    S = ok ? S : 0;
-    // an unusable hit gets A = -1, B = 0: its value is negative on every row and never votes
-    A = ok ? (int64_t)Z * 65536 - zg.z0min - (int64_t)S * zg.c0 : -1;
-    B = (int64_t)S * zg.dc;
+    return make_int2(ok ? __float2int_rn(zf * 65536.0f) : 0, ok ? S : -1);
+}
+
+// an unusable hit gets A = -1, B = 0: its value is negative on every row and never votes
+__device__ __forceinline__ void zvote_ab(int2 zs, const ZGrid& zg, int64_t& A, int64_t& B) {
+    const bool ok = zs.y >= 0;
+    A = ok ? (int64_t)zs.x * 65536 - zg.z0min - (int64_t)zs.y * zg.c0 : -1;
+    B = ok ? (int64_t)zs.y * zg.dc : 0;
+}
+
+__device__ __forceinline__ void zvote_hit(int32_t h, const float* __restrict__ hz, const uint8_t* __restrict__ hl,
+                                          int h0, const int32_t* __restrict__ Sc, int n_layers, size_t s_layer,
+                                          const ZGrid& zg, int64_t& A, int64_t& B) {
+    zvote_ab(zvote_zs(h, hz, hl, h0, Sc, n_layers, s_layer), zg, A, B);
 }
 
 // floor(65536 / H) + 1 for H = 1..64: slot = (lane * kInvH[H]) >> 16 equals lane / H for lane < 64.
@@ -2346,7 +2750,7 @@ __device__ __forceinline__ uint32_t zvote_small(int H, int lane, uint32_t* regio
     const int slot = (int)(((uint32_t)lane * kInvH.v[H]) >> 16);
     int64_t A = -1, B = 0;
     if (slot < R) get(lane - slot * H, A, B);
-    uint32_t* row = region + slot * nz;
+    uint32_t* row = region + slot * (nz + 1);
     const int64_t z0 = A - (int64_t)slot * B;
     const int64_t step = (int64_t)R * B;
     uint32_t kc = 0x10000u - (uint32_t)(slot * nz);
@@ -2448,7 +2852,8 @@ __global__ __launch_bounds__(kZvoteThreads) void k_zvote(
     const hough_peak_t* __restrict__ peaks_base, int32_t cap_peaks, const int32_t* __restrict__ offsets_base,
     const int32_t* __restrict__ hit_idx_base, int32_t cap_pairs, const hough_status_t* __restrict__ st_base,
     const int32_t* __restrict__ S, int n_d0, int n_qpt, ZGrid zg, int32_t* __restrict__ out_base) {
-    // LDS per wave: kZvoteSlots row histograms of n_z0 words, then kZvoteStage staged (A, B)
+    // LDS per wave: kZvoteSlots row histograms of n_z0 words (n_z0 + 1 apart), then kZvoteStage
+    // staged (Z, S)
     extern __shared__ uint32_t zs_u32[];
     const int e = blockIdx.y;
     int h0, nh;
@@ -2462,10 +2867,11 @@ __global__ __launch_bounds__(kZvoteThreads) void k_zvote(
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int nz = zg.n_z0;
     const size_t s_layer = (size_t)n_d0 * n_qpt;
-    const size_t wave_words = (size_t)kZvoteSlots * nz + 4 * kZvoteStage;
+    const size_t slots_words = ((size_t)kZvoteSlots * (nz + 1) + 1) & ~(size_t)1;  // keeps the stage 8-byte aligned
+    const size_t wave_words = slots_words + 2 * kZvoteStage;
     uint32_t* region = zs_u32 + (size_t)wave * wave_words;
-    int64_t* stage = reinterpret_cast<int64_t*>(region + (size_t)kZvoteSlots * nz);  // [kZvoteStage][2]
-    for (int i = lane; i < kZvoteSlots * nz; i += 64) region[i] = 0xFFFFu - (uint32_t)(i % nz);
+    int2* stage = reinterpret_cast<int2*>(region + slots_words);  // [kZvoteStage] (Z, S)
+    for (int i = lane; i < kZvoteSlots * (nz + 1); i += 64) region[i] = 0xFFFFu - (uint32_t)(i % (nz + 1));
     const int waves = kZvoteThreads / 64;
     const int n_groups = (n + kZvoteGroup - 1) / kZvoteGroup;
     const bool fast = zg.shift >= 28 && zg.shift <= 32;
@@ -2494,12 +2900,7 @@ __global__ __launch_bounds__(kZvoteThreads) void k_zvote(
                 for (int j = 1; j < cnt; ++j) c += q >= __builtin_amdgcn_readlane(my_off, j) ? 1 : 0;
                 // with every lane active: a lane shuffle reads nothing from inactive lanes
                 const int32_t l = __shfl(my_l, c, 64), k = __shfl(my_k, c, 64);
-                if (q < qe) {
-                    int64_t A, B;
-                    zvote_hit(hit_idx[q], hz, hl, h0, S + (size_t)l * n_qpt + k, n_layers, s_layer, zg, A, B);
-                    stage[2 * (q - q0)] = A;
-                    stage[2 * (q - q0) + 1] = B;
-                }
+                if (q < qe) stage[q - q0] = zvote_zs(hit_idx[q], hz, hl, h0, S + (size_t)l * n_qpt + k, n_layers, s_layer);
             }
             asm volatile("" ::: "memory");
             for (int c = 0; c < cnt; ++c) {
@@ -2517,11 +2918,8 @@ __global__ __launch_bounds__(kZvoteThreads) void k_zvote(
                 const int H = o1 - o0;
                 uint32_t best = 0;
                 if (H >= 1) {
-                    const int64_t* st_c = stage + 2 * (o0 - q0);
-                    auto get = [&](int i, int64_t& A, int64_t& B) {
-                        A = st_c[2 * i];
-                        B = st_c[2 * i + 1];
-                    };
+                    const int2* st_c = stage + (o0 - q0);
+                    auto get = [&](int i, int64_t& A, int64_t& B) { zvote_ab(st_c[i], zg, A, B); };
                     best = fast ? zvote_small<true>(H, lane, region, zg, get) : zvote_small<false>(H, lane, region, zg, get);
                 }
                 best = wave_max(best);
@@ -2596,6 +2994,19 @@ int bucket_cap_hits(const hough_plan* p) {
     return cap >= 64 ? (int)cap : 0;
 }
 
+// phi0 rows per k_prep_fine workgroup: the tuned value (a power of two), else kFineRows; at most n_phi
+int fine_rows(const hough_plan* p) {
+    int R = p->tuning.prep_rows > 0 ? p->tuning.prep_rows : kFineRows;
+    while (R < p->pt_row - p->g.n_phi) R *= 2;  // chunk 0 writes the window counts past the turn from its rows
+    return p->g.n_phi < R ? p->g.n_phi : R;
+}
+
+// Dynamic LDS of k_prep_fine: R + 1 padded rows of 16-bit counter pairs and the tied-hit list.
+size_t fine_lds_bytes(const hough_plan* p) {
+    const size_t R = (size_t)fine_rows(p);
+    return 4 * ((R + 1) * (((size_t)1 << p->F) / 2 + 1) + kFineTieCap);
+}
+
 // Launchers shared by the single-event and batched entry points.
 void launch_prep(const hough_plan* p, const Events& ev, int n_events, int max_n, const float* x, const float* y,
                  const uint8_t* layer, uint32_t* phi_out, char* ws, const WsOff& O, hough_status_t* st,
@@ -2603,6 +3014,14 @@ void launch_prep(const hough_plan* p, const Events& ev, int n_events, int max_n,
     if (max_n > 0)
         hipLaunchKernelGGL(k_prep_hits, dim3((max_n + 255) / 256, n_events), dim3(256), 0, stream, ev, x, y, layer,
                            p->n_layers, p->cordic, ws, O, phi_out);
+    if (p->pt) {
+        const int R = fine_rows(p);
+        const int n_chunks = p->g.n_phi / R;
+        hipLaunchKernelGGL(k_prep_fine, dim3(p->n_layers * n_chunks, n_events), dim3(kScanThreads),
+                           fine_lds_bytes(p), stream, ev, p->n_layers, p->cell_bits, p->M, p->F, p->g.n_phi,
+                           p->pt_row, R, n_chunks, p->layers, ws, O, st);
+        return;
+    }
     // events of at most cap_h hits are sorted by one workgroup per layer (LDS); the rank pass
     // runs only if a larger event is possible
     const int cap_h = bucket_cap_hits(p);
@@ -2615,12 +3034,6 @@ void launch_prep(const hough_plan* p, const Events& ev, int n_events, int max_n,
     if (max_n > cap_h)
         hipLaunchKernelGGL(k_prep_rank, dim3((max_n + 255) / 256, n_events), dim3(256), 0, stream, ev, p->n_cells,
                            p->cell_bits, p->M, ws, O);
-    if (p->pt) {
-        const int pairs_pad = ((p->pt_row / 2) + 63) & ~63;
-        const int64_t threads = (int64_t)p->n_layers * (((int64_t)1 << p->F) / kPtPhases) * pairs_pad;
-        hipLaunchKernelGGL(k_ptab, dim3((unsigned)((threads + 255) / 256), n_events), dim3(256), 0, stream, ev,
-                           p->n_layers, p->cell_bits, p->M, p->F, p->g.n_phi, p->pt_row, pairs_pad, ws, O);
-    }
 }
 
 // LDS of one vote workgroup: the slab, the queue word (padded to 256 bytes) and, for 16-bit slabs,
@@ -2730,27 +3143,32 @@ void launch_peaks(const hough_plan* p, const Events& ev, int n_events, const voi
     const int32_t* z32 = static_cast<const int32_t*>(p->d_zero);
     const int nd = p->g.n_d0, nq = p->g.n_qpt, nph = p->g.n_phi;
     const dim3 mb(kMarkThreads);
+    // the one-pass scan and writer serves single events and small batches
+    const bool one_pass = n_events <= kScanWriteMaxEvents && groups <= kScanWriteMaxGroups;
+    // staged values pay off where the writer is a pass of its own (its accumulator gathers would be
+    // spread over the whole batch); the one-pass writer reads the values where they lie
+    const bool stage_on = p->stage && !one_pass;
     if (p->g.acc_bits == 32 && strips > 64)
         hipLaunchKernelGGL((k_peaks_mark<int32_t, true>), gm, mb, 0, stream, ev, a, acc_stride, z32, threshold, nd,
-                           nq, nph, gl, planes, ws, O);
+                           nq, nph, gl, planes, stage_on, ws, O);
     else if (p->g.acc_bits == 32)
         hipLaunchKernelGGL((k_peaks_mark<int32_t, false>), gm, mb, 0, stream, ev, a, acc_stride, z32, threshold, nd,
-                           nq, nph, gl, planes, ws, O);
+                           nq, nph, gl, planes, stage_on, ws, O);
     else if (strips > 64)
         hipLaunchKernelGGL((k_peaks_mark<int16_t, true>), gm, mb, 0, stream, ev, a, acc_stride, z16, threshold, nd,
-                           nq, nph, gl, planes, ws, O);
+                           nq, nph, gl, planes, stage_on, ws, O);
     else
         hipLaunchKernelGGL((k_peaks_mark<int16_t, false>), gm, mb, 0, stream, ev, a, acc_stride, z16, threshold, nd,
-                           nq, nph, gl, planes, ws, O);
+                           nq, nph, gl, planes, stage_on, ws, O);
     // scan and writer in one pass: each writer workgroup re-reads the counts of all groups before
     // it, so only while that is cheaper than a separate scan (few events, not too many groups)
-    if (n_events <= kScanWriteMaxEvents && groups <= kScanWriteMaxGroups) {
+    if (one_pass) {
         if (p->g.acc_bits == 32)
             hipLaunchKernelGGL(k_peaks_scan_write<int32_t>, gw, dim3(kWriteThreads), 0, stream, ev, a, acc_stride,
-                               groups, p->g.n_qpt, p->g.n_phi, gl, n_strips, ws, O, peaks, cap, st);
+                               groups, p->g.n_qpt, p->g.n_phi, gl, n_strips, false, ws, O, peaks, cap, st);
         else
             hipLaunchKernelGGL(k_peaks_scan_write<int16_t>, gw, dim3(kWriteThreads), 0, stream, ev, a, acc_stride,
-                               groups, p->g.n_qpt, p->g.n_phi, gl, n_strips, ws, O, peaks, cap, st);
+                               groups, p->g.n_qpt, p->g.n_phi, gl, n_strips, false, ws, O, peaks, cap, st);
         return;
     }
     // workgroups per event: enough to spread a small batch over the CUs, each with >= one tile
@@ -2763,10 +3181,10 @@ void launch_peaks(const hough_plan* p, const Events& ev, int n_events, const voi
                        cap, ws, O, st);
     if (p->g.acc_bits == 32)
         hipLaunchKernelGGL(k_peaks_write<int32_t>, gw, dim3(kWriteThreads), 0, stream, ev, a, acc_stride, groups, p->g.n_qpt,
-                           p->g.n_phi, gl, n_strips, ws, O, peaks, cap);
+                           p->g.n_phi, gl, n_strips, stage_on, ws, O, peaks, cap);
     else
         hipLaunchKernelGGL(k_peaks_write<int16_t>, gw, dim3(kWriteThreads), 0, stream, ev, a, acc_stride, groups, p->g.n_qpt,
-                           p->g.n_phi, gl, n_strips, ws, O, peaks, cap);
+                           p->g.n_phi, gl, n_strips, stage_on, ws, O, peaks, cap);
 }
 
 void launch_assign(const hough_plan* p, const Events& ev, int n_events, const hough_peak_t* peaks,
@@ -2824,7 +3242,8 @@ void launch_zvote(const hough_plan* p, const Events& ev, int n_events, const flo
     int64_t per_event = (2560 + n_events - 1) / n_events;
     per_event = per_event < want ? per_event : want;
     const unsigned nblk = (unsigned)(per_event > 0 ? per_event : 1);
-    const size_t lds = (size_t)(kZvoteThreads / 64) * ((size_t)kZvoteSlots * p->zg.n_z0 * 4 + 16 * kZvoteStage);
+    const size_t slots_words = ((size_t)kZvoteSlots * (p->zg.n_z0 + 1) + 1) & ~(size_t)1;
+    const size_t lds = (size_t)(kZvoteThreads / 64) * (slots_words * 4 + 8 * kZvoteStage);
     hipLaunchKernelGGL(k_zvote, dim3(nblk, n_events), dim3(kZvoteThreads), lds, stream, ev, z, layer, p->n_layers,
                        peaks, cap_peaks, offsets, hit_idx, cap_pairs, st, p->d_S, p->g.n_d0, p->g.n_qpt, p->zg, out);
 }
@@ -3235,6 +3654,7 @@ int hough_plan_create(const hough_geometry_t* geom, const hough_grid_t* grid, ho
     // window-table path: every window count fits 16 bits (at most 65535 hits per event) and a
     // column's bins split evenly over the 64 lanes of a wave in pairs
     p->pt = g.max_hits_per_event <= 65535 && g.n_phi >= 128;
+    p->stage = g.max_hits_per_event <= 65535;  // a bin holds at most one vote per hit
     p->pt_bpl = g.n_phi / 64;
     p->pt_row = ((g.n_phi + p->pt_bpl + 2) + 7) & ~7;  // window-count rows: entries a lane reads past the turn
     p->n_cols = g.n_d0 * g.n_qpt;
@@ -3245,6 +3665,7 @@ int hough_plan_create(const hough_geometry_t* geom, const hough_grid_t* grid, ho
     p->tuning.peak_planes = 8;
     p->tuning.vote_cols = 0;
     p->tuning.assign_blocks = 0;
+    p->tuning.prep_rows = 0;
     for (int i = 0; i < kCordicSteps; ++i)
         p->cordic.t[i] = (int32_t)llrint(atan(ldexp(1.0, -i)) * (2147483648.0 / M_PI));
 
@@ -3369,6 +3790,9 @@ int hough_plan_create(const hough_geometry_t* geom, const hough_grid_t* grid, ho
     if (ae == hipSuccess)
         ae = hipFuncSetAttribute((const void*)k_assign_pt, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
     if (ae == hipSuccess)
+        ae = hipFuncSetAttribute((const void*)k_prep_fine, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 kLdsBytes - 1024);  // static LDS aside
+    if (ae == hipSuccess)
         ae = hipFuncSetAttribute((const void*)k_zvote, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
     if (ae == hipSuccess)
         ae = hipFuncSetAttribute((const void*)k_fit_res, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
@@ -3398,6 +3822,8 @@ int hough_plan_set_tuning(hough_plan_t* p, const hough_tuning_t* t) {
     if (t->vote_cols != 0 && (t->vote_cols < 4 || t->vote_cols > 64 || (t->vote_cols & (t->vote_cols - 1))))
         return HOUGH_E_INVAL;
     if (t->assign_blocks < 0 || t->assign_blocks > 4096) return HOUGH_E_INVAL;
+    if (t->prep_rows != 0 && (t->prep_rows < 16 || t->prep_rows > 256 || (t->prep_rows & (t->prep_rows - 1))))
+        return HOUGH_E_INVAL;
     p->tuning = *t;
     return HOUGH_OK;
 }
@@ -3670,6 +4096,56 @@ int hough_vote_cr(const hough_plan_t* p, const hough_hits_t* hits, int32_t* acc,
     return launch_status();
 }
 
+size_t hough_assign_cr_ws_bytes(const hough_plan_t* p, int32_t cap_peaks, int32_t cap_pairs) {
+    if (!p || cap_peaks < 1 || cap_pairs < 1) return 0;
+    return align_up(4 * (size_t)p->n_bins, 256) + align_up(4 * (size_t)cap_peaks, 256) +
+           8 * ((size_t)cap_pairs + (size_t)p->g.max_hits_per_event);
+}
+
+int hough_assign_cr(const hough_plan_t* p, const hough_hits_t* hits, const hough_peak_t* peaks, int32_t cap_peaks,
+                    int32_t* offsets, int32_t* hit_idx, int32_t cap_pairs, void* ws, size_t ws_bytes, void* ws_cr,
+                    size_t ws_cr_bytes, hough_status_t* st, hipStream_t stream) {
+    int rc = check_hits(p, hits);
+    if (rc) return rc;
+    if (!peaks || !offsets || !hit_idx || !ws || !ws_cr || !st || cap_peaks < 1 || cap_pairs < 1)
+        return HOUGH_E_INVAL;
+    if (p->g.acc_bits != 32) return HOUGH_E_UNSUPPORTED;
+    const WsLayout L = ws_layout(p, cap_peaks);
+    if (ws_bytes < L.total || ws_cr_bytes < hough_assign_cr_ws_bytes(p, cap_peaks, cap_pairs)) return HOUGH_E_SMALL_WS;
+    const WsOff O = ws_off(L);
+    char* w = static_cast<char*>(ws_cr);
+    int32_t* map = reinterpret_cast<int32_t*>(w);
+    int32_t* fill = reinterpret_cast<int32_t*>(w + align_up(4 * (size_t)p->n_bins, 256));
+    uint64_t* keys = reinterpret_cast<uint64_t*>(w + align_up(4 * (size_t)p->n_bins, 256) +
+                                                 align_up(4 * (size_t)cap_peaks, 256));
+    CrGrid g{};
+    g.n_layers = p->n_layers;
+    g.n_qpt = p->g.n_qpt;
+    g.n_cols = p->n_cols;
+    g.n_phi = p->g.n_phi;
+    g.M = p->M;
+    g.F = p->F;
+    g.qpt_min = p->g.qpt_min;
+    g.qstep = (p->g.qpt_max - p->g.qpt_min) / (double)p->g.n_qpt;
+    g.d0_min = p->g.d0_min;
+    g.dstep = (p->g.d0_max - p->g.d0_min) / (double)p->g.n_d0;
+    g.kappa = 0.299792458e-2 * p->B;
+    const int64_t n_init = p->n_bins > cap_peaks ? p->n_bins : cap_peaks;
+    hipLaunchKernelGGL(k_cra_init, dim3((unsigned)((n_init + 255) / 256)), dim3(256), 0, stream, map, p->n_bins, fill,
+                       cap_peaks);
+    hipLaunchKernelGGL(k_cra_map, dim3((unsigned)((cap_peaks + 255) / 256)), dim3(256), 0, stream, peaks, cap_peaks,
+                       static_cast<const char*>(ws), O, p->g.n_qpt, p->g.n_phi, map);
+    const int chunks = (p->n_cols + kCrCols - 1) / kCrCols;
+    const int64_t threads = (int64_t)hits->n * chunks;
+    if (threads > 0)
+        hipLaunchKernelGGL(k_cra_vote, dim3((unsigned)((threads + kCrThreads - 1) / kCrThreads)), dim3(kCrThreads), 0,
+                           stream, hits->x, hits->y, hits->layer, hits->n, g, p->cordic, map,
+                           at<const int64_t>(static_cast<char*>(ws), O.peak_voff), fill, keys, cap_pairs);
+    hipLaunchKernelGGL(k_cra_sort, dim3((unsigned)((cap_peaks + 255) / 256)), dim3(256), 0, stream, peaks, cap_peaks,
+                       static_cast<const char*>(ws), O, keys, offsets, hit_idx, cap_pairs, st);
+    return launch_status();
+}
+
 // ---------------------------------------------------------------------- second transform
 int hough_vertex_plan_create(const hough_plan_t* p, const hough_vertex_grid_t* vgrid, hough_vertex_plan_t** out) {
     if (!p || !vgrid || !out) return HOUGH_E_INVAL;
@@ -3712,6 +4188,7 @@ int hough_vertex_plan_create(const hough_plan_t* p, const hough_vertex_grid_t* v
         return rc;
     }
     vp->grid->tuning = p->tuning;
+    vp->grid->stage = false;  // vertex-space bins count candidates, which may exceed 16 bits
 
     // sample table at the row radii, in IEEE double in the operation order of the first table
     const hough_grid_t& g = p->g;

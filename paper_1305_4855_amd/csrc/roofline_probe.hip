@@ -37,6 +37,54 @@ __global__ __launch_bounds__(kThreads) void k_lds_atomic(int iters, uint32_t* __
     if (s[t] != (uint32_t)(iters * (kUnroll / 2))) out[blockIdx.x * kThreads + t] = s[t];  // never, keeps the adds
 }
 
+// LDS atomic add with return (ds_add_rtn_u32), addresses as for k_lds_atomic; the returned words
+// are folded into one value so that every return is used.
+__global__ __launch_bounds__(kThreads) void k_lds_atomic_rtn(int iters, uint32_t* __restrict__ out) {
+    __shared__ uint32_t s[kThreads * 2];
+    const int t = threadIdx.x;
+    s[t] = 0u;
+    s[t + kThreads] = 0u;
+    __syncthreads();
+    uint32_t* p = &s[t];
+    uint32_t acc = 0u;
+    for (int i = 0; i < iters; ++i) {
+        uint32_t v[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u)
+            v[u] = __hip_atomic_fetch_add(p + (u & 1) * kThreads, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) acc ^= v[u];
+    }
+    __syncthreads();
+    if (s[t] != (uint32_t)(iters * (kUnroll / 2)) || acc == 0x9e3779b9u) out[blockIdx.x * kThreads + t] = s[t] | 1u;
+}
+
+// The counting step of a vote into a histogram whose words are restored right away: an atomic add
+// with return of 2^16 followed by an atomic subtract of 2^16 from the same word (one lane-vote =
+// two LDS atomics).  Every word ends where it started.
+__global__ __launch_bounds__(kThreads) void k_lds_vote_pair(int iters, uint32_t* __restrict__ out) {
+    __shared__ uint32_t s[kThreads * 2];
+    const int t = threadIdx.x;
+    s[t] = 0u;
+    s[t + kThreads] = 0u;
+    __syncthreads();
+    uint32_t* p = &s[t];
+    uint32_t best = 0u;
+    for (int i = 0; i < iters; ++i) {
+        uint32_t v[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            v[u] = __hip_atomic_fetch_add(p + (u & 1) * kThreads, 0x10000u, __ATOMIC_RELAXED,
+                                          __HIP_MEMORY_SCOPE_WORKGROUP);
+            __hip_atomic_fetch_sub(p + (u & 1) * kThreads, 0x10000u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        }
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) best = max(best, v[u]);
+    }
+    __syncthreads();
+    if (s[t] != 0u || best != 0u) out[blockIdx.x * kThreads + t] = s[t] | best | 1u;
+}
+
 // LDS read of one dword per lane: 16 loads per iteration at immediate offsets of one base address
 // (64 consecutive dwords per load, so conflict-free), the base passed through an empty asm each
 // iteration so that the loads cannot be hoisted out of the loop; one XOR per loaded value keeps the
@@ -140,7 +188,8 @@ int timed(int reps, float* us, Launch launch) {
 extern "C" {
 
 // kind: 0 = LDS atomic add (no return), 1 = LDS read 32-bit, 2 = LDS write 32-bit, 3 = LDS read
-// 128-bit.  blocks workgroups of 1024 threads, iters loop iterations of 16 instructions (8 for
+// 128-bit, 4 = LDS atomic add with return, 5 = vote pair (add with return + subtract; one lane-op
+// counts the pair).  blocks workgroups of 1024 threads, iters loop iterations of 16 instructions (8 for
 // kind 3) per wave.  out: device scratch of blocks * 1024 dwords (written only in impossible cases).
 // *lane_ops = lane-operations of one launch; *us = average launch time.  Returns 0 or -1.
 int probe_lds(int kind, int blocks, int iters, int reps, uint32_t* out, double* lane_ops, float* us) {
@@ -152,6 +201,8 @@ int probe_lds(int kind, int blocks, int iters, int reps, uint32_t* out, double* 
         case 1: return timed(reps, us, [&] { hipLaunchKernelGGL(k_lds_read32, dim3(blocks), dim3(kThreads), 0, nullptr, iters, out); });
         case 2: return timed(reps, us, [&] { hipLaunchKernelGGL(k_lds_write32, dim3(blocks), dim3(kThreads), 0, nullptr, iters, out); });
         case 3: return timed(reps, us, [&] { hipLaunchKernelGGL(k_lds_read128, dim3(blocks), dim3(kThreads), 0, nullptr, iters, out); });
+        case 4: return timed(reps, us, [&] { hipLaunchKernelGGL(k_lds_atomic_rtn, dim3(blocks), dim3(kThreads), 0, nullptr, iters, out); });
+        case 5: return timed(reps, us, [&] { hipLaunchKernelGGL(k_lds_vote_pair, dim3(blocks), dim3(kThreads), 0, nullptr, iters, out); });
         default: return -1;
     }
 }

@@ -44,7 +44,7 @@ class Hits(C.Structure):
 
 class Tuning(C.Structure):
     _fields_ = [("vote_threads", C.c_int32), ("vote_grid", C.c_int32), ("peak_planes", C.c_int32),
-                ("vote_cols", C.c_int32), ("assign_blocks", C.c_int32)]
+                ("vote_cols", C.c_int32), ("assign_blocks", C.c_int32), ("prep_rows", C.c_int32)]
 
 
 class VertexGrid(C.Structure):
@@ -120,6 +120,9 @@ def _load() -> C.CDLL:
     L.hough_batch_ws_bytes.restype = S; L.hough_batch_ws_bytes.argtypes = [P, C.c_int32, C.c_int32]
     L.hough_run_batch.restype = C.c_int; L.hough_run_batch.argtypes = [P, C.POINTER(Batch), P]
     L.hough_run_batch_noalloc.restype = C.c_int; L.hough_run_batch_noalloc.argtypes = [P, C.POINTER(Batch), P]
+    L.hough_assign_cr_ws_bytes.restype = S; L.hough_assign_cr_ws_bytes.argtypes = [P, C.c_int32, C.c_int32]
+    L.hough_assign_cr.restype = C.c_int
+    L.hough_assign_cr.argtypes = [P, C.POINTER(Hits), P, C.c_int32, P, P, C.c_int32, P, S, P, S, P, P]
     L.hough_batch_graph_create.restype = C.c_int
     L.hough_batch_graph_create.argtypes = [P, C.POINTER(Batch), P, C.POINTER(C.c_void_p)]
     L.hough_graph_launch.restype = C.c_int; L.hough_graph_launch.argtypes = [P, P]
@@ -134,7 +137,7 @@ EXPORTED = ["hough_plan_create", "hough_plan_destroy", "hough_acc_bytes", "hough
             "hough_assign", "hough_zvote", "hough_fit", "hough_plan_arclen_table", "hough_strerror", "hough_plan_set_tuning", "hough_plan_get_tuning", "hough_plan_set_vote_events",
             "hough_batch_ws_bytes", "hough_run_batch", "hough_run_batch_noalloc", "hough_batch_graph_create",
             "hough_graph_launch",
-            "hough_graph_destroy", "hough_fit_batch", "hough_vote_cr", "hough_vertex_plan_create", "hough_vertex_plan_destroy", "hough_vertex_set_groups",
+            "hough_graph_destroy", "hough_fit_batch", "hough_vote_cr", "hough_assign_cr_ws_bytes", "hough_assign_cr", "hough_vertex_plan_create", "hough_vertex_plan_destroy", "hough_vertex_set_groups",
             "hough_vertex_get_groups", "hough_vertex_vote_ws_bytes", "hough_vertex_peaks_ws_bytes",
             "hough_vertex_vote", "hough_vertex_peaks", "hough_vertex_table", "hough_vertex_batch_vote_ws_bytes",
             "hough_vertex_batch_peaks_ws_bytes", "hough_vertex_vote_batch", "hough_vertex_peaks_batch"]
@@ -210,11 +213,12 @@ class Plan:
         t = Tuning()
         _check(lib.hough_plan_get_tuning(self.handle, C.byref(t)), "hough_plan_get_tuning")
         return dict(vote_threads=t.vote_threads, vote_grid=t.vote_grid, peak_planes=t.peak_planes,
-                    vote_cols=t.vote_cols, assign_blocks=t.assign_blocks)
+                    vote_cols=t.vote_cols, assign_blocks=t.assign_blocks, prep_rows=t.prep_rows)
 
     def set_tuning(self, vote_threads: int = 1024, vote_grid: int = 0, peak_planes: int = 8, vote_cols: int = 0,
-                   assign_blocks: int = 0) -> None:
-        t = Tuning(int(vote_threads), int(vote_grid), int(peak_planes), int(vote_cols), int(assign_blocks))
+                   assign_blocks: int = 0, prep_rows: int = 0) -> None:
+        t = Tuning(int(vote_threads), int(vote_grid), int(peak_planes), int(vote_cols), int(assign_blocks),
+                   int(prep_rows))
         _check(lib.hough_plan_set_tuning(self.handle, C.byref(t)), "hough_plan_set_tuning")
 
     def set_vote_events(self, start=None, stop=None) -> None:
@@ -271,6 +275,21 @@ def vote_cr(plan: Plan, hits: Hits, acc: torch.Tensor, status: torch.Tensor, str
     if acc.dtype != torch.int32:
         raise HoughError("hough_vote_cr needs an int32 accumulator")
     _check(lib.hough_vote_cr(plan.handle, C.byref(hits), _ptr(acc), _ptr(status), _stream(stream)), "hough_vote_cr")
+
+
+def assign_cr_ws_bytes(plan: Plan, cap_peaks: int, cap_pairs: int) -> int:
+    return int(lib.hough_assign_cr_ws_bytes(plan.handle, int(cap_peaks), int(cap_pairs)))
+
+
+def assign_cr(plan: Plan, hits: Hits, peaks: torch.Tensor, offsets: torch.Tensor, hit_idx: torch.Tensor,
+              ws: torch.Tensor, ws_cr: torch.Tensor, status: torch.Tensor, stream=None) -> None:
+    """Hit lists of the candidates of a per-hit-radius accumulator (after vote_cr and peaks on `ws`)."""
+    cap_peaks, cap_pairs = int(peaks.shape[0]), int(hit_idx.numel())
+    if offsets.numel() < cap_peaks + 1:
+        raise HoughError("offsets must hold cap_peaks + 1 entries")
+    _check(lib.hough_assign_cr(plan.handle, C.byref(hits), _ptr(peaks), cap_peaks, _ptr(offsets), _ptr(hit_idx),
+                               cap_pairs, _ptr(ws), ws.numel(), _ptr(ws_cr), ws_cr.numel(), _ptr(status),
+                               _stream(stream)), "hough_assign_cr")
 
 
 def vote_prepared(plan: Plan, acc: torch.Tensor, ws: torch.Tensor, status: torch.Tensor, stream=None) -> None:

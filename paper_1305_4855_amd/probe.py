@@ -2,7 +2,8 @@
 kernels' roofline fractions are taken against.
 
     lds(kind)  conflict-free LDS operations of 64-lane waves, 16 independent instructions per loop
-               iteration: "atomic" (ds_add_u32, no return), "read32", "write32", "read128"
+               iteration: "atomic" (ds_add_u32, no return), "read32", "write32", "read128",
+               "atomic_rtn" (ds_add_rtn_u32), "vote_pair" (add with return + subtract of one word)
     hbm(kind)  streaming "copy" (bytes read + written) or "fill" (bytes written) of a large buffer
 """
 from __future__ import annotations
@@ -14,9 +15,9 @@ import torch
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libroofline_probe.so")
-LDS_KINDS = {"atomic": 0, "read32": 1, "write32": 2, "read128": 3}
+LDS_KINDS = {"atomic": 0, "read32": 1, "write32": 2, "read128": 3, "atomic_rtn": 4, "vote_pair": 5}
 HBM_KINDS = {"copy": 0, "fill": 1}
-LDS_BYTES = {"atomic": 4, "read32": 4, "write32": 4, "read128": 16}
+LDS_BYTES = {"atomic": 4, "read32": 4, "write32": 4, "read128": 16, "atomic_rtn": 4, "vote_pair": 4}
 
 
 def _load() -> C.CDLL:

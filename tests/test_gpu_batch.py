@@ -176,7 +176,11 @@ def test_graph_replays_match_eager(H):
 @pytest.mark.parametrize("tune", [dict(vote_threads=512, vote_grid=64, peak_planes=4),
                                   dict(vote_threads=256, vote_grid=7, peak_planes=16),
                                   dict(vote_threads=512, vote_grid=512, peak_planes=32),
-                                  dict(vote_threads=1024, vote_grid=0, peak_planes=3)])
+                                  dict(vote_threads=1024, vote_grid=0, peak_planes=3),
+                                  dict(vote_threads=512, vote_grid=100, peak_planes=8, vote_cols=4, assign_blocks=3,
+                                       prep_rows=16),
+                                  dict(vote_threads=1024, vote_grid=2048, peak_planes=32, vote_cols=64,
+                                       assign_blocks=1, prep_rows=256)])
 def test_results_identical_across_launch_shapes(H, tune):
     cfg, events = _small_batch_events()
     plan = H.Plan(cfg, max_hits=4096)

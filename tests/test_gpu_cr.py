@@ -87,3 +87,72 @@ def test_cr_rejects_int16_accumulator(H):
     st = torch.zeros(H.STATUS_BYTES // 4, dtype=torch.int32, device="cuda")
     with pytest.raises(H.HoughError, match="unsupported"):
         H.vote_cr(plan, H.make_hits(x, y, lay), acc, st)
+
+
+def _run_assign(H, cfg, ev, cap_peaks=1 << 16, cap_pairs=1 << 22):
+    """vote_cr -> peaks -> assign_cr -> fit on the GPU; returns (status, candidates, offsets, lists, fit)."""
+    plan = H.Plan(cfg, max_hits=max(ev.n, 1))
+    acc = torch.empty((cfg.n_d0, cfg.n_qpt, cfg.n_phi), dtype=torch.int32, device="cuda")
+    st = torch.zeros(H.STATUS_BYTES // 4, dtype=torch.int32, device="cuda")
+    ws = torch.empty(plan.ws_bytes(cap_peaks), dtype=torch.uint8, device="cuda")
+    ws_cr = torch.empty(H.assign_cr_ws_bytes(plan, cap_peaks, cap_pairs), dtype=torch.uint8, device="cuda")
+    pk = torch.empty((cap_peaks, 4), dtype=torch.int32, device="cuda")
+    offs = torch.full((cap_peaks + 1,), -7, dtype=torch.int32, device="cuda")
+    hit_idx = torch.full((cap_pairs,), -7, dtype=torch.int32, device="cuda")
+    x, y, lay, _ = H.hits_to_device(ev)
+    hits = H.make_hits(x, y, lay)
+    H.vote_cr(plan, hits, acc, st)
+    H.peaks(plan, acc, cfg.threshold, pk, ws, st)
+    H.assign_cr(plan, hits, pk, offs, hit_idx, ws, ws_cr, st)
+    fit = torch.full((cap_peaks, 4), 7.0, dtype=torch.float64, device="cuda")
+    H.fit(plan, hits, offs, hit_idx, st, fit)
+    torch.cuda.synchronize()
+    s = H.status_dict(st)
+    n = min(s["n_peaks"], cap_peaks)
+    return (s, pk[:n].cpu().numpy(), offs[: n + 1].cpu().numpy().astype(np.int64),
+            hit_idx[: min(s["n_pairs"], cap_pairs)].cpu().numpy(), fit[:n].cpu().numpy())
+
+
+@pytest.mark.parametrize("cfg,tracks,eid", [
+    (configs.C7, 100, 10), (configs.C6, 50, 11), (configs.C7.with_(n_qpt=64, n_phi=512), 300, 12),
+    (configs.C2.with_(n_phi=128, n_qpt=64, n_d0=8, smear_xy_cm=0.04), 40, 13)])
+def test_cr_assign_equals_oracle(H, oracle_mod, cfg, tracks, eid):
+    """Lists of every candidate of a per-hit-radius accumulator, and their fits, equal the oracle's."""
+    O = oracle_mod
+    cfg = cfg.with_(n_tracks=tracks, n_events=1)
+    ev = synth.make_event(cfg, eid)
+    print(f"[cr-assign] {cfg.name} n_hits={ev.n}", flush=True)
+    st, pk, offs, hit_idx, fit = _run_assign(H, cfg, ev)
+    g = O.Cfg(cfg)
+    ref, _ = O.vote_cr(g, ev)
+    n, pk_ref = O.peaks(g, ref, cfg.threshold)
+    np.testing.assert_array_equal(pk, pk_ref)
+    o_ref, h_ref, tot = O.assign_cr(g, ev, pk_ref)
+    assert st["n_pairs"] == tot and st["flags"] == 0
+    np.testing.assert_array_equal(offs, o_ref)
+    np.testing.assert_array_equal(hit_idx, h_ref)
+    np.testing.assert_array_equal(fit, O.fit(ev, o_ref, h_ref))
+
+
+def test_cr_assign_full_size_and_cut(H, oracle_mod):
+    """The 4000-track paper-detector event: 300 sampled lists equal the oracle's; then with a pair
+    capacity that cuts the lists, the kept entries are the same and the cut is flagged."""
+    O = oracle_mod
+    cfg = configs.C7.with_(n_tracks=4000)
+    ev = synth.make_event(cfg, 0)
+    print(f"[cr-assign] full size n_hits={ev.n}", flush=True)
+    st, pk, offs, hit_idx, _ = _run_assign(H, cfg, ev, cap_pairs=1 << 24)
+    g = O.Cfg(cfg)
+    n = pk.shape[0]
+    assert st["flags"] == 0 and st["n_pairs"] == int(pk[:, 3].sum()) and n > 1000
+    np.testing.assert_array_equal(np.diff(offs), pk[:, 3])
+    sel = np.unique(np.random.default_rng(5).choice(n, 300, replace=False))
+    o_ref, h_ref, _ = O.assign_cr(g, ev, pk[sel])
+    for i, p in enumerate(sel):
+        np.testing.assert_array_equal(hit_idx[offs[p]:offs[p + 1]], h_ref[o_ref[i]:o_ref[i + 1]], err_msg=str(p))
+    cap = int(st["n_pairs"] // 3) + 5
+    st2, pk2, offs2, hit2, fit2 = _run_assign(H, cfg, ev, cap_pairs=cap)
+    assert st2["flags"] & 2 and st2["n_pairs"] == st["n_pairs"]
+    np.testing.assert_array_equal(offs2, offs)
+    np.testing.assert_array_equal(hit2, hit_idx[:cap])
+    assert (fit2[offs2[1:] > cap, 2] == -2.0).all()
