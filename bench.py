@@ -9,8 +9,10 @@ maxima of their 3x3x3 neighbourhood, and their CSR hit lists.  Inputs are
 resident in HBM before the timed region; every step recomputes everything.
 
 Prints one JSON line (see the keys below).  The `roofline` object is for the
-dominant kernel (the vote), timed with HIP events on the stream it runs on;
-`cpu_baseline` times the CPU oracle on the same event.
+dominant kernel of the step (the longer of the window-table vote and the
+assignment, both HBM-bound), timed inside the timed region by HIP events that
+the kernel's own launch records on the stream it runs on; `kernel_rooflines`
+holds both.  `cpu_baseline` times the CPU oracle on the same event.
 """
 from __future__ import annotations
 
@@ -29,11 +31,13 @@ sys.path.insert(0, ROOT)
 
 METRIC = "events/s and hit-votes/s at 1 MI355X (batched vs plain), p99 event latency"
 # MI355X: 256 CUs at 2.4 GHz; an LDS atomic of a 64-wide wave (ds_add_u32) issues once per 4 clocks per CU
-# (16 lanes/clk/CU), so 256 * 2.4e9 * 16 = 9.83e12 atomic adds/s; one hit-vote is one LDS atomic.
+# (16 lanes/clk/CU), so 256 * 2.4e9 * 16 = 9.83e12 atomic adds/s.  This unit-count figure is only the
+# fallback: the micro-benchmarks measure the rate on the device and replace it.
 CUS, CLOCK_HZ, LDS_ATOMIC_LANES_PER_CLK = 256, 2.4e9, 16
 LDS_ATOMIC_PEAK_GVOTES = CUS * CLOCK_HZ * LDS_ATOMIC_LANES_PER_CLK / 1e9
+VOTE_PAIR_PEAK_GOPS = LDS_ATOMIC_PEAK_GVOTES / 2
 HBM_PEAK_GBS = 8000.0
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "vote_c2_traffic.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_c2.json")
 KERNEL_SRC = os.path.join(ROOT, "paper_1305_4855_amd", "csrc", "hough.hip")
 
 
@@ -115,8 +119,24 @@ def bench_roofline_probe():
         r = probe.hbm(k)
         out[f"hbm_{k}"] = {"gb_per_s": r["gb_per_s"], "bytes": r["bytes"], "us_per_launch": r["us_per_launch"]}
     out["note"] = ("LDS rates of 1024-thread workgroups, 16 independent instructions per loop iteration; "
-                   "the LDS-atomic rooflines use lds_atomic.lane_ops_per_s as their peak")
+                   "the LDS-atomic rooflines use lds_atomic.lane_ops_per_s as their peak, the r-z vote's "
+                   "lds_vote_pair.lane_ops_per_s (add-with-return plus restoring add)")
     return out
+
+
+CHAIN_BYTES_NOTE = ("algorithmic HBM bytes of one pass of the chain: accumulator written by the vote and read by the "
+                    "peak finder, 16-byte candidate rows written and read again by the assignment, 4-byte CSR "
+                    "offsets and 4-byte hit indices written (hits and tables are cache-resident)")
+
+
+def chain_hbm_bytes(acc_bytes: int, candidates: int, pairs: int, n_events: int) -> int:
+    return 2 * acc_bytes + 32 * candidates + 4 * (candidates + n_events) + 4 * pairs
+
+
+def assign_hbm_bytes(candidates: int, pairs: int) -> int:
+    """Algorithmic bytes of one assignment launch: each candidate's 16-byte row read and its 4-byte
+    CSR offset written, the closing offset, and one 4-byte hit index per (hit, candidate) pair."""
+    return 20 * candidates + 4 + 4 * pairs
 
 
 def bufs_max_pairs(st_i32: np.ndarray) -> int:
@@ -180,6 +200,7 @@ def bench_batched(H, torch, n_events: int, reps: int):
     st = bufs.status.cpu().numpy().view("int32")
     votes = int(bufs.status.cpu().numpy().view("int64")[:, 1].sum())
     peaks = int(st[:, 4].sum())
+    pairs = int(st.view(np.int64)[:, 3].sum())
     flags = check_flags(st, "batched")
     # the persistent vote kernel of the batch, timed by its own start/end events
     vp = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
@@ -193,7 +214,9 @@ def bench_batched(H, torch, n_events: int, reps: int):
     torch.cuda.synchronize()
     plan.set_vote_events(None, None)
     vote_batch_ms = sum(a.elapsed_time(b) for a, b in vp) / reps
-    vote_rate = votes / (vote_batch_ms * 1e-3) / 1e9
+    vote_bytes = n_events * plan.acc_bytes
+    vote_gbs = vote_bytes / (vote_batch_ms * 1e-3) / 1e9
+    chain_bytes = chain_hbm_bytes(n_events * plan.acc_bytes, peaks, pairs, n_events)
     # the same chain captured once in a hipGraph
     gstream = torch.cuda.Stream()
     graph = H.Graph(bufs, cfg.threshold, gstream)
@@ -227,7 +250,7 @@ def bench_batched(H, torch, n_events: int, reps: int):
         "workload": f"batch of {n_events} uneven events (c3): Gamma-Poisson tracks mean 500 in [50, 2000], "
                     f"5% displaced, 20% noise, 512x256x64 int32",
         "hits": total, "hits_min": min(e.n for e in events), "hits_max": max(e.n for e in events),
-        "hit_votes": votes, "candidates": peaks, "tuning": tuning,
+        "hit_votes": votes, "candidates": peaks, "pairs": pairs, "tuning": tuning,
         "cap_peaks": cap_peaks, "cap_pairs": cap_pairs, "max_candidates_per_event": int(st[:, 4].max()),
         "max_pairs_per_event": int(bufs_max_pairs(st)), **flags,
         "events_per_s_batched": round(n_events / t_batch, 2),
@@ -237,10 +260,16 @@ def bench_batched(H, torch, n_events: int, reps: int):
         "speedup_batched_vs_plain": round(t_plain / t_batch, 3),
         "ms_per_batch": round(t_batch * 1e3, 4), "ms_per_batch_graph": round(t_graph * 1e3, 4),
         "ms_plain_all_events": round(t_plain * 1e3, 4),
-        "roofline_vote": {"kernel": "k_vote (persistent, whole batch)", "bound": "alu",
-                          "achieved": round(vote_rate, 1), "peak": LDS_ATOMIC_PEAK_GVOTES,
-                          "unit": "Gvote/s (LDS atomic adds)", "frac": round(vote_rate / LDS_ATOMIC_PEAK_GVOTES, 4),
-                          "avg_launch_ms": round(vote_batch_ms, 4), "votes_per_launch": votes},
+        "roofline_vote": {"kernel": "k_vote_pt (persistent, whole batch)", "bound": "hbm",
+                          "achieved": round(vote_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                          "frac": round(vote_gbs / HBM_PEAK_GBS, 4), "avg_launch_ms": round(vote_batch_ms, 4),
+                          "bytes_per_launch": vote_bytes, "hit_votes_per_s": round(votes / (vote_batch_ms * 1e-3), 1),
+                          "bytes_note": "every accumulator written once (the window-count tables it reads are "
+                                        "cache-resident)"},
+        "chain_hbm": {"bytes_per_batch": chain_bytes,
+                      "achieved": round(chain_bytes / t_batch / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                      "frac": round(chain_bytes / t_batch / 1e9 / HBM_PEAK_GBS, 4),
+                      "bytes_note": CHAIN_BYTES_NOTE},
     }
 
 
@@ -306,6 +335,12 @@ def bench_large_grid(H, torch, reps: int):
     flags = check_flags(st, "large grid")
     del bufs
     zv_ms = times[True] - times[False]
+    # one (hit, cot(theta) row) evaluation of the r-z vote is an LDS add-with-return and, for a hit
+    # that is not the first of its candidate in the z0 bin, the restoring add: the vote-pair
+    # micro-benchmark measures exactly that pair
+    zv_evals = pairs * cfg.n_cot
+    zv_rate = zv_evals / (zv_ms * 1e-3) / 1e9
+    pair_peak = VOTE_PAIR_PEAK_GOPS
     return {
         "workload": f"batch of {len(events)} events (c4): 600 prompt tracks + 2 displaced vertices, 20% noise, "
                     f"1024x512x128 int16, then 128x128 cot(theta) x z0 vote per candidate",
@@ -317,6 +352,13 @@ def bench_large_grid(H, torch, reps: int):
         "events_per_s_plain": round(len(events) / plain_ms * 1e3, 2),
         "speedup_batched_vs_plain": round(plain_ms / times[True], 3),
         "zvote_ms_per_event": round(zv_ms / len(events), 4),
+        "roofline_zvote": {"kernel": "k_zvote", "bound": "lds_atomic", "achieved": round(zv_rate, 1),
+                           "peak": round(pair_peak, 1), "unit": "G (hit, row) evaluations/s",
+                           "frac": round(zv_rate / pair_peak, 4), "evaluations_per_batch": zv_evals,
+                           "ms_per_batch": round(zv_ms, 3),
+                           "peak_note": "LDS add-with-return plus restoring add per evaluation, as measured by "
+                                        "the vote-pair micro-benchmark (unit-count fallback: half the LDS-atomic "
+                                        "lane rate)"},
         "vertex_ms_per_batch": round(vertex_ms, 3), "vertex_ms_per_event": round(vertex_ms / len(events), 4),
         "vertex_votes": vertex_votes, "vertex_candidates": vertex_cands,
         "vertex_gvotes_per_s": round(vertex_votes / (vertex_ms * 1e-3) / 1e9, 1),
@@ -390,7 +432,7 @@ def bench_vertex(H, torch, reps: int):
     stv = H.status_dict(vb.status)
     votes = stv["n_votes"]
     achieved = votes / (vote_ms * 1e-3) / 1e9
-    peak = 256 * 2.4e9 * 16 / 1e9  # LDS atomic lanes per second, as for the first vote
+    peak = LDS_ATOMIC_PEAK_GVOTES  # one LDS atomic add per vertex vote
     return {
         "workload": "vertex space of one large-grid event (c4 event 0): every first-stage candidate votes into "
                     f"{cfg.n_vr} radius rows x {cfg.n_vphi} azimuth bins over [{cfg.vr_min}, {cfg.vr_max}) cm, "
@@ -398,11 +440,16 @@ def bench_vertex(H, torch, reps: int):
         "hits": ev.n, "candidates": st1["n_peaks"], "vertex_votes": votes, "vertex_candidates": stv["n_peaks"],
         "groups": vp.groups, "first_stage_ms": round(first_ms, 4), "vertex_vote_ms": round(vote_ms, 4),
         "vertex_peaks_ms": round(peaks_ms, 4), "second_over_first": round((vote_ms + peaks_ms) / first_ms, 3),
-        "roofline": {"kernel": "k_vvote + k_vreduce", "bound": "alu", "achieved": round(achieved, 1),
-                     "peak": peak, "unit": "Gvote/s", "frac": round(achieved / peak, 4), "traffic": None},
+        "roofline": {"kernel": "k_vvote + k_vreduce", "bound": "lds_atomic", "achieved": round(achieved, 1),
+                     "peak": round(peak, 1), "unit": "Gvote/s (LDS atomic adds)", "frac": round(achieved / peak, 4),
+                     "traffic": None},
         "note": "per-call time of back-to-back calls; the vote time includes the reduction of the partial "
                 "vertex spaces (split in the kernel trace)",
     }
+
+
+REFINE_WINDOW = 16      # 1/8 of a phi0 bin (frac_bits 7)
+REFINE_MIN_LAYERS = 8   # of the ten layers
 
 
 def bench_quality(H, torch):
@@ -437,11 +484,34 @@ def bench_quality(H, torch):
         chain_ms = a.elapsed_time(b) / 20
         share = quality.quality(r["offsets"], r["hit_idx"], ev.track_id, ntr, cfg.threshold)
         param = quality.quality_params(cfg, ev.truth, ev.track_id, r["peaks"], cfg.threshold)
+        # background suppression inside the bin: one hit per layer from the densest window of the
+        # angle inside the bin (1/8 of a bin); candidates keeping >= 8 of the 10 layers
+        n_c = r["peaks"].shape[0]
+        out_h = torch.empty((max(n_c, 1), cfg.n_layers), dtype=torch.int32, device="cuda")
+        out_l = torch.empty(max(n_c, 1), dtype=torch.int32, device="cuda")
+        H.refine(plan, bufs.peaks[: max(n_c, 1)], bufs.offsets, bufs.hit_idx, bufs.ws, bufs.status,
+                 REFINE_WINDOW, out_h, out_l)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(5):
+            H.refine(plan, bufs.peaks[: max(n_c, 1)], bufs.offsets, bufs.hit_idx, bufs.ws, bufs.status,
+                     REFINE_WINDOW, out_h, out_l)
+        b.record(stream)
+        torch.cuda.synchronize()
+        refine_ms = a.elapsed_time(b) / 5
+        ro, rh, kept = quality.refined_csr(out_h[:n_c].cpu().numpy(), out_l[:n_c].cpu().numpy(), REFINE_MIN_LAYERS)
+        share_r = quality.quality(ro, rh, ev.track_id, ntr, cfg.threshold)
+        param_r = quality.quality_params(cfg, ev.truth, ev.track_id, r["peaks"][kept], cfg.threshold)
         out.append({"workload": cfg.name, "tracks": ntr, "hits": ev.n,
                     "grid": f"{cfg.n_phi}x{cfg.n_qpt}x{cfg.n_d0}", "threshold": cfg.threshold,
                     "candidates": r["status"]["n_peaks"], "chain_ms_per_event": round(chain_ms, 4),
                     "hit_share": {k: share[k] for k in ("efficiency", "purity", "duplicates_per_found_track")},
-                    "parameter_space": {k: param[k] for k in ("efficiency", "purity")}})
+                    "parameter_space": {k: param[k] for k in ("efficiency", "purity")},
+                    "suppressed": {"window": REFINE_WINDOW, "min_layers": REFINE_MIN_LAYERS,
+                                   "candidates": int(kept.size), "refine_ms": round(refine_ms, 4),
+                                   "hit_share": {k: share_r[k] for k in ("efficiency", "purity",
+                                                                         "duplicates_per_found_track")},
+                                   "parameter_space": {k: param_r[k] for k in ("efficiency", "purity")}}})
         del bufs, plan
     return {"note": "context, not a parity figure: the paper quotes about 80 % efficiency at a few thousand "
                     "tracks and 86 % for curved prompt tracks, with comparable purity, on its own simulation",
@@ -563,22 +633,34 @@ def bench_plain(H, torch, args):
 
     for _ in range(args.warmup):
         step()
-    # the vote kernel of every timed step records its own start and end (kernel-accurate HIP
-    # events, no extra packets on the stream); the events are created before the timed region
-    pairs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-             for _ in range(args.steps)]
-    for a, b in pairs:
-        a.record(stream)
-        b.record(stream)
+    # kernel durations: in a second pass of K steps, the vote and assignment kernels of every step
+    # record their own start and end (kernel-accurate HIP events, recorded by the kernel's own
+    # dispatch); the events are created beforehand
+    def event_pairs():
+        ps = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(args.steps)]
+        for a, b in ps:
+            a.record(stream)
+            b.record(stream)
+        return ps
+    vpairs, apairs = event_pairs(), event_pairs()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
-        plan.set_vote_events(*pairs[i])
         step()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    # the same K steps again with the two kernels recording their own start and end (the events
+    # cost the stream a few microseconds per step, so the throughput comes from the pass above)
+    for i in range(args.steps):
+        plan.set_vote_events(*vpairs[i])
+        plan.set_assign_events(*apairs[i])
+        step()
+    torch.cuda.synchronize()
     plan.set_vote_events(None, None)
-    vote_kernel_ms = sum(a.elapsed_time(b) for a, b in pairs) / args.steps
+    plan.set_assign_events(None, None)
+    vote_kernel_ms = sum(a.elapsed_time(b) for a, b in vpairs) / args.steps
+    assign_kernel_ms = sum(a.elapsed_time(b) for a, b in apairs) / args.steps
 
     # Per-stage launch durations: each stage launched `reps` times back to back on the same stream
     # between two HIP events (every stage is idempotent on the event's buffers), so the average is
@@ -636,12 +718,30 @@ def bench_plain(H, torch, args):
         raise RuntimeError(f"plain chain: status flags {st['flags']} (candidate or pair capacity too small)")
     ms_per_step = (t1 - t0) * 1e3 / args.steps
     events_per_s = 1e3 / ms_per_step
-    achieved = st["n_votes"] / (vote_ms * 1e-3) / 1e9
-    traffic = None
+    traffic = {}
     if os.path.exists(TRAFFIC_FILE):
         tr = json.load(open(TRAFFIC_FILE))
         if tr.get("kernel_src_sha256_16") == src_hash():
-            traffic = tr.get("hbm_bytes_per_launch")
+            traffic = {k: v["hbm_bytes_per_launch"] for k, v in tr["kernels"].items()}
+    n_peaks = min(st["n_peaks"], bufs.peaks.shape[0])
+    vote_bytes = plan.acc_bytes
+    assign_bytes = assign_hbm_bytes(n_peaks, st["n_pairs"])
+
+    def hbm_roofline(kernel, nbytes, ms, note):
+        gbs = nbytes / (ms * 1e-3) / 1e9
+        return {"kernel": kernel, "bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": traffic.get(kernel),
+                "avg_launch_ms": round(ms, 5), "bytes_per_launch": nbytes, "bytes_note": note}
+    kr = {
+        "k_vote_pt": hbm_roofline("k_vote_pt", vote_bytes, vote_ms,
+                                  "the 32 MiB accumulator written once; the window-count tables it reads "
+                                  "(about 1.3 MB) are cache-resident"),
+        "k_assign_pt": hbm_roofline("k_assign_pt", assign_bytes, assign_kernel_ms,
+                                    "20 bytes per candidate (16-byte row read, 4-byte CSR offset written) plus "
+                                    "4 bytes per (hit, candidate) pair written"),
+    }
+    dominant = max(kr.values(), key=lambda r: r["avg_launch_ms"])
+    chain_bytes = chain_hbm_bytes(plan.acc_bytes, n_peaks, st["n_pairs"], 1)
     out = {
         "metric": METRIC,
         "value": round(events_per_s, 2),
@@ -664,10 +764,13 @@ def bench_plain(H, torch, args):
                       "bad_hits": st["n_bad_hits"]},
         "stages_ms": {k: round(v, 5) for k, v in zip(("prep", "vote", "peaks", "assign"), stage_ms)},
         "stages_note": "each stage launched back to back, per-launch time including launch gaps",
-        "roofline": {"kernel": "k_vote", "bound": "alu", "achieved": round(achieved, 1),
-                     "peak": LDS_ATOMIC_PEAK_GVOTES, "unit": "Gvote/s (LDS atomic adds)",
-                     "frac": round(achieved / LDS_ATOMIC_PEAK_GVOTES, 4), "traffic": traffic,
-                     "avg_launch_ms": round(vote_ms, 5), "votes_per_launch": st["n_votes"]},
+        "roofline": dominant,
+        "kernel_rooflines": kr,
+        "vote_hit_votes_per_s": round(st["n_votes"] / (vote_ms * 1e-3), 1),
+        "chain_hbm": {"bytes_per_step": chain_bytes, "achieved": round(chain_bytes / (ms_per_step * 1e-3) / 1e9, 1),
+                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                      "frac": round(chain_bytes / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                      "bytes_note": CHAIN_BYTES_NOTE},
         "fit": fit,
     }
     return out
@@ -712,9 +815,10 @@ def main() -> int:
            "dtype": "int32", "data": "synthetic"}
     probe_res = None
     if not args.no_roofline_probe:
-        global LDS_ATOMIC_PEAK_GVOTES
+        global LDS_ATOMIC_PEAK_GVOTES, VOTE_PAIR_PEAK_GOPS
         probe_res = bench_roofline_probe()
         LDS_ATOMIC_PEAK_GVOTES = probe_res["lds_atomic"]["lane_ops_per_s"] / 1e9
+        VOTE_PAIR_PEAK_GOPS = probe_res["lds_vote_pair"]["lane_ops_per_s"] / 1e9
         torch.cuda.empty_cache()
     if not args.no_plain:
         out = bench_plain(H, torch, args)

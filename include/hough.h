@@ -153,6 +153,8 @@ int hough_plan_get_tuning(const hough_plan_t* plan, hough_tuning_t* t);
  * elapsed time is the kernel's duration without launch gaps.  Not for plans
  * used by several threads at once.  NULL, NULL switches it off (default). */
 int hough_plan_set_vote_events(hough_plan_t* plan, hipEvent_t start, hipEvent_t stop);
+/* The same for the assignment kernel of plans with the window tables (the others ignore it). */
+int hough_plan_set_assign_events(hough_plan_t* plan, hipEvent_t start, hipEvent_t stop);
 
 /* Sizes in bytes. */
 size_t hough_acc_bytes(const hough_plan_t* plan);             /* n_d0*n_qpt*n_phi*acc_bits/8 */
@@ -254,6 +256,26 @@ int hough_zvote(const hough_plan_t* plan, const hough_hits_t* hits, const hough_
  * Async, stream-ordered; hits->layer and z are not read. */
 int hough_fit(const hough_plan_t* plan, const hough_hits_t* hits, const int32_t* offsets, const int32_t* hit_idx,
               int32_t cap_peaks, int32_t cap_pairs, const hough_status_t* st, double* out, hipStream_t stream);
+
+/* Background suppression inside each candidate's bin (Sec. "Preliminary
+ * Results", efficiency paragraph: efficiency and purity fall as the number of
+ * tracks grows; with many tracks a bin also collects hits of other tracks that
+ * cross it).  The track's own hits agree on phi0 far more closely than the bin
+ * width, so they sit together in the angle inside the bin.  For each of the
+ * first min(st->n_peaks, cap_peaks) candidates, with each listed hit's angle
+ * inside the bin rel = ((PhiM - E) mod 2^M) - b * 2^frac_bits (E the sample of
+ * its layer at the candidate's (l, k)): among the windows [c, c + window) that
+ * begin at a listed hit's rel, the one holding hits of the most distinct
+ * layers, then the most hits, then the lowest c; for each layer present in it,
+ * the hit nearest the window centre (smallest |2 rel - 2c - window|, ties by
+ * the lower hit index).  out_hits (dev) [cap_peaks][n_layers]: that hit or
+ * -1; out_layers (dev) [cap_peaks]: layers of the refined list (0 for an empty
+ * list, -1 for a list cut by cap_pairs).  Uses the prepared hits left in ws by
+ * hough_vote/hough_prep of the same event and the lists of hough_assign;
+ * 1 <= window <= 2^frac_bits.  Async, stream-ordered. */
+int hough_refine(const hough_plan_t* plan, const hough_peak_t* peaks, int32_t cap_peaks, const int32_t* offsets,
+                 const int32_t* hit_idx, int32_t cap_pairs, const void* ws, size_t ws_bytes, const hough_status_t* st,
+                 int32_t window, int32_t* out_hits, int32_t* out_layers, hipStream_t stream);
 
 /* The vote with each hit's own radius instead of its layer's (a detector
  * whose hits are smeared off the layer circles, like the paper's model with a

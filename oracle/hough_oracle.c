@@ -712,6 +712,89 @@ int64_t or_assign_cr(const or_cfg_t* g, int32_t n, const float* x, const float* 
     return pos;
 }
 
+/* ------------------------------------------------------------------------ */
+/* Background suppression inside a candidate's bin (refinement).  The hits   */
+/* of a crowded bin come from the track and from other tracks crossing the   */
+/* bin; the track's own hits agree on phi0 far more closely than the bin     */
+/* width, at its (d0, q/pT), so they sit together in the angle inside the    */
+/* bin.  For candidate p = (l, k, b) with hit list H (step 7) and each listed */
+/* hit's angle inside the bin rel = ((PhiM - E) mod 2^M) - b * 2^F (E the    */
+/* sample of its layer at (l, k)): among the windows [c, c + w) that begin  */
+/* at a listed hit's rel, take the one holding hits of the most distinct    */
+/* layers, then the most hits, then the lowest c; the refined list keeps,   */
+/* for every layer present in the window, the hit nearest the window centre */
+/* c + w/2 (smallest |2 rel - 2c - w|, ties by the lower hit index).         */
+/* out_hits[p * n_layers + L] = that hit or -1; out_layers[p] = the number  */
+/* of layers of the refined list (0 for an empty list).  Returns the total  */
+/* number of refined entries.                                               */
+/* ------------------------------------------------------------------------ */
+int64_t or_refine(const or_cfg_t* g, int32_t n, const float* x, const float* y, const uint8_t* layer,
+                  int32_t n_peaks, const int32_t* peaks, const int64_t* offsets, const int32_t* hit_idx, int32_t w,
+                  int32_t* out_hits, int32_t* out_layers)
+{
+    int32_t M = or_angle_bits(g), F = g->frac_bits, NL = g->n_layers, p, i, j, L;
+    uint32_t mask = (M >= 32) ? 0xffffffffu : ((1u << M) - 1u);
+    uint32_t* phi = (uint32_t*)malloc(sizeof(uint32_t) * (size_t)(n > 0 ? n : 1));
+    uint8_t* ok = (uint8_t*)malloc((size_t)(n > 0 ? n : 1));
+    int64_t total = 0;
+    or_prep(n, x, y, layer, NL, phi, ok);
+    for (p = 0; p < n_peaks; p++) {
+        int32_t lp = peaks[4 * p], kp = peaks[4 * p + 1], bp = peaks[4 * p + 2];
+        double d = or_d0_centre(g, lp), c = or_curvature(g, kp);
+        int64_t q0 = offsets[p], m = offsets[p + 1] - offsets[p];
+        int32_t E[64], best_l = -1, best_n = -1, best_c = 0;
+        int64_t* rel = (int64_t*)malloc(sizeof(int64_t) * (size_t)(m > 0 ? m : 1));
+        for (L = 0; L < NL; L++) {
+            if (!or_sample(g->r_cm[L], c, d, M, &E[L])) E[L] = 0;
+            out_hits[(int64_t)p * NL + L] = -1;
+        }
+        for (i = 0; i < m; i++) {
+            int32_t h = hit_idx[q0 + i];
+            uint32_t phiM = phi[h] >> (32 - M);
+            rel[i] = (int64_t)((phiM - (uint32_t)E[layer[h]]) & mask) - ((int64_t)bp << F);
+        }
+        for (i = 0; i < m; i++) {
+            int64_t c0 = rel[i];
+            uint32_t lay_mask = 0;
+            int32_t cnt = 0, nl = 0;
+            for (j = 0; j < m; j++) {
+                if (rel[j] >= c0 && rel[j] < c0 + w) {
+                    lay_mask |= 1u << layer[hit_idx[q0 + j]];
+                    cnt++;
+                }
+            }
+            for (L = 0; L < NL; L++) nl += (lay_mask >> L) & 1u;
+            if (nl > best_l || (nl == best_l && cnt > best_n) || (nl == best_l && cnt == best_n && c0 < best_c)) {
+                best_l = nl;
+                best_n = cnt;
+                best_c = (int32_t)c0;
+            }
+        }
+        out_layers[p] = m > 0 ? best_l : 0;
+        for (L = 0; L < NL && m > 0; L++) {
+            int32_t pick = -1;
+            int64_t pick_d = 0;
+            for (j = 0; j < m; j++) {
+                int32_t h = hit_idx[q0 + j];
+                int64_t dist;
+                if (layer[h] != L || !(rel[j] >= best_c && rel[j] < (int64_t)best_c + w)) continue;
+                dist = 2 * rel[j] - 2 * (int64_t)best_c - w;
+                if (dist < 0) dist = -dist;
+                if (pick < 0 || dist < pick_d || (dist == pick_d && h < pick)) {
+                    pick = h;
+                    pick_d = dist;
+                }
+            }
+            out_hits[(int64_t)p * NL + L] = pick;
+            if (pick >= 0) total++;
+        }
+        free(rel);
+    }
+    free(phi);
+    free(ok);
+    return total;
+}
+
 /* Threads of the OpenMP loops above (the vote over d0 planes); for timing the oracle at a chosen
  * thread count.  Returns the count in effect. */
 int or_set_threads(int n)

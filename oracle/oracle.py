@@ -95,6 +95,8 @@ def load(path: str) -> C.CDLL:
     L.or_hit_radius.restype = C.c_double; L.or_hit_radius.argtypes = [C.c_int32, C.c_int32]
     L.or_vote_cr.restype = C.c_int64; L.or_vote_cr.argtypes = [P, C.c_int32, P, P, P, P]
     L.or_set_threads.restype = C.c_int; L.or_set_threads.argtypes = [C.c_int]
+    L.or_refine.restype = C.c_int64
+    L.or_refine.argtypes = [P, C.c_int32, P, P, P, C.c_int32, P, P, P, C.c_int32, P, P]
     L.or_assign_cr.restype = C.c_int64
     L.or_assign_cr.argtypes = [P, C.c_int32, P, P, P, C.c_int32, P, P, P, C.c_int64]
     L.or_vertex_radius.restype = C.c_double
@@ -351,3 +353,19 @@ def assign_cr(cfg: Cfg, ev, pk: np.ndarray, cap_pairs: int = 1 << 26):
 def set_threads(n: int) -> int:
     """Threads of the oracle's OpenMP loops (0: leave as is); returns the count in effect."""
     return int(lib().or_set_threads(int(n)))
+
+
+def refine(cfg: Cfg, ev, pk: np.ndarray, offs: np.ndarray, hit_idx: np.ndarray, w: int):
+    """Refined lists of candidates (background suppression inside the bin): ([n][n_layers] hit or -1,
+    [n] layers covered)."""
+    x, y, lay = _hits(ev)
+    pk = np.ascontiguousarray(pk, dtype=np.int32).reshape(-1, 4)
+    offs = np.ascontiguousarray(offs, dtype=np.int64)
+    hit_idx = np.ascontiguousarray(hit_idx, dtype=np.int32)
+    n = pk.shape[0]
+    nl = len(cfg.src.radii_cm)
+    out = np.full((max(n, 1), nl), -1, dtype=np.int32)
+    layers = np.zeros(max(n, 1), dtype=np.int32)
+    lib().or_refine(cfg.ptr, x.shape[0], _p(x), _p(y), _p(lay), n, _p(pk), _p(offs), _p(hit_idx), int(w),
+                    _p(out), _p(layers))
+    return out[:n], layers[:n]

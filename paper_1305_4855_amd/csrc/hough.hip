@@ -131,6 +131,7 @@ struct hough_plan {
     ZGrid zg;
     int32_t* d_S;    // [n_layers][n_d0][n_qpt] Q16.16 arc length to the layer, -1 = invalid (zvote only)
     hipEvent_t vote_start, vote_stop;  // recorded by every vote launch when set (kernel timing)
+    hipEvent_t assign_start, assign_stop;  // the same for the window-table assignment
     int n_cu;        // compute units of the plan's device
     void* d_zero;    // one accumulator row of zeros (n_phi x 4 bytes): out-of-grid neighbours
     bool pt;         // window-table path: prefix-count table per event, table vote and assignment
@@ -2565,6 +2566,106 @@ __global__ __launch_bounds__(kCrThreads) void k_vote_cr(const float* __restrict_
     }
 }
 
+// Background suppression inside each candidate's bin (refinement).  Per listed candidate (one
+// thread): the angle inside the bin of each listed hit, rel = ((PhiM - E) mod 2^M) - b * 2^F with
+// the sample of its layer at the candidate's (l, k); among the windows [c, c + w) that begin at a
+// listed hit's rel, the one holding hits of the most distinct layers, then the most hits, then the
+// lowest c; per layer present in it, the hit nearest the centre (smallest |2 rel - 2c - w|, ties by
+// the lower hit index).  Lists of up to kRefineStage hits keep (rel, layer) in LDS (16 bits each,
+// entry-major so that a wave's threads hit distinct banks); longer lists recompute them from the
+// workspace.  out_layers = -1 for a list cut by the pair capacity.
+constexpr int kRefineThreads = 256;
+constexpr int kRefineStage = 64;
+
+__global__ __launch_bounds__(kRefineThreads) void k_refine(
+    const hough_peak_t* __restrict__ peaks, int32_t cap_peaks, const int32_t* __restrict__ offsets,
+    const int32_t* __restrict__ hit_idx, int32_t cap_pairs, const char* __restrict__ ws, WsOff O,
+    const hough_status_t* __restrict__ st, const int32_t* __restrict__ E, int n_layers, int n_cols, int n_qpt,
+    int M, int F, int32_t w, int32_t* __restrict__ out_hits, int32_t* __restrict__ out_layers) {
+    __shared__ uint16_t s_rl[kRefineStage * kRefineThreads];
+    const int n = min(st->n_peaks, cap_peaks);
+    const int p = blockIdx.x * kRefineThreads + threadIdx.x;
+    if (p >= n) return;
+    const hough_peak_t pk = peaks[p];
+    const int32_t q0 = offsets[p], q1 = offsets[p + 1];
+    int32_t* oh = out_hits + (size_t)p * n_layers;
+    for (int L = 0; L < n_layers; ++L) oh[L] = -1;
+    if (q1 > cap_pairs) {
+        out_layers[p] = -1;
+        return;
+    }
+    const int m = q1 - q0;
+    const uint32_t* phi32 = at<const uint32_t>(const_cast<char*>(ws), O.phi32);
+    const uint8_t* lay = at<const uint8_t>(const_cast<char*>(ws), O.lay);
+    const int32_t* Ec = E + (size_t)pk.l * n_qpt + pk.k;
+    const uint32_t mask = M >= 32 ? 0xFFFFFFFFu : ((1u << M) - 1u);
+    const uint32_t bW = (uint32_t)pk.b << F;
+    auto rel_of = [&](int j, int& L) -> int32_t {
+        const int32_t h = hit_idx[q0 + j];
+        L = lay[h];
+        return (int32_t)(((phi32[h] >> (32 - M)) - (uint32_t)Ec[(size_t)L * n_cols]) & mask) - (int32_t)bW;
+    };
+    const bool staged = m <= kRefineStage;
+    if (staged) {
+        for (int j = 0; j < m; ++j) {
+            int L;
+            const int32_t r = rel_of(j, L);
+            s_rl[j * kRefineThreads + threadIdx.x] = (uint16_t)((r << 5) | L);  // r < 2^F <= 256, L < 32
+        }
+    }
+    auto get = [&](int j, int32_t& r, int& L) {
+        if (staged) {
+            const uint32_t v = s_rl[j * kRefineThreads + threadIdx.x];
+            r = (int32_t)(v >> 5);
+            L = (int)(v & 31u);
+        } else {
+            r = rel_of(j, L);
+        }
+    };
+    int best_l = -1, best_n = -1;
+    int32_t best_c = 0;
+    for (int i = 0; i < m; ++i) {
+        int32_t c0;
+        int Li;
+        get(i, c0, Li);
+        uint32_t lm = 0;
+        int cnt = 0;
+        for (int j = 0; j < m; ++j) {
+            int32_t r;
+            int L;
+            get(j, r, L);
+            if (r >= c0 && r < c0 + w) {
+                lm |= 1u << L;
+                ++cnt;
+            }
+        }
+        const int nl = __popc(lm);
+        if (nl > best_l || (nl == best_l && cnt > best_n) || (nl == best_l && cnt == best_n && c0 < best_c)) {
+            best_l = nl;
+            best_n = cnt;
+            best_c = c0;
+        }
+    }
+    out_layers[p] = m > 0 ? best_l : 0;
+    if (m == 0) return;
+    for (int L = 0; L < n_layers; ++L) {
+        int32_t pick = -1, pick_d = 0;
+        for (int j = 0; j < m; ++j) {
+            int32_t r;
+            int Lj;
+            get(j, r, Lj);
+            if (Lj != L || !(r >= best_c && r < best_c + w)) continue;
+            const int32_t h = hit_idx[q0 + j];
+            const int32_t d = abs(2 * r - 2 * best_c - w);
+            if (pick < 0 || d < pick_d || (d == pick_d && h < pick)) {
+                pick = h;
+                pick_d = d;
+            }
+        }
+        oh[L] = pick;
+    }
+}
+
 // Assignment under the per-hit radius: the lists of the candidates found in a per-hit-radius
 // accumulator (hough_vote_cr, then hough_peaks on it).  Each hit's bin in a column follows its own
 // radius, so the lists are collected by voting again: k_cra_init clears the bin -> candidate map
@@ -2699,7 +2800,7 @@ __global__ __launch_bounds__(256) void k_cra_sort(const hough_peak_t* __restrict
 // holding a candidate of more than 64 hits is voted from memory instead, one row at a time in
 // chunks of 64 hits, restoring the row after its last chunk.
 constexpr int kZvoteGroup = 4;                    // candidates staged together by a wave
-constexpr int kZvoteUnroll = 4;                   // rows voted before their returned words are used
+constexpr int kZvoteUnroll = 8;                   // rows voted before their returned words are used
 constexpr int kZvoteStage = kZvoteGroup * 64;     // staged hits per wave (Z, S: 8 bytes each)
 
 // Q16.16 z and arc length of a listed hit; S = -1 when the hit has no usable z or arc length
@@ -3146,8 +3247,10 @@ void launch_peaks(const hough_plan* p, const Events& ev, int n_events, const voi
     // the one-pass scan and writer serves single events and small batches
     const bool one_pass = n_events <= kScanWriteMaxEvents && groups <= kScanWriteMaxGroups;
     // staged values pay off where the writer is a pass of its own (its accumulator gathers would be
-    // spread over the whole batch); the one-pass writer reads the values where they lie
-    const bool stage_on = p->stage && !one_pass;
+    // spread over the whole batch); the one-pass writer reads the values where they lie.  The marker
+    // of rows wider than a wave (more than 512 bins) holds more registers, and staging there costs
+    // it a wave per SIMD: its writer gathers instead.
+    const bool stage_on = p->stage && !one_pass && strips <= 64;
     if (p->g.acc_bits == 32 && strips > 64)
         hipLaunchKernelGGL((k_peaks_mark<int32_t, true>), gm, mb, 0, stream, ev, a, acc_stride, z32, threshold, nd,
                            nq, nph, gl, planes, stage_on, ws, O);
@@ -3197,9 +3300,10 @@ void launch_assign(const hough_plan* p, const Events& ev, int n_events, const ho
     const int cells_words = (p->n_cells + 1 + 3) & ~3;
     const int lds_words = kLdsBytes / 4;
     if (p->pt) {
-        hipLaunchKernelGGL(k_assign_pt, dim3(nblk, n_events), dim3(kAssignThreads), kLdsBytes, stream, ev, peaks,
-                           peak_stride, cap_peaks, st, p->d_E, p->n_layers, p->cell_bits, p->n_cols, p->g.n_qpt,
-                           p->M, p->F, p->g.n_phi, p->pt_row, ws, O, offsets, hit_idx, cap_pairs, lds_words);
+        hipExtLaunchKernelGGL(k_assign_pt, dim3(nblk, n_events), dim3(kAssignThreads), kLdsBytes, stream,
+                              p->assign_start, p->assign_stop, 0, ev, peaks, peak_stride, cap_peaks, st, p->d_E,
+                              p->n_layers, p->cell_bits, p->n_cols, p->g.n_qpt, p->M, p->F, p->g.n_phi, p->pt_row, ws,
+                              O, offsets, hit_idx, cap_pairs, lds_words);
         return;
     }
     // one packed word per staged hit: angles of at most 16 bits and hit indices below 2^16
@@ -3835,6 +3939,13 @@ int hough_plan_set_vote_events(hough_plan_t* p, hipEvent_t start, hipEvent_t sto
     return HOUGH_OK;
 }
 
+int hough_plan_set_assign_events(hough_plan_t* p, hipEvent_t start, hipEvent_t stop) {
+    if (!p) return HOUGH_E_INVAL;
+    p->assign_start = start;
+    p->assign_stop = stop;
+    return HOUGH_OK;
+}
+
 int hough_plan_get_tuning(const hough_plan_t* p, hough_tuning_t* t) {
     if (!p || !t) return HOUGH_E_INVAL;
     *t = p->tuning;
@@ -4093,6 +4204,21 @@ int hough_vote_cr(const hough_plan_t* p, const hough_hits_t* hits, int32_t* acc,
         hipLaunchKernelGGL(k_vote_cr, dim3(blocks), dim3(kCrThreads), 0, stream, hits->x, hits->y, hits->layer,
                            hits->n, g, p->cordic, acc, st);
     }
+    return launch_status();
+}
+
+int hough_refine(const hough_plan_t* p, const hough_peak_t* peaks, int32_t cap_peaks, const int32_t* offsets,
+                 const int32_t* hit_idx, int32_t cap_pairs, const void* ws, size_t ws_bytes, const hough_status_t* st,
+                 int32_t window, int32_t* out_hits, int32_t* out_layers, hipStream_t stream) {
+    if (!p || !peaks || !offsets || !hit_idx || !ws || !st || !out_hits || !out_layers) return HOUGH_E_INVAL;
+    if (cap_peaks < 1 || cap_pairs < 1 || window < 1 || window > (1 << p->F)) return HOUGH_E_INVAL;
+    if (p->n_layers > 32 || p->F > 8) return HOUGH_E_UNSUPPORTED;
+    const WsLayout L = ws_layout(p, cap_peaks);
+    if (ws_bytes < L.total) return HOUGH_E_SMALL_WS;
+    hipLaunchKernelGGL(k_refine, dim3((unsigned)((cap_peaks + kRefineThreads - 1) / kRefineThreads)),
+                       dim3(kRefineThreads), 0, stream, peaks, cap_peaks, offsets, hit_idx, cap_pairs,
+                       static_cast<const char*>(ws), ws_off(L), st, p->d_E, p->n_layers, p->n_cols, p->g.n_qpt, p->M,
+                       p->F, window, out_hits, out_layers);
     return launch_status();
 }
 

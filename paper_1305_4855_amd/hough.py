@@ -117,9 +117,12 @@ def _load() -> C.CDLL:
     L.hough_plan_set_tuning.restype = C.c_int; L.hough_plan_set_tuning.argtypes = [P, C.POINTER(Tuning)]
     L.hough_plan_get_tuning.restype = C.c_int; L.hough_plan_get_tuning.argtypes = [P, C.POINTER(Tuning)]
     L.hough_plan_set_vote_events.restype = C.c_int; L.hough_plan_set_vote_events.argtypes = [P, P, P]
+    L.hough_plan_set_assign_events.restype = C.c_int; L.hough_plan_set_assign_events.argtypes = [P, P, P]
     L.hough_batch_ws_bytes.restype = S; L.hough_batch_ws_bytes.argtypes = [P, C.c_int32, C.c_int32]
     L.hough_run_batch.restype = C.c_int; L.hough_run_batch.argtypes = [P, C.POINTER(Batch), P]
     L.hough_run_batch_noalloc.restype = C.c_int; L.hough_run_batch_noalloc.argtypes = [P, C.POINTER(Batch), P]
+    L.hough_refine.restype = C.c_int
+    L.hough_refine.argtypes = [P, P, C.c_int32, P, P, C.c_int32, P, S, P, C.c_int32, P, P, P]
     L.hough_assign_cr_ws_bytes.restype = S; L.hough_assign_cr_ws_bytes.argtypes = [P, C.c_int32, C.c_int32]
     L.hough_assign_cr.restype = C.c_int
     L.hough_assign_cr.argtypes = [P, C.POINTER(Hits), P, C.c_int32, P, P, C.c_int32, P, S, P, S, P, P]
@@ -135,9 +138,10 @@ lib = _load()
 EXPORTED = ["hough_plan_create", "hough_plan_destroy", "hough_acc_bytes", "hough_event_ws_bytes",
             "hough_angle_bits", "hough_plan_table", "hough_prep", "hough_vote", "hough_vote_prepared", "hough_peaks",
             "hough_assign", "hough_zvote", "hough_fit", "hough_plan_arclen_table", "hough_strerror", "hough_plan_set_tuning", "hough_plan_get_tuning", "hough_plan_set_vote_events",
+            "hough_plan_set_assign_events",
             "hough_batch_ws_bytes", "hough_run_batch", "hough_run_batch_noalloc", "hough_batch_graph_create",
             "hough_graph_launch",
-            "hough_graph_destroy", "hough_fit_batch", "hough_vote_cr", "hough_assign_cr_ws_bytes", "hough_assign_cr", "hough_vertex_plan_create", "hough_vertex_plan_destroy", "hough_vertex_set_groups",
+            "hough_graph_destroy", "hough_fit_batch", "hough_vote_cr", "hough_assign_cr_ws_bytes", "hough_assign_cr", "hough_refine", "hough_vertex_plan_create", "hough_vertex_plan_destroy", "hough_vertex_set_groups",
             "hough_vertex_get_groups", "hough_vertex_vote_ws_bytes", "hough_vertex_peaks_ws_bytes",
             "hough_vertex_vote", "hough_vertex_peaks", "hough_vertex_table", "hough_vertex_batch_vote_ws_bytes",
             "hough_vertex_batch_peaks_ws_bytes", "hough_vertex_vote_batch", "hough_vertex_peaks_batch"]
@@ -232,6 +236,16 @@ class Plan:
             return ev.cuda_event
         _check(lib.hough_plan_set_vote_events(self.handle, raw(start), raw(stop)), "hough_plan_set_vote_events")
 
+    def set_assign_events(self, start=None, stop=None) -> None:
+        """The same for the assignment kernel (plans with the window tables)."""
+        def raw(ev):
+            if ev is None:
+                return None
+            if not ev.cuda_event:
+                ev.record()
+            return ev.cuda_event
+        _check(lib.hough_plan_set_assign_events(self.handle, raw(start), raw(stop)), "hough_plan_set_assign_events")
+
     def table(self) -> np.ndarray:
         c = self.cfg
         out = np.zeros((c.n_layers, c.n_d0, c.n_qpt), dtype=np.int32)
@@ -275,6 +289,18 @@ def vote_cr(plan: Plan, hits: Hits, acc: torch.Tensor, status: torch.Tensor, str
     if acc.dtype != torch.int32:
         raise HoughError("hough_vote_cr needs an int32 accumulator")
     _check(lib.hough_vote_cr(plan.handle, C.byref(hits), _ptr(acc), _ptr(status), _stream(stream)), "hough_vote_cr")
+
+
+def refine(plan: Plan, peaks: torch.Tensor, offsets: torch.Tensor, hit_idx: torch.Tensor, ws: torch.Tensor,
+           status: torch.Tensor, window: int, out_hits: torch.Tensor, out_layers: torch.Tensor, stream=None) -> None:
+    """Background suppression inside each candidate's bin: per candidate, one hit per layer of the
+    densest window of the angle inside the bin (out_hits [cap_peaks][n_layers], out_layers [cap_peaks])."""
+    cap_peaks = int(peaks.shape[0])
+    if out_hits.numel() < cap_peaks * plan.cfg.n_layers or out_layers.numel() < cap_peaks:
+        raise HoughError("out_hits needs [cap_peaks][n_layers] and out_layers [cap_peaks] entries")
+    _check(lib.hough_refine(plan.handle, _ptr(peaks), cap_peaks, _ptr(offsets), _ptr(hit_idx), int(hit_idx.numel()),
+                            _ptr(ws), ws.numel(), _ptr(status), int(window), _ptr(out_hits), _ptr(out_layers),
+                            _stream(stream)), "hough_refine")
 
 
 def assign_cr_ws_bytes(plan: Plan, cap_peaks: int, cap_pairs: int) -> int:

@@ -8,6 +8,10 @@ reconstructible when it left at least `min_hits` hits (default: the first-stage 
 found when some candidate is matched to it.  Efficiency = found / reconstructible; purity =
 matched candidates / candidates; duplicates = matched candidates per found track.
 
+With background suppression inside the bin (hough_refine: one hit per layer from the densest
+window of the angle inside the bin), the refined lists of the candidates that keep at least
+`min_layers` layers are matched the same way (refined_csr builds their CSR lists).
+
 A second reading, in parameter space (the figures show candidates as peaks at the generated
 tracks' parameters): a generated track is found when a candidate lies within one bin of the bin
 holding its true (d0, q/pT, phi0) in every direction (phi0 cyclic); purity = candidates within
@@ -130,3 +134,15 @@ def quality_params(cfg, truth, track_id, peaks: np.ndarray, min_hits: int) -> di
             "candidates_near_a_track": n_near,
             "efficiency": round(int(found.sum()) / n_recon, 4) if n_recon else None,
             "purity": round(n_near / len(cand), 4) if cand else None}
+
+
+def refined_csr(out_hits: np.ndarray, out_layers: np.ndarray, min_layers: int):
+    """CSR lists of the refined candidates with at least `min_layers` layers: (offsets, hit_idx, kept
+    candidate indices); each list holds its layers' hits in layer order."""
+    out_hits = np.asarray(out_hits)
+    keep = np.flatnonzero(np.asarray(out_layers) >= min_layers)
+    rows = out_hits[keep]
+    sizes = (rows >= 0).sum(axis=1)
+    offsets = np.zeros(keep.size + 1, dtype=np.int64)
+    np.cumsum(sizes, out=offsets[1:])
+    return offsets, rows[rows >= 0].astype(np.int64), keep

@@ -55,6 +55,11 @@ MUTATIONS = {
     "cr_round_down": ("*E = (int32_t)((t + ((int64_t)1 << (s - 1))) >> s);", "*E = (int32_t)(t >> s);"),
     "cr_isqrt_step": ("            root = (root >> 1) + bit;", "            root = (root >> 1) + bit + 1;"),
     "cr_layer_radius": ("        r = or_hit_radius(X, Y);", "        r = g->r_cm[layer[h]];"),
+    "refine_window_inclusive": ("if (rel[j] >= c0 && rel[j] < c0 + w) {", "if (rel[j] >= c0 && rel[j] <= c0 + w) {"),
+    "refine_counts_hits_not_layers": ("for (L = 0; L < NL; L++) nl += (lay_mask >> L) & 1u;", "nl = cnt;"),
+    "refine_nearest_to_start": ("dist = 2 * rel[j] - 2 * (int64_t)best_c - w;", "dist = rel[j] - (int64_t)best_c;"),
+    "refine_any_hit_of_layer": ("if (layer[h] != L || !(rel[j] >= best_c && rel[j] < (int64_t)best_c + w)) continue;",
+                                "if (layer[h] != L) continue;"),
     "cr_assign_layer_radius": ("if (!or_sample_cr(rad[h], c, d, M, &E)) continue;",
                                "if (!or_sample_cr(g->r_cm[L], c, d, M, &E)) continue;"),
     "cr_assign_wrong_bin": ("if (bp != or_bin(phiM[h], E, M, F)) continue;",

@@ -1202,3 +1202,123 @@ def test_cr_assign_track_hits_in_its_list(oracle_mod):
     lst = hit_idx[offs[0]:offs[1]]
     assert sorted(lst.tolist()) == list(range(ev.n))
     assert list(ev.layer[lst]) == list(range(cfg.n_layers))
+
+
+def _rel_of_lists(O, g, cfg, ev, pk, offs, hit_idx):
+    """Angle inside the bin of every listed hit, from the oracle's pinned azimuth and sample."""
+    M = O.angle_bits(g)
+    W = 1 << cfg.frac_bits
+    phi, _ = O.prep(ev, cfg.n_layers)
+    rels = []
+    for p in range(pk.shape[0]):
+        l, k, b = (int(t) for t in pk[p][:3])
+        r = []
+        for h in hit_idx[offs[p]:offs[p + 1]]:
+            okE, E = O.sample(cfg.radii_cm[ev.layer[h]], O.curvature(g, k), O.d0_centre(g, l), M)
+            assert okE
+            r.append(((int(phi[h]) >> (32 - M)) - E) % (1 << M) - b * W)
+        rels.append(np.array(r, dtype=np.int64))
+    return rels
+
+
+def test_refine_window_covers_the_most_layers(oracle_mod):
+    """Refined lists on a crowded small event: every refined hit is on the candidate's list, one per
+    layer, all within one window of width w; the number of layers equals the best layer coverage
+    of any window of width w over the list's angles (every integer start tried); a layer of the
+    refined list is represented by the listed hit of that layer nearest some window's centre."""
+    O = oracle_mod
+    cfg = configs.C7.with_(n_phi=128, n_qpt=64, n_tracks=60)
+    ev = synth.make_event(cfg, 21)
+    g = O.Cfg(cfg)
+    acc, _ = O.vote(g, ev)
+    n, pk = O.peaks(g, acc, cfg.threshold)
+    pk = pk[:: max(1, n // 80)]
+    offs, hit_idx, _ = O.assign(g, ev, pk)
+    rels = _rel_of_lists(O, g, cfg, ev, pk, offs, hit_idx)
+    for w in (4, 16, 40):
+        ref, layers = O.refine(g, ev, pk, offs, hit_idx, w)
+        for p in range(pk.shape[0]):
+            lst = hit_idx[offs[p]:offs[p + 1]]
+            rel = rels[p]
+            lay = ev.layer[lst]
+            best = 0
+            for c in range(int(rel.min()), int(rel.max()) + 1):
+                best = max(best, len(set(lay[(rel >= c) & (rel < c + w)].tolist())))
+            assert layers[p] == best, (w, p)
+            kept = ref[p][ref[p] >= 0]
+            assert len(kept) == layers[p]
+            assert set(ev.layer[kept].tolist()) == {L for L in range(cfg.n_layers) if ref[p][L] >= 0}
+            for L in range(cfg.n_layers):
+                if ref[p][L] >= 0:
+                    assert ev.layer[ref[p][L]] == L and ref[p][L] in set(lst.tolist())
+            if len(kept):
+                kr = np.array([rel[np.flatnonzero(lst == h)[0]] for h in kept])
+                assert kr.max() - kr.min() < w
+
+
+def test_refine_isolates_a_bin_centred_track(oracle_mod):
+    """A noise-free prompt track at bin centres crossing a bin shared with a few stray hits: the
+    refined list of its candidate is exactly the track's ten hits (its angles inside the bin agree
+    to far better than the window), whatever the stray hits' angles."""
+    O = oracle_mod
+    cfg = configs.C7.with_(n_phi=256, n_qpt=64, n_tracks=1, smear_xy_cm=0.0)
+    g = O.Cfg(cfg)
+    k, b = 40, 77
+    qpt = float(Fraction(cfg.qpt_min) + Fraction(2 * k + 1, 2) * (Fraction(cfg.qpt_max) - Fraction(cfg.qpt_min))
+                / cfg.n_qpt)
+    phi0 = (b + 0.5) * 2 * math.pi / cfg.n_phi
+    rng = np.random.default_rng(9)
+    x, y, _, lay, tid = synth._helix_hits(rng, cfg, np.array([np.sign(qpt)]), np.array([abs(qpt)]),
+                                          np.array([phi0]), np.array([0.0]), np.zeros(1), np.zeros(1))
+    # stray hits on three layers inside the track's bin but spread in angle
+    xs, ys, ls = [], [], []
+    for L, dphi in ((2, -0.009), (5, 0.011), (7, 0.004)):
+        r = cfg.radii_cm[L]
+        okE, E = O.sample(r, O.curvature(g, k), 0.0, O.angle_bits(g))
+        ang = phi0 + E * math.pi / (1 << (O.angle_bits(g) - 1)) + dphi
+        xs.append(r * math.cos(ang)); ys.append(r * math.sin(ang)); ls.append(L)
+    ev = synth.Event(x=np.concatenate([x, xs]).astype(np.float32), y=np.concatenate([y, ys]).astype(np.float32),
+                     z=None, layer=np.concatenate([lay, ls]).astype(np.uint8),
+                     track_id=np.concatenate([tid, [-1] * 3]).astype(np.int32), truth={})
+    acc, _ = O.vote(g, ev)
+    pk = np.array([[0, k, b, acc[0, k, b]]], dtype=np.int32)
+    offs, hit_idx, _ = O.assign(g, ev, pk)
+    assert offs[1] == 13  # the ten track hits and the three stray ones share the bin
+    ref, layers = O.refine(g, ev, pk, offs, hit_idx, 8)
+    assert layers[0] == 10
+    assert sorted(ref[0].tolist()) == list(range(10))
+    # a second hit on the track's layer-3 circle, half a window below the track's own hit: the
+    # window with the most hits starts at it, and the layer keeps the hit nearest the centre
+    i3 = int(np.flatnonzero(ev.layer[:10] == 3)[0])
+    ang = math.atan2(float(ev.y[i3]), float(ev.x[i3])) - 4 * 2 * math.pi / (1 << O.angle_bits(g))
+    r3 = cfg.radii_cm[3]
+    ev2 = synth.Event(x=np.append(ev.x, np.float32(r3 * math.cos(ang))), y=np.append(ev.y, np.float32(r3 * math.sin(ang))),
+                      z=None, layer=np.append(ev.layer, np.uint8(3)), track_id=np.append(ev.track_id, -1).astype(np.int32),
+                      truth={})
+    acc2, _ = O.vote(g, ev2)
+    pk2 = np.array([[0, k, b, acc2[0, k, b]]], dtype=np.int32)
+    offs2, hit2, _ = O.assign(g, ev2, pk2)
+    assert offs2[1] == 14
+    ref2, layers2 = O.refine(g, ev2, pk2, offs2, hit2, 8)
+    assert layers2[0] == 10 and ref2[0][3] == i3
+    assert sorted(ref2[0].tolist()) == list(range(10))
+
+
+def test_refine_rotation_covariance(oracle_mod):
+    """A quarter turn of every hit moves each refined list to the candidate n_phi / 4 bins on."""
+    O = oracle_mod
+    cfg = configs.C7.with_(n_phi=128, n_qpt=64, n_tracks=40)
+    ev = synth.make_event(cfg, 22)
+    g = O.Cfg(cfg)
+    acc, _ = O.vote(g, ev)
+    n, pk = O.peaks(g, acc, cfg.threshold)
+    offs, hit_idx, _ = O.assign(g, ev, pk)
+    rot = synth.Event(x=(-ev.y).astype(np.float32), y=ev.x.copy(), z=None, layer=ev.layer, track_id=ev.track_id,
+                      truth=ev.truth)
+    pk_rot = pk.copy()
+    pk_rot[:, 2] = (pk[:, 2] + cfg.n_phi // 4) % cfg.n_phi
+    offs_r, hit_r, _ = O.assign(g, rot, pk_rot)
+    a, la = O.refine(g, ev, pk, offs, hit_idx, 16)
+    b2, lb = O.refine(g, rot, pk_rot, offs_r, hit_r, 16)
+    np.testing.assert_array_equal(a, b2)
+    np.testing.assert_array_equal(la, lb)
