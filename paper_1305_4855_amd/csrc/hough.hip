@@ -266,6 +266,20 @@ __device__ __forceinline__ int64_t block_inclusive_scan(int64_t v, int64_t* wsum
     return r;
 }
 
+// Sum of one int64 value per thread over a workgroup of kScanThreads threads (every thread gets it).
+// `wsum` is LDS scratch of kScanThreads / 64 entries.
+__device__ __forceinline__ int64_t block_reduce_sum(int64_t v, int64_t* wsum) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = v;
+    __syncthreads();
+    int64_t t = 0;
+#pragma unroll
+    for (int i = 0; i < kScanThreads / 64; ++i) t += wsum[i];
+    __syncthreads();
+    return t;
+}
+
 struct WsOff {
     size_t misc, phi32, lay, cell_start, tmp_phi, tmp_key, sorted_phi, sorted_h, ptab, gtab;
     size_t flags, grp_count, grp_votes, grp_off, grp_voff, stage, peak_voff;
@@ -564,16 +578,17 @@ __global__ __launch_bounds__(256) void k_prep_rank(Events ev, int n_cells, int c
 // ------------------------------------------------------------------ prep for the window tables
 // Plans with the window tables (see below) sort the hits and build both tables in one pass over a
 // fine histogram: one workgroup per (event, layer L, chunk of R consecutive phi0 rows of the
-// layer), R = min(n_phi, 128).  With W = 2^F angles per row, the workgroup counts the layer's hits
-// of every M-bit angle of its rows and of the row after them (the next chunk's first row, or the
-// turn's first row) in LDS (16-bit counters, two per word, rows padded to W/2 + 1 words so that
+// layer), R = the plan's prep_rows (tuned).  With W = 2^F angles per row, the workgroup counts the
+// layer's hits of every M-bit angle of its rows and of the row after them (the next chunk's first
+// row, or the turn's first row) in LDS (16-bit counters, two per word, rows padded to W/2 + 1 words so that
 // reads of one phase down consecutive rows hit distinct banks), scans the counts into prefix
 // counts P_L(x) (relative to the layer's first sorted hit; the layer's hits below the chunk come
 // from a count over all hits), writes PT and GT for its rows and every phase, and places each of
 // its hits at sorted position P_L(angle) (+ its rank among the hits of the same angle by hit
 // index: tied hits are collected in LDS and ranked there).  Chunk 0 also writes the window-count
 // entries past n_phi (the turn repeated) and the layer's start; workgroup 0 of the event writes the
-// status.  Every workgroup reads the event's prepared hits (k_prep_hits) twice from L2.
+// status.  Every workgroup reads the event's prepared hits (k_prep_hits) from L2 (once for events
+// of at most 16384 hits, which stay in registers; twice otherwise).
 constexpr int kFineRows = 128;     // phi0 rows per chunk
 constexpr int kFineTieCap = 1024;  // tied hits a workgroup ranks in LDS (more: all tied hits ranked from memory)
 constexpr int kFineUnroll = 16;    // hits per thread loaded at once
@@ -612,16 +627,29 @@ __global__ __launch_bounds__(kScanThreads) void k_prep_fine(Events ev, int n_lay
     if (tid < kMaxLayers) s_vc[tid] = tid < n_layers ? LT.valid_cols[tid] : 0;
     if (tid == 0) n_tie = 0;
     __syncthreads();
-    // the hits are read kFineUnroll per thread at a time, all loads in flight together; an event of
-    // at most kScanThreads * kFineUnroll hits stays in registers for the placing pass
+    // a thread reads kFineUnroll (16) consecutive hits at a time: their layers as one 16-byte load,
+    // their azimuths as four (the regions are 256-byte aligned and padded, so a last partial group
+    // stays inside them); an event of at most kScanThreads * kFineUnroll hits stays in registers
+    // for the placing pass
+    static_assert(kFineUnroll == 16, "one 16-byte load of layer bytes per thread");
     uint8_t lh[kFineUnroll];
     uint32_t ah[kFineUnroll];
     auto load_hits = [&](int hb) {
+        const int h0 = hb + kFineUnroll * tid;
+        uint4 lv = make_uint4(0xFEFEFEFEu, 0xFEFEFEFEu, 0xFEFEFEFEu, 0xFEFEFEFEu);  // 0xFE: no hit
+        uint4 pv[4] = {};
+        if (h0 < n) {
+            lv = *reinterpret_cast<const uint4*>(lay + h0);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) pv[q] = *reinterpret_cast<const uint4*>(phi32 + h0 + 4 * q);
+        }
+        const uint32_t lw[4] = {lv.x, lv.y, lv.z, lv.w};
 #pragma unroll
         for (int j = 0; j < kFineUnroll; ++j) {
-            const int h = hb + j * kScanThreads + tid;
-            lh[j] = h < n ? lay[h] : (uint8_t)0xFE;  // 0xFE: no hit, 0xFF: bad hit
-            ah[j] = h < n ? phi32[h] >> sh : 0u;
+            const bool in = h0 + j < n;
+            const uint32_t pj = j % 4 == 0 ? pv[j / 4].x : j % 4 == 1 ? pv[j / 4].y : j % 4 == 2 ? pv[j / 4].z : pv[j / 4].w;
+            lh[j] = in ? (uint8_t)(lw[j / 4] >> (8 * (j % 4))) : (uint8_t)0xFE;  // 0xFF: bad hit
+            ah[j] = in ? pj >> sh : 0u;
         }
     };
     const bool resident = n <= kScanThreads * kFineUnroll;
@@ -645,12 +673,12 @@ __global__ __launch_bounds__(kScanThreads) void k_prep_fine(Events ev, int n_lay
             if ((a >> F) == next_row) atomicAdd(&hist[R * wpr + (int)(col >> 1)], inc);
         }
     }
-    int64_t t1, t2, t_votes = 0;
-    block_inclusive_scan((int64_t)before | ((int64_t)bad << 32), wsum, &t1);
-    block_inclusive_scan((int64_t)below | ((int64_t)mine << 32), wsum, &t2);
-    if (counter) block_inclusive_scan(votes, wsum, &t_votes);  // uniform per workgroup
-    const int base = (int)(t1 & 0xFFFFFFFFll), n_bad = (int)(t1 >> 32);
-    const int cbase = (int)(t2 & 0xFFFFFFFFll), n_L = (int)(t2 >> 32);
+    // the four counts in 16-bit fields of one sum (each is at most the event's hits, <= 65535 here)
+    const uint64_t tot4 = (uint64_t)block_reduce_sum(
+        (int64_t)((uint64_t)before | ((uint64_t)bad << 16) | ((uint64_t)below << 32) | ((uint64_t)mine << 48)), wsum);
+    const int64_t t_votes = counter ? block_reduce_sum(votes, wsum) : 0;  // uniform per workgroup
+    const int base = (int)(tot4 & 0xFFFFu), n_bad = (int)((tot4 >> 16) & 0xFFFFu);
+    const int cbase = (int)((tot4 >> 32) & 0xFFFFu), n_L = (int)(tot4 >> 48);
     // exclusive scan of the counts in angle order -> prefix counts (16 bits: differences stay exact)
     const int T = (R + 1) << F;
     const int k = ((T + kScanThreads - 1) / kScanThreads + 1) & ~1;
@@ -700,7 +728,7 @@ __global__ __launch_bounds__(kScanThreads) void k_prep_fine(Events ev, int n_lay
         for (int j = 0; j < kFineUnroll; ++j) {
             const uint32_t a = ah[j];
             if (lh[j] != L || a < a_lo || a >= a_hi) continue;
-            const int h = hb + j * kScanThreads + tid;
+            const int h = hb + kFineUnroll * tid + j;
             const uint32_t x = a - a_lo;
             const int rl = (int)(x >> F), cl = (int)(x & (uint32_t)(W - 1));
             const uint32_t p = P16(rl, cl);
@@ -2087,33 +2115,74 @@ __global__ __launch_bounds__(kAssignThreads) void k_assign_fill(
 // k_assign_fill; the layers are taken ten at a time so that their loads are in flight together.
 typedef __attribute__((address_space(3))) const uint16_t lds_cu16;
 
+// hit_run(i, a1): entry i of a run ending at a1, read up to two entries past a1 (the staged LDS
+// view reads them, as the LDS past the staged hits is the wave buffers; the global view clamps).
 struct HitsU16 {
     lds_cu16* h;
     __device__ __forceinline__ int32_t hit(int i) const { return (int32_t)h[i]; }
+    __device__ __forceinline__ int32_t hit_run(int i, int) const { return (int32_t)h[i]; }
 };
 struct HitsIdx {
     const int32_t* __restrict__ h;
     __device__ __forceinline__ int32_t hit(int i) const { return h[i]; }
+    __device__ __forceinline__ int32_t hit_run(int i, int a1) const { return h[min(i, a1 - 1)]; }
 };
 
 constexpr int kAssignLayerChunk = 10;
 
+// Copies entries [a0, a1) of the sorted hits to CSR positions from wpos on: the first n_buf of them
+// into the wave's buffer (index rel), the rest straight to memory, none past cap_pairs (the counts are
+// split once per run, so the copy loops carry no per-entry tests).  Reads may run up to two
+// entries past a1 (inside the LDS, or clamped for the global view); whole quads of writes are
+// unconditional.
+template <typename View>
+__device__ __forceinline__ void pt_copy_run(int a0, int a1, int32_t wpos, int32_t o0, const View& hv, int32_t* buf,
+                                            int buf_words, int32_t* hit_idx, int32_t cap_pairs) {
+    const int n_e = min(a1 - a0, cap_pairs - wpos);  // entries written (wpos <= cap_pairs here)
+    if (n_e <= 0) return;
+    const int rel = wpos - o0;
+    const int n_buf = max(0, min(n_e, buf_words - rel));
+    int t = 0;
+    for (; t + 4 <= n_buf; t += 4) {
+        int32_t h[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) h[v] = hv.hit_run(a0 + t + v, a1);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) buf[rel + t + v] = h[v];
+    }
+    if (t < n_buf) {
+        int32_t h[3];
+#pragma unroll
+        for (int v = 0; v < 3; ++v) h[v] = hv.hit_run(a0 + t + v, a1);
+#pragma unroll
+        for (int v = 0; v < 3; ++v)
+            if (t + v < n_buf) buf[rel + t + v] = h[v];
+        t = n_buf;
+    }
+    for (; t < n_e; ++t) hit_idx[wpos + t] = hv.hit_run(a0 + t, a1);  // past the wave's buffer
+}
+
 template <typename View>
 __device__ __forceinline__ void assign_candidate_pt(const hough_peak_t& pk, int64_t off, int64_t o0,
-                                                    const int32_t* __restrict__ Ec, int n_layers, int n_cols, int M,
-                                                    int F, int n_phi, int row, const uint16_t* __restrict__ pt,
-                                                    const int32_t* lay_start, const View& hv, int32_t* buf,
-                                                    int buf_words, int32_t* hit_idx, int32_t cap_pairs) {
+                                                    const int32_t* __restrict__ Ec,
+                                                    int n_layers, int n_cols, int M, int F, int n_phi, int row,
+                                                    const uint16_t* __restrict__ pt, const int32_t* lay_start,
+                                                    const View& hv, int32_t* buf, int buf_words, int32_t* hit_idx,
+                                                    int32_t cap_pairs) {
     constexpr int LC = kAssignLayerChunk;
     const uint32_t mmask = (1u << M) - 1u, wmask = (1u << F) - 1u;
-    int64_t wpos = off;
+    if (off >= cap_pairs) return;
+    // positions below cap_pairs fit 32 bits, and so does the wave's first position o0 <= off
+    int32_t wpos = (int32_t)off;
+    const int32_t o0_32 = (int32_t)o0;
     for (int L0 = 0; L0 < n_layers; L0 += LC) {
         if (wpos >= cap_pairs) break;
         int32_t ev_l[LC];
 #pragma unroll
-        for (int u = 0; u < LC; ++u) ev_l[u] = L0 + u < n_layers ? Ec[(size_t)(L0 + u) * n_cols] : INT32_MIN;
-        uint32_t lo[LC], hi[LC];
-        bool wr[LC];
+        for (int u = 0; u < LC; ++u)
+            ev_l[u] = L0 + u < n_layers ? Ec[(size_t)(L0 + u) * n_cols] : INT32_MIN;
+        uint32_t lh[LC];  // lo | hi << 16: the run's first and end entries in the layer
+        uint32_t wr = 0;  // layers whose window passes the turn
 #pragma unroll
         for (int u = 0; u < LC; ++u) {
             // every load is in bounds (an invalid sample still gives an angle below 2^M; the pair of
@@ -2123,18 +2192,19 @@ __device__ __forceinline__ void assign_candidate_pt(const hough_peak_t& pk, int6
             const uint32_t r = x & wmask, j = x >> F;
             const int Lc = min(L0 + u, n_layers - 1);
             const uint32_t* rp = reinterpret_cast<const uint32_t*>(pt + ((size_t)Lc * (wmask + 1u) + r) * n_phi);
-            wr[u] = (int)j == n_phi - 1;
+            wr |= ((int)j == n_phi - 1 ? 1u : 0u) << u;
             uint2 v;
             __builtin_memcpy(&v, rp + (j >> 1), 8);
-            lo[u] = (j & 1u) ? v.x >> 16 : v.x & 0xFFFFu;
-            hi[u] = (j & 1u) ? v.y & 0xFFFFu : v.x >> 16;
+            // entries j and j + 1 of the row: the dword's halves for even j, else its high half and
+            // the next dword's low half
+            lh[u] = (j & 1u) ? (v.x >> 16) | (v.y << 16) : v.x;
         }
 #pragma unroll
         for (int u = 0; u < LC; ++u) {
-            if (wr[u]) {  // the window passes the turn: it ends at entry 0 of the row
+            if (wr & (1u << u)) {  // the window passes the turn: it ends at entry 0 of the row
                 const uint32_t r = ((uint32_t)ev_l[u] + ((uint32_t)pk.b << F)) & wmask;
                 const int Lc = min(L0 + u, n_layers - 1);
-                hi[u] = pt[((size_t)Lc * (wmask + 1u) + r) * n_phi];
+                lh[u] = (lh[u] & 0xFFFFu) | ((uint32_t)pt[((size_t)Lc * (wmask + 1u) + r) * n_phi] << 16);
             }
         }
 #pragma unroll
@@ -2142,26 +2212,17 @@ __device__ __forceinline__ void assign_candidate_pt(const hough_peak_t& pk, int6
             const int L = L0 + u;
             if (L >= n_layers || ev_l[u] == INT32_MIN) continue;
             const int base = lay_start[L];
-            for (int seg = 0; seg < 2; ++seg) {
-                if (seg == 1 && !wr[u]) break;
-                const int a0 = seg == 0 ? base + (int)lo[u] : base;
-                const int a1 = seg == 0 ? (wr[u] ? lay_start[L + 1] : base + (int)hi[u]) : base + (int)hi[u];
-                // four entries at a time: the four loads go out before the four stores
-                for (int q = a0; q < a1; q += 4) {
-                    int32_t h[4];
-#pragma unroll
-                    for (int v = 0; v < 4; ++v) h[v] = hv.hit(min(q + v, a1 - 1));
-#pragma unroll
-                    for (int v = 0; v < 4; ++v) {
-                        const int64_t wp = wpos + (q - a0) + v;
-                        if (q + v < a1 && wp < cap_pairs) {
-                            const int64_t rel = wp - o0;
-                            if (rel < buf_words) buf[rel] = h[v];
-                            else hit_idx[wp] = h[v];
-                        }
-                    }
-                }
-                wpos += a1 > a0 ? a1 - a0 : 0;
+            const int lo_u = (int)(lh[u] & 0xFFFFu), hi_u = (int)(lh[u] >> 16);
+            if (!(wr & (1u << u))) {
+                const int a0 = base + lo_u, a1 = base + hi_u;
+                pt_copy_run(a0, a1, wpos, o0_32, hv, buf, buf_words, hit_idx, cap_pairs);
+                wpos = (int32_t)min((int64_t)wpos + (a1 - a0), (int64_t)cap_pairs);
+            } else {  // the run to the layer's end, then the layer's first entries
+                const int a0 = base + lo_u, a1 = lay_start[L + 1];
+                pt_copy_run(a0, a1, wpos, o0_32, hv, buf, buf_words, hit_idx, cap_pairs);
+                wpos = (int32_t)min((int64_t)wpos + (a1 - a0), (int64_t)cap_pairs);
+                pt_copy_run(base, base + hi_u, wpos, o0_32, hv, buf, buf_words, hit_idx, cap_pairs);
+                wpos = (int32_t)min((int64_t)wpos + hi_u, (int64_t)cap_pairs);
             }
         }
     }
