@@ -788,6 +788,7 @@ def main() -> int:
     ap.add_argument("--batch-events", type=int, default=256)
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-plain", action="store_true", help="skip the single-event section (profiling runs)")
+    ap.add_argument("--no-small", action="store_true", help="skip the small-event section (profiling runs)")
     ap.add_argument("--no-large-grid", action="store_true")
     ap.add_argument("--no-vertex", action="store_true")
     ap.add_argument("--no-quality", action="store_true")
@@ -823,7 +824,7 @@ def main() -> int:
     if not args.no_plain:
         out = bench_plain(H, torch, args)
         torch.cuda.empty_cache()
-    if not args.no_plain:
+    if not args.no_plain and not args.no_small:
         out["small_event"] = bench_small(H, torch, steps=500)
     if not args.no_batched:
         out["batched"] = bench_batched(H, torch, args.batch_events, reps=10)
