@@ -193,6 +193,15 @@ WsLayout ws_layout(const hough_plan* p, int32_t max_peaks) {
 // Batch header in front of the per-event workspaces: work-queue counter and event order.
 size_t batch_header_bytes(int32_t n_events) { return align_up(256 + 4 * (size_t)n_events, 256); }
 
+// XCD-aware placement of a batch's events.  Workgroups are dispatched to the 8 XCDs round-robin by
+// their linear index, and each XCD has its own L2, so the per-event tables the vote and the
+// assignment look up (window counts, prefix counts, sorted hits: a few MB per event) are fetched
+// once per XCD that works on the event.  The batched kernels therefore keep all the work of one
+// event on one XCD: XCD x takes the events of size rank 8g + x for even g and 8g + 7 - x for odd g
+// (a snake over the size order, which balances the XCDs' totals).
+constexpr int kXcds = 8;
+__host__ __device__ __forceinline__ int xcd_rank(int g, int x) { return kXcds * g + ((g & 1) ? kXcds - 1 - x : x); }
+
 template <typename T>
 __device__ __host__ __forceinline__ T* at(void* base, size_t off) {
     return reinterpret_cast<T*>(static_cast<char*>(base) + off);
@@ -305,7 +314,7 @@ __global__ __launch_bounds__(1024) void k_batch_init(const int32_t* __restrict__
         }
         order[rank] = e;
     }
-    if (threadIdx.x == 0) *queue = 0;
+    if (threadIdx.x < kXcds) queue[threadIdx.x] = 0;  // one work-queue counter per XCD
 }
 
 // ------------------------------------------------------------------ prep kernels
@@ -1048,11 +1057,28 @@ __global__ __launch_bounds__(kVotePtThreads) void k_vote_pt(Events ev, const int
     const uint32_t mmask = (1u << M) - 1u;
     const uint32_t wmask = (1u << F) - 1u;
     const int row2 = row / 2;                        // row length in dwords
-    int item = blockIdx.x;
-    while (item < total) {
-        const int rank = item / n_blocks;
+    // with a queue (batches): the workgroups of XCD x = blockIdx.x % 8 take the (event, column
+    // block) items of that XCD's events (xcd_rank) from the XCD's own queue counter
+    const bool by_xcd = queue != nullptr && gridDim.x % kXcds == 0;
+    const int xcd = (int)(blockIdx.x % kXcds);
+    const int xcd_wgs = (int)gridDim.x / kXcds;
+    const int xcd_total = ((n_events + kXcds - 1) / kXcds) * n_blocks;
+    int item = by_xcd ? (int)blockIdx.x / kXcds : (int)blockIdx.x;
+    while (item < (by_xcd ? xcd_total : total)) {
+        int rank, blk;
+        if (by_xcd) {
+            const int g = item / n_blocks;
+            rank = xcd_rank(g, xcd);
+            blk = item - g * n_blocks;
+        } else {
+            rank = item / n_blocks;
+            blk = item - rank * n_blocks;
+        }
+        if (rank >= n_events) {  // the last group of eight ranks is short: no such event on this XCD
+            item = by_xcd ? xcd_total : total;
+            continue;
+        }
         const int e = order ? order[rank] : rank;
-        const int blk = item - rank * n_blocks;
         const uint32_t* gt = at<const uint32_t>(event_ws(ws, ev, e), O.gtab);
         char* acc_e = acc_base + (size_t)e * acc_stride;
         for (int ci = 0; ci < cpw; ++ci) {
@@ -1105,7 +1131,12 @@ __global__ __launch_bounds__(kVotePtThreads) void k_vote_pt(Events ev, const int
                 }
             }
         }
-        if (queue) {
+        if (by_xcd) {
+            __syncthreads();
+            if (threadIdx.x == 0) next_item = xcd_wgs + atomicAdd(queue + xcd, 1);
+            __syncthreads();
+            item = __builtin_amdgcn_readfirstlane(next_item);
+        } else if (queue) {
             __syncthreads();
             if (threadIdx.x == 0) next_item = (int)gridDim.x + atomicAdd(queue, 1);
             __syncthreads();
@@ -2236,11 +2267,22 @@ __global__ __launch_bounds__(kAssignThreads) void k_assign_pt(
     Events ev, const hough_peak_t* __restrict__ peaks_base, int32_t peak_stride, int32_t cap_peaks,
     hough_status_t* __restrict__ st_base, const int32_t* __restrict__ E, int n_layers, int cell_bits, int n_cols,
     int n_qpt, int M, int F, int n_phi, int row, char* __restrict__ ws, WsOff O,
-    int32_t* __restrict__ offsets_base, int32_t* __restrict__ hit_idx_base, int32_t cap_pairs, int lds_words) {
+    int32_t* __restrict__ offsets_base, int32_t* __restrict__ hit_idx_base, int32_t cap_pairs, int lds_words,
+    const int32_t* __restrict__ order, int n_events) {
     extern __shared__ int32_t sm_i32[];
     constexpr int kWaves = kAssignThreads / 64;
     constexpr int kHead = 64;  // words for the layer starts (n_layers + 1 <= 33)
-    const int e = blockIdx.y;
+    // workgroup bx of event e; with `order` (batches, grid.y a multiple of 8), all workgroups of one
+    // event run on one XCD (see xcd_rank): linear index L -> XCD L % 8, its (L / 8)-th workgroup
+    int bx = (int)blockIdx.x, e = (int)blockIdx.y;
+    if (order) {
+        const int64_t L = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
+        const int64_t k = L / kXcds;
+        const int rank = xcd_rank((int)(k / gridDim.x), (int)(L % kXcds));
+        if (rank >= n_events) return;  // padding of the last group of eight events
+        e = order[rank];
+        bx = (int)(k % gridDim.x);
+    }
     char* w = event_ws(ws, ev, e);
     const hough_peak_t* peaks = peaks_base + (size_t)e * peak_stride;
     const int64_t* peak_voff = at<int64_t>(w, O.peak_voff);
@@ -2254,13 +2296,13 @@ __global__ __launch_bounds__(kAssignThreads) void k_assign_pt(
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
-    if (blockIdx.x == 0 && tid == 0) {
+    if (bx == 0 && tid == 0) {
         const int64_t tot = n > 0 ? peak_voff[n - 1] + peaks[n - 1].votes : 0;
         offsets[n] = (int32_t)min(tot, (int64_t)INT32_MAX);
         st->n_pairs = tot;
         if (tot > cap_pairs) atomicOr(&st->flags, HOUGH_F_PAIR_OVERFLOW);
     }
-    if ((int)blockIdx.x * kAssignThreads >= n) return;  // uniform per block
+    if (bx * kAssignThreads >= n) return;  // uniform per block
     const int n_valid = g_cell_start[n_layers << cell_bits];
     const int h4 = (n_valid + 3) >> 2;          // 16-byte chunks of sorted hit indices
     const int stage_words = (2 * h4 + 3) & ~3;  // as 16-bit values
@@ -2271,7 +2313,7 @@ __global__ __launch_bounds__(kAssignThreads) void k_assign_pt(
     uint32_t* s16 = reinterpret_cast<uint32_t*>(sm_i32 + kHead);
     int32_t* buf = sm_i32 + kHead + (staged ? stage_words : 0) + wave * buf_words;
     const int stride = gridDim.x * kAssignThreads;
-    int base = blockIdx.x * kAssignThreads + wave * 64;
+    int base = bx * kAssignThreads + wave * 64;
     hough_peak_t pk{};
     int64_t off = 0;
     if (base < n) {
@@ -3353,7 +3395,8 @@ void launch_peaks(const hough_plan* p, const Events& ev, int n_events, const voi
 
 void launch_assign(const hough_plan* p, const Events& ev, int n_events, const hough_peak_t* peaks,
                    int32_t peak_stride, int32_t cap_peaks, int32_t* offsets, int32_t* hit_idx, int32_t cap_pairs,
-                   char* ws, const WsOff& O, hough_status_t* st, hipStream_t stream) {
+                   char* ws, const WsOff& O, hough_status_t* st, hipStream_t stream,
+                   const int32_t* order = nullptr) {
     const int64_t want = ((int64_t)cap_peaks + kAssignThreads - 1) / kAssignThreads;
     const int per_event_cap = p->tuning.assign_blocks > 0 ? p->tuning.assign_blocks : n_events > 1 ? 64 : 2 * 256;
     const unsigned nblk = (unsigned)(want < per_event_cap ? want : per_event_cap);
@@ -3361,10 +3404,13 @@ void launch_assign(const hough_plan* p, const Events& ev, int n_events, const ho
     const int cells_words = (p->n_cells + 1 + 3) & ~3;
     const int lds_words = kLdsBytes / 4;
     if (p->pt) {
-        hipExtLaunchKernelGGL(k_assign_pt, dim3(nblk, n_events), dim3(kAssignThreads), kLdsBytes, stream,
+        // batches with the size order: events grouped per XCD, grid.y padded to a multiple of 8
+        const int32_t* ord = n_events > 1 ? order : nullptr;
+        const unsigned gy = ord ? (unsigned)((n_events + kXcds - 1) / kXcds * kXcds) : (unsigned)n_events;
+        hipExtLaunchKernelGGL(k_assign_pt, dim3(nblk, gy), dim3(kAssignThreads), kLdsBytes, stream,
                               p->assign_start, p->assign_stop, 0, ev, peaks, peak_stride, cap_peaks, st, p->d_E,
                               p->n_layers, p->cell_bits, p->n_cols, p->g.n_qpt, p->M, p->F, p->g.n_phi, p->pt_row, ws,
-                              O, offsets, hit_idx, cap_pairs, lds_words);
+                              O, offsets, hit_idx, cap_pairs, lds_words, ord, n_events);
         return;
     }
     // one packed word per staged hit: angles of at most 16 bits and hit indices below 2^16
@@ -4150,7 +4196,7 @@ int run_batch_on(const hough_plan_t* p, const hough_batch_t* b, void* ws_base, s
     launch_peaks(p, ev, b->n_events, b->acc, hough_acc_bytes(p), b->threshold, b->peaks, b->cap_peaks, ev_ws, O,
                  b->status, stream);
     launch_assign(p, ev, b->n_events, b->peaks, b->cap_peaks, b->cap_peaks, b->offsets, b->hit_idx, b->cap_pairs,
-                  ev_ws, O, b->status, stream);
+                  ev_ws, O, b->status, stream, order);
     if (b->zvote)
         launch_zvote(p, ev, b->n_events, b->z, b->layer, b->peaks, b->cap_peaks, b->offsets, b->hit_idx,
                      b->cap_pairs, b->status, b->zvote, stream);
