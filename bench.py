@@ -228,8 +228,10 @@ def bench_batched(H, torch, n_events: int, reps: int):
     gstream.synchronize()
     t_graph = (time.perf_counter() - t0) / reps
     graph.close()
-    # plain per-event chain over the same events
-    ev_bufs = H.EventBuffers(plan, cap_peaks=cap_peaks, cap_pairs=cap_pairs)
+    # plain per-event chain over the same events, with the single-event tuning of this grid
+    plan_single = H.Plan(cfg, max_hits=cfg.max_hits_per_event)
+    tune.apply(plan_single, "single")
+    ev_bufs = H.EventBuffers(plan_single, cap_peaks=cap_peaks, cap_pairs=cap_pairs)
     dev_hits = []
     for e in events:
         x, y, lay, _ = H.hits_to_device(e)
@@ -298,7 +300,9 @@ def bench_large_grid(H, torch, reps: int):
         torch.cuda.synchronize()
         times[with_z] = a.elapsed_time(b) / reps
     # the plain per-event chain (prep, vote, peaks, assign, r-z stage) over the same events
-    ev_bufs = H.EventBuffers(plan, cap_peaks=cap_peaks, cap_pairs=cap_pairs)
+    plan_single = H.Plan(cfg, max_hits=cfg.max_hits_per_event)
+    tune.apply(plan_single, "single")  # the single-event tuning of this grid, if there is one
+    ev_bufs = H.EventBuffers(plan_single, cap_peaks=cap_peaks, cap_pairs=cap_pairs)
     dev_hits = []
     for e in events:
         x, y, lay, z = H.hits_to_device(e)
@@ -311,7 +315,7 @@ def bench_large_grid(H, torch, reps: int):
     b.record(stream)
     torch.cuda.synchronize()
     plain_ms = a.elapsed_time(b)
-    del ev_bufs, dev_hits
+    del ev_bufs, dev_hits, plan_single
     # the second transform (vertex space) of every event's candidates, batched
     vp = H.VertexPlan.of(plan)
     vb = H.VertexBatchBuffers(vp, len(events), cap_peaks, 1 << 16)

@@ -2263,14 +2263,15 @@ __device__ __forceinline__ void assign_candidate_pt(const hough_peak_t& pk, int6
 // own one contiguous stretch of the CSR list, assembled in the wave's LDS buffer and stored
 // coalesced.  LDS: the layers' first sorted positions, then the event's sorted hit indices as 16-bit
 // values (staged when they leave room for buffers of kAssignBufMin words), then 16 wave buffers.
-__global__ __launch_bounds__(kAssignThreads) void k_assign_pt(
+template <int THREADS>
+__global__ __launch_bounds__(THREADS) void k_assign_pt(
     Events ev, const hough_peak_t* __restrict__ peaks_base, int32_t peak_stride, int32_t cap_peaks,
     hough_status_t* __restrict__ st_base, const int32_t* __restrict__ E, int n_layers, int cell_bits, int n_cols,
     int n_qpt, int M, int F, int n_phi, int row, char* __restrict__ ws, WsOff O,
     int32_t* __restrict__ offsets_base, int32_t* __restrict__ hit_idx_base, int32_t cap_pairs, int lds_words,
     const int32_t* __restrict__ order, int n_events) {
     extern __shared__ int32_t sm_i32[];
-    constexpr int kWaves = kAssignThreads / 64;
+    constexpr int kWaves = THREADS / 64;
     constexpr int kHead = 64;  // words for the layer starts (n_layers + 1 <= 33)
     // workgroup bx of event e; with `order` (batches, grid.y a multiple of 8), all workgroups of one
     // event run on one XCD (see xcd_rank): linear index L -> XCD L % 8, its (L / 8)-th workgroup
@@ -2302,7 +2303,7 @@ __global__ __launch_bounds__(kAssignThreads) void k_assign_pt(
         st->n_pairs = tot;
         if (tot > cap_pairs) atomicOr(&st->flags, HOUGH_F_PAIR_OVERFLOW);
     }
-    if (bx * kAssignThreads >= n) return;  // uniform per block
+    if (bx * THREADS >= n) return;  // uniform per block
     const int n_valid = g_cell_start[n_layers << cell_bits];
     const int h4 = (n_valid + 3) >> 2;          // 16-byte chunks of sorted hit indices
     const int stage_words = (2 * h4 + 3) & ~3;  // as 16-bit values
@@ -2312,8 +2313,8 @@ __global__ __launch_bounds__(kAssignThreads) void k_assign_pt(
     int32_t* lay_start = sm_i32;
     uint32_t* s16 = reinterpret_cast<uint32_t*>(sm_i32 + kHead);
     int32_t* buf = sm_i32 + kHead + (staged ? stage_words : 0) + wave * buf_words;
-    const int stride = gridDim.x * kAssignThreads;
-    int base = bx * kAssignThreads + wave * 64;
+    const int stride = gridDim.x * THREADS;
+    int base = bx * THREADS + wave * 64;
     hough_peak_t pk{};
     int64_t off = 0;
     if (base < n) {
@@ -2323,14 +2324,14 @@ __global__ __launch_bounds__(kAssignThreads) void k_assign_pt(
     }
     if (tid <= n_layers) lay_start[tid] = g_cell_start[tid << cell_bits];
     if (staged) {
-        for (int c0 = tid; c0 < h4; c0 += kStageUnroll * kAssignThreads) {
+        for (int c0 = tid; c0 < h4; c0 += kStageUnroll * THREADS) {
             uint4 v[kStageUnroll];
 #pragma unroll
             for (int u = 0; u < kStageUnroll; ++u)
-                v[u] = reinterpret_cast<const uint4*>(sorted_h)[min(c0 + u * kAssignThreads, h4 - 1)];
+                v[u] = reinterpret_cast<const uint4*>(sorted_h)[min(c0 + u * THREADS, h4 - 1)];
 #pragma unroll
             for (int u = 0; u < kStageUnroll; ++u) {
-                const int c = c0 + u * kAssignThreads;
+                const int c = c0 + u * THREADS;
                 if (c < h4)
                     reinterpret_cast<uint2*>(s16)[c] =
                         make_uint2((v[u].x & 0xFFFFu) | (v[u].y << 16), (v[u].z & 0xFFFFu) | (v[u].w << 16));
@@ -3397,7 +3398,11 @@ void launch_assign(const hough_plan* p, const Events& ev, int n_events, const ho
                    int32_t peak_stride, int32_t cap_peaks, int32_t* offsets, int32_t* hit_idx, int32_t cap_pairs,
                    char* ws, const WsOff& O, hough_status_t* st, hipStream_t stream,
                    const int32_t* order = nullptr) {
-    const int64_t want = ((int64_t)cap_peaks + kAssignThreads - 1) / kAssignThreads;
+    // batches: 512-thread workgroups with half the LDS, so that two share a CU and one's table loads
+    // and staging overlap the other's copying; a single event: 1024 threads and the whole LDS
+    const bool half = n_events > 1 && p->pt;
+    const int threads = half ? kAssignThreads / 2 : kAssignThreads;
+    const int64_t want = ((int64_t)cap_peaks + threads - 1) / threads;
     const int per_event_cap = p->tuning.assign_blocks > 0 ? p->tuning.assign_blocks : n_events > 1 ? 64 : 2 * 256;
     const unsigned nblk = (unsigned)(want < per_event_cap ? want : per_event_cap);
     // the kernel lays out its LDS per event (cell table, staged hits, wave buffers)
@@ -3407,10 +3412,17 @@ void launch_assign(const hough_plan* p, const Events& ev, int n_events, const ho
         // batches with the size order: events grouped per XCD, grid.y padded to a multiple of 8
         const int32_t* ord = n_events > 1 ? order : nullptr;
         const unsigned gy = ord ? (unsigned)((n_events + kXcds - 1) / kXcds * kXcds) : (unsigned)n_events;
-        hipExtLaunchKernelGGL(k_assign_pt, dim3(nblk, gy), dim3(kAssignThreads), kLdsBytes, stream,
-                              p->assign_start, p->assign_stop, 0, ev, peaks, peak_stride, cap_peaks, st, p->d_E,
-                              p->n_layers, p->cell_bits, p->n_cols, p->g.n_qpt, p->M, p->F, p->g.n_phi, p->pt_row, ws,
-                              O, offsets, hit_idx, cap_pairs, lds_words, ord, n_events);
+        if (half)
+            hipExtLaunchKernelGGL(k_assign_pt<kAssignThreads / 2>, dim3(nblk, gy), dim3(kAssignThreads / 2),
+                                  kLdsBytes / 2, stream, p->assign_start, p->assign_stop, 0, ev, peaks, peak_stride,
+                                  cap_peaks, st, p->d_E, p->n_layers, p->cell_bits, p->n_cols, p->g.n_qpt, p->M, p->F,
+                                  p->g.n_phi, p->pt_row, ws, O, offsets, hit_idx, cap_pairs, lds_words / 2, ord,
+                                  n_events);
+        else
+            hipExtLaunchKernelGGL(k_assign_pt<kAssignThreads>, dim3(nblk, gy), dim3(kAssignThreads), kLdsBytes, stream,
+                                  p->assign_start, p->assign_stop, 0, ev, peaks, peak_stride, cap_peaks, st, p->d_E,
+                                  p->n_layers, p->cell_bits, p->n_cols, p->g.n_qpt, p->M, p->F, p->g.n_phi,
+                                  p->pt_row, ws, O, offsets, hit_idx, cap_pairs, lds_words, ord, n_events);
         return;
     }
     // one packed word per staged hit: angles of at most 16 bits and hit indices below 2^16
@@ -3999,7 +4011,11 @@ int hough_plan_create(const hough_geometry_t* geom, const hough_grid_t* grid, ho
         ae = hipFuncSetAttribute((const void*)k_prep_bucket, hipFuncAttributeMaxDynamicSharedMemorySize,
                                  kLdsBytes - 1024);
     if (ae == hipSuccess)
-        ae = hipFuncSetAttribute((const void*)k_assign_pt, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
+        ae = hipFuncSetAttribute((const void*)k_assign_pt<kAssignThreads>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 kLdsBytes);
+    if (ae == hipSuccess)
+        ae = hipFuncSetAttribute((const void*)k_assign_pt<kAssignThreads / 2>,
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes / 2);
     if (ae == hipSuccess)
         ae = hipFuncSetAttribute((const void*)k_prep_fine, hipFuncAttributeMaxDynamicSharedMemorySize,
                                  kLdsBytes - 1024);  // static LDS aside
