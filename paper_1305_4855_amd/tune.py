@@ -113,7 +113,8 @@ def tune(cfg, events, mode: str = "batch", reps: int = 3, passes: int = 2, log=p
         def outputs():
             return (bufs.acc, bufs.peaks, bufs.offsets, bufs.hit_idx, bufs.status, bufs.zv)
     else:
-        bufs = H.EventBuffers(plan, cap_peaks=1 << 19, cap_pairs=1 << 24)
+        big = bool(cfg.n_cot)  # the large grid: about 1.5 M candidates and 16 M pairs per event
+        bufs = H.EventBuffers(plan, cap_peaks=1 << 21 if big else 1 << 19, cap_pairs=1 << 25 if big else 1 << 24)
         x, y, lay, z = H.hits_to_device(events[0])
         hits = H.make_hits(x, y, lay, z)
 
