@@ -2262,7 +2262,8 @@ __device__ __forceinline__ void assign_candidate_pt(const hough_peak_t& pk, int6
 // One thread per listed candidate (grid.y = event), as k_assign_fill: the 64 candidates of a wave
 // own one contiguous stretch of the CSR list, assembled in the wave's LDS buffer and stored
 // coalesced.  LDS: the layers' first sorted positions, then the event's sorted hit indices as 16-bit
-// values (staged when they leave room for buffers of kAssignBufMin words), then 16 wave buffers.
+// values (staged when they leave room for buffers of kAssignBufMin words), then THREADS / 64 wave
+// buffers.  THREADS = 1024 with the whole LDS for a single event, 512 with half of it for batches.
 template <int THREADS>
 __global__ __launch_bounds__(THREADS) void k_assign_pt(
     Events ev, const hough_peak_t* __restrict__ peaks_base, int32_t peak_stride, int32_t cap_peaks,
