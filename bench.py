@@ -852,6 +852,14 @@ def main() -> int:
             out["serving_below_capacity"] = res[1]
     if probe_res is not None:
         out["roofline_probe"] = probe_res
+    # the paper's own GPU figure, as context (its timing plots are not recoverable; only the prose survives)
+    out["paper_context"] = {
+        "gpu_hough_time_per_event": "several tens of ms per event of up to 5000 hits, data resident on the GPU, "
+                                    "transfers excluded (Tesla C2075 / K20c; Sec. Preliminary Results)",
+        "gpu_hough_events_per_s_implied": "a few tens per second",
+        "cpu_openmp_speedup": "2.6 to 3.6 times one thread on a 4-core Ivy Bridge (Sec. Preliminary Results)",
+        "note": "two-parameter transform on the paper's own simulation; not the workload measured here",
+    }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(configs.C2, synth.make_event(configs.C2, 0))
     print(json.dumps(out, default=lambda o: o.item() if isinstance(o, np.generic) else str(o)), flush=True)

@@ -200,6 +200,7 @@ size_t batch_header_bytes(int32_t n_events) { return align_up(256 + 4 * (size_t)
 // event on one XCD: XCD x takes the events of size rank 8g + x for even g and 8g + 7 - x for odd g
 // (a snake over the size order, which balances the XCDs' totals).
 constexpr int kXcds = 8;
+constexpr int kXcdMinEvents = 4 * kXcds;  // fewer events would leave XCDs idle: they are spread instead
 __host__ __device__ __forceinline__ int xcd_rank(int g, int x) { return kXcds * g + ((g & 1) ? kXcds - 1 - x : x); }
 
 template <typename T>
@@ -1059,7 +1060,7 @@ __global__ __launch_bounds__(kVotePtThreads) void k_vote_pt(Events ev, const int
     const int row2 = row / 2;                        // row length in dwords
     // with a queue (batches): the workgroups of XCD x = blockIdx.x % 8 take the (event, column
     // block) items of that XCD's events (xcd_rank) from the XCD's own queue counter
-    const bool by_xcd = queue != nullptr && gridDim.x % kXcds == 0;
+    const bool by_xcd = queue != nullptr && gridDim.x % kXcds == 0 && n_events >= kXcdMinEvents;
     const int xcd = (int)(blockIdx.x % kXcds);
     const int xcd_wgs = (int)gridDim.x / kXcds;
     const int xcd_total = ((n_events + kXcds - 1) / kXcds) * n_blocks;
@@ -3399,19 +3400,23 @@ void launch_assign(const hough_plan* p, const Events& ev, int n_events, const ho
                    int32_t peak_stride, int32_t cap_peaks, int32_t* offsets, int32_t* hit_idx, int32_t cap_pairs,
                    char* ws, const WsOff& O, hough_status_t* st, hipStream_t stream,
                    const int32_t* order = nullptr) {
-    // batches: 512-thread workgroups with half the LDS, so that two share a CU and one's table loads
-    // and staging overlap the other's copying; a single event: 1024 threads and the whole LDS
-    const bool half = n_events > 1 && p->pt;
+    // batches of at least 8 events: 512-thread workgroups with half the LDS, so that two share a CU
+    // and one's table loads and staging overlap the other's copying; fewer events: 1024 threads and
+    // the whole LDS, as for a single event
+    const bool half = n_events >= kXcds && p->pt;
     const int threads = half ? kAssignThreads / 2 : kAssignThreads;
     const int64_t want = ((int64_t)cap_peaks + threads - 1) / threads;
-    const int per_event_cap = p->tuning.assign_blocks > 0 ? p->tuning.assign_blocks : n_events > 1 ? 64 : 2 * 256;
+    int64_t per_event_cap = p->tuning.assign_blocks > 0 ? p->tuning.assign_blocks : n_events > 1 ? 64 : 2 * 256;
+    // a small batch still gets two workgroups per CU in all
+    const int64_t fill = (2 * (int64_t)p->n_cu * (kAssignThreads / threads) + n_events - 1) / n_events;
+    if (n_events > 1 && per_event_cap < fill) per_event_cap = fill;
     const unsigned nblk = (unsigned)(want < per_event_cap ? want : per_event_cap);
     // the kernel lays out its LDS per event (cell table, staged hits, wave buffers)
     const int cells_words = (p->n_cells + 1 + 3) & ~3;
     const int lds_words = kLdsBytes / 4;
     if (p->pt) {
-        // batches with the size order: events grouped per XCD, grid.y padded to a multiple of 8
-        const int32_t* ord = n_events > 1 ? order : nullptr;
+        // large batches with the size order: events grouped per XCD, grid.y padded to a multiple of 8
+        const int32_t* ord = n_events >= kXcdMinEvents ? order : nullptr;
         const unsigned gy = ord ? (unsigned)((n_events + kXcds - 1) / kXcds * kXcds) : (unsigned)n_events;
         if (half)
             hipExtLaunchKernelGGL(k_assign_pt<kAssignThreads / 2>, dim3(nblk, gy), dim3(kAssignThreads / 2),
