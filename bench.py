@@ -581,7 +581,7 @@ def bench_serving(H, torch, runs, pool_size: int = 256):
     cfg = configs.C5
     pool = [synth.make_event(cfg, i) for i in range(pool_size)]
     plan = H.Plan(cfg, max_hits=cfg.max_hits_per_event)
-    tune.apply(plan, "batch")
+    tuning = tune.apply(plan, "serve")  # tuned on launches of a few events, as serving makes them
     # per-event capacities hold the pool's largest event (2000 tracks: about 2.4e5 candidates and
     # 1.3e7 hit-candidate pairs), so no served list is cut
     srv = serve.Server(plan, cfg.threshold, budget_bytes=cfg.hbm_budget_bytes, n_contexts=4, max_batch=64,
@@ -600,7 +600,8 @@ def bench_serving(H, torch, runs, pool_size: int = 256):
             f"[bench] serving t={t:.0f}s served={n} queued={q}", file=sys.stderr, flush=True))
         if stats["events_flagged"]:
             raise RuntimeError(f"serving: {stats['events_flagged']} events flagged (flags {stats['status_flags_or']})")
-        stats.update(workload=f"Poisson arrivals at {rate_hz:.0f} Hz for {duration_s:.0f} s, sizes as the batched "
+        stats.update(tuning=tuning,
+                     workload=f"Poisson arrivals at {rate_hz:.0f} Hz for {duration_s:.0f} s, sizes as the batched "
                               f"workload (pool of {pool_size} distinct events), 64 GiB device budget "
                               f"({srv.n_slots} resident slots, {len(srv.contexts)} launch contexts of up to "
                               f"{srv.max_batch} events), 512x256x64 int32",

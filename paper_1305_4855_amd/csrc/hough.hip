@@ -3407,8 +3407,8 @@ void launch_assign(const hough_plan* p, const Events& ev, int n_events, const ho
     const int threads = half ? kAssignThreads / 2 : kAssignThreads;
     const int64_t want = ((int64_t)cap_peaks + threads - 1) / threads;
     int64_t per_event_cap = p->tuning.assign_blocks > 0 ? p->tuning.assign_blocks : n_events > 1 ? 64 : 2 * 256;
-    // a small batch still gets two workgroups per CU in all
-    const int64_t fill = (2 * (int64_t)p->n_cu * (kAssignThreads / threads) + n_events - 1) / n_events;
+    // a small batch still fills every CU once (one 1024-thread or two 512-thread workgroups per CU)
+    const int64_t fill = ((int64_t)p->n_cu * (kAssignThreads / threads) + n_events - 1) / n_events;
     if (n_events > 1 && per_event_cap < fill) per_event_cap = fill;
     const unsigned nblk = (unsigned)(want < per_event_cap ? want : per_event_cap);
     // the kernel lays out its LDS per event (cell table, staged hits, wave buffers)

@@ -13,10 +13,12 @@ at a time, keeps the fastest, and sweeps all knobs twice (coordinate descent).  
 shape it checks that the shape's outputs (accumulators, candidate lists, CSR offsets and hit
 lists, statuses, r-z results) have the same checksums as the first shape's.  The best shape is
 stored in tuning_cache.json under a key of device architecture, grid, counter width, angle bits,
-kernel path and mode ("batch": the batched chain; "single": the per-event chain).
+kernel path and mode ("batch": the batched chain on a large batch; "serve": the batched chain on the
+few events a serving launch holds; "single": the per-event chain).
 
-    python -m paper_1305_4855_amd.tune --config c3 --events 64          # batched chain
-    python -m paper_1305_4855_amd.tune --config c2 --mode single         # per-event chain
+    python -m paper_1305_4855_amd.tune --config c3 --events 64                # batched chain
+    python -m paper_1305_4855_amd.tune --config c3 --mode serve --events 4    # serving launches
+    python -m paper_1305_4855_amd.tune --config c2 --mode single               # per-event chain
 """
 from __future__ import annotations
 
@@ -31,6 +33,8 @@ CACHE = os.path.join(HERE, "tuning_cache.json")
 SPACE = {
     "batch": dict(vote_cols=(16, 32, 64), vote_grid=(1024, 2048, 4096), peak_planes=(8, 16, 32),
                   assign_blocks=(32, 64, 128), prep_rows=(64, 128, 256), vote_threads=(512, 1024)),
+    "serve": dict(vote_cols=(8, 16, 32), vote_grid=(512, 1024, 2048), peak_planes=(8, 16, 32),
+                  assign_blocks=(64, 128, 256), prep_rows=(32, 64, 128, 256), vote_threads=(512, 1024)),
     "single": dict(vote_cols=(4, 8, 16, 32), peak_planes=(4, 8, 16), assign_blocks=(256, 512, 1024),
                    prep_rows=(32, 64, 128, 256), vote_threads=(512, 1024)),
 }
@@ -60,8 +64,13 @@ def load_cache() -> dict:
 
 
 def apply(plan, mode: str = "batch") -> dict:
-    """Set the cached tuning for this plan's grid, path and mode on this device, if there is one."""
-    entry = load_cache().get(cache_key(plan.cfg, device_arch(), plan.max_hits, mode))
+    """Set the cached tuning for this plan's grid, path and mode on this device, if there is one (a
+    serving plan without its own entry takes the batch entry)."""
+    cache = load_cache()
+    arch = device_arch()
+    entry = cache.get(cache_key(plan.cfg, arch, plan.max_hits, mode))
+    if entry is None and mode == "serve":
+        entry = cache.get(cache_key(plan.cfg, arch, plan.max_hits, "batch"))
     if entry:
         plan.set_tuning(**{**DEFAULT, **entry["best"]})
     return plan.tuning
@@ -99,9 +108,10 @@ def tune(cfg, events, mode: str = "batch", reps: int = 3, passes: int = 2, log=p
 
     from . import hough as H
 
-    max_hits = cfg.max_hits_per_event if mode == "batch" else max(16384, max(e.n for e in events))
+    batched = mode in ("batch", "serve")
+    max_hits = cfg.max_hits_per_event if batched else max(16384, max(e.n for e in events))
     plan = H.Plan(cfg, max_hits=max_hits)
-    if mode == "batch":
+    if batched:
         total = sum(e.n for e in events)
         bufs = H.BatchBuffers(plan, len(events), total, cap_peaks=1 << 21 if cfg.n_cot else 1 << 19,
                               cap_pairs=1 << 24)
@@ -142,7 +152,7 @@ def tune(cfg, events, mode: str = "batch", reps: int = 3, passes: int = 2, log=p
         flags = bufs.status.view(-1, H.STATUS_BYTES // 4)[:, 5].cpu().numpy()
         if flags.any():
             raise RuntimeError(f"capacity too small for the tuning events (flags {int(flags.max())})")
-        d = _digest(outputs(), per_event=mode == "batch")
+        d = _digest(outputs(), per_event=batched)
         if ref is None:
             ref = d
         elif d != ref:
@@ -171,13 +181,13 @@ def main() -> int:
 
     ap = argparse.ArgumentParser()
     ap.add_argument("--config", default="c3")
-    ap.add_argument("--mode", choices=("batch", "single"), default="batch")
+    ap.add_argument("--mode", choices=("batch", "serve", "single"), default="batch")
     ap.add_argument("--events", type=int, default=64)
     ap.add_argument("--reps", type=int, default=3)
     ap.add_argument("--cache", default=CACHE, help="cache file to update (default: the package's)")
     args = ap.parse_args()
     cfg = configs.get(args.config)
-    n = args.events if args.mode == "batch" else 1
+    n = args.events if args.mode != "single" else 1
     events = [synth.make_event(cfg, i) for i in range(n)]
     arch = device_arch()
     print(f"tuning {cfg.name} ({args.mode}) on {arch} with {len(events)} events", flush=True)
