@@ -137,6 +137,7 @@ struct hough_plan {
     bool pt;         // window-table path: prefix-count table per event, table vote and assignment
     int pt_bpl;      // bins per lane of the table vote (n_phi / 64)
     int pt_row;      // entries per window-count row (n_phi + pt_bpl + 2, rounded up to 8)
+    int pt_row8;     // bytes per 8-bit window-count row (n_phi + pt_bpl + 4, rounded up to 16); 0 = none
     bool stage;      // bin values fit 16 bits: the peak marker keeps each group's candidate values
 };
 
@@ -144,7 +145,7 @@ namespace {
 
 // ------------------------------------------------------------------ layout
 struct WsLayout {
-    size_t misc, phi32, lay, cell_start, tmp_phi, tmp_key, sorted_phi, sorted_h, ptab, gtab;
+    size_t misc, phi32, lay, cell_start, tmp_phi, tmp_key, sorted_phi, sorted_h, ptab, gtab, gtab8;
     size_t flags, grp_count, grp_votes, grp_off, grp_voff, stage, peak_voff, total;
 };
 
@@ -179,6 +180,7 @@ WsLayout ws_layout(const hough_plan* p, int32_t max_peaks) {
     L.sorted_h = take(4 * maxh);
     L.ptab = take(p->pt ? (size_t)p->n_layers * ((size_t)1 << p->F) * p->g.n_phi * 2 : 0);
     L.gtab = take(p->pt ? (size_t)p->n_layers * ((size_t)1 << p->F) * p->pt_row * 2 : 0);
+    L.gtab8 = take(p->pt ? (size_t)p->n_layers * ((size_t)1 << p->F) * p->pt_row8 : 0);
     L.flags = take((size_t)(p->n_bins / kStrip));
     L.grp_count = take(4 * (size_t)(peak_groups(p) + 1));
     L.grp_votes = take(4 * (size_t)(peak_groups(p) + 1));
@@ -291,15 +293,20 @@ __device__ __forceinline__ int64_t block_reduce_sum(int64_t v, int64_t* wsum) {
 }
 
 struct WsOff {
-    size_t misc, phi32, lay, cell_start, tmp_phi, tmp_key, sorted_phi, sorted_h, ptab, gtab;
+    size_t misc, phi32, lay, cell_start, tmp_phi, tmp_key, sorted_phi, sorted_h, ptab, gtab, gtab8;
     size_t flags, grp_count, grp_votes, grp_off, grp_voff, stage, peak_voff;
 };
 
 WsOff ws_off(const WsLayout& L) {
-    return WsOff{L.misc,  L.phi32, L.lay,       L.cell_start, L.tmp_phi,  L.tmp_key, L.sorted_phi, L.sorted_h,
-                 L.ptab,  L.gtab,  L.flags,     L.grp_count,  L.grp_votes, L.grp_off, L.grp_voff,  L.stage,
-                 L.peak_voff};
+    return WsOff{L.misc,  L.phi32, L.lay,   L.cell_start, L.tmp_phi,   L.tmp_key,  L.sorted_phi, L.sorted_h,
+                 L.ptab,  L.gtab,  L.gtab8, L.flags,      L.grp_count, L.grp_votes, L.grp_off,   L.grp_voff,
+                 L.stage, L.peak_voff};
 }
+
+// misc words of an event's workspace: [0] listed candidates, [1] sorted by the bucketing pass (slab
+// path), [2] some window of the table path holds more than 255 hits (the vote then reads the
+// 16-bit window counts instead of the 8-bit ones)
+constexpr int kMiscWide = 2;
 
 // ------------------------------------------------------------------ batch set-up
 // One workgroup: order the events by decreasing hit count (ties by index) for the vote's work
@@ -329,8 +336,9 @@ __global__ __launch_bounds__(256) void k_prep_hits(Events ev, const float* __res
     event_hits(ev, e, h0, n);
     if (n > ev.max_hits) return;
     const int h = blockIdx.x * blockDim.x + threadIdx.x;
-    if (h >= n) return;
     char* w = event_ws(ws, ev, e);
+    if (h == 0) at<int32_t>(w, O.misc)[kMiscWide] = 0;  // set again by k_prep_fine if a window is wide
+    if (h >= n) return;
     const float x = hx[h0 + h], y = hy[h0 + h];
     const uint8_t L = hl[h0 + h];
     bool ok = (int)L < n_layers && isfinite(x) && isfinite(y) && fabsf(x) < 32768.0f && fabsf(y) < 32768.0f;
@@ -604,7 +612,8 @@ constexpr int kFineTieCap = 1024;  // tied hits a workgroup ranks in LDS (more: 
 constexpr int kFineUnroll = 16;    // hits per thread loaded at once
 
 __global__ __launch_bounds__(kScanThreads) void k_prep_fine(Events ev, int n_layers, int cell_bits, int M, int F,
-                                                            int n_phi, int row, int R, int n_chunks, LayerTable LT,
+                                                            int n_phi, int row, int row8, int R, int n_chunks,
+                                                            LayerTable LT,
                                                             char* __restrict__ ws, WsOff O,
                                                             hough_status_t* __restrict__ st_base) {
     extern __shared__ uint32_t fine_lds[];
@@ -729,6 +738,36 @@ __global__ __launch_bounds__(kScanThreads) void k_prep_fine(Events ev, int n_lay
             const uint32_t p0 = P16(2 * jp, r), p1 = P16(2 * jp + 1, r), p2 = P16(2 * jp + 2, r);
             gt[((size_t)r * row + n_phi) / 2 + jp] = ((p1 - p0) & 0xFFFFu) | ((p2 - p1) << 16);
         }
+    }
+    // the same window counts as bytes, four per store (the vote's table while no window of the event
+    // holds more than 255 hits; a wider one sets the event's flag and the vote reads the 16-bit rows)
+    if (row8 > 0) {
+        uint32_t* gt8 = reinterpret_cast<uint32_t*>(at<uint8_t>(w, O.gtab8) + (size_t)L * W * row8);
+        bool wide = false;
+        auto quad = [&](int j0, int r) -> uint32_t {  // counts of local rows j0 .. j0 + 3 at phase r
+            uint32_t word = 0, prev = P16(j0, r);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const uint32_t next = P16(j0 + u + 1, r), cnt = (next - prev) & 0xFFFFu;
+                wide = wide || cnt > 255u;
+                word |= (cnt > 255u ? 255u : cnt) << (8 * u);
+                prev = next;
+            }
+            return word;
+        };
+        const int RQ = R / 4;
+        for (int t = tid; t < W * RQ; t += kScanThreads) {
+            const int r = t / RQ, jq = t - r * RQ;
+            gt8[((size_t)r * row8 + row0) / 4 + jq] = quad(4 * jq, r);
+        }
+        if (c == 0) {
+            const int EQ = (row8 - n_phi) / 4;
+            for (int t = tid; t < W * EQ; t += kScanThreads) {
+                const int r = t / EQ, jq = t - r * EQ;
+                gt8[((size_t)r * row8 + n_phi) / 4 + jq] = quad(4 * jq, r);
+            }
+        }
+        if (wide) atomicOr(at<int32_t>(w, O.misc) + kMiscWide, 1);
     }
     // sorted positions of the chunk's hits
     int32_t* sorted_h = at<int32_t>(w, O.sorted_h) + base;
@@ -1039,7 +1078,7 @@ constexpr int kVotePtThreads = 256;
 
 template <int BPL, bool OUT16>
 __global__ __launch_bounds__(kVotePtThreads) void k_vote_pt(Events ev, const int32_t* __restrict__ E, int n_layers,
-                                                           int n_cols, int n_phi, int M, int F, int row,
+                                                           int n_cols, int n_phi, int M, int F, int row, int row8,
                                                            const uint32_t* __restrict__ zero_row,
                                                            char* __restrict__ ws, WsOff O,
                                                            char* __restrict__ acc_base, size_t acc_stride,
@@ -1081,13 +1120,54 @@ __global__ __launch_bounds__(kVotePtThreads) void k_vote_pt(Events ev, const int
         }
         const int e = order ? order[rank] : rank;
         const uint32_t* gt = at<const uint32_t>(event_ws(ws, ev, e), O.gtab);
+        const uint8_t* gt8 = at<const uint8_t>(event_ws(ws, ev, e), O.gtab8);
+        // the 8-bit window counts unless a window of this event holds more than 255 hits
+        const bool use8 = row8 > 0 && at<const int32_t>(event_ws(ws, ev, e), O.misc)[kMiscWide] == 0;
         char* acc_e = acc_base + (size_t)e * acc_stride;
         for (int ci = 0; ci < cpw; ++ci) {
             const int col = blk * cpi + wave * cpw + ci;
             uint32_t acc[NP];
 #pragma unroll
             for (int q = 0; q < NP; ++q) acc[q] = 0u;
-            for (int L0 = 0; L0 < n_layers; L0 += LG) {
+            if constexpr (BPL >= 4) {
+                if (use8) {
+                    // a lane's BPL bytes from the dword holding its first entry on: sh = the entry's byte
+                    // in that dword (the same for every lane, BPL being a multiple of 4); the bytes past
+                    // the lane's dwords are the next lane's first dword (ds_bpermute), and
+                    // v_alignbyte/v_perm spread each run of four counts into two 16-bit pairs
+                    constexpr int NQ = BPL / 4;
+                    constexpr int LG8 = (NQ + 1) * 10 <= 60 ? 10 : (60 / (NQ + 1) > 0 ? 60 / (NQ + 1) : 1);
+                    for (int L0 = 0; L0 < n_layers; L0 += LG8) {
+                        uint32_t d[LG8][NQ + 1];
+                        uint32_t sh[LG8];
+#pragma unroll
+                        for (int u = 0; u < LG8; ++u) {
+                            const int L = L0 + u;
+                            const int32_t ev_l = L < n_layers ? E[(size_t)L * n_cols + col] : INT32_MIN;
+                            const uint32_t ep = (uint32_t)ev_l & mmask;
+                            const uint32_t r = ep & wmask, sft = ep >> F;
+                            const uint32_t i0 = (sft + (uint32_t)(lane * BPL)) & (uint32_t)(n_phi - 1);
+                            const uint32_t* src =
+                                ev_l != INT32_MIN
+                                    ? reinterpret_cast<const uint32_t*>(gt8 + ((size_t)L * (1u << F) + r) * row8)
+                                    : zero_row;
+                            sh[u] = __builtin_amdgcn_readfirstlane(sft) & 3u;
+                            __builtin_memcpy(&d[u][0], src + (i0 >> 2), 4 * NQ);  // dword-aligned loads
+                        }
+#pragma unroll
+                        for (int u = 0; u < LG8; ++u) {
+                            d[u][NQ] = sh[u] ? (uint32_t)__builtin_amdgcn_ds_bpermute(next4, (int)d[u][0]) : 0u;
+#pragma unroll
+                            for (int k = 0; k < NQ; ++k) {
+                                const uint32_t x = __builtin_amdgcn_alignbyte(d[u][k + 1], d[u][k], sh[u]);
+                                acc[2 * k] += __builtin_amdgcn_perm(x, x, 0x0c010c00u);
+                                acc[2 * k + 1] += __builtin_amdgcn_perm(x, x, 0x0c030c02u);
+                            }
+                        }
+                    }
+                }
+            }
+            for (int L0 = 0; L0 < ((BPL >= 4 && use8) ? 0 : n_layers); L0 += LG) {
                 uint32_t d[LG][ND];
                 uint32_t sel[LG];
                 bool odd[LG];
@@ -3204,7 +3284,8 @@ int bucket_cap_hits(const hough_plan* p) {
 // phi0 rows per k_prep_fine workgroup: the tuned value (a power of two), else kFineRows; at most n_phi
 int fine_rows(const hough_plan* p) {
     int R = p->tuning.prep_rows > 0 ? p->tuning.prep_rows : kFineRows;
-    while (R < p->pt_row - p->g.n_phi) R *= 2;  // chunk 0 writes the window counts past the turn from its rows
+    const int past = (p->pt_row > p->pt_row8 ? p->pt_row : p->pt_row8) - p->g.n_phi;
+    while (R < past) R *= 2;  // chunk 0 writes the window counts past the turn from its rows
     return p->g.n_phi < R ? p->g.n_phi : R;
 }
 
@@ -3215,6 +3296,11 @@ size_t fine_lds_bytes(const hough_plan* p) {
 }
 
 // Launchers shared by the single-event and batched entry points.
+// The 8-bit window counts serve batches (where the vote's table reads bound it); a single event's
+// vote waits on latency instead, and writing the second table would only lengthen its prep.  The
+// prep and the vote of one chain see the same event count, so they agree on the table.
+int pt_row8_for(const hough_plan* p, int n_events) { return n_events > 1 ? p->pt_row8 : 0; }
+
 void launch_prep(const hough_plan* p, const Events& ev, int n_events, int max_n, const float* x, const float* y,
                  const uint8_t* layer, uint32_t* phi_out, char* ws, const WsOff& O, hough_status_t* st,
                  hipStream_t stream) {
@@ -3226,7 +3312,7 @@ void launch_prep(const hough_plan* p, const Events& ev, int n_events, int max_n,
         const int n_chunks = p->g.n_phi / R;
         hipLaunchKernelGGL(k_prep_fine, dim3(p->n_layers * n_chunks, n_events), dim3(kScanThreads),
                            fine_lds_bytes(p), stream, ev, p->n_layers, p->cell_bits, p->M, p->F, p->g.n_phi,
-                           p->pt_row, R, n_chunks, p->layers, ws, O, st);
+                           p->pt_row, pt_row8_for(p, n_events), R, n_chunks, p->layers, ws, O, st);
         return;
     }
     // events of at most cap_h hits are sorted by one workgroup per layer (LDS); the rank pass
@@ -3270,11 +3356,11 @@ void launch_vote_pt_bpl(const hough_plan* p, const Events& ev, int n_events, cha
     if (p->g.acc_bits == 16)
         hipExtLaunchKernelGGL((k_vote_pt<BPL, true>), dim3(grid), dim3(kVotePtThreads), 0, stream, p->vote_start,
                               p->vote_stop, 0, ev, p->d_E, p->n_layers, p->n_cols, p->g.n_phi, p->M, p->F, p->pt_row,
-                              zr, ws, O, a, acc_stride, n_events, order, queue, cpi);
+                              pt_row8_for(p, n_events), zr, ws, O, a, acc_stride, n_events, order, queue, cpi);
     else
         hipExtLaunchKernelGGL((k_vote_pt<BPL, false>), dim3(grid), dim3(kVotePtThreads), 0, stream, p->vote_start,
                               p->vote_stop, 0, ev, p->d_E, p->n_layers, p->n_cols, p->g.n_phi, p->M, p->F, p->pt_row,
-                              zr, ws, O, a, acc_stride, n_events, order, queue, cpi);
+                              pt_row8_for(p, n_events), zr, ws, O, a, acc_stride, n_events, order, queue, cpi);
 }
 
 void launch_vote_pt(const hough_plan* p, const Events& ev, int n_events, char* ws, const WsOff& O, void* acc,
@@ -3886,6 +3972,8 @@ int hough_plan_create(const hough_geometry_t* geom, const hough_grid_t* grid, ho
     p->stage = g.max_hits_per_event <= 65535;  // a bin holds at most one vote per hit
     p->pt_bpl = g.n_phi / 64;
     p->pt_row = ((g.n_phi + p->pt_bpl + 2) + 7) & ~7;  // window-count rows: entries a lane reads past the turn
+    // 8-bit window counts: a lane reads its bins as whole dwords (at least four bins per lane)
+    p->pt_row8 = p->pt_bpl >= 4 ? ((g.n_phi + p->pt_bpl + 4) + 15) & ~15 : 0;
     p->n_cols = g.n_d0 * g.n_qpt;
     p->n_cells = p->n_layers << p->cell_bits;
     p->n_bins = (int64_t)p->n_cols * g.n_phi;

@@ -72,6 +72,45 @@ def test_batch_equals_single_and_oracle(H, oracle_mod):
         np.testing.assert_array_equal(acc[e], single["acc"])
 
 
+def test_batch_wide_windows_read_the_16bit_counts(H, oracle_mod):
+    """Batches vote from 8-bit window counts unless a window of the event holds more than 255 hits:
+    an event with 300 extra hits at one azimuth of the innermost layer takes the 16-bit counts, its
+    neighbours in the batch keep the 8-bit ones, and every event equals the oracle and the single
+    path."""
+    O = oracle_mod
+    cfg, base = _small_batch_events()
+    ev = base[3]
+    phi = 0.7 + np.arange(300) * 1e-6
+    r0 = cfg.radii_cm[0]
+    x = np.concatenate([ev.x, (r0 * np.cos(phi)).astype(np.float32)])
+    y = np.concatenate([ev.y, (r0 * np.sin(phi)).astype(np.float32)])
+    lay = np.concatenate([ev.layer, np.zeros(300, np.uint8)])
+    tid = np.concatenate([ev.track_id, np.full(300, -1, np.int32)])
+    crowded = synth.Event(x=x, y=y, z=None, layer=lay, track_id=tid, truth=ev.truth)
+    events = [base[0], crowded, base[5]]
+    plan = H.Plan(cfg, max_hits=4096)
+    cap_peaks, cap_pairs = 1 << 14, 1 << 18
+    bufs = H.BatchBuffers(plan, len(events), sum(e.n for e in events), cap_peaks, cap_pairs)
+    bufs.load(events)
+    print(f"[batch] wide windows: {[e.n for e in events]} hits", flush=True)
+    bufs.run(cfg.threshold)
+    torch.cuda.synchronize()
+    acc = bufs.acc.cpu().numpy()
+    g = O.Cfg(cfg)
+    for e, evt in enumerate(events):
+        res = bufs.results(e)
+        acc_ref, nv = O.vote(g, evt)
+        np.testing.assert_array_equal(acc[e], acc_ref, err_msg=f"event {e}")
+        n_ref, pk_ref = O.peaks(g, acc_ref, cfg.threshold)
+        np.testing.assert_array_equal(res["peaks"], pk_ref)
+        offs_ref, hit_ref, _ = O.assign(g, evt, pk_ref)
+        np.testing.assert_array_equal(res["offsets"], offs_ref)
+        np.testing.assert_array_equal(res["hit_idx"], hit_ref)
+        single = _single(H, plan, evt, cfg.threshold, cap_peaks, cap_pairs)
+        _assert_same(res, single, f"event {e}")
+    assert acc[1].max() >= 300  # the crowded window really voted
+
+
 def test_batch_event_too_large_is_flagged(H):
     cfg, events = _small_batch_events()
     plan = H.Plan(cfg, max_hits=200)
