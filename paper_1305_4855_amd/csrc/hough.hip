@@ -127,6 +127,8 @@ struct hough_plan {
     LayerTable layers;
     hough_tuning_t tuning;
     int32_t* d_E;    // [n_layers][n_d0][n_qpt], INT32_MIN = invalid
+    const int32_t* d_Et;  // the same samples column by column, [n_d0 * n_qpt][et_stride] (inside d_E's block)
+    int et_stride;        // layers per column of d_Et: n_layers, then INT32_MIN up to a multiple of 16
     bool zvote;      // second-stage grid present
     ZGrid zg;
     int32_t* d_S;    // [n_layers][n_d0][n_qpt] Q16.16 arc length to the layer, -1 = invalid (zvote only)
@@ -1077,7 +1079,8 @@ __global__ __launch_bounds__(kVoteMaxThreads) void k_vote(Events ev, const int32
 constexpr int kVotePtThreads = 256;
 
 template <int BPL, bool OUT16>
-__global__ __launch_bounds__(kVotePtThreads) void k_vote_pt(Events ev, const int32_t* __restrict__ E, int n_layers,
+__global__ __launch_bounds__(kVotePtThreads) void k_vote_pt(Events ev, const int32_t* __restrict__ Et, int et_stride,
+                                                           int n_layers,
                                                            int n_cols, int n_phi, int M, int F, int row, int row8,
                                                            const uint32_t* __restrict__ zero_row,
                                                            char* __restrict__ ws, WsOff O,
@@ -1124,8 +1127,17 @@ __global__ __launch_bounds__(kVotePtThreads) void k_vote_pt(Events ev, const int
         // the 8-bit window counts unless a window of this event holds more than 255 hits
         const bool use8 = row8 > 0 && at<const int32_t>(event_ws(ws, ev, e), O.misc)[kMiscWide] == 0;
         char* acc_e = acc_base + (size_t)e * acc_stride;
+        // The column's samples (layer-major, padded with invalid ones past the last layer) come in
+        // one vector load, lane L holding layer L, read out with v_readlane: one load per column
+        // instead of a scalar load and wait per layer; the next column's load is issued before the
+        // current column is summed.
+        const int col_first = blk * cpi + wave * cpw;
+        const int lane_l = lane < et_stride ? lane : 0;
+        int32_t ev_next = Et[(size_t)col_first * et_stride + lane_l];
         for (int ci = 0; ci < cpw; ++ci) {
-            const int col = blk * cpi + wave * cpw + ci;
+            const int col = col_first + ci;
+            const int32_t ev_lane = ev_next;
+            if (ci + 1 < cpw) ev_next = Et[(size_t)(col + 1) * et_stride + lane_l];
             uint32_t acc[NP];
 #pragma unroll
             for (int q = 0; q < NP; ++q) acc[q] = 0u;
@@ -1143,7 +1155,7 @@ __global__ __launch_bounds__(kVotePtThreads) void k_vote_pt(Events ev, const int
 #pragma unroll
                         for (int u = 0; u < LG8; ++u) {
                             const int L = L0 + u;
-                            const int32_t ev_l = L < n_layers ? E[(size_t)L * n_cols + col] : INT32_MIN;
+                            const int32_t ev_l = __builtin_amdgcn_readlane(ev_lane, L);
                             const uint32_t ep = (uint32_t)ev_l & mmask;
                             const uint32_t r = ep & wmask, sft = ep >> F;
                             const uint32_t i0 = (sft + (uint32_t)(lane * BPL)) & (uint32_t)(n_phi - 1);
@@ -1174,7 +1186,7 @@ __global__ __launch_bounds__(kVotePtThreads) void k_vote_pt(Events ev, const int
 #pragma unroll
                 for (int u = 0; u < LG; ++u) {
                     const int L = L0 + u;
-                    const int32_t ev_l = L < n_layers ? E[(size_t)L * n_cols + col] : INT32_MIN;
+                    const int32_t ev_l = __builtin_amdgcn_readlane(ev_lane, L);
                     const uint32_t ep = (uint32_t)ev_l & mmask;
                     const uint32_t r = ep & wmask, sft = ep >> F;
                     const uint32_t i0 = (sft + (uint32_t)(lane * BPL)) & (uint32_t)(n_phi - 1);
@@ -2308,8 +2320,10 @@ __device__ __forceinline__ void assign_candidate_pt(const hough_peak_t& pk, int6
             uint2 v;
             __builtin_memcpy(&v, rp + (j >> 1), 8);
             // entries j and j + 1 of the row: the dword's halves for even j, else its high half and
-            // the next dword's low half
-            lh[u] = (j & 1u) ? (v.x >> 16) | (v.y << 16) : v.x;
+            // the next dword's low half.  A byte shift rather than a select on the parity of j: with a
+            // select the compiler would load the second dword only in the odd branch and wait for it
+            // there, one layer after another, instead of keeping all the layers' loads in flight.
+            lh[u] = __builtin_amdgcn_alignbyte(v.y, v.x, (j & 1u) * 2u);
         }
 #pragma unroll
         for (int u = 0; u < LC; ++u) {
@@ -3355,12 +3369,14 @@ void launch_vote_pt_bpl(const hough_plan* p, const Events& ev, int n_events, cha
     const uint32_t* zr = static_cast<const uint32_t*>(p->d_zero);
     if (p->g.acc_bits == 16)
         hipExtLaunchKernelGGL((k_vote_pt<BPL, true>), dim3(grid), dim3(kVotePtThreads), 0, stream, p->vote_start,
-                              p->vote_stop, 0, ev, p->d_E, p->n_layers, p->n_cols, p->g.n_phi, p->M, p->F, p->pt_row,
-                              pt_row8_for(p, n_events), zr, ws, O, a, acc_stride, n_events, order, queue, cpi);
+                              p->vote_stop, 0, ev, p->d_Et, p->et_stride, p->n_layers, p->n_cols, p->g.n_phi, p->M, p->F,
+                              p->pt_row, pt_row8_for(p, n_events), zr, ws, O, a, acc_stride, n_events, order, queue,
+                              cpi);
     else
         hipExtLaunchKernelGGL((k_vote_pt<BPL, false>), dim3(grid), dim3(kVotePtThreads), 0, stream, p->vote_start,
-                              p->vote_stop, 0, ev, p->d_E, p->n_layers, p->n_cols, p->g.n_phi, p->M, p->F, p->pt_row,
-                              pt_row8_for(p, n_events), zr, ws, O, a, acc_stride, n_events, order, queue, cpi);
+                              p->vote_stop, 0, ev, p->d_Et, p->et_stride, p->n_layers, p->n_cols, p->g.n_phi, p->M, p->F,
+                              p->pt_row, pt_row8_for(p, n_events), zr, ws, O, a, acc_stride, n_events, order, queue,
+                              cpi);
 }
 
 void launch_vote_pt(const hough_plan* p, const Events& ev, int n_events, char* ws, const WsOff& O, void* acc,
@@ -4052,12 +4068,23 @@ int hough_plan_create(const hough_geometry_t* geom, const hough_grid_t* grid, ho
         delete p;
         return HOUGH_E_UNSUPPORTED;
     }
-    if (hipMalloc(&p->d_E, ntab * sizeof(int32_t)) != hipSuccess) {
+    // the column-major copy for the table vote: every layer group it reads (up to ten layers from a
+    // layer below n_layers) stays inside a column's et_stride entries
+    p->et_stride = (p->n_layers + 9 + 15) & ~15;  // at most 64 (n_layers <= 32): one wave's lanes
+    const size_t ntab_pad = (ntab + 15) & ~(size_t)15;
+    const size_t n_et = (size_t)p->n_cols * p->et_stride;
+    int32_t* Et = (int32_t*)malloc(n_et * sizeof(int32_t));
+    if (!Et || hipMalloc(&p->d_E, (ntab_pad + n_et) * sizeof(int32_t)) != hipSuccess) {
+        free(Et);
         free(E);
         free(Stab);
         delete p;
         return HOUGH_E_NOMEM;
     }
+    for (int c = 0; c < p->n_cols; ++c)
+        for (int L = 0; L < p->et_stride; ++L)
+            Et[(size_t)c * p->et_stride + L] = L < p->n_layers ? E[(size_t)L * p->n_cols + c] : INT32_MIN;
+    p->d_Et = p->d_E + ntab_pad;
     if (hipMalloc(&p->d_zero, (size_t)g.n_phi * 4) != hipSuccess ||
         hipMemset(p->d_zero, 0, (size_t)g.n_phi * 4) != hipSuccess) {
         if (p->d_zero) (void)hipFree(p->d_zero);
@@ -4076,8 +4103,11 @@ int hough_plan_create(const hough_geometry_t* geom, const hough_grid_t* grid, ho
         return HOUGH_E_NOMEM;
     }
     hipError_t ce = hipMemcpy(p->d_E, E, ntab * sizeof(int32_t), hipMemcpyHostToDevice);
+    if (ce == hipSuccess)
+        ce = hipMemcpy(p->d_E + ntab_pad, Et, n_et * sizeof(int32_t), hipMemcpyHostToDevice);
     if (ce == hipSuccess && Stab) ce = hipMemcpy(p->d_S, Stab, ntab * sizeof(int32_t), hipMemcpyHostToDevice);
     free(E);
+    free(Et);
     free(Stab);
     if (ce != hipSuccess) {
         (void)hipFree(p->d_E);
