@@ -1350,10 +1350,19 @@ __device__ __forceinline__ void finish_plane(const PlaneRaw<T>& r, const EdgeLan
 
 // grid.y = event.  Each thread walks `planes` (<= kMaxPeakPlanes) d0 planes of one strip, keeping
 // the planes l-1, l, l+1 reduced in registers and the loads of plane l+2 in flight.  Its outputs
-// (flag bytes, group sums) are kept in LDS and stored after the walk: a global store inside the
-// walk would make every wait for the next plane's loads also wait for that store.
+// (flag bytes, vote sums) are kept in LDS and stored after the walk: a global store inside the
+// walk would make every wait for the next plane's loads also wait for that store.  The group sums
+// are formed once after the walk from the per-strip flags and vote sums in LDS (16-byte reads),
+// not by lane shuffles at every plane.
 constexpr int kMaxPeakPlanes = 32;
 constexpr int kMarkThreads = 256;
+
+// Dynamic LDS of one marker workgroup: per plane the flag bytes and vote sums of its strips, the
+// group counts and (staging on) the groups' candidate values.
+__host__ __device__ __forceinline__ size_t mark_lds_bytes(int planes, int group_lanes, bool stage_on) {
+    const size_t G = (size_t)(kMarkThreads / group_lanes);
+    return (size_t)planes * (5 * (size_t)kMarkThreads + 4 * G + (stage_on ? 2 * G * (size_t)stage_cap(group_lanes) : 0));
+}
 
 template <typename T, bool WIDE>
 __global__ __launch_bounds__(kMarkThreads) void k_peaks_mark(Events ev, const char* __restrict__ acc_base,
@@ -1361,10 +1370,13 @@ __global__ __launch_bounds__(kMarkThreads) void k_peaks_mark(Events ev, const ch
                                                              int32_t thr, int n_d0, int n_qpt, int n_phi,
                                                              int group_lanes, int planes, bool stage_on,
                                                              char* __restrict__ ws, WsOff O) {
-    __shared__ uint8_t s_flags[kMaxPeakPlanes][kMarkThreads];
-    __shared__ int32_t s_cnt[kMaxPeakPlanes][kMarkThreads / 2];
-    __shared__ int32_t s_vs[kMaxPeakPlanes][kMarkThreads / 2];
-    __shared__ uint16_t s_val[kMaxPeakPlanes][kMarkThreads * 3 / 4];  // staged values, stage_cap per group
+    // [planes][256] flag bytes | [planes][256] vote sums | [planes][G] group counts | [planes][G][capg] values
+    extern __shared__ uint32_t mk_lds[];
+    const int G = kMarkThreads / group_lanes;  // groups per workgroup
+    uint8_t* s_flags = reinterpret_cast<uint8_t*>(mk_lds);
+    int32_t* s_vl = reinterpret_cast<int32_t*>(mk_lds) + planes * (kMarkThreads / 4);
+    int32_t* s_cnt = s_vl + planes * kMarkThreads;
+    uint16_t* s_val = reinterpret_cast<uint16_t*>(s_cnt + planes * G);
     const int e = blockIdx.y;
     const T* acc = reinterpret_cast<const T*>(acc_base + (size_t)e * acc_stride);
     char* w = event_ws(ws, ev, e);
@@ -1415,15 +1427,16 @@ __global__ __launch_bounds__(kMarkThreads) void k_peaks_mark(Events ev, const ch
                 vsum += v;
             }
         }
-        s_flags[l - l0][threadIdx.x] = (uint8_t)bits;
-        int32_t cnt = __popc(bits);
-        if (stage_on) {  // the group's candidate values in candidate order, while they are in registers
+        s_flags[(l - l0) * kMarkThreads + threadIdx.x] = (uint8_t)bits;
+        s_vl[(l - l0) * kMarkThreads + threadIdx.x] = vsum;
+        if (stage_on) {
+            const int32_t cnt = __popc(bits);  // the group's candidate values in candidate order, while they are in registers
             // a strip holds at most 4 candidates (two adjacent bins cannot both win the tie rule):
             // the group's exclusive prefix of the counts from three ballots of their bits
             const uint64_t b0 = __ballot(cnt & 1), b1 = __ballot(cnt & 2), b2 = __ballot(cnt & 4);
             const uint64_t below = gmask & ((1ull << (threadIdx.x & 63)) - 1ull);
             int pos = __popcll(b0 & below) + 2 * __popcll(b1 & below) + 4 * __popcll(b2 & below);
-            uint16_t* sv = &s_val[l - l0][gi * capg];
+            uint16_t* sv = s_val + ((l - l0) * G + gi) * capg;
 #pragma unroll
             for (int i = 0; i < kStrip; ++i) {
                 if ((bits >> i) & 1u) {
@@ -1431,15 +1444,6 @@ __global__ __launch_bounds__(kMarkThreads) void k_peaks_mark(Events ev, const ch
                     ++pos;
                 }
             }
-        }
-        // per-group sums: a group is `group_lanes` consecutive strips of one column
-        for (int o = group_lanes >> 1; o >= 1; o >>= 1) {
-            cnt += __shfl_xor(cnt, o, 64);
-            vsum += __shfl_xor(vsum, o, 64);
-        }
-        if ((threadIdx.x & (group_lanes - 1)) == 0) {
-            s_cnt[l - l0][threadIdx.x / group_lanes] = cnt;
-            s_vs[l - l0][threadIdx.x / group_lanes] = vsum;
         }
     };
     for (int l = l0; l < l1; l += 3) {
@@ -1449,15 +1453,50 @@ __global__ __launch_bounds__(kMarkThreads) void k_peaks_mark(Events ev, const ch
         if (l + 2 >= l1) break;
         test_plane(l + 2, wc, wa, wb);
     }
+    // Group sums (a group is `group_lanes` consecutive strips of one column, inside one wave): lane x
+    // of the wave takes its (plane, group) pairs x, x + 64, ..., adding the group's vote sums and
+    // counting its flag bits in LDS.  The LDS written by the wave's other lanes is read after a wave
+    // barrier (a wave's LDS operations complete in order).
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    {
+        const int np = l1 - l0;
+        const int gw = 64 / group_lanes;  // groups per wave
+        const int wave_t0 = (int)threadIdx.x & ~63;
+        for (int x = (int)threadIdx.x & 63; x < np * gw; x += 64) {
+            const int p = x / gw, g = x - p * gw;
+            const int tid0 = wave_t0 + g * group_lanes;  // the group's first thread
+            const int32_t* vl = s_vl + p * kMarkThreads + tid0;
+            const uint8_t* fl = s_flags + p * kMarkThreads + tid0;
+            int32_t vs = 0, cn = 0;
+            if (group_lanes >= 4) {
+                for (int i = 0; i < group_lanes; i += 4) {
+                    const int4 v4 = *reinterpret_cast<const int4*>(vl + i);
+                    vs += v4.x + v4.y + v4.z + v4.w;
+                    cn += __popc(*reinterpret_cast<const uint32_t*>(fl + i));
+                }
+            } else {
+                for (int i = 0; i < group_lanes; ++i) {
+                    vs += vl[i];
+                    cn += __popc((uint32_t)fl[i]);
+                }
+            }
+            s_cnt[p * G + tid0 / group_lanes] = cn;
+            const int64_t t0 = (int64_t)tile * blockDim.x + tid0;
+            const int64_t sid0 = ((int64_t)(l0 + p) * n_qpt + (int)((t0 / strips) % n_qpt)) * strips + (int)(t0 % strips);
+            grp_count[sid0 / group_lanes] = cn;
+            grp_votes[sid0 / group_lanes] = vs;
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     for (int l = l0; l < l1; ++l) {
         const int64_t strip_id = ((int64_t)l * n_qpt + k) * strips + s;
-        flags[strip_id] = s_flags[l - l0][threadIdx.x];
-        if ((threadIdx.x & (group_lanes - 1)) == 0) {
-            grp_count[strip_id / group_lanes] = s_cnt[l - l0][threadIdx.x / group_lanes];
-            grp_votes[strip_id / group_lanes] = s_vs[l - l0][threadIdx.x / group_lanes];
-        }
-        if (stage_on && gq < min(s_cnt[l - l0][gi], capg))
-            stage[(strip_id / group_lanes) * capg + gq] = s_val[l - l0][gi * capg + gq];
+        flags[strip_id] = s_flags[(l - l0) * kMarkThreads + threadIdx.x];
+        if (stage_on && gq < min(s_cnt[(l - l0) * G + gi], capg))
+            stage[(strip_id / group_lanes) * capg + gq] = s_val[((l - l0) * G + gi) * capg + gq];
     }
 }
 
@@ -3459,17 +3498,18 @@ void launch_peaks(const hough_plan* p, const Events& ev, int n_events, const voi
     // of rows wider than a wave (more than 512 bins) holds more registers, and staging there costs
     // it a wave per SIMD: its writer gathers instead.
     const bool stage_on = p->stage && !one_pass && strips <= 64;
+    const size_t mlds = mark_lds_bytes(planes, gl, stage_on);
     if (p->g.acc_bits == 32 && strips > 64)
-        hipLaunchKernelGGL((k_peaks_mark<int32_t, true>), gm, mb, 0, stream, ev, a, acc_stride, z32, threshold, nd,
+        hipLaunchKernelGGL((k_peaks_mark<int32_t, true>), gm, mb, mlds, stream, ev, a, acc_stride, z32, threshold, nd,
                            nq, nph, gl, planes, stage_on, ws, O);
     else if (p->g.acc_bits == 32)
-        hipLaunchKernelGGL((k_peaks_mark<int32_t, false>), gm, mb, 0, stream, ev, a, acc_stride, z32, threshold, nd,
+        hipLaunchKernelGGL((k_peaks_mark<int32_t, false>), gm, mb, mlds, stream, ev, a, acc_stride, z32, threshold, nd,
                            nq, nph, gl, planes, stage_on, ws, O);
     else if (strips > 64)
-        hipLaunchKernelGGL((k_peaks_mark<int16_t, true>), gm, mb, 0, stream, ev, a, acc_stride, z16, threshold, nd,
+        hipLaunchKernelGGL((k_peaks_mark<int16_t, true>), gm, mb, mlds, stream, ev, a, acc_stride, z16, threshold, nd,
                            nq, nph, gl, planes, stage_on, ws, O);
     else
-        hipLaunchKernelGGL((k_peaks_mark<int16_t, false>), gm, mb, 0, stream, ev, a, acc_stride, z16, threshold, nd,
+        hipLaunchKernelGGL((k_peaks_mark<int16_t, false>), gm, mb, mlds, stream, ev, a, acc_stride, z16, threshold, nd,
                            nq, nph, gl, planes, stage_on, ws, O);
     // scan and writer in one pass: each writer workgroup re-reads the counts of all groups before
     // it, so only while that is cheaper than a separate scan (few events, not too many groups)
@@ -4145,6 +4185,18 @@ int hough_plan_create(const hough_geometry_t* geom, const hough_grid_t* grid, ho
                                  kLdsBytes - 1024);  // static LDS aside
     if (ae == hipSuccess)
         ae = hipFuncSetAttribute((const void*)k_zvote, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
+    if (ae == hipSuccess)
+        ae = hipFuncSetAttribute((const void*)k_peaks_mark<int32_t, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 kLdsBytes);
+    if (ae == hipSuccess)
+        ae = hipFuncSetAttribute((const void*)k_peaks_mark<int32_t, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 kLdsBytes);
+    if (ae == hipSuccess)
+        ae = hipFuncSetAttribute((const void*)k_peaks_mark<int16_t, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 kLdsBytes);
+    if (ae == hipSuccess)
+        ae = hipFuncSetAttribute((const void*)k_peaks_mark<int16_t, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 kLdsBytes);
     if (ae == hipSuccess)
         ae = hipFuncSetAttribute((const void*)k_fit_res, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
     if (ae != hipSuccess) {
