@@ -1364,7 +1364,10 @@ __host__ __device__ __forceinline__ size_t mark_lds_bytes(int planes, int group_
     return (size_t)planes * (5 * (size_t)kMarkThreads + 4 * G + (stage_on ? 2 * G * (size_t)stage_cap(group_lanes) : 0));
 }
 
-template <typename T, bool WIDE>
+// ROWW: rows of at least 64 strips, so that the 64 lanes of a wave hold strips of one row (one
+// column and plane range per wave): the row addresses are then computed once per wave, in scalar
+// registers.
+template <typename T, bool WIDE, bool ROWW>
 __global__ __launch_bounds__(kMarkThreads) void k_peaks_mark(Events ev, const char* __restrict__ acc_base,
                                                              size_t acc_stride, const T* __restrict__ zero_row,
                                                              int32_t thr, int n_d0, int n_qpt, int n_phi,
@@ -1396,8 +1399,12 @@ __global__ __launch_bounds__(kMarkThreads) void k_peaks_mark(Events ev, const ch
     const unsigned tile = (blockIdx.x % 8u) * (gridDim.x / 8u) + blockIdx.x / 8u;
     const int64_t t = (int64_t)tile * blockDim.x + threadIdx.x;
     const int s = (int)(t % strips);
-    const int k = (int)((t / strips) % n_qpt);
-    const int lr = (int)(t / ((int64_t)strips * n_qpt));
+    int k = (int)((t / strips) % n_qpt);
+    int lr = (int)(t / ((int64_t)strips * n_qpt));
+    if constexpr (ROWW) {
+        k = __builtin_amdgcn_readfirstlane(k);
+        lr = __builtin_amdgcn_readfirstlane(lr);
+    }
     const int l0 = lr * planes;
     if (l0 >= n_d0) return;  // whole waves exit together (strips * n_qpt is a multiple of 64)
     const int l1 = min(n_d0, l0 + planes);
@@ -3500,17 +3507,23 @@ void launch_peaks(const hough_plan* p, const Events& ev, int n_events, const voi
     const bool stage_on = p->stage && !one_pass && strips <= 64;
     const size_t mlds = mark_lds_bytes(planes, gl, stage_on);
     if (p->g.acc_bits == 32 && strips > 64)
-        hipLaunchKernelGGL((k_peaks_mark<int32_t, true>), gm, mb, mlds, stream, ev, a, acc_stride, z32, threshold, nd,
-                           nq, nph, gl, planes, stage_on, ws, O);
+        hipLaunchKernelGGL((k_peaks_mark<int32_t, true, true>), gm, mb, mlds, stream, ev, a, acc_stride, z32, threshold,
+                           nd, nq, nph, gl, planes, stage_on, ws, O);
+    else if (p->g.acc_bits == 32 && strips == 64)
+        hipLaunchKernelGGL((k_peaks_mark<int32_t, false, true>), gm, mb, mlds, stream, ev, a, acc_stride, z32, threshold,
+                           nd, nq, nph, gl, planes, stage_on, ws, O);
     else if (p->g.acc_bits == 32)
-        hipLaunchKernelGGL((k_peaks_mark<int32_t, false>), gm, mb, mlds, stream, ev, a, acc_stride, z32, threshold, nd,
-                           nq, nph, gl, planes, stage_on, ws, O);
+        hipLaunchKernelGGL((k_peaks_mark<int32_t, false, false>), gm, mb, mlds, stream, ev, a, acc_stride, z32, threshold,
+                           nd, nq, nph, gl, planes, stage_on, ws, O);
     else if (strips > 64)
-        hipLaunchKernelGGL((k_peaks_mark<int16_t, true>), gm, mb, mlds, stream, ev, a, acc_stride, z16, threshold, nd,
-                           nq, nph, gl, planes, stage_on, ws, O);
+        hipLaunchKernelGGL((k_peaks_mark<int16_t, true, true>), gm, mb, mlds, stream, ev, a, acc_stride, z16, threshold,
+                           nd, nq, nph, gl, planes, stage_on, ws, O);
+    else if (strips == 64)
+        hipLaunchKernelGGL((k_peaks_mark<int16_t, false, true>), gm, mb, mlds, stream, ev, a, acc_stride, z16, threshold,
+                           nd, nq, nph, gl, planes, stage_on, ws, O);
     else
-        hipLaunchKernelGGL((k_peaks_mark<int16_t, false>), gm, mb, mlds, stream, ev, a, acc_stride, z16, threshold, nd,
-                           nq, nph, gl, planes, stage_on, ws, O);
+        hipLaunchKernelGGL((k_peaks_mark<int16_t, false, false>), gm, mb, mlds, stream, ev, a, acc_stride, z16, threshold,
+                           nd, nq, nph, gl, planes, stage_on, ws, O);
     // scan and writer in one pass: each writer workgroup re-reads the counts of all groups before
     // it, so only while that is cheaper than a separate scan (few events, not too many groups)
     if (one_pass) {
@@ -4186,17 +4199,23 @@ int hough_plan_create(const hough_geometry_t* geom, const hough_grid_t* grid, ho
     if (ae == hipSuccess)
         ae = hipFuncSetAttribute((const void*)k_zvote, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
     if (ae == hipSuccess)
-        ae = hipFuncSetAttribute((const void*)k_peaks_mark<int32_t, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                 kLdsBytes);
+        ae = hipFuncSetAttribute((const void*)k_peaks_mark<int32_t, false, false>,
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
     if (ae == hipSuccess)
-        ae = hipFuncSetAttribute((const void*)k_peaks_mark<int32_t, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                 kLdsBytes);
+        ae = hipFuncSetAttribute((const void*)k_peaks_mark<int32_t, false, true>,
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
     if (ae == hipSuccess)
-        ae = hipFuncSetAttribute((const void*)k_peaks_mark<int16_t, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                 kLdsBytes);
+        ae = hipFuncSetAttribute((const void*)k_peaks_mark<int32_t, true, true>,
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
     if (ae == hipSuccess)
-        ae = hipFuncSetAttribute((const void*)k_peaks_mark<int16_t, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                 kLdsBytes);
+        ae = hipFuncSetAttribute((const void*)k_peaks_mark<int16_t, false, false>,
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
+    if (ae == hipSuccess)
+        ae = hipFuncSetAttribute((const void*)k_peaks_mark<int16_t, false, true>,
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
+    if (ae == hipSuccess)
+        ae = hipFuncSetAttribute((const void*)k_peaks_mark<int16_t, true, true>,
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
     if (ae == hipSuccess)
         ae = hipFuncSetAttribute((const void*)k_fit_res, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
     if (ae != hipSuccess) {
