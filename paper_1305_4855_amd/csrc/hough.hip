@@ -2332,10 +2332,20 @@ __device__ __forceinline__ void pt_copy_run(int a0, int a1, int32_t wpos, int32_
     for (; t < n_e; ++t) hit_idx[wpos + t] = hv.hit_run(a0 + t, a1);  // past the wave's buffer
 }
 
+// The samples of a candidate's column for the layers [L0, L0 + kAssignLayerChunk) from the column-major
+// copy of the sample table (INT32_MIN past the last layer: no test per layer, contiguous loads).
+__device__ __forceinline__ void col_samples(const int32_t* __restrict__ Ecol, int L0,
+                                            int32_t (&ev)[kAssignLayerChunk]) {
+    __builtin_memcpy(ev, Ecol + L0, sizeof(ev));
+}
+
+// ev0: the candidate's samples of its first kAssignLayerChunk layers (loaded ahead by the caller);
+// Ecol: its column in the column-major sample table, for further layers.
 template <typename View>
 __device__ __forceinline__ void assign_candidate_pt(const hough_peak_t& pk, int64_t off, int64_t o0,
-                                                    const int32_t* __restrict__ Ec,
-                                                    int n_layers, int n_cols, int M, int F, int n_phi, int row,
+                                                    const int32_t* __restrict__ Ecol,
+                                                    const int32_t (&ev0)[kAssignLayerChunk],
+                                                    int n_layers, int M, int F, int n_phi, int row,
                                                     const uint16_t* __restrict__ pt, const int32_t* lay_start,
                                                     const View& hv, int32_t* buf, int buf_words, int32_t* hit_idx,
                                                     int32_t cap_pairs) {
@@ -2348,9 +2358,12 @@ __device__ __forceinline__ void assign_candidate_pt(const hough_peak_t& pk, int6
     for (int L0 = 0; L0 < n_layers; L0 += LC) {
         if (wpos >= cap_pairs) break;
         int32_t ev_l[LC];
+        if (L0 == 0) {
 #pragma unroll
-        for (int u = 0; u < LC; ++u)
-            ev_l[u] = L0 + u < n_layers ? Ec[(size_t)(L0 + u) * n_cols] : INT32_MIN;
+            for (int u = 0; u < LC; ++u) ev_l[u] = ev0[u];
+        } else {
+            col_samples(Ecol, L0, ev_l);
+        }
         uint32_t lh[LC];  // lo | hi << 16: the run's first and end entries in the layer
         uint32_t wr = 0;  // layers whose window passes the turn
 #pragma unroll
@@ -2408,7 +2421,8 @@ __device__ __forceinline__ void assign_candidate_pt(const hough_peak_t& pk, int6
 template <int THREADS>
 __global__ __launch_bounds__(THREADS) void k_assign_pt(
     Events ev, const hough_peak_t* __restrict__ peaks_base, int32_t peak_stride, int32_t cap_peaks,
-    hough_status_t* __restrict__ st_base, const int32_t* __restrict__ E, int n_layers, int cell_bits, int n_cols,
+    hough_status_t* __restrict__ st_base, const int32_t* __restrict__ Et, int et_stride, int n_layers, int cell_bits,
+    int n_cols,
     int n_qpt, int M, int F, int n_phi, int row, char* __restrict__ ws, WsOff O,
     int32_t* __restrict__ offsets_base, int32_t* __restrict__ hit_idx_base, int32_t cap_pairs, int lds_words,
     const int32_t* __restrict__ order, int n_events) {
@@ -2457,13 +2471,16 @@ __global__ __launch_bounds__(THREADS) void k_assign_pt(
     int32_t* buf = sm_i32 + kHead + (staged ? stage_words : 0) + wave * buf_words;
     const int stride = gridDim.x * THREADS;
     int base = bx * THREADS + wave * 64;
-    hough_peak_t pk{};
-    int64_t off = 0;
-    if (base < n) {
-        const int i = min(base + lane, n - 1);
-        pk = peaks[i];
-        off = peak_voff[i];
-    }
+    // a two-deep pipeline over the wave's candidates: while a candidate copies its runs, the samples
+    // of the next one and the row of the one after are in flight (a candidate then waits for its
+    // table loads only, not for its samples first)
+    // (n >= 1 here; the loads clamp to the last candidate and are issued without a condition, so
+    // that no branch join makes the wave wait for them early)
+    const int i1 = min(base + lane, n - 1), i2 = min(base + stride + lane, n - 1);
+    hough_peak_t pk = peaks[i1], pk2 = peaks[i2];
+    int64_t off = peak_voff[i1], off2 = peak_voff[i2];
+    int32_t ev_n[kAssignLayerChunk];
+    col_samples(Et + (size_t)(pk.l * n_qpt + pk.k) * et_stride, 0, ev_n);
     if (tid <= n_layers) lay_start[tid] = g_cell_start[tid << cell_bits];
     if (staged) {
         for (int c0 = tid; c0 < h4; c0 += kStageUnroll * THREADS) {
@@ -2488,19 +2505,24 @@ __global__ __launch_bounds__(THREADS) void k_assign_pt(
         const int64_t o1 = __shfl(off, last - base, 64) + __shfl(pk.votes, last - base, 64);
         const hough_peak_t cur = pk;
         const int64_t cur_off = off;
-        if (base + stride < n) {  // the wave's next candidates (wave-uniform)
-            const int i2 = min(base + stride + lane, n - 1);
-            pk = peaks[i2];
-            off = peak_voff[i2];
-        }
+        int32_t ev_c[kAssignLayerChunk];
+#pragma unroll
+        for (int u = 0; u < kAssignLayerChunk; ++u) ev_c[u] = ev_n[u];
+        // the wave's next candidates: their samples, and the rows of the ones after
+        pk = pk2;
+        off = off2;
+        col_samples(Et + (size_t)(pk.l * n_qpt + pk.k) * et_stride, 0, ev_n);
+        const int i3 = min(base + 2 * stride + lane, n - 1);
+        pk2 = peaks[i3];
+        off2 = peak_voff[i3];
         if (i < n) {
             offsets[i] = (int32_t)min(cur_off, (int64_t)INT32_MAX);
-            const int32_t* Ec = E + (size_t)cur.l * n_qpt + cur.k;
+            const int32_t* Ecol = Et + (size_t)(cur.l * n_qpt + cur.k) * et_stride;
             if (staged)
-                assign_candidate_pt(cur, cur_off, o0, Ec, n_layers, n_cols, M, F, n_phi, row, pt, lay_start,
+                assign_candidate_pt(cur, cur_off, o0, Ecol, ev_c, n_layers, M, F, n_phi, row, pt, lay_start,
                                     HitsU16{(lds_cu16*)s16}, buf, buf_words, hit_idx, cap_pairs);
             else
-                assign_candidate_pt(cur, cur_off, o0, Ec, n_layers, n_cols, M, F, n_phi, row, pt, lay_start,
+                assign_candidate_pt(cur, cur_off, o0, Ecol, ev_c, n_layers, M, F, n_phi, row, pt, lay_start,
                                     HitsIdx{sorted_h}, buf, buf_words, hit_idx, cap_pairs);
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -3576,14 +3598,14 @@ void launch_assign(const hough_plan* p, const Events& ev, int n_events, const ho
         if (half)
             hipExtLaunchKernelGGL(k_assign_pt<kAssignThreads / 2>, dim3(nblk, gy), dim3(kAssignThreads / 2),
                                   kLdsBytes / 2, stream, p->assign_start, p->assign_stop, 0, ev, peaks, peak_stride,
-                                  cap_peaks, st, p->d_E, p->n_layers, p->cell_bits, p->n_cols, p->g.n_qpt, p->M, p->F,
-                                  p->g.n_phi, p->pt_row, ws, O, offsets, hit_idx, cap_pairs, lds_words / 2, ord,
-                                  n_events);
+                                  cap_peaks, st, p->d_Et, p->et_stride, p->n_layers, p->cell_bits, p->n_cols,
+                                  p->g.n_qpt, p->M, p->F, p->g.n_phi, p->pt_row, ws, O, offsets, hit_idx, cap_pairs,
+                                  lds_words / 2, ord, n_events);
         else
             hipExtLaunchKernelGGL(k_assign_pt<kAssignThreads>, dim3(nblk, gy), dim3(kAssignThreads), kLdsBytes, stream,
-                                  p->assign_start, p->assign_stop, 0, ev, peaks, peak_stride, cap_peaks, st, p->d_E,
-                                  p->n_layers, p->cell_bits, p->n_cols, p->g.n_qpt, p->M, p->F, p->g.n_phi,
-                                  p->pt_row, ws, O, offsets, hit_idx, cap_pairs, lds_words, ord, n_events);
+                                  p->assign_start, p->assign_stop, 0, ev, peaks, peak_stride, cap_peaks, st, p->d_Et,
+                                  p->et_stride, p->n_layers, p->cell_bits, p->n_cols, p->g.n_qpt, p->M, p->F,
+                                  p->g.n_phi, p->pt_row, ws, O, offsets, hit_idx, cap_pairs, lds_words, ord, n_events);
         return;
     }
     // one packed word per staged hit: angles of at most 16 bits and hit indices below 2^16
