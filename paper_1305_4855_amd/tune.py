@@ -36,7 +36,7 @@ SPACE = {
     "serve": dict(vote_cols=(8, 16, 32), vote_grid=(512, 1024, 2048), peak_planes=(8, 16, 32),
                   assign_blocks=(64, 128, 256), prep_rows=(32, 64, 128, 256), vote_threads=(512, 1024)),
     "single": dict(vote_cols=(4, 8, 16, 32), peak_planes=(4, 8, 16), assign_blocks=(256, 512, 1024),
-                   prep_rows=(32, 64, 128, 256), vote_threads=(512, 1024)),
+                   prep_rows=(16, 32, 64, 128, 256), vote_threads=(512, 1024)),
 }
 DEFAULT = dict(vote_threads=1024, vote_grid=0, peak_planes=8, vote_cols=0, assign_blocks=0, prep_rows=0)
 
