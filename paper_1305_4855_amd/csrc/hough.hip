@@ -1159,9 +1159,11 @@ __global__ __launch_bounds__(kVotePtThreads) void k_vote_pt(Events ev, const int
                             const uint32_t ep = (uint32_t)ev_l & mmask;
                             const uint32_t r = ep & wmask, sft = ep >> F;
                             const uint32_t i0 = (sft + (uint32_t)(lane * BPL)) & (uint32_t)(n_phi - 1);
+                            // the row offset fits 32 bits (fewer than 2^31 table bytes per event): one
+                            // scalar multiply instead of a 64-bit one
                             const uint32_t* src =
                                 ev_l != INT32_MIN
-                                    ? reinterpret_cast<const uint32_t*>(gt8 + ((size_t)L * (1u << F) + r) * row8)
+                                    ? reinterpret_cast<const uint32_t*>(gt8 + ((((uint32_t)L << F) | r) * (uint32_t)row8))
                                     : zero_row;
                             sh[u] = __builtin_amdgcn_readfirstlane(sft) & 3u;
                             __builtin_memcpy(&d[u][0], src + (i0 >> 2), 4 * NQ);  // dword-aligned loads
@@ -1190,7 +1192,7 @@ __global__ __launch_bounds__(kVotePtThreads) void k_vote_pt(Events ev, const int
                     const uint32_t ep = (uint32_t)ev_l & mmask;
                     const uint32_t r = ep & wmask, sft = ep >> F;
                     const uint32_t i0 = (sft + (uint32_t)(lane * BPL)) & (uint32_t)(n_phi - 1);
-                    const uint32_t* src = ev_l != INT32_MIN ? gt + ((size_t)L * (1u << F) + r) * row2 : zero_row;
+                    const uint32_t* src = ev_l != INT32_MIN ? gt + ((((uint32_t)L << F) | r) * (uint32_t)row2) : zero_row;
                     // byte selector: the pair starting at an odd entry spans two dwords
                     odd[u] = (__builtin_amdgcn_readfirstlane(sft) & 1u) != 0u;
                     sel[u] = odd[u] ? 0x05040302u : 0x03020100u;
