@@ -2376,7 +2376,8 @@ __device__ __forceinline__ void assign_candidate_pt(const hough_peak_t& pk, int6
             const uint32_t x = ((uint32_t)ev_l[u] + ((uint32_t)pk.b << F)) & mmask;
             const uint32_t r = x & wmask, j = x >> F;
             const int Lc = min(L0 + u, n_layers - 1);
-            const uint32_t* rp = reinterpret_cast<const uint32_t*>(pt + ((size_t)Lc * (wmask + 1u) + r) * n_phi);
+            // the row offset fits 32 bits (fewer than 2^31 table entries per event)
+            const uint32_t* rp = reinterpret_cast<const uint32_t*>(pt + ((((uint32_t)Lc << F) | r) * (uint32_t)n_phi));
             wr |= ((int)j == n_phi - 1 ? 1u : 0u) << u;
             uint2 v;
             __builtin_memcpy(&v, rp + (j >> 1), 8);
@@ -2391,7 +2392,7 @@ __device__ __forceinline__ void assign_candidate_pt(const hough_peak_t& pk, int6
             if (wr & (1u << u)) {  // the window passes the turn: it ends at entry 0 of the row
                 const uint32_t r = ((uint32_t)ev_l[u] + ((uint32_t)pk.b << F)) & wmask;
                 const int Lc = min(L0 + u, n_layers - 1);
-                lh[u] = (lh[u] & 0xFFFFu) | ((uint32_t)pt[((size_t)Lc * (wmask + 1u) + r) * n_phi] << 16);
+                lh[u] = (lh[u] & 0xFFFFu) | ((uint32_t)pt[(((uint32_t)Lc << F) | r) * (uint32_t)n_phi] << 16);
             }
         }
 #pragma unroll
